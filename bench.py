@@ -1,0 +1,249 @@
+"""Benchmark of the radix-group random-walk hot path on one MI355X.
+
+Workload (R-MAT scale 24, edge factor 16: 16,777,216 vertices, 268,435,456 edges, a/b/c/d =
+0.57/0.19/0.19/0.05, ids permuted, weights uniform in [1, 2^24)), resident in HBM.  One step is one
+pass of the whole hot path over one batch: a batch of 10^6 edge updates (500,000 R-MAT inserts with
+uniform weights, 500,000 deletions of existing edges) followed by personalized-PageRank walks from
+10,000 distinct non-sink sources x 1,000 walks (termination probability 0.15 before every step,
+at most 200 steps), reduced to per-source visit histograms.  The graph build is timed once.
+
+Prints one JSON line.  `value` is walk transitions per second of whole step time (updates + walks +
+histograms); the update and walk phases are also reported on their own.  The roofline object covers
+the walk kernel, timed with HIP events recorded by the library on the stream it runs on.  The
+cpu_baseline object times the CPU oracle on this host on the same workload (the same batches, then
+the last step's PPR query) and checks the GPU histograms against it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walk-steps/s + edge-updates/s at R-MAT-24 on 1 GPU; p99 query latency"
+HBM_PEAK_GBS = 8000.0
+LINE = 64  # bytes per random access line counted as algorithmic traffic
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--sources", type=int, default=10_000)
+    ap.add_argument("--walks-per-source", type=int, default=1_000)
+    ap.add_argument("--batch", type=int, default=1_000_000)
+    ap.add_argument("--mode", choices=["persistent", "per_step"], default="persistent")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration runs)")
+    return ap.parse_args()
+
+
+def walk_src_hash():
+    h = hashlib.sha256()
+    for f in ("walk.hip", "dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2504_10233_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
+              "walk and update phases would shard). Use --gpus 1.", flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_10233_amd import Graph, MODE_PER_STEP, MODE_PERSISTENT, ppr_threshold
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scale, ef = args.scale, args.edge_factor
+    n, m = 1 << scale, ef << scale
+    c = 3  # seeds of the R-MAT-24 PPR workload
+    t0 = time.time()
+    src, dst = synth.rmat_graph(scale, m, synth.SEEDS["graph"] + c, device=dev)
+    w = synth.weights_uniform(m, 1, 1 << 24, synth.SEEDS["weights"] + c, device=dev)
+    torch.cuda.synchronize()
+    log("graph generated: n=%d m=%d in %.1fs" % (n, m, time.time() - t0))
+
+    torch.cuda.synchronize()
+    tb = time.time()
+    g = Graph(n, src, dst, w, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.time() - tb
+    log("built in %.2fs" % build_s)
+
+    # sources: distinct non-sink vertices
+    deg = torch.bincount(src, minlength=n)
+    nz = torch.nonzero(deg > 0).flatten()
+    order = torch.argsort(synth.uniform_u32(synth.SEEDS["walks"] + c, 1, nz.numel(), dev))
+    sources = nz[order[: args.sources]].contiguous()
+    del deg, nz, order
+
+    # update batches (device resident before timing)
+    nb = args.warmup + args.steps
+    mirror = synth.EdgeMirror(src, dst)
+    batches = []
+    half = args.batch // 2
+    for b in range(nb):
+        bseed = synth.SEEDS["batch"] + 100 * c + b
+        isrc, idst = synth.rmat_graph(scale, half, bseed, device=dev)
+        iw = synth.weights_uniform(half, 1, 1 << 24, bseed, device=dev, stream=7)
+        pos = mirror.pick_deletions(args.batch - half, bseed, 30)
+        dsrc, ddst = mirror.src[pos], mirror.dst[pos]
+        mirror.apply(isrc, idst, pos)
+        batches.append(tuple(x.to(torch.int32).contiguous() for x in (isrc, idst, iw, dsrc, ddst)))
+    del mirror
+    torch.cuda.synchronize()
+    log("%d update batches ready" % nb)
+
+    thr = ppr_threshold(0.15)
+    cap = 200
+    R = args.walks_per_source
+    mode = MODE_PERSISTENT if args.mode == "persistent" else MODE_PER_STEP
+    seed = synth.SEEDS["walks"] + c
+    stream = torch.cuda.current_stream()
+    rows = []
+    last = None
+    for i in range(nb):
+        base = i * args.sources * R
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        st = g.update(*batches[i])
+        upd_phases = g.last_phase_ms()
+        e1.record(stream)
+        off, vtx, cnt, steps = g.ppr(sources, R, thr, cap, seed, base=base, mode=mode)
+        ppr_phases = g.last_phase_ms()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        rows.append({"update_ms": e0.elapsed_time(e1), "ppr_ms": e1.elapsed_time(e2),
+                     "step_ms": e0.elapsed_time(e2), "walk_kernel_ms": ppr_phases[0],
+                     "hist_ms": ppr_phases[1], "update_phases_ms": upd_phases, "steps": steps,
+                     "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel())})
+        log("step %d: update %.2f ms, ppr %.2f ms (walk kernel %.2f), %d transitions" %
+            (i, rows[-1]["update_ms"], rows[-1]["ppr_ms"], ppr_phases[0], steps))
+        if i == nb - 1:
+            last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32),
+                    steps)
+    timed = rows[args.warmup:]
+    tot_ms = sum(r["step_ms"] for r in timed)
+    tot_steps = sum(r["steps"] for r in timed)
+    upd_ms = sum(r["update_ms"] for r in timed)
+    walk_ms = sum(r["walk_kernel_ms"] for r in timed)
+    ppr_ms = sum(r["ppr_ms"] for r in timed)
+    recs = sum(r["records"] for r in timed)
+
+    # the other walk form on the same (final) graph, for the persistent vs per-step comparison
+    other = MODE_PER_STEP if mode == MODE_PERSISTENT else MODE_PERSISTENT
+    g.ppr(sources, R, thr, cap, seed, base=last[0], mode=other)
+    other_ms = g.last_phase_ms()[0]
+
+    if args.calibrate_copy_mb:
+        a = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    result = {
+        "metric": METRIC,
+        "value": tot_steps / (tot_ms / 1e3),
+        "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tot_ms / len(timed),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "rmat%d-ef%d-uniform24-ppr-with-update-batches" % (scale, ef), "vertices": n,
+                   "edges": m, "weights": "uniform[1,2^24)", "ppr_sources": args.sources, "walks_per_source": R,
+                   "termination_prob": 0.15, "max_len": cap, "update_batch_records": args.batch,
+                   "walk_form": args.mode, "group_adaption": True},
+        "walk_steps_per_s": tot_steps / (walk_ms / 1e3),
+        "ppr_query_ms": ppr_ms / len(timed),
+        "edge_updates_per_s": recs / (upd_ms / 1e3),
+        "update_batch_ms": upd_ms / len(timed),
+        "build_s": build_s,
+        "walk_form_compare": {"persistent_ms" if mode == MODE_PERSISTENT else "per_step_ms": walk_ms / len(timed),
+                              "per_step_ms" if mode == MODE_PERSISTENT else "persistent_ms": other_ms},
+        "p99_query_latency_ms": None,
+        "steps_detail": rows,
+    }
+    mem = g.memory()
+    result["memory"] = {k: mem[k] for k in ("pool_used_bytes", "header_bytes", "adjacency_bytes", "list_bytes",
+                                             "model_ga_bytes", "model_bs_bytes", "groups_by_type")}
+
+    # ---- CPU oracle on the host: same batches, then the last step's query; parity of the histograms
+    mix = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        th = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+        log("oracle: building on the host (%d edges)" % m)
+        t = time.time()
+        og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
+        log("oracle: built in %.1fs" % (time.time() - t))
+        del src, dst, w
+        t = time.time()
+        urecs = 0
+        for bt in batches:
+            a = [x.cpu().numpy().view(np.uint32) for x in bt]
+            s2 = og.update(*a)
+            urecs += s2["inserted"] + s2["deleted"] + s2["not_found"]
+        oracle_upd_s = time.time() - t
+        base, off, vtx, cnt, steps = last
+        t = time.time()
+        ooff, ovtx, ocnt, osteps, ost = og.ppr(sources.cpu().numpy(), R, thr, cap, seed, base=base, threads=th,
+                                               with_stats=True)
+        oracle_ppr_s = time.time() - t
+        same = (np.array_equal(off.astype(np.uint64), ooff) and np.array_equal(vtx, ovtx)
+                and np.array_equal(cnt, ocnt) and steps == osteps)
+        result["parity"] = {"last_step_ppr_histograms_equal": bool(same), "sources": args.sources,
+                            "entries": int(len(ovtx)), "transitions": int(osteps)}
+        result["cpu_baseline"] = {"value": osteps / oracle_ppr_s, "unit": "walk-steps/s", "cores": th,
+                                  "kind": "oracle",
+                                  "sample": "the last step's full PPR query (%d sources x %d walks, %d transitions) "
+                                            "on the graph after the same %d update batches; oracle updates ran at "
+                                            "%.3g records/s single-threaded" % (args.sources, R, osteps, nb,
+                                                                                 urecs / oracle_upd_s)}
+        mix = {"steps": int(ost[1] + ost[2] + ost[3] + ost[4]), "one": int(ost[1]), "dense": int(ost[2]),
+               "sparse": int(ost[3]), "regular": int(ost[4]), "dense_attempts": int(ost[5])}
+        result["selection_mix"] = mix
+        log("oracle: ppr %.1fs (%d threads), parity %s" % (oracle_ppr_s, th, same))
+
+    # ---- roofline of the walk kernel: algorithmic random lines per transition from the selection mix
+    roof = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "achieved": None, "frac": None, "traffic": None}
+    if mix and mix["steps"]:
+        lines = 2 * mix["one"] + 3 * (mix["sparse"] + mix["regular"]) + mix["dense"] + mix["dense_attempts"]
+        per_step = LINE * lines / mix["steps"] + 8  # + the 8-byte visit record written per transition
+        per_walk = LINE + 8  # the start vertex's header line and its visit record
+        nwalks = args.sources * R
+        byts = per_step * tot_steps / len(timed) + per_walk * nwalks
+        ach = byts / (walk_ms / len(timed) / 1e3) / 1e9
+        roof.update({"achieved": ach, "frac": ach / HBM_PEAK_GBS, "bytes_per_transition": per_step,
+                     "lines_per_transition": lines / mix["steps"]})
+    prof = os.path.join(ROOT, "profiles", "walk_kernel_counters.json")
+    if os.path.exists(prof):
+        pc = json.load(open(prof))
+        if pc.get("src_hash") == walk_src_hash():
+            roof["traffic"] = pc.get("traffic_bytes_per_launch")
+    result["roofline"] = roof
+    result["walk_src_hash"] = walk_src_hash()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * bingo.h -- C ABI of the MI355X implementation of radix-based bias
+ * factorization for random walks on dynamic graphs (Bingo, arXiv 2504.10233).
+ *
+ * Plain C: no HIP or torch types appear here.  Streams are passed as void*
+ * (a hipStream_t, or NULL for the default stream).  Pointers named d_* are
+ * device pointers; h_* are host pointers.  Every call is asynchronous on the
+ * given stream unless its comment says it synchronizes.
+ *
+ * Errors.  Calls return 0 (BINGO_OK) or a negative code.  Argument errors
+ * (null pointers, sizes out of range) and device-pool exhaustion are reported
+ * synchronously and leave the graph unchanged.  Data errors found on the
+ * device (a vertex id >= n, a zero weight) make the whole call a no-op; they
+ * are returned by the calls that synchronize and by bingo_status().
+ *
+ * Ownership.  Input and output buffers belong to the caller and must stay
+ * valid until the stream work that uses them has finished.  A bingo_graph owns
+ * all of its device memory and releases it in bingo_destroy().
+ *
+ * Concurrency.  A handle is not thread-safe.  bingo_walk calls may overlap
+ * each other on different streams; bingo_update_batch and bingo_ppr must not
+ * overlap any other call on the same handle.
+ *
+ * Determinism.  Results are a pure function of (graph version, inputs, seed,
+ * walk id base); they do not depend on stream, launch shape or timing.
+ */
+#ifndef BINGO_H
+#define BINGO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BINGO_OK = 0,
+    BINGO_E_INVALID = -1,   /* null pointer, zero or oversized count, bad config */
+    BINGO_E_RANGE = -2,     /* a vertex id >= n (device-detected) */
+    BINGO_E_WEIGHT = -3,    /* a zero weight (device-detected) */
+    BINGO_E_OOM = -4,       /* the device pool cannot hold the result */
+    BINGO_E_CAPACITY = -5,  /* a caller-supplied output buffer is too small */
+    BINGO_E_HIP = -6        /* a HIP runtime call failed */
+};
+
+/* Group types of the adaptive representation (Sec. 5.1, Eq. eq:group). */
+enum { BINGO_T_EMPTY = 0, BINGO_T_ONE = 1, BINGO_T_DENSE = 2, BINGO_T_SPARSE = 3, BINGO_T_REGULAR = 4 };
+
+/* Walk execution forms: one persistent launch that keeps each walk in a
+ * thread until it ends (default), or one launch per step over all walks (the
+ * step-by-step form of the paper's Sec. 6, item iii). */
+enum { BINGO_WALK_PERSISTENT = 0, BINGO_WALK_PER_STEP = 1 };
+
+typedef struct bingo_graph bingo_graph;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(bingo_config) */
+    uint32_t adaptive;      /* 1: group adaption (Sec. 5.1); 0: every non-empty group regular */
+    uint32_t alpha_pct;     /* dense threshold alpha in percent (paper: 40) */
+    uint32_t beta_pct;      /* sparse threshold beta in percent (paper: 10) */
+    uint64_t pool_bytes;    /* device arena for adjacency and group lists; 0 = sized from the input */
+} bingo_config;
+
+typedef struct {
+    uint64_t inserted;          /* insert records applied */
+    uint64_t deleted;           /* delete records that removed an edge */
+    uint64_t not_found;         /* delete records with no live matching edge */
+    uint64_t touched_vertices;  /* vertices with at least one record */
+    uint64_t transitions[25];   /* [old*5 + new] group-type changes over all groups of touched vertices */
+} bingo_update_stats;
+
+typedef struct {
+    uint64_t vertices, edges;
+    uint64_t pool_bytes, pool_used_bytes, pool_garbage_bytes;
+    uint64_t header_bytes;          /* per-vertex inter-group sampling space */
+    uint64_t adjacency_bytes;       /* live edges: dst, weight, seq (12 B each) */
+    uint64_t adjacency_reserved_bytes;
+    uint64_t list_bytes;            /* live entries of listed (sparse + regular) groups */
+    uint64_t list_reserved_bytes;
+    uint64_t groups_by_type[5];     /* number of groups per type */
+    uint64_t model_ga_bytes;        /* paper's memory model with adaption (Sec. 5.1) */
+    uint64_t model_bs_bytes;        /* ... and without (all regular, Sec. 6.2) */
+} bingo_mem_stats;
+
+/*
+ * bingo_build -- build the dynamic graph and its sampling space from COO edges
+ * (Sec. 4.1 sampling-space construction: Eq. eq:dwi decomposition, Eq. eq:wpk
+ * group totals; Sec. 5.1 group adaption).
+ *   n           number of vertices, 1 <= n < 2^31.
+ *   m           number of edges, m < 2^32.
+ *   d_src, d_dst, d_w   m device uint32 each; weights must be >= 1.
+ * The edges of vertex u keep their input order; an edge's sequence number is
+ * its rank among u's edges.  Synchronizes the stream.  Returns BINGO_E_RANGE or
+ * BINGO_E_WEIGHT (and no graph) for bad input.  *out receives the handle.
+ */
+int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m,
+                const uint32_t* d_src, const uint32_t* d_dst, const uint32_t* d_w,
+                void* stream, bingo_graph** out);
+
+/*
+ * bingo_update_batch -- apply one batch of edge insertions and deletions
+ * (Sec. 5.2 parallel batched updates; Sec. 4.2 insertion and deletion).
+ * All insertions are applied first, then all deletions, then one rebuild per
+ * touched vertex.  Inserts of a vertex are appended in batch order.  A delete
+ * record (s, t) removes the live edge s->t with the smallest sequence number
+ * (the earliest version); records with no live match are counted in
+ * not_found.  Deleted entries are removed from the adjacency and from every
+ * listed group by the two-phase delete-and-swap (Fig. 10b), holes and tail
+ * survivors paired in ascending order.  Types are recomputed from the new
+ * counts; groups that change to a listed type get a fresh ascending list.
+ *   d_ins_*     n_ins device uint32 each (weights >= 1).
+ *   d_del_*     n_del device uint32 each.
+ *   h_stats     optional; filled after the call (the call synchronizes).
+ * Returns BINGO_E_RANGE / BINGO_E_WEIGHT (batch not applied) or BINGO_E_OOM
+ * (pool too small; batch not applied).
+ */
+int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src,
+                       const uint32_t* d_ins_dst, const uint32_t* d_ins_w,
+                       uint64_t n_del, const uint32_t* d_del_src, const uint32_t* d_del_dst,
+                       void* stream, bingo_update_stats* h_stats);
+
+/*
+ * bingo_walk -- biased first-order walks of fixed length (DeepWalk, Sec. 2.2).
+ * Walk j has id walk_id_base + j and starts at d_starts[j]; step s of that walk
+ * draws from the Philox-4x32-10 stream keyed by (seed, id, s).  Each step picks
+ * a group with probability c_k 2^k / W (Eq. eq:group_prob) and then a member
+ * uniformly (Eq. eq:pvp), by rejection on the adjacency for dense groups.
+ *   d_paths        n_walks * (length + 1) uint32, row-major; entry 0 is the
+ *                  start; after a vertex without out-edges the rest is
+ *                  0xFFFFFFFF.
+ *   d_steps_taken  optional, one uint64 that receives the transitions taken
+ *                  (overwritten, not accumulated).
+ *   mode           BINGO_WALK_PERSISTENT or BINGO_WALK_PER_STEP.
+ * Start ids >= n give BINGO_E_RANGE at the next synchronizing call and the
+ * paths are left unspecified.
+ */
+int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
+               uint64_t walk_id_base, uint32_t length, uint64_t seed,
+               uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode, void* stream);
+
+/*
+ * bingo_ppr -- personalized PageRank by Monte-Carlo visit counts (Sec. 1 and
+ * Sec. 6.1).  Source index q runs walks_per_source walks with ids
+ * walk_id_base + q * walks_per_source + r.  The start counts as a visit;
+ * before every transition the walk ends if the next word of its stream is
+ * below term_threshold (= floor(p * 2^32) for termination probability p), at
+ * a vertex without out-edges, or after max_len transitions.  The result is,
+ * per source, the visited vertices in ascending order with their counts; it
+ * stays in the handle until bingo_ppr_fetch or the next bingo_ppr.
+ * Synchronizes; *h_total_entries receives the number of (vertex, count)
+ * pairs and *h_total_steps (optional) the transitions taken.
+ */
+int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources,
+              uint32_t walks_per_source, uint32_t term_threshold, uint32_t max_len,
+              uint64_t seed, uint64_t walk_id_base, uint32_t mode,
+              uint64_t* h_total_entries, uint64_t* h_total_steps, void* stream);
+
+/*
+ * bingo_ppr_fetch -- copy the last PPR result: d_offsets (n_sources + 1
+ * uint64, CSR offsets per source), d_vertex and d_count (capacity uint32
+ * each).  Returns BINGO_E_CAPACITY if capacity is below the entry count.
+ */
+int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uint32_t* d_count,
+                    uint64_t capacity, void* stream);
+
+/*
+ * bingo_export -- canonical dump of the whole structure into host memory, as
+ * little-endian uint32 words: for each vertex u ascending: d, next sequence
+ * number, non-empty group mask, then (dst, weight, seq) for each neighbor
+ * index, then for each non-empty group k ascending: k, type, count, followed
+ * by the member index (one-element group) or the list in order (sparse and
+ * regular groups).  With h_buf == NULL only *h_len (words) is set.
+ * Synchronizes.  Returns BINGO_E_CAPACITY if cap_words is too small.
+ */
+int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* h_len, void* stream);
+
+/*
+ * bingo_export_range -- the same dump restricted to vertices [u_begin, u_end),
+ * for sampled checks of large graphs.
+ */
+int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
+                       uint64_t* h_len, void* stream);
+
+/* bingo_memory -- device memory by structure (synchronizes). */
+int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream);
+
+/* bingo_status -- sticky device-detected error of the last call (synchronizes), then cleared. */
+int bingo_status(bingo_graph* g, void* stream);
+
+/*
+ * bingo_last_phase_ms -- device time of each phase of the last bingo_walk,
+ * bingo_ppr or bingo_update_batch call on this handle, measured with HIP
+ * events recorded on that call's stream.  bingo_walk: [walk kernel];
+ * bingo_ppr: [walk kernel, visit histogram]; bingo_update_batch: [sort and
+ * segment, delete matching, deleted sets and analysis, mutation].  *h_n
+ * receives the number of phases; h_ms (capacity cap) may be NULL.
+ * Synchronizes on the last event.
+ */
+int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n);
+
+/* bingo_num_vertices -- n of the handle. */
+uint32_t bingo_num_vertices(const bingo_graph* g);
+
+/* bingo_destroy -- release the handle and all its device memory. */
+void bingo_destroy(bingo_graph* g);
+
+/* bingo_strerror -- static description of a return code. */
+const char* bingo_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BINGO_H */

@@ -1,0 +1,215 @@
+"""ctypes binding of libbingo.so: argument marshalling only.
+
+Every function here converts torch device tensors into the plain pointers and sizes of the C ABI
+(include/bingo.h) and raises BingoError on a non-zero return code.  No step of the method runs in
+Python; if the shared library is missing the first call raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libbingo.so")
+_lock = threading.Lock()
+_lib = None
+
+MODE_PERSISTENT = 0
+MODE_PER_STEP = 1
+STOP = 0xFFFFFFFF
+
+
+class BingoError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = load().bingo_strerror(code).decode()
+        super().__init__("%s: %s (%d)" % (where, msg, code))
+
+
+class _Config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("adaptive", C.c_uint32), ("alpha_pct", C.c_uint32),
+                ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64)]
+
+
+class _UpdateStats(C.Structure):
+    _fields_ = [("inserted", C.c_uint64), ("deleted", C.c_uint64), ("not_found", C.c_uint64),
+                ("touched_vertices", C.c_uint64), ("transitions", C.c_uint64 * 25)]
+
+
+class _MemStats(C.Structure):
+    _fields_ = [("vertices", C.c_uint64), ("edges", C.c_uint64), ("pool_bytes", C.c_uint64),
+                ("pool_used_bytes", C.c_uint64), ("pool_garbage_bytes", C.c_uint64),
+                ("header_bytes", C.c_uint64), ("adjacency_bytes", C.c_uint64),
+                ("adjacency_reserved_bytes", C.c_uint64), ("list_bytes", C.c_uint64),
+                ("list_reserved_bytes", C.c_uint64), ("groups_by_type", C.c_uint64 * 5),
+                ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64)]
+
+
+EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
+           "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_num_vertices",
+           "bingo_destroy", "bingo_strerror"]
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def load():
+    """Load libbingo.so (built by __graft_entry__.build() / build_lib.py)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB):
+            raise RuntimeError("libbingo.so is not built (%s); run __graft_entry__.build()" % _LIB)
+        L = C.CDLL(_LIB)
+        vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+        L.bingo_build.argtypes = [C.POINTER(_Config), u32, u64, vp, vp, vp, vp, C.POINTER(vp)]
+        L.bingo_update_batch.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(_UpdateStats)]
+        L.bingo_walk.argtypes = [vp, u64, vp, u64, u32, u64, vp, vp, u32, vp]
+        L.bingo_ppr.argtypes = [vp, u32, vp, u32, u32, u32, u64, u64, u32, C.POINTER(u64), C.POINTER(u64), vp]
+        L.bingo_ppr_fetch.argtypes = [vp, vp, vp, vp, u64, vp]
+        L.bingo_export.argtypes = [vp, vp, u64, C.POINTER(u64), vp]
+        L.bingo_export_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
+        L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
+        L.bingo_status.argtypes = [vp, vp]
+        L.bingo_last_phase_ms.argtypes = [vp, C.POINTER(C.c_float), u32, C.POINTER(u32)]
+        L.bingo_num_vertices.argtypes = [vp]
+        L.bingo_num_vertices.restype = u32
+        L.bingo_destroy.argtypes = [vp]
+        L.bingo_destroy.restype = None
+        L.bingo_strerror.argtypes = [C.c_int]
+        L.bingo_strerror.restype = C.c_char_p
+        _lib = L
+        return L
+
+
+def ppr_threshold(p: float) -> int:
+    """Termination word threshold floor(p * 2^32)."""
+    return int(p * 4294967296.0)
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise BingoError(rc, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def as_u32(x, device=None) -> torch.Tensor:
+    """A contiguous int32 device tensor holding the low 32 bits of x (uint32 bit pattern)."""
+    t = torch.as_tensor(x)
+    if device is not None:
+        t = t.to(device)
+    if t.dtype != torch.int32:
+        t = t.to(torch.int64) & 0xFFFFFFFF
+        t = torch.where(t >= 2**31, t - 2**32, t).to(torch.int32)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+
+
+class Graph:
+    """A dynamic graph with its radix-group sampling space resident in device memory."""
+
+    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None):
+        L = load()
+        self.device = torch.device(device)
+        s, d, ww = as_u32(src, self.device), as_u32(dst, self.device), as_u32(w, self.device)
+        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes)
+        h = C.c_void_p()
+        rc = L.bingo_build(C.byref(cfg), n, s.numel(), _ptr(s), _ptr(d), _ptr(ww), _stream(stream), C.byref(h))
+        _check(rc, "bingo_build")
+        self.h = h
+        self.n = n
+        self.adaptive = bool(adaptive)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bingo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def walk(self, starts, length, seed, base=0, mode=MODE_PERSISTENT, stream=None, out=None):
+        """DeepWalk paths (n_walks, length + 1) as int32 bit patterns of uint32; returns (paths, steps)."""
+        st = as_u32(starts, self.device)
+        nw = st.numel()
+        paths = out if out is not None else torch.empty((nw, length + 1), dtype=torch.int32, device=self.device)
+        steps = torch.zeros(1, dtype=torch.int64, device=self.device)
+        rc = load().bingo_walk(self.h, nw, _ptr(st), base, length, seed, _ptr(paths), _ptr(steps), mode,
+                               _stream(stream))
+        _check(rc, "bingo_walk")
+        return paths, steps
+
+    def ppr(self, sources, walks_per_source, thr, max_len, seed, base=0, mode=MODE_PERSISTENT, stream=None):
+        """Per-source visit histograms: (offsets int64 [n_src+1], vertex int32, count int32, steps)."""
+        src = as_u32(sources, self.device)
+        L = load()
+        ne, ns = C.c_uint64(0), C.c_uint64(0)
+        rc = L.bingo_ppr(self.h, src.numel(), _ptr(src), walks_per_source, thr, max_len, seed, base, mode,
+                         C.byref(ne), C.byref(ns), _stream(stream))
+        _check(rc, "bingo_ppr")
+        off = torch.empty(src.numel() + 1, dtype=torch.int64, device=self.device)
+        vtx = torch.empty(max(ne.value, 1), dtype=torch.int32, device=self.device)
+        cnt = torch.empty(max(ne.value, 1), dtype=torch.int32, device=self.device)
+        rc = L.bingo_ppr_fetch(self.h, _ptr(off), _ptr(vtx), _ptr(cnt), vtx.numel(), _stream(stream))
+        _check(rc, "bingo_ppr_fetch")
+        return off, vtx[: ne.value], cnt[: ne.value], int(ns.value)
+
+    def update(self, ins_src, ins_dst, ins_w, del_src, del_dst, stream=None):
+        a, b, c = (as_u32(x, self.device) for x in (ins_src, ins_dst, ins_w))
+        d, e = (as_u32(x, self.device) for x in (del_src, del_dst))
+        stats = _UpdateStats()
+        rc = load().bingo_update_batch(self.h, a.numel(), _ptr(a), _ptr(b), _ptr(c), d.numel(), _ptr(d), _ptr(e),
+                                       _stream(stream), C.byref(stats))
+        _check(rc, "bingo_update_batch")
+        return {"inserted": stats.inserted, "deleted": stats.deleted, "not_found": stats.not_found,
+                "touched_vertices": stats.touched_vertices,
+                "transitions": np.array(list(stats.transitions), dtype=np.int64).reshape(5, 5)}
+
+    def export(self, u_begin=None, u_end=None, stream=None) -> np.ndarray:
+        """Canonical dump as uint32 words (layout in include/bingo.h)."""
+        L = load()
+        n = C.c_uint64(0)
+        ub = 0 if u_begin is None else u_begin
+        ue = self.n if u_end is None else u_end
+        rc = L.bingo_export_range(self.h, ub, ue, None, 0, C.byref(n), _stream(stream))
+        _check(rc, "bingo_export")
+        buf = np.zeros(max(n.value, 1), dtype=np.uint32)
+        rc = L.bingo_export_range(self.h, ub, ue, C.c_void_p(buf.ctypes.data), buf.size, C.byref(n),
+                                  _stream(stream))
+        _check(rc, "bingo_export")
+        return buf[: n.value]
+
+    def memory(self, stream=None) -> dict:
+        m = _MemStats()
+        _check(load().bingo_memory(self.h, C.byref(m), _stream(stream)), "bingo_memory")
+        out = {k: getattr(m, k) for k, _ in _MemStats._fields_ if k != "groups_by_type"}
+        out["groups_by_type"] = list(m.groups_by_type)
+        return out
+
+    def last_phase_ms(self) -> list:
+        """Device milliseconds per phase of the last walk / ppr / update call (HIP events on its stream)."""
+        L = load()
+        buf = (C.c_float * 8)()
+        n = C.c_uint32(0)
+        _check(L.bingo_last_phase_ms(self.h, buf, 8, C.byref(n)), "bingo_last_phase_ms")
+        return [float(buf[i]) for i in range(n.value)]
+
+    def status(self, stream=None) -> int:
+        return load().bingo_status(self.h, _stream(stream))

@@ -1,0 +1,192 @@
+// api.hip -- the extern "C" entry points of libbingo (declared in bingo.h).
+#include "dev.h"
+#include <stdio.h>
+#include <string.h>
+#include <new>
+
+void* ws_get(bingo_graph* g, size_t bytes) {
+    if (bytes <= g->ws_bytes && g->ws) return g->ws;
+    hipDeviceSynchronize();
+    if (g->ws) hipFree(g->ws);
+    g->ws = nullptr;
+    g->ws_bytes = 0;
+    const size_t want = bytes + bytes / 4 + 4096;
+    if (hipMalloc(&g->ws, want) != hipSuccess) {
+        g->ws = nullptr;
+        return nullptr;
+    }
+    g->ws_bytes = want;
+    return g->ws;
+}
+
+// Record the next phase boundary of the current call on its stream.
+void phase_mark(bingo_graph* g, hipStream_t st, bool first) {
+    if (first) g->nev = 0;
+    if (g->nev >= PHASE_EVENTS) return;
+    if (!g->ev[g->nev] && hipEventCreate(&g->ev[g->nev]) != hipSuccess) return;
+    if (hipEventRecord(g->ev[g->nev], st) == hipSuccess) g->nev++;
+}
+
+int err_to_code(uint32_t bits) {
+    if (bits & ERR_RANGE) return BINGO_E_RANGE;
+    if (bits & ERR_WEIGHT) return BINGO_E_WEIGHT;
+    if (bits & ERR_OOM) return BINGO_E_OOM;
+    if (bits & ERR_INTERNAL) return BINGO_E_HIP;
+    return BINGO_OK;
+}
+
+static void release(bingo_graph* g) {
+    if (!g) return;
+    for (int i = 0; i < PHASE_EVENTS; ++i)
+        if (g->ev[i]) hipEventDestroy(g->ev[i]);
+    hipFree(g->hdr);
+    hipFree(g->pool);
+    hipFree(g->d_ctl);
+    hipFree(g->d_err);
+    hipFree(g->ppr_off);
+    hipFree(g->ppr_vtx);
+    hipFree(g->ppr_cnt);
+    hipFree(g->ws);
+    delete g;
+}
+
+extern "C" {
+
+int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t* d_src, const uint32_t* d_dst,
+                const uint32_t* d_w, void* stream, bingo_graph** out) {
+    if (!out) return BINGO_E_INVALID;
+    *out = nullptr;
+    if (!cfg || cfg->struct_size != sizeof(bingo_config)) return BINGO_E_INVALID;
+    if (n == 0 || n >= (1u << 31) || m >= (1ull << 32)) return BINGO_E_INVALID;
+    if (m && (!d_src || !d_dst || !d_w)) return BINGO_E_INVALID;
+    if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100) return BINGO_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    bingo_graph* g = new (std::nothrow) bingo_graph();
+    if (!g) return BINGO_E_OOM;
+    g->n = n;
+    g->rule.adaptive = cfg->adaptive;
+    g->rule.alpha = cfg->alpha_pct;
+    g->rule.beta = cfg->beta_pct;
+    g->pool_words = cfg->pool_bytes / 4;
+    g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr;
+    if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
+        hipMalloc(&g->d_ctl, CTL_WORDS * 8) != hipSuccess || hipMalloc(&g->d_err, 4) != hipSuccess) {
+        release(g);
+        return BINGO_E_OOM;
+    }
+    if (hipMemsetAsync(g->hdr, 0, (size_t)n * HDR_WORDS * 4, st) != hipSuccess ||
+        hipMemsetAsync(g->d_ctl, 0, CTL_WORDS * 8, st) != hipSuccess) {
+        release(g);
+        return BINGO_E_HIP;
+    }
+    const int rc = build_graph(g, m, d_src, d_dst, d_w, st);
+    if (rc != BINGO_OK) {
+        hipStreamSynchronize(st);
+        release(g);
+        return rc;
+    }
+    *out = g;
+    return BINGO_OK;
+}
+
+int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src, const uint32_t* d_ins_dst,
+                       const uint32_t* d_ins_w, uint64_t n_del, const uint32_t* d_del_src, const uint32_t* d_del_dst,
+                       void* stream, bingo_update_stats* h_stats) {
+    if (!g) return BINGO_E_INVALID;
+    if (n_ins && (!d_ins_src || !d_ins_dst || !d_ins_w)) return BINGO_E_INVALID;
+    if (n_del && (!d_del_src || !d_del_dst)) return BINGO_E_INVALID;
+    return update_batch(g, n_ins, d_ins_src, d_ins_dst, d_ins_w, n_del, d_del_src, d_del_dst, h_stats,
+                        (hipStream_t)stream);
+}
+
+int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
+               uint32_t length, uint64_t seed, uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode,
+               void* stream) {
+    if (!g || (n_walks && (!d_starts || !d_paths))) return BINGO_E_INVALID;
+    if (mode > BINGO_WALK_PER_STEP || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    return launch_walk(const_cast<bingo_graph*>(g), n_walks, d_starts, walk_id_base, length, seed, d_paths,
+                       d_steps_taken, mode, (hipStream_t)stream);
+}
+
+int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources, uint32_t walks_per_source,
+              uint32_t term_threshold, uint32_t max_len, uint64_t seed, uint64_t walk_id_base, uint32_t mode,
+              uint64_t* h_total_entries, uint64_t* h_total_steps, void* stream) {
+    if (!g || !h_total_entries || n_sources == 0 || walks_per_source == 0 || !d_sources) return BINGO_E_INVALID;
+    if (mode > BINGO_WALK_PER_STEP) return BINGO_E_INVALID;
+    if ((uint64_t)n_sources * walks_per_source >= (1ull << 40)) return BINGO_E_INVALID;
+    return run_ppr(g, n_sources, d_sources, walks_per_source, term_threshold, max_len, seed, walk_id_base, mode,
+                   h_total_entries, h_total_steps, (hipStream_t)stream);
+}
+
+int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uint32_t* d_count, uint64_t capacity,
+                    void* stream) {
+    if (!g || !d_offsets || !d_vertex || !d_count || !g->ppr_off) return BINGO_E_INVALID;
+    if (capacity < g->ppr_entries) return BINGO_E_CAPACITY;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(d_offsets, g->ppr_off, ((uint64_t)g->ppr_nsrc + 1) * 8, hipMemcpyDeviceToDevice, st));
+    if (g->ppr_entries) {
+        HIPCHK(hipMemcpyAsync(d_vertex, g->ppr_vtx, g->ppr_entries * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_count, g->ppr_cnt, g->ppr_entries * 4, hipMemcpyDeviceToDevice, st));
+    }
+    return BINGO_OK;
+}
+
+int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* h_len, void* stream) {
+    if (!g || !h_len) return BINGO_E_INVALID;
+    return export_graph(g, 0, g->n, h_buf, cap_words, h_len, (hipStream_t)stream);
+}
+
+int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
+                       uint64_t* h_len, void* stream) {
+    if (!g || !h_len) return BINGO_E_INVALID;
+    return export_graph(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
+}
+
+int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
+    if (!g || !out) return BINGO_E_INVALID;
+    return memory_stats(g, out, (hipStream_t)stream);
+}
+
+int bingo_status(bingo_graph* g, void* stream) {
+    if (!g) return BINGO_E_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    return err_to_code(bits);
+}
+
+uint32_t bingo_num_vertices(const bingo_graph* g) { return g ? g->n : 0u; }
+
+int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n) {
+    if (!g || !h_n) return BINGO_E_INVALID;
+    const uint32_t n = g->nev > 1 ? g->nev - 1 : 0;
+    *h_n = n;
+    if (!h_ms) return BINGO_OK;
+    if (cap < n) return BINGO_E_CAPACITY;
+    if (n) HIPCHK(hipEventSynchronize(g->ev[n]));
+    for (uint32_t i = 0; i < n; ++i) HIPCHK(hipEventElapsedTime(&h_ms[i], g->ev[i], g->ev[i + 1]));
+    return BINGO_OK;
+}
+
+void bingo_destroy(bingo_graph* g) {
+    if (!g) return;
+    hipDeviceSynchronize();
+    release(g);
+}
+
+const char* bingo_strerror(int code) {
+    switch (code) {
+        case BINGO_OK: return "ok";
+        case BINGO_E_INVALID: return "invalid argument";
+        case BINGO_E_RANGE: return "vertex id out of range";
+        case BINGO_E_WEIGHT: return "zero edge weight";
+        case BINGO_E_OOM: return "device memory pool exhausted";
+        case BINGO_E_CAPACITY: return "output buffer too small";
+        case BINGO_E_HIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

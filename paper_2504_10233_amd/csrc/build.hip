@@ -1,0 +1,264 @@
+// build.hip -- sampling-space construction (Sec. 4.1: decomposition of every
+// weight into its set bits, Eq. eq:dwi, and per-group totals c_k 2^k,
+// Eq. eq:wpk; Sec. 5.1: group adaption).  One wave per vertex: for every
+// 64-edge chunk, one ballot per bit position gives that bit's members in the
+// chunk; popcounts give the counts and prefix popcounts the list positions.
+#include "dev.h"
+#include <stdio.h>
+#include <algorithm>
+
+namespace {
+
+constexpr int WB = 256;  // block of 4 waves, one vertex per wave
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
+    return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
+}
+
+// Adjacency capacity of a vertex with d edges and the block size in words.
+__host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
+    if (d == 0) return 0;
+    uint32_t c = 2;
+    while (c < d) c <<= 1;
+    return c;
+}
+__host__ __device__ inline uint64_t adj_block_words(uint32_t cap) {
+    return ((uint64_t)cap * 3 + 7) & ~7ull;
+}
+// List capacity of a listed group with c members: a power of two >= max(c, 8).
+__host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
+    uint32_t x = 8;
+    while (x < c) x <<= 1;
+    return x;
+}
+
+__global__ void k_validate(uint64_t m, uint32_t n, const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                           const uint32_t* __restrict__ w, uint32_t* __restrict__ err) {
+    uint32_t bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (src[i] >= n || dst[i] >= n) bad |= ERR_RANGE;
+        if (w[i] == 0) bad |= ERR_WEIGHT;
+    }
+    // combine in the wave first; one atomic per wave that saw a problem
+    bad |= __shfl_xor(bad, 1); bad |= __shfl_xor(bad, 2); bad |= __shfl_xor(bad, 4);
+    bad |= __shfl_xor(bad, 8); bad |= __shfl_xor(bad, 16); bad |= __shfl_xor(bad, 32);
+    if (bad && lane_id() == 0) atomicOr(err, bad);
+}
+
+__global__ void k_iota(uint32_t* __restrict__ v, uint64_t m) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+        v[i] = (uint32_t)i;
+}
+
+__global__ void k_gather(uint64_t m, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ dst,
+                         const uint32_t* __restrict__ w, uint32_t* __restrict__ cdst, uint32_t* __restrict__ cw) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = ids[i];
+        cdst[i] = dst[e];
+        cw[i] = w[e];
+    }
+}
+
+// start[u] = first position of key u in the sorted keys (u = 0..n).
+__global__ void k_row_start(const uint32_t* __restrict__ keys, uint64_t m, uint32_t n, uint32_t* __restrict__ start) {
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n) return;
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    start[u] = (uint32_t)lo;
+}
+
+// Pass 1: counts, totals, one-element members, types; block sizes.
+__global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __restrict__ start,
+                                               const uint32_t* __restrict__ cw, uint32_t* __restrict__ hdr,
+                                               uint64_t* __restrict__ adjw, uint64_t* __restrict__ listw,
+                                               GroupRule rule) {
+    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t b = start[u], d = start[u + 1] - b;
+    uint32_t cnt = 0, last = 0;  // lane k < 32 owns bit k
+    for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        const uint32_t wv = i < d ? cw[b + i] : 0u;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const uint64_t bal = __ballot((wv >> k) & 1u);
+            if (lane == (uint32_t)k && bal) {
+                cnt += __popcll(bal);
+                last = c0 + 63 - __clzll(bal);
+            }
+        }
+    }
+    const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
+    uint64_t wsum = lane < 32 ? ((uint64_t)cnt << lane) : 0ull;
+    uint64_t lw = type_listed(t) ? (uint64_t)list_cap_for(cnt) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        wsum += __shfl_xor(wsum, o);
+        lw += __shfl_xor(lw, o);
+    }
+    const uint64_t mask = __ballot(cnt > 0) & 0xFFFFFFFFull;
+    uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    if (lane < 32) {
+        h[H_CNT + lane] = cnt;
+        h[H_INFO + lane] = (t == GT_ONE) ? last : 0u;
+    }
+    if (lane == 0) {
+        const uint32_t cap = adj_cap_for(d);
+        h[H_MASK] = (uint32_t)mask;
+        h[H_DEG] = d;
+        h[H_WLO] = (uint32_t)wsum;
+        h[H_WHI] = (uint32_t)(wsum >> 32);
+        h[H_ACAP] = cap;
+        h[H_NSEQ] = d;
+        adjw[u] = adj_block_words(cap);
+        listw[u] = lw;
+    }
+}
+
+// Pass 2: adjacency blocks (edge words and sequence numbers) and listed-group
+// lists (ascending neighbor indices).
+__global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restrict__ start,
+                                             const uint32_t* __restrict__ cdst, const uint32_t* __restrict__ cw,
+                                             const uint64_t* __restrict__ adj_off, const uint64_t* __restrict__ list_off,
+                                             uint64_t list_base, uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                             GroupRule rule) {
+    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t b = start[u], d = start[u + 1] - b;
+    uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    if (d == 0) {
+        if (lane == 0) { h[H_ADJLO] = 0; h[H_ADJHI] = 0; }
+        if (lane < 8) h[H_LCAPLOG + lane] = 0;
+        return;
+    }
+    const uint32_t cap = h[H_ACAP];
+    const uint64_t ao = adj_off[u];
+    if (lane == 0) { h[H_ADJLO] = (uint32_t)ao; h[H_ADJHI] = (uint32_t)(ao >> 32); }
+    uint64_t* edges = (uint64_t*)(pool + ao);
+    uint32_t* seqs = pool + ao + 2ull * cap;
+    // list blocks of the listed groups, in ascending k
+    const uint32_t cnt = lane < 32 ? h[H_CNT + lane] : 0u;
+    const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
+    const bool lst = type_listed(t);
+    const uint32_t lcap = lst ? list_cap_for(cnt) : 0u;
+    uint64_t x = lcap;  // inclusive scan over lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    const uint64_t my_block = list_base + list_off[u] + (x - lcap);  // words
+    if (lane < 32 && lst) h[H_INFO + lane] = (uint32_t)(my_block / LIST_UNIT_WORDS);
+    // list capacity exponents, one byte per group, packed four per word
+    const uint32_t lg = lst ? (31 - __clz(lcap)) : 0u;
+    const uint32_t byte = lg << (8 * (lane & 3));
+    uint32_t packed = byte;
+    packed |= __shfl_xor(packed, 1);
+    packed |= __shfl_xor(packed, 2);
+    if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
+    const uint32_t lmask = (uint32_t)(__ballot(lst) & 0xFFFFFFFFull);
+    uint32_t fill = 0;  // lane k: entries written so far into group k
+    for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        uint32_t wv = 0;
+        if (i < d) {
+            wv = cw[b + i];
+            edges[i] = (uint64_t)cdst[b + i] | ((uint64_t)wv << 32);
+            seqs[i] = i;
+        }
+        uint32_t mm = lmask;
+        while (mm) {
+            const int k = __ffs(mm) - 1;
+            mm &= mm - 1;
+            const bool bit = (wv >> k) & 1u;
+            const uint64_t bal = __ballot(bit);
+            const uint64_t blk = __shfl(my_block, k, 64);
+            const uint32_t f = __shfl(fill, k, 64);
+            if (bit) pool[blk + f + __popcll(bal & lanemask_lt())] = i;
+            if (lane == (uint32_t)k) fill += __popcll(bal);
+        }
+    }
+}
+
+inline uint32_t grid_for(uint64_t n, uint32_t block) {
+    uint64_t g = (n + block - 1) / block;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1u << 20);
+}
+
+int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
+    int b = 0;
+    while (b < 64 && (v >> b)) ++b;
+    return b;
+}
+
+}  // namespace
+
+int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
+                hipStream_t st) {
+    const uint32_t n = g->n;
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    if (m) hipLaunchKernelGGL(k_validate, dim3(grid_for(m, 256)), dim3(256), 0, st, m, n, src, dst, w, g->d_err);
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return err_to_code(err);
+
+    // scratch layout
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t mm = m ? m : 1;
+    const size_t sort_tmp = sort_temp_bytes(mm, false);
+    const size_t scan_tmp = scan_temp_bytes((uint64_t)n + 1);
+    const size_t need = al(mm * 4) * 4 + al(((uint64_t)n + 1) * 4) + 2 * al(((uint64_t)n + 1) * 8) * 2 +
+                        std::max(sort_tmp, scan_tmp) + 1024;
+    char* ws = (char*)ws_get(g, need);
+    if (!ws) return BINGO_E_OOM;
+    uint32_t* ids = (uint32_t*)ws;            ws += al(mm * 4);
+    uint32_t* skeys = (uint32_t*)ws;          ws += al(mm * 4);
+    uint32_t* sids = (uint32_t*)ws;           ws += al(mm * 4);
+    uint32_t* cdst = ids;                     // ids are dead after the sort
+    uint32_t* cw = (uint32_t*)ws;             ws += al(mm * 4);
+    uint32_t* start = (uint32_t*)ws;          ws += al(((uint64_t)n + 1) * 4);
+    uint64_t* adjw = (uint64_t*)ws;           ws += al(((uint64_t)n + 1) * 8);
+    uint64_t* listw = (uint64_t*)ws;          ws += al(((uint64_t)n + 1) * 8);
+    uint64_t* adj_off = (uint64_t*)ws;        ws += al(((uint64_t)n + 1) * 8);
+    uint64_t* list_off = (uint64_t*)ws;       ws += al(((uint64_t)n + 1) * 8);
+    unsigned long long* totals = (unsigned long long*)ws;  ws += 256;
+    void* tmp = ws;
+
+    if (m) {
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(m, 256)), dim3(256), 0, st, ids, m);
+        sort_pairs_u32(src, ids, skeys, sids, m, bits_for(n - 1), tmp, st);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(m, 256)), dim3(256), 0, st, m, sids, dst, w, cdst, cw);
+    }
+    hipLaunchKernelGGL(k_row_start, dim3(((uint64_t)n + 1 + 255) / 256), dim3(256), 0, st, skeys, m, n, start);
+    const uint32_t vgrid = (uint32_t)(((uint64_t)n + 3) / 4);
+    hipLaunchKernelGGL(k_header, dim3(vgrid), dim3(WB), 0, st, n, start, cw, g->hdr, adjw, listw, g->rule);
+    scan_u64(adjw, adj_off, n, tmp, totals, st);
+    scan_u64(listw, list_off, n, tmp, totals + 1, st);
+    unsigned long long tot[2];
+    HIPCHK(hipMemcpyAsync(tot, totals, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t used = tot[0] + tot[1];
+    uint64_t pool_words = g->pool_words;  // requested size (words), 0 = automatic
+    if (pool_words == 0) pool_words = used * 2 + (64ull << 20);
+    if (pool_words < used + 1024) return BINGO_E_OOM;
+    if (pool_words > (1ull << 35)) pool_words = std::max<uint64_t>(1ull << 35, used + 1024);
+    if (used + 1024 > (1ull << 35)) return BINGO_E_OOM;  // list offsets are 32-bit in 32-byte units
+    if (hipMalloc(&g->pool, pool_words * 4) != hipSuccess) {
+        g->pool = nullptr;
+        return BINGO_E_OOM;
+    }
+    g->pool_words = pool_words;
+    hipLaunchKernelGGL(k_fill, dim3(vgrid), dim3(WB), 0, st, n, start, cdst, cw, adj_off, list_off, (uint64_t)tot[0],
+                       g->hdr, g->pool, g->rule);
+    unsigned long long ctl[2] = {(unsigned long long)used, 0ull};
+    HIPCHK(hipMemcpyAsync(g->d_ctl, ctl, 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return BINGO_OK;
+}

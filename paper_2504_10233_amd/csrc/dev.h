@@ -1,0 +1,242 @@
+// dev.h -- device data layout and device helpers shared by the HIP kernels of
+// libbingo (radix-based bias factorization, arXiv 2504.10233), gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "bingo.h"
+
+// ---------------------------------------------------------------------------
+// Per-vertex header: the inter-group sampling space of Sec. 3 / Sec. 4.1, one
+// fixed 384-byte slot (three 128-byte lines) per vertex, 128-byte aligned.
+//   line 0: mask of non-empty groups, degree d, W = sum_k c_k 2^k (u64),
+//           adjacency block offset (u64, in pool words), c_k for k = 0..25
+//   line 1: c_k for k = 26..31, info_k for k = 0..25
+//   line 2: info_k for k = 26..31, adjacency capacity, next sequence number,
+//           log2 of each listed group's list capacity (bytes), spare
+// info_k is the member index of a one-element group, or the offset of a
+// listed group's list block in 32-byte units of the pool.  Dense and empty
+// groups have no info.  A walk step reads line 0 and, for one-element and
+// listed groups, one word of line 1.
+// ---------------------------------------------------------------------------
+#define HDR_WORDS 96
+#define H_MASK 0
+#define H_DEG 1
+#define H_WLO 2
+#define H_WHI 3
+#define H_ADJLO 4
+#define H_ADJHI 5
+#define H_CNT 6        // 32 words
+#define H_INFO 38      // 32 words
+#define H_ACAP 70
+#define H_NSEQ 71
+#define H_LCAPLOG 72   // 32 bytes = 8 words
+#define STOP_VERTEX 0xFFFFFFFFu
+
+// Adjacency block of capacity cap (words): cap edge words of 64 bits
+// (dst | weight << 32) followed by cap sequence numbers (u32).
+// List block: cap u32 neighbor indices, 32-byte aligned.
+#define LIST_UNIT_WORDS 8u
+
+enum { GT_EMPTY = 0, GT_ONE = 1, GT_DENSE = 2, GT_SPARSE = 3, GT_REGULAR = 4 };
+
+// Sticky device error bits (mapped to BINGO_E_* on the host).
+#define ERR_RANGE 1u
+#define ERR_WEIGHT 2u
+#define ERR_OOM 4u
+#define ERR_INTERNAL 8u
+
+#define PHASE_EVENTS 8
+
+struct GroupRule {
+    uint32_t adaptive, alpha, beta;
+};
+
+// Group type from (count, degree): empty, one element, dense above alpha %,
+// sparse below beta %, regular otherwise, in that order (Sec. 5.1).
+__host__ __device__ inline uint32_t group_type(uint32_t c, uint32_t d, GroupRule r) {
+    if (c == 0) return GT_EMPTY;
+    if (!r.adaptive) return GT_REGULAR;
+    if (c == 1) return GT_ONE;
+    uint64_t c100 = (uint64_t)c * 100u;
+    if (c100 > (uint64_t)r.alpha * d) return GT_DENSE;
+    if (c100 < (uint64_t)r.beta * d) return GT_SPARSE;
+    return GT_REGULAR;
+}
+__host__ __device__ inline bool type_listed(uint32_t t) { return t == GT_SPARSE || t == GT_REGULAR; }
+
+// ---------------------------------------------------------------------------
+// Counter-based random stream (Philox-4x32-10, Salmon et al. SC'11).  The
+// stream of a walk step is keyed by the 64-bit seed; its counter holds the
+// 64-bit walk id, the step and a block index.  Words are consumed in block
+// order; a 64-bit draw takes the first word as its high half.
+// ---------------------------------------------------------------------------
+struct RandStream {
+    uint32_t k0, k1, w0, w1, step, blk;
+    uint32_t b0, b1, b2, b3;
+    uint32_t left;
+};
+
+__device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1, uint32_t& o0, uint32_t& o1,
+                                             uint32_t& o2, uint32_t& o3) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    o0 = c0; o1 = c1; o2 = c2; o3 = c3;
+}
+
+__device__ __forceinline__ void rs_init(RandStream& s, uint64_t seed, uint64_t walk, uint32_t step) {
+    s.k0 = (uint32_t)seed; s.k1 = (uint32_t)(seed >> 32);
+    s.w0 = (uint32_t)walk; s.w1 = (uint32_t)(walk >> 32);
+    s.step = step; s.blk = 0; s.left = 0;
+}
+
+__device__ __forceinline__ uint32_t rs_next32(RandStream& s) {
+    if (s.left == 0) {
+        philox_block(s.w0, s.w1, s.step, s.blk, s.k0, s.k1, s.b0, s.b1, s.b2, s.b3);
+        s.blk++;
+        s.left = 4;
+    }
+    const uint32_t v = s.b0;
+    s.b0 = s.b1; s.b1 = s.b2; s.b2 = s.b3;
+    s.left--;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t rs_next64(RandStream& s) {
+    const uint64_t hi = rs_next32(s);
+    return (hi << 32) | rs_next32(s);
+}
+
+// Exact uniform draw on [0, n), n >= 1: multiply the word by n, keep the high
+// half, and redraw while the low half falls in the biased zone below
+// (2^32 - n) mod n (Lemire, ACM TOMACS 2019).
+__device__ __forceinline__ uint32_t rs_below32(RandStream& s, uint32_t n) {
+    uint64_t m = (uint64_t)rs_next32(s) * n;
+    uint32_t low = (uint32_t)m;
+    if (low < n) {
+        const uint32_t zone = (0u - n) % n;
+        while (low < zone) {
+            m = (uint64_t)rs_next32(s) * n;
+            low = (uint32_t)m;
+        }
+    }
+    return (uint32_t)(m >> 32);
+}
+
+__device__ __forceinline__ uint64_t rs_below64(RandStream& s, uint64_t n) {
+    uint64_t x = rs_next64(s);
+    uint64_t low = x * n;
+    uint64_t high = __umul64hi(x, n);
+    if (low < n) {
+        const uint64_t zone = (0ull - n) % n;
+        while (low < zone) {
+            x = rs_next64(s);
+            low = x * n;
+            high = __umul64hi(x, n);
+        }
+    }
+    return high;
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// ---------------------------------------------------------------------------
+// Host-side graph handle.
+// ---------------------------------------------------------------------------
+struct bingo_graph {
+    uint32_t n;
+    GroupRule rule;
+    uint32_t* hdr;          // n * HDR_WORDS
+    uint32_t* pool;         // device arena, pool_words u32
+    uint64_t pool_words;
+    unsigned long long* d_ctl;  // [0] words used, [1] garbage words
+    uint32_t* d_err;        // sticky error bits
+    // last PPR result
+    uint64_t* ppr_off = nullptr;
+    uint32_t* ppr_vtx = nullptr;
+    uint32_t* ppr_cnt = nullptr;
+    uint64_t ppr_entries = 0, ppr_cap = 0;
+    uint32_t ppr_nsrc = 0, ppr_off_cap = 0;
+    // grow-only scratch for sorts, scans and temporaries
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // ring of per-call counter slots for walks (queue head, transitions)
+    uint32_t walk_slot = 0;
+    // per-phase timing of the last walk / PPR / update call (events on its stream)
+    hipEvent_t ev[PHASE_EVENTS] = {};
+    uint32_t nev = 0;
+};
+void phase_mark(bingo_graph* g, hipStream_t st, bool first);
+// d_ctl layout (u64): [0] pool words used, [1] garbage words, [2..15] PPR and
+// update counters, [16 + 2*i .. 17 + 2*i] walk call slot i (WALK_SLOTS slots).
+#define CTL_WALK0 16
+#define WALK_SLOTS 64
+#define CTL_WORDS (CTL_WALK0 + 2 * WALK_SLOTS)
+
+#define HIPCHK(x)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) {                                                    \
+            fprintf(stderr, "libbingo: %s failed: %s (%s:%d)\n", #x,              \
+                    hipGetErrorString(e_), __FILE__, __LINE__);                    \
+            return BINGO_E_HIP;                                                    \
+        }                                                                          \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Host launchers implemented in the .hip files.
+// ---------------------------------------------------------------------------
+// prim.hip: scans and LSD radix sort (stable), all on `stream`.
+size_t scan_temp_bytes(uint64_t n);
+// exclusive scan of n u32 or u64 values into u64 out; out may alias nothing; writes total to *d_total if non-null
+void scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, void* temp, unsigned long long* d_total,
+                     hipStream_t st);
+void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, void* temp, unsigned long long* d_total,
+              hipStream_t st);
+size_t sort_temp_bytes(uint64_t n, bool wide_keys);
+// stable sort of (keys, vals) by bits [0, bits) of the key; results in keys_out/vals_out
+void sort_pairs_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                    uint64_t n, int bits, void* temp, hipStream_t st);
+void sort_pairs_u64(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* keys_out, uint32_t* vals_out,
+                    uint64_t n, int bits, void* temp, hipStream_t st);
+void sort_keys_u64(const uint64_t* keys_in, uint64_t* keys_out, uint64_t n, int bits, void* temp,
+                   hipStream_t st);
+
+// build.hip
+int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
+                hipStream_t st);
+// walk.hip
+int launch_walk(bingo_graph* g, uint64_t n_walks, const uint32_t* starts, uint64_t base, uint32_t len,
+                uint64_t seed, uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st);
+int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr, uint32_t cap,
+            uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps,
+            hipStream_t st);
+// export.hip
+int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
+                 hipStream_t st);
+int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
+// update.hip
+int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
+                 uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats,
+                 hipStream_t st);
+// api.hip
+void* ws_get(bingo_graph* g, size_t bytes);  // grow-only scratch (synchronizes when it grows)
+int err_to_code(uint32_t bits);

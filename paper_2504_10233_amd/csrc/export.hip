@@ -1,0 +1,187 @@
+// export.hip -- canonical dump of the structure (the layout is defined in
+// bingo.h) and memory statistics, including the paper's memory model with and
+// without group adaption (Sec. 4.4 space complexity, Sec. 6.2).
+#include "dev.h"
+#include <stdio.h>
+#include <algorithm>
+#include <vector>
+
+namespace {
+
+constexpr int WB = 256;
+
+__device__ __forceinline__ uint32_t stored_words(uint32_t t, uint32_t c) {
+    return t == GT_ONE ? 1u : (type_listed(t) ? c : 0u);
+}
+
+__global__ void k_dump_size(const uint32_t* __restrict__ hdr, uint32_t u0, uint32_t u1, GroupRule rule,
+                            uint64_t* __restrict__ sz) {
+    const uint32_t u = u0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= u1) return;
+    const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    const uint32_t d = h[H_DEG], mask = h[H_MASK];
+    uint64_t s = 3 + 3ull * d;
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
+        const int k = __ffs(mm) - 1;
+        const uint32_t c = h[H_CNT + k];
+        s += 3 + stored_words(group_type(c, d, rule), c);
+    }
+    sz[u - u0] = s;
+}
+
+__global__ void __launch_bounds__(WB) k_dump_write(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                                   uint32_t u0, uint32_t u1, GroupRule rule,
+                                                   const uint64_t* __restrict__ off, uint32_t* __restrict__ out) {
+    const uint32_t u = u0 + blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= u1) return;
+    const uint32_t lane = lane_id();
+    const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    const uint32_t d = h[H_DEG], mask = h[H_MASK];
+    uint32_t* o = out + off[u - u0];
+    if (lane == 0) { o[0] = d; o[1] = h[H_NSEQ]; o[2] = mask; }
+    const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+    const uint32_t cap = h[H_ACAP];
+    const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
+    const uint32_t* seqs = pool + adj + 2ull * cap;
+    for (uint32_t i = lane; i < d; i += 64) {
+        const uint64_t e = edges[i];
+        o[3 + 3 * (uint64_t)i] = (uint32_t)e;
+        o[4 + 3 * (uint64_t)i] = (uint32_t)(e >> 32);
+        o[5 + 3 * (uint64_t)i] = seqs[i];
+    }
+    // group records in ascending k: lane k computes its record's size and start
+    const bool ne = lane < 32 && ((mask >> lane) & 1u);
+    const uint32_t c = ne ? h[H_CNT + lane] : 0u;
+    const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+    const uint64_t sz = ne ? 3ull + stored_words(t, c) : 0ull;
+    uint64_t x = sz;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const uint64_t y = __shfl_up(x, s, 64);
+        if (lane >= (uint32_t)s) x += y;
+    }
+    const uint64_t my = 3 + 3ull * d + (x - sz);
+    const uint32_t info = ne ? h[H_INFO + lane] : 0u;
+    if (ne) {
+        o[my] = lane;
+        o[my + 1] = t;
+        o[my + 2] = c;
+        if (t == GT_ONE) o[my + 3] = info;
+    }
+    uint32_t lm = (uint32_t)(__ballot(ne && type_listed(t)) & 0xFFFFFFFFull);
+    while (lm) {
+        const int k = __ffs(lm) - 1;
+        lm &= lm - 1;
+        const uint64_t dst0 = __shfl(my, k, 64) + 3;
+        const uint32_t ck = __shfl(c, k, 64);
+        const uint64_t src0 = (uint64_t)__shfl(info, k, 64) * LIST_UNIT_WORDS;
+        for (uint32_t i = lane; i < ck; i += 64) o[dst0 + i] = pool[src0 + i];
+    }
+}
+
+// memory statistics: [0] groups by type (5), [5] list live bytes, [6] list reserved bytes,
+// [10] adjacency reserved bytes, [11] GA model bytes, [12] BS model bytes, [13] edges
+__global__ void __launch_bounds__(WB) k_mem(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                            uint32_t n, GroupRule rule, unsigned long long* __restrict__ acc) {
+    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    const uint32_t d = h[H_DEG], mask = h[H_MASK];
+    const bool ne = lane < 32 && ((mask >> lane) & 1u);
+    const uint32_t c = ne ? h[H_CNT + lane] : 0u;
+    const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+    const uint32_t capb = lane < 32 ? ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
+    const uint32_t smask = (uint32_t)(__ballot(ne && t == GT_SPARSE) & 0xFFFFFFFFull);
+    // |S(u)|: edges in at least one sparse group
+    uint64_t S = 0;
+    if (smask) {
+        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
+        for (uint32_t i0 = 0; i0 < d; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            const bool in = i < d && ((uint32_t)(edges[i] >> 32) & smask);
+            S += __popcll(__ballot(in));
+        }
+    }
+    uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0};  // live list, reserved list, ga, bs
+    if (ne) {
+        if (type_listed(t)) { v[0] = 4ull * c; v[1] = 4ull << capb; }
+        v[2] = t == GT_ONE ? 4ull : (t == GT_SPARSE ? 4ull * c + 4ull * S : (t == GT_REGULAR ? 4ull * (c + (uint64_t)d) : 0));
+        v[3] = 4ull * (c + (uint64_t)d);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
+    // groups by type
+    uint64_t cnt_t[5];
+#pragma unroll
+    for (int tt = 0; tt < 5; ++tt) cnt_t[tt] = __popcll(__ballot(ne && t == (uint32_t)tt));
+    if (lane == 0) {
+        for (int tt = 1; tt < 5; ++tt) if (cnt_t[tt]) atomicAdd(acc + tt, (unsigned long long)cnt_t[tt]);
+        if (v[0]) atomicAdd(acc + 5, (unsigned long long)v[0]);
+        if (v[1]) atomicAdd(acc + 6, (unsigned long long)v[1]);
+        atomicAdd(acc + 10, 12ull * h[H_ACAP]);
+        atomicAdd(acc + 11, (unsigned long long)(v[2] + 4ull * S + 12ull * d));
+        atomicAdd(acc + 12, (unsigned long long)(v[3] + 12ull * d));
+        atomicAdd(acc + 13, (unsigned long long)d);
+    }
+}
+
+}  // namespace
+
+int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
+                 hipStream_t st) {
+    if (u1 > g->n || u0 > u1) return BINGO_E_INVALID;
+    const uint32_t nv = u1 - u0;
+    if (nv == 0) { *h_len = 0; return BINGO_OK; }
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    char* ws = (char*)ws_get(g, 2 * al((uint64_t)nv * 8) + scan_temp_bytes(nv) + 512);
+    if (!ws) return BINGO_E_OOM;
+    uint64_t* sz = (uint64_t*)ws;
+    uint64_t* off = (uint64_t*)(ws + al((uint64_t)nv * 8));
+    unsigned long long* total = (unsigned long long*)(ws + 2 * al((uint64_t)nv * 8));
+    void* tmp = ws + 2 * al((uint64_t)nv * 8) + 256;
+    hipLaunchKernelGGL(k_dump_size, dim3((nv + 255) / 256), dim3(256), 0, st, g->hdr, u0, u1, g->rule, sz);
+    scan_u64(sz, off, nv, tmp, total, st);
+    unsigned long long T = 0;
+    HIPCHK(hipMemcpyAsync(&T, total, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *h_len = T;
+    if (!h_buf) return BINGO_OK;
+    if (cap < T) return BINGO_E_CAPACITY;
+    uint32_t* dbuf = nullptr;
+    if (hipMalloc(&dbuf, std::max<uint64_t>(T, 1) * 4) != hipSuccess) return BINGO_E_OOM;
+    hipLaunchKernelGGL(k_dump_write, dim3((nv + 3) / 4), dim3(WB), 0, st, g->hdr, g->pool, u0, u1, g->rule,
+                       (const uint64_t*)off, dbuf);
+    hipError_t e1 = hipMemcpyAsync(h_buf, dbuf, T * 4, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipFree(dbuf);
+    return (e1 == hipSuccess && e2 == hipSuccess) ? BINGO_OK : BINGO_E_HIP;
+}
+
+int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st) {
+    unsigned long long* acc = (unsigned long long*)ws_get(g, 16 * 8);
+    if (!acc) return BINGO_E_OOM;
+    HIPCHK(hipMemsetAsync(acc, 0, 16 * 8, st));
+    hipLaunchKernelGGL(k_mem, dim3((g->n + 3) / 4), dim3(WB), 0, st, g->hdr, g->pool, g->n, g->rule, acc);
+    unsigned long long a[16], ctl[2];
+    HIPCHK(hipMemcpyAsync(a, acc, sizeof a, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->vertices = g->n;
+    out->edges = a[13];
+    out->pool_bytes = g->pool_words * 4;
+    out->pool_used_bytes = ctl[0] * 4;
+    out->pool_garbage_bytes = ctl[1] * 4;
+    out->header_bytes = (uint64_t)g->n * HDR_WORDS * 4;
+    out->adjacency_bytes = 12ull * a[13];
+    out->adjacency_reserved_bytes = a[10];
+    out->list_bytes = a[5];
+    out->list_reserved_bytes = a[6];
+    for (int t = 0; t < 5; ++t) out->groups_by_type[t] = t ? a[t] : 0;
+    out->model_ga_bytes = a[11];
+    out->model_bs_bytes = a[12];
+    return BINGO_OK;
+}

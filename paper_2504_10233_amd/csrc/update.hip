@@ -1,0 +1,789 @@
+// update.hip -- batched edge insertions and deletions (Sec. 5.2, Fig. 10;
+// Sec. 4.2 insertion / deletion on the radix groups).
+//
+// Pipeline (all on one stream):
+//   1. validate; sort records by (src, op, dst) keeping batch order for inserts;
+//      segment into touched vertices (the "group updates by vertex" step).
+//   2. match deletes: every live edge and every insert of a touched vertex is
+//      looked up among that vertex's delete targets; candidates are sorted by
+//      (delete run, sequence number) so each run of k identical delete records
+//      takes the k oldest live occurrences.
+//   3. per touched vertex, the set X of deleted indices (sorted).
+//   4. analysis (one wave per vertex): new counts c'_k, new degree, new types,
+//      and the pool words needed; one scan and one bump allocate them.
+//   5. mutation (one wave per vertex): two-phase delete-and-swap on the
+//      adjacency (holes below the new degree filled by tail survivors in rank
+//      order), appends, the same rule on every listed group that keeps its type,
+//      renames of moved indices, fresh lists for groups that change type, and
+//      the new header (the inter-group space, updated once per vertex).
+#include "dev.h"
+#include <stdio.h>
+#include <algorithm>
+#include <string.h>
+
+namespace {
+
+constexpr int TB = 256;
+constexpr int WB = 256;
+constexpr uint32_t NF = 0xFFFFFFFFu;
+constexpr uint32_t MB = 1024;  // flat elements per matching block
+
+__host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
+    if (d == 0) return 0;
+    uint32_t c = 2;
+    while (c < d) c <<= 1;
+    return c;
+}
+__host__ __device__ inline uint64_t adj_block_words(uint32_t cap) { return ((uint64_t)cap * 3 + 7) & ~7ull; }
+__host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
+    uint32_t x = 8;
+    while (x < c) x <<= 1;
+    return x;
+}
+
+inline uint32_t grid_for(uint64_t n) {
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n + TB - 1) / TB, 1), 1u << 20);
+}
+int bits_for(uint64_t v) {
+    int b = 0;
+    while (b < 64 && (v >> b)) ++b;
+    return b;
+}
+
+#define GRID_LOOP(i, n) for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
+
+__global__ void k_upd_validate(uint32_t n, uint64_t ni, const uint32_t* __restrict__ is, const uint32_t* __restrict__ id,
+                               const uint32_t* __restrict__ iw, uint64_t nd, const uint32_t* __restrict__ ds,
+                               const uint32_t* __restrict__ dd, uint32_t* __restrict__ err) {
+    uint32_t bad = 0;
+    GRID_LOOP(i, ni) {
+        if (is[i] >= n || id[i] >= n) bad |= ERR_RANGE;
+        if (iw[i] == 0) bad |= ERR_WEIGHT;
+    }
+    GRID_LOOP(i, nd) {
+        if (ds[i] >= n || dd[i] >= n) bad |= ERR_RANGE;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// insert j: key (src << (vb+1)); delete j: key (src << (vb+1)) | 1 << vb | dst
+__global__ void k_upd_keys(uint64_t ni, uint64_t nd, const uint32_t* __restrict__ is, const uint32_t* __restrict__ ds,
+                           const uint32_t* __restrict__ dd, int vb, uint64_t* __restrict__ keys,
+                           uint32_t* __restrict__ vals) {
+    GRID_LOOP(r, ni + nd) {
+        if (r < ni) {
+            keys[r] = (uint64_t)is[r] << (vb + 1);
+        } else {
+            const uint64_t j = r - ni;
+            keys[r] = ((uint64_t)ds[j] << (vb + 1)) | (1ull << vb) | dd[j];
+        }
+        vals[r] = (uint32_t)r;
+    }
+}
+
+__device__ __forceinline__ uint32_t key_src(uint64_t k, int vb) { return (uint32_t)(k >> (vb + 1)); }
+__device__ __forceinline__ uint32_t key_op(uint64_t k, int vb) { return (uint32_t)(k >> vb) & 1u; }
+__device__ __forceinline__ uint32_t key_dst(uint64_t k, int vb) { return (uint32_t)(k & ((1ull << vb) - 1)); }
+
+__global__ void k_seg_heads(const uint64_t* __restrict__ sk, uint64_t R, int vb, uint32_t* __restrict__ head) {
+    GRID_LOOP(p, R) head[p] = (p == 0 || key_src(sk[p], vb) != key_src(sk[p - 1], vb)) ? 1u : 0u;
+}
+
+// per touched vertex t: tv (vertex), ts (first record), tdl (first delete record)
+__global__ void k_seg_fill(const uint64_t* __restrict__ sk, uint64_t R, int vb, const uint32_t* __restrict__ head,
+                           const uint64_t* __restrict__ hx, uint32_t* __restrict__ tv, uint32_t* __restrict__ ts,
+                           uint32_t* __restrict__ tdl, uint32_t* __restrict__ rec_t) {
+    GRID_LOOP(p, R) {
+        const uint64_t t = hx[p] + head[p] - 1;
+        rec_t[p] = (uint32_t)t;
+        if (head[p]) { tv[t] = key_src(sk[p], vb); ts[t] = (uint32_t)p; }
+        if (key_op(sk[p], vb) && (head[p] || !key_op(sk[p - 1], vb))) tdl[t] = (uint32_t)p;
+    }
+}
+
+__global__ void k_seg_end(uint64_t T, uint64_t R, const uint32_t* __restrict__ ts, uint32_t* __restrict__ te,
+                          uint32_t* __restrict__ tdl, const uint32_t* __restrict__ hdr, uint64_t* __restrict__ fsz) {
+    GRID_LOOP(t, T) {
+        const uint32_t end = (t + 1 < T) ? ts[t + 1] : (uint32_t)R;
+        te[t] = end;
+        if (tdl[t] == NF) tdl[t] = end;
+    }
+}
+
+// flat size of the delete-matching space of t: its live edges and its inserts
+__global__ void k_flat_size(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                            const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                            const uint32_t* __restrict__ hdr, uint64_t* __restrict__ fsz) {
+    GRID_LOOP(t, T) {
+        const uint32_t nd = te[t] - tdl[t];
+        const uint32_t ni = tdl[t] - ts[t];
+        fsz[t] = nd ? (uint64_t)hdr[(size_t)tv[t] * HDR_WORDS + H_DEG] + ni : 0ull;
+    }
+}
+
+// last t with foff[t] <= f, searching in [lo, hi]
+__device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, uint32_t lo, uint32_t hi, uint64_t f) {
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (foff[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Candidate search.  Mode 0 counts, mode 1 writes (run << 32 | seq, virtual index).
+__global__ void __launch_bounds__(TB) k_match(int mode, uint64_t F, uint64_t T, const uint64_t* __restrict__ foff,
+                                              const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                                              const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                                              const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv,
+                                              int vb, const uint32_t* __restrict__ id, const uint32_t* __restrict__ hdr,
+                                              const uint32_t* __restrict__ pool, unsigned long long* __restrict__ cnt,
+                                              uint64_t* __restrict__ ckey, uint32_t* __restrict__ cval, uint64_t cap) {
+    __shared__ uint32_t range[2];
+    const uint64_t f0 = (uint64_t)blockIdx.x * MB;
+    if (threadIdx.x == 0) {
+        range[0] = find_t(foff, 0, (uint32_t)T - 1, f0);
+        range[1] = find_t(foff, range[0], (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
+    }
+    __syncthreads();
+    const uint32_t tlo = range[0], thi = range[1];
+    for (uint32_t s = 0; s < MB; s += TB) {
+        const uint64_t f = f0 + s + threadIdx.x;
+        bool hit = false;
+        uint64_t key = 0;
+        uint32_t vidx = 0;
+        if (f < F) {
+            const uint32_t t = find_t(foff, tlo, thi, f);
+            const uint32_t i = (uint32_t)(f - foff[t]);
+            const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+            const uint32_t d = h[H_DEG];
+            uint32_t dst, seq;
+            if (i < d) {
+                const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+                dst = pool[adj + 2ull * i];
+                seq = pool[adj + 2ull * h[H_ACAP] + i];
+            } else {
+                const uint32_t a = i - d;
+                dst = id[sv[ts[t] + a]];
+                seq = h[H_NSEQ] + a;
+            }
+            // lower bound of dst among the delete records of t (sorted by dst)
+            uint32_t lo = tdl[t], hi = te[t];
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (key_dst(sk[mid], vb) < dst) lo = mid + 1; else hi = mid;
+            }
+            if (lo < te[t] && key_dst(sk[lo], vb) == dst) {
+                hit = true;
+                key = ((uint64_t)lo << 32) | seq;
+                vidx = i;
+            }
+        }
+        const uint64_t m = __ballot(hit);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long b = 0;
+            if ((int)lane_id() == leader) b = atomicAdd(cnt, (unsigned long long)__popcll(m));
+            b = __shfl(b, leader, 64);
+            if (mode == 1 && hit) {
+                const uint64_t pos = b + __popcll(m & lanemask_lt());
+                if (pos < cap) { ckey[pos] = key; cval[pos] = vidx; }
+            }
+        }
+    }
+}
+
+// first candidate position of every run (candidates sorted by run, then seq)
+__global__ void k_cand_first(const uint64_t* __restrict__ ck, uint64_t C, uint32_t* __restrict__ first) {
+    GRID_LOOP(c, C) {
+        const uint32_t run = (uint32_t)(ck[c] >> 32);
+        if (c == 0 || (uint32_t)(ck[c - 1] >> 32) != run) first[run] = (uint32_t)c;
+    }
+}
+
+// the rank-th oldest occurrence goes to the rank-th record of the run
+__global__ void k_cand_assign(const uint64_t* __restrict__ ck, const uint32_t* __restrict__ cv, uint64_t C,
+                              const uint32_t* __restrict__ first, const uint64_t* __restrict__ sk, uint64_t R,
+                              const uint32_t* __restrict__ rec_t, uint32_t* __restrict__ matched,
+                              uint32_t* __restrict__ ncnt) {
+    GRID_LOOP(c, C) {
+        const uint32_t run = (uint32_t)(ck[c] >> 32);
+        const uint32_t rank = (uint32_t)c - first[run];
+        // run length: records with exactly the same key
+        uint64_t lo = run, hi = R;
+        const uint64_t key = sk[run];
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (sk[mid] <= key) lo = mid + 1; else hi = mid;
+        }
+        if (rank < lo - run) {
+            matched[run + rank] = cv[c];
+            atomicAdd(&ncnt[rec_t[run]], 1u);
+        }
+    }
+}
+
+__global__ void k_xkeys(uint64_t R, const uint32_t* __restrict__ matched, const uint32_t* __restrict__ rec_t,
+                        uint64_t pad, uint64_t* __restrict__ xk) {
+    GRID_LOOP(p, R) xk[p] = matched[p] != NF ? (((uint64_t)rec_t[p] << 32) | matched[p]) : pad;
+}
+
+__global__ void k_xextract(uint64_t R, const uint64_t* __restrict__ xk, uint32_t* __restrict__ xs) {
+    GRID_LOOP(p, R) xs[p] = (uint32_t)xk[p];
+}
+
+// ---------------------------------------------------------------------------
+// per-vertex state shared by the analysis and mutation kernels
+// ---------------------------------------------------------------------------
+struct VState {
+    uint32_t u, d, cap, nseq, mask;
+    uint64_t adj;
+    uint32_t ts, ni, nd, N, xoff;
+    uint32_t d1, dn;
+    // lane k < 32
+    uint32_t c, cn, app, del, told, tnew, lcap, info;
+};
+
+__device__ __forceinline__ uint32_t ins_rec(const uint32_t* __restrict__ sv, uint32_t ts, uint32_t a) {
+    return sv[ts + a];
+}
+
+// weight of virtual index x: an old edge (x < d) or insert x - d
+__device__ __forceinline__ uint32_t vweight(uint32_t x, const VState& s, const uint32_t* __restrict__ pool,
+                                            const uint32_t* __restrict__ sv, const uint32_t* __restrict__ iw) {
+    if (x < s.d) return pool[s.adj + 2ull * x + 1];
+    return iw[sv[s.ts + (x - s.d)]];
+}
+
+__device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                           const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                           const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
+                           const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
+                           const uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
+                           const uint32_t* __restrict__ iw, GroupRule rule) {
+    const uint32_t lane = lane_id();
+    s.u = tv[t];
+    const uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
+    s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ]; s.mask = h[H_MASK];
+    s.adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+    s.ts = ts[t]; s.ni = tdl[t] - ts[t]; s.nd = te[t] - tdl[t];
+    s.N = ncnt[t]; s.xoff = (uint32_t)xoff[t];
+    s.d1 = s.d + s.ni; s.dn = s.d1 - s.N;
+    s.c = lane < 32 ? h[H_CNT + lane] : 0u;
+    s.info = lane < 32 ? h[H_INFO + lane] : 0u;
+    s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
+    s.told = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
+    // bit counts of the inserts and of the deleted entries
+    uint32_t app = 0, del = 0;
+    for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+        const uint32_t a = a0 + lane;
+        const uint32_t w = a < s.ni ? vweight(s.d + a, s, pool, sv, iw) : 0u;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const uint64_t b = __ballot((w >> k) & 1u);
+            if (lane == (uint32_t)k) app += __popcll(b);
+        }
+    }
+    const uint32_t* X = xs + s.xoff;
+    for (uint32_t j0 = 0; j0 < s.N; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const uint32_t w = j < s.N ? vweight(X[j], s, pool, sv, iw) : 0u;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const uint64_t b = __ballot((w >> k) & 1u);
+            if (lane == (uint32_t)k) del += __popcll(b);
+        }
+    }
+    s.app = app; s.del = del;
+    s.cn = s.c + app - del;
+    s.tnew = lane < 32 ? group_type(s.cn, s.dn, rule) : GT_EMPTY;
+}
+
+__device__ __forceinline__ bool kept_listed(const VState& s) { return type_listed(s.told) && s.tnew == s.told; }
+
+// pool words this vertex allocates: a larger adjacency block, list blocks
+__device__ __forceinline__ uint64_t lane_list_need(const VState& s) {
+    if (!type_listed(s.tnew)) return 0;
+    if (kept_listed(s)) return s.cn > s.lcap ? (uint64_t)list_cap_for(s.cn) : 0ull;
+    return (uint64_t)list_cap_for(s.cn);
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ void __launch_bounds__(WB) k_analyze(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
+                                                const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
+                                                const uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
+                                                const uint32_t* __restrict__ iw, GroupRule rule,
+                                                uint64_t* __restrict__ need, unsigned long long* __restrict__ stats) {
+    const uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (t >= T) return;
+    VState s;
+    load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
+    const uint32_t lane = lane_id();
+    uint64_t w = lane_list_need(s);
+    if (lane == 0 && s.dn > s.cap) w += adj_block_words(adj_cap_for(s.dn));
+    w = wave_sum(w);
+    // type transitions over all 32 groups of the vertex
+    const uint32_t code = lane < 32 ? s.told * 5 + s.tnew : 31u;
+    uint32_t my = 0;
+#pragma unroll
+    for (int c = 0; c < 25; ++c) {
+        const uint32_t k = __popcll(__ballot(code == (uint32_t)c));
+        if (lane == (uint32_t)c) my = k;
+    }
+    if (lane == 0) {
+        need[t] = w;
+        atomicAdd(stats + 0, (unsigned long long)s.ni);
+        atomicAdd(stats + 1, (unsigned long long)s.N);
+        atomicAdd(stats + 2, (unsigned long long)(s.nd - s.N));
+    }
+    if (lane < 25 && my) atomicAdd(stats + 3 + lane, (unsigned long long)my);
+}
+
+// ---------------------------------------------------------------------------
+// mutation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ bool in_set(const uint32_t* __restrict__ X, uint32_t N, uint32_t v) {
+    const uint32_t p = lower_bound_u32(X, N, v);
+    return p < N && X[p] == v;
+}
+// new index of a surviving virtual index v (adjacency two-phase rule)
+__device__ __forceinline__ uint32_t rho(uint32_t v, const uint32_t* __restrict__ X, uint32_t N, uint32_t dn,
+                                        uint32_t nholes) {
+    if (v < dn) return v;
+    const uint32_t j = (v - dn) - (lower_bound_u32(X, N, v) - nholes);
+    return X[j];
+}
+
+// virtual list entry p of a kept group k: the old list, then new members (inserts with bit k)
+// in insert order.  Positions p >= c are enumerated by the insert scans below.
+
+__global__ void __launch_bounds__(WB) k_mutate(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
+                                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
+                                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
+                                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
+                                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
+                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ garbage) {
+    const uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (t >= T) return;
+    VState s;
+    load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
+    const uint32_t lane = lane_id();
+    const uint32_t* X = xs + s.xoff;
+    const uint32_t N = s.N;
+    const uint32_t nholes = lower_bound_u32(X, N, s.dn);  // X entries below the new degree
+    uint64_t abase = abase0 + aoff[t];
+    uint64_t freed = 0;
+
+    // ---- adjacency
+    uint64_t nadj = s.adj;
+    uint32_t ncap = s.cap;
+    if (s.dn > s.cap) {
+        ncap = adj_cap_for(s.dn);
+        nadj = abase;
+        abase += adj_block_words(ncap);
+        freed += adj_block_words(s.cap) * (s.cap > 0);
+    }
+    uint64_t* eold = reinterpret_cast<uint64_t*>(pool + s.adj);
+    const uint32_t* qold = pool + s.adj + 2ull * s.cap;
+    uint64_t* enew = reinterpret_cast<uint64_t*>(pool + nadj);
+    uint32_t* qnew = pool + nadj + 2ull * ncap;
+    const uint32_t keep = s.d < s.dn ? s.d : s.dn;
+    if (nadj != s.adj) {
+        for (uint32_t i = lane; i < keep; i += 64) { enew[i] = eold[i]; qnew[i] = qold[i]; }
+    }
+    __threadfence_block();
+    // inserts that stay where they were appended
+    for (uint32_t q = s.d + lane; q < s.dn; q += 64) {
+        if (!in_set(X, N, q)) {
+            const uint32_t a = q - s.d, r = sv[s.ts + a];
+            enew[q] = (uint64_t)id[r] | ((uint64_t)iw[r] << 32);
+            qnew[q] = s.nseq + a;
+        }
+    }
+    // tail survivors fill the holes in rank order
+    for (uint32_t q = s.dn + lane; q < s.d1; q += 64) {
+        if (!in_set(X, N, q)) {
+            const uint32_t dest = rho(q, X, N, s.dn, nholes);
+            uint64_t e;
+            uint32_t sq;
+            if (q < s.d) { e = eold[q]; sq = qold[q]; }
+            else { const uint32_t a = q - s.d, r = sv[s.ts + a]; e = (uint64_t)id[r] | ((uint64_t)iw[r] << 32); sq = s.nseq + a; }
+            enew[dest] = e;
+            qnew[dest] = sq;
+        }
+    }
+    __threadfence_block();
+
+    // ---- listed groups that keep their type
+    uint32_t newinfo = 0, newlcap = s.lcap;
+    const bool kl = lane < 32 && kept_listed(s);
+    uint32_t km = (uint32_t)(__ballot(kl) & 0xFFFFFFFFull);
+    // per-lane (k) new block for kept lists that outgrow their capacity, or fresh lists
+    const uint64_t lneed = lane < 32 ? lane_list_need(s) : 0ull;
+    uint64_t lx = lneed;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(lx, o, 64);
+        if (lane >= (uint32_t)o) lx += y;
+    }
+    const uint64_t my_block = abase + (lx - lneed);
+    abase += __shfl(lx, 63, 64);
+    uint32_t* S = sur + s.xoff;
+    while (km) {
+        const int k = __ffs(km) - 1;
+        km &= km - 1;
+        const uint32_t ck = __shfl(s.c, k, 64), cnk = __shfl(s.cn, k, 64), appk = __shfl(s.app, k, 64);
+        const uint32_t lcapk = __shfl(s.lcap, k, 64);
+        const uint64_t oblk = (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
+        const uint64_t nblk = cnk > lcapk ? __shfl(my_block, k, 64) : oblk;
+        const uint32_t lenv = ck + appk;
+        const uint32_t* Lold = pool + oblk;
+        uint32_t* Lnew = pool + nblk;
+        // pass B: survivors of the tail window [cnk, lenv) in order -> S[]
+        uint32_t nsur = 0;
+        // old-list part of the window
+        for (uint32_t p0 = cnk; p0 < ck; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            const bool v = p < ck;
+            const uint32_t e = v ? Lold[p] : 0u;
+            const bool surv = v && !in_set(X, N, e);
+            const uint64_t b = __ballot(surv);
+            if (surv) S[nsur + __popcll(b & lanemask_lt())] = rho(e, X, N, s.dn, nholes);
+            nsur += __popcll(b);
+        }
+        // new-member part: inserts with bit k, position ck + rank
+        uint32_t rank = 0;
+        for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+            const uint32_t a = a0 + lane;
+            const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+            const uint64_t b = __ballot(v);
+            const uint32_t p = ck + rank + __popcll(b & lanemask_lt());
+            const uint32_t e = s.d + a;
+            const bool inwin = v && p >= cnk;
+            const bool surv = inwin && !in_set(X, N, e);
+            const uint64_t sb = __ballot(surv);
+            if (surv) S[nsur + __popcll(sb & lanemask_lt())] = rho(e, X, N, s.dn, nholes);
+            nsur += __popcll(sb);
+            rank += __popcll(b);
+        }
+        __threadfence_block();
+        // pass A: final entries [0, cnk): kept entries renamed, holes take S[] in rank order
+        uint32_t nh = 0;
+        const uint32_t oldpart = ck < cnk ? ck : cnk;
+        for (uint32_t p0 = 0; p0 < oldpart; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            const bool v = p < oldpart;
+            const uint32_t e = v ? Lold[p] : 0u;
+            const bool hole = v && in_set(X, N, e);
+            const uint64_t hb = __ballot(hole);
+            if (v) {
+                const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
+                if (val != e || nblk != oblk) Lnew[p] = val;
+            }
+            nh += __popcll(hb);
+        }
+        if (cnk > ck) {
+            // new members at positions [ck, cnk)
+            uint32_t r2 = 0;
+            for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+                const uint32_t a = a0 + lane;
+                const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+                const uint64_t b = __ballot(v);
+                const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
+                const uint32_t e = s.d + a;
+                const bool inpre = v && p < cnk;
+                const bool hole = inpre && in_set(X, N, e);
+                const uint64_t hb = __ballot(hole);
+                if (inpre) Lnew[p] = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
+                nh += __popcll(hb);
+                r2 += __popcll(b);
+            }
+        }
+        __threadfence_block();
+        if (lane == (uint32_t)k) {
+            newinfo = (uint32_t)(nblk / LIST_UNIT_WORDS);
+            if (nblk != oblk) { newlcap = list_cap_for(cnk); freed += lcapk; }
+        }
+    }
+
+    // ---- groups that become listed or switch between sparse and regular: fresh lists
+    const bool fresh = lane < 32 && type_listed(s.tnew) && !kept_listed(s);
+    if (fresh) { newinfo = (uint32_t)(my_block / LIST_UNIT_WORDS); newlcap = list_cap_for(s.cn); }
+    if (lane < 32 && type_listed(s.told) && !kept_listed(s)) freed += s.lcap;
+    const uint32_t fm = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
+    // one-element groups: the surviving member
+    const bool one = lane < 32 && s.tnew == GT_ONE;
+    uint32_t member = NF;
+    if (one) {
+        if (s.told == GT_ONE && !in_set(X, N, s.info)) member = rho(s.info, X, N, s.dn, nholes);
+    }
+    // members found among the inserts
+    {
+        for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+            const uint32_t a = a0 + lane;
+            const bool v = a < s.ni;
+            const uint32_t e = s.d + a;
+            const uint32_t w = v && !in_set(X, N, e) ? iw[sv[s.ts + a]] : 0u;
+            const uint32_t dest = w ? rho(e, X, N, s.dn, nholes) : 0u;
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const uint64_t b = __ballot((w >> k) & 1u);
+                if (b) {
+                    const int src = __ffsll((long long)b) - 1;
+                    const uint32_t cand = __shfl(dest, src, 64);
+                    if (lane == (uint32_t)k && one && member == NF) member = cand;
+                }
+            }
+        }
+    }
+    const uint32_t need_scan = (uint32_t)(__ballot(one && member == NF) & 0xFFFFFFFFull);
+    if (fm | need_scan) {
+        // one pass over the final adjacency
+        uint32_t fill = 0;
+        for (uint32_t i0 = 0; i0 < s.dn; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            const uint32_t w = i < s.dn ? (uint32_t)(enew[i] >> 32) : 0u;
+            uint32_t mm = fm | need_scan;
+            while (mm) {
+                const int k = __ffs(mm) - 1;
+                mm &= mm - 1;
+                const bool bit = (w >> k) & 1u;
+                const uint64_t b = __ballot(bit);
+                if ((fm >> k) & 1u) {
+                    const uint64_t blk = (uint64_t)__shfl(newinfo, k, 64) * LIST_UNIT_WORDS;
+                    const uint32_t f = __shfl(fill, k, 64);
+                    if (bit) pool[blk + f + __popcll(b & lanemask_lt())] = i;
+                    if (lane == (uint32_t)k) fill += __popcll(b);
+                } else if (b) {
+                    const uint32_t first = i0 + (__ffsll((long long)b) - 1);
+                    if (lane == (uint32_t)k && member == NF) member = first;
+                }
+            }
+        }
+    }
+
+    // ---- header: the inter-group sampling space of the vertex
+    uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
+    const bool ne = lane < 32 && s.cn > 0;
+    const uint64_t wsum = wave_sum(ne ? ((uint64_t)s.cn << lane) : 0ull);
+    const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
+    if (lane < 32) {
+        h[H_CNT + lane] = s.cn;
+        uint32_t inf = 0;
+        if (type_listed(s.tnew)) inf = newinfo;
+        else if (s.tnew == GT_ONE) inf = member;
+        h[H_INFO + lane] = inf;
+    }
+    const uint32_t lg = (lane < 32 && type_listed(s.tnew)) ? (31 - __clz(newlcap)) : 0u;
+    uint32_t packed = lg << (8 * (lane & 3));
+    packed |= __shfl_xor(packed, 1);
+    packed |= __shfl_xor(packed, 2);
+    if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
+    freed = wave_sum(freed);
+    if (lane == 0) {
+        h[H_MASK] = nmask;
+        h[H_DEG] = s.dn;
+        h[H_WLO] = (uint32_t)wsum;
+        h[H_WHI] = (uint32_t)(wsum >> 32);
+        h[H_ADJLO] = (uint32_t)nadj;
+        h[H_ADJHI] = (uint32_t)(nadj >> 32);
+        h[H_ACAP] = ncap;
+        h[H_NSEQ] = s.nseq + s.ni;
+        if (freed) atomicAdd(garbage, (unsigned long long)freed);
+    }
+}
+
+__global__ void k_alloc_check(unsigned long long* ctl, uint64_t pool_words, const unsigned long long* total,
+                              uint32_t* err, unsigned long long* base_out) {
+    const unsigned long long used = ctl[0];
+    if (used + *total > pool_words) {
+        atomicOr(err, ERR_OOM);
+        *base_out = 0;
+    } else {
+        *base_out = used;
+        ctl[0] = used + *total;
+    }
+}
+
+}  // namespace
+
+int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
+                 uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats, hipStream_t st) {
+    const uint64_t R = n_ins + n_del;
+    if (h_stats) memset(h_stats, 0, sizeof(*h_stats));
+    if (R == 0) return BINGO_OK;
+    if (R >= (1ull << 32) - 1) return BINGO_E_INVALID;
+    const int vb = std::max(1, bits_for((uint64_t)g->n - 1));
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    unsigned long long* ctl = g->d_ctl;  // [0] used, [1] garbage, [2..] counters
+    unsigned long long* stats = g->d_ctl + 2;  // [2..29]: 28 counters would collide; use scratch below
+
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    hipLaunchKernelGGL(k_upd_validate, dim3(grid_for(R)), dim3(TB), 0, st, g->n, n_ins, is, id, iw, n_del, ds, dd,
+                       g->d_err);
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return err_to_code(err);
+    (void)stats;
+
+    // ---- workspace, part 1 (records)
+    const size_t srt = sort_temp_bytes(R, true);
+    const size_t sc = scan_temp_bytes(R + 1);
+    size_t need = al(R * 8) * 3 + al(R * 4) * 8 + al(R * 8) * 2 + std::max(srt, sc) + 64 * 8 + 4096;
+    char* ws = (char*)ws_get(g, need);
+    if (!ws) return BINGO_E_OOM;
+    char* w0 = ws;
+    uint64_t* keys = (uint64_t*)ws;     ws += al(R * 8);
+    uint64_t* sk = (uint64_t*)ws;       ws += al(R * 8);
+    uint64_t* hx = (uint64_t*)ws;       ws += al(R * 8);
+    uint32_t* vals = (uint32_t*)ws;     ws += al(R * 4);
+    uint32_t* sv = (uint32_t*)ws;       ws += al(R * 4);
+    uint32_t* head = (uint32_t*)ws;     ws += al(R * 4);
+    uint32_t* rec_t = (uint32_t*)ws;    ws += al(R * 4);
+    uint32_t* tv = (uint32_t*)ws;       ws += al(R * 4);
+    uint32_t* tsa = (uint32_t*)ws;      ws += al(R * 4);
+    uint32_t* tdl = (uint32_t*)ws;      ws += al(R * 4);
+    uint32_t* te = (uint32_t*)ws;       ws += al(R * 4);
+    uint64_t* fsz = (uint64_t*)ws;      ws += al(R * 8);
+    uint64_t* foff = (uint64_t*)ws;     ws += al(R * 8);
+    unsigned long long* cnt = (unsigned long long*)ws; ws += 64 * 8;
+    void* tmp = ws;
+    (void)w0;
+
+    phase_mark(g, st, true);
+    hipLaunchKernelGGL(k_upd_keys, dim3(grid_for(R)), dim3(TB), 0, st, n_ins, n_del, is, ds, dd, vb, keys, vals);
+    sort_pairs_u64(keys, vals, sk, sv, R, 2 * vb + 1, tmp, st);
+    hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(R)), dim3(TB), 0, st, sk, R, vb, head);
+    scan_u32_to_u64(head, hx, R, tmp, cnt, st);
+    HIPCHK(hipMemsetAsync(tdl, 0xFF, R * 4, st));
+    hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(R)), dim3(TB), 0, st, sk, R, vb, head, hx, tv, tsa, tdl, rec_t);
+    unsigned long long T64 = 0;
+    HIPCHK(hipMemcpyAsync(&T64, cnt, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t T = T64;
+    hipLaunchKernelGGL(k_seg_end, dim3(grid_for(T)), dim3(TB), 0, st, T, R, tsa, te, tdl, g->hdr, fsz);
+    hipLaunchKernelGGL(k_flat_size, dim3(grid_for(T)), dim3(TB), 0, st, T, tv, tsa, tdl, te, g->hdr, fsz);
+    scan_u64(fsz, foff, T, tmp, cnt + 1, st);
+    HIPCHK(hipMemsetAsync(cnt + 2, 0, 8 * 8, st));
+    unsigned long long F = 0;
+    HIPCHK(hipMemcpyAsync(&F, cnt + 1, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+
+    phase_mark(g, st, false);
+    // ---- delete matching: candidates
+    const uint32_t mgrid = (uint32_t)std::max<uint64_t>((F + MB - 1) / MB, 1);
+    if (F) hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, 0, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
+                              vb, id, g->hdr, g->pool, cnt + 2, (uint64_t*)nullptr, (uint32_t*)nullptr, 0ull);
+    unsigned long long C = 0;
+    HIPCHK(hipMemcpyAsync(&C, cnt + 2, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+
+    // ---- workspace, part 2 (candidates, X, allocation); part 1 stays in place
+    const uint64_t CC = std::max<uint64_t>(C, 1);
+    const size_t p1 = (size_t)(ws - w0) + std::max(srt, sc);
+    const size_t srt2 = sort_temp_bytes(std::max<uint64_t>(CC, R), true);
+    const size_t need2 = p1 + al(CC * 8) * 2 + al(CC * 4) * 2 + al(R * 4) * 3 + al(R * 8) * 3 + al(T * 8) * 4 +
+                         std::max(srt2, scan_temp_bytes(std::max<uint64_t>(T, R) + 1)) + 4096;
+    if (need2 > g->ws_bytes) {
+        // growing the workspace moves it: copy part 1 over
+        void* old = g->ws;
+        size_t oldb = g->ws_bytes;
+        void* nw = nullptr;
+        if (hipMalloc(&nw, need2) != hipSuccess) return BINGO_E_OOM;
+        HIPCHK(hipMemcpyAsync(nw, old, std::min(oldb, p1), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        hipFree(old);
+        g->ws = nw;
+        g->ws_bytes = need2;
+        const ptrdiff_t delta = (char*)nw - (char*)old;
+        keys = (uint64_t*)((char*)keys + delta); sk = (uint64_t*)((char*)sk + delta); hx = (uint64_t*)((char*)hx + delta);
+        vals = (uint32_t*)((char*)vals + delta); sv = (uint32_t*)((char*)sv + delta); head = (uint32_t*)((char*)head + delta);
+        rec_t = (uint32_t*)((char*)rec_t + delta); tv = (uint32_t*)((char*)tv + delta); tsa = (uint32_t*)((char*)tsa + delta);
+        tdl = (uint32_t*)((char*)tdl + delta); te = (uint32_t*)((char*)te + delta); fsz = (uint64_t*)((char*)fsz + delta);
+        foff = (uint64_t*)((char*)foff + delta); cnt = (unsigned long long*)((char*)cnt + delta);
+        w0 = (char*)nw;
+    }
+    char* w2 = w0 + p1;
+    uint64_t* ckey = (uint64_t*)w2;     w2 += al(CC * 8);
+    uint64_t* cks = (uint64_t*)w2;      w2 += al(CC * 8);
+    uint32_t* cval = (uint32_t*)w2;     w2 += al(CC * 4);
+    uint32_t* cvs = (uint32_t*)w2;      w2 += al(CC * 4);
+    uint32_t* first = (uint32_t*)w2;    w2 += al(R * 4);
+    uint32_t* matched = (uint32_t*)w2;  w2 += al(R * 4);
+    uint32_t* xs = (uint32_t*)w2;       w2 += al(R * 4);
+    uint64_t* xk = (uint64_t*)w2;       w2 += al(R * 8);
+    uint64_t* xks = (uint64_t*)w2;      w2 += al(R * 8);
+    uint32_t* sur = (uint32_t*)w2;      w2 += al(R * 8);
+    uint32_t* ncnt = (uint32_t*)w2;     w2 += al(T * 8);
+    uint64_t* xoff = (uint64_t*)w2;     w2 += al(T * 8);
+    uint64_t* needw = (uint64_t*)w2;    w2 += al(T * 8);
+    uint64_t* aoff = (uint64_t*)w2;     w2 += al(T * 8);
+    void* tmp2 = w2;
+
+    HIPCHK(hipMemsetAsync(matched, 0xFF, R * 4, st));
+    HIPCHK(hipMemsetAsync(ncnt, 0, T * 4, st));
+    if (C) {
+        hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, 1, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
+                           vb, id, g->hdr, g->pool, cnt + 3, ckey, cval, (uint64_t)C);
+        sort_pairs_u64(ckey, cval, cks, cvs, C, bits_for(R) + 32, tmp2, st);
+        hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, cks, (uint64_t)C, first);
+        hipLaunchKernelGGL(k_cand_assign, dim3(grid_for(C)), dim3(TB), 0, st, cks, cvs, (uint64_t)C, first, sk, R,
+                           rec_t, matched, ncnt);
+    }
+    phase_mark(g, st, false);
+    // X: deleted indices per touched vertex, sorted
+    const int tb = bits_for(T);
+    const uint64_t pad = ((uint64_t)T << 32) | 0xFFFFFFFFull;
+    hipLaunchKernelGGL(k_xkeys, dim3(grid_for(R)), dim3(TB), 0, st, R, matched, rec_t, pad, xk);
+    sort_keys_u64(xk, xks, R, tb + 32, tmp2, st);
+    hipLaunchKernelGGL(k_xextract, dim3(grid_for(R)), dim3(TB), 0, st, R, xks, xs);
+    scan_u32_to_u64(ncnt, xoff, T, tmp2, cnt + 4, st);
+
+    // ---- analysis and allocation
+    unsigned long long* dstats = cnt + 8;  // 28 counters
+    HIPCHK(hipMemsetAsync(dstats, 0, 28 * 8, st));
+    const uint32_t vgrid = (uint32_t)((T + 3) / 4);
+    hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
+                       iw, g->rule, needw, dstats);
+    scan_u64(needw, aoff, T, tmp2, cnt + 5, st);
+    hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, ctl, g->pool_words, cnt + 5, g->d_err, cnt + 6);
+    unsigned long long ab[2];
+    HIPCHK(hipMemcpyAsync(ab, cnt + 5, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return err_to_code(err);
+
+    // ---- mutation
+    phase_mark(g, st, false);
+    hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
+                       id, iw, g->rule, aoff, (uint64_t)ab[1], sur, ctl + 1);
+    phase_mark(g, st, false);
+    unsigned long long hs[28];
+    HIPCHK(hipMemcpyAsync(hs, dstats, sizeof hs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h_stats) {
+        h_stats->inserted = hs[0];
+        h_stats->deleted = hs[1];
+        h_stats->not_found = hs[2];
+        h_stats->touched_vertices = T;
+        for (int i = 0; i < 25; ++i) h_stats->transitions[i] = hs[3 + i];
+    }
+    return BINGO_OK;
+}
