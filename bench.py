@@ -134,11 +134,12 @@ def main():
         e2.record(stream)
         torch.cuda.synchronize()
         rows.append({"update_ms": e0.elapsed_time(e1), "ppr_ms": e1.elapsed_time(e2),
-                     "step_ms": e0.elapsed_time(e2), "walk_kernel_ms": ppr_phases[0],
-                     "hist_ms": ppr_phases[1], "update_phases_ms": upd_phases, "steps": steps,
+                     "step_ms": e0.elapsed_time(e2), "bound_ms": ppr_phases[0], "walk_kernel_ms": ppr_phases[1],
+                     "hist_ms": ppr_phases[2], "update_phases_ms": upd_phases, "steps": steps,
                      "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel())})
-        log("step %d: update %.2f ms, ppr %.2f ms (walk kernel %.2f), %d transitions" %
-            (i, rows[-1]["update_ms"], rows[-1]["ppr_ms"], ppr_phases[0], steps))
+        log("step %d: update %.2f ms %s, ppr %.2f ms (bound %.2f, walk kernel %.2f, histogram %.2f), %d transitions" %
+            (i, rows[-1]["update_ms"], ["%.2f" % x for x in upd_phases], rows[-1]["ppr_ms"], ppr_phases[0],
+             ppr_phases[1], ppr_phases[2], steps))
         if i == nb - 1:
             last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32),
                     steps)
@@ -153,7 +154,7 @@ def main():
     # the other walk form on the same (final) graph, for the persistent vs per-step comparison
     other = MODE_PER_STEP if mode == MODE_PERSISTENT else MODE_PERSISTENT
     g.ppr(sources, R, thr, cap, seed, base=last[0], mode=other)
-    other_ms = g.last_phase_ms()[0]
+    other_ms = g.last_phase_ms()[1]
 
     if args.calibrate_copy_mb:
         a = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.int32, device=dev)

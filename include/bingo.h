@@ -191,7 +191,7 @@ int bingo_status(bingo_graph* g, void* stream);
  * bingo_last_phase_ms -- device time of each phase of the last bingo_walk,
  * bingo_ppr or bingo_update_batch call on this handle, measured with HIP
  * events recorded on that call's stream.  bingo_walk: [walk kernel];
- * bingo_ppr: [walk kernel, visit histogram]; bingo_update_batch: [sort and
+ * bingo_ppr: [walk-length bound pass and scan, walk kernel, visit histogram]; bingo_update_batch: [sort and
  * segment, delete matching, deleted sets and analysis, mutation].  *h_n
  * receives the number of phases; h_ms (capacity cap) may be NULL.
  * Synchronizes on the last event.

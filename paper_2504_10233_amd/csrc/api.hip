@@ -47,6 +47,7 @@ static void release(bingo_graph* g) {
     hipFree(g->ppr_vtx);
     hipFree(g->ppr_cnt);
     hipFree(g->ws);
+    hipFree(g->aux);
     delete g;
 }
 

@@ -178,6 +178,9 @@ struct bingo_graph {
     // grow-only scratch for sorts, scans and temporaries
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // grow-only per-walk arrays of PPR calls (lengths, segments, active lists)
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
     // ring of per-call counter slots for walks (queue head, transitions)
     uint32_t walk_slot = 0;
     // per-phase timing of the last walk / PPR / update call (events on its stream)

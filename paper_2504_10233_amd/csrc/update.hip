@@ -130,8 +130,15 @@ __device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, ui
     return lo;
 }
 
-// Candidate search.  Mode 0 counts, mode 1 writes (run << 32 | seq, virtual index).
-__global__ void __launch_bounds__(TB) k_match(int mode, uint64_t F, uint64_t T, const uint64_t* __restrict__ foff,
+// Candidate search: every element of the flat space (live edges, then inserts,
+// of each touched vertex with deletes) whose dst is among the vertex's delete
+// targets becomes a candidate (run << 32 | seq, virtual index).  A block that
+// covers a single vertex stages that vertex's header fields and delete targets
+// in LDS, so the per-element search runs in LDS (hubs); other blocks search
+// global memory (small vertices with few targets).
+constexpr uint32_t LDS_TARGETS = 4096;
+
+__global__ void __launch_bounds__(TB) k_match(uint64_t F, uint64_t T, const uint64_t* __restrict__ foff,
                                               const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                               const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv,
@@ -139,40 +146,78 @@ __global__ void __launch_bounds__(TB) k_match(int mode, uint64_t F, uint64_t T, 
                                               const uint32_t* __restrict__ pool, unsigned long long* __restrict__ cnt,
                                               uint64_t* __restrict__ ckey, uint32_t* __restrict__ cval, uint64_t cap) {
     __shared__ uint32_t range[2];
+    __shared__ uint32_t vinfo[8];  // d, acap, nseq, adj lo, adj hi, ts, tdl, te of a single-vertex block
+    __shared__ uint32_t tgt[LDS_TARGETS];
     const uint64_t f0 = (uint64_t)blockIdx.x * MB;
     if (threadIdx.x == 0) {
         range[0] = find_t(foff, 0, (uint32_t)T - 1, f0);
         range[1] = find_t(foff, range[0], (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
+        if (range[0] == range[1]) {
+            const uint32_t t = range[0];
+            const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+            vinfo[0] = h[H_DEG]; vinfo[1] = h[H_ACAP]; vinfo[2] = h[H_NSEQ];
+            vinfo[3] = h[H_ADJLO]; vinfo[4] = h[H_ADJHI];
+            vinfo[5] = ts[t]; vinfo[6] = tdl[t]; vinfo[7] = te[t];
+        }
     }
     __syncthreads();
     const uint32_t tlo = range[0], thi = range[1];
+    const bool single = tlo == thi;
+    const uint32_t nd1 = single ? vinfo[7] - vinfo[6] : 0u;
+    const bool staged = single && nd1 <= LDS_TARGETS;
+    if (staged) {
+        for (uint32_t i = threadIdx.x; i < nd1; i += TB) tgt[i] = key_dst(sk[vinfo[6] + i], vb);
+        __syncthreads();
+    }
     for (uint32_t s = 0; s < MB; s += TB) {
         const uint64_t f = f0 + s + threadIdx.x;
         bool hit = false;
         uint64_t key = 0;
         uint32_t vidx = 0;
         if (f < F) {
-            const uint32_t t = find_t(foff, tlo, thi, f);
+            uint32_t t, d, acap, nseq, tsv, tdlv, tev;
+            uint64_t adj;
+            if (single) {
+                t = tlo; d = vinfo[0]; acap = vinfo[1]; nseq = vinfo[2];
+                adj = ((uint64_t)vinfo[4] << 32) | vinfo[3];
+                tsv = vinfo[5]; tdlv = vinfo[6]; tev = vinfo[7];
+            } else {
+                t = find_t(foff, tlo, thi, f);
+                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+                d = h[H_DEG]; acap = h[H_ACAP]; nseq = h[H_NSEQ];
+                adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+                tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
+            }
             const uint32_t i = (uint32_t)(f - foff[t]);
-            const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-            const uint32_t d = h[H_DEG];
             uint32_t dst, seq;
             if (i < d) {
-                const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
                 dst = pool[adj + 2ull * i];
-                seq = pool[adj + 2ull * h[H_ACAP] + i];
+                seq = pool[adj + 2ull * acap + i];
             } else {
                 const uint32_t a = i - d;
-                dst = id[sv[ts[t] + a]];
-                seq = h[H_NSEQ] + a;
+                dst = id[sv[tsv + a]];
+                seq = nseq + a;
             }
             // lower bound of dst among the delete records of t (sorted by dst)
-            uint32_t lo = tdl[t], hi = te[t];
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (key_dst(sk[mid], vb) < dst) lo = mid + 1; else hi = mid;
+            uint32_t lo, found;
+            if (staged) {
+                uint32_t l = 0, r = nd1;
+                while (l < r) {
+                    const uint32_t mid = (l + r) >> 1;
+                    if (tgt[mid] < dst) l = mid + 1; else r = mid;
+                }
+                lo = tdlv + l;
+                found = l < nd1 && tgt[l] == dst;
+            } else {
+                uint32_t l = tdlv, r = tev;
+                while (l < r) {
+                    const uint32_t mid = (l + r) >> 1;
+                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else r = mid;
+                }
+                lo = l;
+                found = l < tev && key_dst(sk[l], vb) == dst;
             }
-            if (lo < te[t] && key_dst(sk[lo], vb) == dst) {
+            if (found) {
                 hit = true;
                 key = ((uint64_t)lo << 32) | seq;
                 vidx = i;
@@ -184,7 +229,7 @@ __global__ void __launch_bounds__(TB) k_match(int mode, uint64_t F, uint64_t T, 
             unsigned long long b = 0;
             if ((int)lane_id() == leader) b = atomicAdd(cnt, (unsigned long long)__popcll(m));
             b = __shfl(b, leader, 64);
-            if (mode == 1 && hit) {
+            if (hit) {
                 const uint64_t pos = b + __popcll(m & lanemask_lt());
                 if (pos < cap) { ckey[pos] = key; cval[pos] = vidx; }
             }
@@ -687,16 +732,9 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     HIPCHK(hipStreamSynchronize(st));
 
     phase_mark(g, st, false);
-    // ---- delete matching: candidates
-    const uint32_t mgrid = (uint32_t)std::max<uint64_t>((F + MB - 1) / MB, 1);
-    if (F) hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, 0, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
-                              vb, id, g->hdr, g->pool, cnt + 2, (uint64_t*)nullptr, (uint32_t*)nullptr, 0ull);
-    unsigned long long C = 0;
-    HIPCHK(hipMemcpyAsync(&C, cnt + 2, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-
-    // ---- workspace, part 2 (candidates, X, allocation); part 1 stays in place
-    const uint64_t CC = std::max<uint64_t>(C, 1);
+    // ---- workspace, part 2 (candidates, X, allocation); part 1 stays in place.
+    // Candidates are at most the flat elements F.
+    const uint64_t CC = std::max<uint64_t>(F, 1);
     const size_t p1 = (size_t)(ws - w0) + std::max(srt, sc);
     const size_t srt2 = sort_temp_bytes(std::max<uint64_t>(CC, R), true);
     const size_t need2 = p1 + al(CC * 8) * 2 + al(CC * 4) * 2 + al(R * 4) * 3 + al(R * 8) * 3 + al(T * 8) * 4 +
@@ -737,11 +775,18 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     uint64_t* aoff = (uint64_t*)w2;     w2 += al(T * 8);
     void* tmp2 = w2;
 
+    phase_mark(g, st, false);
+    // ---- delete matching: candidates in one pass
+    const uint32_t mgrid = (uint32_t)std::max<uint64_t>((F + MB - 1) / MB, 1);
+    if (F) hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
+                              vb, id, g->hdr, g->pool, cnt + 2, ckey, cval, (uint64_t)CC);
+    unsigned long long C = 0;
+    HIPCHK(hipMemcpyAsync(&C, cnt + 2, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+
     HIPCHK(hipMemsetAsync(matched, 0xFF, R * 4, st));
     HIPCHK(hipMemsetAsync(ncnt, 0, T * 4, st));
     if (C) {
-        hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, 1, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
-                           vb, id, g->hdr, g->pool, cnt + 3, ckey, cval, (uint64_t)C);
         sort_pairs_u64(ckey, cval, cks, cvs, C, bits_for(R) + 32, tmp2, st);
         hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, cks, (uint64_t)C, first);
         hipLaunchKernelGGL(k_cand_assign, dim3(grid_for(C)), dim3(TB), 0, st, cks, cvs, (uint64_t)C, first, sk, R,

@@ -16,18 +16,15 @@ namespace {
 constexpr int TB = 256;
 constexpr uint64_t NO_WALK = ~0ull;
 
-// One transition from u.  Returns the next vertex or STOP_VERTEX.
-template <bool PPR>
-__device__ __forceinline__ uint32_t walk_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
-                                              uint32_t u, RandStream& rs, uint32_t thr, GroupRule rule) {
+// One transition from u (no termination test).  Returns the next vertex or
+// STOP_VERTEX for a vertex without out-edges.
+__device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                                   uint32_t u, RandStream& rs, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
     // line 0 of the header in one go: mask, d, W, adjacency offset, c_0..c_25
     const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3], q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
     const uint32_t d = q0.y;
     if (d == 0) return STOP_VERTEX;
-    if (PPR) {
-        if (rs_next32(rs) < thr) return STOP_VERTEX;
-    }
     const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
     const uint64_t r = rs_below64(rs, W);
     const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
@@ -74,21 +71,38 @@ __device__ __forceinline__ uint32_t walk_step(const uint32_t* __restrict__ hdr, 
     return pool[adj + 2ull * i];
 }
 
+// Walk ids are handed to waves in chunks: one atomic per QCHUNK ids, and the
+// lanes of a wave that need a walk take consecutive ids from the chunk.
+constexpr uint32_t QCHUNK = 256;
+struct WaveQueue {
+    uint64_t next = 0, end = 0;  // identical in every lane of the wave
+};
+
+__device__ __forceinline__ uint64_t wave_take_chunked(bool need, WaveQueue& q, unsigned long long* head) {
+    const uint64_t want = __ballot(need);
+    if (!want) return NO_WALK;
+    const uint32_t cnt = __popcll(want);
+    const uint32_t rank = __popcll(want & lanemask_lt());
+    const uint64_t avail = q.end - q.next;
+    uint64_t id;
+    if (avail >= cnt) {
+        id = q.next + rank;
+        q.next += cnt;
+    } else {
+        unsigned long long nb = 0;
+        if (lane_id() == 0) nb = atomicAdd(head, (unsigned long long)QCHUNK);
+        nb = __shfl(nb, 0, 64);
+        id = rank < avail ? q.next + rank : nb + (rank - avail);
+        q.next = nb + (cnt - avail);
+        q.end = nb + QCHUNK;
+    }
+    return need ? id : NO_WALK;
+}
+
 __device__ __forceinline__ void wave_add_u64(unsigned long long* p, uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (lane_id() == 0 && v) atomicAdd(p, (unsigned long long)v);
-}
-
-// Take one walk id per lane that asked for one (ballot + one atomic per wave).
-__device__ __forceinline__ uint64_t wave_take(bool need, unsigned long long* queue) {
-    const uint64_t want = __ballot(need);
-    if (!want) return NO_WALK;
-    const int leader = __ffsll((long long)want) - 1;
-    unsigned long long basew = 0;
-    if ((int)lane_id() == leader) basew = atomicAdd(queue, (unsigned long long)__popcll(want));
-    basew = __shfl(basew, leader, 64);
-    return need ? basew + __popcll(want & lanemask_lt()) : NO_WALK;
 }
 
 // ------------------------------------------------------------------ DeepWalk
@@ -100,6 +114,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
                                                             unsigned long long* __restrict__ ctl,
                                                             uint32_t* __restrict__ err) {
     // ctl[0] = queue head, ctl[1] = transitions taken
+    WaveQueue wq;
     uint64_t j = NO_WALK;
     uint32_t u = 0, s = 0;
     uint64_t steps = 0;
@@ -107,7 +122,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
     bool done = false;
     for (;;) {
         const bool need = !done && j == NO_WALK;
-        const uint64_t got = wave_take(need, ctl);
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
         if (need) {
             if (got >= nw) {
                 done = true;
@@ -131,7 +146,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
             if (s < L) {
                 RandStream rs;
                 rs_init(rs, seed, base + j, s);
-                const uint32_t v = walk_step<false>(hdr, pool, u, rs, 0, rule);
+                const uint32_t v = walk_step_body(hdr, pool, u, rs, rule);
                 if (v == STOP_VERTEX) {
                     for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
                     j = NO_WALK;
@@ -169,7 +184,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
         if (u != STOP_VERTEX) {
             RandStream rs;
             rs_init(rs, seed, base + j, s);
-            v = walk_step<false>(hdr, pool, u, rs, 0, rule);
+            v = walk_step_body(hdr, pool, u, rs, rule);
             steps += (v != STOP_VERTEX);
         }
         row[s + 1] = v;
@@ -178,41 +193,44 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
 }
 
 // ------------------------------------------------------------------ PPR
-// Visits are appended as keys (source index << vbits | vertex) to a buffer of
-// capacity cap_visits; the count keeps growing past the capacity so the host
-// can size a retry exactly.
-__device__ __forceinline__ void wave_append(bool has, uint64_t key, unsigned long long* counter,
-                                            uint64_t* __restrict__ out, uint64_t capv) {
-    const uint64_t m = __ballot(has);
-    if (!m) return;
-    const int leader = __ffsll((long long)m) - 1;
-    unsigned long long b = 0;
-    if ((int)lane_id() == leader) b = atomicAdd(counter, (unsigned long long)__popcll(m));
-    b = __shfl(b, leader, 64);
-    if (has) {
-        const uint64_t pos = b + __popcll(m & lanemask_lt());
-        if (pos < capv) out[pos] = key;
+// The termination word of step s is the first word of the stream (seed, id, s)
+// and depends on nothing else, so a cheap pass finds each walk's last possible
+// step B_j (the first s with word < thr, or the cap).  The walk then writes at
+// most 1 + B_j visits into its own pre-scanned segment: no atomics on the
+// visit path, and the steps s < B_j skip the comparison (their word is known
+// to be >= thr).  A walk stopped early by a vertex without out-edges pads the
+// rest of its segment with a key that sorts after every real key.
+__global__ void __launch_bounds__(TB) k_ppr_bound(uint64_t nw, uint64_t base, uint64_t seed, uint32_t thr,
+                                                  uint32_t cap, uint32_t* __restrict__ len) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nw; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t id = base + j;
+        uint32_t b = cap;
+        for (uint32_t s = 0; s < cap; ++s) {
+            uint32_t w0, w1, w2, w3;
+            philox_block((uint32_t)id, (uint32_t)(id >> 32), s, 0, (uint32_t)seed, (uint32_t)(seed >> 32), w0, w1, w2,
+                         w3);
+            if (w0 < thr) { b = s; break; }
+        }
+        len[j] = b + 1;
     }
 }
 
 __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
-                                                       uint32_t R, uint32_t thr, uint32_t cap, uint64_t seed,
-                                                       uint64_t base, int vbits, GroupRule rule,
+                                                       uint32_t R, uint64_t seed, uint64_t base, int vbits,
+                                                       uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                       const uint32_t* __restrict__ len,
                                                        unsigned long long* __restrict__ ctl,
-                                                       uint64_t* __restrict__ visits, uint64_t capv,
-                                                       uint32_t* __restrict__ err) {
-    // ctl[0] queue head, ctl[1] transitions, ctl[2] visits appended
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+    // ctl[0] queue head, ctl[1] transitions
     const uint64_t nw = (uint64_t)nsrc * R;
-    uint64_t j = NO_WALK;
+    WaveQueue wq;
+    uint64_t j = NO_WALK, pos = 0, lim = 0, q = 0, steps = 0;
     uint32_t u = 0, s = 0;
-    uint64_t q = 0, steps = 0;
     bool done = false;
     for (;;) {
         const bool need = !done && j == NO_WALK;
-        const uint64_t got = wave_take(need, ctl);
-        bool has = false;
-        uint64_t key = 0;
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
         if (need) {
             if (got >= nw) {
                 done = true;
@@ -221,76 +239,73 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
                 q = j / R;
                 u = sources[q];
                 s = 0;
+                pos = seg[j];
+                lim = pos + len[j];
                 if (u >= n) {
                     atomicOr(err, ERR_RANGE);
+                    for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
                     j = NO_WALK;
                 } else {
-                    has = true;
-                    key = (q << vbits) | u;
+                    keys[pos++] = (q << vbits) | u;
+                    if (pos == lim) j = NO_WALK;
                 }
             }
         }
-        wave_append(has, key, ctl + 2, visits, capv);
         if (__ballot(!done) == 0) break;
-        has = false;
         if (j != NO_WALK) {
-            uint32_t v = STOP_VERTEX;
-            if (s < cap) {
-                RandStream rs;
-                rs_init(rs, seed, base + j, s);
-                v = walk_step<true>(hdr, pool, u, rs, thr, rule);
-            }
+            RandStream rs;
+            rs_init(rs, seed, base + j, s);
+            rs_next32(rs);  // the termination word, known to be >= thr here
+            const uint32_t v = walk_step_body(hdr, pool, u, rs, rule);
             if (v == STOP_VERTEX) {
+                for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
                 j = NO_WALK;
             } else {
-                has = true;
-                key = (q << vbits) | v;
+                keys[pos++] = (q << vbits) | v;
                 u = v;
                 ++s;
                 ++steps;
+                if (pos == lim) j = NO_WALK;
             }
         }
-        wave_append(has, key, ctl + 2, visits, capv);
     }
     wave_add_u64(ctl + 1, steps);
 }
 
 // Per-step PPR: active walks are (walk id, current vertex) pairs compacted into
-// the next list after every step.
+// the next list after every step; visits go to the same per-walk segments.
 __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
-                                                  uint32_t R, int vbits, uint64_t* __restrict__ act_id,
-                                                  uint32_t* __restrict__ act_v, unsigned long long* __restrict__ ctl,
-                                                  uint64_t* __restrict__ visits, uint64_t capv,
+                                                  uint32_t R, int vbits, uint64_t pad,
+                                                  const uint64_t* __restrict__ seg, const uint32_t* __restrict__ len,
+                                                  uint64_t* __restrict__ act_id, uint32_t* __restrict__ act_v,
+                                                  unsigned long long* __restrict__ ctl, uint64_t* __restrict__ keys,
                                                   uint32_t* __restrict__ err) {
-    // ctl[2] visits, ctl[3] active count of list A
+    // ctl[3] = size of active list A
     const uint64_t nw = (uint64_t)nsrc * R;
-    const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t iters = (nw + stride - 1) / stride;
-    for (uint64_t it = 0; it < iters; ++it) {
-        const uint64_t j = j0 + it * stride;
-        bool has = false;
-        uint64_t key = 0;
-        uint32_t u = 0;
-        if (j < nw) {
-            const uint64_t q = j / R;
-            u = sources[q];
-            if (u >= n) atomicOr(err, ERR_RANGE);
-            else { has = true; key = (q << vbits) | u; }
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nw; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = j / R;
+        const uint32_t u = sources[q];
+        const uint64_t p = seg[j];
+        if (u >= n) {
+            atomicOr(err, ERR_RANGE);
+            for (uint64_t x = p; x < p + len[j]; ++x) keys[x] = pad;
+            act_id[j] = NO_WALK;
+        } else {
+            keys[p] = (q << vbits) | u;
+            act_id[j] = len[j] > 1 ? j : NO_WALK;
         }
-        wave_append(has, key, ctl + 2, visits, capv);
-        // the initial active list is the walks themselves, in id order
-        if (j < nw) { act_id[j] = has ? j : NO_WALK; act_v[j] = has ? u : STOP_VERTEX; }
+        act_v[j] = u;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl[3] = nw;
 }
 
 __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
-                                                 uint32_t R, uint32_t thr, uint32_t s, uint64_t seed, uint64_t base,
-                                                 int vbits, GroupRule rule, const uint64_t* __restrict__ in_id,
+                                                 uint32_t R, uint32_t s, uint64_t seed, uint64_t base, int vbits,
+                                                 uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                 const uint32_t* __restrict__ len, const uint64_t* __restrict__ in_id,
                                                  const uint32_t* __restrict__ in_v, uint64_t* __restrict__ out_id,
                                                  uint32_t* __restrict__ out_v, unsigned long long* __restrict__ ctl,
-                                                 int in_slot, uint64_t* __restrict__ visits, uint64_t capv) {
+                                                 int in_slot, uint64_t* __restrict__ keys) {
     const uint64_t cnt = ctl[3 + in_slot];
     const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -299,23 +314,27 @@ __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hd
     for (uint64_t it = 0; it < iters; ++it) {
         const uint64_t a = j0 + it * stride;
         bool alive = false;
-        uint64_t key = 0, id = NO_WALK;
+        uint64_t id = NO_WALK;
         uint32_t v = STOP_VERTEX;
         if (a < cnt) {
             id = in_id[a];
             if (id != NO_WALK) {
+                // the walk is active at step s, so s < len - 1 and its termination word is >= thr
                 RandStream rs;
                 rs_init(rs, seed, base + id, s);
-                v = walk_step<true>(hdr, pool, in_v[a], rs, thr, rule);
-                if (v != STOP_VERTEX) {
-                    alive = true;
-                    key = ((id / R) << vbits) | v;
+                rs_next32(rs);
+                v = walk_step_body(hdr, pool, in_v[a], rs, rule);
+                const uint64_t p0 = seg[id], l = len[id];
+                if (v == STOP_VERTEX) {
+                    for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) keys[x] = pad;
+                } else {
+                    keys[p0 + 1 + s] = ((id / R) << vbits) | v;
                     ++steps;
+                    alive = (uint64_t)s + 2 < l;
                 }
             }
         }
-        wave_append(alive, key, ctl + 2, visits, capv);
-        // compact survivors into the other list
+        // compact the walks that continue into the other list
         const uint64_t m = __ballot(alive);
         if (m) {
             const int leader = __ffsll((long long)m) - 1;
@@ -424,102 +443,110 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
             uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps, hipStream_t st) {
     const uint64_t nw = (uint64_t)nsrc * R;
     const int vbits = std::max(1, bits_for((uint64_t)g->n - 1));
-    const int qbits = std::max(1, bits_for(nsrc));  // q < nsrc < 2^qbits, so the pad key is above every key
+    const int qbits = std::max(1, bits_for(nsrc));  // q < nsrc < 2^qbits
     if (vbits + qbits > 63) return BINGO_E_INVALID;
-    // expected visits per walk without sinks: 1 + sum_{s=1..cap} (1-p)^s
-    const double p = (double)thr / 4294967296.0;
-    double ev = 1.0, a = 1.0;
-    for (uint32_t s = 0; s < cap; ++s) { a *= (1.0 - p); ev += a; if (a < 1e-12) break; }
-    uint64_t capv = (uint64_t)((double)nw * ev * 1.15) + 4096;
-    capv = std::min<uint64_t>(capv, nw * ((uint64_t)cap + 1));
+    const uint64_t pad = (1ull << (vbits + qbits)) - 1;  // above every (q, v) key
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-    unsigned long long* ctl = g->d_ctl + 2;  // [2] queue, [3] transitions, [4] visits, [5..6] active counts
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        const uint64_t act_bytes = mode == BINGO_WALK_PER_STEP ? 2 * (al(nw * 8) + al(nw * 4)) : 0;
-        const size_t need = al(capv * 8) * 2 + act_bytes + 1024;
-        char* ws = (char*)ws_get(g, need + std::max(sort_temp_bytes(capv, true), scan_temp_bytes(capv)) +
-                                        al(capv * 4) + al(capv * 8) * 2);
-        if (!ws) return BINGO_E_OOM;
-        uint64_t* visits = (uint64_t*)ws;  ws += al(capv * 8);
-        uint64_t* sorted = (uint64_t*)ws;  ws += al(capv * 8);
-        char* act = ws;                    ws += act_bytes;
-        uint32_t* head = (uint32_t*)ws;    ws += al(capv * 4);
-        uint64_t* idx = (uint64_t*)ws;     ws += al(capv * 8);
-        uint64_t* hpos = (uint64_t*)ws;    ws += al(capv * 8);
-        void* tmp = ws;
-        HIPCHK(hipMemsetAsync(ctl, 0, 40, st));
-        HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
-        phase_mark(g, st, true);
-        if (mode == BINGO_WALK_PER_STEP) {
-            uint64_t* idA = (uint64_t*)act;
-            uint32_t* vA = (uint32_t*)(act + al(nw * 8));
-            uint64_t* idB = (uint64_t*)(act + al(nw * 8) + al(nw * 4));
-            uint32_t* vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
-            const uint32_t grid = grid_for(nw);
-            hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, vbits, idA, vA, ctl,
-                               visits, capv, g->d_err);
-            for (uint32_t s = 0; s < cap; ++s) {
-                const int in_slot = s & 1;
-                hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
-                hipLaunchKernelGGL(k_ppr_step, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, thr, s, seed, base,
-                                   vbits, g->rule, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
-                                   in_slot ? vA : vB, ctl, in_slot, visits, capv);
-            }
-        } else {
-            static int rgrid = 0;
-            if (!rgrid) rgrid = resident_grid((const void*)k_ppr_persistent);
-            const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rgrid, (nw + TB - 1) / TB);
-            hipLaunchKernelGGL(k_ppr_persistent, dim3(std::max<uint32_t>(grid, 1)), dim3(TB), 0, st, g->hdr, g->pool,
-                               g->n, nsrc, sources, R, thr, cap, seed, base, vbits, g->rule, ctl, visits, capv,
-                               g->d_err);
-        }
-        phase_mark(g, st, false);
-        unsigned long long c[3];
-        HIPCHK(hipMemcpyAsync(c, ctl + 1, 24, hipMemcpyDeviceToHost, st));
-        uint32_t err = 0;
-        HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    unsigned long long* ctl = g->d_ctl + 2;  // [0] queue, [1] transitions, [2] scan total, [3..4] active counts
+    // per-walk arrays (lengths, segment offsets, active lists) live in the handle's aux buffer so
+    // that the workspace can grow once the total is known
+    const uint64_t act_bytes = mode == BINGO_WALK_PER_STEP ? 2 * (al(nw * 8) + al(nw * 4)) : 0;
+    const size_t aux_need = al(nw * 4) + al(nw * 8) + act_bytes + scan_temp_bytes(nw) + 512;
+    if (aux_need > g->aux_bytes) {
         HIPCHK(hipStreamSynchronize(st));
-        if (err) return err_to_code(err);
-        const uint64_t N = c[1];
-        if (N > capv) {  // more visits than the estimate: retry with the exact size
-            capv = N;
-            continue;
-        }
-        // histogram: sort (source, vertex) keys, then run-length encode
-        sort_keys_u64(visits, sorted, N, vbits + qbits, tmp, st);
-        hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head);
-        scan_u32_to_u64(head, idx, N, tmp, ctl + 4, st);
-        unsigned long long U = 0;
-        HIPCHK(hipMemcpyAsync(&U, ctl + 4, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (g->ppr_cap < U || !g->ppr_vtx) {
-            hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
-            g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
-            if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess ||
-                hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
-                g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
-                return BINGO_E_OOM;
-            }
-        }
-        if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
-            hipFree(g->ppr_off);
-            g->ppr_off_cap = nsrc + 1;
-            if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
-                g->ppr_off = nullptr; g->ppr_off_cap = 0;
-                return BINGO_E_OOM;
-            }
-        }
-        hipLaunchKernelGGL(k_emit, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head, idx, vbits, g->ppr_vtx, hpos,
-                           g->ppr_off);
-        hipLaunchKernelGGL(k_counts, dim3(grid_for(U)), dim3(TB), 0, st, hpos, (uint64_t)U, N, g->ppr_cnt,
-                           g->ppr_off, nsrc);
-        phase_mark(g, st, false);
-        HIPCHK(hipStreamSynchronize(st));
-        g->ppr_entries = U;
-        g->ppr_nsrc = nsrc;
-        if (h_entries) *h_entries = U;
-        if (h_steps) *h_steps = c[0];
-        return BINGO_OK;
+        hipFree(g->aux);
+        g->aux = nullptr;
+        g->aux_bytes = 0;
+        if (hipMalloc(&g->aux, aux_need + aux_need / 4) != hipSuccess) { g->aux = nullptr; return BINGO_E_OOM; }
+        g->aux_bytes = aux_need + aux_need / 4;
     }
-    return BINGO_E_CAPACITY;
+    char* a = (char*)g->aux;
+    uint32_t* len = (uint32_t*)a;  a += al(nw * 4);
+    uint64_t* seg = (uint64_t*)a;  a += al(nw * 8);
+    char* act = a;                 a += act_bytes;
+    void* atmp = a;
+    HIPCHK(hipMemsetAsync(ctl, 0, 40, st));
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    phase_mark(g, st, true);
+    hipLaunchKernelGGL(k_ppr_bound, dim3(grid_for(nw)), dim3(TB), 0, st, nw, base, seed, thr, cap, len);
+    scan_u32_to_u64(len, seg, nw, atmp, ctl + 2, st);
+    unsigned long long total = 0;
+    HIPCHK(hipMemcpyAsync(&total, ctl + 2, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t TT = std::max<uint64_t>(total, 1);
+    char* ws = (char*)ws_get(g, 2 * al(TT * 8) + al(TT * 4) + 2 * al(TT * 8) +
+                                    std::max(sort_temp_bytes(TT, true), scan_temp_bytes(TT)) + 1024);
+    if (!ws) return BINGO_E_OOM;
+    uint64_t* keys = (uint64_t*)ws;    ws += al(TT * 8);
+    uint64_t* sorted = (uint64_t*)ws;  ws += al(TT * 8);
+    uint32_t* head = (uint32_t*)ws;    ws += al(TT * 4);
+    uint64_t* idx = (uint64_t*)ws;     ws += al(TT * 8);
+    uint64_t* hpos = (uint64_t*)ws;    ws += al(TT * 8);
+    void* tmp = ws;
+    phase_mark(g, st, false);
+    if (mode == BINGO_WALK_PER_STEP) {
+        uint64_t* idA = (uint64_t*)act;
+        uint32_t* vA = (uint32_t*)(act + al(nw * 8));
+        uint64_t* idB = (uint64_t*)(act + al(nw * 8) + al(nw * 4));
+        uint32_t* vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
+        const uint32_t grid = grid_for(nw);
+        hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, vbits, pad, seg, len, idA,
+                           vA, ctl, keys, g->d_err);
+        for (uint32_t s = 0; s < cap; ++s) {
+            const int in_slot = s & 1;
+            hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
+            hipLaunchKernelGGL(k_ppr_step, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base, vbits, pad,
+                               g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
+                               in_slot ? vA : vB, ctl, in_slot, keys);
+        }
+    } else {
+        static int rgrid = 0;
+        if (!rgrid) rgrid = resident_grid((const void*)k_ppr_persistent);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rgrid, (nw + TB - 1) / TB);
+        hipLaunchKernelGGL(k_ppr_persistent, dim3(std::max<uint32_t>(grid, 1)), dim3(TB), 0, st, g->hdr, g->pool, g->n,
+                           nsrc, sources, R, seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err);
+    }
+    phase_mark(g, st, false);
+    unsigned long long steps = 0;
+    HIPCHK(hipMemcpyAsync(&steps, ctl + 1, 8, hipMemcpyDeviceToHost, st));
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return err_to_code(err);
+    const uint64_t N = nw + steps;  // visits: every start and every transition
+    // histogram: sort (source, vertex) keys (padding sorts last), then run-length encode
+    sort_keys_u64(keys, sorted, total, vbits + qbits, tmp, st);
+    hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head);
+    scan_u32_to_u64(head, idx, N, tmp, ctl + 2, st);
+    unsigned long long U = 0;
+    HIPCHK(hipMemcpyAsync(&U, ctl + 2, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (g->ppr_cap < U || !g->ppr_vtx) {
+        hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
+        g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
+        if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess ||
+            hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
+            g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
+        hipFree(g->ppr_off);
+        g->ppr_off_cap = nsrc + 1;
+        if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
+            g->ppr_off = nullptr; g->ppr_off_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head, idx, vbits, g->ppr_vtx, hpos,
+                       g->ppr_off);
+    hipLaunchKernelGGL(k_counts, dim3(grid_for(U)), dim3(TB), 0, st, hpos, (uint64_t)U, N, g->ppr_cnt, g->ppr_off,
+                       nsrc);
+    phase_mark(g, st, false);
+    HIPCHK(hipStreamSynchronize(st));
+    g->ppr_entries = U;
+    g->ppr_nsrc = nsrc;
+    if (h_entries) *h_entries = U;
+    if (h_steps) *h_steps = steps;
+    return BINGO_OK;
 }
