@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=1_000_000)
     ap.add_argument("--mode", choices=["persistent", "per_step"], default="persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk (skips the autotuner)")
     ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration runs)")
@@ -119,6 +121,16 @@ def main():
     mode = MODE_PERSISTENT if args.mode == "persistent" else MODE_PER_STEP
     seed = synth.SEEDS["walks"] + c
     stream = torch.cuda.current_stream()
+    tune = None
+    if args.tuning:
+        v, b_, q_ = (int(x) for x in args.tuning.split(","))
+        g.set_tuning(walk_variant=v, blocks_per_cu=b_, queue_chunk=q_)
+    elif not args.no_autotune:
+        from paper_2504_10233_amd.autotune import tune_ppr
+        probe = sources[: max(1, args.sources // 10)]
+        tune = tune_ppr(g, probe, R, thr, cap, seed + 1, base=1 << 40,
+                        signature=[n, m, args.sources, R, "uniform24"], use_cache=False)
+        log("autotune: chose %s" % tune["chosen"])
     rows = []
     last = None
     for i in range(nb):
@@ -182,6 +194,8 @@ def main():
         "walk_form_compare": {"persistent_ms" if mode == MODE_PERSISTENT else "per_step_ms": walk_ms / len(timed),
                               "per_step_ms" if mode == MODE_PERSISTENT else "persistent_ms": other_ms},
         "p99_query_latency_ms": None,
+        "tuning": g.get_tuning(),
+        "autotune": tune,
         "steps_detail": rows,
     }
     mem = g.memory()

@@ -198,6 +198,27 @@ int bingo_status(bingo_graph* g, void* stream);
  */
 int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n);
 
+/*
+ * Launch tuning of the persistent walk kernels.  Results never depend on it
+ * (walks are keyed by seed and walk id); only speed does.
+ *   walk_variant     0: the lanes of a wave take each step together;
+ *                    1: attempt-interleaved lanes (a lane still rejecting in a
+ *                       dense group does not hold back lanes that are done).
+ *   blocks_per_cu    resident 256-thread blocks per compute unit for the
+ *                    persistent grid; 0 = as many as occupancy allows.
+ *   queue_chunk      walk ids a wave takes per queue atomic (power of two,
+ *                    16..4096); 0 = default (256).
+ */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t walk_variant;
+    uint32_t blocks_per_cu;
+    uint32_t queue_chunk;
+} bingo_tuning;
+
+int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);
+int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t);
+
 /* bingo_num_vertices -- n of the handle. */
 uint32_t bingo_num_vertices(const bingo_graph* g);
 

@@ -84,6 +84,8 @@ def lib():
             L.o_update.restype = C.c_int
             L.o_dump.argtypes = [C.c_void_p, u32p]
             L.o_dump.restype = C.c_uint64
+            L.o_dump_range.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, u32p]
+            L.o_dump_range.restype = C.c_uint64
             L.o_memory.argtypes = [C.c_void_p, u64p]
             _lib = L
     return _lib
@@ -223,11 +225,18 @@ class Graph:
         return {"inserted": int(st[0]), "deleted": int(st[1]), "not_found": int(st[2]),
                 "transitions": st[3:].reshape(5, 5).astype(np.int64)}
 
-    def dump(self):
+    def dump(self, u_begin=None, u_end=None):
         L = lib()
-        nw = L.o_dump(self.h, None)
+        if u_begin is None and u_end is None:
+            nw = L.o_dump(self.h, None)
+            out = np.zeros(max(nw, 1), np.uint32)
+            L.o_dump(self.h, _p(out, C.c_uint32))
+            return out[:nw]
+        ub = 0 if u_begin is None else u_begin
+        ue = self.n if u_end is None else u_end
+        nw = L.o_dump_range(self.h, ub, ue, None)
         out = np.zeros(max(nw, 1), np.uint32)
-        L.o_dump(self.h, _p(out, C.c_uint32))
+        L.o_dump_range(self.h, ub, ue, _p(out, C.c_uint32))
         return out[:nw]
 
     def memory(self):

@@ -738,6 +738,13 @@ uint64_t o_dump(const ograph *G, uint32_t *out) {
     return o;
 }
 
+/* The same for vertices [u0, u1) only. */
+uint64_t o_dump_range(const ograph *G, uint32_t u0, uint32_t u1, uint32_t *out) {
+    uint64_t o = 0;
+    for (uint32_t u = u0; u < u1 && u < G->n; u++) o += dump_vertex(&G->v[u], out ? out + o : NULL);
+    return o;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Memory model.  out[0] adjacency bytes (12 per edge); out[t] for t = 1..4  */
 /* group bytes by type (one-element, dense, sparse, regular) under adaption: */

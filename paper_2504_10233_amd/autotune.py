@@ -1,0 +1,61 @@
+"""Autotuner for the persistent walk kernels.
+
+It sweeps the launch knobs of bingo_set_tuning (walk variant, resident blocks per compute unit,
+walk ids per queue atomic) on a probe query and keeps the fastest setting.  Walks are keyed by
+(seed, walk id), so every setting returns the same results; only the walk-kernel time differs.
+That time is read from the library's HIP events (bingo_last_phase_ms).  Results are cached as
+JSON keyed by device and workload signature.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+DEFAULT_SPACE = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=c)
+                 for v in (0, 1) for b in (0, 4, 2) for c in (64, 256, 1024)]
+
+
+def _cache_path():
+    return os.environ.get("BINGO_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "bingo_tune.json"))
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune_ppr(g, sources, walks_per_source, thr, max_len, seed, base=0, space=None, repeats=2, signature=None,
+             use_cache=True):
+    """Pick the fastest tuning for a PPR query shape; returns {"chosen", "results", "cached"}."""
+    import torch
+    dev = torch.cuda.get_device_name(g.device)
+    key = json.dumps([dev, signature]) if signature is not None else None
+    path = _cache_path()
+    cache = _load_cache(path) if use_cache else {}
+    if key and key in cache:
+        g.set_tuning(**cache[key]["chosen"])
+        return dict(cache[key], cached=True)
+    results = []
+    for cfg in (space or DEFAULT_SPACE):
+        g.set_tuning(**cfg)
+        best = None
+        for _ in range(repeats):
+            g.ppr(sources, walks_per_source, thr, max_len, seed, base=base)
+            ms = g.last_phase_ms()[1]
+            best = ms if best is None else min(best, ms)
+        results.append({"tuning": cfg, "walk_kernel_ms": best})
+    chosen = min(results, key=lambda r: r["walk_kernel_ms"])["tuning"]
+    g.set_tuning(**chosen)
+    out = {"chosen": chosen, "results": results}
+    if key and use_cache:
+        cache[key] = out
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return dict(out, cached=False)

@@ -50,8 +50,13 @@ class _MemStats(C.Structure):
 
 
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
-           "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_num_vertices",
-           "bingo_destroy", "bingo_strerror"]
+           "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
+           "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror"]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("walk_variant", C.c_uint32), ("blocks_per_cu", C.c_uint32),
+                ("queue_chunk", C.c_uint32)]
 
 
 def lib_path() -> str:
@@ -78,6 +83,8 @@ def load():
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
         L.bingo_status.argtypes = [vp, vp]
         L.bingo_last_phase_ms.argtypes = [vp, C.POINTER(C.c_float), u32, C.POINTER(u32)]
+        L.bingo_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.bingo_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
         L.bingo_num_vertices.argtypes = [vp]
         L.bingo_num_vertices.restype = u32
         L.bingo_destroy.argtypes = [vp]
@@ -210,6 +217,18 @@ class Graph:
         n = C.c_uint32(0)
         _check(L.bingo_last_phase_ms(self.h, buf, 8, C.byref(n)), "bingo_last_phase_ms")
         return [float(buf[i]) for i in range(n.value)]
+
+    def set_tuning(self, walk_variant=None, blocks_per_cu=None, queue_chunk=None):
+        cur = self.get_tuning()
+        t = _Tuning(C.sizeof(_Tuning), cur["walk_variant"] if walk_variant is None else walk_variant,
+                    cur["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu,
+                    cur["queue_chunk"] if queue_chunk is None else queue_chunk)
+        _check(load().bingo_set_tuning(self.h, C.byref(t)), "bingo_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(load().bingo_get_tuning(self.h, C.byref(t)), "bingo_get_tuning")
+        return {"walk_variant": t.walk_variant, "blocks_per_cu": t.blocks_per_cu, "queue_chunk": t.queue_chunk}
 
     def status(self, stream=None) -> int:
         return load().bingo_status(self.h, _stream(stream))

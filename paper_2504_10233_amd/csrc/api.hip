@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <new>
+#include <stdlib.h>
 
 void* ws_get(bingo_graph* g, size_t bytes) {
     if (bytes <= g->ws_bytes && g->ws) return g->ws;
@@ -159,6 +160,26 @@ int bingo_status(bingo_graph* g, void* stream) {
 }
 
 uint32_t bingo_num_vertices(const bingo_graph* g) { return g ? g->n : 0u; }
+
+int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
+    if (!g || !t || t->struct_size != sizeof(bingo_tuning)) return BINGO_E_INVALID;
+    if (t->walk_variant > 1 || t->blocks_per_cu > 64) return BINGO_E_INVALID;
+    const uint32_t qc = t->queue_chunk ? t->queue_chunk : 256u;
+    if (qc < 16 || qc > 4096 || (qc & (qc - 1))) return BINGO_E_INVALID;
+    g->walk_variant = t->walk_variant;
+    g->blocks_per_cu = t->blocks_per_cu;
+    g->queue_chunk = qc;
+    return BINGO_OK;
+}
+
+int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
+    if (!g || !t) return BINGO_E_INVALID;
+    t->struct_size = sizeof(bingo_tuning);
+    t->walk_variant = g->walk_variant;
+    t->blocks_per_cu = g->blocks_per_cu;
+    t->queue_chunk = g->queue_chunk;
+    return BINGO_OK;
+}
 
 int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n) {
     if (!g || !h_n) return BINGO_E_INVALID;

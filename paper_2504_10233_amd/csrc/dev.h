@@ -183,6 +183,10 @@ struct bingo_graph {
     size_t aux_bytes = 0;
     // ring of per-call counter slots for walks (queue head, transitions)
     uint32_t walk_slot = 0;
+    // persistent walk kernel: 0 = step-synchronous lanes, 1 = attempt-interleaved lanes
+    uint32_t walk_variant = 1;
+    uint32_t blocks_per_cu = 0;   // 0 = occupancy limit
+    uint32_t queue_chunk = 256;
     // per-phase timing of the last walk / PPR / update call (events on its stream)
     hipEvent_t ev[PHASE_EVENTS] = {};
     uint32_t nev = 0;

@@ -27,6 +27,7 @@ constexpr int TB = 256;
 constexpr int WB = 256;
 constexpr uint32_t NF = 0xFFFFFFFFu;
 constexpr uint32_t MB = 1024;  // flat elements per matching block
+constexpr uint32_t PART_BLOCKS = 2048;  // grid cap of the per-vertex kernels (blocks of 4 waves)
 
 __host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
     if (d == 0) return 0;
@@ -169,11 +170,17 @@ __global__ void __launch_bounds__(TB) k_match(uint64_t F, uint64_t T, const uint
         for (uint32_t i = threadIdx.x; i < nd1; i += TB) tgt[i] = key_dst(sk[vinfo[6] + i], vb);
         __syncthreads();
     }
-    for (uint32_t s = 0; s < MB; s += TB) {
-        const uint64_t f = f0 + s + threadIdx.x;
-        bool hit = false;
-        uint64_t key = 0;
-        uint32_t vidx = 0;
+    // each thread looks at MB / TB elements; hits stay in registers until the
+    // block has reserved one contiguous output range with a single atomic
+    constexpr int PER = MB / TB;
+    uint64_t hkey[PER];
+    uint32_t hidx[PER];
+    uint32_t nh = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
+        hkey[r] = 0;
+        hidx[r] = 0;
         if (f < F) {
             uint32_t t, d, acap, nseq, tsv, tdlv, tev;
             uint64_t adj;
@@ -199,40 +206,58 @@ __global__ void __launch_bounds__(TB) k_match(uint64_t F, uint64_t T, const uint
                 seq = nseq + a;
             }
             // lower bound of dst among the delete records of t (sorted by dst)
-            uint32_t lo, found;
+            uint32_t lo;
+            bool found;
             if (staged) {
-                uint32_t l = 0, r = nd1;
-                while (l < r) {
-                    const uint32_t mid = (l + r) >> 1;
-                    if (tgt[mid] < dst) l = mid + 1; else r = mid;
+                uint32_t l = 0, rr = nd1;
+                while (l < rr) {
+                    const uint32_t mid = (l + rr) >> 1;
+                    if (tgt[mid] < dst) l = mid + 1; else rr = mid;
                 }
                 lo = tdlv + l;
                 found = l < nd1 && tgt[l] == dst;
             } else {
-                uint32_t l = tdlv, r = tev;
-                while (l < r) {
-                    const uint32_t mid = (l + r) >> 1;
-                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else r = mid;
+                uint32_t l = tdlv, rr = tev;
+                while (l < rr) {
+                    const uint32_t mid = (l + rr) >> 1;
+                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
                 }
                 lo = l;
                 found = l < tev && key_dst(sk[l], vb) == dst;
             }
             if (found) {
-                hit = true;
-                key = ((uint64_t)lo << 32) | seq;
-                vidx = i;
+                hkey[nh] = ((uint64_t)lo << 32) | seq;
+                hidx[nh] = i;
+                ++nh;
             }
         }
-        const uint64_t m = __ballot(hit);
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            unsigned long long b = 0;
-            if ((int)lane_id() == leader) b = atomicAdd(cnt, (unsigned long long)__popcll(m));
-            b = __shfl(b, leader, 64);
-            if (hit) {
-                const uint64_t pos = b + __popcll(m & lanemask_lt());
-                if (pos < cap) { ckey[pos] = key; cval[pos] = vidx; }
-            }
+    }
+    // block-wide exclusive scan of the per-thread hit counts
+    __shared__ uint32_t wtot[TB / 64];
+    __shared__ unsigned long long bbase;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t x = nh;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < TB / 64; ++w) {
+        if (w < (int)wave) before += wtot[w];
+        total += wtot[w];
+    }
+    if (threadIdx.x == 0) bbase = total ? atomicAdd(cnt, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    const uint64_t pos0 = bbase + before + x - nh;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        if ((uint32_t)r < nh && pos0 + r < cap) {
+            ckey[pos0 + r] = hkey[r];
+            cval[pos0 + r] = hidx[r];
         }
     }
 }
@@ -358,36 +383,62 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
     return v;
 }
 
+// Statistics are accumulated per lane in registers over a grid-stride loop and
+// reduced per block into partials[block * 32 + i] (i: 0 inserted, 1 deleted,
+// 2 not found, 3.. the 25 type transitions); k_stats_reduce sums the blocks.
+// No global atomics: a per-vertex atomic on a handful of addresses would
+// serialize in L2 across ~10^6 touched vertices.
 __global__ void __launch_bounds__(WB) k_analyze(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                                 const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                 const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
                                                 const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
                                                 const uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                                 const uint32_t* __restrict__ iw, GroupRule rule,
-                                                uint64_t* __restrict__ need, unsigned long long* __restrict__ stats) {
-    const uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
-    if (t >= T) return;
-    VState s;
-    load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
-    const uint32_t lane = lane_id();
-    uint64_t w = lane_list_need(s);
-    if (lane == 0 && s.dn > s.cap) w += adj_block_words(adj_cap_for(s.dn));
-    w = wave_sum(w);
-    // type transitions over all 32 groups of the vertex
-    const uint32_t code = lane < 32 ? s.told * 5 + s.tnew : 31u;
-    uint32_t my = 0;
+                                                uint64_t* __restrict__ need, unsigned long long* __restrict__ partials) {
+    __shared__ unsigned long long red[WB / 64][32];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint64_t acc = 0;  // lane i < 28 accumulates counter i
+    for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + wave; t < T; t += (uint64_t)gridDim.x * (WB / 64)) {
+        VState s;
+        load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
+        uint64_t w = lane_list_need(s);
+        if (lane == 0 && s.dn > s.cap) w += adj_block_words(adj_cap_for(s.dn));
+        w = wave_sum(w);
+        // type transitions over all 32 groups of the vertex
+        const uint32_t code = lane < 32 ? s.told * 5 + s.tnew : 31u;
 #pragma unroll
-    for (int c = 0; c < 25; ++c) {
-        const uint32_t k = __popcll(__ballot(code == (uint32_t)c));
-        if (lane == (uint32_t)c) my = k;
+        for (int c = 0; c < 25; ++c) {
+            const uint32_t k = __popcll(__ballot(code == (uint32_t)c));
+            if (lane == (uint32_t)(3 + c)) acc += k;
+        }
+        if (lane == 0) { need[t] = w; acc += s.ni; }
+        if (lane == 1) acc += s.N;
+        if (lane == 2) acc += s.nd - s.N;
     }
-    if (lane == 0) {
-        need[t] = w;
-        atomicAdd(stats + 0, (unsigned long long)s.ni);
-        atomicAdd(stats + 1, (unsigned long long)s.N);
-        atomicAdd(stats + 2, (unsigned long long)(s.nd - s.N));
+    if (lane < 32) red[wave][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        unsigned long long v = 0;
+#pragma unroll
+        for (int w = 0; w < WB / 64; ++w) v += red[w][threadIdx.x];
+        partials[(uint64_t)blockIdx.x * 32 + threadIdx.x] = v;
     }
-    if (lane < 25 && my) atomicAdd(stats + 3 + lane, (unsigned long long)my);
+}
+
+// Sum per-block partials: out[i] = sum_b partials[b * 32 + i], i < 32.
+__global__ void k_stats_reduce(const unsigned long long* __restrict__ partials, uint32_t nblocks,
+                               unsigned long long* __restrict__ out, int accumulate) {
+    __shared__ unsigned long long red[8][32];
+    const uint32_t i = threadIdx.x & 31, r = threadIdx.x >> 5;  // 256 threads: 8 rows x 32 counters
+    unsigned long long v = 0;
+    for (uint32_t b = r; b < nblocks; b += 8) v += partials[(uint64_t)b * 32 + i];
+    red[r][i] = v;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        unsigned long long sum = 0;
+        for (int k = 0; k < 8; ++k) sum += red[k][threadIdx.x];
+        if (accumulate) out[threadIdx.x] += sum; else out[threadIdx.x] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -416,6 +467,15 @@ __device__ __forceinline__ uint32_t rho(uint32_t v, const uint32_t* __restrict__
 // virtual list entry p of a kept group k: the old list, then new members (inserts with bit k)
 // in insert order.  Positions p >= c are enumerated by the insert scans below.
 
+__device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
+                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
+                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
+                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
+                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
+                               uint32_t* __restrict__ sur);
+
 __global__ void __launch_bounds__(WB) k_mutate(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
@@ -423,9 +483,32 @@ __global__ void __launch_bounds__(WB) k_mutate(uint64_t T, const uint32_t* __res
                                                uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                                const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
                                                GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
-                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ garbage) {
-    const uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
-    if (t >= T) return;
+                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ partials) {
+    __shared__ unsigned long long red[WB / 64];
+    uint64_t freed_total = 0;  // lane 0 of each wave
+    for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6); t < T;
+         t += (uint64_t)gridDim.x * (WB / 64)) {
+        freed_total += mutate_one(t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, id, iw, rule, aoff, abase0, sur);
+    }
+    if (lane_id() == 0) red[threadIdx.x >> 6] = freed_total;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        unsigned long long v = 0;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < WB / 64; ++w) v += red[w];
+        partials[(uint64_t)blockIdx.x * 32 + threadIdx.x] = v;  // counter 0: garbage words
+    }
+}
+
+// One touched vertex; returns (in every lane) the pool words it freed.
+__device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
+                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
+                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
+                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
+                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
+                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
+                               uint32_t* __restrict__ sur) {
     VState s;
     load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
     const uint32_t lane = lane_id();
@@ -650,9 +733,11 @@ __global__ void __launch_bounds__(WB) k_mutate(uint64_t T, const uint32_t* __res
         h[H_ADJHI] = (uint32_t)(nadj >> 32);
         h[H_ACAP] = ncap;
         h[H_NSEQ] = s.nseq + s.ni;
-        if (freed) atomicAdd(garbage, (unsigned long long)freed);
     }
+    return freed;
 }
+
+__global__ void k_add_u64(unsigned long long* dst, const unsigned long long* src) { *dst += *src; }
 
 __global__ void k_alloc_check(unsigned long long* ctl, uint64_t pool_words, const unsigned long long* total,
                               uint32_t* err, unsigned long long* base_out) {
@@ -691,7 +776,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     // ---- workspace, part 1 (records)
     const size_t srt = sort_temp_bytes(R, true);
     const size_t sc = scan_temp_bytes(R + 1);
-    size_t need = al(R * 8) * 3 + al(R * 4) * 8 + al(R * 8) * 2 + std::max(srt, sc) + 64 * 8 + 4096;
+    size_t need = al(R * 8) * 3 + al(R * 4) * 8 + al(R * 8) * 2 + std::max(srt, sc) + 128 * 8 + 4096;
     char* ws = (char*)ws_get(g, need);
     if (!ws) return BINGO_E_OOM;
     char* w0 = ws;
@@ -708,7 +793,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     uint32_t* te = (uint32_t*)ws;       ws += al(R * 4);
     uint64_t* fsz = (uint64_t*)ws;      ws += al(R * 8);
     uint64_t* foff = (uint64_t*)ws;     ws += al(R * 8);
-    unsigned long long* cnt = (unsigned long long*)ws; ws += 64 * 8;
+    unsigned long long* cnt = (unsigned long long*)ws; ws += 128 * 8;
     void* tmp = ws;
     (void)w0;
 
@@ -737,19 +822,20 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     const uint64_t CC = std::max<uint64_t>(F, 1);
     const size_t p1 = (size_t)(ws - w0) + std::max(srt, sc);
     const size_t srt2 = sort_temp_bytes(std::max<uint64_t>(CC, R), true);
-    const size_t need2 = p1 + al(CC * 8) * 2 + al(CC * 4) * 2 + al(R * 4) * 3 + al(R * 8) * 3 + al(T * 8) * 4 +
+    const size_t need2 = p1 + al(CC * 8) * 2 + al(CC * 4) * 2 + al(R * 4) * 3 + al(R * 8) * 3 + al(T * 8) * 4 + al(PART_BLOCKS * 32 * 8) +
                          std::max(srt2, scan_temp_bytes(std::max<uint64_t>(T, R) + 1)) + 4096;
     if (need2 > g->ws_bytes) {
         // growing the workspace moves it: copy part 1 over
         void* old = g->ws;
         size_t oldb = g->ws_bytes;
         void* nw = nullptr;
-        if (hipMalloc(&nw, need2) != hipSuccess) return BINGO_E_OOM;
+        const size_t grow = need2 + need2 / 4;  // slack so that the next, slightly larger batch fits
+        if (hipMalloc(&nw, grow) != hipSuccess) return BINGO_E_OOM;
         HIPCHK(hipMemcpyAsync(nw, old, std::min(oldb, p1), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         hipFree(old);
         g->ws = nw;
-        g->ws_bytes = need2;
+        g->ws_bytes = grow;
         const ptrdiff_t delta = (char*)nw - (char*)old;
         keys = (uint64_t*)((char*)keys + delta); sk = (uint64_t*)((char*)sk + delta); hx = (uint64_t*)((char*)hx + delta);
         vals = (uint32_t*)((char*)vals + delta); sv = (uint32_t*)((char*)sv + delta); head = (uint32_t*)((char*)head + delta);
@@ -773,6 +859,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     uint64_t* xoff = (uint64_t*)w2;     w2 += al(T * 8);
     uint64_t* needw = (uint64_t*)w2;    w2 += al(T * 8);
     uint64_t* aoff = (uint64_t*)w2;     w2 += al(T * 8);
+    unsigned long long* parts = (unsigned long long*)w2;  w2 += al(PART_BLOCKS * 32 * 8);
     void* tmp2 = w2;
 
     phase_mark(g, st, false);
@@ -802,11 +889,11 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     scan_u32_to_u64(ncnt, xoff, T, tmp2, cnt + 4, st);
 
     // ---- analysis and allocation
-    unsigned long long* dstats = cnt + 8;  // 28 counters
-    HIPCHK(hipMemsetAsync(dstats, 0, 28 * 8, st));
-    const uint32_t vgrid = (uint32_t)((T + 3) / 4);
+    unsigned long long* dstats = cnt + 8;  // 32 counters (28 used)
+    const uint32_t vgrid = (uint32_t)std::min<uint64_t>((T + 3) / 4, PART_BLOCKS);
     hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
-                       iw, g->rule, needw, dstats);
+                       iw, g->rule, needw, parts);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)parts, vgrid, dstats, 0);
     scan_u64(needw, aoff, T, tmp2, cnt + 5, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, ctl, g->pool_words, cnt + 5, g->d_err, cnt + 6);
     unsigned long long ab[2];
@@ -818,9 +905,12 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     // ---- mutation
     phase_mark(g, st, false);
     hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
-                       id, iw, g->rule, aoff, (uint64_t)ab[1], sur, ctl + 1);
+                       id, iw, g->rule, aoff, (uint64_t)ab[1], sur, parts);
+    // garbage words freed by this batch: counter 0 of the partials, added to ctl[1]
+    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)parts, vgrid, cnt + 40, 0);
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, ctl + 1, (const unsigned long long*)(cnt + 40));
     phase_mark(g, st, false);
-    unsigned long long hs[28];
+    unsigned long long hs[32];
     HIPCHK(hipMemcpyAsync(hs, dstats, sizeof hs, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (h_stats) {

@@ -71,11 +71,74 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
     return pool[adj + 2ull * i];
 }
 
+// ---------------------------------------------------------------------------
+// Attempt-interleaved stepping.  A step is split into "begin" (header, group
+// choice; one-element and listed groups finish here) and "attempt" (one dense
+// rejection try).  In every loop iteration a lane either begins a step and
+// makes its first attempt, or makes one more attempt, so the lanes of a wave do
+// not wait for the lane with the longest rejection run.
+// ---------------------------------------------------------------------------
+constexpr uint32_t PENDING = 0xFFFFFFFEu;
+
+struct StepState {
+    RandStream rs;
+    uint64_t adj;
+    uint32_t d, sel, tries;
+    bool pending;
+};
+
+__device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                               uint32_t u, StepState& ss, GroupRule rule) {
+    const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
+    const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3], q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
+    const uint32_t d = q0.y;
+    if (d == 0) return STOP_VERTEX;
+    const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
+    const uint64_t r = rs_below64(ss.rs, W);
+    const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
+                            q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
+    uint64_t acc = 0;
+    int sel = -1;
+    uint32_t csel = 0;
+#pragma unroll
+    for (int k = 0; k < 26; ++k) {
+        acc += (uint64_t)c[k] << k;
+        if (sel < 0 && r < acc) { sel = k; csel = c[k]; }
+    }
+    if (sel < 0) {
+        const uint4 a = h4[8], b = h4[9];
+        const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            acc += (uint64_t)hc[k] << (26 + k);
+            if (sel < 0 && r < acc) { sel = 26 + k; csel = hc[k]; }
+        }
+    }
+    const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
+    const uint32_t t = group_type(csel, d, rule);
+    if (t == GT_DENSE) {
+        ss.adj = adj; ss.d = d; ss.sel = (uint32_t)sel; ss.tries = 0; ss.pending = true;
+        return PENDING;
+    }
+    const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
+    const uint32_t i = (t == GT_ONE) ? info : pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(ss.rs, csel)];
+    return pool[adj + 2ull * i];
+}
+
+__device__ __forceinline__ uint32_t step_attempt(const uint32_t* __restrict__ pool, StepState& ss) {
+    const uint32_t i = rs_below32(ss.rs, ss.d);
+    const uint64_t e = reinterpret_cast<const uint64_t*>(pool + ss.adj)[i];
+    if ((e >> (32 + ss.sel)) & 1ull) { ss.pending = false; return (uint32_t)e; }
+    // bounded only against a corrupted structure (acceptance is above alpha % per try)
+    if (++ss.tries >= (1u << 16)) { ss.pending = false; return STOP_VERTEX; }
+    return PENDING;
+}
+
 // Walk ids are handed to waves in chunks: one atomic per QCHUNK ids, and the
 // lanes of a wave that need a walk take consecutive ids from the chunk.
-constexpr uint32_t QCHUNK = 256;
 struct WaveQueue {
     uint64_t next = 0, end = 0;  // identical in every lane of the wave
+    uint32_t chunk = 256;
 };
 
 __device__ __forceinline__ uint64_t wave_take_chunked(bool need, WaveQueue& q, unsigned long long* head) {
@@ -90,11 +153,11 @@ __device__ __forceinline__ uint64_t wave_take_chunked(bool need, WaveQueue& q, u
         q.next += cnt;
     } else {
         unsigned long long nb = 0;
-        if (lane_id() == 0) nb = atomicAdd(head, (unsigned long long)QCHUNK);
+        if (lane_id() == 0) nb = atomicAdd(head, (unsigned long long)q.chunk);
         nb = __shfl(nb, 0, 64);
         id = rank < avail ? q.next + rank : nb + (rank - avail);
         q.next = nb + (cnt - avail);
-        q.end = nb + QCHUNK;
+        q.end = nb + q.chunk;
     }
     return need ? id : NO_WALK;
 }
@@ -112,9 +175,10 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
                                                             uint64_t base, uint32_t L, uint64_t seed,
                                                             uint32_t* __restrict__ paths, GroupRule rule,
                                                             unsigned long long* __restrict__ ctl,
-                                                            uint32_t* __restrict__ err) {
+                                                            uint32_t* __restrict__ err, uint32_t qchunk) {
     // ctl[0] = queue head, ctl[1] = transitions taken
     WaveQueue wq;
+    wq.chunk = qchunk;
     uint64_t j = NO_WALK;
     uint32_t u = 0, s = 0;
     uint64_t steps = 0;
@@ -158,6 +222,66 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
                 }
             }
             if (j != NO_WALK && s == L) j = NO_WALK;
+        }
+    }
+    wave_add_u64(ctl + 1, steps);
+}
+
+__global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __restrict__ hdr,
+                                                             const uint32_t* __restrict__ pool, uint32_t n,
+                                                             uint64_t nw, const uint32_t* __restrict__ starts,
+                                                             uint64_t base, uint32_t L, uint64_t seed,
+                                                             uint32_t* __restrict__ paths, GroupRule rule,
+                                                             unsigned long long* __restrict__ ctl,
+                                                             uint32_t* __restrict__ err, uint32_t qchunk) {
+    WaveQueue wq;
+    wq.chunk = qchunk;
+    StepState ss;
+    ss.pending = false;
+    uint64_t j = NO_WALK, steps = 0;
+    uint32_t u = 0, s = 0;
+    uint32_t* row = nullptr;
+    bool done = false;
+    for (;;) {
+        const bool need = !done && j == NO_WALK;
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
+        if (need) {
+            if (got >= nw) {
+                done = true;
+            } else {
+                j = got;
+                row = paths + j * (uint64_t)(L + 1);
+                u = starts[j];
+                s = 0;
+                ss.pending = false;
+                row[0] = u;
+                if (u >= n) {
+                    atomicOr(err, ERR_RANGE);
+                    for (uint32_t x = 1; x <= L; ++x) row[x] = STOP_VERTEX;
+                    j = NO_WALK;
+                } else if (L == 0) {
+                    j = NO_WALK;
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        uint32_t v = PENDING;
+        if (j != NO_WALK && !ss.pending) {
+            rs_init(ss.rs, seed, base + j, s);
+            v = step_begin(hdr, pool, u, ss, rule);
+        }
+        if (j != NO_WALK && ss.pending) v = step_attempt(pool, ss);
+        if (j != NO_WALK && v != PENDING) {
+            if (v == STOP_VERTEX) {
+                for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
+                j = NO_WALK;
+            } else {
+                row[s + 1] = v;
+                u = v;
+                ++s;
+                ++steps;
+                if (s == L) j = NO_WALK;
+            }
         }
     }
     wave_add_u64(ctl + 1, steps);
@@ -221,10 +345,11 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
                                                        uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
                                                        const uint32_t* __restrict__ len,
                                                        unsigned long long* __restrict__ ctl,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ err, uint32_t qchunk) {
     // ctl[0] queue head, ctl[1] transitions
     const uint64_t nw = (uint64_t)nsrc * R;
     WaveQueue wq;
+    wq.chunk = qchunk;
     uint64_t j = NO_WALK, pos = 0, lim = 0, q = 0, steps = 0;
     uint32_t u = 0, s = 0;
     bool done = false;
@@ -257,6 +382,69 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
             rs_init(rs, seed, base + j, s);
             rs_next32(rs);  // the termination word, known to be >= thr here
             const uint32_t v = walk_step_body(hdr, pool, u, rs, rule);
+            if (v == STOP_VERTEX) {
+                for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                j = NO_WALK;
+            } else {
+                keys[pos++] = (q << vbits) | v;
+                u = v;
+                ++s;
+                ++steps;
+                if (pos == lim) j = NO_WALK;
+            }
+        }
+    }
+    wave_add_u64(ctl + 1, steps);
+}
+
+__global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
+                                                        uint32_t R, uint64_t seed, uint64_t base, int vbits,
+                                                        uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                        const uint32_t* __restrict__ len,
+                                                        unsigned long long* __restrict__ ctl,
+                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ err, uint32_t qchunk) {
+    const uint64_t nw = (uint64_t)nsrc * R;
+    WaveQueue wq;
+    wq.chunk = qchunk;
+    StepState ss;
+    ss.pending = false;
+    uint64_t j = NO_WALK, pos = 0, lim = 0, q = 0, steps = 0;
+    uint32_t u = 0, s = 0;
+    bool done = false;
+    for (;;) {
+        const bool need = !done && j == NO_WALK;
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
+        if (need) {
+            if (got >= nw) {
+                done = true;
+            } else {
+                j = got;
+                q = j / R;
+                u = sources[q];
+                s = 0;
+                pos = seg[j];
+                lim = pos + len[j];
+                ss.pending = false;
+                if (u >= n) {
+                    atomicOr(err, ERR_RANGE);
+                    for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                    j = NO_WALK;
+                } else {
+                    keys[pos++] = (q << vbits) | u;
+                    if (pos == lim) j = NO_WALK;
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        uint32_t v = PENDING;
+        if (j != NO_WALK && !ss.pending) {
+            rs_init(ss.rs, seed, base + j, s);
+            rs_next32(ss.rs);  // the termination word, known to be >= thr here
+            v = step_begin(hdr, pool, u, ss, rule);
+        }
+        if (j != NO_WALK && ss.pending) v = step_attempt(pool, ss);
+        if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
                 j = NO_WALK;
@@ -381,12 +569,139 @@ __global__ void k_counts(const uint64_t* __restrict__ hpos, uint64_t U, uint64_t
     if (blockIdx.x == 0 && threadIdx.x == 0) off[nsrc] = U;
 }
 
+// ------------------------------------------------------------------ per-source histogram in LDS
+// The visits of source q are the contiguous key range [seg[q R], seg[(q+1) R]).
+// One 1024-thread block per source sorts that range in LDS (bitonic), run-length
+// encodes it and writes (vertex << 32 | count) back over the start of the same
+// range; a compaction then builds the CSR.  A source whose range exceeds the
+// LDS capacity raises a flag and the query falls back to the global sort.
+constexpr int HB = 1024;
+constexpr uint32_t HCAP = 16384;
+
+__global__ void __launch_bounds__(HB) k_hist_seg(uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
+                                                 uint32_t R, uint32_t nsrc, uint64_t total, uint64_t pad,
+                                                 uint64_t vmask, uint32_t* __restrict__ ucount,
+                                                 unsigned long long* __restrict__ too_big) {
+    __shared__ uint32_t a[HCAP];
+    __shared__ uint32_t st[HCAP];
+    __shared__ uint32_t wsum[HB / 64];
+    const uint32_t q = blockIdx.x, tid = threadIdx.x;
+    const uint64_t S0 = seg[(uint64_t)q * R];
+    const uint64_t S1 = (q + 1 < nsrc) ? seg[(uint64_t)(q + 1) * R] : total;
+    const uint32_t L = (uint32_t)std::min<uint64_t>(S1 - S0, (uint64_t)HCAP + 1);
+    if (L > HCAP) {
+        if (tid == 0) { ucount[q] = 0; atomicOr(too_big, 1ull); }
+        return;
+    }
+    uint32_t P = 64;
+    while (P < L) P <<= 1;
+    for (uint32_t i = tid; i < P; i += HB) {
+        uint32_t v = 0xFFFFFFFFu;
+        if (i < L) {
+            const uint64_t k = keys[S0 + i];
+            if (k != pad) v = (uint32_t)(k & vmask);
+        }
+        a[i] = v;
+    }
+    __syncthreads();
+    // bitonic sort of a[0, P)
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < P; i += HB) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t x = a[i], y = a[l];
+                    const bool up = (i & kk) == 0;
+                    if ((x > y) == up) { a[i] = y; a[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // run heads among valid entries; each thread scans a contiguous chunk of P / HB entries
+    const uint32_t per = (P + HB - 1) / HB;
+    const uint32_t b0 = tid * per, b1 = min(b0 + per, P);
+    uint32_t mine = 0;
+    for (uint32_t i = b0; i < b1; ++i)
+        if (a[i] != 0xFFFFFFFFu && (i == 0 || a[i] != a[i - 1])) ++mine;
+    const uint32_t lane = lane_id(), wave = tid >> 6;
+    uint32_t x = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, U = 0;
+    for (int w = 0; w < HB / 64; ++w) {
+        if (w < (int)wave) before += wsum[w];
+        U += wsum[w];
+    }
+    uint32_t r = before + x - mine;
+    for (uint32_t i = b0; i < b1; ++i)
+        if (a[i] != 0xFFFFFFFFu && (i == 0 || a[i] != a[i - 1])) st[r++] = i;
+    __syncthreads();
+    // number of valid entries: first invalid position (invalid entries sort last)
+    for (uint32_t k = tid; k < U; k += HB) {
+        const uint32_t from = st[k];
+        uint32_t to;
+        if (k + 1 < U) {
+            to = st[k + 1];
+        } else {
+            to = from;
+            while (to < P && a[to] == a[from]) ++to;
+        }
+        keys[S0 + k] = ((uint64_t)a[from] << 32) | (to - from);
+    }
+    if (tid == 0) ucount[q] = U;
+}
+
+__global__ void __launch_bounds__(256) k_hist_compact(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
+                                                      uint32_t R, const uint32_t* __restrict__ ucount,
+                                                      const uint64_t* __restrict__ off, uint32_t* __restrict__ vtx,
+                                                      uint32_t* __restrict__ cnt) {
+    const uint32_t q = blockIdx.x;
+    const uint64_t S0 = seg[(uint64_t)q * R], o = off[q];
+    const uint32_t U = ucount[q];
+    for (uint32_t k = threadIdx.x; k < U; k += 256) {
+        const uint64_t e = keys[S0 + k];
+        vtx[o + k] = (uint32_t)(e >> 32);
+        cnt[o + k] = (uint32_t)e;
+    }
+}
+
+__global__ void k_set_last_off(uint64_t* off, uint32_t nsrc, const unsigned long long* total) { off[nsrc] = *total; }
+
+// Largest per-source key range (visits plus padding), reduced per block then one atomic per block.
+__global__ void __launch_bounds__(256) k_seg_maxlen(const uint64_t* __restrict__ seg, uint32_t R, uint32_t nsrc,
+                                                    const unsigned long long* __restrict__ total,
+                                                    unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long m[4];
+    unsigned long long best = 0;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nsrc; q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t S0 = seg[q * R];
+        const uint64_t S1 = (q + 1 < nsrc) ? seg[(q + 1) * R] : *total;
+        best = std::max<unsigned long long>(best, S1 - S0);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = std::max<unsigned long long>(best, __shfl_xor(best, o));
+    if (lane_id() == 0) m[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) best = std::max<unsigned long long>(best, m[w]);
+        atomicMax(out, best);
+    }
+}
+
 inline uint32_t grid_for(uint64_t n) {
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n + TB - 1) / TB, 1), 1u << 20);
 }
 
-int resident_grid(const void* kernel) {
+int resident_grid(const void* kernel, uint32_t blocks_per_cu) {
     static int cus = 0;
+    static const void* seen[8] = {};
+    static int occ[8] = {};
     if (!cus) {
         int dev = 0;
         hipGetDevice(&dev);
@@ -394,7 +709,15 @@ int resident_grid(const void* kernel) {
         if (cus <= 0) cus = 256;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TB, 0) != hipSuccess || per_cu <= 0) per_cu = 4;
+    for (int i = 0; i < 8; ++i)
+        if (seen[i] == kernel) per_cu = occ[i];
+    if (!per_cu) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TB, 0) != hipSuccess || per_cu <= 0)
+            per_cu = 4;
+        for (int i = 0; i < 8; ++i)
+            if (!seen[i]) { seen[i] = kernel; occ[i] = per_cu; break; }
+    }
+    if (blocks_per_cu && (int)blocks_per_cu < per_cu) per_cu = (int)blocks_per_cu;
     return cus * per_cu;
 }
 
@@ -422,17 +745,21 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
         if (L == 0) {
             // only the start entries
             hipLaunchKernelGGL(k_deepwalk_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                               base, L, seed, paths, g->rule, ctl, g->d_err);
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
         }
         for (uint32_t s = 0; s < L; ++s)
             hipLaunchKernelGGL(k_deepwalk_step, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
                                L, s, seed, paths, g->rule, ctl, g->d_err);
     } else {
-        static int rgrid = 0;
-        if (!rgrid) rgrid = resident_grid((const void*)k_deepwalk_persistent);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rgrid, (nw + TB - 1) / TB);
-        hipLaunchKernelGGL(k_deepwalk_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                           base, L, seed, paths, g->rule, ctl, g->d_err);
+        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved : (const void*)k_deepwalk_persistent;
+        const int rg = resident_grid(kern, g->blocks_per_cu);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
+        if (g->walk_variant)
+            hipLaunchKernelGGL(k_deepwalk_interleaved, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+        else
+            hipLaunchKernelGGL(k_deepwalk_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
     }
     phase_mark(g, st, false);
     if (steps) HIPCHK(hipMemcpyAsync(steps, ctl + 1, 8, hipMemcpyDeviceToDevice, st));
@@ -470,9 +797,13 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     phase_mark(g, st, true);
     hipLaunchKernelGGL(k_ppr_bound, dim3(grid_for(nw)), dim3(TB), 0, st, nw, base, seed, thr, cap, len);
     scan_u32_to_u64(len, seg, nw, atmp, ctl + 2, st);
-    unsigned long long total = 0;
-    HIPCHK(hipMemcpyAsync(&total, ctl + 2, 8, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_seg_maxlen, dim3((uint32_t)std::min<uint64_t>((nsrc + 255) / 256, 1024)), dim3(256), 0, st, seg,
+                       R, nsrc, (const unsigned long long*)(ctl + 2), ctl + 3);
+    unsigned long long tm[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(tm, ctl + 2, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const unsigned long long total = tm[0];
+    const bool lds_hist = tm[1] <= HCAP;
     const uint64_t TT = std::max<uint64_t>(total, 1);
     char* ws = (char*)ws_get(g, 2 * al(TT * 8) + al(TT * 4) + 2 * al(TT * 8) +
                                     std::max(sort_temp_bytes(TT, true), scan_temp_bytes(TT)) + 1024);
@@ -500,11 +831,15 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
                                in_slot ? vA : vB, ctl, in_slot, keys);
         }
     } else {
-        static int rgrid = 0;
-        if (!rgrid) rgrid = resident_grid((const void*)k_ppr_persistent);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rgrid, (nw + TB - 1) / TB);
-        hipLaunchKernelGGL(k_ppr_persistent, dim3(std::max<uint32_t>(grid, 1)), dim3(TB), 0, st, g->hdr, g->pool, g->n,
-                           nsrc, sources, R, seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err);
+        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved : (const void*)k_ppr_persistent;
+        const int rg = resident_grid(kern, g->blocks_per_cu);
+        const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
+        if (g->walk_variant)
+            hipLaunchKernelGGL(k_ppr_interleaved, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+        else
+            hipLaunchKernelGGL(k_ppr_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
     }
     phase_mark(g, st, false);
     unsigned long long steps = 0;
@@ -514,6 +849,49 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     HIPCHK(hipStreamSynchronize(st));
     if (err) return err_to_code(err);
     const uint64_t N = nw + steps;  // visits: every start and every transition
+    if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
+        hipFree(g->ppr_off);
+        g->ppr_off_cap = nsrc + 1;
+        if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
+            g->ppr_off = nullptr; g->ppr_off_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    if (lds_hist) {
+        // per-source histograms in LDS; ucount reuses the head array
+        uint32_t* ucount = head;
+        HIPCHK(hipMemsetAsync(ctl + 3, 0, 8, st));
+        hipLaunchKernelGGL(k_hist_seg, dim3(nsrc), dim3(HB), 0, st, keys, seg, R, nsrc, (uint64_t)total, pad,
+                           (1ull << vbits) - 1, ucount, ctl + 3);
+        scan_u32_to_u64(ucount, g->ppr_off, nsrc, tmp, ctl + 2, st);
+        unsigned long long hv[2];
+        HIPCHK(hipMemcpyAsync(hv, ctl + 2, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!hv[1]) {
+            const uint64_t U = hv[0];
+            if (g->ppr_cap < U || !g->ppr_vtx) {
+                hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
+                g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
+                if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess ||
+                    hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
+                    g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
+                    return BINGO_E_OOM;
+                }
+            }
+            hipLaunchKernelGGL(k_set_last_off, dim3(1), dim3(1), 0, st, g->ppr_off, nsrc,
+                               (const unsigned long long*)(ctl + 2));
+            hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, st, keys, seg, R, ucount, g->ppr_off,
+                               g->ppr_vtx, g->ppr_cnt);
+            phase_mark(g, st, false);
+            HIPCHK(hipStreamSynchronize(st));
+            g->ppr_entries = U;
+            g->ppr_nsrc = nsrc;
+            if (h_entries) *h_entries = U;
+            if (h_steps) *h_steps = steps;
+            return BINGO_OK;
+        }
+        return BINGO_E_HIP;  // unreachable: every range was checked against HCAP before the walk
+    }
     // histogram: sort (source, vertex) keys (padding sorts last), then run-length encode
     sort_keys_u64(keys, sorted, total, vbits + qbits, tmp, st);
     hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head);

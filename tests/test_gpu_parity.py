@@ -291,3 +291,55 @@ def test_generators_match_across_devices():
     b = synth.rmat_graph(12, 5000, 7, device="cuda")
     assert torch.equal(a[0], b[0].cpu()) and torch.equal(a[1], b[1].cpu())
     assert torch.equal(synth.weights_uniform(999, 1, 1 << 24, 3), synth.weights_uniform(999, 1, 1 << 24, 3, "cuda").cpu())
+
+
+# --------------------------------------------------------------------------- tuning invariance
+@pytest.mark.parametrize("variant,bpc,chunk", [(0, 0, 256), (1, 0, 256), (1, 1, 16), (0, 2, 4096), (1, 3, 64)])
+def test_results_independent_of_tuning(variant, bpc, chunk):
+    c = c1()
+    og, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk)
+    assert gg.get_tuning() == {"walk_variant": variant, "blocks_per_cu": bpc, "queue_chunk": chunk}
+    paths, steps = gg.walk(c["starts"], c["length"], c["seed"])
+    opaths, osteps = og.deepwalk(c["starts"], c["length"], c["seed"])
+    assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps
+    thr = int(0.15 * 2**32)
+    sources = np.arange(0, 1000, 37)
+    off, vtx, cnt, st = gg.ppr(sources, 100, thr, 200, seed=4)
+    ooff, ovtx, ocnt, ost = og.ppr(sources, 100, thr, 200, seed=4)
+    assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and st == ost
+
+
+def test_tuning_rejects_bad_values():
+    b = B()
+    c = c1()
+    _, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    for kw in [dict(walk_variant=2), dict(queue_chunk=100), dict(queue_chunk=8), dict(blocks_per_cu=65)]:
+        with pytest.raises(b.BingoError):
+            gg.set_tuning(**kw)
+
+
+def test_ppr_histogram_global_path():
+    # p = 0 and a cap of 10: each source owns R * 11 > 16384 keys, beyond the per-source LDS
+    # histogram, so the query takes the global sort path; both paths must agree with the oracle
+    c = c1()
+    og, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    sources = np.array([3, 4, 900])
+    for R in (2000, 64):
+        off, vtx, cnt, steps = gg.ppr(sources, R, 0, 10, seed=12, base=5)
+        ooff, ovtx, ocnt, osteps = og.ppr(sources, R, 0, 10, seed=12, base=5)
+        assert np.array_equal(off.cpu().numpy().astype(np.uint64), ooff)
+        assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and steps == osteps
+
+
+def test_autotune_keeps_results():
+    from paper_2504_10233_amd.autotune import tune_ppr
+    c = c1()
+    og, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    thr = int(0.15 * 2**32)
+    space = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=q) for v in (0, 1) for b in (0, 1) for q in (16, 256)]
+    res = tune_ppr(gg, np.arange(50), 20, thr, 200, 1, space=space, repeats=1, use_cache=False)
+    assert res["chosen"] in space and len(res["results"]) == len(space)
+    off, vtx, cnt, st = gg.ppr(np.arange(0, 1000, 9), 50, thr, 200, seed=2)
+    ooff, ovtx, ocnt, ost = og.ppr(np.arange(0, 1000, 9), 50, thr, 200, seed=2)
+    assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and st == ost
