@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk (skips the autotuner)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
     ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration runs)")
@@ -59,6 +61,74 @@ def walk_src_hash():
     for f in ("walk.hip", "dev.h"):
         h.update(open(os.path.join(ROOT, "paper_2504_10233_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def serve_phase(g, n, src, dst, args, log):
+    """Requests through the serving loop on the resident graph: Poisson arrivals at args.serve_rate,
+    4 walk queries per update batch; query start sets log-uniform in [1, 10^4] walks with length
+    uniform in 5..80, update batches log-uniform in [1, 10^4] records (half inserts with uniform
+    weights, half deletions of input edges).  Latency is submission to result ready."""
+    import threading
+    import numpy as np
+    from paper_2504_10233_amd import Server
+    rng = np.random.default_rng(5005)
+    m = src.numel()
+    reqs = []
+    for i in range(args.serve_requests):
+        if rng.random() < 0.2:
+            k = int(10 ** rng.uniform(0, 4))
+            ki = k // 2
+            pos = rng.integers(0, m, k - ki)
+            reqs.append(("update", rng.integers(0, n, ki), rng.integers(0, n, ki), rng.integers(1, 1 << 24, ki),
+                         src[torch_index(pos)].cpu().numpy(), dst[torch_index(pos)].cpu().numpy()))
+        else:
+            nw = int(10 ** rng.uniform(0, 4))
+            reqs.append(("walk", rng.integers(0, n, nw), int(rng.integers(5, 81)), int(rng.integers(1 << 62)),
+                         i << 24))
+    gaps = rng.exponential(1.0 / args.serve_rate, len(reqs))
+    srv = Server(g, max_inflight=8)
+    tickets = [None] * len(reqs)
+    infos = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            _, infos[i] = srv.wait(tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    due = t0
+    for i, r in enumerate(reqs):
+        due += gaps[i]
+        while time.perf_counter() < due:
+            pass
+        if r[0] == "walk":
+            tickets[i] = srv.submit_walk(r[1], r[2], r[3], r[4])
+        else:
+            tickets[i] = srv.submit_update(*r[1:])
+        ready.release()
+    th.join()
+    makespan = time.perf_counter() - t0
+    srv.close()
+    q = np.array([x["latency_us"] for x in infos if x["kind"] == 0]) / 1e3
+    u = np.array([x["latency_us"] for x in infos if x["kind"] == 1]) / 1e3
+    steps = sum(x["steps"] for x in infos if x["kind"] == 0)
+    res = {"requests": len(reqs), "offered_rate_per_s": args.serve_rate, "max_inflight": 8,
+           "query_p50_ms": float(np.percentile(q, 50)), "query_p99_ms": float(np.percentile(q, 99)),
+           "update_p50_ms": float(np.percentile(u, 50)) if u.size else None,
+           "update_p99_ms": float(np.percentile(u, 99)) if u.size else None,
+           "sustained_walk_steps_per_s": steps / makespan, "makespan_s": makespan,
+           "errors": int(sum(1 for x in infos if x["status"] != 0))}
+    log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
+        (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
+    return res
+
+
+def torch_index(pos):
+    import torch
+    return torch.from_numpy(pos).to("cuda:0")
 
 
 def main():
@@ -168,6 +238,10 @@ def main():
     g.ppr(sources, R, thr, cap, seed, base=last[0], mode=other)
     other_ms = g.last_phase_ms()[1]
 
+    serving = None
+    if args.serve_requests:
+        serving = serve_phase(g, n, src, dst, args, log)
+
     if args.calibrate_copy_mb:
         a = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.int32, device=dev)
         b = torch.empty_like(a)
@@ -193,7 +267,8 @@ def main():
         "build_s": build_s,
         "walk_form_compare": {"persistent_ms" if mode == MODE_PERSISTENT else "per_step_ms": walk_ms / len(timed),
                               "per_step_ms" if mode == MODE_PERSISTENT else "persistent_ms": other_ms},
-        "p99_query_latency_ms": None,
+        "p99_query_latency_ms": serving["query_p99_ms"] if serving else None,
+        "serving": serving,
         "tuning": g.get_tuning(),
         "autotune": tune,
         "steps_detail": rows,

@@ -219,6 +219,70 @@ typedef struct {
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);
 int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t);
 
+/*
+ * Serving loop.  A scheduler thread owned by the server keeps the graph
+ * resident and runs requests in submission order, with these rules (the
+ * paper's consistency rule, Sec. 6 item ii: a query sees exactly the update
+ * batches submitted before it):
+ *   - a walk query runs once every update batch submitted before it has been
+ *     applied and a slot (one of max_inflight streams) and its device memory
+ *     (counted against hbm_budget_bytes; 0 = unlimited) are free;
+ *     admitted queries run concurrently;
+ *   - an update batch runs once every query submitted before it has finished.
+ * Requests are admitted first-in first-out.  Results equal those of the same
+ * requests issued one by one through bingo_walk / bingo_update_batch.  The
+ * graph handle must not be used directly while a server is attached to it.
+ */
+typedef struct bingo_server bingo_server;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(bingo_server_config) */
+    uint32_t max_inflight;      /* concurrent walk queries, 1..64 */
+    uint64_t hbm_budget_bytes;  /* device bytes of admitted queries; 0 = no limit */
+} bingo_server_config;
+
+typedef struct {
+    uint32_t kind;              /* 0 walk query, 1 update batch */
+    int32_t status;             /* BINGO_OK or an error code */
+    uint64_t epoch;             /* update batches submitted before the request */
+    double queue_us;            /* submission to start on the device */
+    double latency_us;          /* submission to result ready */
+    uint64_t steps;             /* transitions taken (walk query) */
+    uint64_t path_words;        /* n_walks * (length + 1) (walk query) */
+    uint64_t updates_applied;   /* inserted + deleted (update batch) */
+    uint64_t updates_not_found; /* delete records without a live edge (update batch) */
+} bingo_request_info;
+
+/* bingo_server_create -- start the scheduler thread on a built graph. */
+int bingo_server_create(bingo_graph* g, const bingo_server_config* cfg, bingo_server** out);
+
+/*
+ * bingo_server_submit_walk -- enqueue a DeepWalk query (same semantics as
+ * bingo_walk); h_starts is copied before the call returns.  *ticket names the
+ * request in bingo_server_wait.
+ */
+int bingo_server_submit_walk(bingo_server* s, uint64_t n_walks, const uint32_t* h_starts, uint32_t length,
+                             uint64_t seed, uint64_t walk_id_base, uint64_t* ticket);
+
+/* bingo_server_submit_update -- enqueue an update batch (same semantics as
+ * bingo_update_batch); host arrays are copied before the call returns. */
+int bingo_server_submit_update(bingo_server* s, uint64_t n_ins, const uint32_t* h_ins_src,
+                               const uint32_t* h_ins_dst, const uint32_t* h_ins_w, uint64_t n_del,
+                               const uint32_t* h_del_src, const uint32_t* h_del_dst, uint64_t* ticket);
+
+/*
+ * bingo_server_wait -- block until the request is done; a walk query's paths
+ * (path_words uint32, row-major as in bingo_walk) are copied to h_paths when
+ * it is non-NULL and cap_words suffices (else BINGO_E_CAPACITY and the request
+ * stays available).  The ticket is released on return.  Returns the request's
+ * status.
+ */
+int bingo_server_wait(bingo_server* s, uint64_t ticket, uint32_t* h_paths, uint64_t cap_words,
+                      bingo_request_info* info);
+
+/* bingo_server_destroy -- finish all submitted requests, stop the thread, free the server. */
+int bingo_server_destroy(bingo_server* s);
+
 /* bingo_num_vertices -- n of the handle. */
 uint32_t bingo_num_vertices(const bingo_graph* g);
 

@@ -51,7 +51,18 @@ class _MemStats(C.Structure):
 
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
-           "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror"]
+           "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
+           "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy"]
+
+
+class _ServerConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("max_inflight", C.c_uint32), ("hbm_budget_bytes", C.c_uint64)]
+
+
+class _RequestInfo(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("status", C.c_int32), ("epoch", C.c_uint64), ("queue_us", C.c_double),
+                ("latency_us", C.c_double), ("steps", C.c_uint64), ("path_words", C.c_uint64),
+                ("updates_applied", C.c_uint64), ("updates_not_found", C.c_uint64)]
 
 
 class _Tuning(C.Structure):
@@ -85,6 +96,11 @@ def load():
         L.bingo_last_phase_ms.argtypes = [vp, C.POINTER(C.c_float), u32, C.POINTER(u32)]
         L.bingo_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
         L.bingo_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.bingo_server_create.argtypes = [vp, C.POINTER(_ServerConfig), C.POINTER(vp)]
+        L.bingo_server_submit_walk.argtypes = [vp, u64, vp, u32, u64, u64, C.POINTER(u64)]
+        L.bingo_server_submit_update.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, C.POINTER(u64)]
+        L.bingo_server_wait.argtypes = [vp, u64, vp, u64, C.POINTER(_RequestInfo)]
+        L.bingo_server_destroy.argtypes = [vp]
         L.bingo_num_vertices.argtypes = [vp]
         L.bingo_num_vertices.restype = u32
         L.bingo_destroy.argtypes = [vp]
@@ -232,3 +248,63 @@ class Graph:
 
     def status(self, stream=None) -> int:
         return load().bingo_status(self.h, _stream(stream))
+
+
+def _host_u32(x):
+    a = x.cpu().numpy() if isinstance(x, torch.Tensor) else np.asarray(x)
+    return np.ascontiguousarray((a.astype(np.int64) & 0xFFFFFFFF).astype(np.uint32))
+
+
+def _hptr(a):
+    return C.c_void_p(a.ctypes.data if a.size else None)
+
+
+class Server:
+    """Request loop over a resident graph (see include/bingo.h): walk queries and update batches are
+    admitted first-in first-out; queries run concurrently on up to max_inflight streams."""
+
+    def __init__(self, graph: Graph, max_inflight=8, hbm_budget_bytes=0):
+        L = load()
+        cfg = _ServerConfig(C.sizeof(_ServerConfig), max_inflight, hbm_budget_bytes)
+        h = C.c_void_p()
+        _check(L.bingo_server_create(graph.h, C.byref(cfg), C.byref(h)), "bingo_server_create")
+        self.h = h
+        self.graph = graph
+        self._shapes = {}
+
+    def submit_walk(self, starts, length, seed, base=0) -> int:
+        st = _host_u32(starts)
+        t = C.c_uint64(0)
+        _check(load().bingo_server_submit_walk(self.h, st.size, _hptr(st), length, seed, base, C.byref(t)),
+               "bingo_server_submit_walk")
+        self._shapes[t.value] = (st.size, length + 1)
+        return t.value
+
+    def submit_update(self, ins_src, ins_dst, ins_w, del_src, del_dst) -> int:
+        a, b, c, d, e = (_host_u32(x) for x in (ins_src, ins_dst, ins_w, del_src, del_dst))
+        t = C.c_uint64(0)
+        _check(load().bingo_server_submit_update(self.h, a.size, _hptr(a), _hptr(b), _hptr(c), d.size, _hptr(d),
+                                                 _hptr(e), C.byref(t)), "bingo_server_submit_update")
+        self._shapes[t.value] = None
+        return t.value
+
+    def wait(self, ticket):
+        """Returns (paths as uint32 numpy (n_walks, length + 1) or None, info dict)."""
+        shape = self._shapes.pop(ticket)
+        info = _RequestInfo()
+        out = np.zeros(shape, np.uint32) if shape else None
+        rc = load().bingo_server_wait(self.h, ticket, C.c_void_p(out.ctypes.data) if out is not None and out.size
+                                      else None, out.size if out is not None else 0, C.byref(info))
+        _check(rc, "bingo_server_wait")
+        return out, {k: getattr(info, k) for k, _ in _RequestInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bingo_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
