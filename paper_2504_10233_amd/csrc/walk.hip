@@ -152,12 +152,14 @@ __device__ __forceinline__ uint64_t wave_take_chunked(bool need, WaveQueue& q, u
         id = q.next + rank;
         q.next += cnt;
     } else {
+        // reserve enough whole chunks for every lane that is still short
+        const uint64_t chunks = (cnt - avail + q.chunk - 1) / q.chunk;
         unsigned long long nb = 0;
-        if (lane_id() == 0) nb = atomicAdd(head, (unsigned long long)q.chunk);
+        if (lane_id() == 0) nb = atomicAdd(head, (unsigned long long)(chunks * q.chunk));
         nb = __shfl(nb, 0, 64);
         id = rank < avail ? q.next + rank : nb + (rank - avail);
         q.next = nb + (cnt - avail);
-        q.end = nb + q.chunk;
+        q.end = nb + chunks * q.chunk;
     }
     return need ? id : NO_WALK;
 }
