@@ -111,8 +111,15 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m,
  *   d_ins_*     n_ins device uint32 each (weights >= 1).
  *   d_del_*     n_del device uint32 each.
  *   h_stats     optional; filled after the call (the call synchronizes).
- * Returns BINGO_E_RANGE / BINGO_E_WEIGHT (batch not applied) or BINGO_E_OOM
- * (pool too small; batch not applied).
+ * The records are staged into a workspace of the batch's power-of-two size
+ * bucket (at least 1024 records); the pipeline reads every count from device
+ * memory, so one captured hipGraph per bucket serves every batch of that
+ * bucket (bingo_tuning.update_graphs).  The library allocates a bucket's
+ * workspace at its first use and keeps it with the handle.
+ * Returns BINGO_E_RANGE / BINGO_E_WEIGHT (batch not applied), BINGO_E_OOM
+ * (pool or workspace too small; batch not applied), BINGO_E_INVALID (more
+ * than 2^31 records) or BINGO_E_CAPACITY (delete matching kept overflowing
+ * its candidate buffer; batch not applied).
  */
 int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src,
                        const uint32_t* d_ins_dst, const uint32_t* d_ins_w,
@@ -191,8 +198,9 @@ int bingo_status(bingo_graph* g, void* stream);
  * bingo_last_phase_ms -- device time of each phase of the last bingo_walk,
  * bingo_ppr or bingo_update_batch call on this handle, measured with HIP
  * events recorded on that call's stream.  bingo_walk: [walk kernel];
- * bingo_ppr: [walk-length bound pass and scan, walk kernel, visit histogram]; bingo_update_batch: [sort and
- * segment, delete matching, deleted sets and analysis, mutation].  *h_n
+ * bingo_ppr: [walk-length bound pass and scan, walk kernel, visit histogram];
+ * bingo_update_batch: [the device pipeline of the batch, from the sort of its
+ * records to the last mutation kernel; the graph launch when one is used].  *h_n
  * receives the number of phases; h_ms (capacity cap) may be NULL.
  * Synchronizes on the last event.
  */
@@ -208,12 +216,16 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *                    persistent grid; 0 = as many as occupancy allows.
  *   queue_chunk      walk ids a wave takes per queue atomic (power of two,
  *                    16..4096); 0 = default (256).
+ *   update_graphs    1: bingo_update_batch replays one captured hipGraph per
+ *                    power-of-two batch-size bucket (default); 0: it launches
+ *                    the same kernels one by one.
  */
 typedef struct {
     uint32_t struct_size;
     uint32_t walk_variant;
     uint32_t blocks_per_cu;
     uint32_t queue_chunk;
+    uint32_t update_graphs;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

@@ -38,6 +38,7 @@ int err_to_code(uint32_t bits) {
 
 static void release(bingo_graph* g) {
     if (!g) return;
+    update_release(g);
     for (int i = 0; i < PHASE_EVENTS; ++i)
         if (g->ev[i]) hipEventDestroy(g->ev[i]);
     hipFree(g->hdr);
@@ -163,12 +164,13 @@ uint32_t bingo_num_vertices(const bingo_graph* g) { return g ? g->n : 0u; }
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     if (!g || !t || t->struct_size != sizeof(bingo_tuning)) return BINGO_E_INVALID;
-    if (t->walk_variant > 1 || t->blocks_per_cu > 64) return BINGO_E_INVALID;
+    if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1) return BINGO_E_INVALID;
     const uint32_t qc = t->queue_chunk ? t->queue_chunk : 256u;
     if (qc < 16 || qc > 4096 || (qc & (qc - 1))) return BINGO_E_INVALID;
     g->walk_variant = t->walk_variant;
     g->blocks_per_cu = t->blocks_per_cu;
     g->queue_chunk = qc;
+    g->update_graphs = t->update_graphs;
     return BINGO_OK;
 }
 
@@ -178,6 +180,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
     t->walk_variant = g->walk_variant;
     t->blocks_per_cu = g->blocks_per_cu;
     t->queue_chunk = g->queue_chunk;
+    t->update_graphs = g->update_graphs;
     return BINGO_OK;
 }
 

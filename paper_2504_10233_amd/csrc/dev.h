@@ -187,6 +187,9 @@ struct bingo_graph {
     uint32_t walk_variant = 1;
     uint32_t blocks_per_cu = 0;   // 0 = occupancy limit
     uint32_t queue_chunk = 256;
+    // update pipeline: 1 = capture one hipGraph per batch-size bucket and replay it
+    uint32_t update_graphs = 1;
+    struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // per-phase timing of the last walk / PPR / update call (events on its stream)
     hipEvent_t ev[PHASE_EVENTS] = {};
     uint32_t nev = 0;
@@ -226,6 +229,9 @@ void sort_pairs_u64(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* 
                     uint64_t n, int bits, void* temp, hipStream_t st);
 void sort_keys_u64(const uint64_t* keys_in, uint64_t* keys_out, uint64_t n, int bits, void* temp,
                    hipStream_t st);
+// the same on the first min(nmax, *dn) entries, with launches sized by nmax (capturable)
+void sort_pairs_u64_dn(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* keys_out, uint32_t* vals_out,
+                       uint64_t nmax, const unsigned long long* dn, int bits, void* temp, hipStream_t st);
 
 // build.hip
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
@@ -241,6 +247,7 @@ int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint
                  hipStream_t st);
 int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
 // update.hip
+void update_release(bingo_graph* g);
 int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
                  uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats,
                  hipStream_t st);

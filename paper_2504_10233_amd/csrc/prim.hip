@@ -106,9 +106,11 @@ __device__ __forceinline__ uint32_t digit_of(K k, int sh) {
 }
 
 template <typename K>
-__global__ void __launch_bounds__(SORT_BLOCK) k_digit_hist(const K* __restrict__ keys, uint64_t n, int sh,
+__global__ void __launch_bounds__(SORT_BLOCK) k_digit_hist(const K* __restrict__ keys, uint64_t n,
+                                                           const unsigned long long* __restrict__ dn, int sh,
                                                            uint32_t* __restrict__ hist, uint32_t nblocks) {
     __shared__ uint32_t h[RADIX];
+    if (dn) n = std::min<uint64_t>(n, *dn);
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
@@ -124,9 +126,11 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_hist(const K* __restrict__
 template <typename K, bool HAS_V>
 __global__ void __launch_bounds__(SORT_BLOCK) k_digit_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                               K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                              uint64_t n, int sh, const uint64_t* __restrict__ offs,
+                                                              uint64_t n, const unsigned long long* __restrict__ dn,
+                                                              int sh, const uint64_t* __restrict__ offs,
                                                               uint32_t nblocks) {
     __shared__ uint64_t run[RADIX];
+    if (dn) n = std::min<uint64_t>(n, *dn);
     __shared__ uint32_t wc[SORT_WAVES][RADIX];
     const int tid = threadIdx.x, wave = tid >> 6;
     run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
@@ -170,9 +174,11 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_scatter(const K* __restric
     }
 }
 
+// Stable LSD sort of the first min(n, *dn) entries (all n when dn is null);
+// grids are sized by n, so a device-side count keeps the launch sequence fixed.
 template <typename K, bool HAS_V>
 void sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint64_t n, int bits, void* temp,
-               hipStream_t st) {
+               hipStream_t st, const unsigned long long* dn = nullptr) {
     if (n == 0) return;
     const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
     const uint64_t nb = cdiv(n, SORT_TILE);
@@ -195,11 +201,11 @@ void sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint6
         K* nk = to_out ? kout : ktmp;
         uint32_t* nv = to_out ? vout : vtmp;
         const int sh = 8 * p;
-        hipLaunchKernelGGL((k_digit_hist<K>), dim3((uint32_t)nb), dim3(SORT_BLOCK), 0, st, ck, n, sh, hist,
+        hipLaunchKernelGGL((k_digit_hist<K>), dim3((uint32_t)nb), dim3(SORT_BLOCK), 0, st, ck, n, dn, sh, hist,
                            (uint32_t)nb);
         scan_impl<uint32_t>(hist, offs, nb * RADIX, scratch, nullptr, st);
         hipLaunchKernelGGL((k_digit_scatter<K, HAS_V>), dim3((uint32_t)nb), dim3(SORT_BLOCK), 0, st, ck, cv, nk,
-                           nv, n, sh, (const uint64_t*)offs, (uint32_t)nb);
+                           nv, n, dn, sh, (const uint64_t*)offs, (uint32_t)nb);
         ck = nk;
         cv = nv;
     }
@@ -240,4 +246,8 @@ void sort_pairs_u64(const uint64_t* ki, const uint32_t* vi, uint64_t* ko, uint32
 }
 void sort_keys_u64(const uint64_t* ki, uint64_t* ko, uint64_t n, int bits, void* temp, hipStream_t st) {
     sort_impl<uint64_t, false>(ki, nullptr, ko, nullptr, n, bits, temp, st);
+}
+void sort_pairs_u64_dn(const uint64_t* ki, const uint32_t* vi, uint64_t* ko, uint32_t* vo, uint64_t nmax,
+                       const unsigned long long* dn, int bits, void* temp, hipStream_t st) {
+    sort_impl<uint64_t, true>(ki, vi, ko, vo, nmax, bits, temp, st, dn);
 }

@@ -20,6 +20,7 @@
 #include <stdio.h>
 #include <algorithm>
 #include <string.h>
+#include <vector>
 
 namespace {
 
@@ -53,9 +54,37 @@ int bits_for(uint64_t v) {
 
 #define GRID_LOOP(i, n) for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
 
-__global__ void k_upd_validate(uint32_t n, uint64_t ni, const uint32_t* __restrict__ is, const uint32_t* __restrict__ id,
-                               const uint32_t* __restrict__ iw, uint64_t nd, const uint32_t* __restrict__ ds,
-                               const uint32_t* __restrict__ dd, uint32_t* __restrict__ err) {
+// Control block of one update pipeline run (u64 words, device memory):
+//   [0] inserts  [1] deletes  [2] touched vertices T  [3] flat matching size F
+//   [4] candidates C  [5] deleted-set entries  [6] pool words requested  [7] pool base
+//   [8] overflow flags (bit 0: more candidates than the candidate buffer holds)  [9] records
+//   [16..47] statistics (inserted, deleted, not found, 25 type transitions)
+//   [48..79] freed pool words (entry 48)
+// Every kernel reads its element counts from here, so the whole pipeline runs
+// without host round trips and can be captured in a hipGraph; grids and
+// buffers are sized by the batch-size bucket Rmax.
+enum { UC_NI = 0, UC_ND = 1, UC_T = 2, UC_F = 3, UC_C = 4, UC_X = 5, UC_ALLOC = 6, UC_BASE = 7, UC_FLAGS = 8,
+       UC_R = 9,
+       UC_STATS = 16, UC_FREED = 48, UC_WORDS = 96 };
+
+__global__ void k_upd_begin(unsigned long long* __restrict__ uc, uint64_t ni, uint64_t nd, uint32_t* __restrict__ err) {
+    const uint32_t i = threadIdx.x;
+    if (i < UC_WORDS) uc[i] = i == UC_NI ? ni : (i == UC_ND ? nd : (i == UC_R ? ni + nd : 0ull));
+    if (i == 0) *err = 0;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ a, uint64_t n, uint32_t v) {
+    GRID_LOOP(i, n) a[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* __restrict__ a, uint64_t n, uint64_t v) {
+    GRID_LOOP(i, n) a[i] = v;
+}
+
+__global__ void k_upd_validate(uint32_t n, const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ is,
+                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
+                               const uint32_t* __restrict__ ds, const uint32_t* __restrict__ dd,
+                               uint32_t* __restrict__ err) {
+    const uint64_t ni = uc[UC_NI], nd = uc[UC_ND];
     uint32_t bad = 0;
     GRID_LOOP(i, ni) {
         if (is[i] >= n || id[i] >= n) bad |= ERR_RANGE;
@@ -67,17 +96,27 @@ __global__ void k_upd_validate(uint32_t n, uint64_t ni, const uint32_t* __restri
     if (bad) atomicOr(err, bad);
 }
 
-// insert j: key (src << (vb+1)); delete j: key (src << (vb+1)) | 1 << vb | dst
-__global__ void k_upd_keys(uint64_t ni, uint64_t nd, const uint32_t* __restrict__ is, const uint32_t* __restrict__ ds,
-                           const uint32_t* __restrict__ dd, int vb, uint64_t* __restrict__ keys,
-                           uint32_t* __restrict__ vals) {
-    GRID_LOOP(r, ni + nd) {
+// A rejected batch runs the rest of the pipeline as an empty one, so no kernel
+// indexes a header with an out-of-range vertex.
+__global__ void k_upd_gate(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err) {
+    if (*err) uc[UC_NI] = uc[UC_ND] = uc[UC_R] = 0ull;
+}
+
+// insert j: key (src << (vb+1)); delete j: key (src << (vb+1)) | 1 << vb | dst;
+// slots past the batch hold `pad`, which sorts after every record key
+__global__ void k_upd_keys(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ is,
+                           const uint32_t* __restrict__ ds, const uint32_t* __restrict__ dd, int vb, uint64_t pad,
+                           uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint64_t ni = uc[UC_NI], nd = uc[UC_ND];
+    GRID_LOOP(r, rmax) {
+        uint64_t k = pad;
         if (r < ni) {
-            keys[r] = (uint64_t)is[r] << (vb + 1);
-        } else {
+            k = (uint64_t)is[r] << (vb + 1);
+        } else if (r < ni + nd) {
             const uint64_t j = r - ni;
-            keys[r] = ((uint64_t)ds[j] << (vb + 1)) | (1ull << vb) | dd[j];
+            k = ((uint64_t)ds[j] << (vb + 1)) | (1ull << vb) | dd[j];
         }
+        keys[r] = k;
         vals[r] = (uint32_t)r;
     }
 }
@@ -86,14 +125,18 @@ __device__ __forceinline__ uint32_t key_src(uint64_t k, int vb) { return (uint32
 __device__ __forceinline__ uint32_t key_op(uint64_t k, int vb) { return (uint32_t)(k >> vb) & 1u; }
 __device__ __forceinline__ uint32_t key_dst(uint64_t k, int vb) { return (uint32_t)(k & ((1ull << vb) - 1)); }
 
-__global__ void k_seg_heads(const uint64_t* __restrict__ sk, uint64_t R, int vb, uint32_t* __restrict__ head) {
-    GRID_LOOP(p, R) head[p] = (p == 0 || key_src(sk[p], vb) != key_src(sk[p - 1], vb)) ? 1u : 0u;
+__global__ void k_seg_heads(const uint64_t* __restrict__ sk, const unsigned long long* __restrict__ uc, uint64_t rmax,
+                            int vb, uint32_t* __restrict__ head) {
+    const uint64_t R = uc[UC_NI] + uc[UC_ND];
+    GRID_LOOP(p, rmax) head[p] = (p < R && (p == 0 || key_src(sk[p], vb) != key_src(sk[p - 1], vb))) ? 1u : 0u;
 }
 
 // per touched vertex t: tv (vertex), ts (first record), tdl (first delete record)
-__global__ void k_seg_fill(const uint64_t* __restrict__ sk, uint64_t R, int vb, const uint32_t* __restrict__ head,
-                           const uint64_t* __restrict__ hx, uint32_t* __restrict__ tv, uint32_t* __restrict__ ts,
-                           uint32_t* __restrict__ tdl, uint32_t* __restrict__ rec_t) {
+__global__ void k_seg_fill(const uint64_t* __restrict__ sk, const unsigned long long* __restrict__ uc, int vb,
+                           const uint32_t* __restrict__ head, const uint64_t* __restrict__ hx,
+                           uint32_t* __restrict__ tv, uint32_t* __restrict__ ts, uint32_t* __restrict__ tdl,
+                           uint32_t* __restrict__ rec_t) {
+    const uint64_t R = uc[UC_NI] + uc[UC_ND];
     GRID_LOOP(p, R) {
         const uint64_t t = hx[p] + head[p] - 1;
         rec_t[p] = (uint32_t)t;
@@ -102,8 +145,9 @@ __global__ void k_seg_fill(const uint64_t* __restrict__ sk, uint64_t R, int vb, 
     }
 }
 
-__global__ void k_seg_end(uint64_t T, uint64_t R, const uint32_t* __restrict__ ts, uint32_t* __restrict__ te,
-                          uint32_t* __restrict__ tdl, const uint32_t* __restrict__ hdr, uint64_t* __restrict__ fsz) {
+__global__ void k_seg_end(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ ts,
+                          uint32_t* __restrict__ te, uint32_t* __restrict__ tdl) {
+    const uint64_t T = uc[UC_T], R = uc[UC_NI] + uc[UC_ND];
     GRID_LOOP(t, T) {
         const uint32_t end = (t + 1 < T) ? ts[t + 1] : (uint32_t)R;
         te[t] = end;
@@ -111,14 +155,20 @@ __global__ void k_seg_end(uint64_t T, uint64_t R, const uint32_t* __restrict__ t
     }
 }
 
-// flat size of the delete-matching space of t: its live edges and its inserts
-__global__ void k_flat_size(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
-                            const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
-                            const uint32_t* __restrict__ hdr, uint64_t* __restrict__ fsz) {
-    GRID_LOOP(t, T) {
-        const uint32_t nd = te[t] - tdl[t];
-        const uint32_t ni = tdl[t] - ts[t];
-        fsz[t] = nd ? (uint64_t)hdr[(size_t)tv[t] * HDR_WORDS + H_DEG] + ni : 0ull;
+// flat size of the delete-matching space of t: its live edges and its inserts (0 past T)
+__global__ void k_flat_size(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
+                            const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
+                            const uint32_t* __restrict__ te, const uint32_t* __restrict__ hdr,
+                            uint64_t* __restrict__ fsz) {
+    const uint64_t T = uc[UC_T];
+    GRID_LOOP(t, rmax) {
+        uint64_t v = 0;
+        if (t < T) {
+            const uint32_t nd = te[t] - tdl[t];
+            const uint32_t ni = tdl[t] - ts[t];
+            v = nd ? (uint64_t)hdr[(size_t)tv[t] * HDR_WORDS + H_DEG] + ni : 0ull;
+        }
+        fsz[t] = v;
     }
 }
 
@@ -133,137 +183,148 @@ __device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, ui
 
 // Candidate search: every element of the flat space (live edges, then inserts,
 // of each touched vertex with deletes) whose dst is among the vertex's delete
-// targets becomes a candidate (run << 32 | seq, virtual index).  A block that
-// covers a single vertex stages that vertex's header fields and delete targets
-// in LDS, so the per-element search runs in LDS (hubs); other blocks search
-// global memory (small vertices with few targets).
+// targets becomes a candidate (run << 32 | seq, virtual index).  The grid loops
+// over blocks of MB elements.  A block of elements that belongs to a single
+// vertex stages that vertex's header fields and delete targets in LDS, so the
+// per-element search runs in LDS (hubs); other blocks search global memory
+// (small vertices with few targets).  Each block reserves its output range with
+// one atomic.
 constexpr uint32_t LDS_TARGETS = 4096;
 
-__global__ void __launch_bounds__(TB) k_match(uint64_t F, uint64_t T, const uint64_t* __restrict__ foff,
+__global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ uc, const uint64_t* __restrict__ foff,
                                               const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                               const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv,
                                               int vb, const uint32_t* __restrict__ id, const uint32_t* __restrict__ hdr,
-                                              const uint32_t* __restrict__ pool, unsigned long long* __restrict__ cnt,
-                                              uint64_t* __restrict__ ckey, uint32_t* __restrict__ cval, uint64_t cap) {
+                                              const uint32_t* __restrict__ pool, uint64_t* __restrict__ ckey,
+                                              uint32_t* __restrict__ cval, uint64_t cap) {
     __shared__ uint32_t range[2];
     __shared__ uint32_t vinfo[8];  // d, acap, nseq, adj lo, adj hi, ts, tdl, te of a single-vertex block
     __shared__ uint32_t tgt[LDS_TARGETS];
-    const uint64_t f0 = (uint64_t)blockIdx.x * MB;
-    if (threadIdx.x == 0) {
-        range[0] = find_t(foff, 0, (uint32_t)T - 1, f0);
-        range[1] = find_t(foff, range[0], (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
-        if (range[0] == range[1]) {
-            const uint32_t t = range[0];
-            const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-            vinfo[0] = h[H_DEG]; vinfo[1] = h[H_ACAP]; vinfo[2] = h[H_NSEQ];
-            vinfo[3] = h[H_ADJLO]; vinfo[4] = h[H_ADJHI];
-            vinfo[5] = ts[t]; vinfo[6] = tdl[t]; vinfo[7] = te[t];
-        }
-    }
-    __syncthreads();
-    const uint32_t tlo = range[0], thi = range[1];
-    const bool single = tlo == thi;
-    const uint32_t nd1 = single ? vinfo[7] - vinfo[6] : 0u;
-    const bool staged = single && nd1 <= LDS_TARGETS;
-    if (staged) {
-        for (uint32_t i = threadIdx.x; i < nd1; i += TB) tgt[i] = key_dst(sk[vinfo[6] + i], vb);
-        __syncthreads();
-    }
-    // each thread looks at MB / TB elements; hits stay in registers until the
-    // block has reserved one contiguous output range with a single atomic
-    constexpr int PER = MB / TB;
-    uint64_t hkey[PER];
-    uint32_t hidx[PER];
-    uint32_t nh = 0;
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
-        hkey[r] = 0;
-        hidx[r] = 0;
-        if (f < F) {
-            uint32_t t, d, acap, nseq, tsv, tdlv, tev;
-            uint64_t adj;
-            if (single) {
-                t = tlo; d = vinfo[0]; acap = vinfo[1]; nseq = vinfo[2];
-                adj = ((uint64_t)vinfo[4] << 32) | vinfo[3];
-                tsv = vinfo[5]; tdlv = vinfo[6]; tev = vinfo[7];
-            } else {
-                t = find_t(foff, tlo, thi, f);
-                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-                d = h[H_DEG]; acap = h[H_ACAP]; nseq = h[H_NSEQ];
-                adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
-                tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
-            }
-            const uint32_t i = (uint32_t)(f - foff[t]);
-            uint32_t dst, seq;
-            if (i < d) {
-                dst = pool[adj + 2ull * i];
-                seq = pool[adj + 2ull * acap + i];
-            } else {
-                const uint32_t a = i - d;
-                dst = id[sv[tsv + a]];
-                seq = nseq + a;
-            }
-            // lower bound of dst among the delete records of t (sorted by dst)
-            uint32_t lo;
-            bool found;
-            if (staged) {
-                uint32_t l = 0, rr = nd1;
-                while (l < rr) {
-                    const uint32_t mid = (l + rr) >> 1;
-                    if (tgt[mid] < dst) l = mid + 1; else rr = mid;
-                }
-                lo = tdlv + l;
-                found = l < nd1 && tgt[l] == dst;
-            } else {
-                uint32_t l = tdlv, rr = tev;
-                while (l < rr) {
-                    const uint32_t mid = (l + rr) >> 1;
-                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
-                }
-                lo = l;
-                found = l < tev && key_dst(sk[l], vb) == dst;
-            }
-            if (found) {
-                hkey[nh] = ((uint64_t)lo << 32) | seq;
-                hidx[nh] = i;
-                ++nh;
-            }
-        }
-    }
-    // block-wide exclusive scan of the per-thread hit counts
     __shared__ uint32_t wtot[TB / 64];
     __shared__ unsigned long long bbase;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    uint32_t x = nh;
+    const uint64_t F = uc[UC_F], T = uc[UC_T];
+    const uint64_t nblk = (F + MB - 1) / MB;
+    constexpr int PER = MB / TB;
+    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint64_t f0 = blk * MB;
+        __syncthreads();  // the previous block's users of the shared state are done
+        if (threadIdx.x == 0) {
+            range[0] = find_t(foff, 0, (uint32_t)T - 1, f0);
+            range[1] = find_t(foff, range[0], (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
+            if (range[0] == range[1]) {
+                const uint32_t t = range[0];
+                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+                vinfo[0] = h[H_DEG]; vinfo[1] = h[H_ACAP]; vinfo[2] = h[H_NSEQ];
+                vinfo[3] = h[H_ADJLO]; vinfo[4] = h[H_ADJHI];
+                vinfo[5] = ts[t]; vinfo[6] = tdl[t]; vinfo[7] = te[t];
+            }
+        }
+        __syncthreads();
+        const uint32_t tlo = range[0], thi = range[1];
+        const bool single = tlo == thi;
+        const uint32_t nd1 = single ? vinfo[7] - vinfo[6] : 0u;
+        const bool staged = single && nd1 <= LDS_TARGETS;
+        if (staged) {
+            for (uint32_t i = threadIdx.x; i < nd1; i += TB) tgt[i] = key_dst(sk[vinfo[6] + i], vb);
+            __syncthreads();
+        }
+        // each thread looks at PER elements; hits stay in registers until the
+        // block has reserved one contiguous output range
+        uint64_t hkey[PER];
+        uint32_t hidx[PER];
+        uint32_t nh = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    if (lane == 63) wtot[wave] = x;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
+        for (int r = 0; r < PER; ++r) {
+            const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
+            hkey[r] = 0;
+            hidx[r] = 0;
+            if (f < F) {
+                uint32_t t, d, acap, nseq, tsv, tdlv, tev;
+                uint64_t adj;
+                if (single) {
+                    t = tlo; d = vinfo[0]; acap = vinfo[1]; nseq = vinfo[2];
+                    adj = ((uint64_t)vinfo[4] << 32) | vinfo[3];
+                    tsv = vinfo[5]; tdlv = vinfo[6]; tev = vinfo[7];
+                } else {
+                    t = find_t(foff, tlo, thi, f);
+                    const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+                    d = h[H_DEG]; acap = h[H_ACAP]; nseq = h[H_NSEQ];
+                    adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+                    tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
+                }
+                const uint32_t i = (uint32_t)(f - foff[t]);
+                uint32_t dst, seq;
+                if (i < d) {
+                    dst = pool[adj + 2ull * i];
+                    seq = pool[adj + 2ull * acap + i];
+                } else {
+                    const uint32_t a = i - d;
+                    dst = id[sv[tsv + a]];
+                    seq = nseq + a;
+                }
+                uint32_t lo;
+                bool found;
+                if (staged) {
+                    uint32_t l = 0, rr = nd1;
+                    while (l < rr) {
+                        const uint32_t mid = (l + rr) >> 1;
+                        if (tgt[mid] < dst) l = mid + 1; else rr = mid;
+                    }
+                    lo = tdlv + l;
+                    found = l < nd1 && tgt[l] == dst;
+                } else {
+                    uint32_t l = tdlv, rr = tev;
+                    while (l < rr) {
+                        const uint32_t mid = (l + rr) >> 1;
+                        if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
+                    }
+                    lo = l;
+                    found = l < tev && key_dst(sk[l], vb) == dst;
+                }
+                if (found) {
+                    hkey[nh] = ((uint64_t)lo << 32) | seq;
+                    hidx[nh] = i;
+                    ++nh;
+                }
+            }
+        }
+        const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+        uint32_t x = nh;
 #pragma unroll
-    for (int w = 0; w < TB / 64; ++w) {
-        if (w < (int)wave) before += wtot[w];
-        total += wtot[w];
-    }
-    if (threadIdx.x == 0) bbase = total ? atomicAdd(cnt, (unsigned long long)total) : 0ull;
-    __syncthreads();
-    const uint64_t pos0 = bbase + before + x - nh;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        if ((uint32_t)r < nh && pos0 + r < cap) {
-            ckey[pos0 + r] = hkey[r];
-            cval[pos0 + r] = hidx[r];
+        for (int w = 0; w < TB / 64; ++w) {
+            if (w < (int)wave) before += wtot[w];
+            total += wtot[w];
+        }
+        if (threadIdx.x == 0) bbase = total ? atomicAdd(uc + UC_C, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        const uint64_t pos0 = bbase + before + x - nh;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if ((uint32_t)r < nh && pos0 + r < cap) {
+                ckey[pos0 + r] = hkey[r];
+                cval[pos0 + r] = hidx[r];
+            }
         }
     }
 }
 
-// first candidate position of every run (candidates sorted by run, then seq)
-__global__ void k_cand_first(const uint64_t* __restrict__ ck, uint64_t C, uint32_t* __restrict__ first) {
+__global__ void k_check_overflow(unsigned long long* uc, uint64_t cap) {
+    if (uc[UC_C] > cap) uc[UC_FLAGS] |= 1ull;
+}
+
+// first candidate position of every run (candidates sorted by run, then seq; padding last)
+__global__ void k_cand_first(const uint64_t* __restrict__ ck, const unsigned long long* __restrict__ uc, uint64_t cap,
+                             uint32_t* __restrict__ first) {
+    const uint64_t C = std::min<uint64_t>(uc[UC_C], cap);
     GRID_LOOP(c, C) {
         const uint32_t run = (uint32_t)(ck[c] >> 32);
         if (c == 0 || (uint32_t)(ck[c - 1] >> 32) != run) first[run] = (uint32_t)c;
@@ -271,10 +332,12 @@ __global__ void k_cand_first(const uint64_t* __restrict__ ck, uint64_t C, uint32
 }
 
 // the rank-th oldest occurrence goes to the rank-th record of the run
-__global__ void k_cand_assign(const uint64_t* __restrict__ ck, const uint32_t* __restrict__ cv, uint64_t C,
-                              const uint32_t* __restrict__ first, const uint64_t* __restrict__ sk, uint64_t R,
+__global__ void k_cand_assign(const uint64_t* __restrict__ ck, const uint32_t* __restrict__ cv,
+                              const unsigned long long* __restrict__ uc, uint64_t cap,
+                              const uint32_t* __restrict__ first, const uint64_t* __restrict__ sk,
                               const uint32_t* __restrict__ rec_t, uint32_t* __restrict__ matched,
                               uint32_t* __restrict__ ncnt) {
+    const uint64_t C = std::min<uint64_t>(uc[UC_C], cap), R = uc[UC_NI] + uc[UC_ND];
     GRID_LOOP(c, C) {
         const uint32_t run = (uint32_t)(ck[c] >> 32);
         const uint32_t rank = (uint32_t)c - first[run];
@@ -292,9 +355,10 @@ __global__ void k_cand_assign(const uint64_t* __restrict__ ck, const uint32_t* _
     }
 }
 
-__global__ void k_xkeys(uint64_t R, const uint32_t* __restrict__ matched, const uint32_t* __restrict__ rec_t,
-                        uint64_t pad, uint64_t* __restrict__ xk) {
-    GRID_LOOP(p, R) xk[p] = matched[p] != NF ? (((uint64_t)rec_t[p] << 32) | matched[p]) : pad;
+__global__ void k_xkeys(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ matched,
+                        const uint32_t* __restrict__ rec_t, uint64_t pad, uint64_t* __restrict__ xk) {
+    const uint64_t R = uc[UC_NI] + uc[UC_ND];
+    GRID_LOOP(p, rmax) xk[p] = (p < R && matched[p] != NF) ? (((uint64_t)rec_t[p] << 32) | matched[p]) : pad;
 }
 
 __global__ void k_xextract(uint64_t R, const uint64_t* __restrict__ xk, uint32_t* __restrict__ xs) {
@@ -388,7 +452,8 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 // 2 not found, 3.. the 25 type transitions); k_stats_reduce sums the blocks.
 // No global atomics: a per-vertex atomic on a handful of addresses would
 // serialize in L2 across ~10^6 touched vertices.
-__global__ void __launch_bounds__(WB) k_analyze(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+__global__ void __launch_bounds__(WB) k_analyze(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ tv,
+                                                const uint32_t* __restrict__ ts,
                                                 const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                 const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
                                                 const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
@@ -397,6 +462,7 @@ __global__ void __launch_bounds__(WB) k_analyze(uint64_t T, const uint32_t* __re
                                                 uint64_t* __restrict__ need, unsigned long long* __restrict__ partials) {
     __shared__ unsigned long long red[WB / 64][32];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t T = uc[UC_T];
     uint64_t acc = 0;  // lane i < 28 accumulates counter i
     for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + wave; t < T; t += (uint64_t)gridDim.x * (WB / 64)) {
         VState s;
@@ -476,15 +542,20 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
                                GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
                                uint32_t* __restrict__ sur);
 
-__global__ void __launch_bounds__(WB) k_mutate(uint64_t T, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
+__global__ void __launch_bounds__(WB) k_mutate(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+                                               const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
                                                const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
                                                uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                                const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
-                                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
+                                               GroupRule rule, const uint64_t* __restrict__ aoff,
                                                uint32_t* __restrict__ sur, unsigned long long* __restrict__ partials) {
     __shared__ unsigned long long red[WB / 64];
+    // a batch with bad input, a candidate overflow or no pool space changes nothing
+    const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
+    const uint64_t T = skip ? 0 : uc[UC_T];
+    const uint64_t abase0 = uc[UC_BASE];
     uint64_t freed_total = 0;  // lane 0 of each wave
     for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6); t < T;
          t += (uint64_t)gridDim.x * (WB / 64)) {
@@ -739,186 +810,257 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
 
 __global__ void k_add_u64(unsigned long long* dst, const unsigned long long* src) { *dst += *src; }
 
-__global__ void k_alloc_check(unsigned long long* ctl, uint64_t pool_words, const unsigned long long* total,
-                              uint32_t* err, unsigned long long* base_out) {
-    const unsigned long long used = ctl[0];
-    if (used + *total > pool_words) {
+// Reserve the batch's pool words with one bump, unless the batch is already
+// rejected (bad input or candidate overflow); no space sets ERR_OOM.
+__global__ void k_alloc_check(unsigned long long* __restrict__ ctl, uint64_t pool_words,
+                              unsigned long long* __restrict__ uc, uint32_t* __restrict__ err) {
+    if (*err || uc[UC_FLAGS]) return;
+    const unsigned long long used = ctl[0], total = uc[UC_ALLOC];
+    if (used + total > pool_words) {
         atomicOr(err, ERR_OOM);
-        *base_out = 0;
     } else {
-        *base_out = used;
-        ctl[0] = used + *total;
+        uc[UC_BASE] = used;
+        ctl[0] = used + total;
     }
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Plans: one workspace (and captured graph) per power-of-two batch-size bucket.
+// ---------------------------------------------------------------------------
+struct UpdPlan {
+    uint64_t rmax = 0, cmax = 0;
+    char* ws = nullptr;
+    size_t bytes = 0;
+    uint32_t *is = nullptr, *id = nullptr, *iw = nullptr, *ds = nullptr, *dd = nullptr;  // staged inputs
+    unsigned long long* uc = nullptr;
+    uint64_t *keys, *sk, *hx, *fsz, *foff, *ckey, *cks, *xk, *xks, *needw, *aoff, *xoff;
+    uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt;
+    unsigned long long* parts;
+    void* tmp;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_failed = false;
+};
+
+struct UpdPlans {
+    std::vector<UpdPlan*> plans;
+    hipStream_t cap_stream = nullptr;  // private stream for captures (never the legacy default stream)
+};
+
+static constexpr uint32_t MATCH_GRID = 2048;
+static constexpr size_t PLAN_CACHE_BYTES = 16ull << 30;
+
+static void plan_free(UpdPlan* p) {
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    hipFree(p->ws);
+    delete p;
+}
+
+static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t R = rmax, C = cmax;
+    const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)), scan_temp_bytes(R + 1));
+    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 10 + al(C * 8) * 2 + al(R * 4) * 13 +
+                         al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + tmpb + 4096;
+    UpdPlan* p = new UpdPlan();
+    p->rmax = R;
+    p->cmax = C;
+    if (hipMalloc(&p->ws, bytes) != hipSuccess) { delete p; return nullptr; }
+    p->bytes = bytes;
+    char* w = p->ws;
+    auto take = [&](uint64_t b) { char* r = w; w += al(b); return r; };
+    p->is = (uint32_t*)take(R * 4); p->id = (uint32_t*)take(R * 4); p->iw = (uint32_t*)take(R * 4);
+    p->ds = (uint32_t*)take(R * 4); p->dd = (uint32_t*)take(R * 4);
+    p->uc = (unsigned long long*)take(UC_WORDS * 8);
+    p->keys = (uint64_t*)take(R * 8); p->sk = (uint64_t*)take(R * 8); p->hx = (uint64_t*)take(R * 8);
+    p->fsz = (uint64_t*)take(R * 8); p->foff = (uint64_t*)take(R * 8); p->xk = (uint64_t*)take(R * 8);
+    p->xks = (uint64_t*)take(R * 8); p->needw = (uint64_t*)take(R * 8); p->aoff = (uint64_t*)take(R * 8);
+    p->xoff = (uint64_t*)take(R * 8);
+    p->ckey = (uint64_t*)take(C * 8); p->cks = (uint64_t*)take(C * 8);
+    p->vals = (uint32_t*)take(R * 4); p->sv = (uint32_t*)take(R * 4); p->head = (uint32_t*)take(R * 4);
+    p->rec_t = (uint32_t*)take(R * 4); p->tv = (uint32_t*)take(R * 4); p->tsa = (uint32_t*)take(R * 4);
+    p->tdl = (uint32_t*)take(R * 4); p->te = (uint32_t*)take(R * 4); p->first = (uint32_t*)take(R * 4);
+    p->matched = (uint32_t*)take(R * 4); p->xs = (uint32_t*)take(R * 4); p->ncnt = (uint32_t*)take(R * 4);
+    (void)take(R * 4);  // spare
+    p->sur = (uint32_t*)take(R * 8);
+    p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
+    p->parts = (unsigned long long*)take(PART_BLOCKS * 32 * 8);
+    p->tmp = w;
+    return p;
+}
+
+static uint64_t pow2_at_least(uint64_t x, uint64_t lo) {
+    uint64_t c = lo;
+    while (c < x) c <<= 1;
+    return c;
+}
+
+// The whole pipeline for one batch, sizes from the control block; no host round trips.
+static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
+    const uint64_t R = p->rmax, C = p->cmax;
+    const int vb = std::max(1, bits_for((uint64_t)g->n - 1));
+    const int cbits = bits_for(R) + 32;  // candidate key: run (< R) << 32 | seq
+    const uint64_t xpad = cbits >= 64 ? ~0ull : (1ull << cbits) - 1;
+    const uint32_t vgrid = (uint32_t)std::min<uint64_t>((R + 3) / 4, PART_BLOCKS);
+    unsigned long long* uc = p->uc;
+    uint32_t* err = g->d_err;
+    hipLaunchKernelGGL(k_upd_validate, dim3(grid_for(R)), dim3(TB), 0, st, g->n, (const unsigned long long*)uc, p->is,
+                       p->id, p->iw, p->ds, p->dd, err);
+    hipLaunchKernelGGL(k_upd_gate, dim3(1), dim3(1), 0, st, uc, (const uint32_t*)err);
+    // 1. records sorted by (src, op, dst); segments per touched vertex
+    hipLaunchKernelGGL(k_upd_keys, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->is, p->ds,
+                       p->dd, vb, ~0ull, p->keys, p->vals);
+    sort_pairs_u64_dn(p->keys, p->vals, p->sk, p->sv, R, uc + UC_R, 2 * vb + 1, p->tmp, st);
+    hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(R)), dim3(TB), 0, st, p->sk, (const unsigned long long*)uc, R, vb,
+                       p->head);
+    scan_u32_to_u64(p->head, p->hx, R, p->tmp, uc + UC_T, st);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R)), dim3(TB), 0, st, p->tdl, R, NF);
+    hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(R)), dim3(TB), 0, st, p->sk, (const unsigned long long*)uc, vb,
+                       p->head, p->hx, p->tv, p->tsa, p->tdl, p->rec_t);
+    hipLaunchKernelGGL(k_seg_end, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, p->tsa, p->te,
+                       p->tdl);
+    hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->tv,
+                       p->tsa, p->tdl, p->te, g->hdr, p->fsz);
+    scan_u64(p->fsz, p->foff, R, p->tmp, uc + UC_F, st);
+    // 2. delete matching: candidates, sorted by (run, seq); the k oldest per run
+    hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tv, p->tsa, p->tdl, p->te, p->sk,
+                       p->sv, vb, p->id, g->hdr, g->pool, p->ckey, p->cval, C);
+    hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, st, uc, C);
+    sort_pairs_u64_dn(p->ckey, p->cval, p->cks, p->cvs, C, uc + UC_C, cbits, p->tmp, st);
+    hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, p->cks, (const unsigned long long*)uc, C,
+                       p->first);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R)), dim3(TB), 0, st, p->matched, R, NF);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R)), dim3(TB), 0, st, p->ncnt, R, 0u);
+    hipLaunchKernelGGL(k_cand_assign, dim3(grid_for(C)), dim3(TB), 0, st, p->cks, p->cvs,
+                       (const unsigned long long*)uc, C, p->first, p->sk, p->rec_t, p->matched, p->ncnt);
+    // 3. the deleted indices of every touched vertex, sorted
+    hipLaunchKernelGGL(k_xkeys, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->matched,
+                       p->rec_t, xpad, p->xk);
+    sort_keys_u64(p->xk, p->xks, R, cbits, p->tmp, st);
+    hipLaunchKernelGGL(k_xextract, dim3(grid_for(R)), dim3(TB), 0, st, R, p->xks, p->xs);
+    scan_u32_to_u64(p->ncnt, p->xoff, R, p->tmp, uc + UC_X, st);
+    // 4. analysis and one bump allocation
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R)), dim3(TB), 0, st, p->needw, R, 0ull);
+    hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, p->tv, p->tsa, p->tdl,
+                       p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->iw, g->rule, p->needw, p->parts);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+                       uc + UC_STATS, 0);
+    scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
+    hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
+    // 5. mutation (a no-op for a rejected batch)
+    hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, (const uint32_t*)err,
+                       p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
+                       g->rule, p->aoff, p->sur, p->parts);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+                       uc + UC_FREED, 0);
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
+}
+
+static UpdPlan* get_plan(bingo_graph* g, uint64_t rmax, uint64_t cmax_min) {
+    if (!g->upd) g->upd = new UpdPlans();
+    UpdPlans* ps = g->upd;
+    for (size_t i = 0; i < ps->plans.size(); ++i) {
+        UpdPlan* p = ps->plans[i];
+        if (p->rmax == rmax) {
+            if (p->cmax >= cmax_min) return p;
+            hipDeviceSynchronize();
+            plan_free(p);
+            ps->plans.erase(ps->plans.begin() + i);
+            break;
+        }
+    }
+    const uint64_t cmax = std::max<uint64_t>(cmax_min, std::max<uint64_t>(4 * rmax, 1ull << 16));
+    // keep the cached workspaces bounded: drop the largest others first
+    size_t total = 0;
+    for (auto* p : ps->plans) total += p->bytes;
+    while (!ps->plans.empty() && total > PLAN_CACHE_BYTES) {
+        size_t big = 0;
+        for (size_t i = 1; i < ps->plans.size(); ++i)
+            if (ps->plans[i]->bytes > ps->plans[big]->bytes) big = i;
+        total -= ps->plans[big]->bytes;
+        hipDeviceSynchronize();
+        plan_free(ps->plans[big]);
+        ps->plans.erase(ps->plans.begin() + big);
+    }
+    UpdPlan* p = plan_make(rmax, cmax);
+    if (p) ps->plans.push_back(p);
+    return p;
+}
+
+void update_release(bingo_graph* g) {
+    if (!g->upd) return;
+    for (auto* p : g->upd->plans) plan_free(p);
+    if (g->upd->cap_stream) hipStreamDestroy(g->upd->cap_stream);
+    delete g->upd;
+    g->upd = nullptr;
+}
 
 int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
                  uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats, hipStream_t st) {
     const uint64_t R = n_ins + n_del;
     if (h_stats) memset(h_stats, 0, sizeof(*h_stats));
     if (R == 0) return BINGO_OK;
-    if (R >= (1ull << 32) - 1) return BINGO_E_INVALID;
-    const int vb = std::max(1, bits_for((uint64_t)g->n - 1));
-    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-    unsigned long long* ctl = g->d_ctl;  // [0] used, [1] garbage, [2..] counters
-    unsigned long long* stats = g->d_ctl + 2;  // [2..29]: 28 counters would collide; use scratch below
-
-    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
-    hipLaunchKernelGGL(k_upd_validate, dim3(grid_for(R)), dim3(TB), 0, st, g->n, n_ins, is, id, iw, n_del, ds, dd,
-                       g->d_err);
-    uint32_t err = 0;
-    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (err) return err_to_code(err);
-    (void)stats;
-
-    // ---- workspace, part 1 (records)
-    const size_t srt = sort_temp_bytes(R, true);
-    const size_t sc = scan_temp_bytes(R + 1);
-    size_t need = al(R * 8) * 3 + al(R * 4) * 8 + al(R * 8) * 2 + std::max(srt, sc) + 128 * 8 + 4096;
-    char* ws = (char*)ws_get(g, need);
-    if (!ws) return BINGO_E_OOM;
-    char* w0 = ws;
-    uint64_t* keys = (uint64_t*)ws;     ws += al(R * 8);
-    uint64_t* sk = (uint64_t*)ws;       ws += al(R * 8);
-    uint64_t* hx = (uint64_t*)ws;       ws += al(R * 8);
-    uint32_t* vals = (uint32_t*)ws;     ws += al(R * 4);
-    uint32_t* sv = (uint32_t*)ws;       ws += al(R * 4);
-    uint32_t* head = (uint32_t*)ws;     ws += al(R * 4);
-    uint32_t* rec_t = (uint32_t*)ws;    ws += al(R * 4);
-    uint32_t* tv = (uint32_t*)ws;       ws += al(R * 4);
-    uint32_t* tsa = (uint32_t*)ws;      ws += al(R * 4);
-    uint32_t* tdl = (uint32_t*)ws;      ws += al(R * 4);
-    uint32_t* te = (uint32_t*)ws;       ws += al(R * 4);
-    uint64_t* fsz = (uint64_t*)ws;      ws += al(R * 8);
-    uint64_t* foff = (uint64_t*)ws;     ws += al(R * 8);
-    unsigned long long* cnt = (unsigned long long*)ws; ws += 128 * 8;
-    void* tmp = ws;
-    (void)w0;
-
-    phase_mark(g, st, true);
-    hipLaunchKernelGGL(k_upd_keys, dim3(grid_for(R)), dim3(TB), 0, st, n_ins, n_del, is, ds, dd, vb, keys, vals);
-    sort_pairs_u64(keys, vals, sk, sv, R, 2 * vb + 1, tmp, st);
-    hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(R)), dim3(TB), 0, st, sk, R, vb, head);
-    scan_u32_to_u64(head, hx, R, tmp, cnt, st);
-    HIPCHK(hipMemsetAsync(tdl, 0xFF, R * 4, st));
-    hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(R)), dim3(TB), 0, st, sk, R, vb, head, hx, tv, tsa, tdl, rec_t);
-    unsigned long long T64 = 0;
-    HIPCHK(hipMemcpyAsync(&T64, cnt, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const uint64_t T = T64;
-    hipLaunchKernelGGL(k_seg_end, dim3(grid_for(T)), dim3(TB), 0, st, T, R, tsa, te, tdl, g->hdr, fsz);
-    hipLaunchKernelGGL(k_flat_size, dim3(grid_for(T)), dim3(TB), 0, st, T, tv, tsa, tdl, te, g->hdr, fsz);
-    scan_u64(fsz, foff, T, tmp, cnt + 1, st);
-    HIPCHK(hipMemsetAsync(cnt + 2, 0, 8 * 8, st));
-    unsigned long long F = 0;
-    HIPCHK(hipMemcpyAsync(&F, cnt + 1, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-
-    phase_mark(g, st, false);
-    // ---- workspace, part 2 (candidates, X, allocation); part 1 stays in place.
-    // Candidates are at most the flat elements F.
-    const uint64_t CC = std::max<uint64_t>(F, 1);
-    const size_t p1 = (size_t)(ws - w0) + std::max(srt, sc);
-    const size_t srt2 = sort_temp_bytes(std::max<uint64_t>(CC, R), true);
-    const size_t need2 = p1 + al(CC * 8) * 2 + al(CC * 4) * 2 + al(R * 4) * 3 + al(R * 8) * 3 + al(T * 8) * 4 + al(PART_BLOCKS * 32 * 8) +
-                         std::max(srt2, scan_temp_bytes(std::max<uint64_t>(T, R) + 1)) + 4096;
-    if (need2 > g->ws_bytes) {
-        // growing the workspace moves it: copy part 1 over
-        void* old = g->ws;
-        size_t oldb = g->ws_bytes;
-        void* nw = nullptr;
-        const size_t grow = need2 + need2 / 4;  // slack so that the next, slightly larger batch fits
-        if (hipMalloc(&nw, grow) != hipSuccess) return BINGO_E_OOM;
-        HIPCHK(hipMemcpyAsync(nw, old, std::min(oldb, p1), hipMemcpyDeviceToDevice, st));
+    if (R > (1ull << 31)) return BINGO_E_INVALID;
+    const uint64_t rmax = pow2_at_least(R, 1024);
+    uint64_t cmin = 0;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        UpdPlan* p = get_plan(g, rmax, cmin);
+        if (!p) return BINGO_E_OOM;
+        if (n_ins) {
+            HIPCHK(hipMemcpyAsync(p->is, is, n_ins * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(p->id, id, n_ins * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(p->iw, iw, n_ins * 4, hipMemcpyDeviceToDevice, st));
+        }
+        if (n_del) {
+            HIPCHK(hipMemcpyAsync(p->ds, ds, n_del * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(p->dd, dd, n_del * 4, hipMemcpyDeviceToDevice, st));
+        }
+        hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(128), 0, st, p->uc, n_ins, n_del, g->d_err);
+        phase_mark(g, st, true);
+        bool launched = false;
+        if (g->update_graphs && !p->graph_failed) {
+            if (!p->exec) {
+                if (!g->upd->cap_stream &&
+                    hipStreamCreateWithFlags(&g->upd->cap_stream, hipStreamNonBlocking) != hipSuccess)
+                    g->upd->cap_stream = nullptr;
+                hipStream_t cs = g->upd->cap_stream;
+                bool ok = cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    enqueue_update(g, p, cs);
+                    ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && p->graph;
+                }
+                if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+                if (!ok) {
+                    p->graph_failed = true;
+                    (void)hipGetLastError();
+                }
+            }
+            if (p->exec && hipGraphLaunch(p->exec, st) == hipSuccess) launched = true;
+        }
+        if (!launched) enqueue_update(g, p, st);
+        phase_mark(g, st, false);
+        unsigned long long uc[UC_WORDS];
+        uint32_t err = 0;
+        HIPCHK(hipMemcpyAsync(uc, p->uc, sizeof uc, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        hipFree(old);
-        g->ws = nw;
-        g->ws_bytes = grow;
-        const ptrdiff_t delta = (char*)nw - (char*)old;
-        keys = (uint64_t*)((char*)keys + delta); sk = (uint64_t*)((char*)sk + delta); hx = (uint64_t*)((char*)hx + delta);
-        vals = (uint32_t*)((char*)vals + delta); sv = (uint32_t*)((char*)sv + delta); head = (uint32_t*)((char*)head + delta);
-        rec_t = (uint32_t*)((char*)rec_t + delta); tv = (uint32_t*)((char*)tv + delta); tsa = (uint32_t*)((char*)tsa + delta);
-        tdl = (uint32_t*)((char*)tdl + delta); te = (uint32_t*)((char*)te + delta); fsz = (uint64_t*)((char*)fsz + delta);
-        foff = (uint64_t*)((char*)foff + delta); cnt = (unsigned long long*)((char*)cnt + delta);
-        w0 = (char*)nw;
+        if (err) return err_to_code(err);
+        if (uc[UC_FLAGS] & 1ull) {  // more candidates than the buffer held: nothing changed, retry larger
+            cmin = pow2_at_least(uc[UC_C], 1ull << 16) * 2;
+            continue;
+        }
+        if (h_stats) {
+            h_stats->inserted = uc[UC_STATS + 0];
+            h_stats->deleted = uc[UC_STATS + 1];
+            h_stats->not_found = uc[UC_STATS + 2];
+            h_stats->touched_vertices = uc[UC_T];
+            for (int i = 0; i < 25; ++i) h_stats->transitions[i] = uc[UC_STATS + 3 + i];
+        }
+        return BINGO_OK;
     }
-    char* w2 = w0 + p1;
-    uint64_t* ckey = (uint64_t*)w2;     w2 += al(CC * 8);
-    uint64_t* cks = (uint64_t*)w2;      w2 += al(CC * 8);
-    uint32_t* cval = (uint32_t*)w2;     w2 += al(CC * 4);
-    uint32_t* cvs = (uint32_t*)w2;      w2 += al(CC * 4);
-    uint32_t* first = (uint32_t*)w2;    w2 += al(R * 4);
-    uint32_t* matched = (uint32_t*)w2;  w2 += al(R * 4);
-    uint32_t* xs = (uint32_t*)w2;       w2 += al(R * 4);
-    uint64_t* xk = (uint64_t*)w2;       w2 += al(R * 8);
-    uint64_t* xks = (uint64_t*)w2;      w2 += al(R * 8);
-    uint32_t* sur = (uint32_t*)w2;      w2 += al(R * 8);
-    uint32_t* ncnt = (uint32_t*)w2;     w2 += al(T * 8);
-    uint64_t* xoff = (uint64_t*)w2;     w2 += al(T * 8);
-    uint64_t* needw = (uint64_t*)w2;    w2 += al(T * 8);
-    uint64_t* aoff = (uint64_t*)w2;     w2 += al(T * 8);
-    unsigned long long* parts = (unsigned long long*)w2;  w2 += al(PART_BLOCKS * 32 * 8);
-    void* tmp2 = w2;
-
-    phase_mark(g, st, false);
-    // ---- delete matching: candidates in one pass
-    const uint32_t mgrid = (uint32_t)std::max<uint64_t>((F + MB - 1) / MB, 1);
-    if (F) hipLaunchKernelGGL(k_match, dim3(mgrid), dim3(TB), 0, st, (uint64_t)F, T, foff, tv, tsa, tdl, te, sk, sv,
-                              vb, id, g->hdr, g->pool, cnt + 2, ckey, cval, (uint64_t)CC);
-    unsigned long long C = 0;
-    HIPCHK(hipMemcpyAsync(&C, cnt + 2, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-
-    HIPCHK(hipMemsetAsync(matched, 0xFF, R * 4, st));
-    HIPCHK(hipMemsetAsync(ncnt, 0, T * 4, st));
-    if (C) {
-        sort_pairs_u64(ckey, cval, cks, cvs, C, bits_for(R) + 32, tmp2, st);
-        hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, cks, (uint64_t)C, first);
-        hipLaunchKernelGGL(k_cand_assign, dim3(grid_for(C)), dim3(TB), 0, st, cks, cvs, (uint64_t)C, first, sk, R,
-                           rec_t, matched, ncnt);
-    }
-    phase_mark(g, st, false);
-    // X: deleted indices per touched vertex, sorted
-    const int tb = bits_for(T);
-    const uint64_t pad = ((uint64_t)T << 32) | 0xFFFFFFFFull;
-    hipLaunchKernelGGL(k_xkeys, dim3(grid_for(R)), dim3(TB), 0, st, R, matched, rec_t, pad, xk);
-    sort_keys_u64(xk, xks, R, tb + 32, tmp2, st);
-    hipLaunchKernelGGL(k_xextract, dim3(grid_for(R)), dim3(TB), 0, st, R, xks, xs);
-    scan_u32_to_u64(ncnt, xoff, T, tmp2, cnt + 4, st);
-
-    // ---- analysis and allocation
-    unsigned long long* dstats = cnt + 8;  // 32 counters (28 used)
-    const uint32_t vgrid = (uint32_t)std::min<uint64_t>((T + 3) / 4, PART_BLOCKS);
-    hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
-                       iw, g->rule, needw, parts);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)parts, vgrid, dstats, 0);
-    scan_u64(needw, aoff, T, tmp2, cnt + 5, st);
-    hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, ctl, g->pool_words, cnt + 5, g->d_err, cnt + 6);
-    unsigned long long ab[2];
-    HIPCHK(hipMemcpyAsync(ab, cnt + 5, 16, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (err) return err_to_code(err);
-
-    // ---- mutation
-    phase_mark(g, st, false);
-    hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, T, tv, tsa, tdl, te, ncnt, xoff, xs, g->hdr, g->pool, sv,
-                       id, iw, g->rule, aoff, (uint64_t)ab[1], sur, parts);
-    // garbage words freed by this batch: counter 0 of the partials, added to ctl[1]
-    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)parts, vgrid, cnt + 40, 0);
-    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, ctl + 1, (const unsigned long long*)(cnt + 40));
-    phase_mark(g, st, false);
-    unsigned long long hs[32];
-    HIPCHK(hipMemcpyAsync(hs, dstats, sizeof hs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (h_stats) {
-        h_stats->inserted = hs[0];
-        h_stats->deleted = hs[1];
-        h_stats->not_found = hs[2];
-        h_stats->touched_vertices = T;
-        for (int i = 0; i < 25; ++i) h_stats->transitions[i] = hs[3 + i];
-    }
-    return BINGO_OK;
+    return BINGO_E_CAPACITY;
 }

@@ -248,6 +248,52 @@ def test_update_rejects_bad_batches():
         assert np.array_equal(gg.export(), before)
 
 
+def test_update_graph_replays_match_eager():
+    """Batches run through the captured graph of their size bucket (replayed many times, with walks,
+    exports and a second bucket in between) leave the same structure as the eager launches and the
+    oracle."""
+    rng = random.Random(11)
+    n = 48
+    src = [rng.randrange(n) for _ in range(600)] + [0] * 400
+    dst = [rng.randrange(n) for _ in range(1000)]
+    w = [rng.choice([1, 3, 1 << rng.randrange(32), rng.randrange(1, 1 << 24)]) for _ in range(1000)]
+    og, gg = both(n, src, dst, w)
+    ge = B().Graph(n, *(torch.tensor(x, dtype=torch.int64) for x in (src, dst, w)))
+    ge.set_tuning(update_graphs=0)
+    assert gg.get_tuning()["update_graphs"] == 1 and ge.get_tuning()["update_graphs"] == 0
+    for b in range(12):
+        cur = O.parse_dump(og.dump(), n)
+        live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
+        big = b in (5, 9)  # a second size bucket between replays of the first
+        ni, nd = (1500, 900) if big else (rng.randrange(1, 300), rng.randrange(1, 300))
+        ins = [(rng.randrange(n), rng.randrange(n), rng.randrange(1, 1 << 32)) for _ in range(ni)]
+        dels = [rng.choice(live) if rng.random() < 0.9 else (rng.randrange(n), rng.randrange(n)) for _ in range(nd)]
+        apply_both(og, gg, ins, dels, "graph batch %d" % b)
+        t = [torch.tensor(x, dtype=torch.int64) for x in zip(*ins)] + [torch.tensor(x, dtype=torch.int64)
+                                                                        for x in zip(*dels)]
+        se = ge.update(*t)
+        assert np.array_equal(ge.export(), gg.export()), b
+        assert se["touched_vertices"] > 0
+        starts = np.arange(n).repeat(2)
+        pg, _ = gg.walk(starts, 10, 50 + b)
+        pe, _ = ge.walk(starts, 10, 50 + b)
+        assert np.array_equal(u32(pg), u32(pe)), b
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_update_candidate_overflow_retries(graphs):
+    """A small batch whose deletes hit more stored occurrences than the bucket's candidate buffer
+    holds is rerun with a larger buffer and still matches the oracle."""
+    og, gg = both(*skew_edges())
+    gg.set_tuning(update_graphs=graphs)
+    rng = random.Random(5)
+    ins = [(6, rng.randrange(60), rng.randrange(1, 1 << 32)) for _ in range(80000)]
+    apply_both(og, gg, ins, [], "hub grows to 85000 edges")
+    apply_both(og, gg, [(6, 1, 3)], [(6, t) for t in range(60)], "60 deletes hit every hub edge")
+    apply_both(og, gg, [(6, 2, 5)] * 4, [(6, 2)] * 3, "small batch after the retry")
+
+
 # --------------------------------------------------------------------------- larger graphs
 @pytest.mark.parametrize("weights", ["uniform24", "zipf", "lognormal"])
 def test_rmat_scale14(weights):
@@ -299,7 +345,8 @@ def test_results_independent_of_tuning(variant, bpc, chunk):
     c = c1()
     og, gg = both(c["n"], c["src"], c["dst"], c["w"])
     gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk)
-    assert gg.get_tuning() == {"walk_variant": variant, "blocks_per_cu": bpc, "queue_chunk": chunk}
+    t = gg.get_tuning()
+    assert (t["walk_variant"], t["blocks_per_cu"], t["queue_chunk"]) == (variant, bpc, chunk)
     paths, steps = gg.walk(c["starts"], c["length"], c["seed"])
     opaths, osteps = og.deepwalk(c["starts"], c["length"], c["seed"])
     assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps
