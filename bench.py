@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--mode", choices=["persistent", "per_step"], default="persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk (skips the autotuner)")
+    ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk[,dense_spec] (skips the autotuner)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
     ap.add_argument("--oracle-threads", type=int, default=16)
@@ -193,8 +193,9 @@ def main():
     stream = torch.cuda.current_stream()
     tune = None
     if args.tuning:
-        v, b_, q_ = (int(x) for x in args.tuning.split(","))
-        g.set_tuning(walk_variant=v, blocks_per_cu=b_, queue_chunk=q_)
+        t_ = [int(x) for x in args.tuning.split(",")]
+        g.set_tuning(walk_variant=t_[0], blocks_per_cu=t_[1], queue_chunk=t_[2],
+                     dense_spec=t_[3] if len(t_) > 3 else None)
     elif not args.no_autotune:
         from paper_2504_10233_amd.autotune import tune_ppr
         probe = sources[: max(1, args.sources // 10)]

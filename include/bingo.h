@@ -219,6 +219,11 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *   update_graphs    1: bingo_update_batch replays one captured hipGraph per
  *                    power-of-two batch-size bucket (default); 0: it launches
  *                    the same kernels one by one.
+ *   dense_spec       dense-rejection attempts issued together per round (1, 2
+ *                    or 4; 0 = default 2).  The attempt indices come from the
+ *                    step's random stream alone, so a round's loads are
+ *                    independent; the first accepting attempt in stream order
+ *                    wins, and results do not depend on this value.
  */
 typedef struct {
     uint32_t struct_size;
@@ -226,6 +231,7 @@ typedef struct {
     uint32_t blocks_per_cu;
     uint32_t queue_chunk;
     uint32_t update_graphs;
+    uint32_t dense_spec;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

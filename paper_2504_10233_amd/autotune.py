@@ -1,7 +1,7 @@
 """Autotuner for the persistent walk kernels.
 
-It sweeps the launch knobs of bingo_set_tuning (walk variant, resident blocks per compute unit,
-walk ids per queue atomic) on a probe query and keeps the fastest setting.  Walks are keyed by
+It sweeps the walk knobs of bingo_set_tuning (walk variant, resident blocks per compute unit,
+walk ids per queue atomic, dense-rejection attempts per round) on a probe query and keeps the fastest setting.  Walks are keyed by
 (seed, walk id), so every setting returns the same results; only the walk-kernel time differs.
 That time is read from the library's HIP events (bingo_last_phase_ms).  Results are cached as
 JSON keyed by device and workload signature.
@@ -11,8 +11,8 @@ from __future__ import annotations
 import json
 import os
 
-DEFAULT_SPACE = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=c)
-                 for v in (0, 1) for b in (0, 4, 2) for c in (64, 256, 1024)]
+DEFAULT_SPACE = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=c, dense_spec=s)
+                 for v in (0, 1) for b in (0, 4, 2) for c in (64, 256) for s in (1, 2, 4)]
 
 
 def _cache_path():

@@ -189,6 +189,7 @@ struct bingo_graph {
     uint32_t queue_chunk = 256;
     // update pipeline: 1 = capture one hipGraph per batch-size bucket and replay it
     uint32_t update_graphs = 1;
+    uint32_t dense_spec = 2;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // per-phase timing of the last walk / PPR / update call (events on its stream)
     hipEvent_t ev[PHASE_EVENTS] = {};

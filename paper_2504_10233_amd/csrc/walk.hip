@@ -16,8 +16,31 @@ namespace {
 constexpr int TB = 256;
 constexpr uint64_t NO_WALK = ~0ull;
 
+constexpr uint32_t PENDING = 0xFFFFFFFEu;
+
+// One round of SPEC dense-rejection attempts.  The attempt indices depend only
+// on the random stream, not on the loaded words, so the SPEC loads are issued
+// together and the dependent chain of a step shrinks from one load per attempt
+// to one per round.  The accepted slot is the first accepting attempt in stream
+// order, exactly as with one attempt at a time; words drawn for attempts after
+// it are never used (every step starts a fresh stream).  Returns PENDING when no
+// attempt of the round accepts.
+template <int SPEC>
+__device__ __forceinline__ uint32_t dense_round(const uint64_t* __restrict__ edges, uint32_t d, uint32_t sel,
+                                                RandStream& rs) {
+    uint64_t e[SPEC];
+#pragma unroll
+    for (int a = 0; a < SPEC; ++a) e[a] = edges[rs_below32(rs, d)];
+    uint32_t v = PENDING;
+#pragma unroll
+    for (int a = SPEC - 1; a >= 0; --a)
+        if ((e[a] >> (32 + sel)) & 1ull) v = (uint32_t)e[a];
+    return v;
+}
+
 // One transition from u (no termination test).  Returns the next vertex or
 // STOP_VERTEX for a vertex without out-edges.
+template <int SPEC>
 __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t u, RandStream& rs, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
@@ -54,10 +77,9 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
         // bit sel.  Acceptance is above alpha % per attempt, so the bound is
         // never reached on a consistent structure; it only keeps a corrupted
         // one from spinning forever.
-        for (uint32_t att = 0; att < (1u << 16); ++att) {
-            const uint32_t i = rs_below32(rs, d);
-            const uint64_t e = edges[i];
-            if ((e >> (32 + sel)) & 1ull) return (uint32_t)e;
+        for (uint32_t att = 0; att < (1u << 16); att += SPEC) {
+            const uint32_t v = dense_round<SPEC>(edges, d, (uint32_t)sel, rs);
+            if (v != PENDING) return v;
         }
         return STOP_VERTEX;
     }
@@ -78,8 +100,6 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
 // makes its first attempt, or makes one more attempt, so the lanes of a wave do
 // not wait for the lane with the longest rejection run.
 // ---------------------------------------------------------------------------
-constexpr uint32_t PENDING = 0xFFFFFFFEu;
-
 struct StepState {
     RandStream rs;
     uint64_t adj;
@@ -125,12 +145,13 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
     return pool[adj + 2ull * i];
 }
 
+template <int SPEC>
 __device__ __forceinline__ uint32_t step_attempt(const uint32_t* __restrict__ pool, StepState& ss) {
-    const uint32_t i = rs_below32(ss.rs, ss.d);
-    const uint64_t e = reinterpret_cast<const uint64_t*>(pool + ss.adj)[i];
-    if ((e >> (32 + ss.sel)) & 1ull) { ss.pending = false; return (uint32_t)e; }
+    const uint32_t v = dense_round<SPEC>(reinterpret_cast<const uint64_t*>(pool + ss.adj), ss.d, ss.sel, ss.rs);
+    if (v != PENDING) { ss.pending = false; return v; }
     // bounded only against a corrupted structure (acceptance is above alpha % per try)
-    if (++ss.tries >= (1u << 16)) { ss.pending = false; return STOP_VERTEX; }
+    ss.tries += SPEC;
+    if (ss.tries >= (1u << 16)) { ss.pending = false; return STOP_VERTEX; }
     return PENDING;
 }
 
@@ -171,6 +192,7 @@ __device__ __forceinline__ void wave_add_u64(unsigned long long* p, uint64_t v) 
 }
 
 // ------------------------------------------------------------------ DeepWalk
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __restrict__ hdr,
                                                             const uint32_t* __restrict__ pool, uint32_t n,
                                                             uint64_t nw, const uint32_t* __restrict__ starts,
@@ -212,7 +234,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
             if (s < L) {
                 RandStream rs;
                 rs_init(rs, seed, base + j, s);
-                const uint32_t v = walk_step_body(hdr, pool, u, rs, rule);
+                const uint32_t v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
                 if (v == STOP_VERTEX) {
                     for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
                     j = NO_WALK;
@@ -229,6 +251,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
     wave_add_u64(ctl + 1, steps);
 }
 
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __restrict__ hdr,
                                                              const uint32_t* __restrict__ pool, uint32_t n,
                                                              uint64_t nw, const uint32_t* __restrict__ starts,
@@ -272,7 +295,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
             rs_init(ss.rs, seed, base + j, s);
             v = step_begin(hdr, pool, u, ss, rule);
         }
-        if (j != NO_WALK && ss.pending) v = step_attempt(pool, ss);
+        if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
                 for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
@@ -289,6 +312,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
     wave_add_u64(ctl + 1, steps);
 }
 
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                       uint32_t n, uint64_t nw, const uint32_t* __restrict__ starts,
                                                       uint64_t base, uint32_t L, uint32_t s, uint64_t seed,
@@ -310,7 +334,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
         if (u != STOP_VERTEX) {
             RandStream rs;
             rs_init(rs, seed, base + j, s);
-            v = walk_step_body(hdr, pool, u, rs, rule);
+            v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
             steps += (v != STOP_VERTEX);
         }
         row[s + 1] = v;
@@ -341,6 +365,7 @@ __global__ void __launch_bounds__(TB) k_ppr_bound(uint64_t nw, uint64_t base, ui
     }
 }
 
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                        uint32_t R, uint64_t seed, uint64_t base, int vbits,
@@ -383,7 +408,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
             RandStream rs;
             rs_init(rs, seed, base + j, s);
             rs_next32(rs);  // the termination word, known to be >= thr here
-            const uint32_t v = walk_step_body(hdr, pool, u, rs, rule);
+            const uint32_t v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
                 j = NO_WALK;
@@ -399,6 +424,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
     wave_add_u64(ctl + 1, steps);
 }
 
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                         uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                         uint32_t R, uint64_t seed, uint64_t base, int vbits,
@@ -445,7 +471,7 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
             rs_next32(ss.rs);  // the termination word, known to be >= thr here
             v = step_begin(hdr, pool, u, ss, rule);
         }
-        if (j != NO_WALK && ss.pending) v = step_attempt(pool, ss);
+        if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
@@ -489,6 +515,7 @@ __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, con
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl[3] = nw;
 }
 
+template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                  uint32_t R, uint32_t s, uint64_t seed, uint64_t base, int vbits,
                                                  uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
@@ -513,7 +540,7 @@ __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hd
                 RandStream rs;
                 rs_init(rs, seed, base + id, s);
                 rs_next32(rs);
-                v = walk_step_body(hdr, pool, in_v[a], rs, rule);
+                v = walk_step_body<SPEC>(hdr, pool, in_v[a], rs, rule);
                 const uint64_t p0 = seg[id], l = len[id];
                 if (v == STOP_VERTEX) {
                     for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) keys[x] = pad;
@@ -702,8 +729,8 @@ inline uint32_t grid_for(uint64_t n) {
 
 int resident_grid(const void* kernel, uint32_t blocks_per_cu) {
     static int cus = 0;
-    static const void* seen[8] = {};
-    static int occ[8] = {};
+    static const void* seen[32] = {};
+    static int occ[32] = {};
     if (!cus) {
         int dev = 0;
         hipGetDevice(&dev);
@@ -711,12 +738,12 @@ int resident_grid(const void* kernel, uint32_t blocks_per_cu) {
         if (cus <= 0) cus = 256;
     }
     int per_cu = 0;
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 32; ++i)
         if (seen[i] == kernel) per_cu = occ[i];
     if (!per_cu) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, TB, 0) != hipSuccess || per_cu <= 0)
             per_cu = 4;
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 32; ++i)
             if (!seen[i]) { seen[i] = kernel; occ[i] = per_cu; break; }
     }
     if (blocks_per_cu && (int)blocks_per_cu < per_cu) per_cu = (int)blocks_per_cu;
@@ -727,6 +754,62 @@ int bits_for(uint64_t v) {
     int b = 0;
     while (b < 64 && (v >> b)) ++b;
     return b;
+}
+
+template <int SPEC>
+void deepwalk_kernels(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t L, uint64_t seed,
+                      uint32_t* paths, uint32_t mode, unsigned long long* ctl, hipStream_t st) {
+    if (mode == BINGO_WALK_PER_STEP) {
+        const uint32_t grid = grid_for(nw);
+        if (L == 0) {
+            // only the start entries
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+        }
+        for (uint32_t s = 0; s < L; ++s)
+            hipLaunchKernelGGL((k_deepwalk_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
+                               L, s, seed, paths, g->rule, ctl, g->d_err);
+    } else {
+        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved<SPEC> : (const void*)k_deepwalk_persistent<SPEC>;
+        const int rg = resident_grid(kern, g->blocks_per_cu);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
+        if (g->walk_variant)
+            hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+        else
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+    }
+}
+
+template <int SPEC>
+void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t cap, uint64_t seed,
+                 uint64_t base, int vbits, uint64_t pad, const uint64_t* seg, const uint32_t* len, uint32_t mode,
+                 uint64_t* idA, uint32_t* vA, uint64_t* idB, uint32_t* vB, unsigned long long* ctl, uint64_t* keys,
+                 hipStream_t st) {
+    const uint64_t nw = (uint64_t)nsrc * R;
+    if (mode == BINGO_WALK_PER_STEP) {
+        const uint32_t grid = grid_for(nw);
+        hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, vbits, pad, seg, len, idA,
+                           vA, ctl, keys, g->d_err);
+        for (uint32_t s = 0; s < cap; ++s) {
+            const int in_slot = s & 1;
+            hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
+            hipLaunchKernelGGL((k_ppr_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base, vbits, pad,
+                               g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
+                               in_slot ? vA : vB, ctl, in_slot, keys);
+        }
+    } else {
+        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC> : (const void*)k_ppr_persistent<SPEC>;
+        const int rg = resident_grid(kern, g->blocks_per_cu);
+        const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
+        if (g->walk_variant)
+            hipLaunchKernelGGL((k_ppr_interleaved<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+        else
+            hipLaunchKernelGGL((k_ppr_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+    }
 }
 
 }  // namespace
@@ -742,26 +825,10 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
         if (steps) HIPCHK(hipMemsetAsync(steps, 0, 8, st));
         return BINGO_OK;
     }
-    if (mode == BINGO_WALK_PER_STEP) {
-        const uint32_t grid = grid_for(nw);
-        if (L == 0) {
-            // only the start entries
-            hipLaunchKernelGGL(k_deepwalk_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
-        }
-        for (uint32_t s = 0; s < L; ++s)
-            hipLaunchKernelGGL(k_deepwalk_step, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
-                               L, s, seed, paths, g->rule, ctl, g->d_err);
-    } else {
-        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved : (const void*)k_deepwalk_persistent;
-        const int rg = resident_grid(kern, g->blocks_per_cu);
-        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
-        if (g->walk_variant)
-            hipLaunchKernelGGL(k_deepwalk_interleaved, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
-        else
-            hipLaunchKernelGGL(k_deepwalk_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+    switch (g->dense_spec) {
+        case 1: deepwalk_kernels<1>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+        case 4: deepwalk_kernels<4>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+        default: deepwalk_kernels<2>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
     }
     phase_mark(g, st, false);
     if (steps) HIPCHK(hipMemcpyAsync(steps, ctl + 1, 8, hipMemcpyDeviceToDevice, st));
@@ -817,31 +884,18 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     uint64_t* hpos = (uint64_t*)ws;    ws += al(TT * 8);
     void* tmp = ws;
     phase_mark(g, st, false);
+    uint64_t *idA = nullptr, *idB = nullptr;
+    uint32_t *vA = nullptr, *vB = nullptr;
     if (mode == BINGO_WALK_PER_STEP) {
-        uint64_t* idA = (uint64_t*)act;
-        uint32_t* vA = (uint32_t*)(act + al(nw * 8));
-        uint64_t* idB = (uint64_t*)(act + al(nw * 8) + al(nw * 4));
-        uint32_t* vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
-        const uint32_t grid = grid_for(nw);
-        hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, vbits, pad, seg, len, idA,
-                           vA, ctl, keys, g->d_err);
-        for (uint32_t s = 0; s < cap; ++s) {
-            const int in_slot = s & 1;
-            hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
-            hipLaunchKernelGGL(k_ppr_step, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base, vbits, pad,
-                               g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
-                               in_slot ? vA : vB, ctl, in_slot, keys);
-        }
-    } else {
-        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved : (const void*)k_ppr_persistent;
-        const int rg = resident_grid(kern, g->blocks_per_cu);
-        const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
-        if (g->walk_variant)
-            hipLaunchKernelGGL(k_ppr_interleaved, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
-                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
-        else
-            hipLaunchKernelGGL(k_ppr_persistent, dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
-                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+        idA = (uint64_t*)act;
+        vA = (uint32_t*)(act + al(nw * 8));
+        idB = (uint64_t*)(act + al(nw * 8) + al(nw * 4));
+        vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
+    }
+    switch (g->dense_spec) {
+        case 1: ppr_kernels<1>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
+        case 4: ppr_kernels<4>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
+        default: ppr_kernels<2>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
     }
     phase_mark(g, st, false);
     unsigned long long steps = 0;

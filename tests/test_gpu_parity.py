@@ -340,28 +340,31 @@ def test_generators_match_across_devices():
 
 
 # --------------------------------------------------------------------------- tuning invariance
-@pytest.mark.parametrize("variant,bpc,chunk", [(0, 0, 256), (1, 0, 256), (1, 1, 16), (0, 2, 4096), (1, 3, 64)])
-def test_results_independent_of_tuning(variant, bpc, chunk):
+@pytest.mark.parametrize("variant,bpc,chunk,spec", [(0, 0, 256, 1), (1, 0, 256, 2), (1, 1, 16, 4), (0, 2, 4096, 4),
+                                                    (1, 3, 64, 1), (0, 0, 64, 2)])
+def test_results_independent_of_tuning(variant, bpc, chunk, spec):
     c = c1()
     og, gg = both(c["n"], c["src"], c["dst"], c["w"])
-    gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk)
+    gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk, dense_spec=spec)
     t = gg.get_tuning()
-    assert (t["walk_variant"], t["blocks_per_cu"], t["queue_chunk"]) == (variant, bpc, chunk)
-    paths, steps = gg.walk(c["starts"], c["length"], c["seed"])
+    assert (t["walk_variant"], t["blocks_per_cu"], t["queue_chunk"], t["dense_spec"]) == (variant, bpc, chunk, spec)
     opaths, osteps = og.deepwalk(c["starts"], c["length"], c["seed"])
-    assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps
     thr = int(0.15 * 2**32)
     sources = np.arange(0, 1000, 37)
-    off, vtx, cnt, st = gg.ppr(sources, 100, thr, 200, seed=4)
     ooff, ovtx, ocnt, ost = og.ppr(sources, 100, thr, 200, seed=4)
-    assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and st == ost
+    for mode in (0, 1):
+        paths, steps = gg.walk(c["starts"], c["length"], c["seed"], mode=mode)
+        assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps, mode
+        off, vtx, cnt, st = gg.ppr(sources, 100, thr, 200, seed=4, mode=mode)
+        assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and st == ost, mode
 
 
 def test_tuning_rejects_bad_values():
     b = B()
     c = c1()
     _, gg = both(c["n"], c["src"], c["dst"], c["w"])
-    for kw in [dict(walk_variant=2), dict(queue_chunk=100), dict(queue_chunk=8), dict(blocks_per_cu=65)]:
+    for kw in [dict(walk_variant=2), dict(queue_chunk=100), dict(queue_chunk=8), dict(blocks_per_cu=65),
+               dict(dense_spec=3), dict(dense_spec=8), dict(update_graphs=2)]:
         with pytest.raises(b.BingoError):
             gg.set_tuning(**kw)
 
