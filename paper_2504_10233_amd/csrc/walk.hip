@@ -598,92 +598,147 @@ __global__ void k_counts(const uint64_t* __restrict__ hpos, uint64_t U, uint64_t
     if (blockIdx.x == 0 && threadIdx.x == 0) off[nsrc] = U;
 }
 
-// ------------------------------------------------------------------ per-source histogram in LDS
+// ------------------------------------------------------------------ per-source histogram
 // The visits of source q are the contiguous key range [seg[q R], seg[(q+1) R]).
-// One 1024-thread block per source sorts that range in LDS (bitonic), run-length
-// encodes it and writes (vertex << 32 | count) back over the start of the same
-// range; a compaction then builds the CSR.  A source whose range exceeds the
-// LDS capacity raises a flag and the query falls back to the global sort.
-constexpr int HB = 1024;
+// One block of HSB threads per source sorts that range (bitonic network over
+// N = HSB * E slots, the vertex id only: the source is implied by the block),
+// run-length encodes it and writes (vertex << 32 | count) back over the start of
+// the same range; a compaction then builds the CSR.  Thread t holds slots
+// [t E, t E + E) in registers: partners closer than E slots are exchanged in
+// registers, partners in the same wave by lane shuffles, and only the stages
+// that cross waves go through LDS (6 of the 91 stages at N = 8192), so the
+// block synchronizes a handful of times instead of once per stage.  E is chosen
+// per query from the longest range; ranges above HCAP take the global sort.
+constexpr int HSB = 512;
 constexpr uint32_t HCAP = 16384;
+constexpr uint32_t VINVALID = 0xFFFFFFFFu;  // padding: sorts after every vertex id
+static_assert(HSB * 32 == HCAP, "the widest histogram instantiation covers HCAP");
 
-__global__ void __launch_bounds__(HB) k_hist_seg(uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
-                                                 uint32_t R, uint32_t nsrc, uint64_t total, uint64_t pad,
-                                                 uint64_t vmask, uint32_t* __restrict__ ucount,
-                                                 unsigned long long* __restrict__ too_big) {
-    __shared__ uint32_t a[HCAP];
-    __shared__ uint32_t st[HCAP];
-    __shared__ uint32_t wsum[HB / 64];
-    const uint32_t q = blockIdx.x, tid = threadIdx.x;
+__device__ __forceinline__ void cmp_keep(uint32_t& a, uint32_t b, bool takemin) {
+    a = takemin ? min(a, b) : max(a, b);
+}
+
+template <int E>
+__global__ void __launch_bounds__(HSB) k_hist_seg(uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
+                                                  uint32_t R, uint32_t nsrc, uint64_t total, uint64_t pad,
+                                                  uint64_t vmask, uint32_t* __restrict__ ucount,
+                                                  unsigned long long* __restrict__ too_big) {
+    constexpr uint32_t N = HSB * E;
+    constexpr int NW = HSB / 64;
+    __shared__ uint32_t buf[N];
+    __shared__ uint32_t wred[2][NW];
+    const uint32_t q = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = t >> 6;
     const uint64_t S0 = seg[(uint64_t)q * R];
     const uint64_t S1 = (q + 1 < nsrc) ? seg[(uint64_t)(q + 1) * R] : total;
-    const uint32_t L = (uint32_t)std::min<uint64_t>(S1 - S0, (uint64_t)HCAP + 1);
-    if (L > HCAP) {
-        if (tid == 0) { ucount[q] = 0; atomicOr(too_big, 1ull); }
+    if (S1 - S0 > N) {
+        if (t == 0) { ucount[q] = 0; atomicOr(too_big, 1ull); }
         return;
     }
-    uint32_t P = 64;
-    while (P < L) P <<= 1;
-    for (uint32_t i = tid; i < P; i += HB) {
-        uint32_t v = 0xFFFFFFFFu;
+    const uint32_t L = (uint32_t)(S1 - S0);
+    uint32_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = t * E + e;
+        uint32_t v = VINVALID;
         if (i < L) {
             const uint64_t k = keys[S0 + i];
             if (k != pad) v = (uint32_t)(k & vmask);
         }
-        a[i] = v;
+        x[e] = v;
     }
-    __syncthreads();
-    // bitonic sort of a[0, P)
-    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+    // bitonic network: stage (kk, j) orders slot i against i ^ j, ascending where i & kk == 0
+#pragma unroll
+    for (uint32_t kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < P; i += HB) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint32_t x = a[i], y = a[l];
-                    const bool up = (i & kk) == 0;
-                    if ((x > y) == up) { a[i] = y; a[l] = x; }
+            if (j < (uint32_t)E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int p = e ^ (int)j;
+                    if (p > e) {
+                        const bool up = ((t * E + e) & kk) == 0;
+                        const uint32_t a = x[e], b = x[p];
+                        x[e] = up ? min(a, b) : max(a, b);
+                        x[p] = up ? max(a, b) : min(a, b);
+                    }
+                }
+            } else if (j < 64u * E) {
+                const int d = (int)(j / E);
+                const bool lower = (lane & d) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint32_t y = __shfl_xor(x[e], d, 64);
+                    const bool up = ((t * E + e) & kk) == 0;
+                    cmp_keep(x[e], y, lower == up);
+                }
+            } else {
+                const uint32_t dt = j / E;
+                __syncthreads();  // earlier readers of buf are done
+#pragma unroll
+                for (int e = 0; e < E; ++e) buf[t * E + e] = x[e];
+                __syncthreads();
+                const uint32_t pt = t ^ dt;
+                const bool lower = (t & dt) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool up = ((t * E + e) & kk) == 0;
+                    cmp_keep(x[e], buf[pt * E + e], lower == up);
                 }
             }
-            __syncthreads();
         }
     }
-    // run heads among valid entries; each thread scans a contiguous chunk of P / HB entries
-    const uint32_t per = (P + HB - 1) / HB;
-    const uint32_t b0 = tid * per, b1 = min(b0 + per, P);
-    uint32_t mine = 0;
-    for (uint32_t i = b0; i < b1; ++i)
-        if (a[i] != 0xFFFFFFFFu && (i == 0 || a[i] != a[i - 1])) ++mine;
-    const uint32_t lane = lane_id(), wave = tid >> 6;
-    uint32_t x = mine;
+    // run heads: slot i is a head if it holds a vertex different from slot i - 1
+    uint32_t prev = __shfl_up(x[E - 1], 1, 64);
+    __syncthreads();  // the last cross-wave stage has read buf
+    if (lane == 63) wred[0][wave] = x[E - 1];
+    __syncthreads();
+    if (lane == 0) prev = wave ? wred[0][wave - 1] : VINVALID;
+    uint32_t hmask = 0, nh = 0, nvalid = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t pv = e ? x[e - 1] : prev;
+        const bool valid = x[e] != VINVALID;
+        const bool head = valid && (t * E + e == 0 || x[e] != pv);
+        hmask |= (uint32_t)head << e;
+        nh += head;
+        nvalid += valid;
+    }
+    // block-wide exclusive scan of head counts; total heads and valid slots
+    uint32_t inc = nh, vs = nvalid;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o) inc += y;
     }
-    if (lane == 63) wsum[wave] = x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) vs += __shfl_xor(vs, o, 64);
+    __syncthreads();  // wred[0] reads above are done
+    if (lane == 63) wred[0][wave] = inc;
+    if (lane == 0) wred[1][wave] = vs;
     __syncthreads();
-    uint32_t before = 0, U = 0;
-    for (int w = 0; w < HB / 64; ++w) {
-        if (w < (int)wave) before += wsum[w];
-        U += wsum[w];
+    uint32_t before = 0, U = 0, V = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < (int)wave) before += wred[0][w];
+        U += wred[0][w];
+        V += wred[1][w];
     }
-    uint32_t r = before + x - mine;
-    for (uint32_t i = b0; i < b1; ++i)
-        if (a[i] != 0xFFFFFFFFu && (i == 0 || a[i] != a[i - 1])) st[r++] = i;
+    // head positions by rank, then each head's count is the gap to the next head
+    uint32_t r = before + inc - nh;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if ((hmask >> e) & 1u) buf[r++] = t * E + e;
     __syncthreads();
-    // number of valid entries: first invalid position (invalid entries sort last)
-    for (uint32_t k = tid; k < U; k += HB) {
-        const uint32_t from = st[k];
-        uint32_t to;
-        if (k + 1 < U) {
-            to = st[k + 1];
-        } else {
-            to = from;
-            while (to < P && a[to] == a[from]) ++to;
+    r = before + inc - nh;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if ((hmask >> e) & 1u) {
+            const uint32_t next = r + 1 < U ? buf[r + 1] : V;
+            keys[S0 + r] = ((uint64_t)x[e] << 32) | (next - (t * E + e));
+            ++r;
         }
-        keys[S0 + k] = ((uint64_t)a[from] << 32) | (to - from);
     }
-    if (tid == 0) ucount[q] = U;
+    if (t == 0) ucount[q] = U;
 }
 
 __global__ void __launch_bounds__(256) k_hist_compact(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
@@ -917,8 +972,18 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         // per-source histograms in LDS; ucount reuses the head array
         uint32_t* ucount = head;
         HIPCHK(hipMemsetAsync(ctl + 3, 0, 8, st));
-        hipLaunchKernelGGL(k_hist_seg, dim3(nsrc), dim3(HB), 0, st, keys, seg, R, nsrc, (uint64_t)total, pad,
-                           (1ull << vbits) - 1, ucount, ctl + 3);
+        const uint64_t vm = (1ull << vbits) - 1;
+        const uint64_t ml = tm[1];
+#define BINGO_HIST(E_)                                                                                         \
+    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, st, keys, seg, R, nsrc, (uint64_t)total, pad, vm, \
+                       ucount, ctl + 3)
+        if (ml <= HSB * 1) BINGO_HIST(1);
+        else if (ml <= HSB * 2) BINGO_HIST(2);
+        else if (ml <= HSB * 4) BINGO_HIST(4);
+        else if (ml <= HSB * 8) BINGO_HIST(8);
+        else if (ml <= HSB * 16) BINGO_HIST(16);
+        else BINGO_HIST(32);
+#undef BINGO_HIST
         scan_u32_to_u64(ucount, g->ppr_off, nsrc, tmp, ctl + 2, st);
         unsigned long long hv[2];
         HIPCHK(hipMemcpyAsync(hv, ctl + 2, 16, hipMemcpyDeviceToHost, st));

@@ -382,6 +382,19 @@ def test_ppr_histogram_global_path():
         assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and steps == osteps
 
 
+@pytest.mark.parametrize("R,cap", [(40, 9), (100, 9), (200, 9), (300, 12), (500, 15), (1000, 15), (1489, 10)])
+def test_ppr_histogram_widths(R, cap):
+    """p = 0 fixes every per-source key range at R * (cap + 1), so these cases pick each register
+    width of the per-source sort (512 to 16384 slots, the last one exactly full); sinks pad ranges."""
+    c = c1()
+    og, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    sources = np.array([0, 3, 4, 900, 17, 17])
+    off, vtx, cnt, steps = gg.ppr(sources, R, 0, cap, seed=R, base=3)
+    ooff, ovtx, ocnt, osteps = og.ppr(sources, R, 0, cap, seed=R, base=3)
+    assert np.array_equal(off.cpu().numpy().astype(np.uint64), ooff)
+    assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and steps == osteps
+
+
 def test_autotune_keeps_results():
     from paper_2504_10233_amd.autotune import tune_ppr
     c = c1()
