@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
     ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--no-random-probe", action="store_true",
+                    help="skip the random 64-byte gather probe (context for the roofline)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration runs)")
     return ap.parse_args()
@@ -124,6 +126,34 @@ def serve_phase(g, n, src, dst, args, log):
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
     return res
+
+
+def random_gather_probe(dev, table_gib=8, gathers=1 << 26, reps=3):
+    """Achievable rate of independent random 64-byte reads on this GPU, measured with torch's
+    index_select over a table far larger than the caches (context for the walk kernel's roofline:
+    the walk's reads are random 64-byte lines too, but each walk's reads form a dependent chain)."""
+    import torch
+    rows = (table_gib << 30) // 64
+    table = torch.empty((rows, 16), dtype=torch.int32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(77)
+    idx = torch.randint(0, rows, (gathers,), device=dev, generator=g)
+    out = torch.empty((gathers, 16), dtype=torch.int32, device=dev)
+    torch.index_select(table, 0, idx, out=out)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.index_select(table, 0, idx, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del table, idx, out
+    torch.cuda.empty_cache()
+    return {"random_64B_read_GBps": gathers * 64 / (best / 1e3) / 1e9,
+            "total_GBps_incl_index_and_output": gathers * (64 + 64 + 8) / (best / 1e3) / 1e9,
+            "table_GiB": table_gib, "gathers": gathers, "kernel": "torch.index_select"}
 
 
 def torch_index(pos):
@@ -243,6 +273,11 @@ def main():
     if args.serve_requests:
         serving = serve_phase(g, n, src, dst, args, log)
 
+    probe = None
+    if not args.no_random_probe:
+        probe = random_gather_probe(dev)
+        log("random 64-byte gather probe: %.0f GB/s of random reads" % probe["random_64B_read_GBps"])
+
     if args.calibrate_copy_mb:
         a = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.int32, device=dev)
         b = torch.empty_like(a)
@@ -326,6 +361,10 @@ def main():
         ach = byts / (walk_ms / len(timed) / 1e3) / 1e9
         roof.update({"achieved": ach, "frac": ach / HBM_PEAK_GBS, "bytes_per_transition": per_step,
                      "lines_per_transition": lines / mix["steps"]})
+    if probe:
+        roof["random_gather_probe"] = probe
+        if roof["achieved"]:
+            roof["frac_of_random_gather_probe"] = roof["achieved"] / probe["random_64B_read_GBps"]
     prof = os.path.join(ROOT, "profiles", "walk_kernel_counters.json")
     if os.path.exists(prof):
         pc = json.load(open(prof))
