@@ -81,51 +81,66 @@ __global__ void __launch_bounds__(WB) k_dump_write(const uint32_t* __restrict__ 
 
 // memory statistics: [0] groups by type (5), [5] list live bytes, [6] list reserved bytes,
 // [10] adjacency reserved bytes, [11] GA model bytes, [12] BS model bytes, [13] edges
+// Totals are kept per wave in registers over a grid-stride loop and reduced per
+// block; one atomic per counter per block (per-vertex atomics on a dozen
+// addresses would serialize in L2 over 10^7 vertices).
+constexpr uint32_t MEM_GRID = 2048;
+constexpr int MEM_CTRS = 14;
+
 __global__ void __launch_bounds__(WB) k_mem(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                             uint32_t n, GroupRule rule, unsigned long long* __restrict__ acc) {
-    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
-    if (u >= n) return;
-    const uint32_t lane = lane_id();
-    const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-    const uint32_t d = h[H_DEG], mask = h[H_MASK];
-    const bool ne = lane < 32 && ((mask >> lane) & 1u);
-    const uint32_t c = ne ? h[H_CNT + lane] : 0u;
-    const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
-    const uint32_t capb = lane < 32 ? ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
-    const uint32_t smask = (uint32_t)(__ballot(ne && t == GT_SPARSE) & 0xFFFFFFFFull);
-    // |S(u)|: edges in at least one sparse group
-    uint64_t S = 0;
-    if (smask) {
-        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
-        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
-        for (uint32_t i0 = 0; i0 < d; i0 += 64) {
-            const uint32_t i = i0 + lane;
-            const bool in = i < d && ((uint32_t)(edges[i] >> 32) & smask);
-            S += __popcll(__ballot(in));
+    __shared__ unsigned long long red[WB / 64][MEM_CTRS];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint64_t tot[MEM_CTRS];  // identical in every lane of the wave
+#pragma unroll
+    for (int i = 0; i < MEM_CTRS; ++i) tot[i] = 0;
+    for (uint64_t u = (uint64_t)blockIdx.x * (WB / 64) + wave; u < n; u += (uint64_t)gridDim.x * (WB / 64)) {
+        const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG], mask = h[H_MASK];
+        const bool ne = lane < 32 && ((mask >> lane) & 1u);
+        const uint32_t c = ne ? h[H_CNT + lane] : 0u;
+        const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+        const uint32_t capb = lane < 32 ? ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
+        const uint32_t smask = (uint32_t)(__ballot(ne && t == GT_SPARSE) & 0xFFFFFFFFull);
+        // |S(u)|: edges in at least one sparse group
+        uint64_t S = 0;
+        if (smask) {
+            const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+            const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
+            for (uint32_t i0 = 0; i0 < d; i0 += 64) {
+                const uint32_t i = i0 + lane;
+                const bool in = i < d && ((uint32_t)(edges[i] >> 32) & smask);
+                S += __popcll(__ballot(in));
+            }
         }
+        uint64_t v[4] = {0, 0, 0, 0};  // live list, reserved list, ga, bs
+        if (ne) {
+            if (type_listed(t)) { v[0] = 4ull * c; v[1] = 4ull << capb; }
+            v[2] = t == GT_ONE ? 4ull : (t == GT_SPARSE ? 4ull * c + 4ull * S : (t == GT_REGULAR ? 4ull * (c + (uint64_t)d) : 0));
+            v[3] = 4ull * (c + (uint64_t)d);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
+#pragma unroll
+        for (int tt = 1; tt < 5; ++tt) tot[tt] += __popcll(__ballot(ne && t == (uint32_t)tt));
+        tot[5] += v[0];
+        tot[6] += v[1];
+        tot[10] += 12ull * h[H_ACAP];
+        tot[11] += v[2] + 4ull * S + 12ull * d;
+        tot[12] += v[3] + 12ull * d;
+        tot[13] += d;
     }
-    uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0};  // live list, reserved list, ga, bs
-    if (ne) {
-        if (type_listed(t)) { v[0] = 4ull * c; v[1] = 4ull << capb; }
-        v[2] = t == GT_ONE ? 4ull : (t == GT_SPARSE ? 4ull * c + 4ull * S : (t == GT_REGULAR ? 4ull * (c + (uint64_t)d) : 0));
-        v[3] = 4ull * (c + (uint64_t)d);
-    }
+    if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < MEM_CTRS; ++i) red[wave][i] = tot[i];
+    __syncthreads();
+    if (threadIdx.x < MEM_CTRS) {
+        unsigned long long x = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
-    // groups by type
-    uint64_t cnt_t[5];
-#pragma unroll
-    for (int tt = 0; tt < 5; ++tt) cnt_t[tt] = __popcll(__ballot(ne && t == (uint32_t)tt));
-    if (lane == 0) {
-        for (int tt = 1; tt < 5; ++tt) if (cnt_t[tt]) atomicAdd(acc + tt, (unsigned long long)cnt_t[tt]);
-        if (v[0]) atomicAdd(acc + 5, (unsigned long long)v[0]);
-        if (v[1]) atomicAdd(acc + 6, (unsigned long long)v[1]);
-        atomicAdd(acc + 10, 12ull * h[H_ACAP]);
-        atomicAdd(acc + 11, (unsigned long long)(v[2] + 4ull * S + 12ull * d));
-        atomicAdd(acc + 12, (unsigned long long)(v[3] + 12ull * d));
-        atomicAdd(acc + 13, (unsigned long long)d);
+        for (int w = 0; w < WB / 64; ++w) x += red[w][threadIdx.x];
+        if (x) atomicAdd(acc + threadIdx.x, x);
     }
 }
 
@@ -165,7 +180,8 @@ int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st) {
     unsigned long long* acc = (unsigned long long*)ws_get(g, 16 * 8);
     if (!acc) return BINGO_E_OOM;
     HIPCHK(hipMemsetAsync(acc, 0, 16 * 8, st));
-    hipLaunchKernelGGL(k_mem, dim3((g->n + 3) / 4), dim3(WB), 0, st, g->hdr, g->pool, g->n, g->rule, acc);
+    hipLaunchKernelGGL(k_mem, dim3(std::min<uint32_t>(MEM_GRID, (g->n + 3) / 4)), dim3(WB), 0, st, g->hdr, g->pool, g->n,
+                       g->rule, acc);
     unsigned long long a[16], ctl[2];
     HIPCHK(hipMemcpyAsync(a, acc, sizeof a, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
