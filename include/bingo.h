@@ -301,6 +301,26 @@ int bingo_server_wait(bingo_server* s, uint64_t ticket, uint32_t* h_paths, uint6
 /* bingo_server_destroy -- finish all submitted requests, stop the thread, free the server. */
 int bingo_server_destroy(bingo_server* s);
 
+/*
+ * bingo_probe_random_reads -- measurement aid, not part of the method.  Times
+ * one kernel of `lanes` threads that each read `reads` random lines of
+ * `line_bytes` (64 or 128) from d_table, giving the random-line read rate this
+ * device sustains (the ceiling that bounds the walk kernels, whose transitions
+ * are short chains of dependent random line reads).
+ *   d_table      device buffer of table_bytes bytes (at least 64 KiB, a
+ *                multiple of line_bytes; contents arbitrary, only read).
+ *   lanes        multiple of 256; reads a multiple of 4.
+ *   dependent    0: a lane's addresses hash (seed, lane, read index), so each
+ *                lane keeps 4 reads in flight; 1: each address also hashes the
+ *                previous line's content (one pointer chase per lane).
+ *   d_sink       lanes uint32 written (keeps the reads live).
+ *   h_ms         receives the kernel time from HIP events on the stream.
+ * Synchronizes.  BINGO_E_INVALID for a bad size or line width.
+ */
+int bingo_probe_random_reads(const void* d_table, uint64_t table_bytes, uint32_t lanes, uint32_t reads,
+                             uint32_t dependent, uint32_t line_bytes, uint64_t seed, uint32_t* d_sink,
+                             float* h_ms, void* stream);
+
 /* bingo_num_vertices -- n of the handle. */
 uint32_t bingo_num_vertices(const bingo_graph* g);
 

@@ -52,7 +52,8 @@ class _MemStats(C.Structure):
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
-           "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy"]
+           "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
+           "bingo_probe_random_reads"]
 
 
 class _ServerConfig(C.Structure):
@@ -101,6 +102,7 @@ def load():
         L.bingo_server_submit_update.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, C.POINTER(u64)]
         L.bingo_server_wait.argtypes = [vp, u64, vp, u64, C.POINTER(_RequestInfo)]
         L.bingo_server_destroy.argtypes = [vp]
+        L.bingo_probe_random_reads.argtypes = [vp, u64, u32, u32, u32, u32, u64, vp, C.POINTER(C.c_float), vp]
         L.bingo_num_vertices.argtypes = [vp]
         L.bingo_num_vertices.restype = u32
         L.bingo_destroy.argtypes = [vp]
@@ -109,6 +111,20 @@ def load():
         L.bingo_strerror.restype = C.c_char_p
         _lib = L
         return L
+
+
+def probe_random_reads(table, lanes, reads, dependent, line_bytes=64, seed=1, stream=None) -> dict:
+    """Random-line read rate over a device tensor (measurement aid; see bingo_probe_random_reads)."""
+    import torch
+    sink = torch.empty(lanes, dtype=torch.int32, device=table.device)
+    ms = C.c_float(0.0)
+    rc = load().bingo_probe_random_reads(C.c_void_p(table.data_ptr()), table.numel() * table.element_size(), lanes,
+                                         reads, int(bool(dependent)), line_bytes, seed, _ptr(sink), C.byref(ms),
+                                         _stream(stream))
+    _check(rc, "bingo_probe_random_reads")
+    n = lanes * reads
+    return {"ms": ms.value, "lines_per_s": n / (ms.value / 1e3), "GBps": n * line_bytes / (ms.value / 1e3) / 1e9,
+            "lanes": lanes, "reads_per_lane": reads, "dependent": bool(dependent), "line_bytes": line_bytes}
 
 
 def ppr_threshold(p: float) -> int:

@@ -50,3 +50,17 @@ def test_build_rejects_bad_arguments_without_gpu():
     lib = ctypes.CDLL(_lib_path())
     out = ctypes.c_void_p()
     assert lib.bingo_build(None, 10, 0, None, None, None, None, ctypes.byref(out)) == -1
+
+
+def test_probe_rejects_bad_arguments_without_gpu():
+    lib = ctypes.CDLL(_lib_path())
+    f = lib.bingo_probe_random_reads
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    ms = ctypes.c_float()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its argument checks
+    assert f(None, 1 << 20, 256, 4, 0, 64, 1, fake, ctypes.byref(ms), None) == -1
+    assert f(fake, 1 << 20, 256, 4, 0, 32, 1, fake, ctypes.byref(ms), None) == -1   # line width
+    assert f(fake, 1 << 10, 256, 4, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # table too small
+    assert f(fake, 1 << 20, 100, 4, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # lanes
+    assert f(fake, 1 << 20, 256, 3, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # reads
