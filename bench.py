@@ -247,10 +247,13 @@ def main():
         rows.append({"update_ms": e0.elapsed_time(e1), "ppr_ms": e1.elapsed_time(e2),
                      "step_ms": e0.elapsed_time(e2), "bound_ms": ppr_phases[0], "walk_kernel_ms": ppr_phases[1],
                      "hist_ms": ppr_phases[2], "update_phases_ms": upd_phases, "steps": steps,
-                     "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel())})
-        log("step %d: update %.2f ms %s, ppr %.2f ms (bound %.2f, walk kernel %.2f, histogram %.2f), %d transitions" %
-            (i, rows[-1]["update_ms"], ["%.2f" % x for x in upd_phases], rows[-1]["ppr_ms"], ppr_phases[0],
-             ppr_phases[1], ppr_phases[2], steps))
+                     "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel()),
+                     "touched_vertices": st["touched_vertices"], "match_scanned": st["match_scanned"],
+                     "match_candidates": st["match_candidates"]})
+        log("step %d: update %.2f ms %s (%d touched, %d scanned to locate deletes), ppr %.2f ms (bound %.2f, walk "
+            "kernel %.2f, histogram %.2f), %d transitions" %
+            (i, rows[-1]["update_ms"], ["%.2f" % x for x in upd_phases], st["touched_vertices"], st["match_scanned"],
+             rows[-1]["ppr_ms"], ppr_phases[0], ppr_phases[1], ppr_phases[2], steps))
         if i == nb - 1:
             last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32),
                     steps)

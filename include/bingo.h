@@ -67,6 +67,8 @@ typedef struct {
     uint64_t not_found;         /* delete records with no live matching edge */
     uint64_t touched_vertices;  /* vertices with at least one record */
     uint64_t transitions[25];   /* [old*5 + new] group-type changes over all groups of touched vertices */
+    uint64_t match_scanned;     /* live edges and inserts of vertices with deletes, scanned to locate them */
+    uint64_t match_candidates;  /* scanned entries whose dst is among their vertex's delete targets */
 } bingo_update_stats;
 
 typedef struct {

@@ -37,7 +37,8 @@ class _Config(C.Structure):
 
 class _UpdateStats(C.Structure):
     _fields_ = [("inserted", C.c_uint64), ("deleted", C.c_uint64), ("not_found", C.c_uint64),
-                ("touched_vertices", C.c_uint64), ("transitions", C.c_uint64 * 25)]
+                ("touched_vertices", C.c_uint64), ("transitions", C.c_uint64 * 25), ("match_scanned", C.c_uint64),
+                ("match_candidates", C.c_uint64)]
 
 
 class _MemStats(C.Structure):
@@ -218,7 +219,8 @@ class Graph:
                                        _stream(stream), C.byref(stats))
         _check(rc, "bingo_update_batch")
         return {"inserted": stats.inserted, "deleted": stats.deleted, "not_found": stats.not_found,
-                "touched_vertices": stats.touched_vertices,
+                "touched_vertices": stats.touched_vertices, "match_scanned": stats.match_scanned,
+                "match_candidates": stats.match_candidates,
                 "transitions": np.array(list(stats.transitions), dtype=np.int64).reshape(5, 5)}
 
     def export(self, u_begin=None, u_end=None, stream=None) -> np.ndarray:

@@ -184,12 +184,26 @@ __device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, ui
 // Candidate search: every element of the flat space (live edges, then inserts,
 // of each touched vertex with deletes) whose dst is among the vertex's delete
 // targets becomes a candidate (run << 32 | seq, virtual index).  The grid loops
-// over blocks of MB elements.  A block of elements that belongs to a single
-// vertex stages that vertex's header fields and delete targets in LDS, so the
-// per-element search runs in LDS (hubs); other blocks search global memory
-// (small vertices with few targets).  Each block reserves its output range with
-// one atomic.
-constexpr uint32_t LDS_TARGETS = 4096;
+// over ranges of MB elements.  A range stages what its elements look up: the
+// offsets and header fields of the (at most MV) touched vertices it spans and
+// the dst of their batch records, so the per-element vertex search and target
+// search run in LDS; a range that spans more vertices or records than that
+// searches global memory instead.  Hits collect in an LDS buffer that is
+// written out (one atomic per flush) when it could not take another range, so
+// the global atomics number about one per OUTCAP hits, not one per range.
+constexpr uint32_t LDS_TARGETS = 2048;
+constexpr uint32_t MV = 128;      // staged vertices per range
+constexpr uint32_t OUTCAP = 2048;  // buffered hits per block (>= MB + a range's worth)
+static_assert(OUTCAP >= 2 * MB, "the hit buffer takes a full range after any flush threshold");
+
+__device__ __forceinline__ uint32_t find_t_lds(const uint64_t* __restrict__ fo, uint32_t nv, uint64_t f) {
+    uint32_t lo = 0, hi = nv - 1;  // last k with fo[k] <= f
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (fo[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ uc, const uint64_t* __restrict__ foff,
                                               const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
@@ -198,39 +212,53 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                                               int vb, const uint32_t* __restrict__ id, const uint32_t* __restrict__ hdr,
                                               const uint32_t* __restrict__ pool, uint64_t* __restrict__ ckey,
                                               uint32_t* __restrict__ cval, uint64_t cap) {
-    __shared__ uint32_t range[2];
-    __shared__ uint32_t vinfo[8];  // d, acap, nseq, adj lo, adj hi, ts, tdl, te of a single-vertex block
+    __shared__ uint64_t s_fo[MV];
+    __shared__ uint32_t s_v[8][MV];  // d, acap, nseq, adj lo, adj hi, ts, tdl, te
     __shared__ uint32_t tgt[LDS_TARGETS];
+    __shared__ uint64_t okey[OUTCAP];
+    __shared__ uint32_t oidx[OUTCAP];
+    __shared__ uint32_t range[4];  // tlo, thi, record base, staged flags
     __shared__ uint32_t wtot[TB / 64];
-    __shared__ unsigned long long bbase;
+    __shared__ uint32_t ocount;
+    __shared__ unsigned long long obase;
     const uint64_t F = uc[UC_F], T = uc[UC_T];
     const uint64_t nblk = (F + MB - 1) / MB;
     constexpr int PER = MB / TB;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) ocount = 0;
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const uint64_t f0 = blk * MB;
-        __syncthreads();  // the previous block's users of the shared state are done
+        __syncthreads();  // the previous range's users of the shared state are done
         if (threadIdx.x == 0) {
-            range[0] = find_t(foff, 0, (uint32_t)T - 1, f0);
-            range[1] = find_t(foff, range[0], (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
-            if (range[0] == range[1]) {
-                const uint32_t t = range[0];
-                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-                vinfo[0] = h[H_DEG]; vinfo[1] = h[H_ACAP]; vinfo[2] = h[H_NSEQ];
-                vinfo[3] = h[H_ADJLO]; vinfo[4] = h[H_ADJHI];
-                vinfo[5] = ts[t]; vinfo[6] = tdl[t]; vinfo[7] = te[t];
-            }
+            const uint32_t tlo = find_t(foff, 0, (uint32_t)T - 1, f0);
+            const uint32_t thi = find_t(foff, tlo, (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
+            const uint32_t rb = ts[tlo], re = te[thi];
+            range[0] = tlo;
+            range[1] = thi;
+            range[2] = rb;
+            range[3] = (thi - tlo < MV ? 1u : 0u) | (re - rb <= LDS_TARGETS ? 2u : 0u);
         }
         __syncthreads();
-        const uint32_t tlo = range[0], thi = range[1];
-        const bool single = tlo == thi;
-        const uint32_t nd1 = single ? vinfo[7] - vinfo[6] : 0u;
-        const bool staged = single && nd1 <= LDS_TARGETS;
-        if (staged) {
-            for (uint32_t i = threadIdx.x; i < nd1; i += TB) tgt[i] = key_dst(sk[vinfo[6] + i], vb);
-            __syncthreads();
+        const uint32_t tlo = range[0], thi = range[1], rbase = range[2];
+        const bool vstaged = range[3] & 1u, tstaged = (range[3] & 2u) != 0;
+        const uint32_t nv = thi - tlo + 1;
+        if (vstaged) {
+            for (uint32_t k = threadIdx.x; k < nv; k += TB) {
+                const uint32_t t = tlo + k;
+                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+                s_fo[k] = foff[t];
+                s_v[0][k] = h[H_DEG]; s_v[1][k] = h[H_ACAP]; s_v[2][k] = h[H_NSEQ];
+                s_v[3][k] = h[H_ADJLO]; s_v[4][k] = h[H_ADJHI];
+                s_v[5][k] = ts[t]; s_v[6][k] = tdl[t]; s_v[7][k] = te[t];
+            }
         }
+        if (tstaged) {
+            const uint32_t re = te[thi];
+            for (uint32_t p = rbase + threadIdx.x; p < re; p += TB) tgt[p - rbase] = key_dst(sk[p], vb);
+        }
+        __syncthreads();
         // each thread looks at PER elements; hits stay in registers until the
-        // block has reserved one contiguous output range
+        // block has placed them in the LDS buffer
         uint64_t hkey[PER];
         uint32_t hidx[PER];
         uint32_t nh = 0;
@@ -240,20 +268,23 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
             hkey[r] = 0;
             hidx[r] = 0;
             if (f < F) {
-                uint32_t t, d, acap, nseq, tsv, tdlv, tev;
-                uint64_t adj;
-                if (single) {
-                    t = tlo; d = vinfo[0]; acap = vinfo[1]; nseq = vinfo[2];
-                    adj = ((uint64_t)vinfo[4] << 32) | vinfo[3];
-                    tsv = vinfo[5]; tdlv = vinfo[6]; tev = vinfo[7];
+                uint32_t d, acap, nseq, tsv, tdlv, tev;
+                uint64_t adj, fo;
+                if (vstaged) {
+                    const uint32_t k = find_t_lds(s_fo, nv, f);
+                    fo = s_fo[k];
+                    d = s_v[0][k]; acap = s_v[1][k]; nseq = s_v[2][k];
+                    adj = ((uint64_t)s_v[4][k] << 32) | s_v[3][k];
+                    tsv = s_v[5][k]; tdlv = s_v[6][k]; tev = s_v[7][k];
                 } else {
-                    t = find_t(foff, tlo, thi, f);
+                    const uint32_t t = find_t(foff, tlo, thi, f);
                     const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+                    fo = foff[t];
                     d = h[H_DEG]; acap = h[H_ACAP]; nseq = h[H_NSEQ];
                     adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
                     tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
                 }
-                const uint32_t i = (uint32_t)(f - foff[t]);
+                const uint32_t i = (uint32_t)(f - fo);
                 uint32_t dst, seq;
                 if (i < d) {
                     dst = pool[adj + 2ull * i];
@@ -263,33 +294,28 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                     dst = id[sv[tsv + a]];
                     seq = nseq + a;
                 }
-                uint32_t lo;
-                bool found;
-                if (staged) {
-                    uint32_t l = 0, rr = nd1;
+                // lower bound of dst among the vertex's delete targets [tdlv, tev)
+                uint32_t l = tdlv, rr = tev;
+                if (tstaged) {
                     while (l < rr) {
                         const uint32_t mid = (l + rr) >> 1;
-                        if (tgt[mid] < dst) l = mid + 1; else rr = mid;
+                        if (tgt[mid - rbase] < dst) l = mid + 1; else rr = mid;
                     }
-                    lo = tdlv + l;
-                    found = l < nd1 && tgt[l] == dst;
                 } else {
-                    uint32_t l = tdlv, rr = tev;
                     while (l < rr) {
                         const uint32_t mid = (l + rr) >> 1;
                         if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
                     }
-                    lo = l;
-                    found = l < tev && key_dst(sk[l], vb) == dst;
                 }
+                const bool found = l < tev && (tstaged ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
                 if (found) {
-                    hkey[nh] = ((uint64_t)lo << 32) | seq;
+                    hkey[nh] = ((uint64_t)l << 32) | seq;
                     hidx[nh] = i;
                     ++nh;
                 }
             }
         }
-        const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+        // place the hits at the end of the LDS buffer
         uint32_t x = nh;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -304,14 +330,39 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
             if (w < (int)wave) before += wtot[w];
             total += wtot[w];
         }
-        if (threadIdx.x == 0) bbase = total ? atomicAdd(uc + UC_C, (unsigned long long)total) : 0ull;
-        __syncthreads();
-        const uint64_t pos0 = bbase + before + x - nh;
+        const uint32_t o0 = ocount + before + x - nh;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            if ((uint32_t)r < nh && pos0 + r < cap) {
-                ckey[pos0 + r] = hkey[r];
-                cval[pos0 + r] = hidx[r];
+            if ((uint32_t)r < nh) {
+                okey[o0 + r] = hkey[r];
+                oidx[o0 + r] = hidx[r];
+            }
+        }
+        __syncthreads();  // all threads have read ocount and written their hits
+        if (threadIdx.x == 0) ocount += total;
+        __syncthreads();
+        // flush when the buffer could not take another full range
+        if (ocount > OUTCAP - MB) {
+            if (threadIdx.x == 0) obase = atomicAdd(uc + UC_C, (unsigned long long)ocount);
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < ocount; k += TB) {
+                if (obase + k < cap) {
+                    ckey[obase + k] = okey[k];
+                    cval[obase + k] = oidx[k];
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) ocount = 0;
+        }
+    }
+    __syncthreads();
+    if (ocount) {
+        if (threadIdx.x == 0) obase = atomicAdd(uc + UC_C, (unsigned long long)ocount);
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < ocount; k += TB) {
+            if (obase + k < cap) {
+                ckey[obase + k] = okey[k];
+                cval[obase + k] = oidx[k];
             }
         }
     }
@@ -1058,6 +1109,8 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
             h_stats->deleted = uc[UC_STATS + 1];
             h_stats->not_found = uc[UC_STATS + 2];
             h_stats->touched_vertices = uc[UC_T];
+            h_stats->match_scanned = uc[UC_F];
+            h_stats->match_candidates = uc[UC_C];
             for (int i = 0; i < 25; ++i) h_stats->transitions[i] = uc[UC_STATS + 3 + i];
         }
         return BINGO_OK;
