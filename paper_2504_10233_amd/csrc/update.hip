@@ -196,6 +196,27 @@ constexpr uint32_t MV = 128;      // staged vertices per range
 constexpr uint32_t OUTCAP = 2048;  // buffered hits per block (>= MB + a range's worth)
 static_assert(OUTCAP >= 2 * MB, "the hit buffer takes a full range after any flush threshold");
 
+// Wave-cooperative form of find_t over [0, tmax] (foff[0] = 0 <= f): each round
+// probes 64 evenly spaced offsets at once and keeps the stride the answer lies
+// in, so a search over 10^6 vertices takes 4 dependent loads instead of 20.
+// Every lane of the wave calls it and gets the result.
+__device__ __forceinline__ uint32_t wave_find_t(const uint64_t* __restrict__ foff, uint32_t tmax, uint64_t f) {
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0, hi = tmax;  // invariant: foff[lo] <= f, answer in [lo, hi]
+    while (hi - lo >= 64) {
+        const uint32_t stride = (uint32_t)(((uint64_t)(hi - lo) + 64) / 64);  // 64 * stride > hi - lo
+        const uint64_t t = (uint64_t)lo + (uint64_t)lane * stride;
+        const bool le = t <= hi && foff[t] <= f;
+        const uint64_t b = __ballot(le);  // lane 0 (t = lo) is always set
+        const uint32_t k = 63 - __clzll(b);
+        lo += k * stride;
+        hi = (uint32_t)std::min<uint64_t>(hi, (uint64_t)lo + stride - 1);
+    }
+    const uint32_t t = lo + lane;
+    const uint64_t b = __ballot(t <= hi && foff[t] <= f);
+    return lo + (63 - __clzll(b));
+}
+
 __device__ __forceinline__ uint32_t find_t_lds(const uint64_t* __restrict__ fo, uint32_t nv, uint64_t f) {
     uint32_t lo = 0, hi = nv - 1;  // last k with fo[k] <= f
     while (lo < hi) {
@@ -229,12 +250,17 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const uint64_t f0 = blk * MB;
         __syncthreads();  // the previous range's users of the shared state are done
+        // the vertices owning the range's first and last element: waves 0 and 1
+        // search in parallel, 64 probes per round trip
+        if (wave < 2) {
+            const uint64_t f = wave == 0 ? f0 : std::min<uint64_t>(f0 + MB, F) - 1;
+            const uint32_t t = wave_find_t(foff, (uint32_t)T - 1, f);
+            if (lane == 0) range[wave] = t;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
-            const uint32_t tlo = find_t(foff, 0, (uint32_t)T - 1, f0);
-            const uint32_t thi = find_t(foff, tlo, (uint32_t)T - 1, std::min<uint64_t>(f0 + MB, F) - 1);
+            const uint32_t tlo = range[0], thi = range[1];
             const uint32_t rb = ts[tlo], re = te[thi];
-            range[0] = tlo;
-            range[1] = thi;
             range[2] = rb;
             range[3] = (thi - tlo < MV ? 1u : 0u) | (re - rb <= LDS_TARGETS ? 2u : 0u);
         }

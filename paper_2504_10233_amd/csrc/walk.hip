@@ -15,6 +15,10 @@ namespace {
 
 constexpr int TB = 256;
 constexpr uint64_t NO_WALK = ~0ull;
+// PPR visits are vertex ids in per-walk segments (the source is implied by the
+// segment); a walk stopped early by a vertex without out-edges pads the rest of
+// its segment with VPAD, which sorts after every vertex id.
+constexpr uint32_t VPAD = 0xFFFFFFFFu;
 
 constexpr uint32_t PENDING = 0xFFFFFFFEu;
 
@@ -350,34 +354,63 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
 // visit path, and the steps s < B_j skip the comparison (their word is known
 // to be >= thr).  A walk stopped early by a vertex without out-edges pads the
 // rest of its segment with a key that sorts after every real key.
+// Termination words come from one Philox block per (walk, step), and walk
+// lengths are geometric, so a lane that owned one walk would idle until the
+// longest walk of its wave ends (about 4x the mean for 64 lanes at p = 0.15).
+// Instead a wave owns BOUND_CHUNK consecutive walks and a lane whose walk ends
+// takes the wave's next one, so the wave stays busy until its chunk is drained.
+constexpr uint32_t BOUND_CHUNK = 1024;
+
 __global__ void __launch_bounds__(TB) k_ppr_bound(uint64_t nw, uint64_t base, uint64_t seed, uint32_t thr,
                                                   uint32_t cap, uint32_t* __restrict__ len) {
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nw; j += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t id = base + j;
-        uint32_t b = cap;
-        for (uint32_t s = 0; s < cap; ++s) {
-            uint32_t w0, w1, w2, w3;
-            philox_block((uint32_t)id, (uint32_t)(id >> 32), s, 0, (uint32_t)seed, (uint32_t)(seed >> 32), w0, w1, w2,
-                         w3);
-            if (w0 < thr) { b = s; break; }
+    const uint32_t lane = lane_id();
+    const uint64_t nchunks = (nw + BOUND_CHUNK - 1) / BOUND_CHUNK;
+    const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t c = wave0; c < nchunks; c += nwaves) {
+        const uint64_t c0 = c * BOUND_CHUNK;
+        const uint64_t c1 = std::min<uint64_t>(c0 + BOUND_CHUNK, nw);
+        uint64_t next = c0 + 64;  // identical in every lane
+        uint64_t j = c0 + lane;
+        uint32_t s = 0;
+        while (__ballot(j < c1)) {
+            bool fin = false;
+            if (j < c1) {
+                uint32_t w0, w1, w2, w3;
+                const uint64_t id = base + j;
+                philox_block((uint32_t)id, (uint32_t)(id >> 32), s, 0, (uint32_t)seed, (uint32_t)(seed >> 32), w0,
+                             w1, w2, w3);
+                if (w0 < thr || s + 1 >= cap) {
+                    // B_j = s when the word stops the walk at s, else the cap
+                    len[j] = (w0 < thr ? s : cap) + 1;
+                    fin = true;
+                } else {
+                    ++s;
+                }
+            }
+            const uint64_t b = __ballot(fin);
+            if (fin) {
+                j = next + __popcll(b & lanemask_lt());
+                s = 0;
+            }
+            next += __popcll(b);
         }
-        len[j] = b + 1;
     }
 }
 
 template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
-                                                       uint32_t R, uint64_t seed, uint64_t base, int vbits,
-                                                       uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                       uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
+                                                       const uint64_t* __restrict__ seg,
                                                        const uint32_t* __restrict__ len,
                                                        unsigned long long* __restrict__ ctl,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ err, uint32_t qchunk) {
+                                                       uint32_t* __restrict__ vis, uint32_t* __restrict__ err, uint32_t qchunk) {
     // ctl[0] queue head, ctl[1] transitions
     const uint64_t nw = (uint64_t)nsrc * R;
     WaveQueue wq;
     wq.chunk = qchunk;
-    uint64_t j = NO_WALK, pos = 0, lim = 0, q = 0, steps = 0;
+    uint64_t j = NO_WALK, pos = 0, lim = 0, steps = 0;
     uint32_t u = 0, s = 0;
     bool done = false;
     for (;;) {
@@ -388,17 +421,16 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
                 done = true;
             } else {
                 j = got;
-                q = j / R;
-                u = sources[q];
+                u = sources[j / R];
                 s = 0;
                 pos = seg[j];
                 lim = pos + len[j];
                 if (u >= n) {
                     atomicOr(err, ERR_RANGE);
-                    for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                    for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                     j = NO_WALK;
                 } else {
-                    keys[pos++] = (q << vbits) | u;
+                    vis[pos++] = u;
                     if (pos == lim) j = NO_WALK;
                 }
             }
@@ -410,10 +442,10 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
             rs_next32(rs);  // the termination word, known to be >= thr here
             const uint32_t v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
             if (v == STOP_VERTEX) {
-                for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                 j = NO_WALK;
             } else {
-                keys[pos++] = (q << vbits) | v;
+                vis[pos++] = v;
                 u = v;
                 ++s;
                 ++steps;
@@ -427,17 +459,17 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
 template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                         uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
-                                                        uint32_t R, uint64_t seed, uint64_t base, int vbits,
-                                                        uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                        uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
+                                                        const uint64_t* __restrict__ seg,
                                                         const uint32_t* __restrict__ len,
                                                         unsigned long long* __restrict__ ctl,
-                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ err, uint32_t qchunk) {
+                                                        uint32_t* __restrict__ vis, uint32_t* __restrict__ err, uint32_t qchunk) {
     const uint64_t nw = (uint64_t)nsrc * R;
     WaveQueue wq;
     wq.chunk = qchunk;
     StepState ss;
     ss.pending = false;
-    uint64_t j = NO_WALK, pos = 0, lim = 0, q = 0, steps = 0;
+    uint64_t j = NO_WALK, pos = 0, lim = 0, steps = 0;
     uint32_t u = 0, s = 0;
     bool done = false;
     for (;;) {
@@ -448,18 +480,17 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
                 done = true;
             } else {
                 j = got;
-                q = j / R;
-                u = sources[q];
+                u = sources[j / R];
                 s = 0;
                 pos = seg[j];
                 lim = pos + len[j];
                 ss.pending = false;
                 if (u >= n) {
                     atomicOr(err, ERR_RANGE);
-                    for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                    for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                     j = NO_WALK;
                 } else {
-                    keys[pos++] = (q << vbits) | u;
+                    vis[pos++] = u;
                     if (pos == lim) j = NO_WALK;
                 }
             }
@@ -474,10 +505,10 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
         if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
-                for (uint64_t x = pos; x < lim; ++x) keys[x] = pad;
+                for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                 j = NO_WALK;
             } else {
-                keys[pos++] = (q << vbits) | v;
+                vis[pos++] = v;
                 u = v;
                 ++s;
                 ++steps;
@@ -491,10 +522,10 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // Per-step PPR: active walks are (walk id, current vertex) pairs compacted into
 // the next list after every step; visits go to the same per-walk segments.
 __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
-                                                  uint32_t R, int vbits, uint64_t pad,
+                                                  uint32_t R,
                                                   const uint64_t* __restrict__ seg, const uint32_t* __restrict__ len,
                                                   uint64_t* __restrict__ act_id, uint32_t* __restrict__ act_v,
-                                                  unsigned long long* __restrict__ ctl, uint64_t* __restrict__ keys,
+                                                  unsigned long long* __restrict__ ctl, uint32_t* __restrict__ vis,
                                                   uint32_t* __restrict__ err) {
     // ctl[3] = size of active list A
     const uint64_t nw = (uint64_t)nsrc * R;
@@ -504,10 +535,10 @@ __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, con
         const uint64_t p = seg[j];
         if (u >= n) {
             atomicOr(err, ERR_RANGE);
-            for (uint64_t x = p; x < p + len[j]; ++x) keys[x] = pad;
+            for (uint64_t x = p; x < p + len[j]; ++x) vis[x] = VPAD;
             act_id[j] = NO_WALK;
         } else {
-            keys[p] = (q << vbits) | u;
+            vis[p] = u;
             act_id[j] = len[j] > 1 ? j : NO_WALK;
         }
         act_v[j] = u;
@@ -517,12 +548,12 @@ __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, con
 
 template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
-                                                 uint32_t R, uint32_t s, uint64_t seed, uint64_t base, int vbits,
-                                                 uint64_t pad, GroupRule rule, const uint64_t* __restrict__ seg,
+                                                 uint32_t R, uint32_t s, uint64_t seed, uint64_t base,
+                                                 GroupRule rule, const uint64_t* __restrict__ seg,
                                                  const uint32_t* __restrict__ len, const uint64_t* __restrict__ in_id,
                                                  const uint32_t* __restrict__ in_v, uint64_t* __restrict__ out_id,
                                                  uint32_t* __restrict__ out_v, unsigned long long* __restrict__ ctl,
-                                                 int in_slot, uint64_t* __restrict__ keys) {
+                                                 int in_slot, uint32_t* __restrict__ vis) {
     const uint64_t cnt = ctl[3 + in_slot];
     const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -543,9 +574,9 @@ __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hd
                 v = walk_step_body<SPEC>(hdr, pool, in_v[a], rs, rule);
                 const uint64_t p0 = seg[id], l = len[id];
                 if (v == STOP_VERTEX) {
-                    for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) keys[x] = pad;
+                    for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) vis[x] = VPAD;
                 } else {
-                    keys[p0 + 1 + s] = ((id / R) << vbits) | v;
+                    vis[p0 + 1 + s] = v;
                     ++steps;
                     alive = (uint64_t)s + 2 < l;
                 }
@@ -602,8 +633,9 @@ __global__ void k_counts(const uint64_t* __restrict__ hpos, uint64_t U, uint64_t
 // The visits of source q are the contiguous key range [seg[q R], seg[(q+1) R]).
 // One block of HSB threads per source sorts that range (bitonic network over
 // N = HSB * E slots, the vertex id only: the source is implied by the block),
-// run-length encodes it and writes (vertex << 32 | count) back over the start of
-// the same range; a compaction then builds the CSR.  Thread t holds slots
+// run-length encodes it and writes the vertices back over the start of the same
+// range and their counts to the same positions of a count array; a compaction
+// then builds the CSR.  Thread t holds slots
 // [t E, t E + E) in registers: partners closer than E slots are exchanged in
 // registers, partners in the same wave by lane shuffles, and only the stages
 // that cross waves go through LDS (6 of the 91 stages at N = 8192), so the
@@ -611,7 +643,6 @@ __global__ void k_counts(const uint64_t* __restrict__ hpos, uint64_t U, uint64_t
 // per query from the longest range; ranges above HCAP take the global sort.
 constexpr int HSB = 512;
 constexpr uint32_t HCAP = 16384;
-constexpr uint32_t VINVALID = 0xFFFFFFFFu;  // padding: sorts after every vertex id
 static_assert(HSB * 32 == HCAP, "the widest histogram instantiation covers HCAP");
 
 __device__ __forceinline__ void cmp_keep(uint32_t& a, uint32_t b, bool takemin) {
@@ -619,9 +650,9 @@ __device__ __forceinline__ void cmp_keep(uint32_t& a, uint32_t b, bool takemin) 
 }
 
 template <int E>
-__global__ void __launch_bounds__(HSB) k_hist_seg(uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
-                                                  uint32_t R, uint32_t nsrc, uint64_t total, uint64_t pad,
-                                                  uint64_t vmask, uint32_t* __restrict__ ucount,
+__global__ void __launch_bounds__(HSB) k_hist_seg(uint32_t* __restrict__ vis, uint32_t* __restrict__ hcnt,
+                                                  const uint64_t* __restrict__ seg, uint32_t R, uint32_t nsrc,
+                                                  uint64_t total, uint32_t* __restrict__ ucount,
                                                   unsigned long long* __restrict__ too_big) {
     constexpr uint32_t N = HSB * E;
     constexpr int NW = HSB / 64;
@@ -639,12 +670,7 @@ __global__ void __launch_bounds__(HSB) k_hist_seg(uint64_t* __restrict__ keys, c
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t i = t * E + e;
-        uint32_t v = VINVALID;
-        if (i < L) {
-            const uint64_t k = keys[S0 + i];
-            if (k != pad) v = (uint32_t)(k & vmask);
-        }
-        x[e] = v;
+        x[e] = i < L ? vis[S0 + i] : VPAD;
     }
     // bitonic network: stage (kk, j) orders slot i against i ^ j, ascending where i & kk == 0
 #pragma unroll
@@ -692,12 +718,12 @@ __global__ void __launch_bounds__(HSB) k_hist_seg(uint64_t* __restrict__ keys, c
     __syncthreads();  // the last cross-wave stage has read buf
     if (lane == 63) wred[0][wave] = x[E - 1];
     __syncthreads();
-    if (lane == 0) prev = wave ? wred[0][wave - 1] : VINVALID;
+    if (lane == 0) prev = wave ? wred[0][wave - 1] : VPAD;
     uint32_t hmask = 0, nh = 0, nvalid = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t pv = e ? x[e - 1] : prev;
-        const bool valid = x[e] != VINVALID;
+        const bool valid = x[e] != VPAD;
         const bool head = valid && (t * E + e == 0 || x[e] != pv);
         hmask |= (uint32_t)head << e;
         nh += head;
@@ -734,24 +760,43 @@ __global__ void __launch_bounds__(HSB) k_hist_seg(uint64_t* __restrict__ keys, c
     for (int e = 0; e < E; ++e) {
         if ((hmask >> e) & 1u) {
             const uint32_t next = r + 1 < U ? buf[r + 1] : V;
-            keys[S0 + r] = ((uint64_t)x[e] << 32) | (next - (t * E + e));
+            vis[S0 + r] = x[e];
+            hcnt[S0 + r] = next - (t * E + e);
             ++r;
         }
     }
     if (t == 0) ucount[q] = U;
 }
 
-__global__ void __launch_bounds__(256) k_hist_compact(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ seg,
-                                                      uint32_t R, const uint32_t* __restrict__ ucount,
+__global__ void __launch_bounds__(256) k_hist_compact(const uint32_t* __restrict__ vis,
+                                                      const uint32_t* __restrict__ hcnt,
+                                                      const uint64_t* __restrict__ seg, uint32_t R,
+                                                      const uint32_t* __restrict__ ucount,
                                                       const uint64_t* __restrict__ off, uint32_t* __restrict__ vtx,
                                                       uint32_t* __restrict__ cnt) {
     const uint32_t q = blockIdx.x;
     const uint64_t S0 = seg[(uint64_t)q * R], o = off[q];
     const uint32_t U = ucount[q];
     for (uint32_t k = threadIdx.x; k < U; k += 256) {
-        const uint64_t e = keys[S0 + k];
-        vtx[o + k] = (uint32_t)(e >> 32);
-        cnt[o + k] = (uint32_t)e;
+        vtx[o + k] = vis[S0 + k];
+        cnt[o + k] = hcnt[S0 + k];
+    }
+}
+
+// Global path: (source, vertex) keys from the visit segments; padding becomes
+// `pad`, above every key.  The source of position p is the last q whose first
+// walk's segment starts at or before p.
+__global__ void k_vis_keys(const uint32_t* __restrict__ vis, const uint64_t* __restrict__ seg, uint32_t R,
+                           uint32_t nsrc, uint64_t total, int vbits, uint64_t pad, uint64_t* __restrict__ keys) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = vis[p];
+        uint32_t lo = 0, hi = nsrc - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (seg[(uint64_t)mid * R] <= p) lo = mid; else hi = mid - 1;
+        }
+        keys[p] = v == VPAD ? pad : (((uint64_t)lo << vbits) | v);
     }
 }
 
@@ -839,20 +884,20 @@ void deepwalk_kernels(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint6
 
 template <int SPEC>
 void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t cap, uint64_t seed,
-                 uint64_t base, int vbits, uint64_t pad, const uint64_t* seg, const uint32_t* len, uint32_t mode,
-                 uint64_t* idA, uint32_t* vA, uint64_t* idB, uint32_t* vB, unsigned long long* ctl, uint64_t* keys,
+                 uint64_t base, const uint64_t* seg, const uint32_t* len, uint32_t mode,
+                 uint64_t* idA, uint32_t* vA, uint64_t* idB, uint32_t* vB, unsigned long long* ctl, uint32_t* vis,
                  hipStream_t st) {
     const uint64_t nw = (uint64_t)nsrc * R;
     if (mode == BINGO_WALK_PER_STEP) {
         const uint32_t grid = grid_for(nw);
-        hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, vbits, pad, seg, len, idA,
-                           vA, ctl, keys, g->d_err);
+        hipLaunchKernelGGL(k_ppr_start, dim3(grid), dim3(TB), 0, st, g->n, nsrc, sources, R, seg, len, idA, vA, ctl,
+                           vis, g->d_err);
         for (uint32_t s = 0; s < cap; ++s) {
             const int in_slot = s & 1;
             hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
-            hipLaunchKernelGGL((k_ppr_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base, vbits, pad,
+            hipLaunchKernelGGL((k_ppr_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base,
                                g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
-                               in_slot ? vA : vB, ctl, in_slot, keys);
+                               in_slot ? vA : vB, ctl, in_slot, vis);
         }
     } else {
         const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC> : (const void*)k_ppr_persistent<SPEC>;
@@ -860,10 +905,10 @@ void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
         if (g->walk_variant)
             hipLaunchKernelGGL((k_ppr_interleaved<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
-                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+                               seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
         else
             hipLaunchKernelGGL((k_ppr_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
-                               seed, base, vbits, pad, g->rule, seg, len, ctl, keys, g->d_err, g->queue_chunk);
+                               seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
     }
 }
 
@@ -919,7 +964,8 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     HIPCHK(hipMemsetAsync(ctl, 0, 40, st));
     HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
     phase_mark(g, st, true);
-    hipLaunchKernelGGL(k_ppr_bound, dim3(grid_for(nw)), dim3(TB), 0, st, nw, base, seed, thr, cap, len);
+    hipLaunchKernelGGL(k_ppr_bound, dim3((uint32_t)std::min<uint64_t>((nw + BOUND_CHUNK * 4 - 1) / (BOUND_CHUNK * 4), 8192)),
+                       dim3(TB), 0, st, nw, base, seed, thr, cap, len);
     scan_u32_to_u64(len, seg, nw, atmp, ctl + 2, st);
     hipLaunchKernelGGL(k_seg_maxlen, dim3((uint32_t)std::min<uint64_t>((nsrc + 255) / 256, 1024)), dim3(256), 0, st, seg,
                        R, nsrc, (const unsigned long long*)(ctl + 2), ctl + 3);
@@ -929,14 +975,24 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     const unsigned long long total = tm[0];
     const bool lds_hist = tm[1] <= HCAP;
     const uint64_t TT = std::max<uint64_t>(total, 1);
-    char* ws = (char*)ws_get(g, 2 * al(TT * 8) + al(TT * 4) + 2 * al(TT * 8) +
-                                    std::max(sort_temp_bytes(TT, true), scan_temp_bytes(TT)) + 1024);
+    // visits (u32 per position); then the LDS path's count array and per-source
+    // entry counts, or the global path's keys, sorted keys, heads and positions
+    const size_t part = lds_hist ? al(TT * 4) + al((uint64_t)nsrc * 4) : 4 * al(TT * 8) + al(TT * 4);
+    char* ws = (char*)ws_get(g, al(TT * 4) + part + std::max(sort_temp_bytes(TT, true), scan_temp_bytes(TT)) + 1024);
     if (!ws) return BINGO_E_OOM;
-    uint64_t* keys = (uint64_t*)ws;    ws += al(TT * 8);
-    uint64_t* sorted = (uint64_t*)ws;  ws += al(TT * 8);
-    uint32_t* head = (uint32_t*)ws;    ws += al(TT * 4);
-    uint64_t* idx = (uint64_t*)ws;     ws += al(TT * 8);
-    uint64_t* hpos = (uint64_t*)ws;    ws += al(TT * 8);
+    uint32_t* vis = (uint32_t*)ws;     ws += al(TT * 4);
+    uint32_t *hcnt = nullptr, *ucount = nullptr, *head = nullptr;
+    uint64_t *keys = nullptr, *sorted = nullptr, *idx = nullptr, *hpos = nullptr;
+    if (lds_hist) {
+        hcnt = (uint32_t*)ws;    ws += al(TT * 4);
+        ucount = (uint32_t*)ws;  ws += al((uint64_t)nsrc * 4);
+    } else {
+        keys = (uint64_t*)ws;    ws += al(TT * 8);
+        sorted = (uint64_t*)ws;  ws += al(TT * 8);
+        head = (uint32_t*)ws;    ws += al(TT * 4);
+        idx = (uint64_t*)ws;     ws += al(TT * 8);
+        hpos = (uint64_t*)ws;    ws += al(TT * 8);
+    }
     void* tmp = ws;
     phase_mark(g, st, false);
     uint64_t *idA = nullptr, *idB = nullptr;
@@ -948,9 +1004,9 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
     }
     switch (g->dense_spec) {
-        case 1: ppr_kernels<1>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
-        case 4: ppr_kernels<4>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
-        default: ppr_kernels<2>(g, nsrc, sources, R, cap, seed, base, vbits, pad, seg, len, mode, idA, vA, idB, vB, ctl, keys, st); break;
+        case 1: ppr_kernels<1>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+        case 4: ppr_kernels<4>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+        default: ppr_kernels<2>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
     }
     phase_mark(g, st, false);
     unsigned long long steps = 0;
@@ -969,13 +1025,11 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         }
     }
     if (lds_hist) {
-        // per-source histograms in LDS; ucount reuses the head array
-        uint32_t* ucount = head;
+        // per-source histograms, one block per source
         HIPCHK(hipMemsetAsync(ctl + 3, 0, 8, st));
-        const uint64_t vm = (1ull << vbits) - 1;
         const uint64_t ml = tm[1];
-#define BINGO_HIST(E_)                                                                                         \
-    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, st, keys, seg, R, nsrc, (uint64_t)total, pad, vm, \
+#define BINGO_HIST(E_)                                                                                     \
+    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, st, vis, hcnt, seg, R, nsrc, (uint64_t)total, \
                        ucount, ctl + 3)
         if (ml <= HSB * 1) BINGO_HIST(1);
         else if (ml <= HSB * 2) BINGO_HIST(2);
@@ -1001,7 +1055,7 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
             }
             hipLaunchKernelGGL(k_set_last_off, dim3(1), dim3(1), 0, st, g->ppr_off, nsrc,
                                (const unsigned long long*)(ctl + 2));
-            hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, st, keys, seg, R, ucount, g->ppr_off,
+            hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, st, vis, hcnt, seg, R, ucount, g->ppr_off,
                                g->ppr_vtx, g->ppr_cnt);
             phase_mark(g, st, false);
             HIPCHK(hipStreamSynchronize(st));
@@ -1014,6 +1068,8 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         return BINGO_E_HIP;  // unreachable: every range was checked against HCAP before the walk
     }
     // histogram: sort (source, vertex) keys (padding sorts last), then run-length encode
+    hipLaunchKernelGGL(k_vis_keys, dim3(grid_for(total)), dim3(TB), 0, st, vis, seg, R, nsrc, (uint64_t)total, vbits,
+                       pad, keys);
     sort_keys_u64(keys, sorted, total, vbits + qbits, tmp, st);
     hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(TB), 0, st, sorted, N, head);
     scan_u32_to_u64(head, idx, N, tmp, ctl + 2, st);
