@@ -70,6 +70,14 @@ def lib():
             L.o_deepwalk.argtypes = [C.c_void_p, C.c_uint64, u32p, C.c_uint64, C.c_uint32, C.c_uint64, u32p,
                                      C.c_int, u64p]
             L.o_deepwalk.restype = C.c_uint64
+            L.o_node2vec_thresholds.argtypes = [C.c_double, C.c_double, u64p]
+            L.o_node2vec_thresholds.restype = C.c_int
+            L.o_node2vec_step.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32,
+                                          u64p, u64p]
+            L.o_node2vec_step.restype = C.c_uint32
+            L.o_node2vec.argtypes = [C.c_void_p, C.c_uint64, u32p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_double,
+                                     C.c_double, u32p, C.c_int, u64p]
+            L.o_node2vec.restype = C.c_uint64
             L.o_ppr.argtypes = [C.c_void_p, C.c_uint32, u32p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
                                 C.c_uint64, C.c_int]
             L.o_ppr.restype = C.c_void_p
@@ -156,6 +164,14 @@ class OracleError(RuntimeError):
     pass
 
 
+
+def node2vec_thresholds(p, q):
+    """Acceptance thresholds (distance 0, 1, 2) of the node2vec rejection step; 2^32 = always."""
+    thr = np.zeros(3, np.uint64)
+    if lib().o_node2vec_thresholds(p, q, _p(thr, C.c_uint64)):
+        raise ValueError("p and q must be positive")
+    return thr
+
 class Graph:
     """The oracle's dynamic graph with its radix-group sampling structures."""
 
@@ -195,6 +211,22 @@ class Graph:
         if with_stats:
             return paths, int(steps), st[:6].copy()
         return paths, int(steps)
+
+    def node2vec(self, starts, length, seed, p, q, base=0, threads=1, with_proposals=False):
+        """Second-order walks (Sec. 2.2, Eq. node2vec) by rejection on the first-order sampler."""
+        s = _u32(starts)
+        paths = np.zeros((len(s), length + 1), np.uint32)
+        props = np.zeros(1, np.uint64)
+        steps = lib().o_node2vec(self.h, len(s), _p(s, C.c_uint32), base, length, seed, p, q,
+                                 _p(paths, C.c_uint32), threads, _p(props, C.c_uint64))
+        if with_proposals:
+            return paths, int(steps), int(props[0])
+        return paths, int(steps)
+
+    def node2vec_step(self, prev, u, seed, walk_id, step, p, q):
+        """One second-order transition from u after prev (prev = 0xFFFFFFFF: first step)."""
+        thr = node2vec_thresholds(p, q)
+        return int(lib().o_node2vec_step(self.h, prev, u, seed, walk_id, step, _p(thr, C.c_uint64), None))
 
     def ppr(self, sources, walks_per_source, thr, cap, seed, base=0, threads=1, with_stats=False):
         s = _u32(sources)

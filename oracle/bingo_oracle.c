@@ -19,6 +19,8 @@
  *   - the two-stage sampling step (Sec. 4.1, Eq. eq:group_prob and eq:pvp)
  *     with rejection on the adjacency for dense groups (Sec. 5.1);
  *   - DeepWalk and personalized-PageRank walks (Sec. 2.2 and Sec. 6.1);
+ *   - node2vec second-order walks by rejection on the first-order sampler
+ *     (Sec. 2.2, Eq. node2vec; the KnightKing approach the paper adopts);
  *   - the batched update workflow: per vertex insert, then delete, then
  *     rebuild, oldest duplicate deleted first, two-phase parallel
  *     delete-and-swap (Sec. 5.2, Fig. 10);
@@ -416,6 +418,106 @@ uint64_t o_deepwalk(const ograph *G, uint64_t nwalks, const uint32_t *starts, ui
         }
     }
     if (stats_out) for (int t = 0; t < 6; t++) stats_out[t] = agg[t];
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* node2vec (Sec. 2.2, Eq. node2vec): the walker at u that came from w moves */
+/* to neighbour v with probability proportional to w_uv * f(w, v), where     */
+/* f = 1/p if v = w, 1 if w has an edge to v, 1/q otherwise.  The paper       */
+/* samples it as KnightKing does (Sec. 8): propose v from the first-order     */
+/* sampler at u and accept it with probability f(w, v) / max(1/p, 1, 1/q).   */
+/* Readings fixed here:                                                       */
+/*  - "distance 1" means an edge w -> v in the current (directed) structure;  */
+/*  - the first transition of a walk has no previous vertex and is a plain    */
+/*    first-order step;                                                       */
+/*  - acceptance is an integer test: thr_c = 2^32 when f_c is the maximum     */
+/*    (accept without a draw), else floor(f_c / f_max * 2^32) computed in     */
+/*    IEEE double, and the proposal is accepted iff its acceptance word is    */
+/*    below thr_c;                                                            */
+/*  - proposal t of step s of walk id draws its first-order step from the     */
+/*    stream (seed, id, s) starting at block t * 2^16, and its acceptance     */
+/*    word is word 0 of block t * 2^16 + 0xFFFF; so proposal 0 uses exactly   */
+/*    the DeepWalk stream of the step, and p = q = 1 gives the DeepWalk path; */
+/*  - a step gives up after 2^15 proposals and the walk stops (unreachable    */
+/*    unless some thr_c is 0).                                                */
+/* ------------------------------------------------------------------------ */
+#define N2V_MAX_PROPOSALS (1u << 15)
+
+static void st_init_blk(ostream *s, uint64_t seed, uint64_t walk, uint32_t step, uint32_t blk0) {
+    st_init(s, seed, walk, step);
+    s->blk = blk0;
+}
+
+/* Edge w -> v present?  Plain scan of w's adjacency. */
+static int has_edge(const ograph *G, uint32_t w, uint32_t v) {
+    const ovtx *x = &G->v[w];
+    for (uint32_t i = 0; i < x->d; i++)
+        if (x->dst[i] == v) return 1;
+    return 0;
+}
+
+/* Acceptance thresholds for classes distance 0, 1, 2; 2^32 means always. */
+int o_node2vec_thresholds(double p, double q, uint64_t thr[3]) {
+    if (!(p > 0.0) || !(q > 0.0)) return -1;
+    const double f[3] = {1.0 / p, 1.0, 1.0 / q};
+    double fmax = f[0];
+    if (f[1] > fmax) fmax = f[1];
+    if (f[2] > fmax) fmax = f[2];
+    for (int c = 0; c < 3; c++) {
+        if (f[c] == fmax) thr[c] = 1ull << 32;
+        else {
+            double t = (f[c] / fmax) * 4294967296.0;
+            thr[c] = (uint64_t)t;  /* floor: t is positive and below 2^32 */
+        }
+    }
+    return 0;
+}
+
+uint32_t o_node2vec_step(const ograph *G, uint32_t prev, uint32_t u, uint64_t seed, uint64_t id, uint32_t s,
+                         const uint64_t thr[3], uint64_t *proposals) {
+    for (uint32_t t = 0; t < N2V_MAX_PROPOSALS; t++) {
+        ostream rs; st_init_blk(&rs, seed, id, s, t << 16);
+        uint32_t v = step_from(G, u, &rs, 0, 0, NULL);
+        if (proposals) (*proposals)++;
+        if (v == STOPV) return STOPV;
+        if (prev == STOPV) return v;
+        int c = v == prev ? 0 : (has_edge(G, prev, v) ? 1 : 2);
+        if (thr[c] >> 32) return v;
+        ostream as; st_init_blk(&as, seed, id, s, (t << 16) | 0xFFFFu);
+        if (st_next32(&as) < thr[c]) return v;
+    }
+    return STOPV;
+}
+
+/* Walk j has id base + j, starts at starts[j] and takes up to len transitions;
+ * paths as in o_deepwalk.  Returns the transitions taken; *proposals_out
+ * receives the number of proposals (first-order steps) drawn. */
+uint64_t o_node2vec(const ograph *G, uint64_t nwalks, const uint32_t *starts, uint64_t base, uint32_t len,
+                    uint64_t seed, double p, double q, uint32_t *paths, int nthreads, uint64_t *proposals_out) {
+    uint64_t thr[3];
+    if (o_node2vec_thresholds(p, q, thr)) return 0;
+    uint64_t total = 0, props = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total, props)
+#endif
+    for (int64_t j = 0; j < (int64_t)nwalks; j++) {
+        uint32_t *path = paths + (uint64_t)j * (len + 1);
+        uint32_t u = starts[j], prev = STOPV;
+        path[0] = u;
+        uint32_t s = 0;
+        for (; s < len; s++) {
+            uint32_t v = o_node2vec_step(G, prev, u, seed, base + (uint64_t)j, s, thr, &props);
+            if (v == STOPV) break;
+            path[s + 1] = v;
+            prev = u;
+            u = v;
+            total++;
+        }
+        for (; s < len; s++) path[s + 1] = STOPV;
+    }
+    if (proposals_out) *proposals_out = props;
     return total;
 }
 
