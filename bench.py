@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
     ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--node2vec-walks", type=int, default=1_000_000,
+                    help="node2vec walks (length 80, p = 0.5, q = 2) on the final graph; 0 skips")
     ap.add_argument("--no-random-probe", action="store_true",
                     help="skip the random-line read probe (context for the roofline)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -272,6 +274,27 @@ def main():
     g.ppr(sources, R, thr, cap, seed, base=last[0], mode=other)
     other_ms = g.last_phase_ms()[1]
 
+    # node2vec (second order, p = 0.5, q = 2, length 80) on the same final graph: the first call
+    # rebuilds the neighbour index, the second reuses it
+    n2v = None
+    if args.node2vec_walks:
+        n2v_starts = sources.repeat((args.node2vec_walks + args.sources - 1) // args.sources)[: args.node2vec_walks]
+        n2v_starts = n2v_starts.contiguous()
+        n2v_seed = synth.SEEDS["walks"] + 40 + c
+        g.node2vec(n2v_starts, 80, n2v_seed, 0.5, 2.0)
+        idx_ms = g.last_phase_ms()[0]
+        n2v_paths, n2v_counts = g.node2vec(n2v_starts, 80, n2v_seed, 0.5, 2.0)
+        ph = g.last_phase_ms()
+        n2v_steps, n2v_props = (int(x) for x in n2v_counts.tolist())
+        n2v = {"walks": args.node2vec_walks, "length": 80, "p": 0.5, "q": 2.0, "starts": "the PPR sources, repeated",
+               "index_rebuild_ms": idx_ms, "walk_kernel_ms": ph[1], "transitions": n2v_steps,
+               "proposals": n2v_props, "steps_per_s": n2v_steps / (ph[1] / 1e3),
+               "proposals_per_transition": n2v_props / max(n2v_steps, 1)}
+        n2v_check = (n2v_starts[:2000].cpu().numpy(), n2v_paths[:2000].cpu().numpy().view(np.uint32), n2v_seed)
+        del n2v_paths
+        log("node2vec: %d walks, %.2f ms kernel (%.3g steps/s, %.2f proposals per step), index rebuild %.2f ms" %
+            (args.node2vec_walks, ph[1], n2v["steps_per_s"], n2v["proposals_per_transition"], idx_ms))
+
     serving = None
     if args.serve_requests:
         serving = serve_phase(g, n, src, dst, args, log)
@@ -311,6 +334,7 @@ def main():
         "walk_form_compare": {"persistent_ms" if mode == MODE_PERSISTENT else "per_step_ms": walk_ms / len(timed),
                               "per_step_ms" if mode == MODE_PERSISTENT else "persistent_ms": other_ms},
         "p99_query_latency_ms": serving["query_p99_ms"] if serving else None,
+        "node2vec": n2v,
         "serving": serving,
         "tuning": g.get_tuning(),
         "autotune": tune,
@@ -346,6 +370,11 @@ def main():
                 and np.array_equal(cnt, ocnt) and steps == osteps)
         result["parity"] = {"last_step_ppr_histograms_equal": bool(same), "sources": args.sources,
                             "entries": int(len(ovtx)), "transitions": int(osteps)}
+        if n2v:
+            st0, gp, sd = n2v_check
+            op, _ = og.node2vec(st0, 80, sd, 0.5, 2.0, threads=th)
+            result["parity"]["node2vec_first_2000_walks_equal"] = bool(np.array_equal(gp, op))
+            log("oracle: node2vec parity on 2000 walks %s" % result["parity"]["node2vec_first_2000_walks_equal"])
         result["cpu_baseline"] = {"value": osteps / oracle_ppr_s, "unit": "walk-steps/s", "cores": th,
                                   "kind": "oracle",
                                   "sample": "the last step's full PPR query (%d sources x %d walks, %d transitions) "

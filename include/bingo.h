@@ -148,6 +148,32 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
                uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode, void* stream);
 
 /*
+ * bingo_node2vec -- second-order walks (Sec. 2.2, Eq. node2vec): from u, having
+ * come from w, the walk moves to v with probability proportional to
+ * w_uv * f(w, v), f = 1/p if v = w, 1 if the structure holds an edge w -> v,
+ * 1/q otherwise.  Sampled by rejection on the first-order step (the approach
+ * the paper adopts from KnightKing, Sec. 8): propose v as bingo_walk would,
+ * accept with probability f / max(1/p, 1, 1/q).  The first transition of a
+ * walk has no previous vertex and is first-order.
+ *   Random words: proposal t of step s of walk id draws its first-order step
+ *   from the Philox stream (seed, id, s) starting at block t * 2^16 (proposal
+ *   0 is the bingo_walk step) and its acceptance word is word 0 of block
+ *   t * 2^16 + 0xFFFF; it is accepted iff that word < floor(f / f_max * 2^32)
+ *   (computed in IEEE double), without a draw when f = f_max.  So p = q = 1
+ *   reproduces bingo_walk exactly.  A step stops the walk after 2^15
+ *   rejected proposals (only reachable when a threshold is 0).
+ *   d_starts, d_paths  as bingo_walk (paths n_walks * (length + 1)).
+ *   d_counts           optional device uint64[2]: transitions, proposals.
+ * The first call after the structure changed rebuilds the neighbour index
+ * (a sorted copy of every vertex's destinations, 4 bytes per edge, kept with
+ * the handle).  Asynchronous on the stream apart from that rebuild.
+ * BINGO_E_INVALID for p or q not positive and finite.
+ */
+int bingo_node2vec(bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
+                   uint32_t length, double p, double q, uint64_t seed, uint32_t* d_paths, uint64_t* d_counts,
+                   void* stream);
+
+/*
  * bingo_ppr -- personalized PageRank by Monte-Carlo visit counts (Sec. 1 and
  * Sec. 6.1).  Source index q runs walks_per_source walks with ids
  * walk_id_base + q * walks_per_source + r.  The start counts as a visit;
@@ -198,8 +224,9 @@ int bingo_status(bingo_graph* g, void* stream);
 
 /*
  * bingo_last_phase_ms -- device time of each phase of the last bingo_walk,
- * bingo_ppr or bingo_update_batch call on this handle, measured with HIP
- * events recorded on that call's stream.  bingo_walk: [walk kernel];
+ * bingo_ppr, bingo_node2vec or bingo_update_batch call on this handle,
+ * measured with HIP events recorded on that call's stream.  bingo_walk:
+ * [walk kernel]; bingo_node2vec: [neighbour index rebuild, walk kernel];
  * bingo_ppr: [walk-length bound pass and scan, walk kernel, visit histogram];
  * bingo_update_batch: [the device pipeline of the batch, from the sort of its
  * records to the last mutation kernel; the graph launch when one is used].  *h_n

@@ -54,7 +54,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
-           "bingo_probe_random_reads"]
+           "bingo_probe_random_reads", "bingo_node2vec"]
 
 
 class _ServerConfig(C.Structure):
@@ -89,6 +89,7 @@ def load():
         L.bingo_build.argtypes = [C.POINTER(_Config), u32, u64, vp, vp, vp, vp, C.POINTER(vp)]
         L.bingo_update_batch.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(_UpdateStats)]
         L.bingo_walk.argtypes = [vp, u64, vp, u64, u32, u64, vp, vp, u32, vp]
+        L.bingo_node2vec.argtypes = [vp, u64, vp, u64, u32, C.c_double, C.c_double, u64, vp, vp, vp]
         L.bingo_ppr.argtypes = [vp, u32, vp, u32, u32, u32, u64, u64, u32, C.POINTER(u64), C.POINTER(u64), vp]
         L.bingo_ppr_fetch.argtypes = [vp, vp, vp, vp, u64, vp]
         L.bingo_export.argtypes = [vp, vp, u64, C.POINTER(u64), vp]
@@ -195,6 +196,18 @@ class Graph:
                                _stream(stream))
         _check(rc, "bingo_walk")
         return paths, steps
+
+    def node2vec(self, starts, length, seed, p, q, base=0, stream=None, out=None):
+        """Second-order node2vec paths (n_walks, length + 1) as int32 bit patterns of uint32; returns
+        (paths, counts) with counts = int64 [transitions, proposals] on the device."""
+        st = as_u32(starts, self.device)
+        nw = st.numel()
+        paths = out if out is not None else torch.empty((nw, length + 1), dtype=torch.int32, device=self.device)
+        counts = torch.zeros(2, dtype=torch.int64, device=self.device)
+        rc = load().bingo_node2vec(self.h, nw, _ptr(st), base, length, float(p), float(q), seed, _ptr(paths),
+                                   _ptr(counts), _stream(stream))
+        _check(rc, "bingo_node2vec")
+        return paths, counts
 
     def ppr(self, sources, walks_per_source, thr, max_len, seed, base=0, mode=MODE_PERSISTENT, stream=None):
         """Per-source visit histograms: (offsets int64 [n_src+1], vertex int32, count int32, steps)."""

@@ -50,6 +50,8 @@ static void release(bingo_graph* g) {
     hipFree(g->ppr_cnt);
     hipFree(g->ws);
     hipFree(g->aux);
+    hipFree(g->n2v_idx);
+    hipFree(g->n2v_off);
     delete g;
 }
 
@@ -109,6 +111,14 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
     if (mode > BINGO_WALK_PER_STEP || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
     return launch_walk(const_cast<bingo_graph*>(g), n_walks, d_starts, walk_id_base, length, seed, d_paths,
                        d_steps_taken, mode, (hipStream_t)stream);
+}
+
+int bingo_node2vec(bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
+                   uint32_t length, double p, double q, uint64_t seed, uint32_t* d_paths, uint64_t* d_counts,
+                   void* stream) {
+    if (!g || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    return run_node2vec(g, n_walks, d_starts, walk_id_base, length, p, q, seed, d_paths, d_counts,
+                        (hipStream_t)stream);
 }
 
 int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources, uint32_t walks_per_source,

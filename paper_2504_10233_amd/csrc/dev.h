@@ -101,6 +101,12 @@ __device__ __forceinline__ void rs_init(RandStream& s, uint64_t seed, uint64_t w
     s.step = step; s.blk = 0; s.left = 0;
 }
 
+// The same stream starting at block blk0 (node2vec proposals use disjoint block ranges of a step's stream).
+__device__ __forceinline__ void rs_init_blk(RandStream& s, uint64_t seed, uint64_t walk, uint32_t step, uint32_t blk0) {
+    rs_init(s, seed, walk, step);
+    s.blk = blk0;
+}
+
 __device__ __forceinline__ uint32_t rs_next32(RandStream& s) {
     if (s.left == 0) {
         philox_block(s.w0, s.w1, s.step, s.blk, s.k0, s.k1, s.b0, s.b1, s.b2, s.b3);
@@ -191,13 +197,22 @@ struct bingo_graph {
     uint32_t update_graphs = 1;
     uint32_t dense_spec = 2;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
+    // structure version: bumped by every applied update batch
+    uint64_t version = 0;
+    // node2vec neighbour index: per-vertex sorted destinations (node2vec.hip)
+    uint32_t* n2v_idx = nullptr;
+    uint64_t* n2v_off = nullptr;
+    uint64_t n2v_cap = 0;
+    uint64_t n2v_version = ~0ull;
     // per-phase timing of the last walk / PPR / update call (events on its stream)
     hipEvent_t ev[PHASE_EVENTS] = {};
     uint32_t nev = 0;
 };
 void phase_mark(bingo_graph* g, hipStream_t st, bool first);
-// d_ctl layout (u64): [0] pool words used, [1] garbage words, [2..15] PPR and
-// update counters, [16 + 2*i .. 17 + 2*i] walk call slot i (WALK_SLOTS slots).
+// d_ctl layout (u64): [0] pool words used, [1] garbage words, [2..6] PPR
+// counters, [8..11] node2vec counters (CTL_N2V), [16 + 2*i .. 17 + 2*i] walk
+// call slot i (WALK_SLOTS slots).
+#define CTL_N2V 8
 #define CTL_WALK0 16
 #define WALK_SLOTS 64
 #define CTL_WORDS (CTL_WALK0 + 2 * WALK_SLOTS)
@@ -249,6 +264,8 @@ int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint
 int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
 // update.hip
 void update_release(bingo_graph* g);
+int run_node2vec(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t len, double p,
+                 double q, uint64_t seed, uint32_t* paths, uint64_t* d_counts, hipStream_t st);
 int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
                  uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats,
                  hipStream_t st);

@@ -1139,6 +1139,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
             h_stats->match_candidates = uc[UC_C];
             for (int i = 0; i < 25; ++i) h_stats->transitions[i] = uc[UC_STATS + 3 + i];
         }
+        ++g->version;
         return BINGO_OK;
     }
     return BINGO_E_CAPACITY;

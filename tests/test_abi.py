@@ -11,7 +11,7 @@ from conftest import ROOT
 def _declared():
     text = open(os.path.join(ROOT, "include", "bingo.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(bingo_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(bingo_[a-z0-9_]+)\s*\(", text)))
 
 
 def _lib_path():
