@@ -253,6 +253,11 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *                    step's random stream alone, so a round's loads are
  *                    independent; the first accepting attempt in stream order
  *                    wins, and results do not depend on this value.
+ *   ppr_bins         persistent bingo_ppr: 1 (default) appends each source's
+ *                    visits to a bin of fixed capacity (one atomic per source
+ *                    per wave iteration) and reruns the query with exact
+ *                    per-walk segments if a bin overflows; 0 always uses the
+ *                    segments (a length pass first).  Same results either way.
  */
 typedef struct {
     uint32_t struct_size;
@@ -261,6 +266,7 @@ typedef struct {
     uint32_t queue_chunk;
     uint32_t update_graphs;
     uint32_t dense_spec;
+    uint32_t ppr_bins;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

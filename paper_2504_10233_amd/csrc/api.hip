@@ -174,12 +174,14 @@ uint32_t bingo_num_vertices(const bingo_graph* g) { return g ? g->n : 0u; }
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     if (!g || !t || t->struct_size != sizeof(bingo_tuning)) return BINGO_E_INVALID;
-    if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1) return BINGO_E_INVALID;
+    if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1 || t->ppr_bins > 1)
+        return BINGO_E_INVALID;
     const uint32_t qc = t->queue_chunk ? t->queue_chunk : 256u;
     if (qc < 16 || qc > 4096 || (qc & (qc - 1))) return BINGO_E_INVALID;
     const uint32_t ds = t->dense_spec ? t->dense_spec : 2u;
     if (ds != 1 && ds != 2 && ds != 4) return BINGO_E_INVALID;
     g->dense_spec = ds;
+    g->ppr_bins = t->ppr_bins;
     g->walk_variant = t->walk_variant;
     g->blocks_per_cu = t->blocks_per_cu;
     g->queue_chunk = qc;
@@ -195,6 +197,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
     t->queue_chunk = g->queue_chunk;
     t->update_graphs = g->update_graphs;
     t->dense_spec = g->dense_spec;
+    t->ppr_bins = g->ppr_bins;
     return BINGO_OK;
 }
 

@@ -196,6 +196,8 @@ struct bingo_graph {
     // update pipeline: 1 = capture one hipGraph per batch-size bucket and replay it
     uint32_t update_graphs = 1;
     uint32_t dense_spec = 2;
+    // persistent PPR: 1 = visits appended to per-source bins (rerun with segments on overflow), 0 = segments
+    uint32_t ppr_bins = 1;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // structure version: bumped by every applied update batch
     uint64_t version = 0;

@@ -406,6 +406,102 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
     wave_add_u64(ctl + 1, steps);
 }
 
+// Binned PPR: the visits of source q go to bin q (capacity C, fill count
+// cnt[q]) in any order, since only their multiset matters.  The termination
+// word is tested in the walk itself (no length pass), and in every iteration
+// the lanes of a wave that produced a visit append it to their source's bin
+// with one atomic per source present in the wave; lanes of a wave hold
+// consecutive walk ids, so the appends of an iteration land as one or two
+// contiguous runs instead of one partial-sector store per lane.  A bin that
+// would overflow sets a flag and the query is rerun with exact per-walk
+// segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
+template <int SPEC>
+__global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                                   uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
+                                                   uint32_t R, uint64_t seed, uint64_t base, uint32_t thr,
+                                                   uint32_t cap, GroupRule rule, uint64_t C,
+                                                   uint32_t* __restrict__ cnt, uint32_t* __restrict__ vis,
+                                                   unsigned long long* __restrict__ ctl, uint32_t* __restrict__ err,
+                                                   uint32_t qchunk) {
+    const uint64_t nw = (uint64_t)nsrc * R;
+    const uint32_t lane = lane_id();
+    WaveQueue wq;
+    wq.chunk = qchunk;
+    StepState ss;
+    ss.pending = false;
+    uint64_t j = NO_WALK, steps = 0;
+    uint32_t u = 0, s = 0, q = 0;
+    bool done = false, ovf = false;
+    for (;;) {
+        const bool need = !done && j == NO_WALK;
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
+        bool emit = false;
+        uint32_t ev = 0;
+        if (need) {
+            if (got >= nw) {
+                done = true;
+            } else {
+                j = got;
+                q = (uint32_t)(j / R);
+                u = sources[q];
+                s = 0;
+                ss.pending = false;
+                if (u >= n) {
+                    atomicOr(err, ERR_RANGE);
+                    j = NO_WALK;
+                } else {
+                    emit = true;  // the start counts as a visit; the walk steps from the next iteration
+                    ev = u;
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        if (j != NO_WALK && !emit) {
+            uint32_t v = PENDING;
+            if (!ss.pending) {
+                // before every transition: the cap, then the termination word
+                if (s >= cap) {
+                    j = NO_WALK;
+                } else {
+                    rs_init(ss.rs, seed, base + j, s);
+                    if (rs_next32(ss.rs) < thr) j = NO_WALK;
+                    else v = step_begin(hdr, pool, u, ss, rule);
+                }
+            }
+            if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
+            if (j != NO_WALK && v != PENDING) {
+                if (v == STOP_VERTEX) {
+                    j = NO_WALK;
+                } else {
+                    emit = true;
+                    ev = v;
+                    u = v;
+                    ++s;
+                    ++steps;
+                }
+            }
+        }
+        // append this iteration's visits: one atomic per source present in the wave
+        uint64_t m = __ballot(emit);
+        while (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            const uint32_t qq = __shfl(q, leader, 64);
+            const uint64_t same = __ballot(emit && q == qq) & m;
+            uint32_t b = 0;
+            if ((int)lane == leader) b = atomicAdd(cnt + qq, (uint32_t)__popcll(same));
+            b = __shfl(b, leader, 64);
+            if ((same >> lane) & 1ull) {
+                const uint64_t pos = (uint64_t)b + __popcll(same & lanemask_lt());
+                if (pos < C) vis[(uint64_t)qq * C + pos] = ev;
+                else ovf = true;
+            }
+            m &= ~same;
+        }
+    }
+    wave_add_u64(ctl + 1, steps);
+    if (__ballot(ovf) && lane == 0) atomicOr(ctl + 2, 1ull);
+}
+
 // Per-step PPR: active walks are (walk id, current vertex) pairs compacted into
 // the next list after every step; visits go to the same per-walk segments.
 __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
@@ -539,15 +635,17 @@ __device__ __forceinline__ void cmp_keep(uint32_t& a, uint32_t b, bool takemin) 
 template <int E>
 __global__ void __launch_bounds__(HSB) k_hist_seg(uint32_t* __restrict__ vis, uint32_t* __restrict__ hcnt,
                                                   const uint64_t* __restrict__ seg, uint32_t R, uint32_t nsrc,
-                                                  uint64_t total, uint32_t* __restrict__ ucount,
+                                                  uint64_t total, uint64_t C, const uint32_t* __restrict__ bin_cnt,
+                                                  uint32_t* __restrict__ ucount,
                                                   unsigned long long* __restrict__ too_big) {
     constexpr uint32_t N = HSB * E;
     constexpr int NW = HSB / 64;
     __shared__ uint32_t buf[N];
     __shared__ uint32_t wred[2][NW];
     const uint32_t q = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    const uint64_t S0 = seg[(uint64_t)q * R];
-    const uint64_t S1 = (q + 1 < nsrc) ? seg[(uint64_t)(q + 1) * R] : total;
+    // the source's range: its bin, or the segments of its R walks
+    const uint64_t S0 = C ? (uint64_t)q * C : seg[(uint64_t)q * R];
+    const uint64_t S1 = C ? S0 + bin_cnt[q] : ((q + 1 < nsrc) ? seg[(uint64_t)(q + 1) * R] : total);
     if (S1 - S0 > N) {
         if (t == 0) { ucount[q] = 0; atomicOr(too_big, 1ull); }
         return;
@@ -657,12 +755,12 @@ __global__ void __launch_bounds__(HSB) k_hist_seg(uint32_t* __restrict__ vis, ui
 
 __global__ void __launch_bounds__(256) k_hist_compact(const uint32_t* __restrict__ vis,
                                                       const uint32_t* __restrict__ hcnt,
-                                                      const uint64_t* __restrict__ seg, uint32_t R,
+                                                      const uint64_t* __restrict__ seg, uint32_t R, uint64_t C,
                                                       const uint32_t* __restrict__ ucount,
                                                       const uint64_t* __restrict__ off, uint32_t* __restrict__ vtx,
                                                       uint32_t* __restrict__ cnt) {
     const uint32_t q = blockIdx.x;
-    const uint64_t S0 = seg[(uint64_t)q * R], o = off[q];
+    const uint64_t S0 = C ? (uint64_t)q * C : seg[(uint64_t)q * R], o = off[q];
     const uint32_t U = ucount[q];
     for (uint32_t k = threadIdx.x; k < U; k += 256) {
         vtx[o + k] = vis[S0 + k];
@@ -688,6 +786,23 @@ __global__ void k_vis_keys(const uint32_t* __restrict__ vis, const uint64_t* __r
 }
 
 __global__ void k_set_last_off(uint64_t* off, uint32_t nsrc, const unsigned long long* total) { off[nsrc] = *total; }
+
+// Largest bin fill, reduced per block then one atomic per block.
+__global__ void __launch_bounds__(256) k_bin_max(const uint32_t* __restrict__ cnt, uint32_t nsrc,
+                                                 unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long m[4];
+    unsigned long long best = 0;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nsrc; q += (uint64_t)gridDim.x * blockDim.x)
+        best = std::max<unsigned long long>(best, cnt[q]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = std::max<unsigned long long>(best, __shfl_xor(best, o));
+    if (lane_id() == 0) m[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) best = std::max<unsigned long long>(best, m[w]);
+        atomicMax(out, best);
+    }
+}
 
 // Largest per-source key range (visits plus padding), reduced per block then one atomic per block.
 __global__ void __launch_bounds__(256) k_seg_maxlen(const uint64_t* __restrict__ seg, uint32_t R, uint32_t nsrc,
@@ -822,8 +937,127 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
     return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
 }
 
+static int ensure_ppr_off(bingo_graph* g, uint32_t nsrc) {
+    if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
+        hipFree(g->ppr_off);
+        g->ppr_off_cap = nsrc + 1;
+        if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
+            g->ppr_off = nullptr; g->ppr_off_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    return BINGO_OK;
+}
+
+// Per-source histograms in one block per source (ranges of at most HCAP keys:
+// the sources' bins when C != 0, else their walks' segments), then the CSR.
+// Ends the histogram phase and synchronizes.
+static int finish_lds_hist(bingo_graph* g, uint32_t* vis, uint32_t* hcnt, uint32_t* ucount, const uint64_t* seg,
+                           uint32_t R, uint64_t C, const uint32_t* bin_cnt, uint32_t nsrc, uint64_t total,
+                           uint64_t maxlen, void* tmp, unsigned long long* ctl, uint64_t steps, uint64_t* h_entries,
+                           uint64_t* h_steps, hipStream_t st) {
+    const int rc = ensure_ppr_off(g, nsrc);
+    if (rc != BINGO_OK) return rc;
+    HIPCHK(hipMemsetAsync(ctl, 0, 8, st));
+#define BINGO_HIST(E_)                                                                                     \
+    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, st, vis, hcnt, seg, R, nsrc, total, C, bin_cnt, \
+                       ucount, ctl)
+    if (maxlen <= HSB * 1) BINGO_HIST(1);
+    else if (maxlen <= HSB * 2) BINGO_HIST(2);
+    else if (maxlen <= HSB * 4) BINGO_HIST(4);
+    else if (maxlen <= HSB * 8) BINGO_HIST(8);
+    else if (maxlen <= HSB * 16) BINGO_HIST(16);
+    else BINGO_HIST(32);
+#undef BINGO_HIST
+    scan_u32_to_u64(ucount, g->ppr_off, nsrc, tmp, ctl + 1, st);
+    unsigned long long hv[2];
+    HIPCHK(hipMemcpyAsync(hv, ctl, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hv[0]) return BINGO_E_HIP;  // unreachable: every range was checked against the width before
+    const uint64_t U = hv[1];
+    if (g->ppr_cap < U || !g->ppr_vtx) {
+        hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
+        g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
+        if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess || hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
+            g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    hipLaunchKernelGGL(k_set_last_off, dim3(1), dim3(1), 0, st, g->ppr_off, nsrc, (const unsigned long long*)(ctl + 1));
+    hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, st, vis, hcnt, seg, R, C, ucount, g->ppr_off,
+                       g->ppr_vtx, g->ppr_cnt);
+    phase_mark(g, st, false);
+    HIPCHK(hipStreamSynchronize(st));
+    g->ppr_entries = U;
+    g->ppr_nsrc = nsrc;
+    if (h_entries) *h_entries = U;
+    if (h_steps) *h_steps = steps;
+    return BINGO_OK;
+}
+
+constexpr int PPR_RETRY = 1;
+
+// Persistent PPR into per-source bins (k_ppr_binned).  Returns PPR_RETRY when a
+// bin overflowed or a source has more visits than the per-source histogram
+// holds; the caller then reruns the query with exact per-walk segments.
+static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr,
+                          uint32_t cap, uint64_t seed, uint64_t base, uint64_t* h_entries, uint64_t* h_steps,
+                          hipStream_t st) {
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    // bin capacity: 1.25 x the expected visits of R walks plus slack, at most the worst case R (cap + 1)
+    const double keep = 1.0 - (double)thr / 4294967296.0;
+    double mean = 1.0, term = 1.0;
+    for (uint32_t i = 0; i < cap && term > 1e-12; ++i) { term *= keep; mean += term; }
+    const uint64_t worst = (uint64_t)R * ((uint64_t)cap + 1);
+    const uint64_t C = std::min<uint64_t>(worst, (uint64_t)(1.25 * mean * R) + 1024);
+    const uint64_t cells = (uint64_t)nsrc * C;
+    char* ws = (char*)ws_get(g, 2 * al(cells * 4) + 2 * al((uint64_t)nsrc * 4) + scan_temp_bytes(nsrc) + 1024);
+    if (!ws) return BINGO_E_OOM;
+    uint32_t* vis = (uint32_t*)ws;      ws += al(cells * 4);
+    uint32_t* hcnt = (uint32_t*)ws;     ws += al(cells * 4);
+    uint32_t* bin_cnt = (uint32_t*)ws;  ws += al((uint64_t)nsrc * 4);
+    uint32_t* ucount = (uint32_t*)ws;   ws += al((uint64_t)nsrc * 4);
+    void* tmp = ws;
+    unsigned long long* ctl = g->d_ctl + 2;  // [0] queue, [1] transitions, [2] overflow, [3] largest bin
+    HIPCHK(hipMemsetAsync(ctl, 0, 32, st));
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    phase_mark(g, st, true);
+    HIPCHK(hipMemsetAsync(bin_cnt, 0, (uint64_t)nsrc * 4, st));
+    phase_mark(g, st, false);
+#define BINGO_BINNED(S_)                                                                                           \
+    do {                                                                                                           \
+        const int rg = resident_grid((const void*)k_ppr_binned<S_>, g->blocks_per_cu);                             \
+        const uint64_t nw = (uint64_t)nsrc * R;                                                                    \
+        const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1); \
+        hipLaunchKernelGGL((k_ppr_binned<S_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
+                           seed, base, thr, cap, g->rule, C, bin_cnt, vis, ctl, g->d_err, g->queue_chunk);          \
+    } while (0)
+    switch (g->dense_spec) {
+        case 1: BINGO_BINNED(1); break;
+        case 4: BINGO_BINNED(4); break;
+        default: BINGO_BINNED(2); break;
+    }
+#undef BINGO_BINNED
+    phase_mark(g, st, false);
+    hipLaunchKernelGGL(k_bin_max, dim3((uint32_t)std::min<uint64_t>((nsrc + 255) / 256, 1024)), dim3(256), 0, st,
+                       bin_cnt, nsrc, ctl + 3);
+    unsigned long long c4[4];
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(c4, ctl, 32, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (err) return err_to_code(err);
+    if (c4[2] || c4[3] > HCAP) return PPR_RETRY;
+    return finish_lds_hist(g, vis, hcnt, ucount, nullptr, R, C, bin_cnt, nsrc, cells, c4[3], tmp, ctl + 2, c4[1],
+                           h_entries, h_steps, st);
+}
+
 int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr, uint32_t cap,
             uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps, hipStream_t st) {
+    if (mode == BINGO_WALK_PERSISTENT && g->ppr_bins) {
+        const int rc = run_ppr_binned(g, nsrc, sources, R, thr, cap, seed, base, h_entries, h_steps, st);
+        if (rc != PPR_RETRY) return rc;
+    }
     const uint64_t nw = (uint64_t)nsrc * R;
     const int vbits = std::max(1, bits_for((uint64_t)g->n - 1));
     const int qbits = std::max(1, bits_for(nsrc));  // q < nsrc < 2^qbits
@@ -903,56 +1137,12 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     HIPCHK(hipStreamSynchronize(st));
     if (err) return err_to_code(err);
     const uint64_t N = nw + steps;  // visits: every start and every transition
-    if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
-        hipFree(g->ppr_off);
-        g->ppr_off_cap = nsrc + 1;
-        if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
-            g->ppr_off = nullptr; g->ppr_off_cap = 0;
-            return BINGO_E_OOM;
-        }
-    }
-    if (lds_hist) {
-        // per-source histograms, one block per source
-        HIPCHK(hipMemsetAsync(ctl + 3, 0, 8, st));
-        const uint64_t ml = tm[1];
-#define BINGO_HIST(E_)                                                                                     \
-    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, st, vis, hcnt, seg, R, nsrc, (uint64_t)total, \
-                       ucount, ctl + 3)
-        if (ml <= HSB * 1) BINGO_HIST(1);
-        else if (ml <= HSB * 2) BINGO_HIST(2);
-        else if (ml <= HSB * 4) BINGO_HIST(4);
-        else if (ml <= HSB * 8) BINGO_HIST(8);
-        else if (ml <= HSB * 16) BINGO_HIST(16);
-        else BINGO_HIST(32);
-#undef BINGO_HIST
-        scan_u32_to_u64(ucount, g->ppr_off, nsrc, tmp, ctl + 2, st);
-        unsigned long long hv[2];
-        HIPCHK(hipMemcpyAsync(hv, ctl + 2, 16, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (!hv[1]) {
-            const uint64_t U = hv[0];
-            if (g->ppr_cap < U || !g->ppr_vtx) {
-                hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
-                g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
-                if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess ||
-                    hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
-                    g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
-                    return BINGO_E_OOM;
-                }
-            }
-            hipLaunchKernelGGL(k_set_last_off, dim3(1), dim3(1), 0, st, g->ppr_off, nsrc,
-                               (const unsigned long long*)(ctl + 2));
-            hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, st, vis, hcnt, seg, R, ucount, g->ppr_off,
-                               g->ppr_vtx, g->ppr_cnt);
-            phase_mark(g, st, false);
-            HIPCHK(hipStreamSynchronize(st));
-            g->ppr_entries = U;
-            g->ppr_nsrc = nsrc;
-            if (h_entries) *h_entries = U;
-            if (h_steps) *h_steps = steps;
-            return BINGO_OK;
-        }
-        return BINGO_E_HIP;  // unreachable: every range was checked against HCAP before the walk
+    if (lds_hist)
+        return finish_lds_hist(g, vis, hcnt, ucount, seg, R, 0, nullptr, nsrc, total, tm[1], tmp, ctl + 3, steps,
+                               h_entries, h_steps, st);
+    {
+        const int rc = ensure_ppr_off(g, nsrc);
+        if (rc != BINGO_OK) return rc;
     }
     // histogram: sort (source, vertex) keys (padding sorts last), then run-length encode
     hipLaunchKernelGGL(k_vis_keys, dim3(grid_for(total)), dim3(TB), 0, st, vis, seg, R, nsrc, (uint64_t)total, vbits,
@@ -969,14 +1159,6 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess ||
             hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
             g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
-            return BINGO_E_OOM;
-        }
-    }
-    if (g->ppr_off_cap < nsrc + 1 || !g->ppr_off) {
-        hipFree(g->ppr_off);
-        g->ppr_off_cap = nsrc + 1;
-        if (hipMalloc(&g->ppr_off, (uint64_t)(nsrc + 1) * 8) != hipSuccess) {
-            g->ppr_off = nullptr; g->ppr_off_cap = 0;
             return BINGO_E_OOM;
         }
     }

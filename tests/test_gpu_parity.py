@@ -340,14 +340,15 @@ def test_generators_match_across_devices():
 
 
 # --------------------------------------------------------------------------- tuning invariance
-@pytest.mark.parametrize("variant,bpc,chunk,spec", [(0, 0, 256, 1), (1, 0, 256, 2), (1, 1, 16, 4), (0, 2, 4096, 4),
-                                                    (1, 3, 64, 1), (0, 0, 64, 2)])
-def test_results_independent_of_tuning(variant, bpc, chunk, spec):
+@pytest.mark.parametrize("variant,bpc,chunk,spec,bins", [(0, 0, 256, 1, 1), (1, 0, 256, 2, 0), (1, 1, 16, 4, 1),
+                                                         (0, 2, 4096, 4, 0), (1, 3, 64, 1, 1), (0, 0, 64, 2, 1)])
+def test_results_independent_of_tuning(variant, bpc, chunk, spec, bins):
     c = c1()
     og, gg = both(c["n"], c["src"], c["dst"], c["w"])
-    gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk, dense_spec=spec)
+    gg.set_tuning(walk_variant=variant, blocks_per_cu=bpc, queue_chunk=chunk, dense_spec=spec, ppr_bins=bins)
     t = gg.get_tuning()
-    assert (t["walk_variant"], t["blocks_per_cu"], t["queue_chunk"], t["dense_spec"]) == (variant, bpc, chunk, spec)
+    assert (t["walk_variant"], t["blocks_per_cu"], t["queue_chunk"], t["dense_spec"], t["ppr_bins"]) == \
+        (variant, bpc, chunk, spec, bins)
     opaths, osteps = og.deepwalk(c["starts"], c["length"], c["seed"])
     thr = int(0.15 * 2**32)
     sources = np.arange(0, 1000, 37)
@@ -364,7 +365,7 @@ def test_tuning_rejects_bad_values():
     c = c1()
     _, gg = both(c["n"], c["src"], c["dst"], c["w"])
     for kw in [dict(walk_variant=2), dict(queue_chunk=100), dict(queue_chunk=8), dict(blocks_per_cu=65),
-               dict(dense_spec=3), dict(dense_spec=8), dict(update_graphs=2)]:
+               dict(dense_spec=3), dict(dense_spec=8), dict(update_graphs=2), dict(ppr_bins=2)]:
         with pytest.raises(b.BingoError):
             gg.set_tuning(**kw)
 
@@ -383,11 +384,14 @@ def test_ppr_histogram_global_path():
 
 
 @pytest.mark.parametrize("R,cap", [(40, 9), (100, 9), (200, 9), (300, 12), (500, 15), (1000, 15), (1489, 10)])
-def test_ppr_histogram_widths(R, cap):
+@pytest.mark.parametrize("bins", [0, 1])
+def test_ppr_histogram_widths(R, cap, bins):
     """p = 0 fixes every per-source key range at R * (cap + 1), so these cases pick each register
-    width of the per-source sort (512 to 16384 slots, the last one exactly full); sinks pad ranges."""
+    width of the per-source sort (512 to 16384 slots, the last one exactly full), with visits in
+    per-source bins (exactly full at p = 0) or in per-walk segments; sinks pad segments."""
     c = c1()
     og, gg = both(c["n"], c["src"], c["dst"], c["w"])
+    gg.set_tuning(ppr_bins=bins)
     sources = np.array([0, 3, 4, 900, 17, 17])
     off, vtx, cnt, steps = gg.ppr(sources, R, 0, cap, seed=R, base=3)
     ooff, ovtx, ocnt, osteps = og.ppr(sources, R, 0, cap, seed=R, base=3)
