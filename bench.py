@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--mode", choices=["persistent", "per_step"], default="persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk[,dense_spec] (skips the autotuner)")
+    ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk[,dense_spec[,ppr_bins]] (skips the autotuner)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
     ap.add_argument("--oracle-threads", type=int, default=16)
@@ -227,7 +227,7 @@ def main():
     if args.tuning:
         t_ = [int(x) for x in args.tuning.split(",")]
         g.set_tuning(walk_variant=t_[0], blocks_per_cu=t_[1], queue_chunk=t_[2],
-                     dense_spec=t_[3] if len(t_) > 3 else None)
+                     dense_spec=t_[3] if len(t_) > 3 else None, ppr_bins=t_[4] if len(t_) > 4 else None)
     elif not args.no_autotune:
         from paper_2504_10233_amd.autotune import tune_ppr
         probe_src = sources[: max(1, args.sources // 10)]
