@@ -53,8 +53,6 @@ def parse():
     ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--node2vec-walks", type=int, default=1_000_000,
                     help="node2vec walks (length 80, p = 0.5, q = 2) on the final graph; 0 skips")
-    ap.add_argument("--contiguous", action="store_true",
-                    help="build the graph in physically contiguous device memory")
     ap.add_argument("--no-random-probe", action="store_true",
                     help="skip the random-line read probe (context for the roofline)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -190,7 +188,7 @@ def main():
 
     torch.cuda.synchronize()
     tb = time.time()
-    g = Graph(n, src, dst, w, device=dev, contiguous=args.contiguous)
+    g = Graph(n, src, dst, w, device=dev)
     torch.cuda.synchronize()
     build_s = time.time() - tb
     log("built in %.2fs" % build_s)
@@ -327,7 +325,7 @@ def main():
         "config": {"workload": "rmat%d-ef%d-uniform24-ppr-with-update-batches" % (scale, ef), "vertices": n,
                    "edges": m, "weights": "uniform[1,2^24)", "ppr_sources": args.sources, "walks_per_source": R,
                    "termination_prob": 0.15, "max_len": cap, "update_batch_records": args.batch,
-                   "walk_form": args.mode, "group_adaption": True, "contiguous_memory": bool(args.contiguous)},
+                   "walk_form": args.mode, "group_adaption": True},
         "walk_steps_per_s": tot_steps / (walk_ms / 1e3),
         "ppr_query_ms": ppr_ms / len(timed),
         "edge_updates_per_s": recs / (upd_ms / 1e3),

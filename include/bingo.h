@@ -59,10 +59,6 @@ typedef struct {
     uint32_t alpha_pct;     /* dense threshold alpha in percent (paper: 40) */
     uint32_t beta_pct;      /* sparse threshold beta in percent (paper: 10) */
     uint64_t pool_bytes;    /* device arena for adjacency and group lists; 0 = sized from the input */
-    uint32_t contiguous;    /* 1: request physically contiguous device memory for the header array
-                               and the pool (fewer address-translation misses on random access);
-                               falls back to ordinary device memory when the request fails */
-    uint32_t reserved;      /* 0 */
 } bingo_config;
 
 typedef struct {

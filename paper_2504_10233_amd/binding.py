@@ -32,8 +32,7 @@ class BingoError(RuntimeError):
 
 class _Config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("adaptive", C.c_uint32), ("alpha_pct", C.c_uint32),
-                ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64), ("contiguous", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64)]
 
 
 class _UpdateStats(C.Structure):
@@ -165,12 +164,11 @@ def _ptr(t):
 class Graph:
     """A dynamic graph with its radix-group sampling space resident in device memory."""
 
-    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None,
-                 contiguous=False):
+    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None):
         L = load()
         self.device = torch.device(device)
         s, d, ww = as_u32(src, self.device), as_u32(dst, self.device), as_u32(w, self.device)
-        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes, int(bool(contiguous)), 0)
+        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes)
         h = C.c_void_p()
         rc = L.bingo_build(C.byref(cfg), n, s.numel(), _ptr(s), _ptr(d), _ptr(ww), _stream(stream), C.byref(h))
         _check(rc, "bingo_build")

@@ -64,8 +64,7 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     if (!cfg || cfg->struct_size != sizeof(bingo_config)) return BINGO_E_INVALID;
     if (n == 0 || n >= (1u << 31) || m >= (1ull << 32)) return BINGO_E_INVALID;
     if (m && (!d_src || !d_dst || !d_w)) return BINGO_E_INVALID;
-    if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100 || cfg->contiguous > 1 || cfg->reserved)
-        return BINGO_E_INVALID;
+    if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100) return BINGO_E_INVALID;
     hipStream_t st = (hipStream_t)stream;
     bingo_graph* g = new (std::nothrow) bingo_graph();
     if (!g) return BINGO_E_OOM;
@@ -74,9 +73,8 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     g->rule.alpha = cfg->alpha_pct;
     g->rule.beta = cfg->beta_pct;
     g->pool_words = cfg->pool_bytes / 4;
-    g->contiguous = cfg->contiguous;
     g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr;
-    if (dev_alloc((void**)&g->hdr, (size_t)n * HDR_WORDS * 4, g->contiguous) != hipSuccess ||
+    if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
         hipMalloc(&g->d_ctl, CTL_WORDS * 8) != hipSuccess || hipMalloc(&g->d_err, 4) != hipSuccess) {
         release(g);
         return BINGO_E_OOM;

@@ -250,7 +250,7 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
     if (pool_words < used + 1024) return BINGO_E_OOM;
     if (pool_words > (1ull << 35)) pool_words = std::max<uint64_t>(1ull << 35, used + 1024);
     if (used + 1024 > (1ull << 35)) return BINGO_E_OOM;  // list offsets are 32-bit in 32-byte units
-    if (dev_alloc((void**)&g->pool, pool_words * 4, g->contiguous) != hipSuccess) {
+    if (hipMalloc(&g->pool, pool_words * 4) != hipSuccess) {
         g->pool = nullptr;
         return BINGO_E_OOM;
     }

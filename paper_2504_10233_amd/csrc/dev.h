@@ -198,8 +198,6 @@ struct bingo_graph {
     uint32_t dense_spec = 2;
     // persistent PPR: 1 = visits appended to per-source bins (rerun with segments on overflow), 0 = segments
     uint32_t ppr_bins = 1;
-    // header array and pool from physically contiguous memory (bingo_config.contiguous)
-    uint32_t contiguous = 0;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // structure version: bumped by every applied update batch
     uint64_t version = 0;
@@ -274,11 +272,5 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
                  uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats,
                  hipStream_t st);
 // api.hip
-void* ws_get(bingo_graph* g, size_t bytes);
-// Device allocation, physically contiguous when asked and available, else ordinary.
-inline hipError_t dev_alloc(void** p, size_t bytes, uint32_t contiguous) {
-    if (contiguous && hipExtMallocWithFlags(p, bytes, hipDeviceMallocContiguous) == hipSuccess) return hipSuccess;
-    (void)hipGetLastError();
-    return hipMalloc(p, bytes);
-}  // grow-only scratch (synchronizes when it grows)
+void* ws_get(bingo_graph* g, size_t bytes);  // grow-only scratch (synchronizes when it grows)
 int err_to_code(uint32_t bits);

@@ -94,19 +94,6 @@ def test_build_skew(adaptive):
     assert_same_structure(og, gg, "build skew")
 
 
-@pytest.mark.parametrize("adaptive", [True, False])
-def test_build_contiguous_memory(adaptive):
-    """The header array and pool in physically contiguous memory hold the same structure and walks."""
-    c = c1()
-    og = O.Graph(c["n"], c["src"], c["dst"], c["w"], adaptive=adaptive)
-    gg = B().Graph(c["n"], *(torch.from_numpy(np.asarray(x, np.int64)) for x in (c["src"], c["dst"], c["w"])),
-                   adaptive=adaptive, contiguous=True)
-    assert_same_structure(og, gg, "contiguous build")
-    paths, steps = gg.walk(c["starts"], c["length"], c["seed"])
-    opaths, osteps = og.deepwalk(c["starts"], c["length"], c["seed"])
-    assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps
-
-
 def test_build_degenerate():
     og, gg = both(1, [], [], [])
     assert_same_structure(og, gg, "empty graph")
