@@ -62,7 +62,7 @@ def parse():
 
 def walk_src_hash():
     h = hashlib.sha256()
-    for f in ("walk.hip", "dev.h"):
+    for f in ("walk.hip", "dev.h", "step.h"):
         h.update(open(os.path.join(ROOT, "paper_2504_10233_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
