@@ -415,6 +415,28 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // contiguous runs instead of one partial-sector store per lane.  A bin that
 // would overflow sets a flag and the query is rerun with exact per-walk
 // segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
+// Append one visit per flagged lane to its source's bin: one atomic per source
+// present among the flagged lanes (called by every lane of the wave).
+__device__ __forceinline__ void bin_append(bool emit, uint32_t q, uint32_t v, uint64_t C, uint32_t* __restrict__ cnt,
+                                           uint32_t* __restrict__ vis, bool& ovf) {
+    const uint32_t lane = lane_id();
+    uint64_t m = __ballot(emit);
+    while (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        const uint32_t qq = __shfl(q, leader, 64);
+        const uint64_t same = __ballot(emit && q == qq) & m;
+        uint32_t b = 0;
+        if ((int)lane == leader) b = atomicAdd(cnt + qq, (uint32_t)__popcll(same));
+        b = __shfl(b, leader, 64);
+        if ((same >> lane) & 1ull) {
+            const uint64_t pos = (uint64_t)b + __popcll(same & lanemask_lt());
+            if (pos < C) vis[(uint64_t)qq * C + pos] = v;
+            else ovf = true;
+        }
+        m &= ~same;
+    }
+}
+
 template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
@@ -435,8 +457,7 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
     for (;;) {
         const bool need = !done && j == NO_WALK;
         const uint64_t got = wave_take_chunked(need, wq, ctl);
-        bool emit = false;
-        uint32_t ev = 0;
+        bool started = false;
         if (need) {
             if (got >= nw) {
                 done = true;
@@ -450,13 +471,15 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                     atomicOr(err, ERR_RANGE);
                     j = NO_WALK;
                 } else {
-                    emit = true;  // the start counts as a visit; the walk steps from the next iteration
-                    ev = u;
+                    started = true;  // the start counts as a visit
                 }
             }
         }
         if (__ballot(!done) == 0) break;
-        if (j != NO_WALK && !emit) {
+        if (__ballot(started)) bin_append(started, q, u, C, cnt, vis, ovf);
+        bool emit = false;
+        uint32_t ev = 0;
+        if (j != NO_WALK) {
             uint32_t v = PENDING;
             if (!ss.pending) {
                 // before every transition: the cap, then the termination word
@@ -481,22 +504,7 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 }
             }
         }
-        // append this iteration's visits: one atomic per source present in the wave
-        uint64_t m = __ballot(emit);
-        while (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            const uint32_t qq = __shfl(q, leader, 64);
-            const uint64_t same = __ballot(emit && q == qq) & m;
-            uint32_t b = 0;
-            if ((int)lane == leader) b = atomicAdd(cnt + qq, (uint32_t)__popcll(same));
-            b = __shfl(b, leader, 64);
-            if ((same >> lane) & 1ull) {
-                const uint64_t pos = (uint64_t)b + __popcll(same & lanemask_lt());
-                if (pos < C) vis[(uint64_t)qq * C + pos] = ev;
-                else ovf = true;
-            }
-            m &= ~same;
-        }
+        bin_append(emit, q, ev, C, cnt, vis, ovf);
     }
     wave_add_u64(ctl + 1, steps);
     if (__ballot(ovf) && lane == 0) atomicOr(ctl + 2, 1ull);
