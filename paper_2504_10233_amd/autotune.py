@@ -11,8 +11,10 @@ from __future__ import annotations
 import json
 import os
 
-DEFAULT_SPACE = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=c, dense_spec=s)
-                 for v in (0, 1) for b in (0, 4, 2) for c in (64, 256) for s in (1, 2, 4)]
+# The binned PPR kernel has attempt-interleaved lanes whatever walk_variant says; variant 1 is also
+# the faster one for the segmented fallback, so the sweep keeps it fixed.
+DEFAULT_SPACE = [dict(walk_variant=1, blocks_per_cu=b, queue_chunk=c, dense_spec=s)
+                 for b in (0, 4, 2) for c in (64, 256, 1024) for s in (1, 2, 4)]
 
 
 def _cache_path():

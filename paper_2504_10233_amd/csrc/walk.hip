@@ -415,58 +415,39 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // contiguous runs instead of one partial-sector store per lane.  A bin that
 // would overflow sets a flag and the query is rerun with exact per-walk
 // segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
-// Bin appends without an atomic round trip per iteration: a wave reserves
-// RES_CHUNK consecutive slots of a source's bin with one atomic and hands
-// them out to its lanes' visits; it holds reservations for two sources at a
-// time (a wave's walk ids span at most a few sources).  A reservation given up
-// (a third source appears, or the wave ends) is filled with VPAD, which the
-// histogram skips.  Every lane of the wave calls these with the same state.
-constexpr uint32_t RES_CHUNK = 128;
-
-struct BinRes {
-    uint32_t q[2] = {~0u, ~0u};
-    uint64_t next[2] = {0, 0}, end[2] = {0, 0};
-    uint32_t lru = 0;  // slot to give up next
-};
-
-__device__ __forceinline__ void bin_pad(const BinRes& r, int k, uint64_t C, uint32_t* __restrict__ vis) {
-    if (r.q[k] == ~0u) return;
-    for (uint64_t p = r.next[k] + lane_id(); p < r.end[k]; p += 64)
-        if (p < C) vis[(uint64_t)r.q[k] * C + p] = VPAD;
-}
-
-__device__ __forceinline__ void bin_append(bool emit, uint32_t q, uint32_t v, uint64_t C, uint32_t* __restrict__ cnt,
-                                           uint32_t* __restrict__ vis, BinRes& r, bool& ovf) {
+// Append each lane's visits of this iteration (k = 0, 1 or 2: a walk's start
+// and its first step can land in the same iteration) to its source's bin: one
+// atomic per source present in the wave, positions from a prefix sum of k over
+// the wave.  Every lane of the wave calls it.
+__device__ __forceinline__ void bin_append(uint32_t k, uint32_t q, uint32_t v0, uint32_t v1, uint64_t C,
+                                           uint32_t* __restrict__ cnt, uint32_t* __restrict__ vis, bool& ovf) {
     const uint32_t lane = lane_id();
-    uint64_t m = __ballot(emit);
+    uint64_t m = __ballot(k != 0);
     while (m) {
         const int leader = __ffsll((long long)m) - 1;
         const uint32_t qq = __shfl(q, leader, 64);
-        const uint64_t same = __ballot(emit && q == qq) & m;
-        const uint32_t k = __popcll(same);
-        int slot = r.q[0] == qq ? 0 : (r.q[1] == qq ? 1 : -1);
-        if (slot < 0 || r.end[slot] - r.next[slot] < k) {
-            if (slot < 0) {
-                slot = (int)r.lru;
-                bin_pad(r, slot, C, vis);
+        const uint64_t same = __ballot(k != 0 && q == qq) & m;
+        const uint32_t mine = ((same >> lane) & 1ull) ? k : 0u;
+        uint32_t incl = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= (uint32_t)o) incl += y;
+        }
+        const uint32_t total = __shfl(incl, 63, 64);
+        uint32_t b = 0;
+        if ((int)lane == leader) b = atomicAdd(cnt + qq, total);
+        b = __shfl(b, leader, 64);
+        if (mine) {
+            const uint64_t pos = (uint64_t)b + (incl - mine);
+            const uint64_t row = (uint64_t)qq * C;
+            if (pos + mine <= C) {
+                vis[row + pos] = v0;
+                if (mine == 2) vis[row + pos + 1] = v1;
             } else {
-                bin_pad(r, slot, C, vis);
+                ovf = true;
             }
-            const uint32_t take = k > RES_CHUNK ? k : RES_CHUNK;
-            uint32_t b = 0;
-            if ((int)lane == leader) b = atomicAdd(cnt + qq, take);
-            b = __shfl(b, leader, 64);
-            r.q[slot] = qq;
-            r.next[slot] = b;
-            r.end[slot] = (uint64_t)b + take;
         }
-        r.lru = (uint32_t)(slot ^ 1);
-        if ((same >> lane) & 1ull) {
-            const uint64_t pos = r.next[slot] + __popcll(same & lanemask_lt());
-            if (pos < C) vis[(uint64_t)qq * C + pos] = v;
-            else ovf = true;
-        }
-        r.next[slot] += k;
         m &= ~same;
     }
 }
@@ -488,7 +469,6 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
     uint64_t j = NO_WALK, steps = 0;
     uint32_t u = 0, s = 0, q = 0;
     bool done = false, ovf = false;
-    BinRes res;
     for (;;) {
         const bool need = !done && j == NO_WALK;
         const uint64_t got = wave_take_chunked(need, wq, ctl);
@@ -511,7 +491,7 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
             }
         }
         if (__ballot(!done) == 0) break;
-        if (__ballot(started)) bin_append(started, q, u, C, cnt, vis, res, ovf);
+        const uint32_t start_v = u;
         bool emit = false;
         uint32_t ev = 0;
         if (j != NO_WALK) {
@@ -539,13 +519,10 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 }
             }
         }
-        bin_append(emit, q, ev, C, cnt, vis, res, ovf);
+        // this iteration's visits: the start of a walk taken this iteration, then its step
+        const uint32_t k = (started ? 1u : 0u) + (emit ? 1u : 0u);
+        bin_append(k, q, started ? start_v : ev, ev, C, cnt, vis, ovf);
     }
-    bin_pad(res, 0, C, vis);
-    bin_pad(res, 1, C, vis);
-    // a reservation that ran past the capacity is an overflow as well
-    for (int k = 0; k < 2; ++k)
-        if (res.q[k] != ~0u && res.end[k] > C) ovf = true;
     wave_add_u64(ctl + 1, steps);
     if (__ballot(ovf) && lane == 0) atomicOr(ctl + 2, 1ull);
 }
@@ -1057,10 +1034,7 @@ static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources
     double mean = 1.0, term = 1.0;
     for (uint32_t i = 0; i < cap && term > 1e-12; ++i) { term *= keep; mean += term; }
     const uint64_t worst = (uint64_t)R * ((uint64_t)cap + 1);
-    // plus the padding of the slot reservations: a source's walks span about R / queue_chunk + 2 waves,
-    // each of which may give up a partly used reservation of RES_CHUNK slots
-    const uint64_t pad_slack = ((uint64_t)R / g->queue_chunk + 3) * RES_CHUNK;
-    const uint64_t C = std::min<uint64_t>(worst + pad_slack, (uint64_t)(1.25 * mean * R) + 1024 + pad_slack);
+    const uint64_t C = std::min<uint64_t>(worst, (uint64_t)(1.25 * mean * R) + 1024);
     const uint64_t cells = (uint64_t)nsrc * C;
     char* ws = (char*)ws_get(g, 2 * al(cells * 4) + 2 * al((uint64_t)nsrc * 4) + scan_temp_bytes(nsrc) + 1024);
     if (!ws) return BINGO_E_OOM;
