@@ -241,34 +241,45 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
     __shared__ uint32_t range[4];  // tlo, thi, record base, staged flags
     __shared__ uint32_t wtot[TB / 64];
     __shared__ uint32_t ocount;
-    __shared__ unsigned long long obase;
+    __shared__ uint32_t reuse;
+    __shared__ unsigned long long obase, vend;
     const uint64_t F = uc[UC_F], T = uc[UC_T];
     const uint64_t nblk = (F + MB - 1) / MB;
     constexpr int PER = MB / TB;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) ocount = 0;
-    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    if (threadIdx.x == 0) { ocount = 0; vend = 0; range[0] = 1; range[1] = 0; }
+    // each block takes a contiguous run of ranges, so consecutive ranges of
+    // one large vertex reuse its staged header fields and targets
+    const uint64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+    const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = std::min<uint64_t>(nblk, b0 + per);
+    for (uint64_t blk = b0; blk < b1; ++blk) {
         const uint64_t f0 = blk * MB;
+        const uint64_t fl = std::min<uint64_t>(f0 + MB, F) - 1;
         __syncthreads();  // the previous range's users of the shared state are done
-        // the vertices owning the range's first and last element: waves 0 and 1
-        // search in parallel, 64 probes per round trip
-        if (wave < 2) {
-            const uint64_t f = wave == 0 ? f0 : std::min<uint64_t>(f0 + MB, F) - 1;
-            const uint32_t t = wave_find_t(foff, (uint32_t)T - 1, f);
-            if (lane == 0) range[wave] = t;
-        }
+        if (threadIdx.x == 0)
+            reuse = (range[0] == range[1] && (range[3] & 3u) == 3u && fl < vend) ? 1u : 0u;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t tlo = range[0], thi = range[1];
-            const uint32_t rb = ts[tlo], re = te[thi];
-            range[2] = rb;
-            range[3] = (thi - tlo < MV ? 1u : 0u) | (re - rb <= LDS_TARGETS ? 2u : 0u);
+        if (!reuse) {
+            // the vertices owning the range's first and last element: waves 0
+            // and 1 search in parallel, 64 probes per round trip
+            if (wave < 2) {
+                const uint32_t t = wave_find_t(foff, (uint32_t)T - 1, wave == 0 ? f0 : fl);
+                if (lane == 0) range[wave] = t;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t tlo = range[0], thi = range[1];
+                const uint32_t rb = ts[tlo], re = te[thi];
+                range[2] = rb;
+                range[3] = (thi - tlo < MV ? 1u : 0u) | (re - rb <= LDS_TARGETS ? 2u : 0u);
+                vend = thi + 1 < T ? foff[thi + 1] : F;  // end of the last vertex's elements
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const uint32_t tlo = range[0], thi = range[1], rbase = range[2];
         const bool vstaged = range[3] & 1u, tstaged = (range[3] & 2u) != 0;
         const uint32_t nv = thi - tlo + 1;
-        if (vstaged) {
+        if (vstaged && !reuse) {
             for (uint32_t k = threadIdx.x; k < nv; k += TB) {
                 const uint32_t t = tlo + k;
                 const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
@@ -278,7 +289,7 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                 s_v[5][k] = ts[t]; s_v[6][k] = tdl[t]; s_v[7][k] = te[t];
             }
         }
-        if (tstaged) {
+        if (tstaged && !reuse) {
             const uint32_t re = te[thi];
             for (uint32_t p = rbase + threadIdx.x; p < re; p += TB) tgt[p - rbase] = key_dst(sk[p], vb);
         }
@@ -568,19 +579,21 @@ __global__ void __launch_bounds__(WB) k_analyze(const unsigned long long* __rest
     }
 }
 
-// Sum per-block partials: out[i] = sum_b partials[b * 32 + i], i < 32.
-__global__ void k_stats_reduce(const unsigned long long* __restrict__ partials, uint32_t nblocks,
-                               unsigned long long* __restrict__ out, int accumulate) {
-    __shared__ unsigned long long red[8][32];
-    const uint32_t i = threadIdx.x & 31, r = threadIdx.x >> 5;  // 256 threads: 8 rows x 32 counters
+// Sum per-block partials: out[i] = sum_b partials[b * 32 + i]; block i sums counter i.
+__global__ void __launch_bounds__(256) k_stats_reduce(const unsigned long long* __restrict__ partials,
+                                                      uint32_t nblocks, unsigned long long* __restrict__ out,
+                                                      int accumulate) {
+    __shared__ unsigned long long red[4];
+    const uint32_t i = blockIdx.x;
     unsigned long long v = 0;
-    for (uint32_t b = r; b < nblocks; b += 8) v += partials[(uint64_t)b * 32 + i];
-    red[r][i] = v;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += 256) v += partials[(uint64_t)b * 32 + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x < 32) {
-        unsigned long long sum = 0;
-        for (int k = 0; k < 8; ++k) sum += red[k][threadIdx.x];
-        if (accumulate) out[threadIdx.x] += sum; else out[threadIdx.x] = sum;
+    if (threadIdx.x == 0) {
+        const unsigned long long sum = red[0] + red[1] + red[2] + red[3];
+        if (accumulate) out[i] += sum; else out[i] = sum;
     }
 }
 
@@ -1024,7 +1037,7 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R)), dim3(TB), 0, st, p->needw, R, 0ull);
     hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, p->tv, p->tsa, p->tdl,
                        p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->iw, g->rule, p->needw, p->parts);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
                        uc + UC_STATS, 0);
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
@@ -1032,7 +1045,7 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, (const uint32_t*)err,
                        p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
                        g->rule, p->aoff, p->sur, p->parts);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
                        uc + UC_FREED, 0);
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
 }

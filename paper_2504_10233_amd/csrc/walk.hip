@@ -415,43 +415,6 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // contiguous runs instead of one partial-sector store per lane.  A bin that
 // would overflow sets a flag and the query is rerun with exact per-walk
 // segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
-// Append each lane's visits of this iteration (k = 0, 1 or 2: a walk's start
-// and its first step can land in the same iteration) to its source's bin: one
-// atomic per source present in the wave, positions from a prefix sum of k over
-// the wave.  Every lane of the wave calls it.
-__device__ __forceinline__ void bin_append(uint32_t k, uint32_t q, uint32_t v0, uint32_t v1, uint64_t C,
-                                           uint32_t* __restrict__ cnt, uint32_t* __restrict__ vis, bool& ovf) {
-    const uint32_t lane = lane_id();
-    uint64_t m = __ballot(k != 0);
-    while (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        const uint32_t qq = __shfl(q, leader, 64);
-        const uint64_t same = __ballot(k != 0 && q == qq) & m;
-        const uint32_t mine = ((same >> lane) & 1ull) ? k : 0u;
-        uint32_t incl = mine;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, 64);
-            if (lane >= (uint32_t)o) incl += y;
-        }
-        const uint32_t total = __shfl(incl, 63, 64);
-        uint32_t b = 0;
-        if ((int)lane == leader) b = atomicAdd(cnt + qq, total);
-        b = __shfl(b, leader, 64);
-        if (mine) {
-            const uint64_t pos = (uint64_t)b + (incl - mine);
-            const uint64_t row = (uint64_t)qq * C;
-            if (pos + mine <= C) {
-                vis[row + pos] = v0;
-                if (mine == 2) vis[row + pos + 1] = v1;
-            } else {
-                ovf = true;
-            }
-        }
-        m &= ~same;
-    }
-}
-
 template <int SPEC>
 __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
@@ -472,7 +435,8 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
     for (;;) {
         const bool need = !done && j == NO_WALK;
         const uint64_t got = wave_take_chunked(need, wq, ctl);
-        bool started = false;
+        bool emit = false;
+        uint32_t ev = 0;
         if (need) {
             if (got >= nw) {
                 done = true;
@@ -486,15 +450,13 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                     atomicOr(err, ERR_RANGE);
                     j = NO_WALK;
                 } else {
-                    started = true;  // the start counts as a visit
+                    emit = true;  // the start counts as a visit; the walk steps from the next iteration
+                    ev = u;
                 }
             }
         }
         if (__ballot(!done) == 0) break;
-        const uint32_t start_v = u;
-        bool emit = false;
-        uint32_t ev = 0;
-        if (j != NO_WALK) {
+        if (j != NO_WALK && !emit) {
             uint32_t v = PENDING;
             if (!ss.pending) {
                 // before every transition: the cap, then the termination word
@@ -519,9 +481,22 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 }
             }
         }
-        // this iteration's visits: the start of a walk taken this iteration, then its step
-        const uint32_t k = (started ? 1u : 0u) + (emit ? 1u : 0u);
-        bin_append(k, q, started ? start_v : ev, ev, C, cnt, vis, ovf);
+        // append this iteration's visits: one atomic per source present in the wave
+        uint64_t m = __ballot(emit);
+        while (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            const uint32_t qq = __shfl(q, leader, 64);
+            const uint64_t same = __ballot(emit && q == qq) & m;
+            uint32_t b = 0;
+            if ((int)lane == leader) b = atomicAdd(cnt + qq, (uint32_t)__popcll(same));
+            b = __shfl(b, leader, 64);
+            if ((same >> lane) & 1ull) {
+                const uint64_t pos = (uint64_t)b + __popcll(same & lanemask_lt());
+                if (pos < C) vis[(uint64_t)qq * C + pos] = ev;
+                else ovf = true;
+            }
+            m &= ~same;
+        }
     }
     wave_add_u64(ctl + 1, steps);
     if (__ballot(ovf) && lane == 0) atomicOr(ctl + 2, 1ull);
