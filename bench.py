@@ -37,6 +37,11 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["ppr", "deepwalk", "skewed-updates", "serving"], default="ppr",
+                    help="ppr (default): R-MAT 24 PPR with 10^6-record batches; deepwalk: R-MAT 22 Zipf DeepWalk "
+                         "with 2x10^6-record batches; skewed-updates: R-MAT 24 + planted hubs, batches 10^2..10^7; "
+                         "serving: R-MAT 25 request stream at 50/80/95 %% of saturation")
+    ap.add_argument("--serve-count", type=int, default=10_000, help="requests per load level (serving workload)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=24)
@@ -72,59 +77,10 @@ def serve_phase(g, n, src, dst, args, log):
     4 walk queries per update batch; query start sets log-uniform in [1, 10^4] walks with length
     uniform in 5..80, update batches log-uniform in [1, 10^4] records (half inserts with uniform
     weights, half deletions of input edges).  Latency is submission to result ready."""
-    import threading
     import numpy as np
-    from paper_2504_10233_amd import Server
     rng = np.random.default_rng(5005)
-    m = src.numel()
-    reqs = []
-    for i in range(args.serve_requests):
-        if rng.random() < 0.2:
-            k = int(10 ** rng.uniform(0, 4))
-            ki = k // 2
-            pos = rng.integers(0, m, k - ki)
-            reqs.append(("update", rng.integers(0, n, ki), rng.integers(0, n, ki), rng.integers(1, 1 << 24, ki),
-                         src[torch_index(pos)].cpu().numpy(), dst[torch_index(pos)].cpu().numpy()))
-        else:
-            nw = int(10 ** rng.uniform(0, 4))
-            reqs.append(("walk", rng.integers(0, n, nw), int(rng.integers(5, 81)), int(rng.integers(1 << 62)),
-                         i << 24))
-    gaps = rng.exponential(1.0 / args.serve_rate, len(reqs))
-    srv = Server(g, max_inflight=8)
-    tickets = [None] * len(reqs)
-    infos = [None] * len(reqs)
-    ready = threading.Semaphore(0)
-
-    def waiter():
-        for i in range(len(reqs)):
-            ready.acquire()
-            _, infos[i] = srv.wait(tickets[i])
-
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.perf_counter()
-    due = t0
-    for i, r in enumerate(reqs):
-        due += gaps[i]
-        while time.perf_counter() < due:
-            pass
-        if r[0] == "walk":
-            tickets[i] = srv.submit_walk(r[1], r[2], r[3], r[4])
-        else:
-            tickets[i] = srv.submit_update(*r[1:])
-        ready.release()
-    th.join()
-    makespan = time.perf_counter() - t0
-    srv.close()
-    q = np.array([x["latency_us"] for x in infos if x["kind"] == 0]) / 1e3
-    u = np.array([x["latency_us"] for x in infos if x["kind"] == 1]) / 1e3
-    steps = sum(x["steps"] for x in infos if x["kind"] == 0)
-    res = {"requests": len(reqs), "offered_rate_per_s": args.serve_rate, "max_inflight": 8,
-           "query_p50_ms": float(np.percentile(q, 50)), "query_p99_ms": float(np.percentile(q, 99)),
-           "update_p50_ms": float(np.percentile(u, 50)) if u.size else None,
-           "update_p99_ms": float(np.percentile(u, 99)) if u.size else None,
-           "sustained_walk_steps_per_s": steps / makespan, "makespan_s": makespan,
-           "errors": int(sum(1 for x in infos if x["status"] != 0))}
+    reqs = make_requests(rng, args.serve_requests, n, src, dst, 4, 4, 1 << 24)
+    res = serve_requests(g, reqs, args.serve_rate)
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
     return res
@@ -163,6 +119,278 @@ def torch_index(pos):
     return torch.from_numpy(pos).to("cuda:0")
 
 
+def common_fields(args, metric_value, unit, ms_per_step, config, dtype="u32"):
+    return {"metric": METRIC, "value": metric_value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def workload_deepwalk(args):
+    """R-MAT 22 (4,194,304 vertices, 67,108,864 edges), Zipf(1.5) weights clipped at 2^20 - 1; one DeepWalk
+    walk of length 80 per vertex; per step one batch of 10^6 inserts + 10^6 deletions, then the walks again."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph
+    dev = torch.device("cuda:0")
+    scale, ef, c = 22, 16, 2
+    n, m = 1 << scale, ef << scale
+    src, dst = synth.rmat_graph(scale, m, synth.SEEDS["graph"] + c, device=dev)
+    w = synth.weights_zipf(m, 1.5, (1 << 20) - 1, synth.SEEDS["weights"] + c, device=dev)
+    torch.cuda.synchronize()
+    tb = time.time()
+    g = Graph(n, src, dst, w, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.time() - tb
+    nb = args.warmup + args.steps
+    mirror = synth.EdgeMirror(src, dst)
+    batches = []
+    for b in range(nb):
+        bseed = synth.SEEDS["batch"] + 100 * c + b
+        isrc, idst = synth.rmat_graph(scale, 1_000_000, bseed, device=dev)
+        iw = synth.weights_zipf(1_000_000, 1.5, (1 << 20) - 1, bseed, device=dev, stream=7)
+        pos = mirror.pick_deletions(1_000_000, bseed, 30)
+        dsrc, ddst = mirror.src[pos], mirror.dst[pos]
+        mirror.apply(isrc, idst, pos)
+        batches.append(tuple(x.to(torch.int32).contiguous() for x in (isrc, idst, iw, dsrc, ddst)))
+    del mirror
+    starts = torch.arange(n, dtype=torch.int32, device=dev)
+    paths = torch.empty((n, 81), dtype=torch.int32, device=dev)
+    rows = []
+    stream = torch.cuda.current_stream()
+    for i in range(nb):
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        st = g.update(*batches[i])
+        e1.record(stream)
+        _, steps = g.walk(starts, 80, synth.SEEDS["walks"] + c + 10 * i, base=0, out=paths)
+        wk = None
+        e2.record(stream)
+        torch.cuda.synchronize()
+        wk = g.last_phase_ms()[0]
+        rows.append({"update_ms": e0.elapsed_time(e1), "walk_ms": e1.elapsed_time(e2), "walk_kernel_ms": wk,
+                     "steps": int(steps.item()), "records": st["inserted"] + st["deleted"] + st["not_found"]})
+        log("deepwalk step %d: update %.2f ms, walks %.2f ms (kernel %.2f), %d transitions" %
+            (i, rows[-1]["update_ms"], rows[-1]["walk_ms"], wk, rows[-1]["steps"]))
+    timed = rows[args.warmup:]
+    tot_ms = sum(r["update_ms"] + r["walk_ms"] for r in timed)
+    tot_steps = sum(r["steps"] for r in timed)
+    res = common_fields(args, tot_steps / (tot_ms / 1e3), "walk-steps/s", tot_ms / len(timed),
+                        {"workload": "rmat22-ef16-zipf1.5-deepwalk80-per-vertex-with-2e6-record-batches",
+                         "vertices": n, "edges": m, "walks": n, "length": 80, "update_batch_records": 2_000_000})
+    res.update({"walk_steps_per_s": tot_steps / (sum(r["walk_kernel_ms"] for r in timed) / 1e3),
+                "edge_updates_per_s": sum(r["records"] for r in timed) / (sum(r["update_ms"] for r in timed) / 1e3),
+                "build_s": build_s, "steps_detail": rows})
+    # sampled parity against the oracle after the same batches
+    if not args.no_cpu_baseline:
+        import oracle as O
+        th = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+        og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
+        for bt in batches:
+            og.update(*[x.cpu().numpy().view(np.uint32) for x in bt])
+        sample = np.arange(0, n, 97, dtype=np.int64)[:20000]
+        t = time.time()
+        op, osteps = og.deepwalk(sample, 80, synth.SEEDS["walks"] + c + 10 * (nb - 1), threads=th)
+        cpu_s = time.time() - t
+        gp = paths.cpu().numpy().view(np.uint32)[sample]
+        res["parity"] = {"sampled_walks_equal": bool(np.array_equal(gp, op)), "walks": int(len(sample))}
+        res["cpu_baseline"] = {"value": osteps / cpu_s, "unit": "walk-steps/s", "cores": th, "kind": "oracle",
+                               "sample": "%d DeepWalk walks (every 97th vertex) on the graph after the same batches"
+                                         % len(sample)}
+    return res
+
+
+def workload_skewed_updates(args):
+    """R-MAT 24 plus 1,000 planted hubs with 10^U(5,6) extra edges each, lognormal(8, 3) weights;
+    update batches of 10^2, 10^4, 10^6 and 10^7 records (half inserts, half deletions, 80 % of the
+    endpoints on hubs), each size several times, with the captured-graph path and the eager path."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph
+    dev = torch.device("cuda:0")
+    scale, c = 24, 4
+    n = 1 << scale
+    src, dst = synth.rmat_graph(scale, 16 << scale, synth.SEEDS["graph"] + c, device=dev)
+    hubs, hsrc, hdst = synth.planted_hubs(n, 1000, 5.0, 6.0, synth.SEEDS["graph"] + c, device=dev)
+    src = torch.cat([src, hsrc]); dst = torch.cat([dst, hdst])
+    del hsrc, hdst
+    m = src.numel()
+    w = synth.weights_lognormal(m, 8.0, 3.0, synth.SEEDS["weights"] + c, device=dev)
+    torch.cuda.synchronize()
+    tb = time.time()
+    g = Graph(n, src, dst, w, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.time() - tb
+    log("skewed: %d edges (%d on planted hubs), built in %.2fs" % (m, m - (16 << scale), build_s))
+    mirror = synth.EdgeMirror(src, dst)
+    del src, dst, w
+    plan = [(100, 40), (10_000, 20), (1_000_000, 4), (10_000_000, 2)]
+    out = {}
+    b = 0
+    for size, reps in plan:
+        half = size // 2
+        res = {}
+        for graphs in (1, 0):
+            g.set_tuning(update_graphs=graphs)
+            times = []
+            recs = 0
+            for r in range(reps + 1):  # the first batch of each setting is a warm-up (plan build, capture)
+                bseed = synth.SEEDS["batch"] + 100 * c + b
+                b += 1
+                isrc = synth.below(bseed, 1, half, n, device=dev)
+                on_hub = synth.below(bseed, 2, half, 10, device=dev) < 8
+                isrc = torch.where(on_hub, hubs[synth.below(bseed, 3, half, hubs.numel(), device=dev)], isrc)
+                idst = synth.below(bseed, 4, half, n, device=dev)
+                iw = synth.weights_lognormal(half, 8.0, 3.0, bseed, device=dev, stream=6)
+                pos = mirror.pick_deletions(size - half, bseed, 30, hub_ids=hubs, hub_frac=0.8)
+                dsrc, ddst = mirror.src[pos], mirror.dst[pos]
+                mirror.apply(isrc, idst, pos)
+                bt = tuple(x.to(torch.int32).contiguous() for x in (isrc, idst, iw, dsrc, ddst))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = g.update(*bt)
+                t1 = time.perf_counter()
+                if r:
+                    times.append((t1 - t0) * 1e3)
+                    recs += st["inserted"] + st["deleted"] + st["not_found"]
+            times.sort()
+            res["graph" if graphs else "eager"] = {"median_ms": times[len(times) // 2], "min_ms": times[0],
+                                                   "records_per_s": recs / (sum(times) / 1e3), "batches": reps}
+        res["graph_speedup"] = res["eager"]["median_ms"] / res["graph"]["median_ms"]
+        mem = g.memory()
+        res["memory"] = {k: mem[k] for k in ("model_ga_bytes", "model_bs_bytes", "list_bytes", "adjacency_bytes",
+                                             "groups_by_type")}
+        res["memory"]["bs_over_ga"] = mem["model_bs_bytes"] / max(mem["model_ga_bytes"], 1)
+        out[str(size)] = res
+        log("skewed: batch %d: graph %.3f ms, eager %.3f ms (x%.2f), %.3g records/s" %
+            (size, res["graph"]["median_ms"], res["eager"]["median_ms"], res["graph_speedup"],
+             res["graph"]["records_per_s"]))
+    g.set_tuning(update_graphs=1)
+    big = out[str(10_000_000)]["graph"]
+    r = common_fields(args, big["records_per_s"], "edge-updates/s", big["median_ms"],
+                      {"workload": "rmat24-ef16-plus-1000-planted-hubs-lognormal-update-batches",
+                       "vertices": n, "edges": m, "batch_sizes": [p[0] for p in plan], "hub_endpoint_share": 0.8})
+    r.update({"batches": out, "build_s": build_s,
+              "note": "value: edge-updates/s of 10^7-record batches through the captured graph (host clock "
+                      "around bingo_update_batch, which synchronizes); the inputs are device-resident"})
+    return r
+
+
+def make_requests(rng, count, n, src, dst, q_max_exp, u_max_exp, w_hi, base_shift=24):
+    """4 walk queries per update batch: query start sets floor(10^U(0, q_max_exp)) uniform vertices with
+    length uniform in 5..80; update batches floor(10^U(0, u_max_exp)) records, half inserts with uniform
+    weights in [1, w_hi), half deletions of input edges."""
+    m = src.numel()
+    reqs = []
+    for i in range(count):
+        if rng.random() < 0.2:
+            k = max(1, int(10 ** rng.uniform(0, u_max_exp)))
+            ki = k // 2
+            pos = rng.integers(0, m, k - ki)
+            reqs.append(("update", rng.integers(0, n, ki), rng.integers(0, n, ki), rng.integers(1, w_hi, ki),
+                         src[torch_index(pos)].cpu().numpy(), dst[torch_index(pos)].cpu().numpy()))
+        else:
+            nw = max(1, int(10 ** rng.uniform(0, q_max_exp)))
+            reqs.append(("walk", rng.integers(0, n, nw), int(rng.integers(5, 81)), int(rng.integers(1 << 62)),
+                         i << base_shift))
+    return reqs
+
+
+def serve_requests(g, reqs, rate, max_inflight=8):
+    """Submit the requests to the serving loop with Poisson arrivals at `rate` per second (0: all at
+    once), collect every result; latency is submission to result ready."""
+    import threading
+    import numpy as np
+    from paper_2504_10233_amd import Server
+    rng = np.random.default_rng(len(reqs))
+    gaps = rng.exponential(1.0 / rate, len(reqs)) if rate > 0 else np.zeros(len(reqs))
+    srv = Server(g, max_inflight=max_inflight)
+    tickets = [None] * len(reqs)
+    infos = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            _, infos[i] = srv.wait(tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    due = t0
+    for i, r in enumerate(reqs):
+        due += gaps[i]
+        while time.perf_counter() < due:
+            pass
+        if r[0] == "walk":
+            tickets[i] = srv.submit_walk(r[1], r[2], r[3], r[4])
+        else:
+            tickets[i] = srv.submit_update(*r[1:])
+        ready.release()
+    th.join()
+    makespan = time.perf_counter() - t0
+    srv.close()
+    q = np.array([x["latency_us"] for x in infos if x["kind"] == 0]) / 1e3
+    u = np.array([x["latency_us"] for x in infos if x["kind"] == 1]) / 1e3
+    steps = sum(x["steps"] for x in infos if x["kind"] == 0)
+    recs = sum(x["updates_applied"] + x["updates_not_found"] for x in infos if x["kind"] == 1)
+    return {"requests": len(reqs), "offered_rate_per_s": rate, "max_inflight": max_inflight,
+            "achieved_rate_per_s": len(reqs) / makespan,
+            "query_p50_ms": float(np.percentile(q, 50)), "query_p99_ms": float(np.percentile(q, 99)),
+            "update_p50_ms": float(np.percentile(u, 50)) if u.size else None,
+            "update_p99_ms": float(np.percentile(u, 99)) if u.size else None,
+            "sustained_walk_steps_per_s": steps / makespan, "sustained_edge_updates_per_s": recs / makespan,
+            "makespan_s": makespan, "errors": int(sum(1 for x in infos if x["status"] != 0))}
+
+
+def workload_serving(args):
+    """R-MAT 25 (33,554,432 vertices, 536,870,912 edges), Zipf(1.5) weights, resident; Poisson
+    stream of walk queries (start sets log-uniform in [1, 10^5], length 5..80) and update batches
+    (log-uniform in [1, 10^4] records) at 4:1 by count; saturation measured first, then offered
+    loads of 50, 80 and 95 % of it."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph
+    dev = torch.device("cuda:0")
+    scale, c = 25, 5
+    n, m = 1 << scale, 16 << scale
+    src, dst = synth.rmat_graph(scale, m, synth.SEEDS["graph"] + c, device=dev)
+    w = synth.weights_zipf(m, 1.5, (1 << 20) - 1, synth.SEEDS["weights"] + c, device=dev)
+    torch.cuda.synchronize()
+    tb = time.time()
+    g = Graph(n, src, dst, w, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.time() - tb
+    del w
+    rng = np.random.default_rng(synth.SEEDS["serving"] if "serving" in synth.SEEDS else 5005)
+    nreq = args.serve_count
+    warm = make_requests(rng, 200, n, src, dst, 5, 4, 1 << 20)
+    serve_requests(g, warm, 0)
+    sat = serve_requests(g, make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20), 0)
+    rate_sat = sat["achieved_rate_per_s"]
+    log("serving R-MAT 25: saturation %.0f requests/s, %.3g walk steps/s" % (rate_sat, sat["sustained_walk_steps_per_s"]))
+    loads = {}
+    for frac in (0.5, 0.8, 0.95):
+        r = serve_requests(g, make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20), frac * rate_sat)
+        loads["%d%%" % int(frac * 100)] = r
+        log("serving at %d%% load: query p50 %.2f ms p99 %.2f ms, update p50 %.2f ms p99 %.2f ms, %.3g steps/s" %
+            (frac * 100, r["query_p50_ms"], r["query_p99_ms"], r["update_p50_ms"] or -1, r["update_p99_ms"] or -1,
+             r["sustained_walk_steps_per_s"]))
+    mid = loads["80%"]
+    res = common_fields(args, mid["sustained_walk_steps_per_s"], "walk-steps/s",
+                        mid["makespan_s"] * 1e3 / max(mid["requests"], 1),
+                        {"workload": "rmat25-ef16-zipf1.5-serving-4to1-queries-updates", "vertices": n, "edges": m,
+                         "query_starts": "log-uniform [1, 1e5]", "query_length": "uniform 5..80",
+                         "update_records": "log-uniform [1, 1e4]", "max_inflight": 8})
+    res.update({"p99_query_latency_ms": mid["query_p99_ms"], "saturation": sat, "loads": loads, "build_s": build_s,
+                "note": "value: sustained walk-steps/s at 80 % of the measured saturation rate; ms_per_step is "
+                        "makespan per request at that load"})
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -177,6 +405,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "ppr":
+        fn = {"deepwalk": workload_deepwalk, "skewed-updates": workload_skewed_updates,
+              "serving": workload_serving}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
     scale, ef = args.scale, args.edge_factor
     n, m = 1 << scale, ef << scale
     c = 3  # seeds of the R-MAT-24 PPR workload
