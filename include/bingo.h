@@ -258,6 +258,13 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *                    per wave iteration) and reruns the query with exact
  *                    per-walk segments if a bin overflows; 0 always uses the
  *                    segments (a length pass first).  Same results either way.
+ *   update_split     bingo_update_batch: a touched vertex's passes over more
+ *                    than this many entries (copying a grown adjacency, the
+ *                    rename-and-fill pass over a kept list, building a fresh
+ *                    list, finding a new one-element member) are split into
+ *                    chunks spread over the GPU instead of running in the
+ *                    vertex's wave.  0 = never split; otherwise at least 64;
+ *                    default 4096.  Same results either way.
  */
 typedef struct {
     uint32_t struct_size;
@@ -267,6 +274,7 @@ typedef struct {
     uint32_t update_graphs;
     uint32_t dense_spec;
     uint32_t ppr_bins;
+    uint32_t update_split;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

@@ -176,12 +176,14 @@ int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     if (!g || !t || t->struct_size != sizeof(bingo_tuning)) return BINGO_E_INVALID;
     if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1 || t->ppr_bins > 1)
         return BINGO_E_INVALID;
+    if (t->update_split != 0 && t->update_split < 64) return BINGO_E_INVALID;
     const uint32_t qc = t->queue_chunk ? t->queue_chunk : 256u;
     if (qc < 16 || qc > 4096 || (qc & (qc - 1))) return BINGO_E_INVALID;
     const uint32_t ds = t->dense_spec ? t->dense_spec : 2u;
     if (ds != 1 && ds != 2 && ds != 4) return BINGO_E_INVALID;
     g->dense_spec = ds;
     g->ppr_bins = t->ppr_bins;
+    g->update_split = t->update_split;
     g->walk_variant = t->walk_variant;
     g->blocks_per_cu = t->blocks_per_cu;
     g->queue_chunk = qc;
@@ -198,6 +200,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
     t->update_graphs = g->update_graphs;
     t->dense_spec = g->dense_spec;
     t->ppr_bins = g->ppr_bins;
+    t->update_split = g->update_split;
     return BINGO_OK;
 }
 

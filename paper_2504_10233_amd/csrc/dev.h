@@ -198,6 +198,9 @@ struct bingo_graph {
     uint32_t dense_spec = 2;
     // persistent PPR: 1 = visits appended to per-source bins (rerun with segments on overflow), 0 = segments
     uint32_t ppr_bins = 1;
+    // update pipeline: passes of a touched vertex over more than this many entries are split
+    // into chunks processed over the whole GPU (0 = never)
+    uint32_t update_split = 4096;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // structure version: bumped by every applied update batch
     uint64_t version = 0;

@@ -58,13 +58,14 @@ int bits_for(uint64_t v) {
 //   [0] inserts  [1] deletes  [2] touched vertices T  [3] flat matching size F
 //   [4] candidates C  [5] deleted-set entries  [6] pool words requested  [7] pool base
 //   [8] overflow flags (bit 0: more candidates than the candidate buffer holds)  [9] records
+//   [10] split work items  [11] split work chunks  [12] split pass-A survivor words
 //   [16..47] statistics (inserted, deleted, not found, 25 type transitions)
 //   [48..79] freed pool words (entry 48)
 // Every kernel reads its element counts from here, so the whole pipeline runs
 // without host round trips and can be captured in a hipGraph; grids and
 // buffers are sized by the batch-size bucket Rmax.
 enum { UC_NI = 0, UC_ND = 1, UC_T = 2, UC_F = 3, UC_C = 4, UC_X = 5, UC_ALLOC = 6, UC_BASE = 7, UC_FLAGS = 8,
-       UC_R = 9,
+       UC_R = 9, UC_BIG_ITEMS = 10, UC_BIG_CHUNKS = 11, UC_BIG_SUR = 12,
        UC_STATS = 16, UC_FREED = 48, UC_WORDS = 96 };
 
 __global__ void k_upd_begin(unsigned long long* __restrict__ uc, uint64_t ni, uint64_t nd, uint32_t* __restrict__ err) {
@@ -155,18 +156,21 @@ __global__ void k_seg_end(const unsigned long long* __restrict__ uc, const uint3
     }
 }
 
-// flat size of the delete-matching space of t: its live edges and its inserts (0 past T)
+// flat size of the delete-matching space of t: its live edges and its inserts (0 past T);
+// also the degree before the batch, dold[t]
 __global__ void k_flat_size(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
                             const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
                             const uint32_t* __restrict__ te, const uint32_t* __restrict__ hdr,
-                            uint64_t* __restrict__ fsz) {
+                            uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold) {
     const uint64_t T = uc[UC_T];
     GRID_LOOP(t, rmax) {
         uint64_t v = 0;
         if (t < T) {
             const uint32_t nd = te[t] - tdl[t];
             const uint32_t ni = tdl[t] - ts[t];
-            v = nd ? (uint64_t)hdr[(size_t)tv[t] * HDR_WORDS + H_DEG] + ni : 0ull;
+            const uint32_t d = hdr[(size_t)tv[t] * HDR_WORDS + H_DEG];
+            dold[t] = d;
+            v = nd ? (uint64_t)d + ni : 0ull;
         }
         fsz[t] = v;
     }
@@ -623,6 +627,71 @@ __device__ __forceinline__ uint32_t rho(uint32_t v, const uint32_t* __restrict__
 // virtual list entry p of a kept group k: the old list, then new members (inserts with bit k)
 // in insert order.  Positions p >= c are enumerated by the insert scans below.
 
+// ---------------------------------------------------------------------------
+// Split work.  A touched vertex is handled by one wave, but four of its passes
+// are O(d) or O(c_k): copying the adjacency into a larger block, pass A of a
+// kept listed group (renames and holes over the whole list), building a fresh
+// list for a group that changed type, and finding the member of a group that
+// became one-element.  On a hub these would keep one wave busy for
+// milliseconds, so above `split` entries the wave records a work item instead
+// and k_big_count / k_big_apply process it in chunks over the whole GPU after
+// k_mutate.  Items and chunks come from fixed-size tables; a wave that cannot
+// reserve space does the pass itself.
+// ---------------------------------------------------------------------------
+enum { BK_COPY = 1, BK_PASSA = 2, BK_FRESH = 3, BK_ONE = 4 };
+constexpr uint32_t BIG_NONE = 0xFFFFFFFFu;
+constexpr uint32_t BIG_MIN_CHUNK = 1024;
+constexpr uint32_t BIG_MAX_CHUNKS_PER_ITEM = 64;
+
+struct BigItem {
+    uint32_t kind, k, n, csize;    // pass, group, entries, entries per chunk
+    uint32_t cbase, u, xoff, N;    // first chunk, vertex, its deleted set xs[xoff .. xoff + N)
+    uint32_t dn, nholes, keep, reloc;
+    uint32_t sur, ocap, ncap, pad;
+    uint64_t a, b, aold, pad2;     // block offsets in pool words (meaning per kind, see k_big_apply)
+};
+static_assert(sizeof(BigItem) == 96, "BigItem layout");
+
+struct BigCtx {
+    BigItem* items;
+    uint32_t* chunk_item;
+    uint32_t* sur;  // tail survivors of deferred pass-A lists, smax words
+    uint32_t imax, cmax, smax;
+};
+
+// Reserve an item and its chunks (every lane calls; the result is uniform).
+__device__ __forceinline__ bool big_reserve(const BigCtx& bc, unsigned long long* uc, uint32_t n, uint32_t& item,
+                                            uint32_t& cbase, uint32_t& csize) {
+    const uint32_t lane = lane_id();
+    uint32_t cs = BIG_MIN_CHUNK;
+    while ((uint64_t)cs * BIG_MAX_CHUNKS_PER_ITEM < n) cs <<= 1;
+    const uint32_t nch = (n + cs - 1) / cs;
+    unsigned long long it = 0, cb = 0;
+    if (lane == 0) {
+        it = atomicAdd(uc + UC_BIG_ITEMS, 1ull);
+        cb = atomicAdd(uc + UC_BIG_CHUNKS, (unsigned long long)nch);
+    }
+    it = __shfl(it, 0, 64);
+    cb = __shfl(cb, 0, 64);
+    const bool ok = it < bc.imax && cb + nch <= bc.cmax;
+    for (uint64_t g = cb + lane; g < cb + nch && g < bc.cmax; g += 64) bc.chunk_item[g] = ok ? (uint32_t)it : BIG_NONE;
+    item = (uint32_t)it;
+    cbase = (uint32_t)cb;
+    csize = cs;
+    return ok;
+}
+
+// Final adjacency word i (< dn) of a vertex whose kept entries may not have been
+// copied to the new block yet: kept entries that were not deleted still sit in
+// the old block.
+__device__ __forceinline__ uint64_t final_word(uint32_t i, const uint64_t* __restrict__ enew,
+                                               const uint64_t* __restrict__ eold, bool reloc, uint32_t keep,
+                                               const uint32_t* __restrict__ X, uint32_t N) {
+    if (reloc && i < keep && !in_set(X, N, i)) return eold[i];
+    return enew[i];
+}
+
+template <bool SPLIT>
 __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
@@ -630,9 +699,10 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
                                uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
                                GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
-                               uint32_t* __restrict__ sur);
+                               uint32_t* __restrict__ sur, const BigCtx& bc, unsigned long long* uc, uint32_t split);
 
-__global__ void __launch_bounds__(WB) k_mutate(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+template <bool SPLIT>
+__global__ void __launch_bounds__(WB) k_mutate(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
                                                const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
@@ -640,7 +710,8 @@ __global__ void __launch_bounds__(WB) k_mutate(const unsigned long long* __restr
                                                uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                                const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
                                                GroupRule rule, const uint64_t* __restrict__ aoff,
-                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ partials) {
+                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ partials,
+                                               const uint32_t* __restrict__ dold, BigCtx bc, uint32_t split) {
     __shared__ unsigned long long red[WB / 64];
     // a batch with bad input, a candidate overflow or no pool space changes nothing
     const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
@@ -649,7 +720,12 @@ __global__ void __launch_bounds__(WB) k_mutate(const unsigned long long* __restr
     uint64_t freed_total = 0;  // lane 0 of each wave
     for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6); t < T;
          t += (uint64_t)gridDim.x * (WB / 64)) {
-        freed_total += mutate_one(t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, id, iw, rule, aoff, abase0, sur);
+        // the split instance takes the vertices with more than `split` entries after the inserts
+        // (the degree from before the batch: the other instance may have rewritten the header)
+        const bool big = split && dold[t] + (tdl[t] - ts[t]) > split;
+        if (big != SPLIT) continue;
+        freed_total += mutate_one<SPLIT>(t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, id, iw, rule, aoff, abase0,
+                                         sur, bc, uc, split);
     }
     if (lane_id() == 0) red[threadIdx.x >> 6] = freed_total;
     __syncthreads();
@@ -661,7 +737,10 @@ __global__ void __launch_bounds__(WB) k_mutate(const unsigned long long* __restr
     }
 }
 
-// One touched vertex; returns (in every lane) the pool words it freed.
+// One touched vertex; returns (in every lane) the pool words it freed.  The
+// SPLIT instance handles the vertices with more than `split` entries and may
+// hand its long passes to k_big_apply; the other one handles the rest.
+template <bool SPLIT>
 __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                                const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
@@ -669,7 +748,7 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
                                uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
                                const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
                                GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
-                               uint32_t* __restrict__ sur) {
+                               uint32_t* __restrict__ sur, const BigCtx& bc, unsigned long long* uc, uint32_t split) {
     VState s;
     load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
     const uint32_t lane = lane_id();
@@ -693,8 +772,20 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     uint64_t* enew = reinterpret_cast<uint64_t*>(pool + nadj);
     uint32_t* qnew = pool + nadj + 2ull * ncap;
     const uint32_t keep = s.d < s.dn ? s.d : s.dn;
-    if (nadj != s.adj) {
-        for (uint32_t i = lane; i < keep; i += 64) { enew[i] = eold[i]; qnew[i] = qold[i]; }
+    const bool reloc = nadj != s.adj;
+    if (reloc) {
+        uint32_t it, cb, cs;
+        if (SPLIT && keep > split && big_reserve(bc, uc, keep, it, cb, cs)) {
+            // the kept entries that are not deleted are copied by k_big_apply
+            if (lane == 0) {
+                BigItem& bi = bc.items[it];
+                bi.kind = BK_COPY; bi.k = 0; bi.n = keep; bi.csize = cs; bi.cbase = cb; bi.u = s.u;
+                bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep; bi.reloc = 1;
+                bi.sur = 0; bi.ocap = s.cap; bi.ncap = ncap; bi.a = s.adj; bi.b = nadj; bi.aold = s.adj;
+            }
+        } else {
+            for (uint32_t i = lane; i < keep; i += 64) { enew[i] = eold[i]; qnew[i] = qold[i]; }
+        }
     }
     __threadfence_block();
     // inserts that stay where they were appended
@@ -775,17 +866,53 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         // pass A: final entries [0, cnk): kept entries renamed, holes take S[] in rank order
         uint32_t nh = 0;
         const uint32_t oldpart = ck < cnk ? ck : cnk;
-        for (uint32_t p0 = 0; p0 < oldpart; p0 += 64) {
-            const uint32_t p = p0 + lane;
-            const bool v = p < oldpart;
-            const uint32_t e = v ? Lold[p] : 0u;
-            const bool hole = v && in_set(X, N, e);
-            const uint64_t hb = __ballot(hole);
-            if (v) {
-                const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
-                if (val != e || nblk != oblk) Lnew[p] = val;
+        uint32_t it, cb, cs;
+        bool defer = false;
+        unsigned long long soff = 0;
+        if (SPLIT && oldpart > split) {
+            // the tail survivors move to the split survivor buffer: S is reused by the next group
+            if (lane == 0) soff = atomicAdd(uc + UC_BIG_SUR, (unsigned long long)nsur);
+            soff = __shfl(soff, 0, 64);
+            defer = soff + nsur <= bc.smax && big_reserve(bc, uc, oldpart, it, cb, cs);
+        }
+        if (defer) {
+            for (uint32_t i = lane; i < nsur; i += 64) bc.sur[soff + i] = S[i];
+            if (lane == 0) {
+                BigItem& bi = bc.items[it];
+                bi.kind = BK_PASSA; bi.k = (uint32_t)k; bi.n = oldpart; bi.csize = cs; bi.cbase = cb; bi.u = s.u;
+                bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep;
+                bi.reloc = nblk != oblk ? 1u : 0u; bi.sur = (uint32_t)soff; bi.ocap = 0; bi.ncap = 0;
+                bi.a = oblk; bi.b = nblk; bi.aold = 0;
             }
-            nh += __popcll(hb);
+            // holes among the first cnk virtual positions = deleted members of the group less the
+            // deleted entries of the tail window; those among the new members are counted below
+            const uint32_t delk = __shfl(s.del, k, 64);
+            uint32_t hnew = 0;
+            if (cnk > ck) {
+                uint32_t r2 = 0;
+                for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+                    const uint32_t a = a0 + lane;
+                    const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+                    const uint64_t b = __ballot(v);
+                    const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
+                    hnew += __popcll(__ballot(v && p < cnk && in_set(X, N, s.d + a)));
+                    r2 += __popcll(b);
+                }
+            }
+            nh = (delk - (lenv - cnk - nsur)) - hnew;
+        } else {
+            for (uint32_t p0 = 0; p0 < oldpart; p0 += 64) {
+                const uint32_t p = p0 + lane;
+                const bool v = p < oldpart;
+                const uint32_t e = v ? Lold[p] : 0u;
+                const bool hole = v && in_set(X, N, e);
+                const uint64_t hb = __ballot(hole);
+                if (v) {
+                    const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
+                    if (val != e || nblk != oblk) Lnew[p] = val;
+                }
+                nh += __popcll(hb);
+            }
         }
         if (cnk > ck) {
             // new members at positions [ck, cnk)
@@ -842,19 +969,42 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         }
     }
     const uint32_t need_scan = (uint32_t)(__ballot(one && member == NF) & 0xFFFFFFFFull);
-    if (fm | need_scan) {
+    uint32_t fm_seq = fm, ns_seq = need_scan;
+    if (SPLIT && s.dn > split && (fm | need_scan)) {
+        // fresh lists and one-element members of a large vertex: split work
+        uint32_t mm = fm | need_scan;
+        while (mm) {
+            const int k = __ffs(mm) - 1;
+            mm &= mm - 1;
+            uint32_t it, cb, cs;
+            const uint64_t blk = (uint64_t)__shfl(newinfo, k, 64) * LIST_UNIT_WORDS;
+            if (big_reserve(bc, uc, s.dn, it, cb, cs)) {
+                if (lane == 0) {
+                    BigItem& bi = bc.items[it];
+                    bi.kind = ((fm >> k) & 1u) ? BK_FRESH : BK_ONE; bi.k = (uint32_t)k; bi.n = s.dn; bi.csize = cs;
+                    bi.cbase = cb; bi.u = s.u; bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes;
+                    bi.keep = keep; bi.reloc = reloc ? 1u : 0u; bi.sur = 0; bi.ocap = 0; bi.ncap = 0;
+                    bi.a = nadj; bi.b = blk; bi.aold = s.adj;
+                }
+                fm_seq &= ~(1u << k);
+                ns_seq &= ~(1u << k);
+            }
+        }
+    }
+    if (fm_seq | ns_seq) {
         // one pass over the final adjacency
         uint32_t fill = 0;
         for (uint32_t i0 = 0; i0 < s.dn; i0 += 64) {
             const uint32_t i = i0 + lane;
-            const uint32_t w = i < s.dn ? (uint32_t)(enew[i] >> 32) : 0u;
-            uint32_t mm = fm | need_scan;
+            uint32_t w = 0;
+            if (i < s.dn) w = (uint32_t)((SPLIT ? final_word(i, enew, eold, reloc, keep, X, N) : enew[i]) >> 32);
+            uint32_t mm = fm_seq | ns_seq;
             while (mm) {
                 const int k = __ffs(mm) - 1;
                 mm &= mm - 1;
                 const bool bit = (w >> k) & 1u;
                 const uint64_t b = __ballot(bit);
-                if ((fm >> k) & 1u) {
+                if ((fm_seq >> k) & 1u) {
                     const uint64_t blk = (uint64_t)__shfl(newinfo, k, 64) * LIST_UNIT_WORDS;
                     const uint32_t f = __shfl(fill, k, 64);
                     if (bit) pool[blk + f + __popcll(b & lanemask_lt())] = i;
@@ -898,6 +1048,134 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     return freed;
 }
 
+// Split work, pass 1: per chunk, the number of entries the chunk contributes
+// (holes of a pass-A list, members of a fresh list; 0 for the other kinds).
+// One block per chunk, grid-stride over the reserved chunks.
+__device__ __forceinline__ bool big_pred(const BigItem& bi, uint32_t p, const uint32_t* __restrict__ pool,
+                                         const uint32_t* __restrict__ X) {
+    if (bi.kind == BK_PASSA) return in_set(X, bi.N, pool[bi.a + p]);
+    // BK_FRESH / BK_ONE: bit k of the final adjacency word p
+    const uint64_t w = final_word(p, reinterpret_cast<const uint64_t*>(pool + bi.a),
+                                  reinterpret_cast<const uint64_t*>(pool + bi.aold), bi.reloc != 0, bi.keep, X, bi.N);
+    return (w >> (32 + bi.k)) & 1ull;
+}
+
+__global__ void __launch_bounds__(256) k_big_count(const unsigned long long* __restrict__ uc, BigCtx bc,
+                                                   const uint32_t* __restrict__ xs, const uint32_t* __restrict__ pool,
+                                                   uint32_t* __restrict__ ccnt) {
+    __shared__ BigItem bi;
+    __shared__ uint32_t red[4];
+    const uint64_t used = std::min<uint64_t>(uc[UC_BIG_CHUNKS], bc.cmax);
+    for (uint64_t g = blockIdx.x; g < used; g += gridDim.x) {
+        const uint32_t it = bc.chunk_item[g];
+        if (it == BIG_NONE) continue;
+        __syncthreads();
+        if (threadIdx.x == 0) bi = bc.items[it];
+        __syncthreads();
+        uint32_t c = 0;
+        if (bi.kind == BK_PASSA || bi.kind == BK_FRESH) {
+            const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
+            const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
+            const uint32_t* X = xs + bi.xoff;
+            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) c += big_pred(bi, p, pool, X) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        if (lane_id() == 0) red[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) ccnt[g] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// Split work, pass 2.  An item's chunk g starts at rank ccnt[cbase] + ... +
+// ccnt[g - 1] among the item's holes/members (an item has at most 64 chunks);
+// inside a chunk each thread takes a contiguous slice and a block scan orders
+// the slices.
+//   BK_COPY : a = old adjacency, b = new adjacency (capacities ocap, ncap):
+//             kept entries [0, keep) not deleted are copied with their seq.
+//   BK_PASSA: a = old list, b = new list: hole -> next tail survivor
+//             (bc.sur[sur + rank]), other entries renamed; written when changed
+//             or when the list moved.
+//   BK_FRESH: a = new adjacency, aold = old one, b = the list: ascending
+//             indices of the final entries with bit k.
+//   BK_ONE  : the first final entry with bit k becomes the group's member
+//             (header info, set to NF by k_mutate, lowered by atomicMin).
+__global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __restrict__ uc, BigCtx bc,
+                                                   const uint32_t* __restrict__ xs, uint32_t* __restrict__ pool,
+                                                   uint32_t* __restrict__ hdr, const uint32_t* __restrict__ ccnt) {
+    __shared__ BigItem bi;
+    __shared__ uint32_t wsum[4], cbefore;
+    const uint64_t used = std::min<uint64_t>(uc[UC_BIG_CHUNKS], bc.cmax);
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint64_t g = blockIdx.x; g < used; g += gridDim.x) {
+        const uint32_t it = bc.chunk_item[g];
+        if (it == BIG_NONE) continue;
+        __syncthreads();
+        if (threadIdx.x == 0) bi = bc.items[it];
+        __syncthreads();
+        const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
+        const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
+        const uint32_t* X = xs + bi.xoff;
+        if (bi.kind == BK_COPY) {
+            const uint64_t* eo = reinterpret_cast<const uint64_t*>(pool + bi.a);
+            const uint32_t* qo = pool + bi.a + 2ull * bi.ocap;
+            uint64_t* en = reinterpret_cast<uint64_t*>(pool + bi.b);
+            uint32_t* qn = pool + bi.b + 2ull * bi.ncap;
+            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256)
+                if (!in_set(X, bi.N, p)) { en[p] = eo[p]; qn[p] = qo[p]; }
+            continue;
+        }
+        if (bi.kind == BK_ONE) {
+            uint32_t first = NF;
+            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256)
+                if (big_pred(bi, p, pool, X)) { first = p; break; }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) first = min(first, (uint32_t)__shfl_xor(first, o));
+            if (lane == 0 && first != NF) atomicMin(hdr + (size_t)bi.u * HDR_WORDS + H_INFO + bi.k, first);
+            continue;
+        }
+        // BK_PASSA / BK_FRESH: ordered output
+        const uint32_t per = (bi.csize + 255) / 256;
+        const uint32_t q0 = std::min(p0 + threadIdx.x * per, p1), q1 = std::min(q0 + per, p1);
+        uint32_t mine = 0;
+        for (uint32_t p = q0; p < q1; ++p) mine += big_pred(bi, p, pool, X) ? 1u : 0u;
+        uint32_t x = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        if (wave == 0) {
+            uint32_t c = (uint64_t)bi.cbase + lane < g ? ccnt[bi.cbase + lane] : 0u;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+            if (lane == 0) cbefore = c;
+        }
+        __syncthreads();
+        uint32_t before = cbefore;
+        for (int w = 0; w < (int)wave; ++w) before += wsum[w];
+        uint32_t r = before + x - mine;
+        if (bi.kind == BK_FRESH) {
+            uint32_t* L = pool + bi.b;
+            for (uint32_t p = q0; p < q1; ++p)
+                if (big_pred(bi, p, pool, X)) L[r++] = p;
+        } else {
+            const uint32_t* Lold = pool + bi.a;
+            uint32_t* Lnew = pool + bi.b;
+            const uint32_t* S = bc.sur + bi.sur;
+            for (uint32_t p = q0; p < q1; ++p) {
+                const uint32_t e = Lold[p];
+                uint32_t val;
+                if (in_set(X, bi.N, e)) val = S[r++];
+                else val = rho(e, X, bi.N, bi.dn, bi.nholes);
+                if (val != e || bi.reloc) Lnew[p] = val;
+            }
+        }
+        __syncthreads();  // wsum is reused by the next chunk
+    }
+}
+
 __global__ void k_add_u64(unsigned long long* dst, const unsigned long long* src) { *dst += *src; }
 
 // Reserve the batch's pool words with one bump, unless the batch is already
@@ -926,9 +1204,12 @@ struct UpdPlan {
     uint32_t *is = nullptr, *id = nullptr, *iw = nullptr, *ds = nullptr, *dd = nullptr;  // staged inputs
     unsigned long long* uc = nullptr;
     uint64_t *keys, *sk, *hx, *fsz, *foff, *ckey, *cks, *xk, *xks, *needw, *aoff, *xoff;
-    uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt;
+    uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold;
     unsigned long long* parts;
+    BigItem* big_items;
+    uint32_t *chunk_item, *ccnt, *bsur;
     void* tmp;
+    uint32_t split = 0;  // the split threshold the captured graph was made with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_failed = false;
@@ -940,6 +1221,10 @@ struct UpdPlans {
 };
 
 static constexpr uint32_t MATCH_GRID = 2048;
+static constexpr uint32_t BIG_IMAX = 16384;
+static constexpr uint32_t BIG_CMAX = 1u << 18;
+static constexpr uint32_t BIG_SMAX = 1u << 22;
+static constexpr uint32_t BIG_GRID = 2048;
 static constexpr size_t PLAN_CACHE_BYTES = 16ull << 30;
 
 static void plan_free(UpdPlan* p) {
@@ -953,9 +1238,11 @@ static void plan_free(UpdPlan* p) {
 static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const uint64_t R = rmax, C = cmax;
-    const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)), scan_temp_bytes(R + 1));
+    const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)),
+                                 scan_temp_bytes(R + 1));
     const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 10 + al(C * 8) * 2 + al(R * 4) * 13 +
-                         al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + tmpb + 4096;
+                         al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + al(BIG_IMAX * sizeof(BigItem)) +
+                         2 * al(BIG_CMAX * 4) + al(BIG_SMAX * 4) + tmpb + 4096;
     UpdPlan* p = new UpdPlan();
     p->rmax = R;
     p->cmax = C;
@@ -975,10 +1262,14 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->rec_t = (uint32_t*)take(R * 4); p->tv = (uint32_t*)take(R * 4); p->tsa = (uint32_t*)take(R * 4);
     p->tdl = (uint32_t*)take(R * 4); p->te = (uint32_t*)take(R * 4); p->first = (uint32_t*)take(R * 4);
     p->matched = (uint32_t*)take(R * 4); p->xs = (uint32_t*)take(R * 4); p->ncnt = (uint32_t*)take(R * 4);
-    (void)take(R * 4);  // spare
+    p->dold = (uint32_t*)take(R * 4);
     p->sur = (uint32_t*)take(R * 8);
     p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
     p->parts = (unsigned long long*)take(PART_BLOCKS * 32 * 8);
+    p->big_items = (BigItem*)take(BIG_IMAX * sizeof(BigItem));
+    p->chunk_item = (uint32_t*)take(BIG_CMAX * 4);
+    p->ccnt = (uint32_t*)take(BIG_CMAX * 4);
+    p->bsur = (uint32_t*)take(BIG_SMAX * 4);
     p->tmp = w;
     return p;
 }
@@ -1014,7 +1305,7 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     hipLaunchKernelGGL(k_seg_end, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, p->tsa, p->te,
                        p->tdl);
     hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->tv,
-                       p->tsa, p->tdl, p->te, g->hdr, p->fsz);
+                       p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold);
     scan_u64(p->fsz, p->foff, R, p->tmp, uc + UC_F, st);
     // 2. delete matching: candidates, sorted by (run, seq); the k oldest per run
     hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tv, p->tsa, p->tdl, p->te, p->sk,
@@ -1042,11 +1333,25 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
     // 5. mutation (a no-op for a rejected batch)
-    hipLaunchKernelGGL(k_mutate, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, (const uint32_t*)err,
+    BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, BIG_SMAX};
+    const uint32_t split = g->update_split;
+    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err,
                        p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
-                       g->rule, p->aoff, p->sur, p->parts);
+                       g->rule, p->aoff, p->sur, p->parts, p->dold, bc, split);
     hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
                        uc + UC_FREED, 0);
+    if (split) {
+        // vertices with more than `split` entries, then the passes they handed over
+        hipLaunchKernelGGL((k_mutate<true>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err,
+                           p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
+                           g->rule, p->aoff, p->sur, p->parts, p->dold, bc, split);
+        hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+                           uc + UC_FREED, 1);
+        hipLaunchKernelGGL(k_big_count, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
+                           (const uint32_t*)p->xs, (const uint32_t*)g->pool, p->ccnt);
+        hipLaunchKernelGGL(k_big_apply, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
+                           (const uint32_t*)p->xs, g->pool, g->hdr, (const uint32_t*)p->ccnt);
+    }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
 }
 
@@ -1112,8 +1417,15 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
         hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(128), 0, st, p->uc, n_ins, n_del, g->d_err);
         phase_mark(g, st, true);
         bool launched = false;
+        if (p->exec && p->split != g->update_split) {
+            hipGraphExecDestroy(p->exec);
+            hipGraphDestroy(p->graph);
+            p->exec = nullptr;
+            p->graph = nullptr;
+        }
         if (g->update_graphs && !p->graph_failed) {
             if (!p->exec) {
+                p->split = g->update_split;
                 if (!g->upd->cap_stream &&
                     hipStreamCreateWithFlags(&g->upd->cap_stream, hipStreamNonBlocking) != hipSuccess)
                     g->upd->cap_stream = nullptr;

@@ -198,7 +198,8 @@ def test_update_c1(adaptive):
 
 @pytest.mark.parametrize("adaptive", [True, False])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_update_random_batches(adaptive, seed):
+@pytest.mark.parametrize("split", [0, 64])
+def test_update_random_batches(adaptive, seed, split):
     rng = random.Random(seed)
     n = 40
     src = [rng.randrange(n) for _ in range(400)] + [0] * 300 + [1] * 70
@@ -206,6 +207,7 @@ def test_update_random_batches(adaptive, seed):
           [rng.randrange(n) for _ in range(70)]
     w = [rng.choice([1, 2, 3, 7, 64, 1000, rng.randrange(1, 1 << 20), 1 << rng.randrange(32)]) for _ in range(770)]
     og, gg = both(n, src, dst, w, adaptive)
+    gg.set_tuning(update_split=split)
     for b in range(14):
         cur = O.parse_dump(og.dump(), n)
         live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
@@ -226,8 +228,12 @@ def test_update_random_batches(adaptive, seed):
         assert np.array_equal(u32(paths), opaths), b
 
 
-def test_update_edge_cases():
+@pytest.mark.parametrize("split", [0, 64, 4096])
+def test_update_edge_cases(split):
+    """split 0 keeps every vertex in one wave; 64 and the default 4096 hand the hub's passes
+    (5000 to 5700 entries, several chunks) to the split kernels."""
     og, gg = both(*skew_edges())
+    gg.set_tuning(update_split=split)
     apply_both(og, gg, [], [], "empty batch")
     apply_both(og, gg, [(7, 1, 5)], [], "insert into an isolated vertex")
     apply_both(og, gg, [], [(9, 9), (0, 55)], "deletes of absent edges")
@@ -265,6 +271,9 @@ def test_update_graph_replays_match_eager():
         cur = O.parse_dump(og.dump(), n)
         live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
         big = b in (5, 9)  # a second size bucket between replays of the first
+        if b == 7:  # a new split threshold makes the captured graphs stale
+            gg.set_tuning(update_split=64)
+            assert gg.get_tuning()["update_split"] == 64
         ni, nd = (1500, 900) if big else (rng.randrange(1, 300), rng.randrange(1, 300))
         ins = [(rng.randrange(n), rng.randrange(n), rng.randrange(1, 1 << 32)) for _ in range(ni)]
         dels = [rng.choice(live) if rng.random() < 0.9 else (rng.randrange(n), rng.randrange(n)) for _ in range(nd)]
@@ -281,12 +290,12 @@ def test_update_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("graphs", [0, 1])
-def test_update_candidate_overflow_retries(graphs):
+@pytest.mark.parametrize("graphs,split", [(0, 4096), (1, 4096), (1, 0), (0, 64)])
+def test_update_candidate_overflow_retries(graphs, split):
     """A small batch whose deletes hit more stored occurrences than the bucket's candidate buffer
     holds is rerun with a larger buffer and still matches the oracle."""
     og, gg = both(*skew_edges())
-    gg.set_tuning(update_graphs=graphs)
+    gg.set_tuning(update_graphs=graphs, update_split=split)
     rng = random.Random(5)
     ins = [(6, rng.randrange(60), rng.randrange(1, 1 << 32)) for _ in range(80000)]
     apply_both(og, gg, ins, [], "hub grows to 85000 edges")
@@ -365,7 +374,8 @@ def test_tuning_rejects_bad_values():
     c = c1()
     _, gg = both(c["n"], c["src"], c["dst"], c["w"])
     for kw in [dict(walk_variant=2), dict(queue_chunk=100), dict(queue_chunk=8), dict(blocks_per_cu=65),
-               dict(dense_spec=3), dict(dense_spec=8), dict(update_graphs=2), dict(ppr_bins=2)]:
+               dict(dense_spec=3), dict(dense_spec=8), dict(update_graphs=2), dict(ppr_bins=2),
+               dict(update_split=10), dict(update_split=63)]:
         with pytest.raises(b.BingoError):
             gg.set_tuning(**kw)
 
