@@ -42,6 +42,9 @@ def parse():
                          "with 2x10^6-record batches; skewed-updates: R-MAT 24 + planted hubs, batches 10^2..10^7; "
                          "serving: R-MAT 25 request stream at 50/80/95 %% of saturation")
     ap.add_argument("--serve-count", type=int, default=10_000, help="requests per load level (serving workload)")
+    ap.add_argument("--update-sizes", default="100,10000,1000000,10000000",
+                    help="batch sizes of the skewed-updates workload (comma-separated; the value is quoted on the "
+                         "largest)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=24)
@@ -226,7 +229,8 @@ def workload_skewed_updates(args):
     log("skewed: %d edges (%d on planted hubs), built in %.2fs" % (m, m - (16 << scale), build_s))
     mirror = synth.EdgeMirror(src, dst)
     del src, dst, w
-    plan = [(100, 40), (10_000, 20), (1_000_000, 4), (10_000_000, 2)]
+    reps_for = {100: 40, 10_000: 20, 1_000_000: 4, 10_000_000: 2}
+    plan = [(int(x), reps_for.get(int(x), 4)) for x in args.update_sizes.split(",")]
     out = {}
     b = 0
     for size, reps in plan:
@@ -268,7 +272,7 @@ def workload_skewed_updates(args):
             (size, res["graph"]["median_ms"], res["eager"]["median_ms"], res["graph_speedup"],
              res["graph"]["records_per_s"]))
     g.set_tuning(update_graphs=1)
-    big = out[str(10_000_000)]["graph"]
+    big = out[str(plan[-1][0])]["graph"]
     r = common_fields(args, big["records_per_s"], "edge-updates/s", big["median_ms"],
                       {"workload": "rmat24-ef16-plus-1000-planted-hubs-lognormal-update-batches",
                        "vertices": n, "edges": m, "batch_sizes": [p[0] for p in plan], "hub_endpoint_share": 0.8})

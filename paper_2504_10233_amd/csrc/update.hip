@@ -59,13 +59,14 @@ int bits_for(uint64_t v) {
 //   [4] candidates C  [5] deleted-set entries  [6] pool words requested  [7] pool base
 //   [8] overflow flags (bit 0: more candidates than the candidate buffer holds)  [9] records
 //   [10] split work items  [11] split work chunks  [12] split pass-A survivor words
+//   [13] large vertices (more than the split threshold of entries)
 //   [16..47] statistics (inserted, deleted, not found, 25 type transitions)
 //   [48..79] freed pool words (entry 48)
 // Every kernel reads its element counts from here, so the whole pipeline runs
 // without host round trips and can be captured in a hipGraph; grids and
 // buffers are sized by the batch-size bucket Rmax.
 enum { UC_NI = 0, UC_ND = 1, UC_T = 2, UC_F = 3, UC_C = 4, UC_X = 5, UC_ALLOC = 6, UC_BASE = 7, UC_FLAGS = 8,
-       UC_R = 9, UC_BIG_ITEMS = 10, UC_BIG_CHUNKS = 11, UC_BIG_SUR = 12,
+       UC_R = 9, UC_BIG_ITEMS = 10, UC_BIG_CHUNKS = 11, UC_BIG_SUR = 12, UC_NBIG = 13,
        UC_STATS = 16, UC_FREED = 48, UC_WORDS = 96 };
 
 __global__ void k_upd_begin(unsigned long long* __restrict__ uc, uint64_t ni, uint64_t nd, uint32_t* __restrict__ err) {
@@ -157,11 +158,13 @@ __global__ void k_seg_end(const unsigned long long* __restrict__ uc, const uint3
 }
 
 // flat size of the delete-matching space of t: its live edges and its inserts (0 past T);
-// also the degree before the batch, dold[t]
-__global__ void k_flat_size(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
+// also the degree before the batch, dold[t], and the list of the vertices with more than
+// `split` entries after the inserts (in no particular order)
+__global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
                             const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
                             const uint32_t* __restrict__ te, const uint32_t* __restrict__ hdr,
-                            uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold) {
+                            uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold, uint32_t split,
+                            uint32_t* __restrict__ blist) {
     const uint64_t T = uc[UC_T];
     GRID_LOOP(t, rmax) {
         uint64_t v = 0;
@@ -171,6 +174,7 @@ __global__ void k_flat_size(const unsigned long long* __restrict__ uc, uint64_t 
             const uint32_t d = hdr[(size_t)tv[t] * HDR_WORDS + H_DEG];
             dold[t] = d;
             v = nd ? (uint64_t)d + ni : 0ull;
+            if (split && d + ni > split) blist[atomicAdd(uc + UC_NBIG, 1ull)] = (uint32_t)t;
         }
         fsz[t] = v;
     }
@@ -457,6 +461,37 @@ __global__ void k_xextract(uint64_t R, const uint64_t* __restrict__ xk, uint32_t
     GRID_LOOP(p, R) xs[p] = (uint32_t)xk[p];
 }
 
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t n, uint32_t v);
+
+// Per insert record (sorted position j in [ts[t], tdl[t]) of touched vertex t):
+// its weight wv[j], contiguous per vertex, and its final adjacency index
+// idest[j] (NF when the batch deletes it again), so the per-group passes of
+// k_mutate neither gather weights nor search the deleted set for inserts.
+__global__ void k_ins_prep(const unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ sv,
+                           const uint32_t* __restrict__ iw, const uint32_t* __restrict__ rec_t,
+                           const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
+                           const uint32_t* __restrict__ dold, const uint32_t* __restrict__ ncnt,
+                           const uint64_t* __restrict__ xoff, const uint32_t* __restrict__ xs,
+                           uint32_t* __restrict__ wv, uint32_t* __restrict__ idest) {
+    const uint64_t R = uc[UC_NI] + uc[UC_ND];
+    GRID_LOOP(j, rmax) {
+        if (j >= R) continue;
+        const uint32_t t = rec_t[j];
+        const uint32_t s0 = ts[t], s1 = tdl[t];
+        if (j >= s1) continue;  // a delete record
+        const uint32_t a = (uint32_t)j - s0, d = dold[t], N = ncnt[t];
+        const uint32_t* X = xs + xoff[t];
+        const uint32_t e = d + a, dn = d + (s1 - s0) - N;
+        const uint32_t pe = lower_bound_u32(X, N, e);
+        uint32_t dest;
+        if (pe < N && X[pe] == e) dest = NF;
+        else if (e < dn) dest = e;
+        else dest = X[(e - dn) - (pe - lower_bound_u32(X, N, dn))];
+        wv[j] = iw[sv[j]];
+        idest[j] = dest;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-vertex state shared by the analysis and mutation kernels
 // ---------------------------------------------------------------------------
@@ -475,17 +510,16 @@ __device__ __forceinline__ uint32_t ins_rec(const uint32_t* __restrict__ sv, uin
 
 // weight of virtual index x: an old edge (x < d) or insert x - d
 __device__ __forceinline__ uint32_t vweight(uint32_t x, const VState& s, const uint32_t* __restrict__ pool,
-                                            const uint32_t* __restrict__ sv, const uint32_t* __restrict__ iw) {
+                                            const uint32_t* __restrict__ wv) {
     if (x < s.d) return pool[s.adj + 2ull * x + 1];
-    return iw[sv[s.ts + (x - s.d)]];
+    return wv[s.ts + (x - s.d)];
 }
 
 __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
                            const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                            const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
                            const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
-                           const uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
-                           const uint32_t* __restrict__ iw, GroupRule rule) {
+                           const uint32_t* __restrict__ pool, const uint32_t* __restrict__ wv, GroupRule rule) {
     const uint32_t lane = lane_id();
     s.u = tv[t];
     const uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
@@ -502,7 +536,7 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     uint32_t app = 0, del = 0;
     for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
         const uint32_t a = a0 + lane;
-        const uint32_t w = a < s.ni ? vweight(s.d + a, s, pool, sv, iw) : 0u;
+        const uint32_t w = a < s.ni ? wv[s.ts + a] : 0u;
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             const uint64_t b = __ballot((w >> k) & 1u);
@@ -512,7 +546,7 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     const uint32_t* X = xs + s.xoff;
     for (uint32_t j0 = 0; j0 < s.N; j0 += 64) {
         const uint32_t j = j0 + lane;
-        const uint32_t w = j < s.N ? vweight(X[j], s, pool, sv, iw) : 0u;
+        const uint32_t w = j < s.N ? vweight(X[j], s, pool, wv) : 0u;
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             const uint64_t b = __ballot((w >> k) & 1u);
@@ -549,16 +583,16 @@ __global__ void __launch_bounds__(WB) k_analyze(const unsigned long long* __rest
                                                 const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                 const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
                                                 const uint32_t* __restrict__ xs, const uint32_t* __restrict__ hdr,
-                                                const uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
-                                                const uint32_t* __restrict__ iw, GroupRule rule,
-                                                uint64_t* __restrict__ need, unsigned long long* __restrict__ partials) {
+                                                const uint32_t* __restrict__ pool, const uint32_t* __restrict__ wv,
+                                                GroupRule rule, uint64_t* __restrict__ need,
+                                                unsigned long long* __restrict__ partials) {
     __shared__ unsigned long long red[WB / 64][32];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t T = uc[UC_T];
     uint64_t acc = 0;  // lane i < 28 accumulates counter i
     for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + wave; t < T; t += (uint64_t)gridDim.x * (WB / 64)) {
         VState s;
-        load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
+        load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, wv, rule);
         uint64_t w = lane_list_need(s);
         if (lane == 0 && s.dn > s.cap) w += adj_block_words(adj_cap_for(s.dn));
         w = wave_sum(w);
@@ -624,6 +658,45 @@ __device__ __forceinline__ uint32_t rho(uint32_t v, const uint32_t* __restrict__
     return X[j];
 }
 
+// The deleted set of the vertex k_mutate is working on: the sorted array in
+// global memory and, for the large-vertex instance, every 2^sh-th entry of it
+// in LDS (sh = 0: all of it), so a search takes its first steps in LDS and at
+// most sh steps in global memory.
+struct XView {
+    const uint32_t* X;
+    const uint32_t* L;  // nullptr: no LDS samples
+    uint32_t N, nl, sh;
+};
+__device__ __forceinline__ uint32_t xv_lb(const XView& x, uint32_t v) {
+    if (!x.L) return lower_bound_u32(x.X, x.N, v);
+    uint32_t lo = 0, hi = x.nl;  // samples below v
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x.L[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    if (lo == 0) return 0;
+    uint32_t a = ((lo - 1) << x.sh) + 1, b = min(lo << x.sh, x.N);
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if (x.X[mid] < v) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+__device__ __forceinline__ uint32_t xv_at(const XView& x, uint32_t j) {
+    return (x.L && x.sh == 0) ? x.L[j] : x.X[j];
+}
+__device__ __forceinline__ bool xv_in(const XView& x, uint32_t v) {
+    const uint32_t p = xv_lb(x, v);
+    return p < x.N && xv_at(x, p) == v;
+}
+// in_set and rho with one search: NF for a deleted v, else its new index
+__device__ __forceinline__ uint32_t xv_rho(const XView& x, uint32_t v, uint32_t dn, uint32_t nholes) {
+    const uint32_t p = xv_lb(x, v);
+    if (p < x.N && xv_at(x, p) == v) return NF;
+    if (v < dn) return v;
+    return xv_at(x, (v - dn) - (p - nholes));
+}
+
 // virtual list entry p of a kept group k: the old list, then new members (inserts with bit k)
 // in insert order.  Positions p >= c are enumerated by the insert scans below.
 
@@ -634,23 +707,33 @@ __device__ __forceinline__ uint32_t rho(uint32_t v, const uint32_t* __restrict__
 // list for a group that changed type, and finding the member of a group that
 // became one-element.  On a hub these would keep one wave busy for
 // milliseconds, so above `split` entries the wave records a work item instead
-// and k_big_count / k_big_apply process it in chunks over the whole GPU after
+// and the k_big_* kernels process it in chunks over the whole GPU after
 // k_mutate.  Items and chunks come from fixed-size tables; a wave that cannot
 // reserve space does the pass itself.
+//   k_big_pass  : one wave per chunk: adjacency copies, one-element members, and
+//                 pass A of lists with at most BIG_HOLES holes (renames written
+//                 in place, hole positions collected unordered)
+//   k_big_count / k_big_apply : ordered output (fresh lists, pass A of lists
+//                 with more holes): per-chunk counts, then ranks
+//   k_big_holes : per pass-A item of the first kind, its holes sorted by
+//                 position take the tail survivors in order
 // ---------------------------------------------------------------------------
-enum { BK_COPY = 1, BK_PASSA = 2, BK_FRESH = 3, BK_ONE = 4 };
+enum { BK_COPY = 1, BK_PASSA = 2, BK_FRESH = 3, BK_ONE = 4, BK_PASSH = 5 };
+constexpr uint32_t BIG_HOLES = 4096;
 constexpr uint32_t BIG_NONE = 0xFFFFFFFFu;
-constexpr uint32_t BIG_MIN_CHUNK = 1024;
-constexpr uint32_t BIG_MAX_CHUNKS_PER_ITEM = 64;
+constexpr uint32_t BIG_MIN_CHUNK = 2048;
+constexpr uint32_t BIG_MAX_CHUNKS_PER_ITEM = 16;
 
 struct BigItem {
     uint32_t kind, k, n, csize;    // pass, group, entries, entries per chunk
     uint32_t cbase, u, xoff, N;    // first chunk, vertex, its deleted set xs[xoff .. xoff + N)
     uint32_t dn, nholes, keep, reloc;
-    uint32_t sur, ocap, ncap, pad;
-    uint64_t a, b, aold, pad2;     // block offsets in pool words (meaning per kind, see k_big_apply)
+    uint32_t sur, hole, ocap, ncap;  // survivor words sur[..], hole slots sur[hole ..], adjacency capacities
+    uint64_t a, b, aold;           // block offsets in pool words (meaning per kind, see k_big_apply)
+    uint32_t nh, pad;              // BK_PASSH: holes of the list
+    unsigned long long hcnt;       // BK_PASSH: hole positions collected so far
 };
-static_assert(sizeof(BigItem) == 96, "BigItem layout");
+static_assert(sizeof(BigItem) == 104, "BigItem layout");
 
 struct BigCtx {
     BigItem* items;
@@ -675,87 +758,111 @@ __device__ __forceinline__ bool big_reserve(const BigCtx& bc, unsigned long long
     cb = __shfl(cb, 0, 64);
     const bool ok = it < bc.imax && cb + nch <= bc.cmax;
     for (uint64_t g = cb + lane; g < cb + nch && g < bc.cmax; g += 64) bc.chunk_item[g] = ok ? (uint32_t)it : BIG_NONE;
+    if (!ok && it < bc.imax && lane == 0) bc.items[it].kind = 0;  // a slot k_big_holes must skip
     item = (uint32_t)it;
     cbase = (uint32_t)cb;
     csize = cs;
     return ok;
 }
 
-// Final adjacency word i (< dn) of a vertex whose kept entries may not have been
-// copied to the new block yet: kept entries that were not deleted still sit in
-// the old block.
-__device__ __forceinline__ uint64_t final_word(uint32_t i, const uint64_t* __restrict__ enew,
-                                               const uint64_t* __restrict__ eold, bool reloc, uint32_t keep,
-                                               const uint32_t* __restrict__ X, uint32_t N) {
-    if (reloc && i < keep && !in_set(X, N, i)) return eold[i];
-    return enew[i];
-}
+// Arguments of the mutation shared by the per-vertex code.
+struct MutArgs {
+    const uint32_t *tv, *ts, *tdl, *te, *ncnt;
+    const uint64_t *xoff;
+    const uint32_t *xs;
+    uint32_t *hdr, *pool;
+    const uint32_t *sv, *id, *wv, *idest;
+    const uint64_t* aoff;
+    uint32_t* sur;
+    GroupRule rule;
+};
 
 template <bool SPLIT>
-__device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
-                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
-                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
-                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
-                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
-                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
-                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
-                               uint32_t* __restrict__ sur, const BigCtx& bc, unsigned long long* uc, uint32_t split);
+__device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, const XView& xv, const BigCtx& bc,
+                               unsigned long long* uc, uint32_t split);
+
+// The large-vertex instance (SPLIT) runs one wave per block with the deleted
+// set's samples in dynamic LDS; the other runs WB-thread blocks, one vertex per
+// wave at a time.
+constexpr uint32_t XL_WORDS = 8192;  // LDS samples per large vertex (32 KiB)
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(WB) k_mutate(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
-                                               const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
-                                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
-                                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
-                                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
-                                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
-                                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
-                                               GroupRule rule, const uint64_t* __restrict__ aoff,
-                                               uint32_t* __restrict__ sur, unsigned long long* __restrict__ partials,
-                                               const uint32_t* __restrict__ dold, BigCtx bc, uint32_t split) {
+                                               MutArgs A, unsigned long long* __restrict__ partials,
+                                               const uint32_t* __restrict__ dold, const uint32_t* __restrict__ blist,
+                                               BigCtx bc, uint32_t split) {
     __shared__ unsigned long long red[WB / 64];
+    extern __shared__ uint32_t xl[];
     // a batch with bad input, a candidate overflow or no pool space changes nothing
     const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
     const uint64_t T = skip ? 0 : uc[UC_T];
     const uint64_t abase0 = uc[UC_BASE];
+    const uint32_t lane = lane_id();
     uint64_t freed_total = 0;  // lane 0 of each wave
-    for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6); t < T;
-         t += (uint64_t)gridDim.x * (WB / 64)) {
-        // the split instance takes the vertices with more than `split` entries after the inserts
-        // (the degree from before the batch: the other instance may have rewritten the header)
-        const bool big = split && dold[t] + (tdl[t] - ts[t]) > split;
-        if (big != SPLIT) continue;
-        freed_total += mutate_one<SPLIT>(t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, id, iw, rule, aoff, abase0,
-                                         sur, bc, uc, split);
+    if constexpr (!SPLIT) {
+        for (uint64_t t = (uint64_t)blockIdx.x * (WB / 64) + (threadIdx.x >> 6); t < T;
+             t += (uint64_t)gridDim.x * (WB / 64)) {
+            // vertices with more than `split` entries after the inserts belong to the other instance
+            // (the degree from before the batch: headers are rewritten as vertices finish)
+            if (split && dold[t] + (A.tdl[t] - A.ts[t]) > split) continue;
+            const uint32_t N = A.ncnt[t];
+            const XView xv{A.xs + A.xoff[t], nullptr, N, 0u, 0u};
+            freed_total += mutate_one<false>(t, A, abase0, xv, bc, uc, split);
+        }
+    } else {
+        // one block (one wave) per listed large vertex
+        const uint64_t nb = skip ? 0 : uc[UC_NBIG];
+        for (uint64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+            const uint64_t t = blist[i];
+            const uint32_t N = A.ncnt[t];
+            const uint32_t* X = A.xs + A.xoff[t];
+            uint32_t sh = 0;
+            while ((N >> sh) >= XL_WORDS) ++sh;
+            const uint32_t nl = (N + (1u << sh) - 1) >> sh;
+            __syncthreads();  // the previous vertex is done with xl
+            for (uint32_t j = lane; j < nl; j += 64) xl[j] = X[(uint64_t)j << sh];
+            __syncthreads();
+            const XView xv{X, xl, N, nl, sh};
+            freed_total += mutate_one<true>(t, A, abase0, xv, bc, uc, split);
+        }
     }
-    if (lane_id() == 0) red[threadIdx.x >> 6] = freed_total;
+    if (lane == 0) red[threadIdx.x >> 6] = freed_total;
     __syncthreads();
     if (threadIdx.x < 32) {
         unsigned long long v = 0;
         if (threadIdx.x == 0)
-            for (int w = 0; w < WB / 64; ++w) v += red[w];
+            for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) v += red[w];
         partials[(uint64_t)blockIdx.x * 32 + threadIdx.x] = v;  // counter 0: garbage words
     }
+}
+
+// Final adjacency word i (< dn) of a vertex whose kept entries may not have been
+// copied to the new block yet: kept entries that were not deleted still sit in
+// the old block.
+__device__ __forceinline__ uint64_t final_word_xv(uint32_t i, const uint64_t* __restrict__ enew,
+                                                  const uint64_t* __restrict__ eold, bool reloc, uint32_t keep,
+                                                  const XView& xv) {
+    if (reloc && i < keep && !xv_in(xv, i)) return eold[i];
+    return enew[i];
 }
 
 // One touched vertex; returns (in every lane) the pool words it freed.  The
 // SPLIT instance handles the vertices with more than `split` entries and may
 // hand its long passes to k_big_apply; the other one handles the rest.
 template <bool SPLIT>
-__device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
-                               const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
-                               const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
-                               const uint32_t* __restrict__ xs, uint32_t* __restrict__ hdr,
-                               uint32_t* __restrict__ pool, const uint32_t* __restrict__ sv,
-                               const uint32_t* __restrict__ id, const uint32_t* __restrict__ iw,
-                               GroupRule rule, const uint64_t* __restrict__ aoff, uint64_t abase0,
-                               uint32_t* __restrict__ sur, const BigCtx& bc, unsigned long long* uc, uint32_t split) {
+__device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, const XView& xv, const BigCtx& bc,
+                               unsigned long long* uc, uint32_t split) {
+    const uint32_t* __restrict__ wv = A.wv;
+    const uint32_t* __restrict__ idest = A.idest;
+    uint32_t* __restrict__ pool = A.pool;
     VState s;
-    load_state(s, (uint32_t)t, tv, ts, tdl, te, ncnt, xoff, xs, hdr, pool, sv, iw, rule);
+    load_state(s, (uint32_t)t, A.tv, A.ts, A.tdl, A.te, A.ncnt, A.xoff, A.xs, A.hdr, pool, wv, A.rule);
     const uint32_t lane = lane_id();
-    const uint32_t* X = xs + s.xoff;
     const uint32_t N = s.N;
-    const uint32_t nholes = lower_bound_u32(X, N, s.dn);  // X entries below the new degree
-    uint64_t abase = abase0 + aoff[t];
+    const uint32_t nholes = xv_lb(xv, s.dn);  // deleted entries below the new degree
+    const uint32_t* W = wv + s.ts;            // insert weights
+    const uint32_t* D = idest + s.ts;         // insert final indices (NF: deleted)
+    uint64_t abase = abase0 + A.aoff[t];
     uint64_t freed = 0;
 
     // ---- adjacency
@@ -781,7 +888,8 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
                 BigItem& bi = bc.items[it];
                 bi.kind = BK_COPY; bi.k = 0; bi.n = keep; bi.csize = cs; bi.cbase = cb; bi.u = s.u;
                 bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep; bi.reloc = 1;
-                bi.sur = 0; bi.ocap = s.cap; bi.ncap = ncap; bi.a = s.adj; bi.b = nadj; bi.aold = s.adj;
+                bi.sur = 0; bi.hole = 0; bi.ocap = s.cap; bi.ncap = ncap; bi.a = s.adj; bi.b = nadj; bi.aold = s.adj;
+                bi.nh = 0; bi.pad = 0; bi.hcnt = 0;
             }
         } else {
             for (uint32_t i = lane; i < keep; i += 64) { enew[i] = eold[i]; qnew[i] = qold[i]; }
@@ -790,22 +898,23 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     __threadfence_block();
     // inserts that stay where they were appended
     for (uint32_t q = s.d + lane; q < s.dn; q += 64) {
-        if (!in_set(X, N, q)) {
-            const uint32_t a = q - s.d, r = sv[s.ts + a];
-            enew[q] = (uint64_t)id[r] | ((uint64_t)iw[r] << 32);
+        const uint32_t a = q - s.d;
+        if (D[a] != NF) {
+            enew[q] = (uint64_t)A.id[A.sv[s.ts + a]] | ((uint64_t)W[a] << 32);
             qnew[q] = s.nseq + a;
         }
     }
     // tail survivors fill the holes in rank order
     for (uint32_t q = s.dn + lane; q < s.d1; q += 64) {
-        if (!in_set(X, N, q)) {
-            const uint32_t dest = rho(q, X, N, s.dn, nholes);
-            uint64_t e;
-            uint32_t sq;
-            if (q < s.d) { e = eold[q]; sq = qold[q]; }
-            else { const uint32_t a = q - s.d, r = sv[s.ts + a]; e = (uint64_t)id[r] | ((uint64_t)iw[r] << 32); sq = s.nseq + a; }
-            enew[dest] = e;
-            qnew[dest] = sq;
+        if (q < s.d) {
+            const uint32_t dest = xv_rho(xv, q, s.dn, nholes);
+            if (dest != NF) { enew[dest] = eold[q]; qnew[dest] = qold[q]; }
+        } else {
+            const uint32_t a = q - s.d, dest = D[a];
+            if (dest != NF) {
+                enew[dest] = (uint64_t)A.id[A.sv[s.ts + a]] | ((uint64_t)W[a] << 32);
+                qnew[dest] = s.nseq + a;
+            }
         }
     }
     __threadfence_block();
@@ -824,7 +933,7 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     }
     const uint64_t my_block = abase + (lx - lneed);
     abase += __shfl(lx, 63, 64);
-    uint32_t* S = sur + s.xoff;
+    uint32_t* S = A.sur + s.xoff;
     while (km) {
         const int k = __ffs(km) - 1;
         km &= km - 1;
@@ -840,27 +949,25 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         // old-list part of the window
         for (uint32_t p0 = cnk; p0 < ck; p0 += 64) {
             const uint32_t p = p0 + lane;
-            const bool v = p < ck;
-            const uint32_t e = v ? Lold[p] : 0u;
-            const bool surv = v && !in_set(X, N, e);
-            const uint64_t b = __ballot(surv);
-            if (surv) S[nsur + __popcll(b & lanemask_lt())] = rho(e, X, N, s.dn, nholes);
+            const uint32_t r = p < ck ? xv_rho(xv, Lold[p], s.dn, nholes) : NF;
+            const uint64_t b = __ballot(r != NF);
+            if (r != NF) S[nsur + __popcll(b & lanemask_lt())] = r;
             nsur += __popcll(b);
         }
         // new-member part: inserts with bit k, position ck + rank
         uint32_t rank = 0;
         for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
             const uint32_t a = a0 + lane;
-            const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+            const bool v = a < s.ni && ((W[a] >> k) & 1u);
             const uint64_t b = __ballot(v);
-            const uint32_t p = ck + rank + __popcll(b & lanemask_lt());
-            const uint32_t e = s.d + a;
-            const bool inwin = v && p >= cnk;
-            const bool surv = inwin && !in_set(X, N, e);
-            const uint64_t sb = __ballot(surv);
-            if (surv) S[nsur + __popcll(sb & lanemask_lt())] = rho(e, X, N, s.dn, nholes);
-            nsur += __popcll(sb);
-            rank += __popcll(b);
+            if (b) {
+                const uint32_t p = ck + rank + __popcll(b & lanemask_lt());
+                const uint32_t r = v && p >= cnk ? D[a] : NF;
+                const uint64_t sb = __ballot(r != NF);
+                if (r != NF) S[nsur + __popcll(sb & lanemask_lt())] = r;
+                nsur += __popcll(sb);
+                rank += __popcll(b);
+            }
         }
         __threadfence_block();
         // pass A: final entries [0, cnk): kept entries renamed, holes take S[] in rank order
@@ -868,47 +975,54 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         const uint32_t oldpart = ck < cnk ? ck : cnk;
         uint32_t it, cb, cs;
         bool defer = false;
-        unsigned long long soff = 0;
         if (SPLIT && oldpart > split) {
-            // the tail survivors move to the split survivor buffer: S is reused by the next group
-            if (lane == 0) soff = atomicAdd(uc + UC_BIG_SUR, (unsigned long long)nsur);
-            soff = __shfl(soff, 0, 64);
-            defer = soff + nsur <= bc.smax && big_reserve(bc, uc, oldpart, it, cb, cs);
-        }
-        if (defer) {
-            for (uint32_t i = lane; i < nsur; i += 64) bc.sur[soff + i] = S[i];
-            if (lane == 0) {
-                BigItem& bi = bc.items[it];
-                bi.kind = BK_PASSA; bi.k = (uint32_t)k; bi.n = oldpart; bi.csize = cs; bi.cbase = cb; bi.u = s.u;
-                bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep;
-                bi.reloc = nblk != oblk ? 1u : 0u; bi.sur = (uint32_t)soff; bi.ocap = 0; bi.ncap = 0;
-                bi.a = oblk; bi.b = nblk; bi.aold = 0;
-            }
             // holes among the first cnk virtual positions = deleted members of the group less the
-            // deleted entries of the tail window; those among the new members are counted below
+            // deleted entries of the tail window; those among the new members are counted here
             const uint32_t delk = __shfl(s.del, k, 64);
             uint32_t hnew = 0;
             if (cnk > ck) {
                 uint32_t r2 = 0;
-                for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+                for (uint32_t a0 = 0; a0 < s.ni && ck + r2 < cnk; a0 += 64) {
                     const uint32_t a = a0 + lane;
-                    const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+                    const bool v = a < s.ni && ((W[a] >> k) & 1u);
                     const uint64_t b = __ballot(v);
                     const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
-                    hnew += __popcll(__ballot(v && p < cnk && in_set(X, N, s.d + a)));
+                    hnew += __popcll(__ballot(v && p < cnk && D[a] == NF));
                     r2 += __popcll(b);
                 }
             }
-            nh = (delk - (lenv - cnk - nsur)) - hnew;
-        } else {
+            const uint32_t nha = (delk - (lenv - cnk - nsur)) - hnew;  // holes in [0, oldpart)
+            // the tail survivors (and the hole slots) move to the split survivor buffer: S is reused
+            // by the next group
+            const bool listed = nha <= BIG_HOLES;
+            const uint32_t words = nsur + (listed ? nha : 0u);
+            unsigned long long soff = 0;
+            if (lane == 0) soff = atomicAdd(uc + UC_BIG_SUR, (unsigned long long)words);
+            soff = __shfl(soff, 0, 64);
+            defer = soff + words <= bc.smax && big_reserve(bc, uc, oldpart, it, cb, cs);
+            if (defer) {
+                for (uint32_t i = lane; i < nsur; i += 64) bc.sur[soff + i] = S[i];
+                if (lane == 0) {
+                    BigItem& bi = bc.items[it];
+                    bi.kind = listed ? BK_PASSH : BK_PASSA; bi.k = (uint32_t)k; bi.n = oldpart; bi.csize = cs;
+                    bi.cbase = cb; bi.u = s.u; bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes;
+                    bi.keep = keep; bi.reloc = nblk != oblk ? 1u : 0u; bi.sur = (uint32_t)soff;
+                    bi.hole = (uint32_t)(soff + nsur); bi.ocap = 0; bi.ncap = 0; bi.a = oblk; bi.b = nblk;
+                    bi.aold = 0; bi.nh = nha; bi.pad = 0; bi.hcnt = 0;
+                }
+                nh = nha;
+            }
+        }
+        if (!defer) {
             for (uint32_t p0 = 0; p0 < oldpart; p0 += 64) {
                 const uint32_t p = p0 + lane;
                 const bool v = p < oldpart;
                 const uint32_t e = v ? Lold[p] : 0u;
-                const bool hole = v && in_set(X, N, e);
+                const uint32_t r = v ? xv_rho(xv, e, s.dn, nholes) : 0u;
+                const bool hole = v && r == NF;
                 const uint64_t hb = __ballot(hole);
                 if (v) {
-                    const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
+                    const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : r;
                     if (val != e || nblk != oblk) Lnew[p] = val;
                 }
                 nh += __popcll(hb);
@@ -917,16 +1031,16 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         if (cnk > ck) {
             // new members at positions [ck, cnk)
             uint32_t r2 = 0;
-            for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
+            for (uint32_t a0 = 0; a0 < s.ni && ck + r2 < cnk; a0 += 64) {
                 const uint32_t a = a0 + lane;
-                const bool v = a < s.ni && ((iw[sv[s.ts + a]] >> k) & 1u);
+                const bool v = a < s.ni && ((W[a] >> k) & 1u);
                 const uint64_t b = __ballot(v);
                 const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
-                const uint32_t e = s.d + a;
                 const bool inpre = v && p < cnk;
-                const bool hole = inpre && in_set(X, N, e);
+                const uint32_t r = inpre ? D[a] : 0u;
+                const bool hole = inpre && r == NF;
                 const uint64_t hb = __ballot(hole);
-                if (inpre) Lnew[p] = hole ? S[nh + __popcll(hb & lanemask_lt())] : rho(e, X, N, s.dn, nholes);
+                if (inpre) Lnew[p] = hole ? S[nh + __popcll(hb & lanemask_lt())] : r;
                 nh += __popcll(hb);
                 r2 += __popcll(b);
             }
@@ -946,17 +1060,13 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     // one-element groups: the surviving member
     const bool one = lane < 32 && s.tnew == GT_ONE;
     uint32_t member = NF;
-    if (one) {
-        if (s.told == GT_ONE && !in_set(X, N, s.info)) member = rho(s.info, X, N, s.dn, nholes);
-    }
+    if (one && s.told == GT_ONE) member = xv_rho(xv, s.info, s.dn, nholes);
     // members found among the inserts
-    {
+    if (__ballot(one && member == NF)) {
         for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
             const uint32_t a = a0 + lane;
-            const bool v = a < s.ni;
-            const uint32_t e = s.d + a;
-            const uint32_t w = v && !in_set(X, N, e) ? iw[sv[s.ts + a]] : 0u;
-            const uint32_t dest = w ? rho(e, X, N, s.dn, nholes) : 0u;
+            const uint32_t dest = a < s.ni ? D[a] : NF;
+            const uint32_t w = dest != NF ? W[a] : 0u;
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
                 const uint64_t b = __ballot((w >> k) & 1u);
@@ -983,8 +1093,8 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
                     BigItem& bi = bc.items[it];
                     bi.kind = ((fm >> k) & 1u) ? BK_FRESH : BK_ONE; bi.k = (uint32_t)k; bi.n = s.dn; bi.csize = cs;
                     bi.cbase = cb; bi.u = s.u; bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes;
-                    bi.keep = keep; bi.reloc = reloc ? 1u : 0u; bi.sur = 0; bi.ocap = 0; bi.ncap = 0;
-                    bi.a = nadj; bi.b = blk; bi.aold = s.adj;
+                    bi.keep = keep; bi.reloc = reloc ? 1u : 0u; bi.sur = 0; bi.hole = 0; bi.ocap = 0; bi.ncap = 0;
+                    bi.a = nadj; bi.b = blk; bi.aold = s.adj; bi.nh = 0; bi.pad = 0; bi.hcnt = 0;
                 }
                 fm_seq &= ~(1u << k);
                 ns_seq &= ~(1u << k);
@@ -997,7 +1107,7 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
         for (uint32_t i0 = 0; i0 < s.dn; i0 += 64) {
             const uint32_t i = i0 + lane;
             uint32_t w = 0;
-            if (i < s.dn) w = (uint32_t)((SPLIT ? final_word(i, enew, eold, reloc, keep, X, N) : enew[i]) >> 32);
+            if (i < s.dn) w = (uint32_t)((SPLIT ? final_word_xv(i, enew, eold, reloc, keep, xv) : enew[i]) >> 32);
             uint32_t mm = fm_seq | ns_seq;
             while (mm) {
                 const int k = __ffs(mm) - 1;
@@ -1018,7 +1128,7 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     }
 
     // ---- header: the inter-group sampling space of the vertex
-    uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
+    uint32_t* h = A.hdr + (size_t)s.u * HDR_WORDS;
     const bool ne = lane < 32 && s.cn > 0;
     const uint64_t wsum = wave_sum(ne ? ((uint64_t)s.cn << lane) : 0ull);
     const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
@@ -1048,23 +1158,52 @@ __device__ uint64_t mutate_one(uint64_t t, const uint32_t* __restrict__ tv, cons
     return freed;
 }
 
-// Split work, pass 1: per chunk, the number of entries the chunk contributes
-// (holes of a pass-A list, members of a fresh list; 0 for the other kinds).
-// One block per chunk, grid-stride over the reserved chunks.
-__device__ __forceinline__ bool big_pred(const BigItem& bi, uint32_t p, const uint32_t* __restrict__ pool,
-                                         const uint32_t* __restrict__ X) {
-    if (bi.kind == BK_PASSA) return in_set(X, bi.N, pool[bi.a + p]);
-    // BK_FRESH / BK_ONE: bit k of the final adjacency word p
-    const uint64_t w = final_word(p, reinterpret_cast<const uint64_t*>(pool + bi.a),
-                                  reinterpret_cast<const uint64_t*>(pool + bi.aold), bi.reloc != 0, bi.keep, X, bi.N);
+// Split work: the deleted set of an item's vertex, with up to BIG_XL samples in LDS.
+constexpr uint32_t BIG_XL = 1024;
+
+__device__ __forceinline__ XView big_stage_x(const BigItem& bi, const uint32_t* __restrict__ xs, uint32_t* xl) {
+    const uint32_t* X = xs + bi.xoff;
+    uint32_t sh = 0;
+    while ((bi.N >> sh) >= BIG_XL) ++sh;
+    const uint32_t nl = (bi.N + (1u << sh) - 1) >> sh;
+    for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) xl[j] = X[(uint64_t)j << sh];
+    return XView{X, xl, bi.N, nl, sh};
+}
+
+// Entry p of an item in two steps, so a tile's loads are all in flight before
+// the searches: big_load reads the raw words (pass A: the list entry in w0;
+// fresh / one-element: the new adjacency word in w0 and, for a kept entry of a
+// relocated adjacency, the old one in w1); big_eval gives the predicate: a hole
+// of a pass-A list (other entries get their new index in *r), or bit k of the
+// final adjacency word p.
+__device__ __forceinline__ void big_load(const BigItem& bi, uint32_t p, const uint32_t* __restrict__ pool,
+                                         uint64_t& w0, uint64_t& w1) {
+    w1 = 0;
+    if (bi.kind == BK_PASSA) { w0 = pool[bi.a + p]; return; }
+    w0 = reinterpret_cast<const uint64_t*>(pool + bi.a)[p];
+    if (bi.reloc && p < bi.keep) w1 = reinterpret_cast<const uint64_t*>(pool + bi.aold)[p];
+}
+__device__ __forceinline__ bool big_eval(const BigItem& bi, uint32_t p, uint64_t w0, uint64_t w1, const XView& xv,
+                                         uint32_t* r) {
+    if (bi.kind == BK_PASSA) {
+        *r = xv_rho(xv, (uint32_t)w0, bi.dn, bi.nholes);
+        return *r == NF;
+    }
+    const uint64_t w = (bi.reloc && p < bi.keep && !xv_in(xv, p)) ? w1 : w0;
     return (w >> (32 + bi.k)) & 1ull;
 }
 
+constexpr uint32_t BIG_TPT = 8;  // entries per thread per tile (tiles of 2048 entries)
+
+// Split work, pass 1: per chunk, the number of entries the chunk contributes
+// (holes of a pass-A list, members of a fresh list; 0 for the other kinds).
+// One block per chunk, grid-stride over the reserved chunks.
 __global__ void __launch_bounds__(256) k_big_count(const unsigned long long* __restrict__ uc, BigCtx bc,
                                                    const uint32_t* __restrict__ xs, const uint32_t* __restrict__ pool,
                                                    uint32_t* __restrict__ ccnt) {
     __shared__ BigItem bi;
     __shared__ uint32_t red[4];
+    __shared__ uint32_t xl[BIG_XL];
     const uint64_t used = std::min<uint64_t>(uc[UC_BIG_CHUNKS], bc.cmax);
     for (uint64_t g = blockIdx.x; g < used; g += gridDim.x) {
         const uint32_t it = bc.chunk_item[g];
@@ -1072,12 +1211,26 @@ __global__ void __launch_bounds__(256) k_big_count(const unsigned long long* __r
         __syncthreads();
         if (threadIdx.x == 0) bi = bc.items[it];
         __syncthreads();
+        if (bi.kind != BK_PASSA && bi.kind != BK_FRESH) continue;
+        const XView xv = big_stage_x(bi, xs, xl);
+        __syncthreads();
         uint32_t c = 0;
-        if (bi.kind == BK_PASSA || bi.kind == BK_FRESH) {
-            const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
-            const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
-            const uint32_t* X = xs + bi.xoff;
-            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) c += big_pred(bi, p, pool, X) ? 1u : 0u;
+        const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
+        const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
+        for (uint32_t q0 = p0; q0 < p1; q0 += 256 * BIG_TPT) {
+            uint64_t w0[BIG_TPT], w1[BIG_TPT];
+#pragma unroll
+            for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                const uint32_t p = q0 + j * 256 + threadIdx.x;
+                w0[j] = w1[j] = 0;
+                if (p < p1) big_load(bi, p, pool, w0[j], w1[j]);
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                const uint32_t p = q0 + j * 256 + threadIdx.x;
+                uint32_t r;
+                if (p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r)) ++c;
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
@@ -1087,24 +1240,21 @@ __global__ void __launch_bounds__(256) k_big_count(const unsigned long long* __r
     }
 }
 
-// Split work, pass 2.  An item's chunk g starts at rank ccnt[cbase] + ... +
-// ccnt[g - 1] among the item's holes/members (an item has at most 64 chunks);
-// inside a chunk each thread takes a contiguous slice and a block scan orders
-// the slices.
-//   BK_COPY : a = old adjacency, b = new adjacency (capacities ocap, ncap):
-//             kept entries [0, keep) not deleted are copied with their seq.
+// Split work, pass 2 of the ordered kinds.  An item's chunk g starts at rank
+// ccnt[cbase] + ... + ccnt[g - 1] among the item's holes/members (an item has at
+// most 16 chunks); the chunk is walked in tiles of 2048 consecutive entries
+// (entry q0 + 256 j + thread), ranked by ballots.
 //   BK_PASSA: a = old list, b = new list: hole -> next tail survivor
 //             (bc.sur[sur + rank]), other entries renamed; written when changed
 //             or when the list moved.
 //   BK_FRESH: a = new adjacency, aold = old one, b = the list: ascending
 //             indices of the final entries with bit k.
-//   BK_ONE  : the first final entry with bit k becomes the group's member
-//             (header info, set to NF by k_mutate, lowered by atomicMin).
 __global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __restrict__ uc, BigCtx bc,
                                                    const uint32_t* __restrict__ xs, uint32_t* __restrict__ pool,
-                                                   uint32_t* __restrict__ hdr, const uint32_t* __restrict__ ccnt) {
+                                                   const uint32_t* __restrict__ ccnt) {
     __shared__ BigItem bi;
-    __shared__ uint32_t wsum[4], cbefore;
+    __shared__ uint32_t wsum[BIG_TPT][4], cbefore;
+    __shared__ uint32_t xl[BIG_XL];
     const uint64_t used = std::min<uint64_t>(uc[UC_BIG_CHUNKS], bc.cmax);
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     for (uint64_t g = blockIdx.x; g < used; g += gridDim.x) {
@@ -1113,39 +1263,8 @@ __global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __r
         __syncthreads();
         if (threadIdx.x == 0) bi = bc.items[it];
         __syncthreads();
-        const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
-        const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
-        const uint32_t* X = xs + bi.xoff;
-        if (bi.kind == BK_COPY) {
-            const uint64_t* eo = reinterpret_cast<const uint64_t*>(pool + bi.a);
-            const uint32_t* qo = pool + bi.a + 2ull * bi.ocap;
-            uint64_t* en = reinterpret_cast<uint64_t*>(pool + bi.b);
-            uint32_t* qn = pool + bi.b + 2ull * bi.ncap;
-            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256)
-                if (!in_set(X, bi.N, p)) { en[p] = eo[p]; qn[p] = qo[p]; }
-            continue;
-        }
-        if (bi.kind == BK_ONE) {
-            uint32_t first = NF;
-            for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256)
-                if (big_pred(bi, p, pool, X)) { first = p; break; }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) first = min(first, (uint32_t)__shfl_xor(first, o));
-            if (lane == 0 && first != NF) atomicMin(hdr + (size_t)bi.u * HDR_WORDS + H_INFO + bi.k, first);
-            continue;
-        }
-        // BK_PASSA / BK_FRESH: ordered output
-        const uint32_t per = (bi.csize + 255) / 256;
-        const uint32_t q0 = std::min(p0 + threadIdx.x * per, p1), q1 = std::min(q0 + per, p1);
-        uint32_t mine = 0;
-        for (uint32_t p = q0; p < q1; ++p) mine += big_pred(bi, p, pool, X) ? 1u : 0u;
-        uint32_t x = mine;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= (uint32_t)o) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
+        if (bi.kind != BK_PASSA && bi.kind != BK_FRESH) continue;
+        const XView xv = big_stage_x(bi, xs, xl);
         if (wave == 0) {
             uint32_t c = (uint64_t)bi.cbase + lane < g ? ccnt[bi.cbase + lane] : 0u;
 #pragma unroll
@@ -1153,26 +1272,189 @@ __global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __r
             if (lane == 0) cbefore = c;
         }
         __syncthreads();
-        uint32_t before = cbefore;
-        for (int w = 0; w < (int)wave; ++w) before += wsum[w];
-        uint32_t r = before + x - mine;
-        if (bi.kind == BK_FRESH) {
-            uint32_t* L = pool + bi.b;
-            for (uint32_t p = q0; p < q1; ++p)
-                if (big_pred(bi, p, pool, X)) L[r++] = p;
+        const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
+        const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
+        // BK_PASSA / BK_FRESH: ordered output
+        uint32_t base = cbefore;
+        uint32_t* L = pool + bi.b;
+        const uint32_t* S = bc.sur + bi.sur;
+        for (uint32_t q0 = p0; q0 < p1; q0 += 256 * BIG_TPT) {
+            uint64_t w0[BIG_TPT], w1[BIG_TPT];
+#pragma unroll
+            for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                const uint32_t p = q0 + j * 256 + threadIdx.x;
+                w0[j] = w1[j] = 0;
+                if (p < p1) big_load(bi, p, pool, w0[j], w1[j]);
+            }
+            uint32_t r[BIG_TPT];
+            uint64_t b[BIG_TPT];
+#pragma unroll
+            for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                const uint32_t p = q0 + j * 256 + threadIdx.x;
+                r[j] = 0;
+                const bool pr = p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r[j]);
+                b[j] = __ballot(pr);
+                if (lane == 0) wsum[j][wave] = (uint32_t)__popcll(b[j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                const uint32_t p = q0 + j * 256 + threadIdx.x;
+                uint32_t rk = base + (uint32_t)__popcll(b[j] & lanemask_lt());
+                for (uint32_t w = 0; w < wave; ++w) rk += wsum[j][w];
+                base += wsum[j][0] + wsum[j][1] + wsum[j][2] + wsum[j][3];
+                const bool pr = (b[j] >> lane) & 1ull;
+                if (bi.kind == BK_FRESH) {
+                    if (pr) L[rk] = p;
+                } else if (p < p1) {
+                    const uint32_t e = (uint32_t)w0[j];
+                    const uint32_t val = pr ? S[rk] : r[j];
+                    if (val != e || bi.reloc) L[p] = val;
+                }
+            }
+            __syncthreads();  // wsum is rewritten by the next tile
+        }
+    }
+}
+
+// Split work, the unordered kinds, one wave per chunk (the deleted set's samples
+// in a per-wave LDS slice):
+//   BK_COPY : a = old adjacency, b = new adjacency (capacities ocap, ncap):
+//             kept entries [0, keep) not deleted are copied with their seq.
+//   BK_ONE  : the first final entry with bit k becomes the group's member
+//             (header info, set to NF by k_mutate, lowered by atomicMin).
+//   BK_PASSH: a = old list, b = new list: other entries renamed (written when
+//             changed or when the list moved); hole positions appended to
+//             sur[hole ..] for k_big_holes.
+constexpr uint32_t BIG_WXL = 1024;  // LDS samples per wave
+
+__global__ void __launch_bounds__(256) k_big_pass(const unsigned long long* __restrict__ uc, BigCtx bc,
+                                                  const uint32_t* __restrict__ xs, uint32_t* __restrict__ pool,
+                                                  uint32_t* __restrict__ hdr) {
+    __shared__ uint32_t xlw[4][BIG_WXL];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t* xl = xlw[wave];
+    const uint64_t used = std::min<uint64_t>(uc[UC_BIG_CHUNKS], bc.cmax);
+    for (uint64_t g = (uint64_t)blockIdx.x * 4 + wave; g < used; g += (uint64_t)gridDim.x * 4) {
+        const uint32_t it = __builtin_amdgcn_readfirstlane(bc.chunk_item[g]);
+        if (it == BIG_NONE) continue;
+        const BigItem& bi = bc.items[it];
+        const uint32_t kind = bi.kind;
+        if (kind != BK_COPY && kind != BK_ONE && kind != BK_PASSH) continue;
+        // the deleted set: every 2^sh-th entry in this wave's LDS slice
+        const uint32_t* X = xs + bi.xoff;
+        const uint32_t N = bi.N;
+        uint32_t sh = 0;
+        while ((N >> sh) >= BIG_WXL) ++sh;
+        const uint32_t nl = (N + (1u << sh) - 1) >> sh;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t j = lane; j < nl; j += 64) xl[j] = X[(uint64_t)j << sh];
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        const XView xv{X, xl, N, nl, sh};
+        const uint32_t p0 = (uint32_t)(g - bi.cbase) * bi.csize;
+        const uint32_t p1 = std::min(p0 + bi.csize, bi.n);
+        if (kind == BK_COPY) {
+            const uint64_t* eo = reinterpret_cast<const uint64_t*>(pool + bi.a);
+            const uint32_t* qo = pool + bi.a + 2ull * bi.ocap;
+            uint64_t* en = reinterpret_cast<uint64_t*>(pool + bi.b);
+            uint32_t* qn = pool + bi.b + 2ull * bi.ncap;
+            for (uint32_t q0 = p0; q0 < p1; q0 += 64 * 4) {
+                uint64_t e[4];
+                uint32_t q[4];
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t p = q0 + j * 64 + lane;
+                    if (p < p1) { e[j] = eo[p]; q[j] = qo[p]; }
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t p = q0 + j * 64 + lane;
+                    if (p < p1 && !xv_in(xv, p)) { en[p] = e[j]; qn[p] = q[j]; }
+                }
+            }
+        } else if (kind == BK_ONE) {
+            uint32_t first = NF;
+            for (uint32_t q0 = p0; q0 < p1; q0 += 64) {
+                const uint32_t p = q0 + lane;
+                bool hit = false;
+                if (p < p1) {
+                    uint64_t w0, w1;
+                    uint32_t r;
+                    big_load(bi, p, pool, w0, w1);
+                    hit = big_eval(bi, p, w0, w1, xv, &r);
+                }
+                const uint64_t b = __ballot(hit);
+                if (b) { first = q0 + (uint32_t)(__ffsll((long long)b) - 1); break; }
+            }
+            if (lane == 0 && first != NF) atomicMin(hdr + (size_t)bi.u * HDR_WORDS + H_INFO + bi.k, first);
         } else {
             const uint32_t* Lold = pool + bi.a;
             uint32_t* Lnew = pool + bi.b;
-            const uint32_t* S = bc.sur + bi.sur;
-            for (uint32_t p = q0; p < q1; ++p) {
-                const uint32_t e = Lold[p];
-                uint32_t val;
-                if (in_set(X, bi.N, e)) val = S[r++];
-                else val = rho(e, X, bi.N, bi.dn, bi.nholes);
-                if (val != e || bi.reloc) Lnew[p] = val;
+            uint32_t* H = bc.sur + bi.hole;
+            unsigned long long* hc = &bc.items[it].hcnt;
+            const uint32_t dn = bi.dn, nholes = bi.nholes, nh = bi.nh;
+            const bool moved = bi.reloc != 0;
+            for (uint32_t q0 = p0; q0 < p1; q0 += 64 * BIG_TPT) {
+                uint32_t e[BIG_TPT];
+#pragma unroll
+                for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                    const uint32_t p = q0 + j * 64 + lane;
+                    e[j] = p < p1 ? Lold[p] : 0u;
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < BIG_TPT; ++j) {
+                    const uint32_t p = q0 + j * 64 + lane;
+                    const uint32_t r = p < p1 ? xv_rho(xv, e[j], dn, nholes) : 0u;
+                    const bool hole = p < p1 && r == NF;
+                    const uint64_t hb = __ballot(hole);
+                    if (hb) {
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(hc, (unsigned long long)__popcll(hb));
+                        base = __shfl(base, 0, 64);
+                        const uint64_t slot = base + __popcll(hb & lanemask_lt());
+                        if (hole && slot < nh) H[slot] = p;
+                    }
+                    if (p < p1 && !hole && (r != e[j] || moved)) Lnew[p] = r;
+                }
             }
         }
-        __syncthreads();  // wsum is reused by the next chunk
+    }
+}
+
+// Split work, the holes of BK_PASSH lists: one block per item sorts the hole
+// positions (at most BIG_HOLES) in LDS; the i-th hole takes tail survivor i.
+__global__ void __launch_bounds__(256) k_big_holes(const unsigned long long* __restrict__ uc, BigCtx bc,
+                                                   uint32_t* __restrict__ pool) {
+    __shared__ uint32_t hs[BIG_HOLES];
+    const uint64_t nitems = std::min<uint64_t>(uc[UC_BIG_ITEMS], bc.imax);
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BigItem& bi = bc.items[it];
+        if (bi.kind != BK_PASSH) continue;
+        const uint32_t nh = (uint32_t)std::min<unsigned long long>(bi.nh, bi.hcnt);
+        if (nh == 0) continue;
+        uint32_t P = 1;
+        while (P < nh) P <<= 1;
+        const uint32_t* H = bc.sur + bi.hole;
+        const uint32_t* S = bc.sur + bi.sur;
+        uint32_t* L = pool + bi.b;
+        __syncthreads();  // the previous item is done with hs
+        for (uint32_t i = threadIdx.x; i < P; i += 256) hs[i] = i < nh ? H[i] : 0xFFFFFFFFu;
+        __syncthreads();
+        // bitonic sort, ascending
+        for (uint32_t k2 = 2; k2 <= P; k2 <<= 1) {
+            for (uint32_t j = k2 >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = threadIdx.x; i < P; i += 256) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint32_t a = hs[i], b = hs[ixj];
+                        if ((a > b) == ((i & k2) == 0)) { hs[i] = b; hs[ixj] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < nh; i += 256) L[hs[i]] = S[i];
     }
 }
 
@@ -1204,7 +1486,7 @@ struct UpdPlan {
     uint32_t *is = nullptr, *id = nullptr, *iw = nullptr, *ds = nullptr, *dd = nullptr;  // staged inputs
     unsigned long long* uc = nullptr;
     uint64_t *keys, *sk, *hx, *fsz, *foff, *ckey, *cks, *xk, *xks, *needw, *aoff, *xoff;
-    uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold;
+    uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold, *wv, *idest, *blist;
     unsigned long long* parts;
     BigItem* big_items;
     uint32_t *chunk_item, *ccnt, *bsur;
@@ -1221,9 +1503,11 @@ struct UpdPlans {
 };
 
 static constexpr uint32_t MATCH_GRID = 2048;
-static constexpr uint32_t BIG_IMAX = 16384;
-static constexpr uint32_t BIG_CMAX = 1u << 18;
-static constexpr uint32_t BIG_SMAX = 1u << 22;
+static constexpr uint32_t BIG_IMAX = 65536;
+static constexpr uint32_t BIG_CMAX = 1u << 19;
+// survivor words for deferred pass-A lists: a hub's group windows hold about
+// popcount(weight) entries per deleted edge, so the buffer scales with the bucket
+static uint64_t big_smax(uint64_t R) { return std::min<uint64_t>(std::max<uint64_t>(1ull << 22, 4 * R), 1ull << 31); }
 static constexpr uint32_t BIG_GRID = 2048;
 static constexpr size_t PLAN_CACHE_BYTES = 16ull << 30;
 
@@ -1240,9 +1524,9 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     const uint64_t R = rmax, C = cmax;
     const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)),
                                  scan_temp_bytes(R + 1));
-    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 10 + al(C * 8) * 2 + al(R * 4) * 13 +
+    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 10 + al(C * 8) * 2 + al(R * 4) * 16 +
                          al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + al(BIG_IMAX * sizeof(BigItem)) +
-                         2 * al(BIG_CMAX * 4) + al(BIG_SMAX * 4) + tmpb + 4096;
+                         2 * al(BIG_CMAX * 4) + al(big_smax(R) * 4) + tmpb + 4096;
     UpdPlan* p = new UpdPlan();
     p->rmax = R;
     p->cmax = C;
@@ -1263,13 +1547,16 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->tdl = (uint32_t*)take(R * 4); p->te = (uint32_t*)take(R * 4); p->first = (uint32_t*)take(R * 4);
     p->matched = (uint32_t*)take(R * 4); p->xs = (uint32_t*)take(R * 4); p->ncnt = (uint32_t*)take(R * 4);
     p->dold = (uint32_t*)take(R * 4);
+    p->wv = (uint32_t*)take(R * 4);
+    p->idest = (uint32_t*)take(R * 4);
+    p->blist = (uint32_t*)take(R * 4);
     p->sur = (uint32_t*)take(R * 8);
     p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
     p->parts = (unsigned long long*)take(PART_BLOCKS * 32 * 8);
     p->big_items = (BigItem*)take(BIG_IMAX * sizeof(BigItem));
     p->chunk_item = (uint32_t*)take(BIG_CMAX * 4);
     p->ccnt = (uint32_t*)take(BIG_CMAX * 4);
-    p->bsur = (uint32_t*)take(BIG_SMAX * 4);
+    p->bsur = (uint32_t*)take(big_smax(R) * 4);
     p->tmp = w;
     return p;
 }
@@ -1304,8 +1591,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                        p->head, p->hx, p->tv, p->tsa, p->tdl, p->rec_t);
     hipLaunchKernelGGL(k_seg_end, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, p->tsa, p->te,
                        p->tdl);
-    hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->tv,
-                       p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold);
+    hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, uc, R, p->tv,
+                       p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold, g->update_split, p->blist);
     scan_u64(p->fsz, p->foff, R, p->tmp, uc + UC_F, st);
     // 2. delete matching: candidates, sorted by (run, seq); the k oldest per run
     hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tv, p->tsa, p->tdl, p->te, p->sk,
@@ -1324,33 +1611,39 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     sort_keys_u64(p->xk, p->xks, R, cbits, p->tmp, st);
     hipLaunchKernelGGL(k_xextract, dim3(grid_for(R)), dim3(TB), 0, st, R, p->xks, p->xs);
     scan_u32_to_u64(p->ncnt, p->xoff, R, p->tmp, uc + UC_X, st);
+    hipLaunchKernelGGL(k_ins_prep, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, R, p->sv, p->iw,
+                       p->rec_t, p->tsa, p->tdl, p->dold, p->ncnt, p->xoff, p->xs, p->wv, p->idest);
     // 4. analysis and one bump allocation
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R)), dim3(TB), 0, st, p->needw, R, 0ull);
     hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, p->tv, p->tsa, p->tdl,
-                       p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->iw, g->rule, p->needw, p->parts);
+                       p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->wv, g->rule, p->needw, p->parts);
     hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
                        uc + UC_STATS, 0);
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
     // 5. mutation (a no-op for a rejected batch)
-    BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, BIG_SMAX};
+    BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, (uint32_t)big_smax(R)};
     const uint32_t split = g->update_split;
-    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err,
-                       p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
-                       g->rule, p->aoff, p->sur, p->parts, p->dold, bc, split);
+    const MutArgs ma{p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->wv,
+                     p->idest, p->aoff, p->sur, g->rule};
+    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
+                       (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
     hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
                        uc + UC_FREED, 0);
     if (split) {
         // vertices with more than `split` entries, then the passes they handed over
-        hipLaunchKernelGGL((k_mutate<true>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err,
-                           p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->iw,
-                           g->rule, p->aoff, p->sur, p->parts, p->dold, bc, split);
-        hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+        const uint32_t sgrid = (uint32_t)std::min<uint64_t>(R, PART_BLOCKS);
+        hipLaunchKernelGGL((k_mutate<true>), dim3(sgrid), dim3(64), XL_WORDS * 4, st, uc, (const uint32_t*)err, ma,
+                           p->parts, (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
+        hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, sgrid,
                            uc + UC_FREED, 1);
+        hipLaunchKernelGGL(k_big_pass, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
+                           (const uint32_t*)p->xs, g->pool, g->hdr);
         hipLaunchKernelGGL(k_big_count, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
                            (const uint32_t*)p->xs, (const uint32_t*)g->pool, p->ccnt);
         hipLaunchKernelGGL(k_big_apply, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
-                           (const uint32_t*)p->xs, g->pool, g->hdr, (const uint32_t*)p->ccnt);
+                           (const uint32_t*)p->xs, g->pool, (const uint32_t*)p->ccnt);
+        hipLaunchKernelGGL(k_big_holes, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc, g->pool);
     }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
 }
