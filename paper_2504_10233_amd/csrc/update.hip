@@ -194,9 +194,10 @@ __device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, ui
 // targets becomes a candidate (run << 32 | seq, virtual index).  The grid loops
 // over ranges of MB elements.  A range stages what its elements look up: the
 // offsets and header fields of the (at most MV) touched vertices it spans and
-// the dst of their batch records, so the per-element vertex search and target
-// search run in LDS; a range that spans more vertices or records than that
-// searches global memory instead.  Hits collect in an LDS buffer that is
+// the dst of their batch records (every 2^sh-th record when there are more than
+// LDS_TARGETS), so the per-element vertex search and target search run in LDS
+// but for at most sh steps; a range that spans more vertices than MV searches
+// them in global memory instead.  Hits collect in an LDS buffer that is
 // written out (one atomic per flush) when it could not take another range, so
 // the global atomics number about one per OUTCAP hits, not one per range.
 constexpr uint32_t LDS_TARGETS = 2048;
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
     __shared__ uint32_t tgt[LDS_TARGETS];
     __shared__ uint64_t okey[OUTCAP];
     __shared__ uint32_t oidx[OUTCAP];
-    __shared__ uint32_t range[4];  // tlo, thi, record base, staged flags
+    __shared__ uint32_t range[5];  // tlo, thi, record base, staged flags, target sample shift
     __shared__ uint32_t wtot[TB / 64];
     __shared__ uint32_t ocount;
     __shared__ uint32_t reuse;
@@ -278,14 +279,17 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
             if (threadIdx.x == 0) {
                 const uint32_t tlo = range[0], thi = range[1];
                 const uint32_t rb = ts[tlo], re = te[thi];
+                uint32_t sh = 0;
+                while (((re - rb) + (1u << sh) - 1) >> sh > LDS_TARGETS) ++sh;
                 range[2] = rb;
-                range[3] = (thi - tlo < MV ? 1u : 0u) | (re - rb <= LDS_TARGETS ? 2u : 0u);
+                range[3] = (thi - tlo < MV ? 1u : 0u) | 2u;
+                range[4] = sh;
                 vend = thi + 1 < T ? foff[thi + 1] : F;  // end of the last vertex's elements
             }
             __syncthreads();
         }
-        const uint32_t tlo = range[0], thi = range[1], rbase = range[2];
-        const bool vstaged = range[3] & 1u, tstaged = (range[3] & 2u) != 0;
+        const uint32_t tlo = range[0], thi = range[1], rbase = range[2], tsh = range[4];
+        const bool vstaged = range[3] & 1u;
         const uint32_t nv = thi - tlo + 1;
         if (vstaged && !reuse) {
             for (uint32_t k = threadIdx.x; k < nv; k += TB) {
@@ -297,9 +301,9 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                 s_v[5][k] = ts[t]; s_v[6][k] = tdl[t]; s_v[7][k] = te[t];
             }
         }
-        if (tstaged && !reuse) {
-            const uint32_t re = te[thi];
-            for (uint32_t p = rbase + threadIdx.x; p < re; p += TB) tgt[p - rbase] = key_dst(sk[p], vb);
+        if (!reuse) {
+            const uint32_t ns = (te[thi] - rbase + (1u << tsh) - 1) >> tsh;
+            for (uint32_t j = threadIdx.x; j < ns; j += TB) tgt[j] = key_dst(sk[rbase + (j << tsh)], vb);
         }
         __syncthreads();
         // each thread looks at PER elements; hits stay in registers until the
@@ -330,30 +334,26 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                     tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
                 }
                 const uint32_t i = (uint32_t)(f - fo);
-                uint32_t dst, seq;
-                if (i < d) {
-                    dst = pool[adj + 2ull * i];
-                    seq = pool[adj + 2ull * acap + i];
-                } else {
-                    const uint32_t a = i - d;
-                    dst = id[sv[tsv + a]];
-                    seq = nseq + a;
+                const uint32_t dst = i < d ? pool[adj + 2ull * i] : id[sv[tsv + (i - d)]];
+                // lower bound of dst among the vertex's delete targets [tdlv, tev): first over
+                // the LDS samples at positions rbase + (j << tsh) inside [tdlv, tev), then
+                // over the records between two samples in global memory
+                const uint32_t jl = (tdlv - rbase + (1u << tsh) - 1) >> tsh;
+                const uint32_t jr = (tev - rbase + (1u << tsh) - 1) >> tsh;
+                uint32_t ja = jl, jb = jr;
+                while (ja < jb) {
+                    const uint32_t mid = (ja + jb) >> 1;
+                    if (tgt[mid] < dst) ja = mid + 1; else jb = mid;
                 }
-                // lower bound of dst among the vertex's delete targets [tdlv, tev)
-                uint32_t l = tdlv, rr = tev;
-                if (tstaged) {
-                    while (l < rr) {
-                        const uint32_t mid = (l + rr) >> 1;
-                        if (tgt[mid - rbase] < dst) l = mid + 1; else rr = mid;
-                    }
-                } else {
-                    while (l < rr) {
-                        const uint32_t mid = (l + rr) >> 1;
-                        if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
-                    }
+                uint32_t l = ja > jl ? rbase + ((ja - 1) << tsh) + 1 : tdlv;
+                uint32_t rr = ja < jr ? rbase + (ja << tsh) : tev;
+                while (l < rr) {
+                    const uint32_t mid = (l + rr) >> 1;
+                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
                 }
-                const bool found = l < tev && (tstaged ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
+                const bool found = l < tev && (tsh == 0 ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
                 if (found) {
+                    const uint32_t seq = i < d ? pool[adj + 2ull * acap + i] : nseq + (i - d);
                     hkey[nh] = ((uint64_t)l << 32) | seq;
                     hidx[nh] = i;
                     ++nh;
