@@ -18,6 +18,9 @@
  *     groups (Sec. 5.1, Eq. eq:group, alpha = 40, beta = 10);
  *   - the two-stage sampling step (Sec. 4.1, Eq. eq:group_prob and eq:pvp)
  *     with rejection on the adjacency for dense groups (Sec. 5.1);
+ *   - floating-point biases (Sec. 4.3, Fig. SAMPLING2): scaling by the
+ *     amortization factor lambda, an integer part decomposed into radix
+ *     groups and a decimal part collected in one group sampled by rejection;
  *   - DeepWalk and personalized-PageRank walks (Sec. 2.2 and Sec. 6.1);
  *   - node2vec second-order walks by rejection on the first-order sampler
  *     (Sec. 2.2, Eq. node2vec; the KnightKing approach the paper adopts);
@@ -35,6 +38,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdio.h>
+#include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -232,8 +236,47 @@ typedef struct {
     uint32_t n;
     int adaptive;
     uint32_t alpha, beta;
+    uint32_t fbits;    /* 0: integer biases; F > 0: fixed-point biases with F fraction bits */
     ovtx *v;
 } ograph;
+
+/* ------------------------------------------------------------------------ */
+/* Floating-point biases (Sec. 4.3, Fig. SAMPLING2).  Readings fixed here:   */
+/*  - a bias b becomes the stored weight floor(lambda * b * 2^F): lambda * b */
+/*    is one IEEE double product rounded to nearest, the scaling by 2^F is   */
+/*    exact; a result that is not finite, negative, zero or not below 2^32  */
+/*    is stored as 0, which the build and the update reject as a bad weight; */
+/*  - the integer part (bits F..31) is radix-decomposed like an integer     */
+/*    bias: group k >= F holds the edges with bit k set, total c_k 2^k;     */
+/*  - the decimal part q = weight mod 2^F puts the edge in the decimal group */
+/*    (slot 0) when q > 0; the group's total is the sum of its q;           */
+/*    slots 1..F-1 stay empty;                                               */
+/*  - inter-group selection draws r in [0, W) (W = sum of the weights) and   */
+/*    takes the integer groups in ascending k, the decimal group last;       */
+/*  - inside the decimal group, by its type: the one member; or a candidate  */
+/*    drawn uniformly from the list (listed types) or the whole adjacency   */
+/*    (dense), accepted when the top F bits of the next word are below its  */
+/*    q, else a new candidate (rejection with bound 2^F).                    */
+/* With F = 0 everything reduces to the integer case.                        */
+/* ------------------------------------------------------------------------ */
+uint32_t o_quantize_one(float b, double lambda, uint32_t F) {
+    double s = (double)b * lambda;
+    if (!(s >= 0.0) || isinf(s)) return 0;
+    double t = ldexp(s, (int)F);
+    if (!(t < 4294967296.0)) return 0;
+    return (uint32_t)t;
+}
+
+void o_quantize(uint64_t m, const float *b, double lambda, uint32_t F, uint32_t *out) {
+    for (uint64_t i = 0; i < m; i++) out[i] = o_quantize_one(b[i], lambda, F);
+}
+
+/* Group membership word of a stored weight: bit k says "member of group k". */
+static uint32_t mword(const ograph *G, uint32_t w) {
+    if (!G->fbits) return w;
+    uint32_t fm = (1u << G->fbits) - 1u;
+    return (w & ~fm) | ((w & fm) ? 1u : 0u);
+}
 
 static void *xrealloc(void *p, size_t sz) {
     void *q = realloc(p, sz ? sz : 1);
@@ -264,22 +307,21 @@ static void list_clear(ogroup *g) { free(g->list); g->list = NULL; g->len = g->c
 /* Fresh structure of group k of vertex x from its adjacency: listed groups
  * hold the member indices in ascending order; a one-element group keeps its
  * single member; dense and empty groups keep nothing. */
-static void group_fresh(ovtx *x, int k) {
+static void group_fresh(const ograph *G, ovtx *x, int k) {
     ogroup *g = &x->g[k];
     list_clear(g);
     g->one = 0;
     if (g->type == T_ONE) {
-        for (uint32_t i = 0; i < x->d; i++) if (x->w[i] >> k & 1u) { g->one = i; break; }
+        for (uint32_t i = 0; i < x->d; i++) if (mword(G, x->w[i]) >> k & 1u) { g->one = i; break; }
     } else if (listed(g->type)) {
-        for (uint32_t i = 0; i < x->d; i++) if (x->w[i] >> k & 1u) list_push(g, i);
+        for (uint32_t i = 0; i < x->d; i++) if (mword(G, x->w[i]) >> k & 1u) list_push(g, i);
     }
 }
 
 static void vertex_recount(ograph *G, ovtx *x, uint32_t c[32]) {
-    (void)G;
     for (int k = 0; k < 32; k++) c[k] = 0;
     for (uint32_t i = 0; i < x->d; i++)
-        for (int k = 0; k < 32; k++) c[k] += x->w[i] >> k & 1u;
+        for (int k = 0; k < 32; k++) c[k] += mword(G, x->w[i]) >> k & 1u;
 }
 
 static void vertex_fresh(ograph *G, ovtx *x) {
@@ -288,7 +330,7 @@ static void vertex_fresh(ograph *G, ovtx *x) {
     for (int k = 0; k < 32; k++) {
         x->g[k].c = c[k];
         x->g[k].type = (uint8_t)o_type(c[k], x->d, G->adaptive, G->alpha, G->beta);
-        group_fresh(x, k);
+        group_fresh(G, x, k);
     }
 }
 
@@ -307,15 +349,15 @@ void o_free(ograph *G) {
  * their input order; seq of an edge is its rank among u's edges, and the
  * per-vertex sequence counter starts at d. */
 int o_build(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
-            int adaptive, uint32_t alpha, uint32_t beta, ograph **out) {
+            int adaptive, uint32_t alpha, uint32_t beta, uint32_t fbits, ograph **out) {
     *out = NULL;
-    if (n == 0) return O_EINVAL;
+    if (n == 0 || fbits > 16) return O_EINVAL;
     for (uint64_t e = 0; e < m; e++) {
         if (src[e] >= n || dst[e] >= n) return O_ERANGE;
         if (w[e] == 0) return O_EWEIGHT;
     }
     ograph *G = calloc(1, sizeof(ograph));
-    G->n = n; G->adaptive = adaptive; G->alpha = alpha; G->beta = beta;
+    G->n = n; G->adaptive = adaptive; G->alpha = alpha; G->beta = beta; G->fbits = fbits;
     G->v = calloc(n, sizeof(ovtx));
     if (!G->v) { free(G); return O_ENOMEM; }
     uint32_t *deg = calloc(n, 4);
@@ -350,9 +392,37 @@ static uint32_t step_from(const ograph *G, uint32_t u, ostream *s, int ppr, uint
     if (ppr && st_next32(s) < thr) return STOPV;
     uint64_t W = 0;
     uint32_t c[32];
-    for (int k = 0; k < 32; k++) { c[k] = x->g[k].c; W += (uint64_t)c[k] << k; }
-    uint64_t r = st_below64(s, W);
-    int k = o_pick_group(c, r);
+    int k;
+    if (!G->fbits) {
+        for (int j = 0; j < 32; j++) { c[j] = x->g[j].c; W += (uint64_t)c[j] << j; }
+        uint64_t r = st_below64(s, W);
+        k = o_pick_group(c, r);
+    } else {
+        /* integer groups F..31 ascending, then the decimal group (slot 0) */
+        const uint32_t F = G->fbits, fm = (1u << F) - 1u;
+        for (uint32_t i = 0; i < x->d; i++) W += x->w[i];
+        uint64_t r = st_below64(s, W), acc = 0;
+        k = 0;
+        for (int j = (int)F; j < 32; j++) {
+            acc += (uint64_t)x->g[j].c << j;
+            if (r < acc) { k = j; break; }
+        }
+        if (k == 0) {
+            const ogroup *g = &x->g[0];
+            uint32_t i;
+            if (g->type == T_ONE) {
+                i = g->one;
+            } else {
+                for (;;) {
+                    i = listed(g->type) ? g->list[st_below32(s, g->c)] : st_below32(s, x->d);
+                    if (st) st->dense_attempts++;
+                    if ((st_next32(s) >> (32 - F)) < (x->w[i] & fm)) break;
+                }
+            }
+            if (st) { st->steps++; st->sel[g->type]++; }
+            return x->dst[i];
+        }
+    }
     const ogroup *g = &x->g[k];
     uint32_t i;
     if (g->type == T_ONE) {
@@ -760,13 +830,13 @@ int o_update(ograph *G, uint64_t nI, const uint32_t *Isrc, const uint32_t *Idst,
         for (uint32_t i = 0; i < d1; i++) N += del[i];
         uint32_t d2 = d1 - N;
         for (int k = 0; k < 32; k++) nc[k] = 0;
-        for (uint32_t i = 0; i < d1; i++) if (!del[i]) for (int k = 0; k < 32; k++) nc[k] += x->w[i] >> k & 1u;
+        for (uint32_t i = 0; i < d1; i++) if (!del[i]) for (int k = 0; k < 32; k++) nc[k] += mword(G, x->w[i]) >> k & 1u;
         for (int k = 0; k < 32; k++) newt[k] = (uint8_t)o_type(nc[k], d2, G->adaptive, G->alpha, G->beta);
 
         /* 3. kept listed groups: append the new member indices, ascending */
         for (int k = 0; k < 32; k++) {
             if (!(listed(oldt[k]) && newt[k] == oldt[k])) continue;
-            for (uint32_t i = d0; i < d1; i++) if (x->w[i] >> k & 1u) list_push(&x->g[k], i);
+            for (uint32_t i = d0; i < d1; i++) if (mword(G, x->w[i]) >> k & 1u) list_push(&x->g[k], i);
         }
 
         /* 4. two-phase delete-and-swap on the adjacency; rho maps moved indices */
@@ -799,7 +869,7 @@ int o_update(ograph *G, uint64_t nI, const uint32_t *Isrc, const uint32_t *Idst,
             int keep = listed(oldt[k]) && newt[k] == oldt[k];
             g->c = nc[k];
             g->type = newt[k];
-            if (!keep) group_fresh(x, k);
+            if (!keep) group_fresh(G, x, k);
             st[3 + oldt[k] * 5 + newt[k]]++;
         }
         free(del); free(perm); free(mf); free(mt); free(rho);
@@ -865,7 +935,11 @@ void o_memory(const ograph *G, uint64_t out[9]) {
         uint32_t smask = 0;
         for (int k = 0; k < 32; k++) if (x->g[k].type == T_SPARSE) smask |= 1u << k;
         uint64_t S = 0, popc = 0;
-        for (uint32_t i = 0; i < x->d; i++) { if (x->w[i] & smask) S++; popc += (uint64_t)__builtin_popcount(x->w[i]); }
+        for (uint32_t i = 0; i < x->d; i++) {
+            const uint32_t mw = mword(G, x->w[i]);
+            if (mw & smask) S++;
+            popc += (uint64_t)__builtin_popcount(mw);
+        }
         for (int k = 0; k < 32; k++) {
             const ogroup *g = &x->g[k];
             switch (g->type) {
