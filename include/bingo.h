@@ -59,6 +59,16 @@ typedef struct {
     uint32_t alpha_pct;     /* dense threshold alpha in percent (paper: 40) */
     uint32_t beta_pct;      /* sparse threshold beta in percent (paper: 10) */
     uint64_t pool_bytes;    /* device arena for adjacency and group lists; 0 = sized from the input */
+    uint32_t frac_bits;     /* 0: integer biases.  F in 1..16: every weight is a fixed-point bias with
+                               F fraction bits (Sec. 4.3, see bingo_quantize_biases): bits F..31 are
+                               its integer part, decomposed into radix groups F..31; a nonzero
+                               fraction (weight mod 2^F) puts the edge in the decimal group, kept in
+                               slot 0 with total sum(fraction); slots 1..F-1 stay empty.  A walk step
+                               draws r in [0, sum of weights), takes the integer groups in ascending
+                               k and the decimal group last; inside the decimal group a candidate
+                               (from its list, or the whole adjacency when it is dense) is accepted
+                               when the top F bits of the next random word are below its fraction. */
+    uint32_t reserved;      /* 0 */
 } bingo_config;
 
 typedef struct {
@@ -98,6 +108,22 @@ typedef struct {
 int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m,
                 const uint32_t* d_src, const uint32_t* d_dst, const uint32_t* d_w,
                 void* stream, bingo_graph** out);
+
+/*
+ * bingo_quantize_biases -- floating-point biases as stored weights (Sec. 4.3:
+ * amortization factor lambda, integer and decimal parts).
+ *   d_bias      m device float32 biases.
+ *   lambda      the amortization factor (> 0, finite).
+ *   frac_bits   F, 1..16: fraction bits kept (resolution 2^-F of lambda * b).
+ *   d_w         m device uint32 outputs: floor(lambda * b * 2^F), with lambda * b
+ *               one IEEE double product rounded to nearest; 0 where that is not
+ *               a number in [1, 2^32) (negative, not finite, too small or too
+ *               large), which bingo_build / bingo_update_batch then reject as a
+ *               zero weight.
+ * Build the graph with bingo_config.frac_bits = F.  Asynchronous.
+ */
+int bingo_quantize_biases(uint64_t m, const float* d_bias, double lambda, uint32_t frac_bits, uint32_t* d_w,
+                          void* stream);
 
 /*
  * bingo_update_batch -- apply one batch of edge insertions and deletions

@@ -32,7 +32,8 @@ class BingoError(RuntimeError):
 
 class _Config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("adaptive", C.c_uint32), ("alpha_pct", C.c_uint32),
-                ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64)]
+                ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64), ("frac_bits", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class _UpdateStats(C.Structure):
@@ -54,7 +55,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
-           "bingo_probe_random_reads", "bingo_node2vec"]
+           "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases"]
 
 
 class _ServerConfig(C.Structure):
@@ -106,6 +107,7 @@ def load():
         L.bingo_server_wait.argtypes = [vp, u64, vp, u64, C.POINTER(_RequestInfo)]
         L.bingo_server_destroy.argtypes = [vp]
         L.bingo_probe_random_reads.argtypes = [vp, u64, u32, u32, u32, u32, u64, vp, C.POINTER(C.c_float), vp]
+        L.bingo_quantize_biases.argtypes = [u64, vp, C.c_double, u32, vp, vp]
         L.bingo_num_vertices.argtypes = [vp]
         L.bingo_num_vertices.restype = u32
         L.bingo_destroy.argtypes = [vp]
@@ -128,6 +130,19 @@ def probe_random_reads(table, lanes, reads, dependent, line_bytes=64, seed=1, st
     n = lanes * reads
     return {"ms": ms.value, "lines_per_s": n / (ms.value / 1e3), "GBps": n * line_bytes / (ms.value / 1e3) / 1e9,
             "lanes": lanes, "reads_per_lane": reads, "dependent": bool(dependent), "line_bytes": line_bytes}
+
+
+def quantize_biases(bias, lam, frac_bits, out=None, stream=None):
+    """Float32 device biases -> uint32 fixed-point weights floor(lam * b * 2^F) (bingo_quantize_biases);
+    0 marks a bias that gives no weight in [1, 2^32)."""
+    import torch
+    if not isinstance(bias, torch.Tensor) or bias.dtype != torch.float32 or not bias.is_cuda:
+        raise TypeError("bias must be a float32 device tensor")
+    b = bias.contiguous()
+    w = out if out is not None else torch.empty(b.numel(), dtype=torch.int32, device=b.device)
+    _check(load().bingo_quantize_biases(b.numel(), _ptr(b), float(lam), frac_bits, _ptr(w), _stream(stream)),
+           "bingo_quantize_biases")
+    return w
 
 
 def ppr_threshold(p: float) -> int:
@@ -164,17 +179,19 @@ def _ptr(t):
 class Graph:
     """A dynamic graph with its radix-group sampling space resident in device memory."""
 
-    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None):
+    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None,
+                 frac_bits=0):
         L = load()
         self.device = torch.device(device)
         s, d, ww = as_u32(src, self.device), as_u32(dst, self.device), as_u32(w, self.device)
-        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes)
+        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes, frac_bits, 0)
         h = C.c_void_p()
         rc = L.bingo_build(C.byref(cfg), n, s.numel(), _ptr(s), _ptr(d), _ptr(ww), _stream(stream), C.byref(h))
         _check(rc, "bingo_build")
         self.h = h
         self.n = n
         self.adaptive = bool(adaptive)
+        self.frac_bits = frac_bits
 
     def close(self):
         if getattr(self, "h", None):

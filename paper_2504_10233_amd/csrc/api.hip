@@ -4,6 +4,7 @@
 #include <string.h>
 #include <new>
 #include <stdlib.h>
+#include <cmath>
 
 void* ws_get(bingo_graph* g, size_t bytes) {
     if (bytes <= g->ws_bytes && g->ws) return g->ws;
@@ -65,6 +66,7 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     if (n == 0 || n >= (1u << 31) || m >= (1ull << 32)) return BINGO_E_INVALID;
     if (m && (!d_src || !d_dst || !d_w)) return BINGO_E_INVALID;
     if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100) return BINGO_E_INVALID;
+    if (cfg->frac_bits > 16 || cfg->reserved != 0) return BINGO_E_INVALID;
     hipStream_t st = (hipStream_t)stream;
     bingo_graph* g = new (std::nothrow) bingo_graph();
     if (!g) return BINGO_E_OOM;
@@ -72,6 +74,7 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     g->rule.adaptive = cfg->adaptive;
     g->rule.alpha = cfg->alpha_pct;
     g->rule.beta = cfg->beta_pct;
+    g->rule.fbits = cfg->frac_bits;
     g->pool_words = cfg->pool_bytes / 4;
     g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr;
     if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
@@ -92,6 +95,13 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     }
     *out = g;
     return BINGO_OK;
+}
+
+int bingo_quantize_biases(uint64_t m, const float* d_bias, double lambda, uint32_t frac_bits, uint32_t* d_w,
+                          void* stream) {
+    if (m && (!d_bias || !d_w)) return BINGO_E_INVALID;
+    if (frac_bits < 1 || frac_bits > 16 || !(lambda > 0.0) || std::isinf(lambda)) return BINGO_E_INVALID;
+    return quantize_biases(m, d_bias, lambda, frac_bits, d_w, (hipStream_t)stream);
 }
 
 int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src, const uint32_t* d_ins_dst,

@@ -81,9 +81,12 @@ __global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __res
     const uint32_t lane = lane_id();
     const uint32_t b = start[u], d = start[u + 1] - b;
     uint32_t cnt = 0, last = 0;  // lane k < 32 owns bit k
+    uint64_t wraw = 0;           // this lane's share of sum(weights)
     for (uint32_t c0 = 0; c0 < d; c0 += 64) {
         const uint32_t i = c0 + lane;
-        const uint32_t wv = i < d ? cw[b + i] : 0u;
+        const uint32_t w = i < d ? cw[b + i] : 0u;
+        wraw += w;
+        const uint32_t wv = member_word(w, rule.fbits);
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             const uint64_t bal = __ballot((wv >> k) & 1u);
@@ -94,7 +97,8 @@ __global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __res
         }
     }
     const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
-    uint64_t wsum = lane < 32 ? ((uint64_t)cnt << lane) : 0ull;
+    // W = sum of the weights (= sum_k c_k 2^k for integer biases)
+    uint64_t wsum = wraw;
     uint64_t lw = type_listed(t) ? (uint64_t)list_cap_for(cnt) : 0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -168,9 +172,10 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
         const uint32_t i = c0 + lane;
         uint32_t wv = 0;
         if (i < d) {
-            wv = cw[b + i];
-            edges[i] = (uint64_t)cdst[b + i] | ((uint64_t)wv << 32);
+            const uint32_t w = cw[b + i];
+            edges[i] = (uint64_t)cdst[b + i] | ((uint64_t)w << 32);
             seqs[i] = i;
+            wv = member_word(w, rule.fbits);
         }
         uint32_t mm = lmask;
         while (mm) {
@@ -191,6 +196,22 @@ inline uint32_t grid_for(uint64_t n, uint32_t block) {
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1u << 20);
 }
 
+// Floating-point biases as fixed-point weights (Sec. 4.3): floor(lambda * b * 2^F)
+// with lambda * b one IEEE double product (round to nearest) and an exact
+// scaling by 2^F; 0 where the result is not a number in [1, 2^32).
+__global__ void k_quantize(uint64_t m, const float* __restrict__ b, double lambda, uint32_t F,
+                           uint32_t* __restrict__ w) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double s = (double)b[i] * lambda;
+        uint32_t q = 0;
+        if (s >= 0.0 && !isinf(s)) {
+            const double t = s * (double)(1u << F);
+            if (t < 4294967296.0) q = (uint32_t)t;
+        }
+        w[i] = q;
+    }
+}
+
 int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
     int b = 0;
     while (b < 64 && (v >> b)) ++b;
@@ -198,6 +219,12 @@ int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
 }
 
 }  // namespace
+
+int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st) {
+    if (m == 0) return BINGO_OK;
+    hipLaunchKernelGGL(k_quantize, dim3(grid_for(m, 256)), dim3(256), 0, st, m, b, lambda, F, w);
+    return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
+}
 
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st) {

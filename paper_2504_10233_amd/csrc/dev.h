@@ -50,7 +50,18 @@ enum { GT_EMPTY = 0, GT_ONE = 1, GT_DENSE = 2, GT_SPARSE = 3, GT_REGULAR = 4 };
 
 struct GroupRule {
     uint32_t adaptive, alpha, beta;
+    uint32_t fbits;  // 0: integer biases; F: fixed-point biases with F fraction bits (Sec. 4.3)
 };
+
+// Group membership word of a stored weight: bit k set = member of group k.
+// Integer biases: the weight itself.  Fixed-point biases with F fraction bits:
+// bits F..31 (the integer part's radix groups) and bit 0 for the decimal group
+// (a nonzero fraction); bits 1..F-1 are never set.
+__host__ __device__ inline uint32_t member_word(uint32_t w, uint32_t fbits) {
+    if (!fbits) return w;
+    const uint32_t fm = (1u << fbits) - 1u;
+    return (w & ~fm) | ((w & fm) != 0u ? 1u : 0u);
+}
 
 // Group type from (count, degree): empty, one element, dense above alpha %,
 // sparse below beta %, regular otherwise, in that order (Sec. 5.1).
@@ -255,6 +266,7 @@ void sort_pairs_u64_dn(const uint64_t* keys_in, const uint32_t* vals_in, uint64_
                        uint64_t nmax, const unsigned long long* dn, int bits, void* temp, hipStream_t st);
 
 // build.hip
+int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st);
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);
 // walk.hip

@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(WB) k_mem(const uint32_t* __restrict__ hdr, co
             const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
             for (uint32_t i0 = 0; i0 < d; i0 += 64) {
                 const uint32_t i = i0 + lane;
-                const bool in = i < d && ((uint32_t)(edges[i] >> 32) & smask);
+                const bool in = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask);
                 S += __popcll(__ballot(in));
             }
         }

@@ -32,9 +32,38 @@ __device__ __forceinline__ uint32_t dense_round(const uint64_t* __restrict__ edg
     return v;
 }
 
+// The decimal group of fixed-point biases (slot 0; Sec. 4.3): its members weigh
+// their fractions q = weight mod 2^F.  A one-element group returns its member;
+// otherwise a candidate is drawn uniformly from the group's list (listed types)
+// or from the whole adjacency (dense) and accepted when the top F bits of the
+// next random word are below its q.  Every member has q >= 1, so an attempt
+// accepts with probability at least 2^-F (at least alpha % of that for the
+// dense form); the attempt bound (2^24, with F <= 16) is never reached on a
+// consistent structure and only keeps a corrupted one from spinning.
+constexpr uint32_t DEC_MAX_ATTEMPTS = 1u << 24;
+
+__device__ __forceinline__ uint32_t decimal_pick(const uint32_t* __restrict__ h, const uint32_t* __restrict__ pool,
+                                                 uint64_t adj, uint32_t d, uint32_t c0, GroupRule rule,
+                                                 RandStream& rs) {
+    const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
+    const uint32_t t = group_type(c0, d, rule);
+    const uint32_t info = h[H_INFO];
+    if (t == GT_ONE) return (uint32_t)edges[info];
+    const uint32_t fm = (1u << rule.fbits) - 1u;
+    const uint64_t lst = (uint64_t)info * LIST_UNIT_WORDS;
+    for (uint32_t att = 0; att < DEC_MAX_ATTEMPTS; ++att) {
+        const uint32_t i = type_listed(t) ? pool[lst + rs_below32(rs, c0)] : rs_below32(rs, d);
+        const uint32_t x = rs_next32(rs) >> (32 - rule.fbits);
+        const uint64_t e = edges[i];
+        if (x < ((uint32_t)(e >> 32) & fm)) return (uint32_t)e;
+    }
+    return STOP_VERTEX;
+}
+
 // One transition from u (no termination test).  Returns the next vertex or
-// STOP_VERTEX for a vertex without out-edges.
-template <int SPEC>
+// STOP_VERTEX for a vertex without out-edges.  FB: the graph holds fixed-point
+// biases (rule.fbits > 0); the integer instance carries no decimal-group code.
+template <int SPEC, bool FB>
 __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t u, RandStream& rs, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
@@ -46,12 +75,15 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
     const uint64_t r = rs_below64(rs, W);
     const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
+    // groups in ascending k; fixed-point biases skip the slots below F (slot 0
+    // is their decimal group, taken last)
+    const uint32_t fb = FB ? rule.fbits : 0u;
     uint64_t acc = 0;
     int sel = -1;
     uint32_t csel = 0;
 #pragma unroll
     for (int k = 0; k < 26; ++k) {
-        acc += (uint64_t)c[k] << k;
+        if ((uint32_t)k >= fb) acc += (uint64_t)c[k] << k;
         if (sel < 0 && r < acc) { sel = k; csel = c[k]; }
     }
     if (sel < 0) {
@@ -64,6 +96,7 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
+    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], rule, rs);
     const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
     const uint32_t t = group_type(csel, d, rule);
     if (t == GT_DENSE) {

@@ -500,6 +500,7 @@ struct VState {
     uint64_t adj;
     uint32_t ts, ni, nd, N, xoff;
     uint32_t d1, dn;
+    uint64_t W;  // fixed-point biases: sum of the weights after the batch (unused for integer biases)
     // lane k < 32
     uint32_t c, cn, app, del, told, tnew, lcap, info;
 };
@@ -532,11 +533,16 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     s.info = lane < 32 ? h[H_INFO + lane] : 0u;
     s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
     s.told = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
-    // bit counts of the inserts and of the deleted entries
+    // group-membership counts of the inserts and of the deleted entries; for
+    // fixed-point biases also their weight sums (the decimal group's total is
+    // not a count times a power of two)
     uint32_t app = 0, del = 0;
+    uint64_t wadd = 0, wsub = 0;
     for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
         const uint32_t a = a0 + lane;
-        const uint32_t w = a < s.ni ? wv[s.ts + a] : 0u;
+        const uint32_t wr = a < s.ni ? wv[s.ts + a] : 0u;
+        wadd += wr;
+        const uint32_t w = member_word(wr, rule.fbits);
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             const uint64_t b = __ballot((w >> k) & 1u);
@@ -546,12 +552,23 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     const uint32_t* X = xs + s.xoff;
     for (uint32_t j0 = 0; j0 < s.N; j0 += 64) {
         const uint32_t j = j0 + lane;
-        const uint32_t w = j < s.N ? vweight(X[j], s, pool, wv) : 0u;
+        const uint32_t wr = j < s.N ? vweight(X[j], s, pool, wv) : 0u;
+        wsub += wr;
+        const uint32_t w = member_word(wr, rule.fbits);
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             const uint64_t b = __ballot((w >> k) & 1u);
             if (lane == (uint32_t)k) del += __popcll(b);
         }
+    }
+    s.W = 0;
+    if (rule.fbits) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            wadd += __shfl_xor(wadd, o);
+            wsub += __shfl_xor(wsub, o);
+        }
+        s.W = ((((uint64_t)h[H_WHI]) << 32) | h[H_WLO]) + wadd - wsub;
     }
     s.app = app; s.del = del;
     s.cn = s.c + app - del;
@@ -740,6 +757,7 @@ struct BigCtx {
     uint32_t* chunk_item;
     uint32_t* sur;  // tail survivors of deferred pass-A lists, smax words
     uint32_t imax, cmax, smax;
+    uint32_t fbits;  // fraction bits of fixed-point biases (membership words)
 };
 
 // Reserve an item and its chunks (every lane calls; the result is uniform).
@@ -855,6 +873,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     const uint32_t* __restrict__ wv = A.wv;
     const uint32_t* __restrict__ idest = A.idest;
     uint32_t* __restrict__ pool = A.pool;
+    const uint32_t fb = A.rule.fbits;
     VState s;
     load_state(s, (uint32_t)t, A.tv, A.ts, A.tdl, A.te, A.ncnt, A.xoff, A.xs, A.hdr, pool, wv, A.rule);
     const uint32_t lane = lane_id();
@@ -958,7 +977,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         uint32_t rank = 0;
         for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
             const uint32_t a = a0 + lane;
-            const bool v = a < s.ni && ((W[a] >> k) & 1u);
+            const bool v = a < s.ni && ((member_word(W[a], fb) >> k) & 1u);
             const uint64_t b = __ballot(v);
             if (b) {
                 const uint32_t p = ck + rank + __popcll(b & lanemask_lt());
@@ -984,7 +1003,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                 uint32_t r2 = 0;
                 for (uint32_t a0 = 0; a0 < s.ni && ck + r2 < cnk; a0 += 64) {
                     const uint32_t a = a0 + lane;
-                    const bool v = a < s.ni && ((W[a] >> k) & 1u);
+                    const bool v = a < s.ni && ((member_word(W[a], fb) >> k) & 1u);
                     const uint64_t b = __ballot(v);
                     const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
                     hnew += __popcll(__ballot(v && p < cnk && D[a] == NF));
@@ -1033,7 +1052,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
             uint32_t r2 = 0;
             for (uint32_t a0 = 0; a0 < s.ni && ck + r2 < cnk; a0 += 64) {
                 const uint32_t a = a0 + lane;
-                const bool v = a < s.ni && ((W[a] >> k) & 1u);
+                const bool v = a < s.ni && ((member_word(W[a], fb) >> k) & 1u);
                 const uint64_t b = __ballot(v);
                 const uint32_t p = ck + r2 + __popcll(b & lanemask_lt());
                 const bool inpre = v && p < cnk;
@@ -1066,7 +1085,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         for (uint32_t a0 = 0; a0 < s.ni; a0 += 64) {
             const uint32_t a = a0 + lane;
             const uint32_t dest = a < s.ni ? D[a] : NF;
-            const uint32_t w = dest != NF ? W[a] : 0u;
+            const uint32_t w = dest != NF ? member_word(W[a], fb) : 0u;
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
                 const uint64_t b = __ballot((w >> k) & 1u);
@@ -1107,7 +1126,8 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         for (uint32_t i0 = 0; i0 < s.dn; i0 += 64) {
             const uint32_t i = i0 + lane;
             uint32_t w = 0;
-            if (i < s.dn) w = (uint32_t)((SPLIT ? final_word_xv(i, enew, eold, reloc, keep, xv) : enew[i]) >> 32);
+            if (i < s.dn)
+                w = member_word((uint32_t)((SPLIT ? final_word_xv(i, enew, eold, reloc, keep, xv) : enew[i]) >> 32), fb);
             uint32_t mm = fm_seq | ns_seq;
             while (mm) {
                 const int k = __ffs(mm) - 1;
@@ -1130,7 +1150,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     // ---- header: the inter-group sampling space of the vertex
     uint32_t* h = A.hdr + (size_t)s.u * HDR_WORDS;
     const bool ne = lane < 32 && s.cn > 0;
-    const uint64_t wsum = wave_sum(ne ? ((uint64_t)s.cn << lane) : 0ull);
+    const uint64_t wsum = fb ? s.W : wave_sum(ne ? ((uint64_t)s.cn << lane) : 0ull);
     const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
     if (lane < 32) {
         h[H_CNT + lane] = s.cn;
@@ -1184,13 +1204,13 @@ __device__ __forceinline__ void big_load(const BigItem& bi, uint32_t p, const ui
     if (bi.reloc && p < bi.keep) w1 = reinterpret_cast<const uint64_t*>(pool + bi.aold)[p];
 }
 __device__ __forceinline__ bool big_eval(const BigItem& bi, uint32_t p, uint64_t w0, uint64_t w1, const XView& xv,
-                                         uint32_t* r) {
+                                         uint32_t* r, uint32_t fbits) {
     if (bi.kind == BK_PASSA) {
         *r = xv_rho(xv, (uint32_t)w0, bi.dn, bi.nholes);
         return *r == NF;
     }
     const uint64_t w = (bi.reloc && p < bi.keep && !xv_in(xv, p)) ? w1 : w0;
-    return (w >> (32 + bi.k)) & 1ull;
+    return (member_word((uint32_t)(w >> 32), fbits) >> bi.k) & 1u;
 }
 
 constexpr uint32_t BIG_TPT = 8;  // entries per thread per tile (tiles of 2048 entries)
@@ -1229,7 +1249,7 @@ __global__ void __launch_bounds__(256) k_big_count(const unsigned long long* __r
             for (uint32_t j = 0; j < BIG_TPT; ++j) {
                 const uint32_t p = q0 + j * 256 + threadIdx.x;
                 uint32_t r;
-                if (p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r)) ++c;
+                if (p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r, bc.fbits)) ++c;
             }
         }
 #pragma unroll
@@ -1292,7 +1312,7 @@ __global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __r
             for (uint32_t j = 0; j < BIG_TPT; ++j) {
                 const uint32_t p = q0 + j * 256 + threadIdx.x;
                 r[j] = 0;
-                const bool pr = p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r[j]);
+                const bool pr = p < p1 && big_eval(bi, p, w0[j], w1[j], xv, &r[j], bc.fbits);
                 b[j] = __ballot(pr);
                 if (lane == 0) wsum[j][wave] = (uint32_t)__popcll(b[j]);
             }
@@ -1382,7 +1402,7 @@ __global__ void __launch_bounds__(256) k_big_pass(const unsigned long long* __re
                     uint64_t w0, w1;
                     uint32_t r;
                     big_load(bi, p, pool, w0, w1);
-                    hit = big_eval(bi, p, w0, w1, xv, &r);
+                    hit = big_eval(bi, p, w0, w1, xv, &r, bc.fbits);
                 }
                 const uint64_t b = __ballot(hit);
                 if (b) { first = q0 + (uint32_t)(__ffsll((long long)b) - 1); break; }
@@ -1622,7 +1642,7 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
     // 5. mutation (a no-op for a rejected batch)
-    BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, (uint32_t)big_smax(R)};
+    BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, (uint32_t)big_smax(R), g->rule.fbits};
     const uint32_t split = g->update_split;
     const MutArgs ma{p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->wv,
                      p->idest, p->aoff, p->sur, g->rule};

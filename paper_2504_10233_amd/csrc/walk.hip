@@ -34,6 +34,7 @@ struct StepState {
     bool pending;
 };
 
+template <bool FB>
 __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                uint32_t u, StepState& ss, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
@@ -44,12 +45,15 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
     const uint64_t r = rs_below64(ss.rs, W);
     const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
+    // groups in ascending k; fixed-point biases skip the slots below F (slot 0
+    // is their decimal group, taken last)
+    const uint32_t fb = FB ? rule.fbits : 0u;
     uint64_t acc = 0;
     int sel = -1;
     uint32_t csel = 0;
 #pragma unroll
     for (int k = 0; k < 26; ++k) {
-        acc += (uint64_t)c[k] << k;
+        if ((uint32_t)k >= fb) acc += (uint64_t)c[k] << k;
         if (sel < 0 && r < acc) { sel = k; csel = c[k]; }
     }
     if (sel < 0) {
@@ -62,6 +66,7 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
+    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], rule, ss.rs);
     const uint32_t t = group_type(csel, d, rule);
     if (t == GT_DENSE) {
         ss.adj = adj; ss.d = d; ss.sel = (uint32_t)sel; ss.tries = 0; ss.pending = true;
@@ -83,7 +88,7 @@ __device__ __forceinline__ uint32_t step_attempt(const uint32_t* __restrict__ po
 }
 
 // ------------------------------------------------------------------ DeepWalk
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __restrict__ hdr,
                                                             const uint32_t* __restrict__ pool, uint32_t n,
                                                             uint64_t nw, const uint32_t* __restrict__ starts,
@@ -125,7 +130,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
             if (s < L) {
                 RandStream rs;
                 rs_init(rs, seed, base + j, s);
-                const uint32_t v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
+                const uint32_t v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
                 if (v == STOP_VERTEX) {
                     for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
                     j = NO_WALK;
@@ -142,7 +147,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __restrict__ hdr,
                                                              const uint32_t* __restrict__ pool, uint32_t n,
                                                              uint64_t nw, const uint32_t* __restrict__ starts,
@@ -184,7 +189,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
         uint32_t v = PENDING;
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
-            v = step_begin(hdr, pool, u, ss, rule);
+            v = step_begin<FB>(hdr, pool, u, ss, rule);
         }
         if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
@@ -203,7 +208,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                       uint32_t n, uint64_t nw, const uint32_t* __restrict__ starts,
                                                       uint64_t base, uint32_t L, uint32_t s, uint64_t seed,
@@ -225,7 +230,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
         if (u != STOP_VERTEX) {
             RandStream rs;
             rs_init(rs, seed, base + j, s);
-            v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
+            v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
             steps += (v != STOP_VERTEX);
         }
         row[s + 1] = v;
@@ -285,7 +290,7 @@ __global__ void __launch_bounds__(TB) k_ppr_bound(uint64_t nw, uint64_t base, ui
     }
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                        uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
@@ -327,7 +332,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
             RandStream rs;
             rs_init(rs, seed, base + j, s);
             rs_next32(rs);  // the termination word, known to be >= thr here
-            const uint32_t v = walk_step_body<SPEC>(hdr, pool, u, rs, rule);
+            const uint32_t v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                 j = NO_WALK;
@@ -343,7 +348,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                         uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                         uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
@@ -387,7 +392,7 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
             rs_next32(ss.rs);  // the termination word, known to be >= thr here
-            v = step_begin(hdr, pool, u, ss, rule);
+            v = step_begin<FB>(hdr, pool, u, ss, rule);
         }
         if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
@@ -415,7 +420,7 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // contiguous runs instead of one partial-sector store per lane.  A bin that
 // would overflow sets a flag and the query is rerun with exact per-walk
 // segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                    uint32_t R, uint64_t seed, uint64_t base, uint32_t thr,
@@ -465,7 +470,7 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 } else {
                     rs_init(ss.rs, seed, base + j, s);
                     if (rs_next32(ss.rs) < thr) j = NO_WALK;
-                    else v = step_begin(hdr, pool, u, ss, rule);
+                    else v = step_begin<FB>(hdr, pool, u, ss, rule);
                 }
             }
             if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
@@ -529,7 +534,7 @@ __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, con
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl[3] = nw;
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                  uint32_t R, uint32_t s, uint64_t seed, uint64_t base,
                                                  GroupRule rule, const uint64_t* __restrict__ seg,
@@ -554,7 +559,7 @@ __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hd
                 RandStream rs;
                 rs_init(rs, seed, base + id, s);
                 rs_next32(rs);
-                v = walk_step_body<SPEC>(hdr, pool, in_v[a], rs, rule);
+                v = walk_step_body<SPEC, FB>(hdr, pool, in_v[a], rs, rule);
                 const uint64_t p0 = seg[id], l = len[id];
                 if (v == STOP_VERTEX) {
                     for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) vis[x] = VPAD;
@@ -858,33 +863,33 @@ int bits_for(uint64_t v) {
     return b;
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 void deepwalk_kernels(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t L, uint64_t seed,
                       uint32_t* paths, uint32_t mode, unsigned long long* ctl, hipStream_t st) {
     if (mode == BINGO_WALK_PER_STEP) {
         const uint32_t grid = grid_for(nw);
         if (L == 0) {
             // only the start entries
-            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
         }
         for (uint32_t s = 0; s < L; ++s)
-            hipLaunchKernelGGL((k_deepwalk_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
+            hipLaunchKernelGGL((k_deepwalk_step<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
                                L, s, seed, paths, g->rule, ctl, g->d_err);
     } else {
-        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved<SPEC> : (const void*)k_deepwalk_persistent<SPEC>;
+        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved<SPEC, FB> : (const void*)k_deepwalk_persistent<SPEC, FB>;
         const int rg = resident_grid(kern, g->blocks_per_cu);
         const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
         if (g->walk_variant)
-            hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
         else
-            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
     }
 }
 
-template <int SPEC>
+template <int SPEC, bool FB>
 void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t cap, uint64_t seed,
                  uint64_t base, const uint64_t* seg, const uint32_t* len, uint32_t mode,
                  uint64_t* idA, uint32_t* vA, uint64_t* idB, uint32_t* vB, unsigned long long* ctl, uint32_t* vis,
@@ -897,19 +902,19 @@ void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_
         for (uint32_t s = 0; s < cap; ++s) {
             const int in_slot = s & 1;
             hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
-            hipLaunchKernelGGL((k_ppr_step<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base,
+            hipLaunchKernelGGL((k_ppr_step<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base,
                                g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
                                in_slot ? vA : vB, ctl, in_slot, vis);
         }
     } else {
-        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC> : (const void*)k_ppr_persistent<SPEC>;
+        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC, FB> : (const void*)k_ppr_persistent<SPEC, FB>;
         const int rg = resident_grid(kern, g->blocks_per_cu);
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
         if (g->walk_variant)
-            hipLaunchKernelGGL((k_ppr_interleaved<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+            hipLaunchKernelGGL((k_ppr_interleaved<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
                                seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
         else
-            hipLaunchKernelGGL((k_ppr_persistent<SPEC>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+            hipLaunchKernelGGL((k_ppr_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
                                seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
     }
 }
@@ -928,9 +933,11 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
         return BINGO_OK;
     }
     switch (g->dense_spec) {
-        case 1: deepwalk_kernels<1>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
-        case 4: deepwalk_kernels<4>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
-        default: deepwalk_kernels<2>(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+#define DWK(S) (g->rule.fbits ? deepwalk_kernels<S, true> : deepwalk_kernels<S, false>)
+        case 1: DWK(1)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+        case 4: DWK(4)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+        default: DWK(2)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
+#undef DWK
     }
     phase_mark(g, st, false);
     if (steps) HIPCHK(hipMemcpyAsync(steps, ctl + 1, 8, hipMemcpyDeviceToDevice, st));
@@ -1024,18 +1031,18 @@ static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources
     phase_mark(g, st, true);
     HIPCHK(hipMemsetAsync(bin_cnt, 0, (uint64_t)nsrc * 4, st));
     phase_mark(g, st, false);
-#define BINGO_BINNED(S_)                                                                                           \
+#define BINGO_BINNED(S_, F_)                                                                                          \
     do {                                                                                                           \
-        const int rg = resident_grid((const void*)k_ppr_binned<S_>, g->blocks_per_cu);                             \
+        const int rg = resident_grid((const void*)k_ppr_binned<S_, F_>, g->blocks_per_cu);                             \
         const uint64_t nw = (uint64_t)nsrc * R;                                                                    \
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1); \
-        hipLaunchKernelGGL((k_ppr_binned<S_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
+        hipLaunchKernelGGL((k_ppr_binned<S_, F_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
                            seed, base, thr, cap, g->rule, C, bin_cnt, vis, ctl, g->d_err, g->queue_chunk);          \
     } while (0)
     switch (g->dense_spec) {
-        case 1: BINGO_BINNED(1); break;
-        case 4: BINGO_BINNED(4); break;
-        default: BINGO_BINNED(2); break;
+        case 1: if (g->rule.fbits) BINGO_BINNED(1, true); else BINGO_BINNED(1, false); break;
+        case 4: if (g->rule.fbits) BINGO_BINNED(4, true); else BINGO_BINNED(4, false); break;
+        default: if (g->rule.fbits) BINGO_BINNED(2, true); else BINGO_BINNED(2, false); break;
     }
 #undef BINGO_BINNED
     phase_mark(g, st, false);
@@ -1125,9 +1132,11 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
     }
     switch (g->dense_spec) {
-        case 1: ppr_kernels<1>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
-        case 4: ppr_kernels<4>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
-        default: ppr_kernels<2>(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+#define PPK(S) (g->rule.fbits ? ppr_kernels<S, true> : ppr_kernels<S, false>)
+        case 1: PPK(1)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+        case 4: PPK(4)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+        default: PPK(2)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
+#undef PPK
     }
     phase_mark(g, st, false);
     unsigned long long steps = 0;

@@ -64,3 +64,27 @@ def test_probe_rejects_bad_arguments_without_gpu():
     assert f(fake, 1 << 10, 256, 4, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # table too small
     assert f(fake, 1 << 20, 100, 4, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # lanes
     assert f(fake, 1 << 20, 256, 3, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # reads
+
+
+def test_quantize_rejects_bad_arguments_without_gpu():
+    lib = ctypes.CDLL(_lib_path())
+    f = lib.bingo_quantize_biases
+    f.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint32, ctypes.c_void_p,
+                  ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its argument checks
+    assert f(8, None, 1.0, 8, fake, None) == -1
+    assert f(8, fake, 1.0, 8, None, None) == -1
+    assert f(8, fake, 1.0, 0, fake, None) == -1      # frac_bits 1..16
+    assert f(8, fake, 1.0, 17, fake, None) == -1
+    assert f(8, fake, 0.0, 8, fake, None) == -1      # lambda > 0
+    assert f(8, fake, float("nan"), 8, fake, None) == -1
+    assert f(8, fake, float("inf"), 8, fake, None) == -1
+
+
+def test_build_rejects_bad_frac_bits_without_gpu():
+    from paper_2504_10233_amd.binding import _Config
+    lib = ctypes.CDLL(_lib_path())
+    out = ctypes.c_void_p()
+    for fb, res in ((17, 0), (8, 1)):
+        cfg = _Config(ctypes.sizeof(_Config), 1, 40, 10, 0, fb, res)
+        assert lib.bingo_build(ctypes.byref(cfg), 10, 0, None, None, None, None, ctypes.byref(out)) == -1
