@@ -185,6 +185,7 @@ def workload_deepwalk(args):
     res.update({"walk_steps_per_s": tot_steps / (sum(r["walk_kernel_ms"] for r in timed) / 1e3),
                 "edge_updates_per_s": sum(r["records"] for r in timed) / (sum(r["update_ms"] for r in timed) / 1e3),
                 "build_s": build_s, "steps_detail": rows})
+    res["float_bias"] = float_vs_integer(n, src, dst, w, starts, paths, c)
     # sampled parity against the oracle after the same batches
     if not args.no_cpu_baseline:
         import oracle as O
@@ -202,6 +203,41 @@ def workload_deepwalk(args):
                                "sample": "%d DeepWalk walks (every 97th vertex) on the graph after the same batches"
                                          % len(sample)}
     return res
+
+
+def float_vs_integer(n, src, dst, w, starts, paths, c):
+    """Floating-point vs integer biases (the paper's microbenchmark: the float bias is the integer bias
+    plus a uniform value in [0, 1)): the same edges built twice, once with the integer weights and once
+    with the float biases (lambda = 1, 8 fraction bits); DeepWalk of length 80 from every vertex on
+    each, three runs; walk-kernel time and memory ratios."""
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph, quantize_biases
+    frac = synth.below(synth.SEEDS["weights"] + c, 11, w.numel(), 1 << 24, device=w.device).to(torch.float32) / 2**24
+    bias = w.to(torch.float32) + frac
+    qw = quantize_biases(bias, 1.0, 8)
+    del frac, bias
+    out = {}
+    for name, graph in (("integer", lambda: Graph(n, src, dst, w, device=w.device)),
+                        ("float", lambda: Graph(n, src, dst, qw, device=w.device, frac_bits=8))):
+        g = graph()
+        ms = []
+        for r in range(3):
+            g.walk(starts, 80, synth.SEEDS["walks"] + c + 1000 + r, base=0, out=paths)
+            torch.cuda.synchronize()
+            ms.append(g.last_phase_ms()[0])
+        mem = g.memory()
+        out[name] = {"walk_kernel_ms": sorted(ms)[1], "pool_used_bytes": mem["pool_used_bytes"],
+                     "model_ga_bytes": mem["model_ga_bytes"], "groups_by_type": mem["groups_by_type"]}
+        g.close()
+        torch.cuda.synchronize()
+    out["time_ratio"] = out["float"]["walk_kernel_ms"] / out["integer"]["walk_kernel_ms"]
+    out["memory_ratio_pool"] = out["float"]["pool_used_bytes"] / out["integer"]["pool_used_bytes"]
+    out["memory_ratio_model"] = out["float"]["model_ga_bytes"] / out["integer"]["model_ga_bytes"]
+    log("float biases: walk kernel %.2f ms vs %.2f ms integer (x%.3f), pool memory x%.3f, model memory x%.3f" %
+        (out["float"]["walk_kernel_ms"], out["integer"]["walk_kernel_ms"], out["time_ratio"],
+         out["memory_ratio_pool"], out["memory_ratio_model"]))
+    return out
 
 
 def workload_skewed_updates(args):
