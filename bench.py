@@ -186,6 +186,7 @@ def workload_deepwalk(args):
                 "edge_updates_per_s": sum(r["records"] for r in timed) / (sum(r["update_ms"] for r in timed) / 1e3),
                 "build_s": build_s, "steps_detail": rows})
     res["float_bias"] = float_vs_integer(n, src, dst, w, starts, paths, c)
+    res["adaption"] = adaption_vs_baseline(n, src, dst, w, starts, paths, c)
     # sampled parity against the oracle after the same batches
     if not args.no_cpu_baseline:
         import oracle as O
@@ -237,6 +238,37 @@ def float_vs_integer(n, src, dst, w, starts, paths, c):
     log("float biases: walk kernel %.2f ms vs %.2f ms integer (x%.3f), pool memory x%.3f, model memory x%.3f" %
         (out["float"]["walk_kernel_ms"], out["integer"]["walk_kernel_ms"], out["time_ratio"],
          out["memory_ratio_pool"], out["memory_ratio_model"]))
+    return out
+
+
+def adaption_vs_baseline(n, src, dst, w, starts, paths, c):
+    """Group adaption (GA, Sec. 5.1) against the all-regular baseline (BS, Sec. 6.2): the same edges
+    built both ways, DeepWalk of length 80 from every vertex, three runs each; walk-kernel time,
+    pool memory and the paper's memory model."""
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph
+    out = {}
+    for name, adaptive in (("ga", True), ("bs", False)):
+        g = Graph(n, src, dst, w, device=w.device, adaptive=adaptive)
+        ms = []
+        for r in range(3):
+            g.walk(starts, 80, synth.SEEDS["walks"] + c + 2000 + r, base=0, out=paths)
+            torch.cuda.synchronize()
+            ms.append(g.last_phase_ms()[0])
+        mem = g.memory()
+        out[name] = {"walk_kernel_ms": sorted(ms)[1], "pool_used_bytes": mem["pool_used_bytes"],
+                     "groups_by_type": mem["groups_by_type"]}
+        if adaptive:
+            out["model_ga_bytes"], out["model_bs_bytes"] = mem["model_ga_bytes"], mem["model_bs_bytes"]
+        g.close()
+        torch.cuda.synchronize()
+    out["bs_over_ga_time"] = out["bs"]["walk_kernel_ms"] / out["ga"]["walk_kernel_ms"]
+    out["bs_over_ga_pool"] = out["bs"]["pool_used_bytes"] / out["ga"]["pool_used_bytes"]
+    out["bs_over_ga_model"] = out["model_bs_bytes"] / out["model_ga_bytes"]
+    log("adaption: walk kernel %.2f ms (GA) vs %.2f ms (BS, all regular) (x%.3f); pool memory BS/GA x%.3f, "
+        "model BS/GA x%.3f" % (out["ga"]["walk_kernel_ms"], out["bs"]["walk_kernel_ms"], out["bs_over_ga_time"],
+                               out["bs_over_ga_pool"], out["bs_over_ga_model"]))
     return out
 
 
