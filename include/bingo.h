@@ -155,6 +155,30 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
                        void* stream, bingo_update_stats* h_stats);
 
 /*
+ * bingo_update_stream -- streaming updates (Sec. 4.2 insertion and deletion):
+ * n records applied one at a time in the given order; record i has exactly the
+ * meaning of a bingo_update_batch call that holds that record alone, so inserts
+ * and deletes may interleave and a delete sees every earlier record.
+ *   d_op        n device uint32: 0 insert (d_src[i], d_dst[i], d_w[i]), 1 delete
+ *               of the live edge d_src[i] -> d_dst[i] with the smallest sequence
+ *               number (d_w[i] ignored; not found is counted, not an error).
+ *   d_src, d_dst, d_w   n device uint32 each (weights of inserts >= 1).
+ *   h_stats     optional: inserted / deleted / not_found / transitions summed over
+ *               the records (as the batches of one would report them);
+ *               touched_vertices = distinct sources; match_scanned / match_candidates
+ *               = adjacency entries scanned by deletes and those with the target dst.
+ * The records of one source are applied by one wave in order, different
+ * sources in parallel; a delete scans the vertex's adjacency and the lists of
+ * the groups it touches.  Synchronizes the stream.  Returns BINGO_E_RANGE (an
+ * id >= n or an op other than 0/1) or BINGO_E_WEIGHT (a zero insert weight)
+ * with nothing applied; BINGO_E_OOM when the pool cannot hold a record's new
+ * blocks: that source stops before the record (the earlier records of every
+ * source stay applied, the structure is consistent), other sources continue.
+ */
+int bingo_update_stream(bingo_graph* g, uint64_t n, const uint32_t* d_op, const uint32_t* d_src,
+                        const uint32_t* d_dst, const uint32_t* d_w, void* stream, bingo_update_stats* h_stats);
+
+/*
  * bingo_walk -- biased first-order walks of fixed length (DeepWalk, Sec. 2.2).
  * Walk j has id walk_id_base + j and starts at d_starts[j]; step s of that walk
  * draws from the Philox-4x32-10 stream keyed by (seed, id, s).  Each step picks

@@ -269,6 +269,20 @@ class Graph:
         return {"inserted": int(st[0]), "deleted": int(st[1]), "not_found": int(st[2]),
                 "transitions": st[3:].reshape(5, 5).astype(np.int64)}
 
+    def update_stream(self, op, src, dst, w):
+        """Streaming updates (Sec. 4.2): every record is its own batch, in order; statistics summed."""
+        op, src, dst, w = _u32(op), _u32(src), _u32(dst), _u32(w)
+        tot = {"inserted": 0, "deleted": 0, "not_found": 0, "transitions": np.zeros((5, 5), np.int64)}
+        for i in range(len(op)):
+            if op[i] == 0:
+                s = self.update([src[i]], [dst[i]], [w[i]], [], [])
+            else:
+                s = self.update([], [], [], [src[i]], [dst[i]])
+            for k in ("inserted", "deleted", "not_found"):
+                tot[k] += s[k]
+            tot["transitions"] += s["transitions"]
+        return tot
+
     def dump(self, u_begin=None, u_end=None):
         L = lib()
         if u_begin is None and u_end is None:

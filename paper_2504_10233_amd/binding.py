@@ -55,7 +55,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
-           "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases"]
+           "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream"]
 
 
 class _ServerConfig(C.Structure):
@@ -90,6 +90,7 @@ def load():
         vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
         L.bingo_build.argtypes = [C.POINTER(_Config), u32, u64, vp, vp, vp, vp, C.POINTER(vp)]
         L.bingo_update_batch.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(_UpdateStats)]
+        L.bingo_update_stream.argtypes = [vp, u64, vp, vp, vp, vp, vp, C.POINTER(_UpdateStats)]
         L.bingo_walk.argtypes = [vp, u64, vp, u64, u32, u64, vp, vp, u32, vp]
         L.bingo_node2vec.argtypes = [vp, u64, vp, u64, u32, C.c_double, C.c_double, u64, vp, vp, vp]
         L.bingo_ppr.argtypes = [vp, u32, vp, u32, u32, u32, u64, u64, u32, C.POINTER(u64), C.POINTER(u64), vp]
@@ -249,6 +250,18 @@ class Graph:
         rc = load().bingo_update_batch(self.h, a.numel(), _ptr(a), _ptr(b), _ptr(c), d.numel(), _ptr(d), _ptr(e),
                                        _stream(stream), C.byref(stats))
         _check(rc, "bingo_update_batch")
+        return {"inserted": stats.inserted, "deleted": stats.deleted, "not_found": stats.not_found,
+                "touched_vertices": stats.touched_vertices, "match_scanned": stats.match_scanned,
+                "match_candidates": stats.match_candidates,
+                "transitions": np.array(list(stats.transitions), dtype=np.int64).reshape(5, 5)}
+
+    def update_stream(self, op, src, dst, w, stream=None):
+        """Records applied one at a time in order (op 0 insert, 1 delete; see bingo_update_stream)."""
+        o, a, b, c = (as_u32(x, self.device) for x in (op, src, dst, w))
+        stats = _UpdateStats()
+        rc = load().bingo_update_stream(self.h, o.numel(), _ptr(o), _ptr(a), _ptr(b), _ptr(c), _stream(stream),
+                                        C.byref(stats))
+        _check(rc, "bingo_update_stream")
         return {"inserted": stats.inserted, "deleted": stats.deleted, "not_found": stats.not_found,
                 "touched_vertices": stats.touched_vertices, "match_scanned": stats.match_scanned,
                 "match_candidates": stats.match_candidates,

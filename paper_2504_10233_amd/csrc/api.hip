@@ -114,6 +114,12 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
                         (hipStream_t)stream);
 }
 
+int bingo_update_stream(bingo_graph* g, uint64_t n, const uint32_t* d_op, const uint32_t* d_src,
+                        const uint32_t* d_dst, const uint32_t* d_w, void* stream, bingo_update_stats* h_stats) {
+    if (!g || (n && (!d_op || !d_src || !d_dst || !d_w))) return BINGO_E_INVALID;
+    return update_stream(g, n, d_op, d_src, d_dst, d_w, h_stats, (hipStream_t)stream);
+}
+
 int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
                uint32_t length, uint64_t seed, uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode,
                void* stream) {

@@ -286,6 +286,9 @@ int run_node2vec(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t b
 int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,
                  uint64_t n_del, const uint32_t* ds, const uint32_t* dd, bingo_update_stats* h_stats,
                  hipStream_t st);
+// stream.hip
+int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
+                  const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st);
 // api.hip
 void* ws_get(bingo_graph* g, size_t bytes);  // grow-only scratch (synchronizes when it grows)
 int err_to_code(uint32_t bits);

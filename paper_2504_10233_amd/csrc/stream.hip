@@ -1,0 +1,508 @@
+// stream.hip -- streaming updates (Sec. 4.2 insertion and deletion): edge
+// records applied one at a time in their given order, each with exactly the
+// meaning of a bingo_update_batch call that holds that one record.
+//
+// Records of different source vertices commute, so a stable sort by source
+// gives every touched vertex its own records in order; one wave then applies
+// them one by one (vertices in parallel), keeping the vertex's header state in
+// registers (lane k holds group k) between records.  An insert appends at index
+// d and adds the edge to the lists of its groups; a delete removes the live
+// occurrence with the smallest sequence number, moves the tail entry into its
+// slot, and fixes every list it touched: the deleted member's position takes
+// the list's last entry, and the moved entry is renamed.  A group whose type
+// changes gets a fresh ascending list or its one member, as in the batch.
+// Without an inverted index the positions inside a list are found by a wave
+// scan of that list.
+#include "dev.h"
+#include <algorithm>
+#include <string.h>
+
+namespace {
+
+constexpr int TB = 256;
+constexpr uint32_t NF = 0xFFFFFFFFu;
+constexpr uint32_t ST_GRID = 2048;
+constexpr int ST_CTRS = 32;  // 0 inserted, 1 deleted, 2 not found, 3..27 transitions, 28 scanned, 29 matches
+
+enum { OP_INSERT = 0, OP_DELETE = 1 };
+
+__device__ inline uint32_t st_adj_cap_for(uint32_t d) {
+    if (d == 0) return 0;
+    uint32_t c = 2;
+    while (c < d) c <<= 1;
+    return c;
+}
+__device__ inline uint64_t st_adj_block_words(uint32_t cap) { return ((uint64_t)cap * 3 + 7) & ~7ull; }
+__device__ inline uint32_t st_list_cap_for(uint32_t c) {
+    uint32_t x = 8;
+    while (x < c) x <<= 1;
+    return x;
+}
+
+__global__ void k_st_validate(uint64_t m, uint32_t n, const uint32_t* __restrict__ op,
+                              const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                              const uint32_t* __restrict__ w, uint32_t* __restrict__ err) {
+    uint32_t bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (op[i] > OP_DELETE || src[i] >= n || dst[i] >= n) bad |= ERR_RANGE;
+        else if (op[i] == OP_INSERT && w[i] == 0) bad |= ERR_WEIGHT;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_st_iota(uint32_t* __restrict__ a, uint64_t m) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+        a[i] = (uint32_t)i;
+}
+
+// head[p] = 1 where a new source starts in the sorted keys
+__global__ void k_st_heads(const uint32_t* __restrict__ sk, uint64_t m, uint32_t* __restrict__ head) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x)
+        head[p] = (p == 0 || sk[p] != sk[p - 1]) ? 1u : 0u;
+}
+
+// seg_start[segment] = first sorted position of each source
+__global__ void k_st_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hx, uint64_t m,
+                            uint32_t* __restrict__ seg_start) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x)
+        if (head[p]) seg_start[hx[p]] = (uint32_t)p;
+}
+
+// Pool words for the current record, taken with one compare-and-swap on the
+// bump counter (ctl[0]) so that a failed reservation leaves it unchanged.
+// Every lane calls; the result (NF64 on failure) is uniform.
+constexpr uint64_t NF64 = ~0ull;
+__device__ uint64_t st_alloc(unsigned long long* ctl, uint64_t pool_words, uint64_t words) {
+    unsigned long long got = 0;
+    if (lane_id() == 0 && words) {
+        unsigned long long cur = *reinterpret_cast<volatile unsigned long long*>(ctl);
+        for (;;) {
+            if (cur + words > pool_words) { got = NF64; break; }
+            const unsigned long long prev = atomicCAS(ctl, cur, cur + words);
+            if (prev == cur) { got = cur; break; }
+            cur = prev;
+        }
+    }
+    return __shfl(got, 0, 64);
+}
+
+__device__ __forceinline__ uint64_t st_wave_min(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(x, o);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// position of val in L[0, len) (it occurs once), by a wave scan
+__device__ uint32_t st_find(const uint32_t* __restrict__ L, uint32_t len, uint32_t val) {
+    for (uint32_t p0 = 0; p0 < len; p0 += 64) {
+        const uint32_t p = p0 + lane_id();
+        const uint64_t b = __ballot(p < len && L[p] == val);
+        if (b) return p0 + (uint32_t)(__ffsll((long long)b) - 1);
+    }
+    return NF;
+}
+
+// Per-vertex state between records; lane k < 32 holds group k.
+struct SV {
+    uint32_t u, d, cap, nseq;
+    uint64_t adj, W;
+    uint32_t c, info, lcap;
+};
+
+// Group-k lists that need writing after an adjacency change: every group in
+// `todo` gets a fresh ascending list of the indices in [0, d) whose membership
+// word has bit k, in the block `blk` (lane k's value).
+__device__ void st_fresh_lists(uint32_t todo, const uint64_t* __restrict__ edges, uint32_t d, uint32_t fb,
+                               uint64_t blk, uint32_t* __restrict__ pool) {
+    const uint32_t lane = lane_id();
+    uint32_t fill = 0;  // lane k: entries written to group k
+    for (uint32_t i0 = 0; i0 < d && todo; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const uint32_t mw = i < d ? member_word((uint32_t)(edges[i] >> 32), fb) : 0u;
+        uint32_t mm = todo;
+        while (mm) {
+            const int k = __ffs(mm) - 1;
+            mm &= mm - 1;
+            const bool bit = (mw >> k) & 1u;
+            const uint64_t b = __ballot(bit);
+            const uint64_t kb = __shfl(blk, k, 64);
+            const uint32_t f = __shfl(fill, k, 64);
+            if (bit) pool[kb + f + __popcll(b & lanemask_lt())] = i;
+            if (lane == (uint32_t)k) fill += __popcll(b);
+        }
+    }
+}
+
+// first index in [0, d) whose membership word has bit k, for every k in `todo` (lane k's result)
+__device__ uint32_t st_first_members(uint32_t todo, const uint64_t* __restrict__ edges, uint32_t d, uint32_t fb) {
+    const uint32_t lane = lane_id();
+    uint32_t first = NF;
+    for (uint32_t i0 = 0; i0 < d && todo; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const uint32_t mw = i < d ? member_word((uint32_t)(edges[i] >> 32), fb) : 0u;
+        uint32_t mm = todo;
+        while (mm) {
+            const int k = __ffs(mm) - 1;
+            mm &= mm - 1;
+            const uint64_t b = __ballot((mw >> k) & 1u);
+            if (b) {
+                if (lane == (uint32_t)k) first = i0 + (uint32_t)(__ffsll((long long)b) - 1);
+                todo &= ~(1u << k);
+            }
+        }
+    }
+    return first;
+}
+
+// Copy the live part of every list in `todo` to its new block (lane k: old and
+// new block offsets, length).
+__device__ void st_move_lists(uint32_t todo, uint64_t oblk, uint64_t nblk, uint32_t len,
+                              uint32_t* __restrict__ pool) {
+    const uint32_t lane = lane_id();
+    while (todo) {
+        const int k = __ffs(todo) - 1;
+        todo &= todo - 1;
+        const uint64_t o = __shfl(oblk, k, 64), nb = __shfl(nblk, k, 64);
+        const uint32_t L = __shfl(len, k, 64);
+        for (uint32_t p = lane; p < L; p += 64) pool[nb + p] = pool[o + p];
+    }
+}
+
+// Statistics of one record (one batch of one record): lane 0 adds to the
+// wave's counters in LDS; the type transition of group k is lane k's code.
+__device__ void st_count(uint32_t code, unsigned long long* acc) {
+#pragma unroll
+    for (int c = 0; c < 25; ++c) {
+        const uint32_t k = (uint32_t)__popcll(__ballot(code == (uint32_t)c));
+        if (lane_id() == 0 && k) acc[3 + c] += k;
+    }
+}
+
+// One insert record.  Returns false when the pool cannot hold what it needs
+// (nothing changed then).  `freed` is per lane (summed over the wave later).
+__device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_t* __restrict__ pool,
+                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc) {
+    const uint32_t lane = lane_id();
+    const uint32_t fb = rule.fbits;
+    const uint32_t mw = member_word(w, fb);
+    const uint32_t d1 = s.d + 1;
+    const bool g = lane < 32;
+    const bool bit = g && ((mw >> lane) & 1u);
+    const uint32_t cn = s.c + (bit ? 1u : 0u);
+    const uint32_t told = g ? group_type(s.c, s.d, rule) : GT_EMPTY;
+    const uint32_t tnew = g ? group_type(cn, d1, rule) : GT_EMPTY;
+    const bool kept = type_listed(told) && tnew == told;
+    const bool fresh = type_listed(tnew) && !kept;
+    const bool relist = kept && bit && cn > s.lcap;
+    // pool words: a larger adjacency block, moved or fresh lists
+    const bool grow = d1 > s.cap;
+    const uint32_t ncap = grow ? st_adj_cap_for(d1) : s.cap;
+    const uint64_t aw = grow ? st_adj_block_words(ncap) : 0ull;
+    const uint64_t lw = (relist || fresh) ? (uint64_t)st_list_cap_for(cn) : 0ull;
+    uint64_t x = lw;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    const uint64_t total = aw + __shfl(x, 63, 64);
+    const uint64_t base = st_alloc(ctl, pool_words, total);
+    if (base == NF64) return false;
+    const uint64_t myblk = base + aw + (x - lw);
+    // adjacency
+    if (grow) {
+        const uint64_t nadj = base;
+        const uint64_t* eo = reinterpret_cast<const uint64_t*>(pool + s.adj);
+        const uint32_t* qo = pool + s.adj + 2ull * s.cap;
+        uint64_t* en = reinterpret_cast<uint64_t*>(pool + nadj);
+        uint32_t* qn = pool + nadj + 2ull * ncap;
+        for (uint32_t i = lane; i < s.d; i += 64) { en[i] = eo[i]; qn[i] = qo[i]; }
+        if (s.cap && lane == 0) freed += st_adj_block_words(s.cap);
+        s.adj = nadj;
+        s.cap = ncap;
+    }
+    uint64_t* edges = reinterpret_cast<uint64_t*>(pool + s.adj);
+    if (lane == 0) {
+        edges[s.d] = (uint64_t)v | ((uint64_t)w << 32);
+        pool[s.adj + 2ull * s.cap + s.d] = s.nseq;
+    }
+    __threadfence_block();
+    // kept lists: move the ones that outgrow their block, then append index d
+    const uint64_t oblk = (uint64_t)s.info * LIST_UNIT_WORDS;
+    const uint32_t rmask = (uint32_t)(__ballot(relist) & 0xFFFFFFFFull);
+    st_move_lists(rmask, oblk, myblk, s.c, pool);
+    if (relist) {
+        freed += s.lcap;
+        s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
+        s.lcap = st_list_cap_for(cn);
+    }
+    if (kept && bit) pool[(uint64_t)s.info * LIST_UNIT_WORDS + s.c] = s.d;
+    // lists of groups that became listed or switched between sparse and regular
+    if (g && type_listed(told) && !kept) freed += s.lcap;
+    const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
+    if (fresh) {
+        s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
+        s.lcap = st_list_cap_for(cn);
+    }
+    __threadfence_block();
+    st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
+    // one-element groups: an old member stays; a new one is the inserted edge
+    if (tnew == GT_ONE && told != GT_ONE) s.info = s.d;
+    if (g && !type_listed(tnew) && tnew != GT_ONE) s.info = 0;
+    // statistics: one batch with one record
+    if (lane == 0) acc[0] += 1;
+    st_count(g ? told * 5 + tnew : 31u, acc);
+    s.c = cn;
+    s.d = d1;
+    s.nseq += 1;
+    s.W += w;
+    return true;
+}
+
+// One delete record.
+__device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restrict__ pool,
+                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc) {
+    const uint32_t lane = lane_id();
+    const uint32_t fb = rule.fbits;
+    const bool g = lane < 32;
+    uint64_t* edges = reinterpret_cast<uint64_t*>(pool + s.adj);
+    uint32_t* seqs = pool + s.adj + 2ull * s.cap;
+    // the live occurrence with the smallest sequence number
+    uint64_t best = ~0ull;
+    uint32_t hits = 0;
+    for (uint32_t i0 = 0; i0 < s.d; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const bool m = i < s.d && (uint32_t)edges[i] == v;
+        hits += __popcll(__ballot(m));
+        if (m) {
+            const uint64_t key = ((uint64_t)seqs[i] << 32) | i;
+            best = key < best ? key : best;
+        }
+    }
+    best = st_wave_min(best);
+    if (lane == 0) { acc[28] += s.d; acc[29] += hits; }
+    const uint32_t told = g ? group_type(s.c, s.d, rule) : GT_EMPTY;
+    if (best == ~0ull) {
+        if (lane == 0) acc[2] += 1;
+        st_count(g ? told * 5 + told : 31u, acc);
+        return true;
+    }
+    const uint32_t i = (uint32_t)best;
+    const uint32_t last = s.d - 1;
+    const bool moved = i != last;
+    const uint64_t ei = edges[i], el = edges[last];
+    const uint32_t wi = (uint32_t)(ei >> 32);
+    const uint32_t mw = member_word(wi, fb);
+    const uint32_t mwl = member_word((uint32_t)(el >> 32), fb);
+    const uint32_t d1 = s.d - 1;
+    const bool bit = g && ((mw >> lane) & 1u);
+    const uint32_t cn = s.c - (bit ? 1u : 0u);
+    const uint32_t tnew = g ? group_type(cn, d1, rule) : GT_EMPTY;
+    const bool kept = type_listed(told) && tnew == told;
+    const bool fresh = type_listed(tnew) && !kept;
+    const uint64_t lw = fresh ? (uint64_t)st_list_cap_for(cn) : 0ull;
+    uint64_t x = lw;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    const uint64_t total = __shfl(x, 63, 64);
+    const uint64_t base = st_alloc(ctl, pool_words, total);
+    if (base == NF64) return false;
+    const uint64_t myblk = base + (x - lw);
+    // adjacency: the tail entry takes the deleted slot
+    if (moved && lane == 0) {
+        edges[i] = el;
+        seqs[i] = seqs[last];
+    }
+    __threadfence_block();
+    // kept lists: the deleted member's position takes the last entry, then the moved entry is renamed
+    uint32_t km = (uint32_t)(__ballot(kept && bit) & 0xFFFFFFFFull);
+    while (km) {
+        const int k = __ffs(km) - 1;
+        km &= km - 1;
+        uint32_t* L = pool + (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
+        const uint32_t ck = __shfl(s.c, k, 64);
+        const uint32_t p = st_find(L, ck, i);
+        if (lane == 0 && p != NF && p != ck - 1) L[p] = L[ck - 1];
+        __threadfence_block();
+    }
+    if (moved) {
+        uint32_t rm = (uint32_t)(__ballot(kept && ((mwl >> lane) & 1u)) & 0xFFFFFFFFull);
+        while (rm) {
+            const int k = __ffs(rm) - 1;
+            rm &= rm - 1;
+            uint32_t* L = pool + (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
+            const uint32_t len = __shfl(cn, k, 64);
+            const uint32_t q = st_find(L, len, last);
+            if (lane == 0 && q != NF) L[q] = i;
+            __threadfence_block();
+        }
+    }
+    // fresh lists and one-element members from the final adjacency
+    if (g && type_listed(told) && !kept) freed += s.lcap;
+    const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
+    if (fresh) {
+        s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
+        s.lcap = st_list_cap_for(cn);
+    }
+    st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
+    const bool one = tnew == GT_ONE;
+    uint32_t member = NF;
+    if (one && told == GT_ONE) member = (moved && s.info == last) ? i : s.info;
+    const uint32_t scan = (uint32_t)(__ballot(one && member == NF) & 0xFFFFFFFFull);
+    const uint32_t first = st_first_members(scan, edges, d1, fb);
+    if (one) s.info = member != NF ? member : first;
+    if (g && !type_listed(tnew) && tnew != GT_ONE) s.info = 0;
+    if (lane == 0) acc[1] += 1;
+    st_count(g ? told * 5 + tnew : 31u, acc);
+    s.c = cn;
+    s.d = d1;
+    s.W -= wi;
+    return true;
+}
+
+// One wave per touched source vertex: its records in order.
+__global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ err, const unsigned long long* nseg_p,
+                                                 uint64_t m, const uint32_t* __restrict__ sk,
+                                                 const uint32_t* __restrict__ sv, const uint32_t* __restrict__ seg_start,
+                                                 const uint32_t* __restrict__ op, const uint32_t* __restrict__ dst,
+                                                 const uint32_t* __restrict__ w, uint32_t* __restrict__ hdr,
+                                                 uint32_t* __restrict__ pool, unsigned long long* ctl,
+                                                 uint64_t pool_words, GroupRule rule, uint32_t* __restrict__ errw,
+                                                 unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[TB / 64][ST_CTRS];  // per-wave counters, written by lane 0
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t nseg = *err ? 0 : *nseg_p;
+    unsigned long long* acc = red[wave];
+    if (lane < ST_CTRS) acc[lane] = 0;
+    __threadfence_block();
+    uint64_t freed = 0;  // per lane
+    for (uint64_t sg = (uint64_t)blockIdx.x * (TB / 64) + wave; sg < nseg; sg += (uint64_t)gridDim.x * (TB / 64)) {
+        const uint32_t b = seg_start[sg];
+        const uint32_t e = sg + 1 < nseg ? seg_start[sg + 1] : (uint32_t)m;
+        SV s;
+        s.u = sk[b];
+        uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
+        s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ];
+        s.adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        s.W = ((uint64_t)h[H_WHI] << 32) | h[H_WLO];
+        s.c = lane < 32 ? h[H_CNT + lane] : 0u;
+        s.info = lane < 32 ? h[H_INFO + lane] : 0u;
+        s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
+        bool ok = true;
+        for (uint32_t p = b; p < e && ok; ++p) {
+            const uint32_t r = sv[p];
+            if (op[r] == OP_INSERT) ok = st_insert(s, dst[r], w[r], rule, pool, ctl, pool_words, freed, acc);
+            else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, freed, acc);
+            __threadfence_block();
+        }
+        if (!ok && lane == 0) atomicOr(errw, ERR_OOM);
+        // header of the vertex (the records applied so far)
+        const bool ne = lane < 32 && s.c > 0;
+        const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
+        const uint32_t t = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
+        if (lane < 32) {
+            h[H_CNT + lane] = s.c;
+            h[H_INFO + lane] = (type_listed(t) || t == GT_ONE) ? s.info : 0u;
+        }
+        const uint32_t lg = (lane < 32 && type_listed(t)) ? (31 - __clz(s.lcap)) : 0u;
+        uint32_t packed = lg << (8 * (lane & 3));
+        packed |= __shfl_xor(packed, 1);
+        packed |= __shfl_xor(packed, 2);
+        if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
+        if (lane == 0) {
+            h[H_MASK] = nmask;
+            h[H_DEG] = s.d;
+            h[H_WLO] = (uint32_t)s.W;
+            h[H_WHI] = (uint32_t)(s.W >> 32);
+            h[H_ADJLO] = (uint32_t)s.adj;
+            h[H_ADJHI] = (uint32_t)(s.adj >> 32);
+            h[H_ACAP] = s.cap;
+            h[H_NSEQ] = s.nseq;
+        }
+    }
+    // garbage words of the wave, then the block's counters
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) freed += __shfl_xor(freed, o);
+    if (lane == 0 && freed) atomicAdd(ctl + 1, (unsigned long long)freed);
+    __syncthreads();
+    if (threadIdx.x < ST_CTRS) {
+        unsigned long long v = 0;
+        for (int wv = 0; wv < TB / 64; ++wv) v += red[wv][threadIdx.x];
+        if (v) atomicAdd(out + threadIdx.x, v);
+    }
+}
+
+inline uint32_t grid_for(uint64_t n) {
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n + TB - 1) / TB, 1), 8192);
+}
+
+int bits_for_n(uint32_t n) {
+    int b = 1;
+    while (b < 32 && ((n - 1) >> b)) ++b;
+    return b;
+}
+
+}  // namespace
+
+int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
+                  const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st) {
+    if (h_stats) memset(h_stats, 0, sizeof(*h_stats));
+    if (m == 0) return BINGO_OK;
+    if (m > (1ull << 31)) return BINGO_E_INVALID;
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const size_t tmpb = std::max(sort_temp_bytes(m, false), scan_temp_bytes(m));
+    const size_t bytes = al(m * 4) * 6 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
+    char* ws = (char*)ws_get(g, bytes);
+    if (!ws) return BINGO_E_OOM;
+    auto take = [&](uint64_t b) { char* r = ws; ws += al(b); return r; };
+    uint32_t* ids = (uint32_t*)take(m * 4);
+    uint32_t* sk = (uint32_t*)take(m * 4);
+    uint32_t* sv = (uint32_t*)take(m * 4);
+    uint32_t* head = (uint32_t*)take(m * 4);
+    uint32_t* seg = (uint32_t*)take(m * 4);
+    (void)take(m * 4);
+    uint64_t* hx = (uint64_t*)take(m * 8);
+    unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
+    unsigned long long* nseg = (unsigned long long*)take(256);
+    void* tmp = ws;
+    HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
+    HIPCHK(hipMemsetAsync(out, 0, ST_CTRS * 8, st));
+    phase_mark(g, st, true);
+    hipLaunchKernelGGL(k_st_validate, dim3(grid_for(m)), dim3(TB), 0, st, m, g->n, op, src, dst, w, g->d_err);
+    hipLaunchKernelGGL(k_st_iota, dim3(grid_for(m)), dim3(TB), 0, st, ids, m);
+    sort_pairs_u32(src, ids, sk, sv, m, bits_for_n(g->n), tmp, st);
+    hipLaunchKernelGGL(k_st_heads, dim3(grid_for(m)), dim3(TB), 0, st, sk, m, head);
+    scan_u32_to_u64(head, hx, m, tmp, nseg, st);
+    hipLaunchKernelGGL(k_st_starts, dim3(grid_for(m)), dim3(TB), 0, st, head, hx, m, seg);
+    phase_mark(g, st, false);
+    hipLaunchKernelGGL(k_st_apply, dim3(ST_GRID), dim3(TB), 0, st, (const uint32_t*)g->d_err,
+                       (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
+                       g->pool_words, g->rule, g->d_err, out);
+    phase_mark(g, st, false);
+    unsigned long long o[ST_CTRS], ns = 0;
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(o, out, sizeof o, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&ns, nseg, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (err & (ERR_RANGE | ERR_WEIGHT)) return err_to_code(err);
+    ++g->version;  // some records may have been applied before an out-of-pool stop
+    if (h_stats) {
+        h_stats->inserted = o[0];
+        h_stats->deleted = o[1];
+        h_stats->not_found = o[2];
+        h_stats->touched_vertices = ns;
+        for (int i = 0; i < 25; ++i) h_stats->transitions[i] = o[3 + i];
+        h_stats->match_scanned = o[28];
+        h_stats->match_candidates = o[29];
+    }
+    if (err) return err_to_code(err);
+    return BINGO_OK;
+}
