@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--node2vec-walks", type=int, default=1_000_000,
                     help="node2vec walks (length 80, p = 0.5, q = 2) on the final graph; 0 skips")
+    ap.add_argument("--stream-records", type=int, default=1_000_000,
+                    help="records of the streaming-update measurement on the final graph (0 skips)")
     ap.add_argument("--no-random-probe", action="store_true",
                     help="skip the random-line read probe (context for the roofline)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -204,6 +206,55 @@ def workload_deepwalk(args):
                                "sample": "%d DeepWalk walks (every 97th vertex) on the graph after the same batches"
                                          % len(sample)}
     return res
+
+
+def stream_phase(g, n, scale, src, dst, c, count):
+    """Streaming updates (one record at a time, Sec. 4.2) on the final graph: count records, half
+    R-MAT inserts with uniform weights and half deletes of edges drawn from the initial edge list (some
+    already gone: not found), through bingo_update_stream; then 200 records through the batch path
+    one record per call (its captured graph of the smallest bucket)."""
+    import torch
+    import synth
+    dev = src.device
+    half = count // 2
+    bseed = synth.SEEDS["batch"] + 100 * c + 77
+    isrc, idst = synth.rmat_graph(scale, half, bseed, device=dev)
+    iw = synth.weights_uniform(half, 1, 1 << 24, bseed, device=dev)
+    pos = synth.below(bseed, 9, count - half, src.numel(), device=dev)
+    dsrc, ddst = src[pos], dst[pos]
+    order = torch.argsort(synth.hash_u64(bseed, 10, count, dev))  # inserts and deletes interleaved
+    op = torch.cat([torch.zeros(half, dtype=torch.int64, device=dev), torch.ones(count - half, dtype=torch.int64,
+                                                                                   device=dev)])[order]
+    ss = torch.cat([isrc, dsrc])[order]
+    dd = torch.cat([idst, ddst])[order]
+    ww = torch.cat([iw, torch.zeros(count - half, dtype=iw.dtype, device=dev)])[order]
+    rec = tuple(x.to(torch.int32).contiguous() for x in (op, ss, dd, ww))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.update_stream(*rec)
+    t1 = time.perf_counter()
+    ph = g.last_phase_ms()
+    one = []
+    e = torch.empty(0, dtype=torch.int32, device=dev)
+    for i in range(200):
+        if int(rec[0][i]) == 0:
+            a = (rec[1][i:i + 1], rec[2][i:i + 1], rec[3][i:i + 1], e, e)
+        else:
+            a = (e, e, e, rec[1][i:i + 1], rec[2][i:i + 1])
+        torch.cuda.synchronize()
+        u0 = time.perf_counter()
+        g.update(*a)
+        one.append(time.perf_counter() - u0)
+    one.sort()
+    out = {"records": count, "ms": (t1 - t0) * 1e3, "records_per_s": count / (t1 - t0),
+           "apply_kernel_ms": ph[1] if len(ph) > 1 else None, "inserted": st["inserted"], "deleted": st["deleted"],
+           "not_found": st["not_found"], "sources": st["touched_vertices"],
+           "batch_of_one_median_ms": one[len(one) // 2] * 1e3, "batch_of_one_records_per_s": 1.0 / one[len(one) // 2]}
+    log("streaming: %d records in %.1f ms (%.3g records/s; apply kernel %.1f ms, %d sources); batch path with one "
+        "record per call: median %.3f ms (%.3g records/s)" %
+        (count, out["ms"], out["records_per_s"], out["apply_kernel_ms"] or -1, out["sources"],
+         out["batch_of_one_median_ms"], out["batch_of_one_records_per_s"]))
+    return out
 
 
 def float_vs_integer(n, src, dst, w, starts, paths, c):
@@ -711,6 +762,8 @@ def main():
             roof["traffic"] = pc.get("traffic_bytes_per_launch")
     result["roofline"] = roof
     result["walk_src_hash"] = walk_src_hash()
+    if args.stream_records:
+        result["streaming"] = stream_phase(g, n, scale, src, dst, c, args.stream_records)
     print(json.dumps(result), flush=True)
 
 

@@ -95,12 +95,23 @@ __device__ __forceinline__ uint64_t st_wave_min(uint64_t x) {
     return x;
 }
 
-// position of val in L[0, len) (it occurs once), by a wave scan
+// position of val in L[0, len) (it occurs once), by a wave scan with eight
+// loads per lane in flight
+constexpr uint32_t ST_UNROLL = 8;
 __device__ uint32_t st_find(const uint32_t* __restrict__ L, uint32_t len, uint32_t val) {
-    for (uint32_t p0 = 0; p0 < len; p0 += 64) {
-        const uint32_t p = p0 + lane_id();
-        const uint64_t b = __ballot(p < len && L[p] == val);
-        if (b) return p0 + (uint32_t)(__ffsll((long long)b) - 1);
+    const uint32_t lane = lane_id();
+    for (uint32_t p0 = 0; p0 < len; p0 += 64 * ST_UNROLL) {
+        uint32_t v[ST_UNROLL];
+#pragma unroll
+        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+            const uint32_t p = p0 + j * 64 + lane;
+            v[j] = p < len ? L[p] : ~val;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+            const uint64_t b = __ballot(v[j] == val);
+            if (b) return p0 + j * 64 + (uint32_t)(__ffsll((long long)b) - 1);
+        }
     }
     return NF;
 }
@@ -273,13 +284,22 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     // the live occurrence with the smallest sequence number
     uint64_t best = ~0ull;
     uint32_t hits = 0;
-    for (uint32_t i0 = 0; i0 < s.d; i0 += 64) {
-        const uint32_t i = i0 + lane;
-        const bool m = i < s.d && (uint32_t)edges[i] == v;
-        hits += __popcll(__ballot(m));
-        if (m) {
-            const uint64_t key = ((uint64_t)seqs[i] << 32) | i;
-            best = key < best ? key : best;
+    for (uint32_t i0 = 0; i0 < s.d; i0 += 64 * ST_UNROLL) {
+        uint32_t e[ST_UNROLL];
+#pragma unroll
+        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+            const uint32_t i = i0 + j * 64 + lane;
+            e[j] = i < s.d ? (uint32_t)edges[i] : ~v;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+            const uint32_t i = i0 + j * 64 + lane;
+            const bool m = e[j] == v;
+            hits += __popcll(__ballot(m));
+            if (m) {
+                const uint64_t key = ((uint64_t)seqs[i] << 32) | i;
+                best = key < best ? key : best;
+            }
         }
     }
     best = st_wave_min(best);
