@@ -119,6 +119,54 @@ def random_read_probe(dev, sizes_gib=(0.25, 1, 4, 8, 16)):
     return out
 
 
+def stream_copy_GBps(dev, gib=1):
+    """Streaming bandwidth: a 1 GiB device-to-device copy (read + write bytes over the kernel time)."""
+    import torch
+    a = torch.empty(gib << 28, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(3):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None or ms < best else best
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (gib << 30) / (best / 1e3) / 1e9
+
+
+def update_roofline(rows, mem, edges, r_rand_GBps, r_stream_GBps):
+    """Model of the update batch's minimum time (the work the method itself must do): streamed bytes
+    (the records, 12 B per insert and 8 B per delete, and about four radix passes reading and writing
+    8-byte keys) over the streaming bandwidth, plus random 64-byte lines (an insert touches its adjacency
+    slot and, per listed group of the edge, a list slot and its block; a delete the same for the
+    deleted edge and for the moved tail edge) over the random-line rate.  Listed groups per edge are
+    taken from the structure (live list entries / edges).  Locating deletes (the scan of the touched
+    adjacencies, 8 B per scanned entry) is reported beside it, since the paper does not say how an
+    edge (src, dst) is found."""
+    le = mem["list_bytes"] / 4.0 / max(edges, 1)
+    n = len(rows)
+    ins = sum(r["inserted"] for r in rows) / n
+    dels = sum(r["deleted"] + r["not_found"] for r in rows) / n
+    scanned = sum(r["match_scanned"] for r in rows) / n
+    ms = sum(r["update_ms"] for r in rows) / n
+    b_seq = ins * 12 + dels * 8 + (ins + dels) * 4 * 2 * 8
+    lines = ins * (1 + 2 * le) + dels * (1 + 4 * le)
+    t_min = b_seq / (r_stream_GBps * 1e9) + lines * 64 / (r_rand_GBps * 1e9)
+    t_loc = scanned * 8 / (r_stream_GBps * 1e9)
+    rec = ins + dels
+    return {"records_per_batch": rec, "list_entries_per_edge": le, "streamed_bytes": b_seq, "random_lines": lines,
+            "R_stream_GBps": r_stream_GBps, "R_rand_GBps": r_rand_GBps, "t_min_ms": t_min * 1e3,
+            "locate_scanned_entries": scanned, "t_locate_ms": t_loc * 1e3, "measured_ms": ms,
+            "ceiling_updates_per_s": rec / t_min, "ceiling_with_locate_updates_per_s": rec / (t_min + t_loc),
+            "frac": (t_min * 1e3) / ms, "frac_with_locate": ((t_min + t_loc) * 1e3) / ms}
+
+
 def torch_index(pos):
     import torch
     return torch.from_numpy(pos).to("cuda:0")
@@ -608,6 +656,7 @@ def main():
                      "step_ms": e0.elapsed_time(e2), "bound_ms": ppr_phases[0], "walk_kernel_ms": ppr_phases[1],
                      "hist_ms": ppr_phases[2], "update_phases_ms": upd_phases, "steps": steps,
                      "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel()),
+                     "inserted": st["inserted"], "deleted": st["deleted"], "not_found": st["not_found"],
                      "touched_vertices": st["touched_vertices"], "match_scanned": st["match_scanned"],
                      "match_candidates": st["match_candidates"]})
         log("step %d: update %.2f ms %s (%d touched, %d scanned to locate deletes), ppr %.2f ms (bound %.2f, walk "
@@ -709,7 +758,7 @@ def main():
         t = time.time()
         og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
         log("oracle: built in %.1fs" % (time.time() - t))
-        del src, dst, w
+        del w  # src and dst stay for the streaming measurement
         t = time.time()
         urecs = 0
         for bt in batches:
@@ -755,6 +804,15 @@ def main():
                      "lines_per_transition": lines / mix["steps"]})
     if probe:
         roof["random_read_probe"] = probe
+        r_stream = stream_copy_GBps(dev)
+        big = max(probe, key=lambda r: r["table_GiB"])
+        r_rand = max(big["independent_64B_GBps"], big["dependent_64B_GBps"])
+        result["update_roofline"] = update_roofline(timed, mem, m, r_rand, r_stream)
+        ur = result["update_roofline"]
+        log("update roofline: %.2f ms model (%.2f ms locating deletes) vs %.2f ms measured: %.2f of the model, "
+            "%.2f with locating (R_stream %.0f GB/s, R_rand %.0f GB/s over %g GiB)" %
+            (ur["t_min_ms"], ur["t_locate_ms"], ur["measured_ms"], ur["frac"], ur["frac_with_locate"], r_stream,
+             r_rand, big["table_GiB"]))
     prof = os.path.join(ROOT, "profiles", "walk_kernel_counters.json")
     if os.path.exists(prof):
         pc = json.load(open(prof))

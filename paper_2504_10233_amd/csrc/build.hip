@@ -159,6 +159,11 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     }
     const uint64_t my_block = list_base + list_off[u] + (x - lcap);  // words
     if (lane < 32 && lst) h[H_INFO + lane] = (uint32_t)(my_block / LIST_UNIT_WORDS);
+    // one-element groups: the member's destination in the count slot
+    const bool one = lane < 32 && t == GT_ONE;
+    if (one) h[H_CNT + lane] = cdst[b + h[H_INFO + lane]];
+    const uint32_t onemask = (uint32_t)(__ballot(one) & 0xFFFFFFFFull);
+    if (lane == 0) h[H_ONEMASK] = onemask;
     // list capacity exponents, one byte per group, packed four per word
     const uint32_t lg = lst ? (31 - __clz(lcap)) : 0u;
     const uint32_t byte = lg << (8 * (lane & 3));

@@ -9,18 +9,22 @@
 // ---------------------------------------------------------------------------
 // Per-vertex header: the inter-group sampling space of Sec. 3 / Sec. 4.1, one
 // fixed 384-byte slot (three 128-byte lines) per vertex, 128-byte aligned.
-//   line 0: mask of non-empty groups, degree d, W = sum_k c_k 2^k (u64),
-//           adjacency block offset (u64, in pool words), c_k for k = 0..25
-//   line 1: c_k for k = 26..31, info_k for k = 0..25
+//   line 0: mask of one-element groups, degree d, W = sum_k c_k 2^k (u64),
+//           adjacency block offset (u64, in pool words), slot k for k = 0..25
+//   line 1: slot k for k = 26..31, info_k for k = 0..25
 //   line 2: info_k for k = 26..31, adjacency capacity, next sequence number,
-//           log2 of each listed group's list capacity (bytes), spare
-// info_k is the member index of a one-element group, or the offset of a
-// listed group's list block in 32-byte units of the pool.  Dense and empty
-// groups have no info.  A walk step reads line 0 and, for one-element and
-// listed groups, one word of line 1.
+//           log2 of each listed group's list capacity (bytes), mask of
+//           non-empty groups, spare
+// Slot k holds c_k, except for a one-element group (c_k = 1), whose slot holds
+// its member's destination vertex: a step that selects such a group ends on
+// line 0 without touching the adjacency.  info_k is the member index of a
+// one-element group, or the offset of a listed group's list block in 32-byte
+// units of the pool.  Dense and empty groups have no info.  A walk step reads
+// line 0 and, for listed groups, one word of line 1.
 // ---------------------------------------------------------------------------
 #define HDR_WORDS 96
-#define H_MASK 0
+#define H_ONEMASK 0
+#define H_MASK 80
 #define H_DEG 1
 #define H_WLO 2
 #define H_WHI 3
@@ -32,6 +36,11 @@
 #define H_NSEQ 71
 #define H_LCAPLOG 72   // 32 bytes = 8 words
 #define STOP_VERTEX 0xFFFFFFFFu
+
+// c_k from slot k (one-element groups keep their member's destination there)
+__host__ __device__ inline uint32_t slot_count(uint32_t slot, uint32_t onemask, uint32_t k) {
+    return ((onemask >> k) & 1u) ? 1u : slot;
+}
 
 // Adjacency block of capacity cap (words): cap edge words of 64 bits
 // (dst | weight << 32) followed by cap sequence numbers (u32).

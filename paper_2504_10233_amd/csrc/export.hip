@@ -19,11 +19,11 @@ __global__ void k_dump_size(const uint32_t* __restrict__ hdr, uint32_t u0, uint3
     const uint32_t u = u0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= u1) return;
     const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-    const uint32_t d = h[H_DEG], mask = h[H_MASK];
+    const uint32_t d = h[H_DEG], mask = h[H_MASK], onem = h[H_ONEMASK];
     uint64_t s = 3 + 3ull * d;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         const int k = __ffs(mm) - 1;
-        const uint32_t c = h[H_CNT + k];
+        const uint32_t c = slot_count(h[H_CNT + k], onem, k);
         s += 3 + stored_words(group_type(c, d, rule), c);
     }
     sz[u - u0] = s;
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(WB) k_dump_write(const uint32_t* __restrict__ 
     }
     // group records in ascending k: lane k computes its record's size and start
     const bool ne = lane < 32 && ((mask >> lane) & 1u);
-    const uint32_t c = ne ? h[H_CNT + lane] : 0u;
+    const uint32_t c = ne ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
     const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
     const uint64_t sz = ne ? 3ull + stored_words(t, c) : 0ull;
     uint64_t x = sz;
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(WB) k_mem(const uint32_t* __restrict__ hdr, co
         const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         const uint32_t d = h[H_DEG], mask = h[H_MASK];
         const bool ne = lane < 32 && ((mask >> lane) & 1u);
-        const uint32_t c = ne ? h[H_CNT + lane] : 0u;
+        const uint32_t c = ne ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
         const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
         const uint32_t capb = lane < 32 ? ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
         const uint32_t smask = (uint32_t)(__ballot(ne && t == GT_SPARSE) & 0xFFFFFFFFull);

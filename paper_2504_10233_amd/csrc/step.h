@@ -43,12 +43,13 @@ __device__ __forceinline__ uint32_t dense_round(const uint64_t* __restrict__ edg
 constexpr uint32_t DEC_MAX_ATTEMPTS = 1u << 24;
 
 __device__ __forceinline__ uint32_t decimal_pick(const uint32_t* __restrict__ h, const uint32_t* __restrict__ pool,
-                                                 uint64_t adj, uint32_t d, uint32_t c0, GroupRule rule,
-                                                 RandStream& rs) {
+                                                 uint64_t adj, uint32_t d, uint32_t slot0, uint32_t onem,
+                                                 GroupRule rule, RandStream& rs) {
+    if (onem & 1u) return slot0;  // one member: its destination sits in the slot
     const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
+    const uint32_t c0 = slot0;
     const uint32_t t = group_type(c0, d, rule);
     const uint32_t info = h[H_INFO];
-    if (t == GT_ONE) return (uint32_t)edges[info];
     const uint32_t fm = (1u << rule.fbits) - 1u;
     const uint64_t lst = (uint64_t)info * LIST_UNIT_WORDS;
     for (uint32_t att = 0; att < DEC_MAX_ATTEMPTS; ++att) {
@@ -77,26 +78,32 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
     // groups in ascending k; fixed-point biases skip the slots below F (slot 0
     // is their decimal group, taken last)
+    // (a one-element group's slot holds its member's destination; its count is 1)
     const uint32_t fb = FB ? rule.fbits : 0u;
+    const uint32_t onem = q0.x;
     uint64_t acc = 0;
     int sel = -1;
-    uint32_t csel = 0;
+    uint32_t csel = 0, raw = 0;
 #pragma unroll
     for (int k = 0; k < 26; ++k) {
-        if ((uint32_t)k >= fb) acc += (uint64_t)c[k] << k;
-        if (sel < 0 && r < acc) { sel = k; csel = c[k]; }
+        const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
+        if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
+        if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
     }
     if (sel < 0) {
         const uint4 a = h4[8], b = h4[9];
         const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            acc += (uint64_t)hc[k] << (26 + k);
-            if (sel < 0 && r < acc) { sel = 26 + k; csel = hc[k]; }
+            const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
+            acc += (uint64_t)ck << (26 + k);
+            if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], rule, rs);
+    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, rs);
+    if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
+    if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
     const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
     const uint32_t t = group_type(csel, d, rule);
     if (t == GT_DENSE) {
@@ -111,12 +118,7 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
         return STOP_VERTEX;
     }
     const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
-    uint32_t i;
-    if (t == GT_ONE) {
-        i = info;
-    } else {
-        i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(rs, csel)];
-    }
+    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(rs, csel)];
     return pool[adj + 2ull * i];
 }
 

@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ];
         s.adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
         s.W = ((uint64_t)h[H_WHI] << 32) | h[H_WLO];
-        s.c = lane < 32 ? h[H_CNT + lane] : 0u;
+        s.c = lane < 32 ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
         s.info = lane < 32 ? h[H_INFO + lane] : 0u;
         s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
         bool ok = true;
@@ -426,8 +426,11 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         const bool ne = lane < 32 && s.c > 0;
         const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
         const uint32_t t = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
+        // one-element groups: the member's destination in the count slot
+        const bool onek = lane < 32 && t == GT_ONE;
+        const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
         if (lane < 32) {
-            h[H_CNT + lane] = s.c;
+            h[H_CNT + lane] = onek ? (uint32_t)reinterpret_cast<const uint64_t*>(pool + s.adj)[s.info] : s.c;
             h[H_INFO + lane] = (type_listed(t) || t == GT_ONE) ? s.info : 0u;
         }
         const uint32_t lg = (lane < 32 && type_listed(t)) ? (31 - __clz(s.lcap)) : 0u;
@@ -437,6 +440,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
         if (lane == 0) {
             h[H_MASK] = nmask;
+            h[H_ONEMASK] = onemask;
             h[H_DEG] = s.d;
             h[H_WLO] = (uint32_t)s.W;
             h[H_WHI] = (uint32_t)(s.W >> 32);

@@ -529,7 +529,7 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     s.ts = ts[t]; s.ni = tdl[t] - ts[t]; s.nd = te[t] - tdl[t];
     s.N = ncnt[t]; s.xoff = (uint32_t)xoff[t];
     s.d1 = s.d + s.ni; s.dn = s.d1 - s.N;
-    s.c = lane < 32 ? h[H_CNT + lane] : 0u;
+    s.c = lane < 32 ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
     s.info = lane < 32 ? h[H_INFO + lane] : 0u;
     s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
     s.told = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
@@ -1152,8 +1152,15 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     const bool ne = lane < 32 && s.cn > 0;
     const uint64_t wsum = fb ? s.W : wave_sum(ne ? ((uint64_t)s.cn << lane) : 0ull);
     const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
+    // one-element groups keep their member's destination in the count slot (a member
+    // left to k_big_pass gets it from k_big_one_dst)
+    const bool onek = lane < 32 && s.tnew == GT_ONE;
+    uint32_t slot = s.cn;
+    if (onek && member != NF)
+        slot = (uint32_t)(SPLIT ? final_word_xv(member, enew, eold, reloc, keep, xv) : enew[member]);
+    const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
     if (lane < 32) {
-        h[H_CNT + lane] = s.cn;
+        h[H_CNT + lane] = slot;
         uint32_t inf = 0;
         if (type_listed(s.tnew)) inf = newinfo;
         else if (s.tnew == GT_ONE) inf = member;
@@ -1167,6 +1174,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     freed = wave_sum(freed);
     if (lane == 0) {
         h[H_MASK] = nmask;
+        h[H_ONEMASK] = onemask;
         h[H_DEG] = s.dn;
         h[H_WLO] = (uint32_t)wsum;
         h[H_WHI] = (uint32_t)(wsum >> 32);
@@ -1478,6 +1486,21 @@ __global__ void __launch_bounds__(256) k_big_holes(const unsigned long long* __r
     }
 }
 
+// Split work, last step: a one-element member found by k_big_pass puts its
+// destination in the group's count slot (the adjacency copies are complete).
+__global__ void __launch_bounds__(256) k_big_one_dst(const unsigned long long* __restrict__ uc, BigCtx bc,
+                                                     const uint32_t* __restrict__ pool, uint32_t* __restrict__ hdr) {
+    const uint64_t nitems = std::min<uint64_t>(uc[UC_BIG_ITEMS], bc.imax);
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nitems;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        const BigItem& bi = bc.items[it];
+        if (bi.kind != BK_ONE) continue;
+        uint32_t* h = hdr + (size_t)bi.u * HDR_WORDS;
+        const uint32_t member = h[H_INFO + bi.k];
+        if (member < bi.n) h[H_CNT + bi.k] = pool[bi.a + 2ull * member];
+    }
+}
+
 __global__ void k_add_u64(unsigned long long* dst, const unsigned long long* src) { *dst += *src; }
 
 // Reserve the batch's pool words with one bump, unless the batch is already
@@ -1664,6 +1687,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
         hipLaunchKernelGGL(k_big_apply, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc,
                            (const uint32_t*)p->xs, g->pool, (const uint32_t*)p->ccnt);
         hipLaunchKernelGGL(k_big_holes, dim3(BIG_GRID), dim3(256), 0, st, (const unsigned long long*)uc, bc, g->pool);
+        hipLaunchKernelGGL(k_big_one_dst, dim3(64), dim3(256), 0, st, (const unsigned long long*)uc, bc,
+                           (const uint32_t*)g->pool, g->hdr);
     }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
 }

@@ -47,33 +47,39 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
     // groups in ascending k; fixed-point biases skip the slots below F (slot 0
     // is their decimal group, taken last)
+    // (a one-element group's slot holds its member's destination; its count is 1)
     const uint32_t fb = FB ? rule.fbits : 0u;
+    const uint32_t onem = q0.x;
     uint64_t acc = 0;
     int sel = -1;
-    uint32_t csel = 0;
+    uint32_t csel = 0, raw = 0;
 #pragma unroll
     for (int k = 0; k < 26; ++k) {
-        if ((uint32_t)k >= fb) acc += (uint64_t)c[k] << k;
-        if (sel < 0 && r < acc) { sel = k; csel = c[k]; }
+        const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
+        if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
+        if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
     }
     if (sel < 0) {
         const uint4 a = h4[8], b = h4[9];
         const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            acc += (uint64_t)hc[k] << (26 + k);
-            if (sel < 0 && r < acc) { sel = 26 + k; csel = hc[k]; }
+            const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
+            acc += (uint64_t)ck << (26 + k);
+            if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], rule, ss.rs);
+    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, ss.rs);
+    if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
+    if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
     const uint32_t t = group_type(csel, d, rule);
     if (t == GT_DENSE) {
         ss.adj = adj; ss.d = d; ss.sel = (uint32_t)sel; ss.tries = 0; ss.pending = true;
         return PENDING;
     }
     const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
-    const uint32_t i = (t == GT_ONE) ? info : pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(ss.rs, csel)];
+    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(ss.rs, csel)];
     return pool[adj + 2ull * i];
 }
 
