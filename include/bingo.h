@@ -18,8 +18,9 @@
  * all of its device memory and releases it in bingo_destroy().
  *
  * Concurrency.  A handle is not thread-safe.  bingo_walk calls may overlap
- * each other on different streams; bingo_update_batch and bingo_ppr must not
- * overlap any other call on the same handle.
+ * each other on different streams; bingo_update_batch, bingo_update_stream,
+ * bingo_ppr and bingo_node2vec must not overlap any other call on the same
+ * handle.
  *
  * Determinism.  Results are a pure function of (graph version, inputs, seed,
  * walk id base); they do not depend on stream, launch shape or timing.

@@ -137,3 +137,27 @@ def test_stream_rejects_bad_records():
             gg.update_stream(*[torch.tensor(x) for x in (ops, s, d, w)])
         assert e.value.code == code
         assert np.array_equal(gg.export(), before)
+
+
+def test_stream_out_of_pool_keeps_a_consistent_prefix():
+    """A stream that outgrows the device pool returns BINGO_E_OOM; the vertex that ran out keeps exactly
+    the records before the failing one (here the inserts fit until its adjacency or a list must grow),
+    which the oracle reproduces by applying that prefix."""
+    b = B()
+    n, src, dst, w = skew_edges()
+    probe = b.Graph(n, torch.tensor(src), torch.tensor(dst), torch.tensor(w))
+    used = probe.memory()["pool_used_bytes"]
+    probe.close()
+    gg = b.Graph(n, torch.tensor(src), torch.tensor(dst), torch.tensor(w), pool_bytes=used + (64 << 10))
+    og = O.Graph(n, src, dst, w)
+    d0 = O.parse_dump(gg.export(), n)[6]["d"]
+    rng = random.Random(12)
+    k = 30000
+    ops, s, d, ww = [0] * k, [6] * k, [rng.randrange(n) for _ in range(k)], [rng.randrange(1, 1 << 32) for _ in range(k)]
+    with pytest.raises(b.BingoError) as e:
+        gg.update_stream(*[torch.tensor(x) for x in (ops, s, d, ww)])
+    assert e.value.code == -4
+    applied = O.parse_dump(gg.export(), n)[6]["d"] - d0
+    assert 0 < applied < k
+    og.update_stream(ops[:applied], s[:applied], d[:applied], ww[:applied])
+    assert_same_structure(og, gg, "prefix of %d inserts" % applied)
