@@ -62,7 +62,10 @@ def lib():
             L.o_two_phase.argtypes = [u32p, C.c_uint32, u8p]
             L.o_two_phase.restype = C.c_uint32
             L.o_build.argtypes = [C.c_uint32, C.c_uint64, u32p, u32p, u32p, C.c_int, C.c_uint32, C.c_uint32,
-                                  C.c_uint32, C.POINTER(C.c_void_p)]
+                                  C.c_uint32, C.c_int, C.POINTER(C.c_void_p)]
+            L.o_alias_table.argtypes = [u64p, u64p, u32p]
+            L.o_alias_pick.argtypes = [u64p, C.c_uint32, C.c_uint64]
+            L.o_alias_pick.restype = C.c_int
             L.o_quantize.argtypes = [C.c_uint64, C.POINTER(C.c_float), C.c_double, C.c_uint32, u32p]
             L.o_build.restype = C.c_int
             L.o_free.argtypes = [C.c_void_p]
@@ -173,6 +176,22 @@ def node2vec_thresholds(p, q):
         raise ValueError("p and q must be positive")
     return thr
 
+def alias_table(totals):
+    """Inter-group alias table (Sec. 4.1) of 32 group totals -> (cut[32], alias[32])."""
+    T = np.zeros(32, np.uint64)
+    T[: len(totals)] = np.asarray(totals, dtype=np.uint64)
+    cut = np.zeros(32, np.uint64)
+    al = np.zeros(32, np.uint32)
+    lib().o_alias_table(_p(T, C.c_uint64), _p(cut, C.c_uint64), _p(al, C.c_uint32))
+    return cut, al
+
+
+def alias_pick(totals, slot, x):
+    T = np.zeros(32, np.uint64)
+    T[: len(totals)] = np.asarray(totals, dtype=np.uint64)
+    return int(lib().o_alias_pick(_p(T, C.c_uint64), slot, x))
+
+
 def quantize(bias, lam, frac_bits):
     """Floating-point biases (Sec. 4.3) as stored weights: floor(lam * b * 2^F) for float32 b, the
     product in IEEE double; 0 for a bias that does not give a weight in [1, 2^32)."""
@@ -186,18 +205,19 @@ class Graph:
     """The oracle's dynamic graph with its radix-group sampling structures.  frac_bits = F > 0
     reads every weight as a fixed-point bias with F fraction bits (Sec. 4.3)."""
 
-    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, frac_bits=0):
+    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, frac_bits=0, alias=False):
         L = lib()
         self._src = _u32(src); self._dst = _u32(dst); self._w = _u32(w)
         h = C.c_void_p()
         rc = L.o_build(n, len(self._src), _p(self._src, C.c_uint32), _p(self._dst, C.c_uint32),
-                       _p(self._w, C.c_uint32), int(adaptive), alpha, beta, frac_bits, C.byref(h))
+                       _p(self._w, C.c_uint32), int(adaptive), alpha, beta, frac_bits, int(alias), C.byref(h))
         if rc != 0:
             raise OracleError("o_build failed: %d" % rc)
         self.h = h
         self.n = n
         self.adaptive = adaptive
         self.frac_bits = frac_bits
+        self.alias = bool(alias)
         del self._src, self._dst, self._w
 
     def close(self):

@@ -17,7 +17,9 @@
  *   - group adaption into empty / one-element / dense / sparse / regular
  *     groups (Sec. 5.1, Eq. eq:group, alpha = 40, beta = 10);
  *   - the two-stage sampling step (Sec. 4.1, Eq. eq:group_prob and eq:pvp)
- *     with rejection on the adjacency for dense groups (Sec. 5.1);
+ *     with rejection on the adjacency for dense groups (Sec. 5.1); the
+ *     inter-group choice by inverse transform or, as the paper prints it, by
+ *     an alias table over the groups (Sec. 4.1);
  *   - floating-point biases (Sec. 4.3, Fig. SAMPLING2): scaling by the
  *     amortization factor lambda, an integer part decomposed into radix
  *     groups and a decimal part collected in one group sampled by rejection;
@@ -215,6 +217,42 @@ int o_pick_group(const uint32_t c[32], uint64_t r) {
     return -1;
 }
 
+/* Inter-group alias table (Sec. 4.1, Walker / Vose), exact in integers.  The
+ * 32 slots are the 32 groups; every slot holds W units, group k owns 32 T_k
+ * units in total (T_k its group total, W = sum T_k).  Readings fixed here:
+ * the small groups (32 T_k < W) and the large ones (32 T_k >= W) are taken in
+ * ascending k, each as a first-in first-out queue; the front small slot s
+ * keeps 32 T_s of its own units and takes the rest, W - 32 T_s, from the
+ * front large group l, which joins the back of the small queue once what it
+ * has left drops below W; slots left over keep all W units.  A draw takes
+ * slot j from the top 5 bits of the next word, then x = below64(W), and
+ * selects j when x < cut[j], else alias[j].  Group k is then selected by
+ * exactly 32 T_k of the 32 W (j, x) pairs. */
+void o_alias_table(const uint64_t T[32], uint64_t cut[32], uint32_t alias[32]) {
+    u128 W = 0, U[32];
+    for (int k = 0; k < 32; k++) W += T[k];
+    for (int k = 0; k < 32; k++) U[k] = (u128)T[k] * 32;
+    int small[32], large[32], ns = 0, nl = 0, hs = 0, hl = 0;
+    for (int k = 0; k < 32; k++) {
+        if (U[k] < W) small[ns++] = k; else large[nl++] = k;
+    }
+    for (int k = 0; k < 32; k++) { cut[k] = (uint64_t)W; alias[k] = (uint32_t)k; }
+    while (hs < ns && hl < nl) {
+        const int sm = small[hs++], l = large[hl];
+        cut[sm] = (uint64_t)U[sm];
+        alias[sm] = (uint32_t)l;
+        U[l] -= W - U[sm];
+        if (U[l] < W) { hl++; small[ns++] = l; }
+    }
+}
+
+/* Test hook: the group selected by slot j and value x. */
+int o_alias_pick(const uint64_t T[32], uint32_t j, uint64_t x) {
+    uint64_t cut[32]; uint32_t alias[32];
+    o_alias_table(T, cut, alias);
+    return x < cut[j] ? (int)j : (int)alias[j];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Graph state.                                                              */
 /* ------------------------------------------------------------------------ */
@@ -237,6 +275,7 @@ typedef struct {
     int adaptive;
     uint32_t alpha, beta;
     uint32_t fbits;    /* 0: integer biases; F > 0: fixed-point biases with F fraction bits */
+    int alias;         /* 1: inter-group choice by the alias table instead of inverse transform */
     ovtx *v;
 } ograph;
 
@@ -349,15 +388,15 @@ void o_free(ograph *G) {
  * their input order; seq of an edge is its rank among u's edges, and the
  * per-vertex sequence counter starts at d. */
 int o_build(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
-            int adaptive, uint32_t alpha, uint32_t beta, uint32_t fbits, ograph **out) {
+            int adaptive, uint32_t alpha, uint32_t beta, uint32_t fbits, int alias, ograph **out) {
     *out = NULL;
-    if (n == 0 || fbits > 16) return O_EINVAL;
+    if (n == 0 || fbits > 16 || (alias && fbits)) return O_EINVAL;
     for (uint64_t e = 0; e < m; e++) {
         if (src[e] >= n || dst[e] >= n) return O_ERANGE;
         if (w[e] == 0) return O_EWEIGHT;
     }
     ograph *G = calloc(1, sizeof(ograph));
-    G->n = n; G->adaptive = adaptive; G->alpha = alpha; G->beta = beta; G->fbits = fbits;
+    G->n = n; G->adaptive = adaptive; G->alpha = alpha; G->beta = beta; G->fbits = fbits; G->alias = alias;
     G->v = calloc(n, sizeof(ovtx));
     if (!G->v) { free(G); return O_ENOMEM; }
     uint32_t *deg = calloc(n, 4);
@@ -393,7 +432,13 @@ static uint32_t step_from(const ograph *G, uint32_t u, ostream *s, int ppr, uint
     uint64_t W = 0;
     uint32_t c[32];
     int k;
-    if (!G->fbits) {
+    if (G->alias) {
+        uint64_t T[32];
+        for (int j = 0; j < 32; j++) { T[j] = (uint64_t)x->g[j].c << j; W += T[j]; }
+        const uint32_t slot = st_next32(s) >> 27;
+        const uint64_t r = st_below64(s, W);
+        k = o_alias_pick(T, slot, r);
+    } else if (!G->fbits) {
         for (int j = 0; j < 32; j++) { c[j] = x->g[j].c; W += (uint64_t)c[j] << j; }
         uint64_t r = st_below64(s, W);
         k = o_pick_group(c, r);
