@@ -69,7 +69,13 @@ typedef struct {
                                k and the decimal group last; inside the decimal group a candidate
                                (from its list, or the whole adjacency when it is dense) is accepted
                                when the top F bits of the next random word are below its fraction. */
-    uint32_t reserved;      /* 0 */
+    uint32_t alias_table;   /* 0: inter-group choice by inverse transform over the groups in ascending k
+                               (default).  1: by an alias table over the 32 groups, as the paper
+                               prints it (Sec. 4.1): slot j = top 5 bits of the next random word,
+                               x = below64(W), group j if x < cut_j else alias_j, with an exact
+                               integer Walker/Vose table (512 B per vertex beside the header,
+                               rebuilt for every vertex an update touches).  Integer biases only
+                               (frac_bits must be 0). */
 } bingo_config;
 
 typedef struct {

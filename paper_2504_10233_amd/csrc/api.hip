@@ -43,6 +43,7 @@ static void release(bingo_graph* g) {
     for (int i = 0; i < PHASE_EVENTS; ++i)
         if (g->ev[i]) hipEventDestroy(g->ev[i]);
     hipFree(g->hdr);
+    hipFree(g->alias);
     hipFree(g->pool);
     hipFree(g->d_ctl);
     hipFree(g->d_err);
@@ -66,7 +67,7 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     if (n == 0 || n >= (1u << 31) || m >= (1ull << 32)) return BINGO_E_INVALID;
     if (m && (!d_src || !d_dst || !d_w)) return BINGO_E_INVALID;
     if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100) return BINGO_E_INVALID;
-    if (cfg->frac_bits > 16 || cfg->reserved != 0) return BINGO_E_INVALID;
+    if (cfg->frac_bits > 16 || cfg->alias_table > 1 || (cfg->alias_table && cfg->frac_bits)) return BINGO_E_INVALID;
     hipStream_t st = (hipStream_t)stream;
     bingo_graph* g = new (std::nothrow) bingo_graph();
     if (!g) return BINGO_E_OOM;
@@ -75,8 +76,10 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     g->rule.alpha = cfg->alpha_pct;
     g->rule.beta = cfg->beta_pct;
     g->rule.fbits = cfg->frac_bits;
+    g->rule.alias = nullptr;
+    g->alias_mode = cfg->alias_table;
     g->pool_words = cfg->pool_bytes / 4;
-    g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr;
+    g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr; g->alias = nullptr;
     if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
         hipMalloc(&g->d_ctl, CTL_WORDS * 8) != hipSuccess || hipMalloc(&g->d_err, 4) != hipSuccess) {
         release(g);

@@ -217,6 +217,49 @@ __global__ void k_quantize(uint64_t m, const float* __restrict__ b, double lambd
     }
 }
 
+// Inter-group alias rows (alias-table mode; Sec. 4.1), exact in integers: the
+// 32 slots are the 32 groups, every slot holds W units and group k owns
+// 32 c_k 2^k of them.  Small groups (32 T_k < W) and large ones are two
+// first-in first-out queues in ascending k; the front small slot keeps its own
+// units and takes the rest from the front large group, which joins the back of
+// the small queue once its remainder drops below W; leftover slots keep all W
+// units.  Entry j = {cut lo, cut hi, alias, 0}: a draw (j, x < W) selects j when
+// x < cut, else alias.  One thread per vertex.
+__global__ void k_alias_rows(const uint32_t* __restrict__ hdr, uint32_t n, const uint32_t* __restrict__ list,
+                             const unsigned long long* __restrict__ dcount, uint64_t maxc, uint4* __restrict__ alias) {
+    const uint64_t cnt = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = list ? list[i] : (uint32_t)i;
+        if (u >= n) continue;  // a rejected stream's bad source id
+        const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        uint4* row = alias + (size_t)u * ALIAS_ENTRIES;
+        const uint32_t onem = h[H_ONEMASK];
+        unsigned __int128 U[32], W = 0;
+        for (int k = 0; k < 32; ++k) {
+            const uint64_t T = (uint64_t)slot_count(h[H_CNT + k], onem, (uint32_t)k) << k;
+            U[k] = (unsigned __int128)T * 32u;
+            W += T;
+        }
+        uint8_t small[32], large[32];
+        int ns = 0, nl = 0, hs = 0, hl = 0;
+        uint64_t cut[32];
+        uint32_t al[32];
+        for (int k = 0; k < 32; ++k) {
+            if (U[k] < W) small[ns++] = (uint8_t)k; else large[nl++] = (uint8_t)k;
+            cut[k] = (uint64_t)W;
+            al[k] = (uint32_t)k;
+        }
+        while (hs < ns && hl < nl) {
+            const int sm = small[hs++], l = large[hl];
+            cut[sm] = (uint64_t)U[sm];
+            al[sm] = (uint32_t)l;
+            U[l] -= W - U[sm];
+            if (U[l] < W) { ++hl; small[ns++] = (uint8_t)l; }
+        }
+        for (int k = 0; k < 32; ++k) row[k] = make_uint4((uint32_t)cut[k], (uint32_t)(cut[k] >> 32), al[k], 0u);
+    }
+}
+
 int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
     int b = 0;
     while (b < 64 && (v >> b)) ++b;
@@ -224,6 +267,13 @@ int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
 }
 
 }  // namespace
+
+void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
+                hipStream_t st) {
+    if (!g->alias || max_count == 0) return;
+    hipLaunchKernelGGL(k_alias_rows, dim3(grid_for(max_count, 256)), dim3(256), 0, st, (const uint32_t*)g->hdr, g->n,
+                       list, count, max_count, g->alias);
+}
 
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st) {
     if (m == 0) return BINGO_OK;
@@ -289,6 +339,14 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
     g->pool_words = pool_words;
     hipLaunchKernelGGL(k_fill, dim3(vgrid), dim3(WB), 0, st, n, start, cdst, cw, adj_off, list_off, (uint64_t)tot[0],
                        g->hdr, g->pool, g->rule);
+    if (g->alias_mode) {
+        if (hipMalloc(&g->alias, (size_t)n * ALIAS_ENTRIES * sizeof(uint4)) != hipSuccess) {
+            g->alias = nullptr;
+            return BINGO_E_OOM;
+        }
+        g->rule.alias = g->alias;
+        alias_rows(g, nullptr, nullptr, n, st);
+    }
     unsigned long long ctl[2] = {(unsigned long long)used, 0ull};
     HIPCHK(hipMemcpyAsync(g->d_ctl, ctl, 16, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));

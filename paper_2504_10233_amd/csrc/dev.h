@@ -60,7 +60,11 @@ enum { GT_EMPTY = 0, GT_ONE = 1, GT_DENSE = 2, GT_SPARSE = 3, GT_REGULAR = 4 };
 struct GroupRule {
     uint32_t adaptive, alpha, beta;
     uint32_t fbits;  // 0: integer biases; F: fixed-point biases with F fraction bits (Sec. 4.3)
+    // alias-table inter-group choice: ALIAS_ENTRIES entries {cut lo, cut hi, alias, 0} per vertex;
+    // nullptr: inverse transform
+    const uint4* alias;
 };
+#define ALIAS_ENTRIES 32
 
 // Group membership word of a stored weight: bit k set = member of group k.
 // Integer biases: the weight itself.  Fixed-point biases with F fraction bits:
@@ -191,6 +195,8 @@ struct bingo_graph {
     uint32_t n;
     GroupRule rule;
     uint32_t* hdr;          // n * HDR_WORDS
+    uint4* alias = nullptr;  // alias-table mode: n * ALIAS_ENTRIES entries
+    uint32_t alias_mode = 0;
     uint32_t* pool;         // device arena, pool_words u32
     uint64_t pool_words;
     unsigned long long* d_ctl;  // [0] words used, [1] garbage words
@@ -252,6 +258,10 @@ void phase_mark(bingo_graph* g, hipStream_t st, bool first);
         }                                                                          \
     } while (0)
 
+// Selection code of the walk kernels: 0 integer biases by inverse transform,
+// 1 fixed-point biases, 2 integer biases by the alias table.
+inline int walk_mode(const bingo_graph* g) { return g->rule.fbits ? 1 : (g->rule.alias ? 2 : 0); }
+
 // ---------------------------------------------------------------------------
 // Host launchers implemented in the .hip files.
 // ---------------------------------------------------------------------------
@@ -275,6 +285,9 @@ void sort_pairs_u64_dn(const uint64_t* keys_in, const uint32_t* vals_in, uint64_
                        uint64_t nmax, const unsigned long long* dn, int bits, void* temp, hipStream_t st);
 
 // build.hip
+// alias rows of the vertices list[0 .. *count) (list == nullptr: vertices 0 .. *count)
+void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
+                hipStream_t st);
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st);
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);

@@ -67,7 +67,7 @@ __device__ __forceinline__ bool has_edge(const uint32_t* __restrict__ nidx, cons
 // One lane per walk from the chunked device queue (as the DeepWalk kernel); in
 // every iteration a lane makes one proposal, so a rejected lane retries while
 // the others move on.  ctl[0] queue head, ctl[1] transitions, ctl[2] proposals.
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_node2vec(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                  const uint32_t* __restrict__ nidx,
                                                  const uint64_t* __restrict__ noff, uint32_t n, uint64_t nw,
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(TB) k_node2vec(const uint32_t* __restrict__ hd
             const uint64_t id = base + j;
             RandStream rs;
             rs_init_blk(rs, seed, id, s, t << 16);
-            uint32_t v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
+            uint32_t v = walk_step_body<SPEC, MODE>(hdr, pool, u, rs, rule);
             ++props;
             bool accept = true;
             if (v != STOP_VERTEX && prev != STOP_VERTEX) {
@@ -197,12 +197,12 @@ int build_index(bingo_graph* g, hipStream_t st) {
     return BINGO_OK;
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 void launch_n2v(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t L, uint64_t seed,
                 const uint32_t thr[3], uint32_t full, uint32_t* paths, unsigned long long* ctl, hipStream_t st) {
-    const int rg = resident_blocks((const void*)k_node2vec<SPEC, FB>);
+    const int rg = resident_blocks((const void*)k_node2vec<SPEC, MODE>);
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB));
-    hipLaunchKernelGGL((k_node2vec<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n2v_idx, g->n2v_off,
+    hipLaunchKernelGGL((k_node2vec<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n2v_idx, g->n2v_off,
                        g->n, nw, starts, base, L, seed, thr[0], thr[1], thr[2], full, paths, g->rule, ctl, g->d_err,
                        g->queue_chunk);
 }
@@ -241,9 +241,9 @@ int run_node2vec(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t b
     HIPCHK(hipMemsetAsync(ctl, 0, 24, st));
     if (nw) {
         switch (g->dense_spec) {
-            case 1: (g->rule.fbits ? launch_n2v<1, true> : launch_n2v<1, false>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
-            case 4: (g->rule.fbits ? launch_n2v<4, true> : launch_n2v<4, false>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
-            default: (g->rule.fbits ? launch_n2v<2, true> : launch_n2v<2, false>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
+            case 1: (walk_mode(g) == 1 ? launch_n2v<1, 1> : walk_mode(g) == 2 ? launch_n2v<1, 2> : launch_n2v<1, 0>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
+            case 4: (walk_mode(g) == 1 ? launch_n2v<4, 1> : walk_mode(g) == 2 ? launch_n2v<4, 2> : launch_n2v<4, 0>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
+            default: (walk_mode(g) == 1 ? launch_n2v<2, 1> : walk_mode(g) == 2 ? launch_n2v<2, 2> : launch_n2v<2, 0>)(g, nw, starts, base, L, seed, thr, full, paths, ctl, st); break;
         }
     }
     phase_mark(g, st, false);

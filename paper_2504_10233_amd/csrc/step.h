@@ -62,9 +62,11 @@ __device__ __forceinline__ uint32_t decimal_pick(const uint32_t* __restrict__ h,
 }
 
 // One transition from u (no termination test).  Returns the next vertex or
-// STOP_VERTEX for a vertex without out-edges.  FB: the graph holds fixed-point
-// biases (rule.fbits > 0); the integer instance carries no decimal-group code.
-template <int SPEC, bool FB>
+// STOP_VERTEX for a vertex without out-edges.  MODE 0: integer biases, inverse
+// transform over the groups; 1: fixed-point biases (rule.fbits > 0, decimal
+// group taken last); 2: integer biases, alias table (rule.alias).  Each
+// instance carries only its own selection code.
+template <int SPEC, int MODE>
 __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t u, RandStream& rs, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
@@ -73,35 +75,51 @@ __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ 
     const uint32_t d = q0.y;
     if (d == 0) return STOP_VERTEX;
     const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
-    const uint64_t r = rs_below64(rs, W);
     const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
     // groups in ascending k; fixed-point biases skip the slots below F (slot 0
     // is their decimal group, taken last)
     // (a one-element group's slot holds its member's destination; its count is 1)
-    const uint32_t fb = FB ? rule.fbits : 0u;
+    const uint32_t fb = (MODE == 1) ? rule.fbits : 0u;
     const uint32_t onem = q0.x;
     uint64_t acc = 0;
     int sel = -1;
     uint32_t csel = 0, raw = 0;
+    if constexpr (MODE == 2) {
+        // alias table: slot j from the top 5 bits of a word, then x < W against the slot's cut
+        const uint32_t j = rs_next32(rs) >> 27;
+        const uint4 e = rule.alias[(size_t)u * ALIAS_ENTRIES + j];
+        const uint64_t x = rs_below64(rs, W);
+        sel = x < (((uint64_t)e.y << 32) | e.x) ? (int)j : (int)e.z;
+        if (sel < 26) {
 #pragma unroll
-    for (int k = 0; k < 26; ++k) {
-        const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
-        if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
-        if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
-    }
-    if (sel < 0) {
-        const uint4 a = h4[8], b = h4[9];
-        const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+            for (int k = 0; k < 26; ++k)
+                if (k == sel) raw = c[k];
+        } else {
+            raw = hdr[(size_t)u * HDR_WORDS + H_CNT + sel];
+        }
+        csel = ((onem >> sel) & 1u) ? 1u : raw;
+    } else {
+        const uint64_t r = rs_below64(rs, W);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
-            acc += (uint64_t)ck << (26 + k);
-            if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
+        for (int k = 0; k < 26; ++k) {
+            const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
+            if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
+            if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
+        }
+        if (sel < 0) {
+            const uint4 a = h4[8], b = h4[9];
+            const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
+                acc += (uint64_t)ck << (26 + k);
+                if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
+            }
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, rs);
+    if (MODE == 1 && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, rs);
     if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
     if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
     const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);

@@ -61,11 +61,12 @@ __global__ void k_st_heads(const uint32_t* __restrict__ sk, uint64_t m, uint32_t
         head[p] = (p == 0 || sk[p] != sk[p - 1]) ? 1u : 0u;
 }
 
-// seg_start[segment] = first sorted position of each source
+// seg_start[segment] = first sorted position of each source, seg_src[segment] = the source
 __global__ void k_st_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hx, uint64_t m,
-                            uint32_t* __restrict__ seg_start) {
+                            const uint32_t* __restrict__ sk, uint32_t* __restrict__ seg_start,
+                            uint32_t* __restrict__ seg_src) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x)
-        if (head[p]) seg_start[hx[p]] = (uint32_t)p;
+        if (head[p]) { seg_start[hx[p]] = (uint32_t)p; seg_src[hx[p]] = sk[p]; }
 }
 
 // Pool words for the current record, taken with one compare-and-swap on the
@@ -490,7 +491,7 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
     uint32_t* sv = (uint32_t*)take(m * 4);
     uint32_t* head = (uint32_t*)take(m * 4);
     uint32_t* seg = (uint32_t*)take(m * 4);
-    (void)take(m * 4);
+    uint32_t* seg_src = (uint32_t*)take(m * 4);
     uint64_t* hx = (uint64_t*)take(m * 8);
     unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
     unsigned long long* nseg = (unsigned long long*)take(256);
@@ -503,11 +504,13 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
     sort_pairs_u32(src, ids, sk, sv, m, bits_for_n(g->n), tmp, st);
     hipLaunchKernelGGL(k_st_heads, dim3(grid_for(m)), dim3(TB), 0, st, sk, m, head);
     scan_u32_to_u64(head, hx, m, tmp, nseg, st);
-    hipLaunchKernelGGL(k_st_starts, dim3(grid_for(m)), dim3(TB), 0, st, head, hx, m, seg);
+    hipLaunchKernelGGL(k_st_starts, dim3(grid_for(m)), dim3(TB), 0, st, head, hx, m, sk, seg, seg_src);
     phase_mark(g, st, false);
     hipLaunchKernelGGL(k_st_apply, dim3(ST_GRID), dim3(TB), 0, st, (const uint32_t*)g->d_err,
                        (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
                        g->pool_words, g->rule, g->d_err, out);
+    // alias-table mode: the sources' inter-group tables (with bad records nothing changed: rewritten as they were)
+    alias_rows(g, seg_src, nseg, m, st);
     phase_mark(g, st, false);
     unsigned long long o[ST_CTRS], ns = 0;
     uint32_t err = 0;

@@ -1691,6 +1691,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                            (const uint32_t*)g->pool, g->hdr);
     }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
+    // alias-table mode: the touched vertices' inter-group tables (a rejected batch rewrites them unchanged)
+    alias_rows(g, p->tv, uc + UC_T, R, st);
 }
 
 static UpdPlan* get_plan(bingo_graph* g, uint64_t rmax, uint64_t cmax_min) {

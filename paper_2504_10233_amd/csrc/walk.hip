@@ -34,7 +34,7 @@ struct StepState {
     bool pending;
 };
 
-template <bool FB>
+template <int MODE>
 __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                uint32_t u, StepState& ss, GroupRule rule) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
@@ -42,35 +42,51 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
     const uint32_t d = q0.y;
     if (d == 0) return STOP_VERTEX;
     const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
-    const uint64_t r = rs_below64(ss.rs, W);
     const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
                             q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
     // groups in ascending k; fixed-point biases skip the slots below F (slot 0
     // is their decimal group, taken last)
     // (a one-element group's slot holds its member's destination; its count is 1)
-    const uint32_t fb = FB ? rule.fbits : 0u;
+    const uint32_t fb = (MODE == 1) ? rule.fbits : 0u;
     const uint32_t onem = q0.x;
     uint64_t acc = 0;
     int sel = -1;
     uint32_t csel = 0, raw = 0;
+    if constexpr (MODE == 2) {
+        // alias table: slot j from the top 5 bits of a word, then x < W against the slot's cut
+        const uint32_t j = rs_next32(ss.rs) >> 27;
+        const uint4 e = rule.alias[(size_t)u * ALIAS_ENTRIES + j];
+        const uint64_t x = rs_below64(ss.rs, W);
+        sel = x < (((uint64_t)e.y << 32) | e.x) ? (int)j : (int)e.z;
+        if (sel < 26) {
 #pragma unroll
-    for (int k = 0; k < 26; ++k) {
-        const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
-        if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
-        if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
-    }
-    if (sel < 0) {
-        const uint4 a = h4[8], b = h4[9];
-        const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+            for (int k = 0; k < 26; ++k)
+                if (k == sel) raw = c[k];
+        } else {
+            raw = hdr[(size_t)u * HDR_WORDS + H_CNT + sel];
+        }
+        csel = ((onem >> sel) & 1u) ? 1u : raw;
+    } else {
+        const uint64_t r = rs_below64(ss.rs, W);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
-            acc += (uint64_t)ck << (26 + k);
-            if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
+        for (int k = 0; k < 26; ++k) {
+            const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
+            if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
+            if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
+        }
+        if (sel < 0) {
+            const uint4 a = h4[8], b = h4[9];
+            const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
+                acc += (uint64_t)ck << (26 + k);
+                if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
+            }
         }
     }
     const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (FB && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, ss.rs);
+    if (MODE == 1 && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, ss.rs);
     if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
     if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
     const uint32_t t = group_type(csel, d, rule);
@@ -94,7 +110,7 @@ __device__ __forceinline__ uint32_t step_attempt(const uint32_t* __restrict__ po
 }
 
 // ------------------------------------------------------------------ DeepWalk
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __restrict__ hdr,
                                                             const uint32_t* __restrict__ pool, uint32_t n,
                                                             uint64_t nw, const uint32_t* __restrict__ starts,
@@ -136,7 +152,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
             if (s < L) {
                 RandStream rs;
                 rs_init(rs, seed, base + j, s);
-                const uint32_t v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
+                const uint32_t v = walk_step_body<SPEC, MODE>(hdr, pool, u, rs, rule);
                 if (v == STOP_VERTEX) {
                     for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
                     j = NO_WALK;
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_persistent(const uint32_t* __re
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __restrict__ hdr,
                                                              const uint32_t* __restrict__ pool, uint32_t n,
                                                              uint64_t nw, const uint32_t* __restrict__ starts,
@@ -195,7 +211,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
         uint32_t v = PENDING;
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
-            v = step_begin<FB>(hdr, pool, u, ss, rule);
+            v = step_begin<MODE>(hdr, pool, u, ss, rule);
         }
         if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
@@ -214,7 +230,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                       uint32_t n, uint64_t nw, const uint32_t* __restrict__ starts,
                                                       uint64_t base, uint32_t L, uint32_t s, uint64_t seed,
@@ -236,7 +252,7 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
         if (u != STOP_VERTEX) {
             RandStream rs;
             rs_init(rs, seed, base + j, s);
-            v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
+            v = walk_step_body<SPEC, MODE>(hdr, pool, u, rs, rule);
             steps += (v != STOP_VERTEX);
         }
         row[s + 1] = v;
@@ -296,7 +312,7 @@ __global__ void __launch_bounds__(TB) k_ppr_bound(uint64_t nw, uint64_t base, ui
     }
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                        uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                        uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
@@ -338,7 +354,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
             RandStream rs;
             rs_init(rs, seed, base + j, s);
             rs_next32(rs);  // the termination word, known to be >= thr here
-            const uint32_t v = walk_step_body<SPEC, FB>(hdr, pool, u, rs, rule);
+            const uint32_t v = walk_step_body<SPEC, MODE>(hdr, pool, u, rs, rule);
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
                 j = NO_WALK;
@@ -354,7 +370,7 @@ __global__ void __launch_bounds__(TB) k_ppr_persistent(const uint32_t* __restric
     wave_add_u64(ctl + 1, steps);
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                         uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                         uint32_t R, uint64_t seed, uint64_t base, GroupRule rule,
@@ -398,7 +414,7 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
             rs_next32(ss.rs);  // the termination word, known to be >= thr here
-            v = step_begin<FB>(hdr, pool, u, ss, rule);
+            v = step_begin<MODE>(hdr, pool, u, ss, rule);
         }
         if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
         if (j != NO_WALK && v != PENDING) {
@@ -426,7 +442,7 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
 // contiguous runs instead of one partial-sector store per lane.  A bin that
 // would overflow sets a flag and the query is rerun with exact per-walk
 // segments.  ctl[0] queue head, ctl[1] transitions, ctl[2] overflow.
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t n, uint32_t nsrc, const uint32_t* __restrict__ sources,
                                                    uint32_t R, uint64_t seed, uint64_t base, uint32_t thr,
@@ -476,7 +492,7 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 } else {
                     rs_init(ss.rs, seed, base + j, s);
                     if (rs_next32(ss.rs) < thr) j = NO_WALK;
-                    else v = step_begin<FB>(hdr, pool, u, ss, rule);
+                    else v = step_begin<MODE>(hdr, pool, u, ss, rule);
                 }
             }
             if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
@@ -540,7 +556,7 @@ __global__ void __launch_bounds__(TB) k_ppr_start(uint32_t n, uint32_t nsrc, con
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl[3] = nw;
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                  uint32_t R, uint32_t s, uint64_t seed, uint64_t base,
                                                  GroupRule rule, const uint64_t* __restrict__ seg,
@@ -565,7 +581,7 @@ __global__ void __launch_bounds__(TB) k_ppr_step(const uint32_t* __restrict__ hd
                 RandStream rs;
                 rs_init(rs, seed, base + id, s);
                 rs_next32(rs);
-                v = walk_step_body<SPEC, FB>(hdr, pool, in_v[a], rs, rule);
+                v = walk_step_body<SPEC, MODE>(hdr, pool, in_v[a], rs, rule);
                 const uint64_t p0 = seg[id], l = len[id];
                 if (v == STOP_VERTEX) {
                     for (uint64_t x = p0 + 1 + s; x < p0 + l; ++x) vis[x] = VPAD;
@@ -869,33 +885,33 @@ int bits_for(uint64_t v) {
     return b;
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 void deepwalk_kernels(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t L, uint64_t seed,
                       uint32_t* paths, uint32_t mode, unsigned long long* ctl, hipStream_t st) {
     if (mode == BINGO_WALK_PER_STEP) {
         const uint32_t grid = grid_for(nw);
         if (L == 0) {
             // only the start entries
-            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
         }
         for (uint32_t s = 0; s < L; ++s)
-            hipLaunchKernelGGL((k_deepwalk_step<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
+            hipLaunchKernelGGL((k_deepwalk_step<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts, base,
                                L, s, seed, paths, g->rule, ctl, g->d_err);
     } else {
-        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved<SPEC, FB> : (const void*)k_deepwalk_persistent<SPEC, FB>;
+        const void* kern = g->walk_variant ? (const void*)k_deepwalk_interleaved<SPEC, MODE> : (const void*)k_deepwalk_persistent<SPEC, MODE>;
         const int rg = resident_grid(kern, g->blocks_per_cu);
         const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
         if (g->walk_variant)
-            hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
         else
-            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
+            hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
     }
 }
 
-template <int SPEC, bool FB>
+template <int SPEC, int MODE>
 void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t cap, uint64_t seed,
                  uint64_t base, const uint64_t* seg, const uint32_t* len, uint32_t mode,
                  uint64_t* idA, uint32_t* vA, uint64_t* idB, uint32_t* vB, unsigned long long* ctl, uint32_t* vis,
@@ -908,19 +924,19 @@ void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_
         for (uint32_t s = 0; s < cap; ++s) {
             const int in_slot = s & 1;
             hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, ctl + 3 + (in_slot ^ 1), 0ull);
-            hipLaunchKernelGGL((k_ppr_step<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base,
+            hipLaunchKernelGGL((k_ppr_step<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, R, s, seed, base,
                                g->rule, seg, len, in_slot ? idB : idA, in_slot ? vB : vA, in_slot ? idA : idB,
                                in_slot ? vA : vB, ctl, in_slot, vis);
         }
     } else {
-        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC, FB> : (const void*)k_ppr_persistent<SPEC, FB>;
+        const void* kern = g->walk_variant ? (const void*)k_ppr_interleaved<SPEC, MODE> : (const void*)k_ppr_persistent<SPEC, MODE>;
         const int rg = resident_grid(kern, g->blocks_per_cu);
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
         if (g->walk_variant)
-            hipLaunchKernelGGL((k_ppr_interleaved<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+            hipLaunchKernelGGL((k_ppr_interleaved<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
                                seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
         else
-            hipLaunchKernelGGL((k_ppr_persistent<SPEC, FB>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
+            hipLaunchKernelGGL((k_ppr_persistent<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
                                seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
     }
 }
@@ -939,7 +955,7 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
         return BINGO_OK;
     }
     switch (g->dense_spec) {
-#define DWK(S) (g->rule.fbits ? deepwalk_kernels<S, true> : deepwalk_kernels<S, false>)
+#define DWK(S) (walk_mode(g) == 1 ? deepwalk_kernels<S, 1> : walk_mode(g) == 2 ? deepwalk_kernels<S, 2> : deepwalk_kernels<S, 0>)
         case 1: DWK(1)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
         case 4: DWK(4)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
         default: DWK(2)(g, nw, starts, base, L, seed, paths, mode, ctl, st); break;
@@ -1037,18 +1053,18 @@ static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources
     phase_mark(g, st, true);
     HIPCHK(hipMemsetAsync(bin_cnt, 0, (uint64_t)nsrc * 4, st));
     phase_mark(g, st, false);
-#define BINGO_BINNED(S_, F_)                                                                                          \
+#define BINGO_BINNED(S_, M_)                                                                                          \
     do {                                                                                                           \
-        const int rg = resident_grid((const void*)k_ppr_binned<S_, F_>, g->blocks_per_cu);                             \
+        const int rg = resident_grid((const void*)k_ppr_binned<S_, M_>, g->blocks_per_cu);                             \
         const uint64_t nw = (uint64_t)nsrc * R;                                                                    \
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1); \
-        hipLaunchKernelGGL((k_ppr_binned<S_, F_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
+        hipLaunchKernelGGL((k_ppr_binned<S_, M_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
                            seed, base, thr, cap, g->rule, C, bin_cnt, vis, ctl, g->d_err, g->queue_chunk);          \
     } while (0)
     switch (g->dense_spec) {
-        case 1: if (g->rule.fbits) BINGO_BINNED(1, true); else BINGO_BINNED(1, false); break;
-        case 4: if (g->rule.fbits) BINGO_BINNED(4, true); else BINGO_BINNED(4, false); break;
-        default: if (g->rule.fbits) BINGO_BINNED(2, true); else BINGO_BINNED(2, false); break;
+        case 1: if (walk_mode(g) == 1) BINGO_BINNED(1, 1); else if (walk_mode(g) == 2) BINGO_BINNED(1, 2); else BINGO_BINNED(1, 0); break;
+        case 4: if (walk_mode(g) == 1) BINGO_BINNED(4, 1); else if (walk_mode(g) == 2) BINGO_BINNED(4, 2); else BINGO_BINNED(4, 0); break;
+        default: if (walk_mode(g) == 1) BINGO_BINNED(2, 1); else if (walk_mode(g) == 2) BINGO_BINNED(2, 2); else BINGO_BINNED(2, 0); break;
     }
 #undef BINGO_BINNED
     phase_mark(g, st, false);
@@ -1138,7 +1154,7 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
         vB = (uint32_t*)(act + 2 * al(nw * 8) + al(nw * 4));
     }
     switch (g->dense_spec) {
-#define PPK(S) (g->rule.fbits ? ppr_kernels<S, true> : ppr_kernels<S, false>)
+#define PPK(S) (walk_mode(g) == 1 ? ppr_kernels<S, 1> : walk_mode(g) == 2 ? ppr_kernels<S, 2> : ppr_kernels<S, 0>)
         case 1: PPK(1)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
         case 4: PPK(4)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;
         default: PPK(2)(g, nsrc, sources, R, cap, seed, base, seg, len, mode, idA, vA, idB, vB, ctl, vis, st); break;

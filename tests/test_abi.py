@@ -85,6 +85,6 @@ def test_build_rejects_bad_frac_bits_without_gpu():
     from paper_2504_10233_amd.binding import _Config
     lib = ctypes.CDLL(_lib_path())
     out = ctypes.c_void_p()
-    for fb, res in ((17, 0), (8, 1)):
-        cfg = _Config(ctypes.sizeof(_Config), 1, 40, 10, 0, fb, res)
+    for fb, al in ((17, 0), (8, 1), (0, 2)):  # too many fraction bits; alias with fixed point; bad flag
+        cfg = _Config(ctypes.sizeof(_Config), 1, 40, 10, 0, fb, al)
         assert lib.bingo_build(ctypes.byref(cfg), 10, 0, None, None, None, None, ctypes.byref(out)) == -1
