@@ -237,6 +237,7 @@ def workload_deepwalk(args):
                 "build_s": build_s, "steps_detail": rows})
     res["float_bias"] = float_vs_integer(n, src, dst, w, starts, paths, c)
     res["adaption"] = adaption_vs_baseline(n, src, dst, w, starts, paths, c)
+    res["alias"] = alias_vs_its(n, src, dst, w, starts, paths, c, batches[:2])
     # sampled parity against the oracle after the same batches
     if not args.no_cpu_baseline:
         import oracle as O
@@ -368,6 +369,46 @@ def adaption_vs_baseline(n, src, dst, w, starts, paths, c):
     log("adaption: walk kernel %.2f ms (GA) vs %.2f ms (BS, all regular) (x%.3f); pool memory BS/GA x%.3f, "
         "model BS/GA x%.3f" % (out["ga"]["walk_kernel_ms"], out["bs"]["walk_kernel_ms"], out["bs_over_ga_time"],
                                out["bs_over_ga_pool"], out["bs_over_ga_model"]))
+    return out
+
+
+def alias_vs_its(n, src, dst, w, starts, paths, c, batches):
+    """Inter-group selection by inverse transform over the group totals (the default) against the
+    32-slot alias rows: the same edges built both ways, DeepWalk of length 80 from every vertex, three
+    runs each, then the first two 2e6-record update batches of this workload on each; the second
+    batch's pipeline time (which includes rebuilding the rows of every touched vertex) is reported, the
+    first one's carrying the allocation of the update plan."""
+    import torch
+    import synth
+    from paper_2504_10233_amd import Graph
+    out = {}
+    for name, alias in (("its", False), ("alias", True)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g = Graph(n, src, dst, w, device=w.device, alias_table=alias)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t
+        ms = []
+        for r in range(3):
+            g.walk(starts, 80, synth.SEEDS["walks"] + c + 3000 + r, base=0, out=paths)
+            torch.cuda.synchronize()
+            ms.append(g.last_phase_ms()[0])
+        for b in batches:
+            g.update(*b)
+            torch.cuda.synchronize()
+            upd = g.last_phase_ms()[0]
+        mem = g.memory()
+        out[name] = {"walk_kernel_ms": sorted(ms)[1], "build_s": build, "update_pipeline_ms": upd,
+                     "alias_bytes": mem["alias_bytes"], "header_bytes": mem["header_bytes"]}
+        g.close()
+        torch.cuda.synchronize()
+    out["alias_over_its_time"] = out["alias"]["walk_kernel_ms"] / out["its"]["walk_kernel_ms"]
+    out["alias_over_its_update"] = out["alias"]["update_pipeline_ms"] / out["its"]["update_pipeline_ms"]
+    log("alias rows: walk kernel %.2f ms vs %.2f ms inverse transform (x%.3f); update batch %.2f ms vs %.2f ms; "
+        "rows %.2f GB beside %.2f GB of headers" %
+        (out["alias"]["walk_kernel_ms"], out["its"]["walk_kernel_ms"], out["alias_over_its_time"],
+         out["alias"]["update_pipeline_ms"], out["its"]["update_pipeline_ms"], out["alias"]["alias_bytes"] / 1e9,
+         out["alias"]["header_bytes"] / 1e9))
     return out
 
 

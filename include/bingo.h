@@ -99,6 +99,7 @@ typedef struct {
     uint64_t groups_by_type[5];     /* number of groups per type */
     uint64_t model_ga_bytes;        /* paper's memory model with adaption (Sec. 5.1) */
     uint64_t model_bs_bytes;        /* ... and without (all regular, Sec. 6.2) */
+    uint64_t alias_bytes;           /* inter-group alias rows (alias_table = 1): 512 B per vertex, else 0 */
 } bingo_mem_stats;
 
 /*

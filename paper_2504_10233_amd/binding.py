@@ -48,7 +48,7 @@ class _MemStats(C.Structure):
                 ("header_bytes", C.c_uint64), ("adjacency_bytes", C.c_uint64),
                 ("adjacency_reserved_bytes", C.c_uint64), ("list_bytes", C.c_uint64),
                 ("list_reserved_bytes", C.c_uint64), ("groups_by_type", C.c_uint64 * 5),
-                ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64)]
+                ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64), ("alias_bytes", C.c_uint64)]
 
 
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",

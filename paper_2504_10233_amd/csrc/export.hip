@@ -199,5 +199,6 @@ int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st) {
     for (int t = 0; t < 5; ++t) out->groups_by_type[t] = t ? a[t] : 0;
     out->model_ga_bytes = a[11];
     out->model_bs_bytes = a[12];
+    out->alias_bytes = g->alias ? (uint64_t)g->n * ALIAS_ENTRIES * sizeof(uint4) : 0;
     return BINGO_OK;
 }

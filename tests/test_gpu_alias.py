@@ -36,6 +36,7 @@ def test_walks_and_ppr(adaptive, variant, spec):
     n, src, dst, w = random_graph(1)
     og, gg = aboth(n, src, dst, w, adaptive)
     assert_same_structure(og, gg, "alias build")
+    assert gg.memory()["alias_bytes"] == n * 32 * 16
     gg.set_tuning(walk_variant=variant, dense_spec=spec)
     starts = np.array([0, 5, 6, 3, 1, 2, 7, 40, 6, 6] * 40)
     for mode in (0, 1):
