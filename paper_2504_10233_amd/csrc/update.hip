@@ -163,7 +163,8 @@ __global__ void k_seg_end(const unsigned long long* __restrict__ uc, const uint3
 __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
                             const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
                             const uint32_t* __restrict__ te, const uint32_t* __restrict__ hdr,
-                            uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold, uint32_t split,
+                            uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold, uint32_t* __restrict__ vacap,
+                            uint32_t* __restrict__ vnseq, uint64_t* __restrict__ vadj, uint32_t split,
                             uint32_t* __restrict__ blist) {
     const uint64_t T = uc[UC_T];
     GRID_LOOP(t, rmax) {
@@ -171,8 +172,12 @@ __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, 
         if (t < T) {
             const uint32_t nd = te[t] - tdl[t];
             const uint32_t ni = tdl[t] - ts[t];
-            const uint32_t d = hdr[(size_t)tv[t] * HDR_WORDS + H_DEG];
+            const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
+            const uint32_t d = h[H_DEG];
             dold[t] = d;
+            vacap[t] = h[H_ACAP];
+            vnseq[t] = h[H_NSEQ];
+            vadj[t] = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
             v = nd ? (uint64_t)d + ni : 0ull;
             if (split && d + ni > split) blist[atomicAdd(uc + UC_NBIG, 1ull)] = (uint32_t)t;
         }
@@ -191,18 +196,23 @@ __device__ __forceinline__ uint32_t find_t(const uint64_t* __restrict__ foff, ui
 
 // Candidate search: every element of the flat space (live edges, then inserts,
 // of each touched vertex with deletes) whose dst is among the vertex's delete
-// targets becomes a candidate (run << 32 | seq, virtual index).  The grid loops
-// over ranges of MB elements.  A range stages what its elements look up: the
-// offsets and header fields of the (at most MV) touched vertices it spans and
-// the dst of their batch records (every 2^sh-th record when there are more than
-// LDS_TARGETS), so the per-element vertex search and target search run in LDS
-// but for at most sh steps; a range that spans more vertices than MV searches
-// them in global memory instead.  Hits collect in an LDS buffer that is
-// written out (one atomic per flush) when it could not take another range, so
-// the global atomics number about one per OUTCAP hits, not one per range.
+// targets becomes a candidate (run << 32 | seq, virtual index).  Each block
+// takes a contiguous run of ranges of MB elements.  For DESC ranges at a time
+// it first finds, one lane per range, the touched vertices owning the range's
+// first and last element and where its delete targets start, so a range then
+// needs only its staging loads before its elements: the offsets and header
+// fields of the (at most MV) touched vertices it spans, from the per-vertex
+// copies k_flat_size made, and the dst of their batch records (every 2^sh-th
+// record when there are more than LDS_TARGETS).  The per-element vertex search
+// and target search then run in LDS but for at most sh steps; a range that spans
+// more vertices than MV searches them in global memory instead.  Consecutive
+// ranges inside one vertex keep its staged state.  Hits collect in an LDS
+// buffer that is written out (one atomic per flush) when it could not take
+// another range, so the global atomics number about one per OUTCAP hits.
 constexpr uint32_t LDS_TARGETS = 2048;
 constexpr uint32_t MV = 128;      // staged vertices per range
 constexpr uint32_t OUTCAP = 2048;  // buffered hits per block (>= MB + a range's worth)
+constexpr uint32_t DESC = 64;     // ranges whose descriptors are found together (one lane each)
 static_assert(OUTCAP >= 2 * MB, "the hit buffer takes a full range after any flush threshold");
 
 // Wave-cooperative form of find_t over [0, tmax] (foff[0] = 0 <= f): each round
@@ -236,10 +246,11 @@ __device__ __forceinline__ uint32_t find_t_lds(const uint64_t* __restrict__ fo, 
 }
 
 __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ uc, const uint64_t* __restrict__ foff,
-                                              const uint32_t* __restrict__ tv, const uint32_t* __restrict__ ts,
-                                              const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
-                                              const uint64_t* __restrict__ sk, const uint32_t* __restrict__ sv,
-                                              int vb, const uint32_t* __restrict__ id, const uint32_t* __restrict__ hdr,
+                                              const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
+                                              const uint32_t* __restrict__ te, const uint32_t* __restrict__ vdeg,
+                                              const uint32_t* __restrict__ vacap, const uint32_t* __restrict__ vnseq,
+                                              const uint64_t* __restrict__ vadj, const uint64_t* __restrict__ sk,
+                                              const uint32_t* __restrict__ sv, int vb, const uint32_t* __restrict__ id,
                                               const uint32_t* __restrict__ pool, uint64_t* __restrict__ ckey,
                                               uint32_t* __restrict__ cval, uint64_t cap) {
     __shared__ uint64_t s_fo[MV];
@@ -247,157 +258,163 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
     __shared__ uint32_t tgt[LDS_TARGETS];
     __shared__ uint64_t okey[OUTCAP];
     __shared__ uint32_t oidx[OUTCAP];
-    __shared__ uint32_t range[5];  // tlo, thi, record base, staged flags, target sample shift
+    __shared__ uint32_t dlo[DESC], dhi[DESC], drb[DESC], dsh[DESC], dns[DESC];  // per-range descriptors
+    __shared__ uint32_t cspan[2];    // first and last touched vertex of a chunk of ranges
     __shared__ uint32_t wtot[TB / 64];
     __shared__ uint32_t ocount;
-    __shared__ uint32_t reuse;
-    __shared__ unsigned long long obase, vend;
+    __shared__ unsigned long long obase;
     const uint64_t F = uc[UC_F], T = uc[UC_T];
     const uint64_t nblk = (F + MB - 1) / MB;
     constexpr int PER = MB / TB;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) { ocount = 0; vend = 0; range[0] = 1; range[1] = 0; }
+    if (threadIdx.x == 0) ocount = 0;
+    uint32_t held = ~0u;  // the one vertex whose staged fields and targets the LDS still holds (block-uniform)
     // each block takes a contiguous run of ranges, so consecutive ranges of
     // one large vertex reuse its staged header fields and targets
     const uint64_t per = (nblk + gridDim.x - 1) / gridDim.x;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = std::min<uint64_t>(nblk, b0 + per);
-    for (uint64_t blk = b0; blk < b1; ++blk) {
-        const uint64_t f0 = blk * MB;
-        const uint64_t fl = std::min<uint64_t>(f0 + MB, F) - 1;
-        __syncthreads();  // the previous range's users of the shared state are done
-        if (threadIdx.x == 0)
-            reuse = (range[0] == range[1] && (range[3] & 3u) == 3u && fl < vend) ? 1u : 0u;
-        __syncthreads();
-        if (!reuse) {
-            // the vertices owning the range's first and last element: waves 0
-            // and 1 search in parallel, 64 probes per round trip
-            if (wave < 2) {
-                const uint32_t t = wave_find_t(foff, (uint32_t)T - 1, wave == 0 ? f0 : fl);
-                if (lane == 0) range[wave] = t;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const uint32_t tlo = range[0], thi = range[1];
-                const uint32_t rb = ts[tlo], re = te[thi];
-                uint32_t sh = 0;
-                while (((re - rb) + (1u << sh) - 1) >> sh > LDS_TARGETS) ++sh;
-                range[2] = rb;
-                range[3] = (thi - tlo < MV ? 1u : 0u) | 2u;
-                range[4] = sh;
-                vend = thi + 1 < T ? foff[thi + 1] : F;  // end of the last vertex's elements
-            }
-            __syncthreads();
-        }
-        const uint32_t tlo = range[0], thi = range[1], rbase = range[2], tsh = range[4];
-        const bool vstaged = range[3] & 1u;
-        const uint32_t nv = thi - tlo + 1;
-        if (vstaged && !reuse) {
-            for (uint32_t k = threadIdx.x; k < nv; k += TB) {
-                const uint32_t t = tlo + k;
-                const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-                s_fo[k] = foff[t];
-                s_v[0][k] = h[H_DEG]; s_v[1][k] = h[H_ACAP]; s_v[2][k] = h[H_NSEQ];
-                s_v[3][k] = h[H_ADJLO]; s_v[4][k] = h[H_ADJHI];
-                s_v[5][k] = ts[t]; s_v[6][k] = tdl[t]; s_v[7][k] = te[t];
-            }
-        }
-        if (!reuse) {
-            const uint32_t ns = (te[thi] - rbase + (1u << tsh) - 1) >> tsh;
-            for (uint32_t j = threadIdx.x; j < ns; j += TB) tgt[j] = key_dst(sk[rbase + (j << tsh)], vb);
+    for (uint64_t c0 = b0; c0 < b1; c0 += DESC) {
+        const uint32_t nc = (uint32_t)std::min<uint64_t>(DESC, b1 - c0);
+        __syncthreads();  // the previous chunk's readers of the descriptors are done
+        // the touched vertices owning the chunk's first and last element (waves 0 and 1, 64 probes per load)
+        if (wave < 2) {
+            const uint64_t f = wave == 0 ? c0 * MB : std::min<uint64_t>((c0 + nc) * MB, F) - 1;
+            const uint32_t t = wave_find_t(foff, (uint32_t)T - 1, f);
+            if (lane == 0) cspan[wave] = t;
         }
         __syncthreads();
-        // each thread looks at PER elements; hits stay in registers until the
-        // block has placed them in the LDS buffer
-        uint64_t hkey[PER];
-        uint32_t hidx[PER];
-        uint32_t nh = 0;
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
-            hkey[r] = 0;
-            hidx[r] = 0;
-            if (f < F) {
-                uint32_t d, acap, nseq, tsv, tdlv, tev;
-                uint64_t adj, fo;
+        // each range's first (wave 0) and last (wave 1) owner, searched between the two
+        if (wave < 2 && lane < nc) {
+            const uint64_t f0 = (c0 + lane) * MB;
+            const uint64_t f = wave == 0 ? f0 : std::min<uint64_t>(f0 + MB, F) - 1;
+            const uint32_t t = find_t(foff, cspan[0], cspan[1], f);
+            if (wave == 0) dlo[lane] = t; else dhi[lane] = t;
+        }
+        __syncthreads();
+        if (wave == 0 && lane < nc) {
+            const uint32_t rb = ts[dlo[lane]], re = te[dhi[lane]];
+            uint32_t sh = 0;
+            while (((re - rb) + (1u << sh) - 1) >> sh > LDS_TARGETS) ++sh;
+            drb[lane] = rb;
+            dsh[lane] = sh;
+            dns[lane] = ((re - rb) + (1u << sh) - 1) >> sh;
+        }
+        for (uint32_t jr = 0; jr < nc; ++jr) {
+            const uint64_t blk = c0 + jr;
+            const uint64_t f0 = blk * MB;
+            __syncthreads();  // descriptors written; the previous range's users of the shared state are done
+            const uint32_t tlo = dlo[jr], thi = dhi[jr], rbase = drb[jr], tsh = dsh[jr];
+            const bool vstaged = thi - tlo < MV;
+            const bool reuse = tlo == thi && held == tlo;
+            const uint32_t nv = thi - tlo + 1;
+            if (!reuse) {
                 if (vstaged) {
-                    const uint32_t k = find_t_lds(s_fo, nv, f);
-                    fo = s_fo[k];
-                    d = s_v[0][k]; acap = s_v[1][k]; nseq = s_v[2][k];
-                    adj = ((uint64_t)s_v[4][k] << 32) | s_v[3][k];
-                    tsv = s_v[5][k]; tdlv = s_v[6][k]; tev = s_v[7][k];
-                } else {
-                    const uint32_t t = find_t(foff, tlo, thi, f);
-                    const uint32_t* h = hdr + (size_t)tv[t] * HDR_WORDS;
-                    fo = foff[t];
-                    d = h[H_DEG]; acap = h[H_ACAP]; nseq = h[H_NSEQ];
-                    adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
-                    tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
+                    for (uint32_t k = threadIdx.x; k < nv; k += TB) {
+                        const uint32_t t = tlo + k;
+                        const uint64_t a = vadj[t];
+                        s_fo[k] = foff[t];
+                        s_v[0][k] = vdeg[t]; s_v[1][k] = vacap[t]; s_v[2][k] = vnseq[t];
+                        s_v[3][k] = (uint32_t)a; s_v[4][k] = (uint32_t)(a >> 32);
+                        s_v[5][k] = ts[t]; s_v[6][k] = tdl[t]; s_v[7][k] = te[t];
+                    }
                 }
-                const uint32_t i = (uint32_t)(f - fo);
-                const uint32_t dst = i < d ? pool[adj + 2ull * i] : id[sv[tsv + (i - d)]];
-                // lower bound of dst among the vertex's delete targets [tdlv, tev): first over
-                // the LDS samples at positions rbase + (j << tsh) inside [tdlv, tev), then
-                // over the records between two samples in global memory
-                const uint32_t jl = (tdlv - rbase + (1u << tsh) - 1) >> tsh;
-                const uint32_t jr = (tev - rbase + (1u << tsh) - 1) >> tsh;
-                uint32_t ja = jl, jb = jr;
-                while (ja < jb) {
-                    const uint32_t mid = (ja + jb) >> 1;
-                    if (tgt[mid] < dst) ja = mid + 1; else jb = mid;
-                }
-                uint32_t l = ja > jl ? rbase + ((ja - 1) << tsh) + 1 : tdlv;
-                uint32_t rr = ja < jr ? rbase + (ja << tsh) : tev;
-                while (l < rr) {
-                    const uint32_t mid = (l + rr) >> 1;
-                    if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
-                }
-                const bool found = l < tev && (tsh == 0 ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
-                if (found) {
-                    const uint32_t seq = i < d ? pool[adj + 2ull * acap + i] : nseq + (i - d);
-                    hkey[nh] = ((uint64_t)l << 32) | seq;
-                    hidx[nh] = i;
-                    ++nh;
-                }
+                const uint32_t ns = dns[jr];
+                for (uint32_t j = threadIdx.x; j < ns; j += TB) tgt[j] = key_dst(sk[rbase + (j << tsh)], vb);
             }
-        }
-        // place the hits at the end of the LDS buffer
-        uint32_t x = nh;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= (uint32_t)o) x += y;
-        }
-        if (lane == 63) wtot[wave] = x;
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < TB / 64; ++w) {
-            if (w < (int)wave) before += wtot[w];
-            total += wtot[w];
-        }
-        const uint32_t o0 = ocount + before + x - nh;
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            if ((uint32_t)r < nh) {
-                okey[o0 + r] = hkey[r];
-                oidx[o0 + r] = hidx[r];
-            }
-        }
-        __syncthreads();  // all threads have read ocount and written their hits
-        if (threadIdx.x == 0) ocount += total;
-        __syncthreads();
-        // flush when the buffer could not take another full range
-        if (ocount > OUTCAP - MB) {
-            if (threadIdx.x == 0) obase = atomicAdd(uc + UC_C, (unsigned long long)ocount);
+            held = tlo == thi ? tlo : ~0u;
             __syncthreads();
-            for (uint32_t k = threadIdx.x; k < ocount; k += TB) {
-                if (obase + k < cap) {
-                    ckey[obase + k] = okey[k];
-                    cval[obase + k] = oidx[k];
+            // each thread looks at PER elements; hits stay in registers until the
+            // block has placed them in the LDS buffer
+            uint64_t hkey[PER];
+            uint32_t hidx[PER];
+            uint32_t nh = 0;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
+                hkey[r] = 0;
+                hidx[r] = 0;
+                if (f < F) {
+                    uint32_t d, acap, nseq, tsv, tdlv, tev;
+                    uint64_t adj, fo;
+                    if (vstaged) {
+                        const uint32_t k = find_t_lds(s_fo, nv, f);
+                        fo = s_fo[k];
+                        d = s_v[0][k]; acap = s_v[1][k]; nseq = s_v[2][k];
+                        adj = ((uint64_t)s_v[4][k] << 32) | s_v[3][k];
+                        tsv = s_v[5][k]; tdlv = s_v[6][k]; tev = s_v[7][k];
+                    } else {
+                        const uint32_t t = find_t(foff, tlo, thi, f);
+                        fo = foff[t];
+                        d = vdeg[t]; acap = vacap[t]; nseq = vnseq[t];
+                        adj = vadj[t];
+                        tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
+                    }
+                    const uint32_t i = (uint32_t)(f - fo);
+                    const uint32_t dst = i < d ? pool[adj + 2ull * i] : id[sv[tsv + (i - d)]];
+                    // lower bound of dst among the vertex's delete targets [tdlv, tev): first over
+                    // the LDS samples at positions rbase + (j << tsh) inside [tdlv, tev), then
+                    // over the records between two samples in global memory
+                    const uint32_t jl = (tdlv - rbase + (1u << tsh) - 1) >> tsh;
+                    const uint32_t jh = (tev - rbase + (1u << tsh) - 1) >> tsh;
+                    uint32_t ja = jl, jb = jh;
+                    while (ja < jb) {
+                        const uint32_t mid = (ja + jb) >> 1;
+                        if (tgt[mid] < dst) ja = mid + 1; else jb = mid;
+                    }
+                    uint32_t l = ja > jl ? rbase + ((ja - 1) << tsh) + 1 : tdlv;
+                    uint32_t rr = ja < jh ? rbase + (ja << tsh) : tev;
+                    while (l < rr) {
+                        const uint32_t mid = (l + rr) >> 1;
+                        if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
+                    }
+                    const bool found = l < tev && (tsh == 0 ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
+                    if (found) {
+                        const uint32_t seq = i < d ? pool[adj + 2ull * acap + i] : nseq + (i - d);
+                        hkey[nh] = ((uint64_t)l << 32) | seq;
+                        hidx[nh] = i;
+                        ++nh;
+                    }
                 }
             }
+            // place the hits at the end of the LDS buffer
+            uint32_t x = nh;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= (uint32_t)o) x += y;
+            }
+            if (lane == 63) wtot[wave] = x;
             __syncthreads();
-            if (threadIdx.x == 0) ocount = 0;
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < TB / 64; ++w) {
+                if (w < (int)wave) before += wtot[w];
+                total += wtot[w];
+            }
+            const uint32_t o0 = ocount + before + x - nh;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                if ((uint32_t)r < nh) {
+                    okey[o0 + r] = hkey[r];
+                    oidx[o0 + r] = hidx[r];
+                }
+            }
+            __syncthreads();  // all threads have read ocount and written their hits
+            if (threadIdx.x == 0) ocount += total;
+            __syncthreads();
+            // flush when the buffer could not take another full range
+            if (ocount > OUTCAP - MB) {
+                if (threadIdx.x == 0) obase = atomicAdd(uc + UC_C, (unsigned long long)ocount);
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < ocount; k += TB) {
+                    if (obase + k < cap) {
+                        ckey[obase + k] = okey[k];
+                        cval[obase + k] = oidx[k];
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) ocount = 0;
+            }
         }
     }
     __syncthreads();
@@ -1530,11 +1547,14 @@ struct UpdPlan {
     unsigned long long* uc = nullptr;
     uint64_t *keys, *sk, *hx, *fsz, *foff, *ckey, *cks, *xk, *xks, *needw, *aoff, *xoff;
     uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold, *wv, *idest, *blist;
+    uint32_t *vacap, *vnseq;  // header fields of the touched vertices before the batch (k_flat_size)
+    uint64_t* vadj;
     unsigned long long* parts;
     BigItem* big_items;
     uint32_t *chunk_item, *ccnt, *bsur;
     void* tmp;
     uint32_t split = 0;  // the split threshold the captured graph was made with
+    uint32_t grid_an = PART_BLOCKS, grid_mu = PART_BLOCKS;  // resident blocks of k_analyze, k_mutate<false>
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_failed = false;
@@ -1562,17 +1582,32 @@ static void plan_free(UpdPlan* p) {
     delete p;
 }
 
+// Blocks of `kernel` resident at once on the current device (occupancy times
+// compute units), at most PART_BLOCKS.  The per-vertex kernels loop over their
+// vertices with a grid stride, so every block gets the same share of
+// latency-bound iterations; blocks beyond the resident count would only start
+// when the first ones end and then run a whole second share.
+static uint32_t resident_grid(const void* kernel, int block) {
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 4;
+    return (uint32_t)std::min<uint64_t>((uint64_t)cus * per, PART_BLOCKS);
+}
+
 static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const uint64_t R = rmax, C = cmax;
     const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)),
                                  scan_temp_bytes(R + 1));
-    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 10 + al(C * 8) * 2 + al(R * 4) * 16 +
+    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 11 + al(C * 8) * 2 + al(R * 4) * 18 +
                          al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + al(BIG_IMAX * sizeof(BigItem)) +
                          2 * al(BIG_CMAX * 4) + al(big_smax(R) * 4) + tmpb + 4096;
     UpdPlan* p = new UpdPlan();
     p->rmax = R;
     p->cmax = C;
+    p->grid_an = resident_grid((const void*)k_analyze, WB);
+    p->grid_mu = resident_grid((const void*)k_mutate<false>, WB);
     if (hipMalloc(&p->ws, bytes) != hipSuccess) { delete p; return nullptr; }
     p->bytes = bytes;
     char* w = p->ws;
@@ -1593,6 +1628,9 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->wv = (uint32_t*)take(R * 4);
     p->idest = (uint32_t*)take(R * 4);
     p->blist = (uint32_t*)take(R * 4);
+    p->vacap = (uint32_t*)take(R * 4);
+    p->vnseq = (uint32_t*)take(R * 4);
+    p->vadj = (uint64_t*)take(R * 8);
     p->sur = (uint32_t*)take(R * 8);
     p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
     p->parts = (unsigned long long*)take(PART_BLOCKS * 32 * 8);
@@ -1616,7 +1654,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     const int vb = std::max(1, bits_for((uint64_t)g->n - 1));
     const int cbits = bits_for(R) + 32;  // candidate key: run (< R) << 32 | seq
     const uint64_t xpad = cbits >= 64 ? ~0ull : (1ull << cbits) - 1;
-    const uint32_t vgrid = (uint32_t)std::min<uint64_t>((R + 3) / 4, PART_BLOCKS);
+    const uint32_t vgrid_a = (uint32_t)std::min<uint64_t>((R + 3) / 4, p->grid_an);
+    const uint32_t vgrid_m = (uint32_t)std::min<uint64_t>((R + 3) / 4, p->grid_mu);
     unsigned long long* uc = p->uc;
     uint32_t* err = g->d_err;
     hipLaunchKernelGGL(k_upd_validate, dim3(grid_for(R)), dim3(TB), 0, st, g->n, (const unsigned long long*)uc, p->is,
@@ -1635,11 +1674,12 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     hipLaunchKernelGGL(k_seg_end, dim3(grid_for(R)), dim3(TB), 0, st, (const unsigned long long*)uc, p->tsa, p->te,
                        p->tdl);
     hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, uc, R, p->tv,
-                       p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold, g->update_split, p->blist);
+                       p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold, p->vacap, p->vnseq, p->vadj, g->update_split,
+                       p->blist);
     scan_u64(p->fsz, p->foff, R, p->tmp, uc + UC_F, st);
     // 2. delete matching: candidates, sorted by (run, seq); the k oldest per run
-    hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tv, p->tsa, p->tdl, p->te, p->sk,
-                       p->sv, vb, p->id, g->hdr, g->pool, p->ckey, p->cval, C);
+    hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tsa, p->tdl, p->te, p->dold,
+                       p->vacap, p->vnseq, p->vadj, p->sk, p->sv, vb, p->id, g->pool, p->ckey, p->cval, C);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, st, uc, C);
     sort_pairs_u64_dn(p->ckey, p->cval, p->cks, p->cvs, C, uc + UC_C, cbits, p->tmp, st);
     hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, p->cks, (const unsigned long long*)uc, C,
@@ -1658,9 +1698,9 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                        p->rec_t, p->tsa, p->tdl, p->dold, p->ncnt, p->xoff, p->xs, p->wv, p->idest);
     // 4. analysis and one bump allocation
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R)), dim3(TB), 0, st, p->needw, R, 0ull);
-    hipLaunchKernelGGL(k_analyze, dim3(vgrid), dim3(WB), 0, st, (const unsigned long long*)uc, p->tv, p->tsa, p->tdl,
+    hipLaunchKernelGGL(k_analyze, dim3(vgrid_a), dim3(WB), 0, st, (const unsigned long long*)uc, p->tv, p->tsa, p->tdl,
                        p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->wv, g->rule, p->needw, p->parts);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid_a,
                        uc + UC_STATS, 0);
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
@@ -1669,9 +1709,9 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     const uint32_t split = g->update_split;
     const MutArgs ma{p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->wv,
                      p->idest, p->aoff, p->sur, g->rule};
-    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
+    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid_m), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
                        (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
-    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid,
+    hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid_m,
                        uc + UC_FREED, 0);
     if (split) {
         // vertices with more than `split` entries, then the passes they handed over
