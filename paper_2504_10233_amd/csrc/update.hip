@@ -612,7 +612,8 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 // 2 not found, 3.. the 25 type transitions); k_stats_reduce sums the blocks.
 // No global atomics: a per-vertex atomic on a handful of addresses would
 // serialize in L2 across ~10^6 touched vertices.
-__global__ void __launch_bounds__(WB) k_analyze(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ tv,
+// Eight waves per SIMD fit without spilling (the default allocation allowed seven).
+__global__ void __launch_bounds__(WB) __attribute__((amdgpu_waves_per_eu(8, 8))) k_analyze(const unsigned long long* __restrict__ uc, const uint32_t* __restrict__ tv,
                                                 const uint32_t* __restrict__ ts,
                                                 const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ te,
                                                 const uint32_t* __restrict__ ncnt, const uint64_t* __restrict__ xoff,
