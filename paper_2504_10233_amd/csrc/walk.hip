@@ -655,8 +655,79 @@ constexpr int HSB = 512;
 constexpr uint32_t HCAP = 16384;
 static_assert(HSB * 32 == HCAP, "the widest histogram instantiation covers HCAP");
 
+// x of lane (lane ^ D).  Distances 1, 2, 4 and 8 stay inside a row of 16 lanes
+// and are DPP moves on the vector ALU: quad permutations give ^1, ^2 and ^3, the
+// half-row mirror ^7 and the row mirror ^15, and ^4 = ^3 then ^7, ^8 = ^7 then
+// ^15.  Longer distances go through the LDS crossbar.  Every lane of the wave
+// must be active.
+template <uint32_t D>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
+    constexpr int QP_X1 = 0xB1, QP_X2 = 0x4E, QP_X3 = 0x1B, ROW_MIRROR = 0x140, ROW_HALF_MIRROR = 0x141;
+    if constexpr (D == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, QP_X1, 0xF, 0xF, false);
+    } else if constexpr (D == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, QP_X2, 0xF, 0xF, false);
+    } else if constexpr (D == 4) {
+        const int y = __builtin_amdgcn_update_dpp(0, (int)x, QP_X3, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, ROW_HALF_MIRROR, 0xF, 0xF, false);
+    } else if constexpr (D == 8) {
+        const int y = __builtin_amdgcn_update_dpp(0, (int)x, ROW_HALF_MIRROR, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, ROW_MIRROR, 0xF, 0xF, false);
+    } else {
+        return __shfl_xor(x, (int)D, 64);
+    }
+}
+
 __device__ __forceinline__ void cmp_keep(uint32_t& a, uint32_t b, bool takemin) {
     a = takemin ? min(a, b) : max(a, b);
+}
+
+// One stage (KK, J) of the bitonic network over N = HSB * E slots held E per
+// thread: slot i is ordered against slot i ^ J, ascending where i & KK == 0.
+template <int E, uint32_t KK, uint32_t J>
+__device__ __forceinline__ void bitonic_stage(uint32_t (&x)[E], uint32_t t, uint32_t lane, uint32_t* buf) {
+    if constexpr (J < (uint32_t)E) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = e ^ (int)J;
+            if (p > e) {
+                const bool up = ((t * E + e) & KK) == 0;
+                const uint32_t a = x[e], b = x[p];
+                x[e] = up ? min(a, b) : max(a, b);
+                x[p] = up ? max(a, b) : min(a, b);
+            }
+        }
+    } else if constexpr (J < 64u * E) {
+        constexpr uint32_t D = J / E;  // partner lane distance
+        const bool lower = (lane & D) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t y = lane_xor<D>(x[e]);
+            const bool up = ((t * E + e) & KK) == 0;
+            cmp_keep(x[e], y, lower == up);
+        }
+    } else {
+        constexpr uint32_t DT = J / E;  // partner thread distance, across waves
+        __syncthreads();  // earlier readers of buf are done
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf[t * E + e] = x[e];
+        __syncthreads();
+        const uint32_t pt = t ^ DT;
+        const bool lower = (t & DT) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool up = ((t * E + e) & KK) == 0;
+            cmp_keep(x[e], buf[pt * E + e], lower == up);
+        }
+    }
+}
+
+// Stages (KK, J), (KK, J / 2), ..., (KK, 1), then (2 KK, KK), ... up to KK = N.
+template <int E, uint32_t N, uint32_t KK, uint32_t J>
+__device__ __forceinline__ void bitonic_from(uint32_t (&x)[E], uint32_t t, uint32_t lane, uint32_t* buf) {
+    bitonic_stage<E, KK, J>(x, t, lane, buf);
+    if constexpr (J > 1) bitonic_from<E, N, KK, J / 2>(x, t, lane, buf);
+    else if constexpr (KK < N) bitonic_from<E, N, 2 * KK, KK>(x, t, lane, buf);
 }
 
 template <int E>
@@ -684,47 +755,7 @@ __global__ void __launch_bounds__(HSB) k_hist_seg(uint32_t* __restrict__ vis, ui
         const uint32_t i = t * E + e;
         x[e] = i < L ? vis[S0 + i] : VPAD;
     }
-    // bitonic network: stage (kk, j) orders slot i against i ^ j, ascending where i & kk == 0
-#pragma unroll
-    for (uint32_t kk = 2; kk <= N; kk <<= 1) {
-#pragma unroll
-        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            if (j < (uint32_t)E) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int p = e ^ (int)j;
-                    if (p > e) {
-                        const bool up = ((t * E + e) & kk) == 0;
-                        const uint32_t a = x[e], b = x[p];
-                        x[e] = up ? min(a, b) : max(a, b);
-                        x[p] = up ? max(a, b) : min(a, b);
-                    }
-                }
-            } else if (j < 64u * E) {
-                const int d = (int)(j / E);
-                const bool lower = (lane & d) == 0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const uint32_t y = __shfl_xor(x[e], d, 64);
-                    const bool up = ((t * E + e) & kk) == 0;
-                    cmp_keep(x[e], y, lower == up);
-                }
-            } else {
-                const uint32_t dt = j / E;
-                __syncthreads();  // earlier readers of buf are done
-#pragma unroll
-                for (int e = 0; e < E; ++e) buf[t * E + e] = x[e];
-                __syncthreads();
-                const uint32_t pt = t ^ dt;
-                const bool lower = (t & dt) == 0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const bool up = ((t * E + e) & kk) == 0;
-                    cmp_keep(x[e], buf[pt * E + e], lower == up);
-                }
-            }
-        }
-    }
+    bitonic_from<E, N, 2, 1>(x, t, lane, buf);
     // run heads: slot i is a head if it holds a vertex different from slot i - 1
     uint32_t prev = __shfl_up(x[E - 1], 1, 64);
     __syncthreads();  // the last cross-wave stage has read buf
