@@ -225,38 +225,66 @@ __global__ void k_quantize(uint64_t m, const float* __restrict__ b, double lambd
 // the small queue once its remainder drops below W; leftover slots keep all W
 // units.  Entry j = {cut lo, cut hi, alias, 0}: a draw (j, x < W) selects j when
 // x < cut, else alias.  One thread per vertex.
-__global__ void k_alias_rows(const uint32_t* __restrict__ hdr, uint32_t n, const uint32_t* __restrict__ list,
-                             const unsigned long long* __restrict__ dcount, uint64_t maxc, uint4* __restrict__ alias) {
-    const uint64_t cnt = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+constexpr int ALIAS_TB = 128;
+__global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restrict__ hdr, uint32_t n,
+                                                          const uint32_t* __restrict__ list,
+                                                          const unsigned long long* __restrict__ dcount, uint64_t maxc,
+                                                          uint4* __restrict__ alias) {
+    // per thread, one column: the slot counts and the remainders of large slots that fell below W
+    __shared__ uint32_t cnt[ALIAS_ENTRIES][ALIAS_TB];
+    __shared__ uint64_t rem[ALIAS_ENTRIES][ALIAS_TB];
+    const uint32_t tx = threadIdx.x;
+    const uint64_t total = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
+    for (uint64_t i = (uint64_t)blockIdx.x * ALIAS_TB + tx; i < total; i += (uint64_t)gridDim.x * ALIAS_TB) {
         const uint32_t u = list ? list[i] : (uint32_t)i;
         if (u >= n) continue;  // a rejected stream's bad source id
         const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         uint4* row = alias + (size_t)u * ALIAS_ENTRIES;
         const uint32_t onem = h[H_ONEMASK];
-        unsigned __int128 U[32], W = 0;
-        for (int k = 0; k < 32; ++k) {
-            const uint64_t T = (uint64_t)slot_count(h[H_CNT + k], onem, (uint32_t)k) << k;
-            U[k] = (unsigned __int128)T * 32u;
-            W += T;
+        uint64_t W = 0;
+        for (int k = 0; k < ALIAS_ENTRIES; ++k) {
+            const uint32_t c = slot_count(h[H_CNT + k], onem, (uint32_t)k);
+            cnt[k][tx] = c;
+            W += (uint64_t)c << k;
         }
-        uint8_t small[32], large[32];
-        int ns = 0, nl = 0, hs = 0, hl = 0;
-        uint64_t cut[32];
-        uint32_t al[32];
-        for (int k = 0; k < 32; ++k) {
-            if (U[k] < W) small[ns++] = (uint8_t)k; else large[nl++] = (uint8_t)k;
-            cut[k] = (uint64_t)W;
-            al[k] = (uint32_t)k;
+        // slot k holds 32 T_k = c_k 2^(k+5) units (below 2^69); it is small when that is below W
+        uint32_t S = 0, L = 0;
+        for (int k = 0; k < ALIAS_ENTRIES; ++k) {
+            if (((unsigned __int128)cnt[k][tx] << (k + 5)) < W) S |= 1u << k;
+            else L |= 1u << k;
         }
-        while (hs < ns && hl < nl) {
-            const int sm = small[hs++], l = large[hl];
-            cut[sm] = (uint64_t)U[sm];
-            al[sm] = (uint32_t)l;
-            U[l] -= W - U[sm];
-            if (U[l] < W) { ++hl; small[ns++] = (uint8_t)l; }
+        // The small queue is the initial small slots in ascending k, then the large
+        // slots in the order they fall below W; large slots are taken in ascending k,
+        // so both parts are in ascending k and each is a bit mask.
+        uint32_t P = 0, done = 0;
+        int cur = L ? __ffs(L) - 1 : -1;
+        unsigned __int128 R = cur >= 0 ? (unsigned __int128)cnt[cur][tx] << (cur + 5) : 0;
+        while ((S | P) != 0 && cur >= 0) {
+            int sm;
+            uint64_t us;
+            if (S) {
+                sm = __ffs(S) - 1;
+                S &= S - 1;
+                us = (uint64_t)((unsigned __int128)cnt[sm][tx] << (sm + 5));
+            } else {
+                sm = __ffs(P) - 1;
+                P &= P - 1;
+                us = rem[sm][tx];
+            }
+            row[sm] = make_uint4((uint32_t)us, (uint32_t)(us >> 32), (uint32_t)cur, 0u);
+            done |= 1u << sm;
+            R -= W - us;
+            if (R < W) {
+                rem[cur][tx] = (uint64_t)R;
+                P |= 1u << cur;
+                L &= L - 1;
+                cur = L ? __ffs(L) - 1 : -1;
+                R = cur >= 0 ? (unsigned __int128)cnt[cur][tx] << (cur + 5) : 0;
+            }
         }
-        for (int k = 0; k < 32; ++k) row[k] = make_uint4((uint32_t)cut[k], (uint32_t)(cut[k] >> 32), al[k], 0u);
+        // every slot not taken as small keeps exactly W units (the units sum to 32 W)
+        for (int k = 0; k < ALIAS_ENTRIES; ++k)
+            if (!((done >> k) & 1u)) row[k] = make_uint4((uint32_t)W, (uint32_t)(W >> 32), (uint32_t)k, 0u);
     }
 }
 
@@ -271,8 +299,8 @@ int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
 void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
                 hipStream_t st) {
     if (!g->alias || max_count == 0) return;
-    hipLaunchKernelGGL(k_alias_rows, dim3(grid_for(max_count, 256)), dim3(256), 0, st, (const uint32_t*)g->hdr, g->n,
-                       list, count, max_count, g->alias);
+    hipLaunchKernelGGL(k_alias_rows, dim3(grid_for(max_count, ALIAS_TB)), dim3(ALIAS_TB), 0, st,
+                       (const uint32_t*)g->hdr, g->n, list, count, max_count, g->alias);
 }
 
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st) {
