@@ -848,6 +848,11 @@ def main():
         r_stream = stream_copy_GBps(dev)
         big = max(probe, key=lambda r: r["table_GiB"])
         r_rand = max(big["independent_64B_GBps"], big["dependent_64B_GBps"])
+        # the achievable random-access rate over a table at least the walk's working set (headers and adjacency)
+        roof["random_probe_GBps"] = r_rand
+        roof["random_probe_table_GiB"] = big["table_GiB"]
+        if roof["achieved"] is not None:
+            roof["frac_of_random_probe"] = roof["achieved"] / r_rand
         result["update_roofline"] = update_roofline(timed, mem, m, r_rand, r_stream)
         ur = result["update_roofline"]
         log("update roofline: %.2f ms model (%.2f ms locating deletes) vs %.2f ms measured: %.2f of the model, "
