@@ -81,11 +81,16 @@ def serve_phase(g, n, src, dst, args, log):
     """Requests through the serving loop on the resident graph: Poisson arrivals at args.serve_rate,
     4 walk queries per update batch; query start sets log-uniform in [1, 10^4] walks with length
     uniform in 5..80, update batches log-uniform in [1, 10^4] records (half inserts with uniform
-    weights, half deletions of input edges).  Latency is submission to result ready."""
+    weights, half deletions of input edges).  Latency is submission to result ready.  A warm-up
+    stream of 400 requests of the same law comes first: the first batch of each update-size bucket
+    builds that bucket's plan and captured graph, which a resident server does once."""
     import numpy as np
+    warm = make_requests(np.random.default_rng(5004), 400, n, src, dst, 4, 4, 1 << 24)
+    serve_requests(g, warm, args.serve_rate)
     rng = np.random.default_rng(5005)
     reqs = make_requests(rng, args.serve_requests, n, src, dst, 4, 4, 1 << 24)
     res = serve_requests(g, reqs, args.serve_rate)
+    res["warmup_requests"] = len(warm)
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
     return res
@@ -606,8 +611,8 @@ def workload_serving(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
-              "walk and update phases would shard). Use --gpus 1.", flush=True)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the graph would be replicated per "
+              "GPU, walk ids range-sharded and each update batch broadcast). Use --gpus 1.", flush=True)
         sys.exit(2)
     import numpy as np
     import torch
