@@ -152,10 +152,13 @@ int bingo_quantize_biases(uint64_t m, const float* d_bias, double lambda, uint32
  * memory, so one captured hipGraph per bucket serves every batch of that
  * bucket (bingo_tuning.update_graphs).  The library allocates a bucket's
  * workspace at its first use and keeps it with the handle.
+ * When the pool cannot hold the batch's new blocks and holds blocks that
+ * earlier batches replaced (pool_garbage_bytes > 0), the call compacts the pool
+ * once (bingo_compact at the current size) and runs the batch again.
  * Returns BINGO_E_RANGE / BINGO_E_WEIGHT (batch not applied), BINGO_E_OOM
- * (pool or workspace too small; batch not applied), BINGO_E_INVALID (more
- * than 2^31 records) or BINGO_E_CAPACITY (delete matching kept overflowing
- * its candidate buffer; batch not applied).
+ * (pool or workspace too small even after compaction; batch not applied),
+ * BINGO_E_INVALID (more than 2^31 records) or BINGO_E_CAPACITY (delete
+ * matching kept overflowing its candidate buffer; batch not applied).
  */
 int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src,
                        const uint32_t* d_ins_dst, const uint32_t* d_ins_w,
@@ -273,6 +276,24 @@ int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* 
  */
 int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                        uint64_t* h_len, void* stream);
+
+/*
+ * bingo_compact -- pool compaction (the dynamic arrays of Sec. 5.2 grow by
+ * moving to a block of twice the capacity; the old block is left behind as
+ * garbage).  Every live block -- each vertex's adjacency block and the list
+ * block of each listed group, at their capacities -- is copied into a fresh
+ * arena in vertex order and the headers take the new offsets.  Capacities and
+ * contents do not change, so neither does bingo_export nor any walk.
+ *   pool_bytes  size of the new arena; 0 keeps the current size.  At most 2^37
+ *               bytes (BINGO_E_INVALID above).
+ * The new arena is allocated before the old one is freed, so both are held
+ * during the copy.  Returns BINGO_E_OOM, with nothing changed, when the live
+ * blocks do not fit pool_bytes or the allocation fails.  Synchronizes the
+ * stream.  Must not overlap any other call on the handle.  Streaming updates
+ * (bingo_update_stream) do not compact by themselves: after their
+ * BINGO_E_OOM, compact and submit the records not applied.
+ */
+int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream);
 
 /* bingo_memory -- device memory by structure (synchronizes). */
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream);

@@ -55,7 +55,8 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_export_range", "bingo_memory", "bingo_status", "bingo_last_phase_ms", "bingo_set_tuning",
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
-           "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream"]
+           "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
+           "bingo_compact"]
 
 
 class _ServerConfig(C.Structure):
@@ -98,6 +99,7 @@ def load():
         L.bingo_export.argtypes = [vp, vp, u64, C.POINTER(u64), vp]
         L.bingo_export_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
+        L.bingo_compact.argtypes = [vp, C.c_uint64, vp]
         L.bingo_status.argtypes = [vp, vp]
         L.bingo_last_phase_ms.argtypes = [vp, C.POINTER(C.c_float), u32, C.POINTER(u32)]
         L.bingo_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
@@ -281,6 +283,10 @@ class Graph:
                                   _stream(stream))
         _check(rc, "bingo_export")
         return buf[: n.value]
+
+    def compact(self, pool_bytes=0, stream=None):
+        """Move every live block into a fresh arena (0: of the current size), leaving replaced blocks behind."""
+        _check(load().bingo_compact(self.h, int(pool_bytes), _stream(stream)), "bingo_compact")
 
     def memory(self, stream=None) -> dict:
         m = _MemStats()

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["api.hip", "prim.hip", "build.hip", "walk.hip", "export.hip", "update.hip", "serve.hip", "probe.hip", "stream.hip",
-           "node2vec.hip"]
+           "node2vec.hip", "compact.hip"]
 OUT = os.path.join(HERE, "libbingo.so")
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -174,6 +174,12 @@ int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_
     return export_graph(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
+int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream) {
+    if (!g) return BINGO_E_INVALID;
+    if (pool_bytes > (1ull << 37)) return BINGO_E_INVALID;
+    return compact_pool(g, pool_bytes / 4, (hipStream_t)stream);
+}
+
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
     if (!g || !out) return BINGO_E_INVALID;
     return memory_stats(g, out, (hipStream_t)stream);

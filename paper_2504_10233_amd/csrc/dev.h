@@ -303,6 +303,9 @@ int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint
 int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
 // update.hip
 void update_release(bingo_graph* g);
+void update_drop_graphs(bingo_graph* g);  // after the pool moves: captured graphs hold its old address
+// compact.hip
+int compact_pool(bingo_graph* g, uint64_t pool_words, hipStream_t st);
 int run_node2vec(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t len, double p,
                  double q, uint64_t seed, uint32_t* paths, uint64_t* d_counts, hipStream_t st);
 int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint32_t* id, const uint32_t* iw,

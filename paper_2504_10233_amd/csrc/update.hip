@@ -909,7 +909,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         ncap = adj_cap_for(s.dn);
         nadj = abase;
         abase += adj_block_words(ncap);
-        freed += adj_block_words(s.cap) * (s.cap > 0);
+        if (lane == 0) freed += adj_block_words(s.cap) * (s.cap > 0);  // freed is summed over the wave
     }
     uint64_t* eold = reinterpret_cast<uint64_t*>(pool + s.adj);
     const uint32_t* qold = pool + s.adj + 2ull * s.cap;
@@ -1767,6 +1767,16 @@ static UpdPlan* get_plan(bingo_graph* g, uint64_t rmax, uint64_t cmax_min) {
     return p;
 }
 
+void update_drop_graphs(bingo_graph* g) {
+    if (!g->upd) return;
+    for (auto* p : g->upd->plans) {
+        if (p->exec) hipGraphExecDestroy(p->exec);
+        if (p->graph) hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+    }
+}
+
 void update_release(bingo_graph* g) {
     if (!g->upd) return;
     for (auto* p : g->upd->plans) plan_free(p);
@@ -1783,7 +1793,8 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     if (R > (1ull << 31)) return BINGO_E_INVALID;
     const uint64_t rmax = pow2_at_least(R, 1024);
     uint64_t cmin = 0;
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    bool compacted = false;
+    for (int attempt = 0; attempt < 5; ++attempt) {
         UpdPlan* p = get_plan(g, rmax, cmin);
         if (!p) return BINGO_E_OOM;
         if (n_ins) {
@@ -1831,6 +1842,14 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
         HIPCHK(hipMemcpyAsync(uc, p->uc, sizeof uc, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (err == ERR_OOM && !compacted) {
+            // the pool is full; if earlier batches left replaced blocks in it, compact and run again
+            unsigned long long ctl[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            compacted = true;
+            if (ctl[1] > 0 && compact_pool(g, 0, st) == BINGO_OK) continue;
+        }
         if (err) return err_to_code(err);
         if (uc[UC_FLAGS] & 1ull) {  // more candidates than the buffer held: nothing changed, retry larger
             cmin = pow2_at_least(uc[UC_C], 1ull << 16) * 2;
