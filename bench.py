@@ -792,8 +792,21 @@ def main():
         "steps_detail": rows,
     }
     mem = g.memory()
-    result["memory"] = {k: mem[k] for k in ("pool_used_bytes", "header_bytes", "adjacency_bytes", "list_bytes",
-                                             "model_ga_bytes", "model_bs_bytes", "groups_by_type")}
+    result["memory"] = {k: mem[k] for k in ("pool_used_bytes", "pool_garbage_bytes", "header_bytes",
+                                             "adjacency_bytes", "list_bytes", "model_ga_bytes", "model_bs_bytes",
+                                             "groups_by_type")}
+    # ---- pool compaction after the batches (wall time: size scan, new arena, copy, old arena freed)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g.compact()
+    torch.cuda.synchronize()
+    mem2 = g.memory()
+    result["compaction"] = {"ms": (time.perf_counter() - t) * 1e3, "garbage_bytes_before": mem["pool_garbage_bytes"],
+                            "used_bytes_before": mem["pool_used_bytes"], "used_bytes_after": mem2["pool_used_bytes"],
+                            "pool_bytes": mem2["pool_bytes"]}
+    log("compaction: %.1f ms, %.2f GB of replaced blocks reclaimed (pool use %.2f -> %.2f GB)" %
+        (result["compaction"]["ms"], mem["pool_garbage_bytes"] / 1e9, mem["pool_used_bytes"] / 1e9,
+         mem2["pool_used_bytes"] / 1e9))
 
     # ---- CPU oracle on the host: same batches, then the last step's query; parity of the histograms
     mix = None
