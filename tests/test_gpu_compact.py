@@ -112,3 +112,34 @@ def test_compact_rejections_leave_the_graph_unchanged():
     assert gg.memory()["pool_used_bytes"] == used
     assert_same_structure(og, gg, "after refused compactions")
     check_walks(og, gg, 43)
+
+
+def test_compact_after_streaming_updates():
+    # streaming records grow the hub and other vertices past their capacities and convert groups;
+    # the replaced blocks they leave are counted exactly and reclaimed
+    n, src, dst, w = skew_edges()
+    og, gg = build(n, src, dst, w)
+    rng = random.Random(22)
+    for b in range(3):
+        cur = O.parse_dump(og.dump(), n)
+        live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
+        recs = []
+        for _ in range(400):
+            if rng.random() < 0.7:
+                recs.append((0, 6 if rng.random() < 0.5 else rng.randrange(n), rng.randrange(n),
+                             rng.randrange(1, 1 << 32)))
+            else:
+                s_, d_ = rng.choice(live)
+                recs.append((1, s_, d_, 0))
+        ops, ss, dd, ww = (list(x) for x in zip(*recs))
+        og.update_stream(ops, ss, dd, ww)
+        gg.update_stream(*[torch.tensor(x) for x in (ops, ss, dd, ww)])
+        assert_same_structure(og, gg, "stream %d" % b)
+    before = gg.memory()
+    assert before["pool_garbage_bytes"] > 0
+    gg.compact()
+    after = gg.memory()
+    assert after["pool_garbage_bytes"] == 0
+    assert after["pool_used_bytes"] == before["pool_used_bytes"] - before["pool_garbage_bytes"]
+    assert_same_structure(og, gg, "after compaction")
+    check_walks(og, gg, 44)
