@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk[,dense_spec[,ppr_bins]] (skips the autotuner)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
+    ap.add_argument("--serve-batch", type=int, default=1,
+                    help="walk queries the serving loop merges into one launch (1 = none)")
     ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--node2vec-walks", type=int, default=1_000_000,
                     help="node2vec walks (length 80, p = 0.5, q = 2) on the final graph; 0 skips")
@@ -86,10 +88,10 @@ def serve_phase(g, n, src, dst, args, log):
     builds that bucket's plan and captured graph, which a resident server does once."""
     import numpy as np
     warm = make_requests(np.random.default_rng(5004), 400, n, src, dst, 4, 4, 1 << 24)
-    serve_requests(g, warm, args.serve_rate)
+    serve_requests(g, warm, args.serve_rate, max_batch=args.serve_batch)
     rng = np.random.default_rng(5005)
     reqs = make_requests(rng, args.serve_requests, n, src, dst, 4, 4, 1 << 24)
-    res = serve_requests(g, reqs, args.serve_rate)
+    res = serve_requests(g, reqs, args.serve_rate, max_batch=args.serve_batch)
     res["warmup_requests"] = len(warm)
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
@@ -515,7 +517,7 @@ def make_requests(rng, count, n, src, dst, q_max_exp, u_max_exp, w_hi, base_shif
     return reqs
 
 
-def serve_requests(g, reqs, rate, max_inflight=8):
+def serve_requests(g, reqs, rate, max_inflight=8, max_batch=1):
     """Submit the requests to the serving loop with Poisson arrivals at `rate` per second (0: all at
     once), collect every result; latency is submission to result ready."""
     import threading
@@ -523,7 +525,7 @@ def serve_requests(g, reqs, rate, max_inflight=8):
     from paper_2504_10233_amd import Server
     rng = np.random.default_rng(len(reqs))
     gaps = rng.exponential(1.0 / rate, len(reqs)) if rate > 0 else np.zeros(len(reqs))
-    srv = Server(g, max_inflight=max_inflight)
+    srv = Server(g, max_inflight=max_inflight, max_batch=max_batch)
     tickets = [None] * len(reqs)
     infos = [None] * len(reqs)
     ready = threading.Semaphore(0)
@@ -553,7 +555,7 @@ def serve_requests(g, reqs, rate, max_inflight=8):
     u = np.array([x["latency_us"] for x in infos if x["kind"] == 1]) / 1e3
     steps = sum(x["steps"] for x in infos if x["kind"] == 0)
     recs = sum(x["updates_applied"] + x["updates_not_found"] for x in infos if x["kind"] == 1)
-    return {"requests": len(reqs), "offered_rate_per_s": rate, "max_inflight": max_inflight,
+    return {"requests": len(reqs), "offered_rate_per_s": rate, "max_inflight": max_inflight, "max_batch": max_batch,
             "achieved_rate_per_s": len(reqs) / makespan,
             "query_p50_ms": float(np.percentile(q, 50)), "query_p99_ms": float(np.percentile(q, 99)),
             "update_p50_ms": float(np.percentile(u, 50)) if u.size else None,
@@ -585,13 +587,15 @@ def workload_serving(args):
     rng = np.random.default_rng(synth.SEEDS["serving"] if "serving" in synth.SEEDS else 5005)
     nreq = args.serve_count
     warm = make_requests(rng, 200, n, src, dst, 5, 4, 1 << 20)
-    serve_requests(g, warm, 0)
-    sat = serve_requests(g, make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20), 0)
+    serve_requests(g, warm, 0, max_batch=args.serve_batch)
+    sat = serve_requests(g, make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20), 0,
+                         max_batch=args.serve_batch)
     rate_sat = sat["achieved_rate_per_s"]
     log("serving R-MAT 25: saturation %.0f requests/s, %.3g walk steps/s" % (rate_sat, sat["sustained_walk_steps_per_s"]))
     loads = {}
     for frac in (0.5, 0.8, 0.95):
-        r = serve_requests(g, make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20), frac * rate_sat)
+        r = serve_requests(g, make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20), frac * rate_sat,
+                           max_batch=args.serve_batch)
         loads["%d%%" % int(frac * 100)] = r
         log("serving at %d%% load: query p50 %.2f ms p99 %.2f ms, update p50 %.2f ms p99 %.2f ms, %.3g steps/s" %
             (frac * 100, r["query_p50_ms"], r["query_p99_ms"], r["update_p50_ms"] or -1, r["update_p99_ms"] or -1,
@@ -601,7 +605,8 @@ def workload_serving(args):
                         mid["makespan_s"] * 1e3 / max(mid["requests"], 1),
                         {"workload": "rmat25-ef16-zipf1.5-serving-4to1-queries-updates", "vertices": n, "edges": m,
                          "query_starts": "log-uniform [1, 1e5]", "query_length": "uniform 5..80",
-                         "update_records": "log-uniform [1, 1e4]", "max_inflight": 8})
+                         "update_records": "log-uniform [1, 1e4]", "max_inflight": 8,
+                         "max_batch": args.serve_batch})
     res.update({"p99_query_latency_ms": mid["query_p99_ms"], "saturation": sat, "loads": loads, "build_s": build_s,
                 "note": "value: sustained walk-steps/s at 80 % of the measured saturation rate; ms_per_step is "
                         "makespan per request at that load"})

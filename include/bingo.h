@@ -208,6 +208,36 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
                uint64_t walk_id_base, uint32_t length, uint64_t seed,
                uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode, void* stream);
 
+/* One DeepWalk query of a batch: the arguments of one bingo_walk call. */
+typedef struct {
+    uint64_t n_walks;
+    const uint32_t* d_starts;    /* n_walks device uint32 */
+    uint64_t walk_id_base;
+    uint32_t length;             /* transitions per walk */
+    uint32_t reserved;           /* 0 */
+    uint64_t seed;
+    uint32_t* d_paths;           /* n_walks * (length + 1) device uint32 */
+    uint64_t* d_steps_taken;     /* optional, one device uint64 */
+} bingo_walk_query;
+
+#define BINGO_WALK_BATCH_MAX 32
+
+/*
+ * bingo_walk_batch -- several DeepWalk queries (Sec. 2.2) in one persistent
+ * launch: one device work queue over all their walks, so small queries do not
+ * each pay a launch and a partly idle GPU (the serving loop merges the queries
+ * waiting for a slot this way).  Query i's paths and step count are exactly
+ * those of bingo_walk(g, q.n_walks, q.d_starts, q.walk_id_base, q.length,
+ * q.seed, q.d_paths, q.d_steps_taken, BINGO_WALK_PERSISTENT): every walk is
+ * keyed by its own query's (seed, id).
+ *   n_queries   0..BINGO_WALK_BATCH_MAX.
+ *   h_queries   host array of n_queries descriptors (read during the call).
+ * Asynchronous on the stream.  BINGO_E_INVALID for a bad count, a descriptor
+ * with n_walks > 0 and a null pointer, or a length of 0xFFFFFFFF; start ids >= n
+ * as in bingo_walk.
+ */
+int bingo_walk_batch(const bingo_graph* g, uint32_t n_queries, const bingo_walk_query* h_queries, void* stream);
+
 /*
  * bingo_node2vec -- second-order walks (Sec. 2.2, Eq. node2vec): from u, having
  * come from w, the walk moves to v with probability proportional to
@@ -377,8 +407,11 @@ typedef struct bingo_server bingo_server;
 
 typedef struct {
     uint32_t struct_size;       /* sizeof(bingo_server_config) */
-    uint32_t max_inflight;      /* concurrent walk queries, 1..64 */
+    uint32_t max_inflight;      /* concurrent walk launches, 1..64 */
     uint64_t hbm_budget_bytes;  /* device bytes of admitted queries; 0 = no limit */
+    uint32_t max_batch;         /* walk queries merged into one launch (bingo_walk_batch),
+                                   0 or 1 = none, at most BINGO_WALK_BATCH_MAX */
+    uint32_t reserved;          /* 0 */
 } bingo_server_config;
 
 typedef struct {

@@ -56,11 +56,21 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
-           "bingo_compact"]
+           "bingo_compact", "bingo_walk_batch"]
 
 
 class _ServerConfig(C.Structure):
-    _fields_ = [("struct_size", C.c_uint32), ("max_inflight", C.c_uint32), ("hbm_budget_bytes", C.c_uint64)]
+    _fields_ = [("struct_size", C.c_uint32), ("max_inflight", C.c_uint32), ("hbm_budget_bytes", C.c_uint64),
+                ("max_batch", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class _WalkQuery(C.Structure):
+    _fields_ = [("n_walks", C.c_uint64), ("d_starts", C.c_void_p), ("walk_id_base", C.c_uint64),
+                ("length", C.c_uint32), ("reserved", C.c_uint32), ("seed", C.c_uint64), ("d_paths", C.c_void_p),
+                ("d_steps_taken", C.c_void_p)]
+
+
+WALK_BATCH_MAX = 32
 
 
 class _RequestInfo(C.Structure):
@@ -100,6 +110,7 @@ def load():
         L.bingo_export_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
         L.bingo_compact.argtypes = [vp, C.c_uint64, vp]
+        L.bingo_walk_batch.argtypes = [vp, C.c_uint32, C.POINTER(_WalkQuery), vp]
         L.bingo_status.argtypes = [vp, vp]
         L.bingo_last_phase_ms.argtypes = [vp, C.POINTER(C.c_float), u32, C.POINTER(u32)]
         L.bingo_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
@@ -218,6 +229,22 @@ class Graph:
                                _stream(stream))
         _check(rc, "bingo_walk")
         return paths, steps
+
+    def walk_batch(self, queries, stream=None):
+        """Several DeepWalk queries in one launch; queries = [(starts, length, seed, base), ...].
+        Returns [(paths, steps), ...] with the shapes and meaning of walk()."""
+        qs = (_WalkQuery * max(len(queries), 1))()
+        keep, out = [], []
+        for i, (starts, length, seed, base) in enumerate(queries):
+            st = as_u32(starts, self.device)
+            paths = torch.empty((st.numel(), length + 1), dtype=torch.int32, device=self.device)
+            steps = torch.zeros(1, dtype=torch.int64, device=self.device)
+            qs[i] = _WalkQuery(st.numel(), _ptr(st).value, base, length, 0, seed, _ptr(paths).value,
+                               steps.data_ptr())
+            keep.append(st)
+            out.append((paths, steps))
+        _check(load().bingo_walk_batch(self.h, len(queries), qs, _stream(stream)), "bingo_walk_batch")
+        return out
 
     def node2vec(self, starts, length, seed, p, q, base=0, stream=None, out=None):
         """Second-order node2vec paths (n_walks, length + 1) as int32 bit patterns of uint32; returns
@@ -339,9 +366,9 @@ class Server:
     """Request loop over a resident graph (see include/bingo.h): walk queries and update batches are
     admitted first-in first-out; queries run concurrently on up to max_inflight streams."""
 
-    def __init__(self, graph: Graph, max_inflight=8, hbm_budget_bytes=0):
+    def __init__(self, graph: Graph, max_inflight=8, hbm_budget_bytes=0, max_batch=1):
         L = load()
-        cfg = _ServerConfig(C.sizeof(_ServerConfig), max_inflight, hbm_budget_bytes)
+        cfg = _ServerConfig(C.sizeof(_ServerConfig), max_inflight, hbm_budget_bytes, max_batch, 0)
         h = C.c_void_p()
         _check(L.bingo_server_create(graph.h, C.byref(cfg), C.byref(h)), "bingo_server_create")
         self.h = h

@@ -132,6 +132,15 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
                        d_steps_taken, mode, (hipStream_t)stream);
 }
 
+int bingo_walk_batch(const bingo_graph* g, uint32_t n_queries, const bingo_walk_query* h_queries, void* stream) {
+    if (!g || n_queries > BINGO_WALK_BATCH_MAX || (n_queries && !h_queries)) return BINGO_E_INVALID;
+    for (uint32_t i = 0; i < n_queries; ++i) {
+        const bingo_walk_query& q = h_queries[i];
+        if ((q.n_walks && (!q.d_starts || !q.d_paths)) || q.length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    }
+    return launch_walk_batch(const_cast<bingo_graph*>(g), n_queries, h_queries, (hipStream_t)stream);
+}
+
 int bingo_node2vec(bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
                    uint32_t length, double p, double q, uint64_t seed, uint32_t* d_paths, uint64_t* d_counts,
                    void* stream) {

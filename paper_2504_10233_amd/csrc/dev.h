@@ -292,6 +292,8 @@ int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint3
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);
 // walk.hip
+#define WALK_BATCH_MAX BINGO_WALK_BATCH_MAX
+int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, hipStream_t st);
 int launch_walk(bingo_graph* g, uint64_t n_walks, const uint32_t* starts, uint64_t base, uint32_t len,
                 uint64_t seed, uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st);
 int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr, uint32_t cap,

@@ -3,16 +3,21 @@
 // every update submitted before a query is applied before that query runs,
 // and none submitted after it).
 //
-// A scheduler thread admits requests in FIFO order.  Each walk query takes one
-// of max_inflight slots (a HIP stream at default priority) and its device
-// buffers count against the HBM budget; admitted queries run concurrently on
-// their slots, so requests that arrive while others are on the GPU start as
-// soon as a slot and memory are free.  An update batch waits until every query
+// A scheduler thread admits requests in FIFO order.  Walk queries run on
+// max_inflight slots (HIP streams at default priority) and their device buffers
+// count against the HBM budget.  When a slot is free, the small walk queries
+// waiting at the head of the queue for the same graph version -- up to
+// max_batch of them, BATCH_WALKS walks in all, and the budget -- are merged
+// into one persistent launch on that slot (continuous batching: one work queue
+// over all their walks), so a burst of small queries costs one launch instead
+// of one each and a slot per query.  A larger query runs alone, so that no
+// small query waits for it.  An update batch waits until every query
 // submitted before it has finished, then runs on the update stream; queries
 // submitted after it wait for it.  Results do not depend on the mix: a query's
 // walks are keyed by (seed, walk id) and the graph it sees is fixed by its
 // epoch (the number of update batches submitted before it).
 #include "dev.h"
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -25,6 +30,7 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr uint64_t BATCH_WALKS = 16384;  // walks of the queries merged into one launch
 
 struct Req {
     uint64_t ticket = 0;
@@ -55,6 +61,7 @@ struct Req {
 struct bingo_server {
     bingo_graph* g = nullptr;
     uint32_t max_inflight = 8;
+    uint32_t max_batch = 1;
     uint64_t budget = 0;
     std::vector<hipStream_t> streams;
     std::vector<bool> busy;
@@ -137,58 +144,85 @@ bool try_admit(bingo_server* s, std::unique_lock<std::mutex>& lk) {
         s->cv_done.notify_all();
         return true;
     }
-    // a walk query: its epoch's updates must be applied, and a slot and memory must be free
+    // walk queries: their epoch's updates must be applied, and a slot and memory must be free
     if (r->epoch != s->applied_updates) return false;
     int slot = -1;
     for (uint32_t i = 0; i < s->max_inflight; ++i)
         if (!s->busy[i]) { slot = (int)i; break; }
     if (slot < 0) return false;
-    const uint64_t nw = r->starts.size();
-    const uint64_t pw = nw * ((uint64_t)r->length + 1);
-    r->bytes = (nw + pw) * 4 + 8;
-    if (s->budget && s->used_bytes + r->bytes > s->budget && !s->inflight.empty()) return false;
-    s->pending.pop_front();
+    // the front query and the small walk queries of the same epoch right behind it
+    std::vector<Req*> batch;
+    uint64_t extra = 0, walks = 0;
+    for (Req* q : s->pending) {
+        if (batch.size() >= s->max_batch || q->kind != 0 || q->epoch != r->epoch) break;
+        const uint64_t nw = q->starts.size();
+        if (!batch.empty() && walks + nw > BATCH_WALKS) break;
+        walks += nw;
+        q->bytes = (nw + nw * ((uint64_t)q->length + 1)) * 4 + 8;
+        // over the budget only when nothing else holds memory and the batch is empty
+        if (s->budget && s->used_bytes + extra + q->bytes > s->budget && !(s->inflight.empty() && batch.empty()))
+            break;
+        batch.push_back(q);
+        extra += q->bytes;
+    }
+    if (batch.empty()) return false;
+    for (size_t i = 0; i < batch.size(); ++i) s->pending.pop_front();
     s->busy[slot] = true;
-    r->slot = slot;
-    s->used_bytes += r->bytes;
-    s->inflight.push_back(r);
-    r->t_start = Clock::now();
     hipStream_t st = s->streams[slot];
+    std::vector<bingo_walk_query> qs;
     int rc = BINGO_OK;
-    if (hipMallocAsync((void**)&r->d_buf, std::max<uint64_t>(nw + pw, 1) * 4 + 32, st) != hipSuccess) rc = BINGO_E_OOM;
-    if (rc == BINGO_OK && !(r->h_paths = (uint32_t*)pin_get(s, std::max<uint64_t>(pw, 1) * 4 + 32))) rc = BINGO_E_OOM;
-    if (rc == BINGO_OK) {
-        r->h_steps = (uint64_t*)(r->h_paths + std::max<uint64_t>(pw, 1) + 1) ;
-        r->h_steps = (uint64_t*)(((uintptr_t)r->h_steps + 7) & ~(uintptr_t)7);
-        uint32_t* d_starts = r->d_buf;
-        uint32_t* d_paths = r->d_buf + nw;
-        r->d_steps = (uint64_t*)(((uintptr_t)(d_paths + pw) + 7) & ~(uintptr_t)7);
-        if (nw) hipMemcpyAsync(d_starts, r->starts.data(), nw * 4, hipMemcpyHostToDevice, st);
-        rc = bingo_walk(s->g, nw, d_starts, r->base, r->length, r->seed, d_paths, r->d_steps, BINGO_WALK_PERSISTENT,
-                        st);
-        if (rc == BINGO_OK) {
-            if (pw) hipMemcpyAsync(r->h_paths, d_paths, pw * 4, hipMemcpyDeviceToHost, st);
-            hipMemcpyAsync(r->h_steps, r->d_steps, 8, hipMemcpyDeviceToHost, st);
+    for (Req* q : batch) {
+        q->slot = slot;
+        s->used_bytes += q->bytes;
+        s->inflight.push_back(q);
+        q->t_start = Clock::now();
+        const uint64_t nw = q->starts.size(), pw = nw * ((uint64_t)q->length + 1);
+        if (rc == BINGO_OK &&
+            hipMallocAsync((void**)&q->d_buf, std::max<uint64_t>(nw + pw, 1) * 4 + 32, st) != hipSuccess) {
+            q->d_buf = nullptr;
+            rc = BINGO_E_OOM;
         }
-        hipFreeAsync(r->d_buf, st);
-        r->d_buf = nullptr;
-        hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
-        hipEventRecord(r->done_ev, st);
+        if (rc == BINGO_OK && !(q->h_paths = (uint32_t*)pin_get(s, std::max<uint64_t>(pw, 1) * 4 + 32)))
+            rc = BINGO_E_OOM;
+        if (rc != BINGO_OK) continue;
+        q->h_steps = (uint64_t*)(q->h_paths + std::max<uint64_t>(pw, 1) + 1);
+        q->h_steps = (uint64_t*)(((uintptr_t)q->h_steps + 7) & ~(uintptr_t)7);
+        uint32_t* d_starts = q->d_buf;
+        uint32_t* d_paths = q->d_buf + nw;
+        q->d_steps = (uint64_t*)(((uintptr_t)(d_paths + pw) + 7) & ~(uintptr_t)7);
+        if (nw) hipMemcpyAsync(d_starts, q->starts.data(), nw * 4, hipMemcpyHostToDevice, st);
+        qs.push_back(bingo_walk_query{nw, d_starts, q->base, q->length, 0u, q->seed, d_paths, q->d_steps});
+    }
+    if (rc == BINGO_OK) {
+        if (qs.size() == 1)
+            rc = bingo_walk(s->g, qs[0].n_walks, qs[0].d_starts, qs[0].walk_id_base, qs[0].length, qs[0].seed,
+                            qs[0].d_paths, qs[0].d_steps_taken, BINGO_WALK_PERSISTENT, st);
+        else
+            rc = bingo_walk_batch(s->g, (uint32_t)qs.size(), qs.data(), st);
+    }
+    for (size_t i = 0; i < batch.size(); ++i) {
+        Req* q = batch[i];
+        if (rc == BINGO_OK) {
+            const uint64_t pw = qs[i].n_walks * ((uint64_t)q->length + 1);
+            if (pw) hipMemcpyAsync(q->h_paths, qs[i].d_paths, pw * 4, hipMemcpyDeviceToHost, st);
+            hipMemcpyAsync(q->h_steps, q->d_steps, 8, hipMemcpyDeviceToHost, st);
+        }
+        if (q->d_buf) hipFreeAsync(q->d_buf, st);
+        q->d_buf = nullptr;
+        hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming);
+        hipEventRecord(q->done_ev, st);
     }
     if (rc != BINGO_OK) {
-        // release what was taken and fail the request
-        if (r->done_ev) {
-            hipEventSynchronize(r->done_ev);
-            hipEventDestroy(r->done_ev);
-            r->done_ev = nullptr;
-        } else if (r->d_buf) {
-            hipFreeAsync(r->d_buf, st);
-            r->d_buf = nullptr;
+        // release what was taken and fail the batch's requests
+        for (Req* q : batch) {
+            hipEventSynchronize(q->done_ev);
+            hipEventDestroy(q->done_ev);
+            q->done_ev = nullptr;
+            s->used_bytes -= q->bytes;
+            s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), q));
+            finish_req(s, q, rc);
         }
         s->busy[slot] = false;
-        s->used_bytes -= r->bytes;
-        s->inflight.pop_back();
-        finish_req(s, r, rc);
         s->cv_done.notify_all();
     }
     return true;
@@ -236,10 +270,12 @@ extern "C" {
 int bingo_server_create(bingo_graph* g, const bingo_server_config* cfg, bingo_server** out) {
     if (!g || !cfg || !out || cfg->struct_size != sizeof(bingo_server_config)) return BINGO_E_INVALID;
     if (cfg->max_inflight == 0 || cfg->max_inflight > 64) return BINGO_E_INVALID;
+    if (cfg->max_batch > BINGO_WALK_BATCH_MAX || cfg->reserved) return BINGO_E_INVALID;
     *out = nullptr;
     bingo_server* s = new bingo_server();
     s->g = g;
     s->max_inflight = cfg->max_inflight;
+    s->max_batch = std::max<uint32_t>(1, cfg->max_batch);
     s->budget = cfg->hbm_budget_bytes;
     s->streams.resize(s->max_inflight);
     s->busy.assign(s->max_inflight, false);

@@ -10,6 +10,7 @@
 #include "dev.h"
 #include "step.h"
 #include <stdio.h>
+#include <string.h>
 #include <algorithm>
 
 namespace {
@@ -258,6 +259,108 @@ __global__ void __launch_bounds__(TB) k_deepwalk_step(const uint32_t* __restrict
         row[s + 1] = v;
     }
     wave_add_u64(ctl + 1, steps);
+}
+
+// ------------------------------------------------------------------ batched DeepWalk queries
+// Several queries in one persistent launch (continuous batching in the serving
+// loop).  Their walks form one index space, query i holding [first_i, first_i +
+// n_i); a lane that takes walk index g finds its query as the last i with
+// first_i <= g (an empty query never is: the next one starts at the same index)
+// and walks exactly as the single-query kernel does, with that query's seed,
+// id base, length and output rows.  Steps taken are added per query: one atomic
+// per query among the walks a wave finishes in an iteration.  The table travels
+// in the kernel arguments.
+struct WalkQueryDev {
+    const uint32_t* starts;
+    uint32_t* paths;
+    unsigned long long* steps;  // may be null
+    uint64_t first, base, seed;
+    uint32_t L, pad;
+};
+struct WalkQueryTable {
+    WalkQueryDev q[WALK_BATCH_MAX];
+};
+
+template <int SPEC, int MODE>
+__global__ void __launch_bounds__(TB) k_deepwalk_batch(const uint32_t* __restrict__ hdr,
+                                                       const uint32_t* __restrict__ pool, uint32_t n,
+                                                       const WalkQueryTable tab, uint32_t nq, uint64_t nw,
+                                                       GroupRule rule, unsigned long long* __restrict__ ctl,
+                                                       uint32_t* __restrict__ err, uint32_t qchunk) {
+    const uint32_t lane = lane_id();
+    WaveQueue wq;
+    wq.chunk = qchunk;
+    uint64_t j = NO_WALK, seed = 0, id = 0;
+    uint32_t qi = 0, u = 0, s = 0, L = 0;
+    uint32_t* row = nullptr;
+    bool done = false;
+    for (;;) {
+        const bool need = !done && j == NO_WALK;
+        const uint64_t got = wave_take_chunked(need, wq, ctl);
+        bool fin = false;  // a walk ended in this iteration
+        if (need) {
+            if (got >= nw) {
+                done = true;
+            } else {
+                uint32_t lo = 0, hi = nq - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (tab.q[mid].first <= got) lo = mid; else hi = mid - 1;
+                }
+                qi = lo;
+                j = got - tab.q[qi].first;
+                L = tab.q[qi].L;
+                seed = tab.q[qi].seed;
+                id = tab.q[qi].base + j;
+                row = tab.q[qi].paths + j * (uint64_t)(L + 1);
+                u = tab.q[qi].starts[j];
+                s = 0;
+                row[0] = u;
+                if (u >= n) {
+                    atomicOr(err, ERR_RANGE);
+                    for (uint32_t x = 1; x <= L; ++x) row[x] = STOP_VERTEX;
+                    j = NO_WALK;
+                    fin = true;
+                }
+            }
+        }
+        if (__ballot(!done) == 0) break;
+        if (j != NO_WALK) {
+            if (s < L) {
+                RandStream rs;
+                rs_init(rs, seed, id, s);
+                const uint32_t v = walk_step_body<SPEC, MODE>(hdr, pool, u, rs, rule);
+                if (v == STOP_VERTEX) {
+                    for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
+                    j = NO_WALK;
+                    fin = true;
+                } else {
+                    row[s + 1] = v;
+                    u = v;
+                    ++s;
+                }
+            }
+            if (j != NO_WALK && s == L) {
+                j = NO_WALK;
+                fin = true;
+            }
+        }
+        for (uint64_t m = __ballot(fin); m;) {
+            const int leader = __ffsll((long long)m) - 1;
+            const uint32_t qq = __shfl(qi, leader, 64);
+            const uint64_t same = __ballot(fin && qi == qq) & m;
+            uint64_t add = ((same >> lane) & 1ull) ? s : 0u;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) add += __shfl_xor(add, o, 64);
+            if ((int)lane == leader && tab.q[qq].steps) atomicAdd(tab.q[qq].steps, (unsigned long long)add);
+            m &= ~same;
+        }
+    }
+}
+
+__global__ void k_batch_zero(const WalkQueryTable tab, uint32_t nq) {
+    const uint32_t i = threadIdx.x;
+    if (i < nq && tab.q[i].steps) *tab.q[i].steps = 0ull;
 }
 
 // ------------------------------------------------------------------ PPR
@@ -973,6 +1076,44 @@ void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_
 }
 
 }  // namespace
+
+namespace {
+template <int SPEC, int MODE>
+void deepwalk_batch_kernel(bingo_graph* g, const WalkQueryTable& tab, uint32_t nq, uint64_t nw,
+                           unsigned long long* ctl, hipStream_t st) {
+    const int rg = resident_grid((const void*)k_deepwalk_batch<SPEC, MODE>, g->blocks_per_cu);
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB));
+    hipLaunchKernelGGL((k_deepwalk_batch<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, tab, nq, nw,
+                       g->rule, ctl, g->d_err, g->queue_chunk);
+}
+}  // namespace
+
+int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, hipStream_t st) {
+    if (nq == 0) return BINGO_OK;
+    WalkQueryTable tab;
+    memset(&tab, 0, sizeof tab);
+    uint64_t nw = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+        tab.q[i] = WalkQueryDev{hq[i].d_starts, hq[i].d_paths, (unsigned long long*)hq[i].d_steps_taken, nw,
+                                hq[i].walk_id_base, hq[i].seed, hq[i].length, 0u};
+        nw += hq[i].n_walks;
+    }
+    unsigned long long* ctl = g->d_ctl + CTL_WALK0 + 2 * (g->walk_slot++ % WALK_SLOTS);
+    HIPCHK(hipMemsetAsync(ctl, 0, 16, st));
+    phase_mark(g, st, true);
+    hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(WALK_BATCH_MAX), 0, st, tab, nq);
+    if (nw) {
+        switch (g->dense_spec) {
+#define DWB(S) (walk_mode(g) == 1 ? deepwalk_batch_kernel<S, 1> : walk_mode(g) == 2 ? deepwalk_batch_kernel<S, 2> : deepwalk_batch_kernel<S, 0>)
+            case 1: DWB(1)(g, tab, nq, nw, ctl, st); break;
+            case 4: DWB(4)(g, tab, nq, nw, ctl, st); break;
+            default: DWB(2)(g, tab, nq, nw, ctl, st); break;
+#undef DWB
+        }
+    }
+    phase_mark(g, st, false);
+    return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
+}
 
 int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t base, uint32_t L, uint64_t seed,
                 uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st) {

@@ -42,8 +42,8 @@ def arrays(ins, dels):
     return a, b, c, d, e
 
 
-@pytest.mark.parametrize("inflight,budget", [(4, 0), (1, 0), (8, 1)])
-def test_serving_results_equal_sequential(inflight, budget):
+@pytest.mark.parametrize("inflight,budget,batch", [(4, 0, 8), (1, 0, 1), (8, 1, 32), (2, 0, 32), (1, 0, 32)])
+def test_serving_results_equal_sequential(inflight, budget, batch):
     b = B()
     c = synth.config_c1()
     n = c["n"]
@@ -52,7 +52,7 @@ def test_serving_results_equal_sequential(inflight, budget):
     live = list(zip(src.tolist(), dst.tolist()))
     reqs = make_requests(n, live, rng)
     g1 = b.Graph(n, torch.from_numpy(src), torch.from_numpy(dst), torch.from_numpy(w))
-    srv = b.Server(g1, max_inflight=inflight, hbm_budget_bytes=budget)
+    srv = b.Server(g1, max_inflight=inflight, hbm_budget_bytes=budget, max_batch=batch)
     tickets = []
     for r in reqs:
         if r[0] == "walk":
