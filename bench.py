@@ -725,6 +725,28 @@ def main():
     ppr_ms = sum(r["ppr_ms"] for r in timed)
     recs = sum(r["records"] for r in timed)
 
+    # host-to-device time of an update batch (the paper copies its batches from the host): the last
+    # batch's arrays from freshly allocated pinned host buffers; reported beside value, never in it
+    hb = [torch.empty(x.shape, dtype=x.dtype, pin_memory=True) for x in batches[-1]]
+    for h, x in zip(hb, batches[-1]):
+        h.copy_(x)
+    db = [torch.empty_like(x) for x in batches[-1]]
+    torch.cuda.synchronize()
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0.record()
+    for d_, h in zip(db, hb):
+        d_.copy_(h, non_blocking=True)
+    h1.record()
+    torch.cuda.synchronize()
+    h2d_ms = h0.elapsed_time(h1)
+    h2d_bytes = sum(x.numel() * 4 for x in hb)
+    per_batch_ms = upd_ms / len(timed)
+    update_h2d = {"bytes_per_batch": h2d_bytes, "h2d_ms": h2d_ms, "h2d_GBps": h2d_bytes / (h2d_ms / 1e3) / 1e9,
+                  "edge_updates_per_s_with_h2d": (recs / len(timed)) / ((per_batch_ms + h2d_ms) / 1e3)}
+    del hb, db
+    log("update batch from pinned host memory: %.3f ms for %.1f MB (%.1f GB/s); %.3g updates/s with the copy" %
+        (h2d_ms, h2d_bytes / 1e6, update_h2d["h2d_GBps"], update_h2d["edge_updates_per_s_with_h2d"]))
+
     # the other walk form on the same (final) graph, for the persistent vs per-step comparison
     other = MODE_PER_STEP if mode == MODE_PERSISTENT else MODE_PERSISTENT
     g.ppr(sources, R, thr, cap, seed, base=last[0], mode=other)
@@ -786,6 +808,7 @@ def main():
         "ppr_query_ms": ppr_ms / len(timed),
         "edge_updates_per_s": recs / (upd_ms / 1e3),
         "update_batch_ms": upd_ms / len(timed),
+        "update_h2d": update_h2d,
         "build_s": build_s,
         "walk_form_compare": {"persistent_ms" if mode == MODE_PERSISTENT else "per_step_ms": walk_ms / len(timed),
                               "per_step_ms" if mode == MODE_PERSISTENT else "persistent_ms": other_ms},
