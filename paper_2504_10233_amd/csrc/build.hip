@@ -15,23 +15,6 @@ __device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
     return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
 }
 
-// Adjacency capacity of a vertex with d edges and the block size in words.
-__host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
-    if (d == 0) return 0;
-    uint32_t c = 2;
-    while (c < d) c <<= 1;
-    return c;
-}
-__host__ __device__ inline uint64_t adj_block_words(uint32_t cap) {
-    return ((uint64_t)cap * 3 + 7) & ~7ull;
-}
-// List capacity of a listed group with c members: a power of two >= max(c, 8).
-__host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
-    uint32_t x = 8;
-    while (x < c) x <<= 1;
-    return x;
-}
-
 __global__ void k_validate(uint64_t m, uint32_t n, const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
                            const uint32_t* __restrict__ w, uint32_t* __restrict__ err) {
     uint32_t bad = 0;

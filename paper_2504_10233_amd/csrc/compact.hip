@@ -11,8 +11,6 @@ namespace {
 
 constexpr int WB = 256;
 
-__device__ __forceinline__ uint64_t adj_words(uint32_t cap) { return cap ? (((uint64_t)cap * 3 + 7) & ~7ull) : 0ull; }
-
 // Lane k < 32: the list capacity (words) of group k if it is listed, else 0.
 __device__ __forceinline__ uint64_t lane_list_words(const uint32_t* __restrict__ h, uint32_t d, uint32_t mask,
                                                     uint32_t lane, GroupRule rule) {
@@ -35,7 +33,7 @@ __global__ void __launch_bounds__(WB) k_cmp_size(const uint32_t* __restrict__ hd
     for (uint64_t u = (uint64_t)blockIdx.x * (WB / 64) + wave; u < n; u += (uint64_t)gridDim.x * (WB / 64)) {
         const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         const uint64_t w = wave_sum64(lane_list_words(h, h[H_DEG], h[H_MASK], lane, rule));
-        if (lane == 0) need[u] = w + adj_words(h[H_ACAP]);
+        if (lane == 0) need[u] = w + adj_block_words(h[H_ACAP]);
     }
 }
 
@@ -62,7 +60,7 @@ __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, con
         const uint32_t info = lane < 32 ? h[H_INFO + lane] : 0u;
         uint64_t o = off[u];
         if (cap) {
-            const uint64_t words = adj_words(cap);
+            const uint64_t words = adj_block_words(cap);
             wave_copy(src + adj, dst + o, words, lane);
             if (lane == 0) {
                 h[H_ADJLO] = (uint32_t)o;

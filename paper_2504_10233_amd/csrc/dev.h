@@ -89,6 +89,25 @@ __host__ __device__ inline uint32_t group_type(uint32_t c, uint32_t d, GroupRule
 }
 __host__ __device__ inline bool type_listed(uint32_t t) { return t == GT_SPARSE || t == GT_REGULAR; }
 
+// Pool block sizes (the dynamic arrays of Sec. 5.2; the pool is bump-allocated in
+// 32-byte units).  A vertex of d edges has an adjacency block of capacity
+// 2^ceil(log2 d), at least 2 (none for d = 0): cap 64-bit edge words, then cap
+// sequence numbers, rounded up to 8 words.  A listed group of c members has a
+// list of max(8, 2^ceil(log2 c)) entries.  Every path that allocates or frees
+// blocks (build, batched and streaming updates, compaction) uses these sizes.
+__host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
+    if (d == 0) return 0;
+    uint32_t c = 2;
+    while (c < d) c <<= 1;
+    return c;
+}
+__host__ __device__ inline uint64_t adj_block_words(uint32_t cap) { return ((uint64_t)cap * 3 + 7) & ~7ull; }
+__host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
+    uint32_t x = 8;
+    while (x < c) x <<= 1;
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // Counter-based random stream (Philox-4x32-10, Salmon et al. SC'11).  The
 // stream of a walk step is keyed by the 64-bit seed; its counter holds the

@@ -26,18 +26,6 @@ constexpr int ST_CTRS = 32;  // 0 inserted, 1 deleted, 2 not found, 3..27 transi
 
 enum { OP_INSERT = 0, OP_DELETE = 1 };
 
-__device__ inline uint32_t st_adj_cap_for(uint32_t d) {
-    if (d == 0) return 0;
-    uint32_t c = 2;
-    while (c < d) c <<= 1;
-    return c;
-}
-__device__ inline uint64_t st_adj_block_words(uint32_t cap) { return ((uint64_t)cap * 3 + 7) & ~7ull; }
-__device__ inline uint32_t st_list_cap_for(uint32_t c) {
-    uint32_t x = 8;
-    while (x < c) x <<= 1;
-    return x;
-}
 
 __global__ void k_st_validate(uint64_t m, uint32_t n, const uint32_t* __restrict__ op,
                               const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
@@ -211,9 +199,9 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
     const bool relist = kept && bit && cn > s.lcap;
     // pool words: a larger adjacency block, moved or fresh lists
     const bool grow = d1 > s.cap;
-    const uint32_t ncap = grow ? st_adj_cap_for(d1) : s.cap;
-    const uint64_t aw = grow ? st_adj_block_words(ncap) : 0ull;
-    const uint64_t lw = (relist || fresh) ? (uint64_t)st_list_cap_for(cn) : 0ull;
+    const uint32_t ncap = grow ? adj_cap_for(d1) : s.cap;
+    const uint64_t aw = grow ? adj_block_words(ncap) : 0ull;
+    const uint64_t lw = (relist || fresh) ? (uint64_t)list_cap_for(cn) : 0ull;
     uint64_t x = lw;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -232,7 +220,7 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
         uint64_t* en = reinterpret_cast<uint64_t*>(pool + nadj);
         uint32_t* qn = pool + nadj + 2ull * ncap;
         for (uint32_t i = lane; i < s.d; i += 64) { en[i] = eo[i]; qn[i] = qo[i]; }
-        if (s.cap && lane == 0) freed += st_adj_block_words(s.cap);
+        if (s.cap && lane == 0) freed += adj_block_words(s.cap);
         s.adj = nadj;
         s.cap = ncap;
     }
@@ -249,7 +237,7 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
     if (relist) {
         freed += s.lcap;
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = st_list_cap_for(cn);
+        s.lcap = list_cap_for(cn);
     }
     if (kept && bit) pool[(uint64_t)s.info * LIST_UNIT_WORDS + s.c] = s.d;
     // lists of groups that became listed or switched between sparse and regular
@@ -257,7 +245,7 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
     const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
     if (fresh) {
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = st_list_cap_for(cn);
+        s.lcap = list_cap_for(cn);
     }
     __threadfence_block();
     st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
@@ -324,7 +312,7 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     const uint32_t tnew = g ? group_type(cn, d1, rule) : GT_EMPTY;
     const bool kept = type_listed(told) && tnew == told;
     const bool fresh = type_listed(tnew) && !kept;
-    const uint64_t lw = fresh ? (uint64_t)st_list_cap_for(cn) : 0ull;
+    const uint64_t lw = fresh ? (uint64_t)list_cap_for(cn) : 0ull;
     uint64_t x = lw;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -369,7 +357,7 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
     if (fresh) {
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = st_list_cap_for(cn);
+        s.lcap = list_cap_for(cn);
     }
     st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
     const bool one = tnew == GT_ONE;

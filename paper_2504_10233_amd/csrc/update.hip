@@ -30,18 +30,6 @@ constexpr uint32_t NF = 0xFFFFFFFFu;
 constexpr uint32_t MB = 1024;  // flat elements per matching block
 constexpr uint32_t PART_BLOCKS = 2048;  // grid cap of the per-vertex kernels (blocks of 4 waves)
 
-__host__ __device__ inline uint32_t adj_cap_for(uint32_t d) {
-    if (d == 0) return 0;
-    uint32_t c = 2;
-    while (c < d) c <<= 1;
-    return c;
-}
-__host__ __device__ inline uint64_t adj_block_words(uint32_t cap) { return ((uint64_t)cap * 3 + 7) & ~7ull; }
-__host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
-    uint32_t x = 8;
-    while (x < c) x <<= 1;
-    return x;
-}
 
 inline uint32_t grid_for(uint64_t n) {
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n + TB - 1) / TB, 1), 1u << 20);
