@@ -59,7 +59,9 @@ typedef struct {
     uint32_t adaptive;      /* 1: group adaption (Sec. 5.1); 0: every non-empty group regular */
     uint32_t alpha_pct;     /* dense threshold alpha in percent (paper: 40) */
     uint32_t beta_pct;      /* sparse threshold beta in percent (paper: 10) */
-    uint64_t pool_bytes;    /* device arena for adjacency and group lists; 0 = sized from the input */
+    uint64_t pool_bytes;    /* device arena for adjacency and group lists; 0 = sized by the library
+                               (twice the input plus 16 MB, doubled by bingo_update_batch when a
+                               batch does not fit even after compaction); otherwise a fixed size */
     uint32_t frac_bits;     /* 0: integer biases.  F in 1..16: every weight is a fixed-point bias with
                                F fraction bits (Sec. 4.3, see bingo_quantize_biases): bits F..31 are
                                its integer part, decomposed into radix groups F..31; a nonzero
@@ -154,7 +156,10 @@ int bingo_quantize_biases(uint64_t m, const float* d_bias, double lambda, uint32
  * workspace at its first use and keeps it with the handle.
  * When the pool cannot hold the batch's new blocks and holds blocks that
  * earlier batches replaced (pool_garbage_bytes > 0), the call compacts the pool
- * once (bingo_compact at the current size) and runs the batch again.
+ * once (bingo_compact at the current size) and runs the batch again; if it
+ * still does not fit and the library sized the pool (bingo_config.pool_bytes =
+ * 0), it compacts into an arena twice the size (at most 2^37 bytes) and runs the
+ * batch again.
  * Returns BINGO_E_RANGE / BINGO_E_WEIGHT (batch not applied), BINGO_E_OOM
  * (pool or workspace too small even after compaction; batch not applied),
  * BINGO_E_INVALID (more than 2^31 records) or BINGO_E_CAPACITY (delete

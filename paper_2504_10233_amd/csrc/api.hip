@@ -79,6 +79,7 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     g->rule.alias = nullptr;
     g->alias_mode = cfg->alias_table;
     g->pool_words = cfg->pool_bytes / 4;
+    g->pool_auto = cfg->pool_bytes == 0;
     g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr; g->alias = nullptr;
     if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
         hipMalloc(&g->d_ctl, CTL_WORDS * 8) != hipSuccess || hipMalloc(&g->d_err, 4) != hipSuccess) {

@@ -339,7 +339,7 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
     HIPCHK(hipStreamSynchronize(st));
     const uint64_t used = tot[0] + tot[1];
     uint64_t pool_words = g->pool_words;  // requested size (words), 0 = automatic
-    if (pool_words == 0) pool_words = used * 2 + (64ull << 20);
+    if (pool_words == 0) pool_words = used * 2 + (4ull << 20);  // twice the input plus 16 MB; grows on demand
     if (pool_words < used + 1024) return BINGO_E_OOM;
     if (pool_words > (1ull << 35)) pool_words = std::max<uint64_t>(1ull << 35, used + 1024);
     if (used + 1024 > (1ull << 35)) return BINGO_E_OOM;  // list offsets are 32-bit in 32-byte units

@@ -218,6 +218,7 @@ struct bingo_graph {
     uint32_t alias_mode = 0;
     uint32_t* pool;         // device arena, pool_words u32
     uint64_t pool_words;
+    bool pool_auto;  // sized by the library (bingo_config.pool_bytes = 0): may grow
     unsigned long long* d_ctl;  // [0] words used, [1] garbage words
     uint32_t* d_err;        // sticky error bits
     // last PPR result

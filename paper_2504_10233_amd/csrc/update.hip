@@ -1781,8 +1781,8 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     if (R > (1ull << 31)) return BINGO_E_INVALID;
     const uint64_t rmax = pow2_at_least(R, 1024);
     uint64_t cmin = 0;
-    bool compacted = false;
-    for (int attempt = 0; attempt < 5; ++attempt) {
+    bool compacted = false, grown = false;
+    for (int attempt = 0; attempt < 6; ++attempt) {
         UpdPlan* p = get_plan(g, rmax, cmin);
         if (!p) return BINGO_E_OOM;
         if (n_ins) {
@@ -1830,13 +1830,19 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
         HIPCHK(hipMemcpyAsync(uc, p->uc, sizeof uc, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(&err, g->d_err, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (err == ERR_OOM && !compacted) {
-            // the pool is full; if earlier batches left replaced blocks in it, compact and run again
+        if (err == ERR_OOM && !grown) {
+            // the pool is full (nothing was applied): reclaim the blocks earlier batches replaced,
+            // once; then, for a pool the library sized, move to an arena twice the size
             unsigned long long ctl[2] = {0, 0};
             HIPCHK(hipMemcpyAsync(ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            compacted = true;
-            if (ctl[1] > 0 && compact_pool(g, 0, st) == BINGO_OK) continue;
+            if (!compacted && ctl[1] > 0) {
+                compacted = true;
+                if (compact_pool(g, 0, st) == BINGO_OK) continue;
+            }
+            grown = true;
+            const uint64_t bigger = std::min<uint64_t>(g->pool_words * 2, 1ull << 35);
+            if (g->pool_auto && bigger > g->pool_words && compact_pool(g, bigger, st) == BINGO_OK) continue;
         }
         if (err) return err_to_code(err);
         if (uc[UC_FLAGS] & 1ull) {  // more candidates than the buffer held: nothing changed, retry larger

@@ -143,3 +143,29 @@ def test_compact_after_streaming_updates():
     assert after["pool_used_bytes"] == before["pool_used_bytes"] - before["pool_garbage_bytes"]
     assert_same_structure(og, gg, "after compaction")
     check_walks(og, gg, 44)
+
+
+def test_library_sized_pool_grows():
+    # a graph whose library-sized pool (twice the input plus 16 MB) cannot hold the edges inserted
+    # later: a batch that does not fit even after compaction moves the pool to an arena twice the size
+    n, m = 5000, 20000
+    rng = np.random.default_rng(23)
+    src, dst = rng.integers(0, n, m), rng.integers(0, n, m)
+    w = rng.integers(1, 1 << 20, m)
+    og, gg = build(n, src, dst, w)
+    pool0 = gg.memory()["pool_bytes"]
+    empty = np.zeros(0, np.int64)
+    for b in range(4):
+        k = 500_000
+        isrc, idst, iw = rng.integers(0, n, k), rng.integers(0, n, k), rng.integers(1, 1 << 20, k)
+        so = og.update(isrc, idst, iw, empty, empty)
+        sg = gg.update(*[torch.from_numpy(x) for x in (isrc, idst, iw, empty, empty)])
+        assert sg["inserted"] == so["inserted"] == k
+        assert np.array_equal(sg["transitions"], so["transitions"])
+    mem = gg.memory()
+    assert mem["pool_bytes"] > pool0 and mem["pool_used_bytes"] <= mem["pool_bytes"]
+    assert np.array_equal(gg.export(), og.dump())
+    starts = rng.integers(0, n, 500)
+    paths, steps = gg.walk(starts, 30, 45)
+    opaths, osteps = og.deepwalk(starts, 30, 45)
+    assert np.array_equal(u32(paths), opaths) and int(steps.item()) == osteps
