@@ -187,9 +187,15 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
  * sources in parallel; a delete scans the vertex's adjacency and the lists of
  * the groups it touches.  Synchronizes the stream.  Returns BINGO_E_RANGE (an
  * id >= n or an op other than 0/1) or BINGO_E_WEIGHT (a zero insert weight)
- * with nothing applied; BINGO_E_OOM when the pool cannot hold a record's new
- * blocks: that source stops before the record (the earlier records of every
- * source stay applied, the structure is consistent), other sources continue.
+ * with nothing applied.  When the pool cannot hold a record's new blocks, that
+ * source stops before the record and the other sources continue; then, if the
+ * pool holds blocks that earlier updates replaced or the library sized it
+ * (bingo_config.pool_bytes = 0), the call compacts it (into an arena twice the
+ * size for a library-sized pool) and applies the records not yet applied, in
+ * their order, once more.  Records of different sources are independent, so
+ * the result is that of the whole stream.  BINGO_E_OOM if a source still runs
+ * out: it keeps the records before the failing one (the structure is
+ * consistent).
  */
 int bingo_update_stream(bingo_graph* g, uint64_t n, const uint32_t* d_op, const uint32_t* d_src,
                         const uint32_t* d_dst, const uint32_t* d_w, void* stream, bingo_update_stats* h_stats);
@@ -324,9 +330,8 @@ int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_
  * The new arena is allocated before the old one is freed, so both are held
  * during the copy.  Returns BINGO_E_OOM, with nothing changed, when the live
  * blocks do not fit pool_bytes or the allocation fails.  Synchronizes the
- * stream.  Must not overlap any other call on the handle.  Streaming updates
- * (bingo_update_stream) do not compact by themselves: after their
- * BINGO_E_OOM, compact and submit the records not applied.
+ * stream.  Must not overlap any other call on the handle.  bingo_update_batch
+ * and bingo_update_stream call it by themselves when the pool is full.
  */
 int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream);
 

@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
                                                  const uint32_t* __restrict__ w, uint32_t* __restrict__ hdr,
                                                  uint32_t* __restrict__ pool, unsigned long long* ctl,
                                                  uint64_t pool_words, GroupRule rule, uint32_t* __restrict__ errw,
-                                                 unsigned long long* __restrict__ out) {
+                                                 unsigned long long* __restrict__ out, uint32_t* __restrict__ left) {
     __shared__ unsigned long long red[TB / 64][ST_CTRS];  // per-wave counters, written by lane 0
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t nseg = *err ? 0 : *nseg_p;
@@ -404,13 +404,18 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         s.info = lane < 32 ? h[H_INFO + lane] : 0u;
         s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
         bool ok = true;
+        uint32_t stop = e;  // first record not applied
         for (uint32_t p = b; p < e && ok; ++p) {
             const uint32_t r = sv[p];
             if (op[r] == OP_INSERT) ok = st_insert(s, dst[r], w[r], rule, pool, ctl, pool_words, freed, acc);
             else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, freed, acc);
+            if (!ok) stop = p;
             __threadfence_block();
         }
-        if (!ok && lane == 0) atomicOr(errw, ERR_OOM);
+        if (!ok) {
+            if (lane == 0) atomicOr(errw, ERR_OOM);
+            for (uint32_t q = stop + lane; q < e; q += 64) left[sv[q]] = 1u;  // this source's records not applied
+        }
         // header of the vertex (the records applied so far)
         const bool ne = lane < 32 && s.c > 0;
         const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
@@ -463,14 +468,49 @@ int bits_for_n(uint32_t n) {
 
 }  // namespace
 
+namespace {
+// The records flagged in left, in their order: out[pos[r]] = in[r] for each of the four arrays.
+__global__ void k_st_gather(uint64_t m, const uint32_t* __restrict__ left, const uint64_t* __restrict__ pos,
+                            const uint32_t* __restrict__ op, const uint32_t* __restrict__ src,
+                            const uint32_t* __restrict__ dst, const uint32_t* __restrict__ w,
+                            uint32_t* __restrict__ out, uint64_t k) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (uint64_t)gridDim.x * blockDim.x) {
+        if (!left[r]) continue;
+        const uint64_t p = pos[r];
+        out[p] = op[r];
+        out[k + p] = src[r];
+        out[2 * k + p] = dst[r];
+        out[3 * k + p] = w[r];
+    }
+}
+
+void add_stats(bingo_update_stats* a, const bingo_update_stats& b) {
+    a->inserted += b.inserted;
+    a->deleted += b.deleted;
+    a->not_found += b.not_found;
+    a->match_scanned += b.match_scanned;
+    a->match_candidates += b.match_candidates;
+    for (int i = 0; i < 25; ++i) a->transitions[i] += b.transitions[i];
+}
+
+int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
+                 const uint32_t* w, bingo_update_stats* h_stats, bool retry, hipStream_t st);
+}  // namespace
+
 int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
                   const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st) {
     if (h_stats) memset(h_stats, 0, sizeof(*h_stats));
+    return apply_stream(g, m, op, src, dst, w, h_stats, true, st);
+}
+
+namespace {
+int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
+                 const uint32_t* w, bingo_update_stats* h_stats, bool retry, hipStream_t st) {
     if (m == 0) return BINGO_OK;
     if (m > (1ull << 31)) return BINGO_E_INVALID;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const size_t tmpb = std::max(sort_temp_bytes(m, false), scan_temp_bytes(m));
-    const size_t bytes = al(m * 4) * 6 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
+    const size_t bytes = al(m * 4) * 7 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
     char* ws = (char*)ws_get(g, bytes);
     if (!ws) return BINGO_E_OOM;
     auto take = [&](uint64_t b) { char* r = ws; ws += al(b); return r; };
@@ -480,12 +520,14 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
     uint32_t* head = (uint32_t*)take(m * 4);
     uint32_t* seg = (uint32_t*)take(m * 4);
     uint32_t* seg_src = (uint32_t*)take(m * 4);
+    uint32_t* left = (uint32_t*)take(m * 4);
     uint64_t* hx = (uint64_t*)take(m * 8);
     unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
     unsigned long long* nseg = (unsigned long long*)take(256);
     void* tmp = ws;
     HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
     HIPCHK(hipMemsetAsync(out, 0, ST_CTRS * 8, st));
+    HIPCHK(hipMemsetAsync(left, 0, m * 4, st));
     phase_mark(g, st, true);
     hipLaunchKernelGGL(k_st_validate, dim3(grid_for(m)), dim3(TB), 0, st, m, g->n, op, src, dst, w, g->d_err);
     hipLaunchKernelGGL(k_st_iota, dim3(grid_for(m)), dim3(TB), 0, st, ids, m);
@@ -496,7 +538,7 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
     phase_mark(g, st, false);
     hipLaunchKernelGGL(k_st_apply, dim3(ST_GRID), dim3(TB), 0, st, (const uint32_t*)g->d_err,
                        (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
-                       g->pool_words, g->rule, g->d_err, out);
+                       g->pool_words, g->rule, g->d_err, out, left);
     // alias-table mode: the sources' inter-group tables (with bad records nothing changed: rewritten as they were)
     alias_rows(g, seg_src, nseg, m, st);
     phase_mark(g, st, false);
@@ -510,14 +552,43 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
     if (err & (ERR_RANGE | ERR_WEIGHT)) return err_to_code(err);
     ++g->version;  // some records may have been applied before an out-of-pool stop
     if (h_stats) {
-        h_stats->inserted = o[0];
-        h_stats->deleted = o[1];
-        h_stats->not_found = o[2];
-        h_stats->touched_vertices = ns;
-        for (int i = 0; i < 25; ++i) h_stats->transitions[i] = o[3 + i];
-        h_stats->match_scanned = o[28];
-        h_stats->match_candidates = o[29];
+        bingo_update_stats part{};
+        part.inserted = o[0];
+        part.deleted = o[1];
+        part.not_found = o[2];
+        for (int i = 0; i < 25; ++i) part.transitions[i] = o[3 + i];
+        part.match_scanned = o[28];
+        part.match_candidates = o[29];
+        add_stats(h_stats, part);
+        if (!h_stats->touched_vertices) h_stats->touched_vertices = ns;  // the first pass saw every source
     }
-    if (err) return err_to_code(err);
-    return BINGO_OK;
+    if (err != ERR_OOM || !retry) return err ? err_to_code(err) : BINGO_OK;
+    // Out of pool: the records each stopped source did not apply are flagged.  Reclaim the
+    // replaced blocks, or grow a pool the library sized, and apply those records, in their
+    // order, once more (records of different sources are independent, so this equals the
+    // stream applied in one pass).
+    // left and its scan live in the workspace, which compaction and the second pass reuse: gather
+    // the records into a buffer of their own first
+    scan_u32_to_u64(left, hx, m, tmp, nseg, st);
+    unsigned long long k = 0;
+    HIPCHK(hipMemcpyAsync(&k, nseg, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (k == 0) return BINGO_E_OOM;
+    uint32_t* rest = nullptr;
+    if (hipMallocAsync((void**)&rest, k * 16, st) != hipSuccess) return BINGO_E_OOM;
+    hipLaunchKernelGGL(k_st_gather, dim3(grid_for(m)), dim3(TB), 0, st, m, (const uint32_t*)left, (const uint64_t*)hx,
+                       op, src, dst, w, rest, (uint64_t)k);
+    unsigned long long ctl[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t bigger = std::min<uint64_t>(g->pool_words * 2, 1ull << 35);
+    const bool grow = g->pool_auto && bigger > g->pool_words;
+    int rc = BINGO_E_OOM;
+    if (ctl[1] > 0 || grow) rc = compact_pool(g, grow ? bigger : 0, st);
+    if (rc == BINGO_OK) rc = apply_stream(g, k, rest, rest + k, rest + 2 * k, rest + 3 * k, h_stats, false, st);
+    else rc = BINGO_E_OOM;
+    HIPCHK(hipFreeAsync(rest, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return rc;
 }
+}  // namespace

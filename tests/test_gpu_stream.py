@@ -161,3 +161,26 @@ def test_stream_out_of_pool_keeps_a_consistent_prefix():
     assert 0 < applied < k
     og.update_stream(ops[:applied], s[:applied], d[:applied], ww[:applied])
     assert_same_structure(og, gg, "prefix of %d inserts" % applied)
+
+
+def test_stream_grows_a_library_sized_pool():
+    """A stream that outgrows a pool the library sized: the sources that ran out stop, the pool moves
+    to an arena twice the size, and their remaining records are applied in order; the result equals the
+    same stream on a graph whose pool never ran out (and the records counted once each)."""
+    b = B()
+    n, m = 5000, 20000
+    rng = np.random.default_rng(31)
+    src, dst, w = rng.integers(0, n, m), rng.integers(0, n, m), rng.integers(1, 1 << 20, m)
+    g1 = b.Graph(n, torch.from_numpy(src), torch.from_numpy(dst), torch.from_numpy(w))
+    g2 = b.Graph(n, torch.from_numpy(src), torch.from_numpy(dst), torch.from_numpy(w), pool_bytes=1 << 31)
+    pool0 = g1.memory()["pool_bytes"]
+    k = 1_200_000
+    rec = [np.zeros(k, np.int64), rng.integers(0, n, k), rng.integers(0, n, k), rng.integers(1, 1 << 20, k)]
+    rec[0][rng.random(k) < 0.1] = 1  # some deletes (most not found, some of earlier inserts)
+    s1 = g1.update_stream(*[torch.from_numpy(x) for x in rec])
+    s2 = g2.update_stream(*[torch.from_numpy(x) for x in rec])
+    assert g1.memory()["pool_bytes"] > pool0
+    for key in ("inserted", "deleted", "not_found"):
+        assert s1[key] == s2[key], key
+    assert s1["inserted"] + s1["deleted"] + s1["not_found"] == k
+    assert np.array_equal(g1.export(), g2.export())
