@@ -124,7 +124,7 @@ def test_two_phase_example():
     assert len(out) == len(ex["array"]) - len(ex["delete_positions"])
     assert ex["filled_with_not"] not in out.tolist()
     assert out[0] == 8
-    # the survey's small case: deleting positions {0,1} of [a,b,c,d] pairs holes with tail by rank
+    # a small case: deleting positions {0,1} of [a,b,c,d] pairs the holes with the tail by rank
     assert O.two_phase([10, 11, 12, 13], [1, 1, 0, 0]).tolist() == [12, 13]
 
 
