@@ -88,3 +88,23 @@ def test_build_rejects_bad_frac_bits_without_gpu():
     for fb, al in ((17, 0), (8, 1), (0, 2)):  # too many fraction bits; alias with fixed point; bad flag
         cfg = _Config(ctypes.sizeof(_Config), 1, 40, 10, 0, fb, al)
         assert lib.bingo_build(ctypes.byref(cfg), 10, 0, None, None, None, None, ctypes.byref(out)) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # the package without its shared library: the first call raises, nothing falls back to the host
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2504_10233_amd"
+    pkg.mkdir()
+    src = os.path.join(ROOT, "paper_2504_10233_amd")
+    for f in ("__init__.py", "binding.py"):
+        shutil.copy(os.path.join(src, f), pkg / f)
+    code = ("import numpy as np, paper_2504_10233_amd as b\n"
+            "try:\n"
+            "    b.Graph(4, np.array([0]), np.array([1]), np.array([1]), device='cpu')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=tmp_path)
+    assert r.returncode == 0, r.stderr
+    assert "raised: libbingo.so is not built" in r.stdout
