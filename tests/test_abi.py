@@ -108,3 +108,19 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=tmp_path)
     assert r.returncode == 0, r.stderr
     assert "raised: libbingo.so is not built" in r.stdout
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as C99 with every warning on
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler on this host")
+    c = tmp_path / "h.c"
+    c.write_text('#include "bingo.h"\nint main(void) { bingo_walk_query q; bingo_config g; bingo_server_config s;\n'
+                 '(void)q; (void)g; (void)s; return bingo_strerror(0) == 0; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        "-c", str(c), "-o", str(tmp_path / "h.o")], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
