@@ -11,9 +11,10 @@
 // (dense speculation).  Acceptance is the integer test word < thr_c, with
 // thr_c = 2^32 (no draw) for the largest factor.
 //
-// "w has an edge to v" is a binary search in a per-vertex sorted copy of the
-// destinations, rebuilt from the adjacency (one global radix sort of
-// (vertex, dst) keys) at the first node2vec call after the graph changed.
+// "w has an edge to v" is a search (interpolation, then bisection) in a
+// per-vertex sorted copy of the destinations, rebuilt from the adjacency (one
+// global radix sort of (vertex, dst) keys) at the first node2vec call after the
+// graph changed.
 #include "dev.h"
 #include "step.h"
 #include <math.h>
@@ -54,14 +55,34 @@ __global__ void k_n2v_low(const uint64_t* __restrict__ keys, uint64_t m, uint32_
         out[i] = (uint32_t)keys[i];
 }
 
+// Membership of v in w's sorted destinations.  Vertex ids are a seeded
+// permutation, so a vertex's destinations spread over the id range and the
+// position of v is well guessed from its value between two known entries
+// (interpolation: about log log d probes instead of log d); at most four
+// guesses, then bisection.  Invariant: nidx[L] = a < v < b = nidx[H], v can only
+// sit strictly between L and H.
 __device__ __forceinline__ bool has_edge(const uint32_t* __restrict__ nidx, const uint64_t* __restrict__ off,
                                          uint32_t w, uint32_t v) {
-    uint64_t lo = off[w], hi = off[w + 1];
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (nidx[mid] < v) lo = mid + 1; else hi = mid;
+    const uint64_t lo = off[w], hi = off[w + 1];
+    if (lo == hi) return false;
+    uint64_t L = lo, H = hi - 1;
+    uint32_t a = nidx[L], b = nidx[H];
+    if (v <= a) return v == a;
+    if (v >= b) return v == b;
+    for (int it = 0; it < 4 && H - L > 16; ++it) {
+        const uint64_t inner = H - L - 1;  // candidate positions L+1 .. H-1
+        uint64_t g = L + 1 + ((uint64_t)(v - a) * inner) / (uint64_t)(b - a);
+        if (g > H - 1) g = H - 1;
+        const uint32_t x = nidx[g];
+        if (x == v) return true;
+        if (x < v) { L = g; a = x; } else { H = g; b = x; }
     }
-    return lo < off[w + 1] && nidx[lo] == v;
+    uint64_t l = L + 1, h = H;  // bisection over [L+1, H)
+    while (l < h) {
+        const uint64_t mid = (l + h) >> 1;
+        if (nidx[mid] < v) l = mid + 1; else h = mid;
+    }
+    return l < H && nidx[l] == v;
 }
 
 // One lane per walk from the chunked device queue (as the DeepWalk kernel); in
