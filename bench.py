@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--tuning", default=None, help="walk_variant,blocks_per_cu,queue_chunk[,dense_spec[,ppr_bins]] (skips the autotuner)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="offered requests per second (Poisson)")
+    ap.add_argument("--no-insert-delete", action="store_true",
+                    help="skip the insert-only / delete-only batch comparison")
     ap.add_argument("--serve-batch", type=int, default=1,
                     help="walk queries the serving loop merges into one launch (1 = none)")
     ap.add_argument("--oracle-threads", type=int, default=16)
@@ -780,24 +782,27 @@ def main():
     # insert-only and delete-only batches of 5e5 records each (the paper finds inserts slower than
     # deletes, Sec. 6.3): the first batch's inserts again, and deletes of input edges, after an
     # untimed insert-only batch of the same size bucket
+    kinds = None
     half = batches[0][0].numel()
-    pos = synth.below(synth.SEEDS["batch"] + 100 * c + 91, 12, half, m, device=dev)
-    dsrc, ddst = src[pos].to(torch.int32).contiguous(), dst[pos].to(torch.int32).contiguous()
-    e32 = torch.empty(0, dtype=torch.int32, device=dev)
-    kinds = {}
-    g.update(*(batches[1][:3] + (e32, e32)))  # untimed: builds and captures this size bucket's plan
-    for kind, args5 in (("insert_only", batches[0][:3] + (e32, e32)), ("delete_only", (e32, e32, e32, dsrc, ddst))):
-        torch.cuda.synchronize()
-        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        k0.record()
-        st_k = g.update(*args5)
-        k1.record()
-        torch.cuda.synchronize()
-        kinds[kind] = {"records": half, "ms": k0.elapsed_time(k1), "applied": st_k["inserted"] + st_k["deleted"],
-                       "not_found": st_k["not_found"]}
-    kinds["insert_over_delete_time"] = kinds["insert_only"]["ms"] / kinds["delete_only"]["ms"]
-    log("insert-only batch %.2f ms, delete-only batch %.2f ms (%d records each; x%.2f)" %
-        (kinds["insert_only"]["ms"], kinds["delete_only"]["ms"], half, kinds["insert_over_delete_time"]))
+    pos = None if args.no_insert_delete else synth.below(synth.SEEDS["batch"] + 100 * c + 91, 12, half, m, device=dev)
+    if pos is not None:
+        dsrc, ddst = src[pos].to(torch.int32).contiguous(), dst[pos].to(torch.int32).contiguous()
+        e32 = torch.empty(0, dtype=torch.int32, device=dev)
+        kinds = {}
+        g.update(*(batches[1][:3] + (e32, e32)))  # untimed: builds and captures this size bucket's plan
+        for kind, args5 in (("insert_only", batches[0][:3] + (e32, e32)),
+                            ("delete_only", (e32, e32, e32, dsrc, ddst))):
+            torch.cuda.synchronize()
+            k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            k0.record()
+            st_k = g.update(*args5)
+            k1.record()
+            torch.cuda.synchronize()
+            kinds[kind] = {"records": half, "ms": k0.elapsed_time(k1),
+                           "applied": st_k["inserted"] + st_k["deleted"], "not_found": st_k["not_found"]}
+        kinds["insert_over_delete_time"] = kinds["insert_only"]["ms"] / kinds["delete_only"]["ms"]
+        log("insert-only batch %.2f ms, delete-only batch %.2f ms (%d records each; x%.2f)" %
+            (kinds["insert_only"]["ms"], kinds["delete_only"]["ms"], half, kinds["insert_over_delete_time"]))
 
     probe = None
     if not args.no_random_probe:
