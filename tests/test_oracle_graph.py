@@ -428,3 +428,64 @@ def test_memory_model_orders():
     assert mem["adjacency"] == 12 * 2000
     ga = mem["one"] + mem["sparse"] + mem["regular"] + mem["sparse_reduced_lists"]
     assert ga < mem["all_regular_groups"] < mem["naive_bound"]
+
+
+# ---- memory model (Sec. 4.4 space formula; Sec. 5.1 per-type structures; Sec. 6.3 all-regular baseline)
+# Expected byte counts are worked out by hand from the per-type rules: one-element 4 B (the member),
+# dense nothing, regular 4(c + d) (its list and a full inverted index over the d neighbour indices),
+# sparse 4c + 4|S| (its list and an inverted index over the reduced list S(u) of edges in at least one
+# sparse group) plus 4|S| once per vertex for S(u) itself; the all-regular baseline charges 4(c + d)
+# for every non-empty group; the naive bound is 4(dK + sum_i popc w_i) with K = 32.
+
+def test_memory_model_running_example():
+    """Sec. 4.1 running example, vertex 2 with weights 5, 4, 3: groups 2^0 = {5, 3} (c = 2 of d = 3,
+    dense), 2^1 = {3} (one-element), 2^2 = {5, 4} (dense)."""
+    g = O.Graph(6, [2, 2, 2], [1, 4, 5], [5, 4, 3])
+    mem = g.memory()
+    assert mem == {"adjacency": 36, "one": 4, "dense": 0, "sparse": 0, "regular": 0, "reserved": 0,
+                   "sparse_reduced_lists": 0,
+                   "all_regular_groups": 4 * ((2 + 3) + (1 + 3) + (2 + 3)),   # 56
+                   "naive_bound": 4 * (3 * 32 + 2 + 1 + 2)}                   # 404
+    bs = O.Graph(6, [2, 2, 2], [1, 4, 5], [5, 4, 3], adaptive=False).memory()
+    assert bs["regular"] == 56 and bs["one"] == 0 and bs["all_regular_groups"] == 56
+
+
+def test_memory_model_skew_graph():
+    """The skew graph: vertex 0 (d = 40) with dense groups 0 and 3, regular group 1 (c = 12), sparse
+    group 2 (edges 5, 9, 17) and one-element group 9; vertex 1 (weights 3, 6: one-element groups 0
+    and 2, dense group 1); vertex 2 (weight 1: one-element group 0)."""
+    mem = skew_graph().memory()
+    assert mem["adjacency"] == 12 * 43
+    assert mem["one"] == 4 + 2 * 4 + 4
+    assert mem["dense"] == 0
+    assert mem["sparse"] == 4 * 3 + 4 * 3            # list of 3, inverted index over |S| = 3
+    assert mem["sparse_reduced_lists"] == 4 * 3
+    assert mem["regular"] == 4 * (12 + 40)
+    assert mem["all_regular_groups"] == 4 * ((40 + 40) + (12 + 40) + (3 + 40) + (20 + 40) + (1 + 40)
+                                             + (1 + 2) + (2 + 2) + (1 + 2) + (1 + 1))
+    popc0 = 40 + 12 + 3 + 20 + 1
+    assert mem["naive_bound"] == 4 * (40 * 32 + popc0) + 4 * (2 * 32 + 4) + 4 * (32 + 1)
+    bs = skew_graph(adaptive=False).memory()
+    assert bs["regular"] == mem["all_regular_groups"] and bs["sparse"] == 0 and bs["one"] == 0
+
+
+def test_memory_model_two_sparse_groups_share_reduced_list():
+    """A vertex of d = 30 with one group of each type and two sparse groups sharing an edge:
+    e0..e4 weight 3 (bits 0, 1), e5..e14 weight 1, e20 weight 4, e21 weight 12 (bits 2, 3), e22 weight
+    8, e25 weight 16, the other eleven weight 32.  Group 0: c = 15 (dense, 5c > 2d); group 1: c = 5
+    (regular); groups 2 = {e20, e21} and 3 = {e21, e22}: c = 2 each (sparse, 10c < d); group 4 = {e25}
+    (one-element); group 5: c = 11 (regular).  S(u) = {e20, e21, e22}, |S| = 3."""
+    w = [3] * 5 + [1] * 10 + [32] * 5 + [4, 12, 8, 32, 32, 16, 32, 32, 32, 32]
+    assert len(w) == 30
+    g = O.Graph(31, [0] * 30, list(range(1, 31)), w)
+    types = {k: t for k, (t, c, m) in vertex(g, 0)["groups"].items()}
+    assert types == {0: O.T_DENSE, 1: O.T_REGULAR, 2: O.T_SPARSE, 3: O.T_SPARSE, 4: O.T_ONE, 5: O.T_REGULAR}
+    mem = g.memory()
+    assert mem["adjacency"] == 360
+    assert mem["one"] == 4
+    assert mem["sparse"] == 2 * (4 * 2 + 4 * 3)      # 40
+    assert mem["sparse_reduced_lists"] == 4 * 3
+    assert mem["regular"] == 4 * (5 + 30) + 4 * (11 + 30)   # 304
+    assert mem["all_regular_groups"] == 4 * ((15 + 30) + (5 + 30) + (2 + 30) + (2 + 30) + (1 + 30) + (11 + 30))
+    popc = 5 * 2 + 10 * 1 + 11 * 1 + 1 + 2 + 1 + 1
+    assert mem["naive_bound"] == 4 * (30 * 32 + popc)
