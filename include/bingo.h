@@ -17,10 +17,14 @@
  * valid until the stream work that uses them has finished.  A bingo_graph owns
  * all of its device memory and releases it in bingo_destroy().
  *
- * Concurrency.  A handle is not thread-safe.  bingo_walk calls may overlap
- * each other on different streams; bingo_update_batch, bingo_update_stream,
- * bingo_ppr and bingo_node2vec must not overlap any other call on the same
- * handle.
+ * Concurrency.  A handle is not thread-safe.  bingo_walk and bingo_walk_batch
+ * calls may overlap each other on different streams, any number of them: each
+ * call takes one of 64 per-handle counter slots in turn, and when the call that
+ * held its slot last ran on another stream and has not finished, the new call's
+ * stream first waits for it (so more than 64 calls in flight on distinct
+ * streams serialize in part, but never share counters).  bingo_update_batch,
+ * bingo_update_stream, bingo_ppr and bingo_node2vec must not overlap any other
+ * call on the same handle.
  *
  * Determinism.  Results are a pure function of (graph version, inputs, seed,
  * walk id base); they do not depend on stream, launch shape or timing.
@@ -41,7 +45,8 @@ enum {
     BINGO_E_WEIGHT = -3,    /* a zero weight (device-detected) */
     BINGO_E_OOM = -4,       /* the device pool cannot hold the result */
     BINGO_E_CAPACITY = -5,  /* a caller-supplied output buffer is too small */
-    BINGO_E_HIP = -6        /* a HIP runtime call failed */
+    BINGO_E_HIP = -6,       /* a HIP runtime call failed */
+    BINGO_E_INTERNAL = -7   /* a consistency check of the library's own bookkeeping failed */
 };
 
 /* Group types of the adaptive representation (Sec. 5.1, Eq. eq:group). */
@@ -195,7 +200,9 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
  * their order, once more.  Records of different sources are independent, so
  * the result is that of the whole stream.  BINGO_E_OOM if a source still runs
  * out: it keeps the records before the failing one (the structure is
- * consistent).
+ * consistent).  On BINGO_OK every record was applied exactly once
+ * (inserted + deleted + not_found = n, checked on the host; BINGO_E_INTERNAL
+ * otherwise).
  */
 int bingo_update_stream(bingo_graph* g, uint64_t n, const uint32_t* d_op, const uint32_t* d_src,
                         const uint32_t* d_dst, const uint32_t* d_w, void* stream, bingo_update_stats* h_stats);

@@ -33,7 +33,7 @@ int err_to_code(uint32_t bits) {
     if (bits & ERR_RANGE) return BINGO_E_RANGE;
     if (bits & ERR_WEIGHT) return BINGO_E_WEIGHT;
     if (bits & ERR_OOM) return BINGO_E_OOM;
-    if (bits & ERR_INTERNAL) return BINGO_E_HIP;
+    if (bits & ERR_INTERNAL) return BINGO_E_INTERNAL;
     return BINGO_OK;
 }
 
@@ -42,6 +42,8 @@ static void release(bingo_graph* g) {
     update_release(g);
     for (int i = 0; i < PHASE_EVENTS; ++i)
         if (g->ev[i]) hipEventDestroy(g->ev[i]);
+    for (int i = 0; i < WALK_SLOTS; ++i)
+        if (g->slot_ev[i]) hipEventDestroy(g->slot_ev[i]);
     hipFree(g->hdr);
     hipFree(g->alias);
     hipFree(g->pool);
@@ -265,6 +267,7 @@ const char* bingo_strerror(int code) {
         case BINGO_E_OOM: return "device memory pool exhausted";
         case BINGO_E_CAPACITY: return "output buffer too small";
         case BINGO_E_HIP: return "HIP runtime error";
+        case BINGO_E_INTERNAL: return "internal consistency check failed";
         default: return "unknown error";
     }
 }

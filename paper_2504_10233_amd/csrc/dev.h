@@ -210,6 +210,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // ---------------------------------------------------------------------------
 // Host-side graph handle.
 // ---------------------------------------------------------------------------
+#define WALK_SLOTS 64
 struct bingo_graph {
     uint32_t n;
     GroupRule rule;
@@ -233,8 +234,11 @@ struct bingo_graph {
     // grow-only per-walk arrays of PPR calls (lengths, segments, active lists)
     void* aux = nullptr;
     size_t aux_bytes = 0;
-    // ring of per-call counter slots for walks (queue head, transitions)
+    // ring of per-call counter slots for walks (queue head, transitions); slot_ev[i] is
+    // recorded on the stream of the call that last held slot i, after its last use of it
     uint32_t walk_slot = 0;
+    hipEvent_t slot_ev[WALK_SLOTS] = {};
+    hipStream_t slot_st[WALK_SLOTS] = {};
     // persistent walk kernel: 0 = step-synchronous lanes, 1 = attempt-interleaved lanes
     uint32_t walk_variant = 1;
     uint32_t blocks_per_cu = 0;   // 0 = occupancy limit
@@ -265,7 +269,6 @@ void phase_mark(bingo_graph* g, hipStream_t st, bool first);
 // call slot i (WALK_SLOTS slots).
 #define CTL_N2V 8
 #define CTL_WALK0 16
-#define WALK_SLOTS 64
 #define CTL_WORDS (CTL_WALK0 + 2 * WALK_SLOTS)
 
 #define HIPCHK(x)                                                                  \
@@ -313,6 +316,11 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
                 hipStream_t st);
 // walk.hip
 #define WALK_BATCH_MAX BINGO_WALK_BATCH_MAX
+// the next walk counter slot for a call on st: if the call that held it last ran on another
+// stream and may still be running, st first waits for it; the slot's words are cleared on st
+int walk_slot_take(bingo_graph* g, hipStream_t st, uint32_t* slot);
+// after the call's last use of the slot
+int walk_slot_release(bingo_graph* g, uint32_t slot, hipStream_t st);
 int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, hipStream_t st);
 int launch_walk(bingo_graph* g, uint64_t n_walks, const uint32_t* starts, uint64_t base, uint32_t len,
                 uint64_t seed, uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st);

@@ -386,7 +386,9 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
                                                  unsigned long long* __restrict__ out, uint32_t* __restrict__ left) {
     __shared__ unsigned long long red[TB / 64][ST_CTRS];  // per-wave counters, written by lane 0
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint64_t nseg = *err ? 0 : *nseg_p;
+    // only the validation bits gate the kernel: waves of this same kernel set ERR_OOM in the same
+    // word, and a block that starts after such a stop still owns its segments
+    const uint64_t nseg = (*err & (ERR_RANGE | ERR_WEIGHT)) ? 0 : *nseg_p;
     unsigned long long* acc = red[wave];
     if (lane < ST_CTRS) acc[lane] = 0;
     __threadfence_block();
@@ -499,8 +501,17 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
 
 int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
                   const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st) {
-    if (h_stats) memset(h_stats, 0, sizeof(*h_stats));
-    return apply_stream(g, m, op, src, dst, w, h_stats, true, st);
+    bingo_update_stats sum{};
+    const int rc = apply_stream(g, m, op, src, dst, w, &sum, true, st);
+    if (h_stats) *h_stats = sum;
+    // every record of a stream that returns OK was applied exactly once: inserted, deleted or
+    // counted as an absent delete
+    if (rc == BINGO_OK && sum.inserted + sum.deleted + sum.not_found != m) {
+        fprintf(stderr, "libbingo: streaming update applied %llu of %llu records\n",
+                (unsigned long long)(sum.inserted + sum.deleted + sum.not_found), (unsigned long long)m);
+        return BINGO_E_INTERNAL;
+    }
+    return rc;
 }
 
 namespace {

@@ -1088,6 +1088,26 @@ void deepwalk_batch_kernel(bingo_graph* g, const WalkQueryTable& tab, uint32_t n
 }
 }  // namespace
 
+int walk_slot_take(bingo_graph* g, hipStream_t st, uint32_t* slot) {
+    const uint32_t i = g->walk_slot++ % WALK_SLOTS;
+    if (!g->slot_ev[i]) HIPCHK(hipEventCreateWithFlags(&g->slot_ev[i], hipEventDisableTiming));
+    else if (g->slot_st[i] != st) {
+        // a call still in flight on another stream owns these counters until its event
+        const hipError_t q = hipEventQuery(g->slot_ev[i]);
+        if (q == hipErrorNotReady) HIPCHK(hipStreamWaitEvent(st, g->slot_ev[i], 0));
+        else if (q != hipSuccess) HIPCHK(q);
+    }
+    g->slot_st[i] = st;
+    HIPCHK(hipMemsetAsync(g->d_ctl + CTL_WALK0 + 2 * i, 0, 16, st));
+    *slot = i;
+    return BINGO_OK;
+}
+
+int walk_slot_release(bingo_graph* g, uint32_t slot, hipStream_t st) {
+    HIPCHK(hipEventRecord(g->slot_ev[slot], st));
+    return BINGO_OK;
+}
+
 int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, hipStream_t st) {
     if (nq == 0) return BINGO_OK;
     WalkQueryTable tab;
@@ -1098,8 +1118,9 @@ int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, h
                                 hq[i].walk_id_base, hq[i].seed, hq[i].length, 0u};
         nw += hq[i].n_walks;
     }
-    unsigned long long* ctl = g->d_ctl + CTL_WALK0 + 2 * (g->walk_slot++ % WALK_SLOTS);
-    HIPCHK(hipMemsetAsync(ctl, 0, 16, st));
+    uint32_t slot = 0;
+    if (int rc = walk_slot_take(g, st, &slot)) return rc;
+    unsigned long long* ctl = g->d_ctl + CTL_WALK0 + 2 * slot;
     phase_mark(g, st, true);
     hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(WALK_BATCH_MAX), 0, st, tab, nq);
     if (nw) {
@@ -1112,6 +1133,7 @@ int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, h
         }
     }
     phase_mark(g, st, false);
+    if (int rc = walk_slot_release(g, slot, st)) return rc;
     return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
 }
 
@@ -1119,12 +1141,13 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
                 uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st) {
     // per-call queue head and transition counter from a ring of slots, so that
     // walks on different streams do not share counters
-    unsigned long long* ctl = g->d_ctl + CTL_WALK0 + 2 * (g->walk_slot++ % WALK_SLOTS);
-    HIPCHK(hipMemsetAsync(ctl, 0, 16, st));
+    uint32_t slot = 0;
+    if (int rc = walk_slot_take(g, st, &slot)) return rc;
+    unsigned long long* ctl = g->d_ctl + CTL_WALK0 + 2 * slot;
     phase_mark(g, st, true);
     if (nw == 0) {
         if (steps) HIPCHK(hipMemsetAsync(steps, 0, 8, st));
-        return BINGO_OK;
+        return walk_slot_release(g, slot, st);
     }
     switch (g->dense_spec) {
 #define DWK(S) (walk_mode(g) == 1 ? deepwalk_kernels<S, 1> : walk_mode(g) == 2 ? deepwalk_kernels<S, 2> : deepwalk_kernels<S, 0>)
@@ -1135,6 +1158,7 @@ int launch_walk(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint64_t ba
     }
     phase_mark(g, st, false);
     if (steps) HIPCHK(hipMemcpyAsync(steps, ctl + 1, 8, hipMemcpyDeviceToDevice, st));
+    if (int rc = walk_slot_release(g, slot, st)) return rc;
     return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
 }
 

@@ -68,3 +68,35 @@ def test_batch_rejects_bad_arguments():
     qs = (binding._WalkQuery * 1)()
     qs[0] = binding._WalkQuery(1, None, 0, 5, 0, 1, None, None)
     assert b.load().bingo_walk_batch(gg.h, 1, qs, None) != 0
+
+
+def test_more_overlapping_calls_than_counter_slots():
+    """200 bingo_walk / bingo_walk_batch calls issued on 8 streams without a synchronization between
+    them: more calls in flight than the handle's 64 counter slots, so slots are reused while their
+    previous holders may still run on another stream.  Every call's paths and transition count equal
+    the same call issued alone, and the oracle's."""
+    n, og, gg = graphs("integer")
+    rng = random.Random(97)
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    calls, results = [], []
+    for i in range(200):
+        starts = np.array([rng.randrange(n) for _ in range(rng.choice([1, 50, 2000]))], dtype=np.int64)
+        L, seed, base = rng.choice([5, 40, 80]), rng.getrandbits(63), rng.getrandbits(40)
+        s = streams[i % len(streams)]
+        with torch.cuda.stream(s):
+            if i % 5 == 4:
+                (paths, steps), = gg.walk_batch([(starts, L, seed, base)], stream=s)
+            else:
+                paths, steps = gg.walk(starts, L, seed, base=base, stream=s)
+        calls.append((starts, L, seed, base))
+        results.append((paths, steps))
+    torch.cuda.synchronize()
+    for i, ((starts, L, seed, base), (paths, steps)) in enumerate(zip(calls, results)):
+        p1, s1 = gg.walk(starts, L, seed, base=base)
+        torch.cuda.synchronize()
+        assert torch.equal(paths, p1), i
+        assert int(steps.item()) == int(s1.item()), i
+        if i % 20 == 0:
+            op, ost = og.deepwalk(starts, L, seed=seed, base=base)
+            assert np.array_equal(u32(paths), op), i
+            assert int(steps.item()) == ost, i

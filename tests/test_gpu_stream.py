@@ -184,3 +184,37 @@ def test_stream_grows_a_library_sized_pool():
         assert s1[key] == s2[key], key
     assert s1["inserted"] + s1["deleted"] + s1["not_found"] == k
     assert np.array_equal(g1.export(), g2.export())
+
+
+def test_stream_grows_with_many_more_sources_than_resident_waves():
+    """The same growth with 2 x 10^5 distinct sources, many more segments than the waves the apply
+    kernel keeps resident: blocks that start after another source has run out of pool still apply
+    their own segments, so every record is counted once and the result equals the stream on a pool
+    that never ran out."""
+    b = B()
+    n, m = 200_000, 800_000
+    rng = np.random.default_rng(47)
+    src, dst, w = rng.integers(0, n, m), rng.integers(0, n, m), rng.integers(1, 1 << 20, m)
+    g1 = b.Graph(n, torch.from_numpy(src), torch.from_numpy(dst), torch.from_numpy(w))
+    g2 = b.Graph(n, torch.from_numpy(src), torch.from_numpy(dst), torch.from_numpy(w), pool_bytes=1 << 31)
+    pool0 = g1.memory()["pool_bytes"]
+    k = 1_200_000
+    rec = [np.zeros(k, np.int64), rng.integers(0, n, k), rng.integers(0, n, k), rng.integers(1, 1 << 20, k)]
+    dels = rng.random(k) < 0.1
+    rec[0][dels] = 1
+    # half of the deletes name an input edge, so they are found
+    pick = rng.integers(0, m, int(dels.sum()))
+    half = rng.random(pick.size) < 0.5
+    rec[1][np.flatnonzero(dels)[half]] = src[pick[half]]
+    rec[2][np.flatnonzero(dels)[half]] = dst[pick[half]]
+    assert np.unique(rec[1]).size > 100_000
+    s1 = g1.update_stream(*[torch.from_numpy(x) for x in rec])
+    s2 = g2.update_stream(*[torch.from_numpy(x) for x in rec])
+    assert g1.memory()["pool_bytes"] > pool0
+    for key in ("inserted", "deleted", "not_found"):
+        assert s1[key] == s2[key], key
+    assert s1["inserted"] + s1["deleted"] + s1["not_found"] == k
+    assert s1["deleted"] > 0
+    assert np.array_equal(g1.export(), g2.export())
+    g1.close()
+    g2.close()
