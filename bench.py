@@ -74,6 +74,23 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """The host the oracle ran on: CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
 def walk_src_hash():
     h = hashlib.sha256()
     for f in ("walk.hip", "dev.h", "step.h"):
@@ -250,7 +267,7 @@ def workload_deepwalk(args):
     # sampled parity against the oracle after the same batches
     if not args.no_cpu_baseline:
         import oracle as O
-        th = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+        th = max(1, min(args.oracle_threads, host_cpu()["usable_cpus"] or os.cpu_count() or 1))
         og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
         for bt in batches:
             og.update(*[x.cpu().numpy().view(np.uint32) for x in bt])
@@ -868,7 +885,7 @@ def main():
     mix = None
     if not args.no_cpu_baseline:
         import oracle as O
-        th = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+        th = max(1, min(args.oracle_threads, host_cpu()["usable_cpus"] or os.cpu_count() or 1))
         log("oracle: building on the host (%d edges)" % m)
         t = time.time()
         og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
@@ -895,12 +912,24 @@ def main():
             op, _ = og.node2vec(st0, 80, sd, 0.5, 2.0, threads=th)
             result["parity"]["node2vec_first_2000_walks_equal"] = bool(np.array_equal(gp, op))
             log("oracle: node2vec parity on 2000 walks %s" % result["parity"]["node2vec_first_2000_walks_equal"])
+        # the same oracle on one thread, over the first 200 sources of the query
+        n1 = min(200, args.sources)
+        t = time.time()
+        _, _, _, osteps1 = og.ppr(sources[:n1].cpu().numpy(), R, thr, cap, seed, base=base, threads=1)
+        one_s = time.time() - t
         result["cpu_baseline"] = {"value": osteps / oracle_ppr_s, "unit": "walk-steps/s", "cores": th,
                                   "kind": "oracle",
                                   "sample": "the last step's full PPR query (%d sources x %d walks, %d transitions) "
-                                            "on the graph after the same %d update batches; oracle updates ran at "
-                                            "%.3g records/s single-threaded" % (args.sources, R, osteps, nb,
-                                                                                 urecs / oracle_upd_s)}
+                                            "on the graph after the same %d update batches, %d OpenMP threads"
+                                            % (args.sources, R, osteps, nb, th),
+                                  "host": host_cpu(),
+                                  "single_thread": {"value": osteps1 / one_s, "unit": "walk-steps/s",
+                                                    "sample": "the first %d sources of the same query x %d walks "
+                                                              "(%d transitions, %.1f s)" % (n1, R, osteps1, one_s)},
+                                  "update_single_thread": {"value": urecs / oracle_upd_s, "unit": "edge-updates/s",
+                                                           "sample": "the same %d batches of %d records replayed "
+                                                                     "(%.1f s)" % (nb, args.batch, oracle_upd_s)}}
+        log("oracle: single thread %.3g steps/s over %d sources" % (osteps1 / one_s, n1))
         mix = {"steps": int(ost[1] + ost[2] + ost[3] + ost[4]), "one": int(ost[1]), "dense": int(ost[2]),
                "sparse": int(ost[3]), "regular": int(ost[4]), "dense_attempts": int(ost[5])}
         result["selection_mix"] = mix

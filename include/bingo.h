@@ -391,6 +391,14 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *                    chunks spread over the GPU instead of running in the
  *                    vertex's wave.  0 = never split; otherwise at least 64;
  *                    default 4096.  Same results either way.
+ *   wave_degree      attempt-interleaved walk kernels (walk_variant 1, used by
+ *                    bingo_walk, bingo_ppr and the serving loop): a step whose
+ *                    group is dense at a vertex of degree >= wave_degree is
+ *                    served by the whole wave (wave per vertex: the rejection
+ *                    attempts of one round drawn and loaded by 8 lanes at once,
+ *                    the first accepting one in stream order taken by ballot)
+ *                    instead of by its own lane (thread per walk).  0 (default)
+ *                    = never.  Same results either way.
  */
 typedef struct {
     uint32_t struct_size;
@@ -401,6 +409,7 @@ typedef struct {
     uint32_t dense_spec;
     uint32_t ppr_bins;
     uint32_t update_split;
+    uint32_t wave_degree;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

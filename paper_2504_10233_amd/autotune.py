@@ -1,10 +1,12 @@
 """Autotuner for the persistent walk kernels.
 
 It sweeps the walk knobs of bingo_set_tuning (walk variant, resident blocks per compute unit,
-walk ids per queue atomic, dense-rejection attempts per round) on a probe query and keeps the fastest setting.  Walks are keyed by
-(seed, walk id), so every setting returns the same results; only the walk-kernel time differs.
-That time is read from the library's HIP events (bingo_last_phase_ms).  Results are cached as
-JSON keyed by device and workload signature.
+walk ids per queue atomic, dense-rejection attempts per round) on a probe query and keeps the
+fastest setting; then, with that setting, it sweeps the degree threshold above which a dense step
+is served by the whole wave instead of its own lane (wave per vertex against thread per walk).
+Walks are keyed by (seed, walk id), so every setting returns the same results; only the
+walk-kernel time differs.  That time is read from the library's HIP events (bingo_last_phase_ms).
+Results are cached as JSON keyed by device and workload signature.
 """
 from __future__ import annotations
 
@@ -13,8 +15,11 @@ import os
 
 # The binned PPR kernel has attempt-interleaved lanes whatever walk_variant says; variant 1 is also
 # the faster one for the segmented fallback, so the sweep keeps it fixed.
-DEFAULT_SPACE = [dict(walk_variant=1, blocks_per_cu=b, queue_chunk=c, dense_spec=s)
+DEFAULT_SPACE = [dict(walk_variant=1, blocks_per_cu=b, queue_chunk=c, dense_spec=s, wave_degree=0)
                  for b in (0, 4, 2) for c in (64, 256, 1024) for s in (1, 2, 4)]
+# degree thresholds of the wave-per-vertex form (0: every step thread per walk; 1: every dense step
+# wave per vertex)
+WAVE_DEGREES = (0, 1, 64, 1024, 16384, 262144)
 
 
 def _cache_path():
@@ -30,8 +35,9 @@ def _load_cache(path):
 
 
 def tune_ppr(g, sources, walks_per_source, thr, max_len, seed, base=0, space=None, repeats=2, signature=None,
-             use_cache=True):
-    """Pick the fastest tuning for a PPR query shape; returns {"chosen", "results", "cached"}."""
+             use_cache=True, wave_degrees=WAVE_DEGREES):
+    """Pick the fastest tuning for a PPR query shape; returns {"chosen", "results", "wave_results",
+    "cached"}."""
     import torch
     dev = torch.cuda.get_device_name(g.device)
     key = json.dumps([dev, signature]) if signature is not None else None
@@ -49,9 +55,20 @@ def tune_ppr(g, sources, walks_per_source, thr, max_len, seed, base=0, space=Non
             ms = g.last_phase_ms()[1]
             best = ms if best is None else min(best, ms)
         results.append({"tuning": cfg, "walk_kernel_ms": best})
-    chosen = min(results, key=lambda r: r["walk_kernel_ms"])["tuning"]
+    chosen = dict(min(results, key=lambda r: r["walk_kernel_ms"])["tuning"])
+    wave_results = []
+    for wd in wave_degrees:
+        g.set_tuning(**dict(chosen, wave_degree=wd))
+        best = None
+        for _ in range(repeats):
+            g.ppr(sources, walks_per_source, thr, max_len, seed, base=base)
+            ms = g.last_phase_ms()[1]
+            best = ms if best is None else min(best, ms)
+        wave_results.append({"wave_degree": wd, "walk_kernel_ms": best})
+    if wave_results:
+        chosen["wave_degree"] = min(wave_results, key=lambda r: r["walk_kernel_ms"])["wave_degree"]
     g.set_tuning(**chosen)
-    out = {"chosen": chosen, "results": results}
+    out = {"chosen": chosen, "results": results, "wave_results": wave_results}
     if key and use_cache:
         cache[key] = out
         try:

@@ -82,7 +82,7 @@ class _RequestInfo(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("walk_variant", C.c_uint32), ("blocks_per_cu", C.c_uint32),
                 ("queue_chunk", C.c_uint32), ("update_graphs", C.c_uint32), ("dense_spec", C.c_uint32),
-                ("ppr_bins", C.c_uint32), ("update_split", C.c_uint32)]
+                ("ppr_bins", C.c_uint32), ("update_split", C.c_uint32), ("wave_degree", C.c_uint32)]
 
 
 def lib_path() -> str:
@@ -331,7 +331,7 @@ class Graph:
         return [float(buf[i]) for i in range(n.value)]
 
     def set_tuning(self, walk_variant=None, blocks_per_cu=None, queue_chunk=None, update_graphs=None, dense_spec=None,
-                   ppr_bins=None, update_split=None):
+                   ppr_bins=None, update_split=None, wave_degree=None):
         cur = self.get_tuning()
         t = _Tuning(C.sizeof(_Tuning), cur["walk_variant"] if walk_variant is None else walk_variant,
                     cur["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu,
@@ -339,7 +339,8 @@ class Graph:
                     cur["update_graphs"] if update_graphs is None else update_graphs,
                     cur["dense_spec"] if dense_spec is None else dense_spec,
                     cur["ppr_bins"] if ppr_bins is None else ppr_bins,
-                    cur["update_split"] if update_split is None else update_split)
+                    cur["update_split"] if update_split is None else update_split,
+                    cur["wave_degree"] if wave_degree is None else wave_degree)
         _check(load().bingo_set_tuning(self.h, C.byref(t)), "bingo_set_tuning")
 
     def get_tuning(self) -> dict:
@@ -347,7 +348,7 @@ class Graph:
         _check(load().bingo_get_tuning(self.h, C.byref(t)), "bingo_get_tuning")
         return {"walk_variant": t.walk_variant, "blocks_per_cu": t.blocks_per_cu, "queue_chunk": t.queue_chunk,
                 "update_graphs": t.update_graphs, "dense_spec": t.dense_spec, "ppr_bins": t.ppr_bins,
-                "update_split": t.update_split}
+                "update_split": t.update_split, "wave_degree": t.wave_degree}
 
     def status(self, stream=None) -> int:
         return load().bingo_status(self.h, _stream(stream))

@@ -225,6 +225,7 @@ int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     g->blocks_per_cu = t->blocks_per_cu;
     g->queue_chunk = qc;
     g->update_graphs = t->update_graphs;
+    g->wave_degree = t->wave_degree;
     return BINGO_OK;
 }
 
@@ -238,6 +239,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
     t->dense_spec = g->dense_spec;
     t->ppr_bins = g->ppr_bins;
     t->update_split = g->update_split;
+    t->wave_degree = g->wave_degree;
     return BINGO_OK;
 }
 

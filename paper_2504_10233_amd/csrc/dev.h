@@ -251,6 +251,9 @@ struct bingo_graph {
     // update pipeline: passes of a touched vertex over more than this many entries are split
     // into chunks processed over the whole GPU (0 = never)
     uint32_t update_split = 4096;
+    // attempt-interleaved walks: dense steps at vertices of at least this degree are served by
+    // the whole wave (0 = never)
+    uint32_t wave_degree = 0;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // structure version: bumped by every applied update batch
     uint64_t version = 0;

@@ -33,11 +33,12 @@ struct StepState {
     uint64_t adj;
     uint32_t d, sel, tries;
     bool pending;
+    bool wave;  // a dense group of a vertex of degree >= the wave threshold: the wave serves it
 };
 
 template <int MODE>
 __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
-                                               uint32_t u, StepState& ss, GroupRule rule) {
+                                               uint32_t u, StepState& ss, GroupRule rule, uint32_t wave_deg = 0) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
     const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3], q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
     const uint32_t d = q0.y;
@@ -93,6 +94,7 @@ __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr,
     const uint32_t t = group_type(csel, d, rule);
     if (t == GT_DENSE) {
         ss.adj = adj; ss.d = d; ss.sel = (uint32_t)sel; ss.tries = 0; ss.pending = true;
+        ss.wave = wave_deg != 0 && d >= wave_deg;
         return PENDING;
     }
     const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
@@ -108,6 +110,76 @@ __device__ __forceinline__ uint32_t step_attempt(const uint32_t* __restrict__ po
     ss.tries += SPEC;
     if (ss.tries >= (1u << 16)) { ss.pending = false; return STOP_VERTEX; }
     return PENDING;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-per-vertex dense rejection.  The lanes whose step selected a dense group
+// of a vertex with at least the wave threshold's degree are served one at a time
+// by the whole wave: in a round, lane j < WK takes word j of the served walk's
+// stream from where it stands (its own Philox block; the words are those the
+// walk itself would draw next), makes it a draw on [0, d) with Lemire's
+// rejection, and the draws that are not rejected are the attempts in stream
+// order (rank by ballot).  Every attempting lane loads its slot's edge word;
+// the first accepting attempt (ballot, lowest lane) is exactly the slot the
+// walk's own attempt loop would accept, so results do not depend on the mode.
+// Every lane of the wave must call this.
+// ---------------------------------------------------------------------------
+constexpr int WAVE_ROUND = 8;
+constexpr uint32_t DENSE_MAX_ATTEMPTS = 1u << 16;
+
+__device__ __forceinline__ uint32_t wave_dense_serve(const uint32_t* __restrict__ pool, const StepState& ss,
+                                                     bool want) {
+    uint64_t m = __ballot(want);
+    if (!m) return PENDING;
+    const uint32_t lane = lane_id();
+    uint32_t mine = PENDING;
+    while (m) {
+        const int ld = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const uint64_t adj = ((uint64_t)__shfl((uint32_t)(ss.adj >> 32), ld, 64) << 32) |
+                             __shfl((uint32_t)ss.adj, ld, 64);
+        const uint32_t d = __shfl(ss.d, ld, 64), sel = __shfl(ss.sel, ld, 64);
+        const uint32_t k0 = __shfl(ss.rs.k0, ld, 64), k1 = __shfl(ss.rs.k1, ld, 64);
+        const uint32_t w0 = __shfl(ss.rs.w0, ld, 64), w1 = __shfl(ss.rs.w1, ld, 64);
+        const uint32_t stp = __shfl(ss.rs.step, ld, 64);
+        // position of the next word of the served stream
+        uint64_t pos = (uint64_t)__shfl(ss.rs.blk, ld, 64) * 4u - __shfl(ss.rs.left, ld, 64);
+        const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
+        const uint32_t zone = (0u - d) % d;
+        uint32_t tries = 0, found = PENDING;
+        while (found == PENDING) {
+            bool valid = false;
+            uint32_t i = 0;
+            if (lane < (uint32_t)WAVE_ROUND) {
+                const uint64_t q = pos + lane;
+                uint32_t o[4];
+                philox_block(w0, w1, stp, (uint32_t)(q >> 2), k0, k1, o[0], o[1], o[2], o[3]);
+                const uint32_t c = (uint32_t)(q & 3u);
+                const uint32_t x = c == 0 ? o[0] : c == 1 ? o[1] : c == 2 ? o[2] : o[3];
+                const uint64_t mm = (uint64_t)x * d;
+                valid = (uint32_t)mm >= zone;
+                i = (uint32_t)(mm >> 32);
+            }
+            const uint64_t vm = __ballot(valid);
+            const uint32_t att = tries + (uint32_t)__popcll(vm & lanemask_lt());
+            uint64_t e = 0;
+            bool acc = false;
+            if (valid && att < DENSE_MAX_ATTEMPTS) {
+                e = edges[i];
+                acc = (e >> (32 + sel)) & 1ull;
+            }
+            const uint64_t am = __ballot(acc);
+            if (am) {
+                found = __shfl((uint32_t)e, __ffsll((long long)am) - 1, 64);
+            } else {
+                tries += (uint32_t)__popcll(vm);
+                pos += WAVE_ROUND;
+                if (tries >= DENSE_MAX_ATTEMPTS) found = STOP_VERTEX;
+            }
+        }
+        if ((int)lane == ld) mine = found;
+    }
+    return mine;
 }
 
 // ------------------------------------------------------------------ DeepWalk
@@ -177,11 +249,13 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
                                                              uint64_t base, uint32_t L, uint64_t seed,
                                                              uint32_t* __restrict__ paths, GroupRule rule,
                                                              unsigned long long* __restrict__ ctl,
-                                                             uint32_t* __restrict__ err, uint32_t qchunk) {
+                                                             uint32_t* __restrict__ err, uint32_t qchunk,
+                                                             uint32_t wave_deg) {
     WaveQueue wq;
     wq.chunk = qchunk;
     StepState ss;
     ss.pending = false;
+    ss.wave = false;
     uint64_t j = NO_WALK, steps = 0;
     uint32_t u = 0, s = 0;
     uint32_t* row = nullptr;
@@ -212,9 +286,14 @@ __global__ void __launch_bounds__(TB) k_deepwalk_interleaved(const uint32_t* __r
         uint32_t v = PENDING;
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
-            v = step_begin<MODE>(hdr, pool, u, ss, rule);
+            v = step_begin<MODE>(hdr, pool, u, ss, rule, wave_deg);
         }
-        if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
+        if (j != NO_WALK && ss.pending && !ss.wave) v = step_attempt<SPEC>(pool, ss);
+        {
+            const bool served = j != NO_WALK && ss.pending && ss.wave;
+            const uint32_t wv = wave_dense_serve(pool, ss, served);
+            if (served) { v = wv; ss.pending = false; }
+        }
         if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
                 for (uint32_t x = s + 1; x <= L; ++x) row[x] = STOP_VERTEX;
@@ -480,12 +559,14 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
                                                         const uint64_t* __restrict__ seg,
                                                         const uint32_t* __restrict__ len,
                                                         unsigned long long* __restrict__ ctl,
-                                                        uint32_t* __restrict__ vis, uint32_t* __restrict__ err, uint32_t qchunk) {
+                                                        uint32_t* __restrict__ vis, uint32_t* __restrict__ err, uint32_t qchunk,
+                                                        uint32_t wave_deg) {
     const uint64_t nw = (uint64_t)nsrc * R;
     WaveQueue wq;
     wq.chunk = qchunk;
     StepState ss;
     ss.pending = false;
+    ss.wave = false;
     uint64_t j = NO_WALK, pos = 0, lim = 0, steps = 0;
     uint32_t u = 0, s = 0;
     bool done = false;
@@ -517,9 +598,14 @@ __global__ void __launch_bounds__(TB) k_ppr_interleaved(const uint32_t* __restri
         if (j != NO_WALK && !ss.pending) {
             rs_init(ss.rs, seed, base + j, s);
             rs_next32(ss.rs);  // the termination word, known to be >= thr here
-            v = step_begin<MODE>(hdr, pool, u, ss, rule);
+            v = step_begin<MODE>(hdr, pool, u, ss, rule, wave_deg);
         }
-        if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
+        if (j != NO_WALK && ss.pending && !ss.wave) v = step_attempt<SPEC>(pool, ss);
+        {
+            const bool served = j != NO_WALK && ss.pending && ss.wave;
+            const uint32_t wv = wave_dense_serve(pool, ss, served);
+            if (served) { v = wv; ss.pending = false; }
+        }
         if (j != NO_WALK && v != PENDING) {
             if (v == STOP_VERTEX) {
                 for (uint64_t x = pos; x < lim; ++x) vis[x] = VPAD;
@@ -552,13 +638,14 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                                                    uint32_t cap, GroupRule rule, uint64_t C,
                                                    uint32_t* __restrict__ cnt, uint32_t* __restrict__ vis,
                                                    unsigned long long* __restrict__ ctl, uint32_t* __restrict__ err,
-                                                   uint32_t qchunk) {
+                                                   uint32_t qchunk, uint32_t wave_deg) {
     const uint64_t nw = (uint64_t)nsrc * R;
     const uint32_t lane = lane_id();
     WaveQueue wq;
     wq.chunk = qchunk;
     StepState ss;
     ss.pending = false;
+    ss.wave = false;
     uint64_t j = NO_WALK, steps = 0;
     uint32_t u = 0, s = 0, q = 0;
     bool done = false, ovf = false;
@@ -586,8 +673,8 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
             }
         }
         if (__ballot(!done) == 0) break;
+        uint32_t v = PENDING;
         if (j != NO_WALK && !emit) {
-            uint32_t v = PENDING;
             if (!ss.pending) {
                 // before every transition: the cap, then the termination word
                 if (s >= cap) {
@@ -595,11 +682,18 @@ __global__ void __launch_bounds__(TB) k_ppr_binned(const uint32_t* __restrict__ 
                 } else {
                     rs_init(ss.rs, seed, base + j, s);
                     if (rs_next32(ss.rs) < thr) j = NO_WALK;
-                    else v = step_begin<MODE>(hdr, pool, u, ss, rule);
+                    else v = step_begin<MODE>(hdr, pool, u, ss, rule, wave_deg);
                 }
             }
-            if (j != NO_WALK && ss.pending) v = step_attempt<SPEC>(pool, ss);
-            if (j != NO_WALK && v != PENDING) {
+            if (j != NO_WALK && ss.pending && !ss.wave) v = step_attempt<SPEC>(pool, ss);
+        }
+        {
+            const bool served = j != NO_WALK && !emit && ss.pending && ss.wave;
+            const uint32_t wv = wave_dense_serve(pool, ss, served);
+            if (served) { v = wv; ss.pending = false; }
+        }
+        if (j != NO_WALK && !emit) {
+            if (v != PENDING) {
                 if (v == STOP_VERTEX) {
                     j = NO_WALK;
                 } else {
@@ -1038,7 +1132,7 @@ void deepwalk_kernels(bingo_graph* g, uint64_t nw, const uint32_t* starts, uint6
         const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB);
         if (g->walk_variant)
             hipLaunchKernelGGL((k_deepwalk_interleaved<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
-                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
+                               base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk, g->wave_degree);
         else
             hipLaunchKernelGGL((k_deepwalk_persistent<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nw, starts,
                                base, L, seed, paths, g->rule, ctl, g->d_err, g->queue_chunk);
@@ -1068,7 +1162,7 @@ void ppr_kernels(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1);
         if (g->walk_variant)
             hipLaunchKernelGGL((k_ppr_interleaved<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
-                               seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
+                               seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk, g->wave_degree);
         else
             hipLaunchKernelGGL((k_ppr_persistent<SPEC, MODE>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R,
                                seed, base, g->rule, seg, len, ctl, vis, g->d_err, g->queue_chunk);
@@ -1255,7 +1349,8 @@ static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources
         const uint64_t nw = (uint64_t)nsrc * R;                                                                    \
         const uint32_t grid = std::max<uint32_t>((uint32_t)std::min<uint64_t>((uint64_t)rg, (nw + TB - 1) / TB), 1); \
         hipLaunchKernelGGL((k_ppr_binned<S_, M_>), dim3(grid), dim3(TB), 0, st, g->hdr, g->pool, g->n, nsrc, sources, R, \
-                           seed, base, thr, cap, g->rule, C, bin_cnt, vis, ctl, g->d_err, g->queue_chunk);          \
+                           seed, base, thr, cap, g->rule, C, bin_cnt, vis, ctl, g->d_err, g->queue_chunk,         \
+                           g->wave_degree);                                                                         \
     } while (0)
     switch (g->dense_spec) {
         case 1: if (walk_mode(g) == 1) BINGO_BINNED(1, 1); else if (walk_mode(g) == 2) BINGO_BINNED(1, 2); else BINGO_BINNED(1, 0); break;

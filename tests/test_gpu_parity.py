@@ -416,7 +416,10 @@ def test_autotune_keeps_results():
     thr = int(0.15 * 2**32)
     space = [dict(walk_variant=v, blocks_per_cu=b, queue_chunk=q) for v in (0, 1) for b in (0, 1) for q in (16, 256)]
     res = tune_ppr(gg, np.arange(50), 20, thr, 200, 1, space=space, repeats=1, use_cache=False)
-    assert res["chosen"] in space and len(res["results"]) == len(space)
+    chosen = dict(res["chosen"])
+    assert chosen.pop("wave_degree") in [r["wave_degree"] for r in res["wave_results"]]
+    assert chosen in space and len(res["results"]) == len(space)
+    assert gg.get_tuning()["wave_degree"] == res["chosen"]["wave_degree"]
     off, vtx, cnt, st = gg.ppr(np.arange(0, 1000, 9), 50, thr, 200, seed=2)
     ooff, ovtx, ocnt, ost = og.ppr(np.arange(0, 1000, 9), 50, thr, 200, seed=2)
     assert np.array_equal(u32(vtx), ovtx) and np.array_equal(u32(cnt), ocnt) and st == ost
