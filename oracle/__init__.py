@@ -99,6 +99,19 @@ def lib():
             L.o_dump_range.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, u32p]
             L.o_dump_range.restype = C.c_uint64
             L.o_memory.argtypes = [C.c_void_p, u64p]
+            L.o4_build.argtypes = [C.c_uint32, C.c_uint64, u32p, u32p, u32p, C.c_int, C.c_uint32, C.c_uint32,
+                                   C.POINTER(C.c_void_p)]
+            L.o4_build.restype = C.c_int
+            L.o4_free.argtypes = [C.c_void_p]
+            L.o4_pick_subgroup.argtypes = [u32p, C.c_uint64]
+            L.o4_pick_subgroup.restype = C.c_int
+            L.o4_step.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32]
+            L.o4_step.restype = C.c_uint32
+            L.o4_deepwalk.argtypes = [C.c_void_p, C.c_uint64, u32p, C.c_uint64, C.c_uint32, C.c_uint64, u32p,
+                                      C.c_int]
+            L.o4_deepwalk.restype = C.c_uint64
+            L.o4_dump.argtypes = [C.c_void_p, u32p]
+            L.o4_dump.restype = C.c_uint64
             _lib = L
     return _lib
 
@@ -354,4 +367,83 @@ def parse_dump(words, n):
         out.append({"d": d, "next_seq": nseq, "mask": mask, "dst": e[:, 0].copy(), "w": e[:, 1].copy(),
                     "seq": e[:, 2].copy(), "groups": groups})
     assert o == len(words), (o, len(words))
+    return out
+
+
+# ---- radix base 4 (Supplement S.2): 48 subgroups s = 3k + v - 1 of the edges whose base-4 digit k is v
+def pick_subgroup(c48, r):
+    """The subgroup an ascending inverse-transform scan over c_s * v * 4^k selects for r."""
+    c = _u32(c48)
+    assert c.size == 48
+    return lib().o4_pick_subgroup(_p(c, C.c_uint32), int(r))
+
+
+class Graph4:
+    """The oracle's static radix-base-4 structure (build and walks)."""
+
+    def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10):
+        s_, d_, w_ = _u32(src), _u32(dst), _u32(w)
+        h = C.c_void_p()
+        rc = lib().o4_build(n, len(s_), _p(s_, C.c_uint32), _p(d_, C.c_uint32), _p(w_, C.c_uint32), int(adaptive),
+                            alpha, beta, C.byref(h))
+        if rc != 0:
+            raise OracleError("o4_build failed: %d" % rc)
+        self.h, self.n = h, n
+
+    def close(self):
+        if self.h:
+            lib().o4_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, u, seed, walk, step):
+        return int(lib().o4_step(self.h, u, seed, walk, step))
+
+    def deepwalk(self, starts, length, seed, base=0, threads=1):
+        st = _u32(starts)
+        paths = np.zeros((st.size, length + 1), np.uint32)
+        total = lib().o4_deepwalk(self.h, st.size, _p(st, C.c_uint32), base, length, seed, _p(paths, C.c_uint32),
+                                  threads)
+        return paths, int(total)
+
+    def dump(self):
+        L = lib()
+        nw = L.o4_dump(self.h, None)
+        out = np.zeros(max(nw, 1), np.uint32)
+        L.o4_dump(self.h, _p(out, C.c_uint32))
+        return out[:nw]
+
+
+def parse_dump4(words, n):
+    """Parse a base-4 canonical dump into per-vertex dicts."""
+    words = np.asarray(words, dtype=np.uint32)
+    out, o = [], 0
+    for _ in range(n):
+        d = int(words[o]); mask = int(words[o + 1]) | (int(words[o + 2]) << 32)
+        o += 3
+        e = words[o:o + 2 * d].reshape(d, 2)
+        o += 2 * d
+        subs = {}
+        for s in range(48):
+            if not (mask >> s) & 1:
+                continue
+            ss, t, c = int(words[o]), int(words[o + 1]), int(words[o + 2])
+            assert ss == s
+            o += 3
+            if t == T_ONE:
+                members = [int(words[o])]
+                o += 1
+            elif t in (T_SPARSE, T_REGULAR):
+                members = [int(x) for x in words[o:o + c]]
+                o += c
+            else:
+                members = None
+            subs[s] = (t, c, members)
+        out.append({"d": d, "mask": mask, "dst": e[:, 0].copy(), "w": e[:, 1].copy(), "subgroups": subs})
+    assert o == len(words)
     return out

@@ -1002,3 +1002,186 @@ void o_memory(const ograph *G, uint64_t out[9]) {
 }
 
 uint32_t o_n(const ograph *G) { return G->n; }
+
+/* ======================================================================== */
+/* Radix base 4 (Supplement S.2, Fig. 17).                                   */
+/*                                                                           */
+/* Every weight is written in base 4, w = sum_k d_k 4^k with digits d_k in   */
+/* {0,1,2,3} (k = 0..15).  Group k holds the edges with d_k != 0; its        */
+/* members do not all carry the same bias, so it is split into subgroups     */
+/* (k, v), v = 1..3, of the edges whose digit is v: every member of (k, v)   */
+/* carries v 4^k, and the subgroup's total is c_{k,v} v 4^k.  A step picks   */
+/* the group by its total, then the subgroup inside it by c_{k,v} v, then a  */
+/* member uniformly.  Readings fixed here: both choices are inverse          */
+/* transform in ascending order on one draw r = below64(W) (the group's      */
+/* residual r - sum of the lower groups picks the subgroup), which is the    */
+/* same as one ascending scan over the 48 subgroups s = 3k + v - 1 with      */
+/* totals T_s = c_s v 4^k; the member of a subgroup is drawn as for a power- */
+/* of-two group, by the subgroup's type from (c_s, d) under the rule of      */
+/* Sec. 5.1 (one-element: its member; listed: L_s[below32(c_s)]; dense:      */
+/* i = below32(d) until digit k of w_i is v).  Build and walks only: the     */
+/* paper leaves updates of nested subgroups open.                            */
+/* ======================================================================== */
+#define R4_SUB 48
+
+typedef struct {
+    uint32_t d;
+    uint32_t *dst, *w;
+    ogroup s[R4_SUB];
+} o4vtx;
+
+typedef struct {
+    uint32_t n;
+    int adaptive;
+    uint32_t alpha, beta;
+    o4vtx *v;
+} o4graph;
+
+static uint32_t r4_digit(uint32_t w, int k) { return (w >> (2 * k)) & 3u; }
+
+int o4_build(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, int adaptive,
+             uint32_t alpha, uint32_t beta, o4graph **out) {
+    *out = NULL;
+    if (n == 0) return O_EINVAL;
+    for (uint64_t e = 0; e < m; e++) {
+        if (src[e] >= n || dst[e] >= n) return O_ERANGE;
+        if (w[e] == 0) return O_EWEIGHT;
+    }
+    o4graph *G = calloc(1, sizeof(o4graph));
+    G->n = n; G->adaptive = adaptive; G->alpha = alpha; G->beta = beta;
+    G->v = calloc(n, sizeof(o4vtx));
+    uint32_t *deg = calloc(n, 4);
+    for (uint64_t e = 0; e < m; e++) deg[src[e]]++;
+    for (uint32_t u = 0; u < n; u++) {
+        G->v[u].dst = malloc((size_t)(deg[u] ? deg[u] : 1) * 4);
+        G->v[u].w = malloc((size_t)(deg[u] ? deg[u] : 1) * 4);
+    }
+    free(deg);
+    /* edges of u in input order */
+    for (uint64_t e = 0; e < m; e++) {
+        o4vtx *x = &G->v[src[e]];
+        x->dst[x->d] = dst[e]; x->w[x->d] = w[e]; x->d++;
+    }
+    for (uint32_t u = 0; u < n; u++) {
+        o4vtx *x = &G->v[u];
+        for (int s = 0; s < R4_SUB; s++) {
+            const int k = s / 3;
+            const uint32_t v = (uint32_t)(s % 3) + 1u;
+            ogroup *g = &x->s[s];
+            g->c = 0;
+            for (uint32_t i = 0; i < x->d; i++) g->c += r4_digit(x->w[i], k) == v;
+            g->type = (uint8_t)o_type(g->c, x->d, adaptive, alpha, beta);
+            g->one = 0;
+            if (g->type == T_ONE) {
+                for (uint32_t i = 0; i < x->d; i++) if (r4_digit(x->w[i], k) == v) { g->one = i; break; }
+            } else if (listed(g->type)) {
+                for (uint32_t i = 0; i < x->d; i++) if (r4_digit(x->w[i], k) == v) list_push(g, i);
+            }
+        }
+    }
+    *out = G;
+    return O_OK;
+}
+
+void o4_free(o4graph *G) {
+    if (!G) return;
+    for (uint32_t u = 0; u < G->n; u++) {
+        free(G->v[u].dst); free(G->v[u].w);
+        for (int s = 0; s < R4_SUB; s++) free(G->v[u].s[s].list);
+    }
+    free(G->v);
+    free(G);
+}
+
+/* Subgroup selection for tests: the first s (ascending) with r < sum_{j<=s} T_j. */
+int o4_pick_subgroup(const uint32_t c[R4_SUB], uint64_t r) {
+    uint64_t acc = 0;
+    for (int s = 0; s < R4_SUB; s++) {
+        acc += (uint64_t)c[s] * (uint64_t)(s % 3 + 1) << (2 * (s / 3));
+        if (r < acc) return s;
+    }
+    return -1;
+}
+
+static uint32_t o4_step_from(const o4graph *G, uint32_t u, ostream *s) {
+    const o4vtx *x = &G->v[u];
+    if (x->d == 0) return STOPV;
+    uint32_t c[R4_SUB];
+    uint64_t W = 0;
+    for (int j = 0; j < R4_SUB; j++) {
+        c[j] = x->s[j].c;
+        W += (uint64_t)c[j] * (uint64_t)(j % 3 + 1) << (2 * (j / 3));
+    }
+    const int sg = o4_pick_subgroup(c, st_below64(s, W));
+    const ogroup *g = &x->s[sg];
+    const int k = sg / 3;
+    const uint32_t v = (uint32_t)(sg % 3) + 1u;
+    uint32_t i;
+    if (g->type == T_ONE) {
+        i = g->one;
+    } else if (listed(g->type)) {
+        i = g->list[st_below32(s, g->c)];
+    } else {
+        for (;;) {
+            i = st_below32(s, x->d);
+            if (r4_digit(x->w[i], k) == v) break;
+        }
+    }
+    return x->dst[i];
+}
+
+uint32_t o4_step(const o4graph *G, uint32_t u, uint64_t seed, uint64_t walk, uint32_t step) {
+    ostream s; st_init(&s, seed, walk, step);
+    return o4_step_from(G, u, &s);
+}
+
+/* DeepWalk on the base-4 structure, with the walk ids, streams and path layout of o_deepwalk. */
+uint64_t o4_deepwalk(const o4graph *G, uint64_t nwalks, const uint32_t *starts, uint64_t base, uint32_t len,
+                     uint64_t seed, uint32_t *paths, int nthreads) {
+    uint64_t total = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
+#endif
+    for (int64_t j = 0; j < (int64_t)nwalks; j++) {
+        uint32_t *p = paths + (uint64_t)j * (len + 1);
+        uint32_t u = starts[j];
+        p[0] = u;
+        uint32_t t = 0;
+        for (; t < len; t++) {
+            ostream rs; st_init(&rs, seed, base + (uint64_t)j, t);
+            const uint32_t nx = o4_step_from(G, u, &rs);
+            if (nx == STOPV) break;
+            p[t + 1] = nx;
+            u = nx;
+        }
+        total += t;
+        for (; t < len; t++) p[t + 1] = STOPV;
+    }
+    return total;
+}
+
+/* Canonical dump of the base-4 structure: for each vertex ascending: d, the */
+/* mask of non-empty subgroups (two words: subgroups 0..31, 32..47), then    */
+/* (dst, w) per index, then for each non-empty subgroup s ascending: s,      */
+/* type, c, and the member (one-element) or the list (listed).               */
+uint64_t o4_dump(const o4graph *G, uint32_t *out) {
+    uint64_t o = 0;
+#define PUT(v) do { if (out) out[o] = (v); o++; } while (0)
+    for (uint32_t u = 0; u < G->n; u++) {
+        const o4vtx *x = &G->v[u];
+        uint64_t mask = 0;
+        for (int s = 0; s < R4_SUB; s++) if (x->s[s].c) mask |= 1ull << s;
+        PUT(x->d); PUT((uint32_t)mask); PUT((uint32_t)(mask >> 32));
+        for (uint32_t i = 0; i < x->d; i++) { PUT(x->dst[i]); PUT(x->w[i]); }
+        for (int s = 0; s < R4_SUB; s++) {
+            const ogroup *g = &x->s[s];
+            if (!g->c) continue;
+            PUT((uint32_t)s); PUT(g->type); PUT(g->c);
+            if (g->type == T_ONE) PUT(g->one);
+            else if (listed(g->type)) for (uint32_t p = 0; p < g->len; p++) PUT(g->list[p]);
+        }
+    }
+#undef PUT
+    return o;
+}
