@@ -98,6 +98,8 @@ def lib():
             L.o_dump.restype = C.c_uint64
             L.o_dump_range.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, u32p]
             L.o_dump_range.restype = C.c_uint64
+            L.o_index_dump_range.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, u32p]
+            L.o_index_dump_range.restype = C.c_uint64
             L.o_memory.argtypes = [C.c_void_p, u64p]
             L.o4_build.argtypes = [C.c_uint32, C.c_uint64, u32p, u32p, u32p, C.c_int, C.c_uint32, C.c_uint32,
                                    C.POINTER(C.c_void_p)]
@@ -328,6 +330,17 @@ class Graph:
         nw = L.o_dump_range(self.h, ub, ue, None)
         out = np.zeros(max(nw, 1), np.uint32)
         L.o_dump_range(self.h, ub, ue, _p(out, C.c_uint32))
+        return out[:nw]
+
+    def index_dump(self, u_begin=None, u_end=None):
+        """Group indexes: per vertex |S|, S, then per listed group k, the inverted index at the
+        members (regular) or over S (sparse); see o_index_dump_range."""
+        L = lib()
+        ub = 0 if u_begin is None else u_begin
+        ue = self.n if u_end is None else u_end
+        nw = L.o_index_dump_range(self.h, ub, ue, None)
+        out = np.zeros(max(nw, 1), np.uint32)
+        L.o_index_dump_range(self.h, ub, ue, _p(out, C.c_uint32))
         return out[:nw]
 
     def memory(self):

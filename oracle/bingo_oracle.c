@@ -963,6 +963,59 @@ uint64_t o_dump_range(const ograph *G, uint32_t u0, uint32_t u1, uint32_t *out) 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Group indexes (Sec. 4.2 inverted index, Sec. 5.1 sparse and regular      */
+/* groups).  The inverted index of a listed group maps a neighbour index to  */
+/* its position in the group's list.  A regular group keeps it over all d    */
+/* neighbour indices.  A sparse group keeps it over the positions of the     */
+/* reduced neighbour list S(u): the neighbour indices, ascending, of the     */
+/* edges in at least one sparse group of u (reading of the garbled example), */
+/* so that index has |S| entries.  Dump per vertex u ascending: |S|, then S; */
+/* then for each listed group k ascending: k, followed by, for a regular     */
+/* group, its inverted index read at the list's members in list order        */
+/* (inv[L[p]] for p = 0..c-1), for a sparse group its index over S (entry s: */
+/* the position of S[s] in the list, or 0xFFFFFFFF when S[s] is not in it).  */
+/* ------------------------------------------------------------------------ */
+static uint64_t index_vertex(const ograph *G, const ovtx *x, uint32_t *out) {
+    uint64_t o = 0;
+#define PUT(v) do { if (out) out[o] = (v); o++; } while (0)
+    uint32_t smask = 0;
+    for (int k = 0; k < 32; k++) if (x->g[k].type == T_SPARSE) smask |= 1u << k;
+    uint32_t *S = malloc(((size_t)x->d + 1) * 4);
+    uint32_t ns = 0;
+    for (uint32_t i = 0; i < x->d; i++) if (mword(G, x->w[i]) & smask) S[ns++] = i;
+    PUT(ns);
+    for (uint32_t s = 0; s < ns; s++) PUT(S[s]);
+    uint32_t *inv = malloc(((size_t)x->d + 1) * 4);
+    for (int k = 0; k < 32; k++) {
+        const ogroup *g = &x->g[k];
+        if (!listed(g->type)) continue;
+        PUT((uint32_t)k);
+        if (g->type == T_REGULAR) {
+            for (uint32_t i = 0; i < x->d; i++) inv[i] = 0xFFFFFFFFu;
+            for (uint32_t p = 0; p < g->len; p++) inv[g->list[p]] = p;
+            for (uint32_t p = 0; p < g->len; p++) PUT(inv[g->list[p]]);
+        } else {
+            for (uint32_t s = 0; s < ns; s++) {
+                uint32_t pos = 0xFFFFFFFFu;
+                for (uint32_t p = 0; p < g->len; p++) if (g->list[p] == S[s]) { pos = p; break; }
+                PUT(pos);
+            }
+        }
+    }
+    free(inv);
+    free(S);
+#undef PUT
+    return o;
+}
+
+/* Index dump of vertices [u0, u1); returns the number of u32 words, writes them if out != NULL. */
+uint64_t o_index_dump_range(const ograph *G, uint32_t u0, uint32_t u1, uint32_t *out) {
+    uint64_t o = 0;
+    for (uint32_t u = u0; u < u1 && u < G->n; u++) o += index_vertex(G, &G->v[u], out ? out + o : NULL);
+    return o;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Memory model.  out[0] adjacency bytes (12 per edge); out[t] for t = 1..4  */
 /* group bytes by type (one-element, dense, sparse, regular) under adaption: */
 /* one-element 4, dense 0, regular                                           */
