@@ -107,6 +107,9 @@ typedef struct {
     uint64_t model_ga_bytes;        /* paper's memory model with adaption (Sec. 5.1) */
     uint64_t model_bs_bytes;        /* ... and without (all regular, Sec. 6.2) */
     uint64_t alias_bytes;           /* inter-group alias rows (alias_table = 1): 512 B per vertex, else 0 */
+    uint64_t index_bytes;           /* live group indexes (Sec. 4.2, 5.1): 4 d per regular group, 4 |S(u)|
+                                       per sparse group and for S(u) itself */
+    uint64_t index_reserved_bytes;  /* their capacities in the pool (list_reserved_bytes counts the lists) */
 } bingo_mem_stats;
 
 /*
@@ -197,10 +200,10 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
  * pool holds blocks that earlier updates replaced or the library sized it
  * (bingo_config.pool_bytes = 0), the call compacts it (into an arena twice the
  * size for a library-sized pool) and applies the records not yet applied, in
- * their order, once more.  Records of different sources are independent, so
- * the result is that of the whole stream.  BINGO_E_OOM if a source still runs
- * out: it keeps the records before the failing one (the structure is
- * consistent).  On BINGO_OK every record was applied exactly once
+ * their order; this repeats, at most 8 times, while a pass runs out.  Records
+ * of different sources are independent, so the result is that of the whole
+ * stream.  BINGO_E_OOM if a source still runs out: it keeps the records before
+ * the failing one (the structure is consistent).  On BINGO_OK every record was applied exactly once
  * (inserted + deleted + not_found = n, checked on the host; BINGO_E_INTERNAL
  * otherwise).
  */
@@ -324,6 +327,25 @@ int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* 
  */
 int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                        uint64_t* h_len, void* stream);
+
+/*
+ * bingo_export_index_range -- the group indexes of vertices [u_begin, u_end)
+ * (Sec. 4.2: the inverted index that maps a neighbor index to its position in
+ * a group's list; Sec. 5.1: the reduced neighbor list S(u) of a vertex, the
+ * ascending neighbor indices of its edges that belong to at least one sparse
+ * group, over whose positions a sparse group keeps its smaller index).  Host
+ * memory, little-endian uint32 words, for each vertex u ascending: |S(u)|,
+ * then S(u); then for each sparse or regular group k ascending: k, followed
+ * by, for a regular group, its index read at the list's members in list order
+ * (index[L[p]] for p = 0..c-1, which is p for a consistent index), for a
+ * sparse group, for each s < |S(u)|, the position of S[s] in the group's list
+ * or 0xFFFFFFFF when S[s] is not a member.  The structures live in the pool
+ * with the lists (bingo_mem_stats counts them); walks never read them.  With
+ * h_buf == NULL only *h_len (words) is set.  Synchronizes.  BINGO_E_INVALID
+ * for a bad range, BINGO_E_CAPACITY if cap_words is too small.
+ */
+int bingo_export_index_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf,
+                             uint64_t cap_words, uint64_t* h_len, void* stream);
 
 /*
  * bingo_compact -- pool compaction (the dynamic arrays of Sec. 5.2 grow by

@@ -48,7 +48,8 @@ class _MemStats(C.Structure):
                 ("header_bytes", C.c_uint64), ("adjacency_bytes", C.c_uint64),
                 ("adjacency_reserved_bytes", C.c_uint64), ("list_bytes", C.c_uint64),
                 ("list_reserved_bytes", C.c_uint64), ("groups_by_type", C.c_uint64 * 5),
-                ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64), ("alias_bytes", C.c_uint64)]
+                ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64), ("alias_bytes", C.c_uint64),
+                ("index_bytes", C.c_uint64), ("index_reserved_bytes", C.c_uint64)]
 
 
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
@@ -56,7 +57,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
-           "bingo_compact", "bingo_walk_batch"]
+           "bingo_compact", "bingo_walk_batch", "bingo_export_index_range"]
 
 
 class _ServerConfig(C.Structure):
@@ -108,6 +109,7 @@ def load():
         L.bingo_ppr_fetch.argtypes = [vp, vp, vp, vp, u64, vp]
         L.bingo_export.argtypes = [vp, vp, u64, C.POINTER(u64), vp]
         L.bingo_export_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
+        L.bingo_export_index_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
         L.bingo_compact.argtypes = [vp, C.c_uint64, vp]
         L.bingo_walk_batch.argtypes = [vp, C.c_uint32, C.POINTER(_WalkQuery), vp]
@@ -309,6 +311,20 @@ class Graph:
         rc = L.bingo_export_range(self.h, ub, ue, C.c_void_p(buf.ctypes.data), buf.size, C.byref(n),
                                   _stream(stream))
         _check(rc, "bingo_export")
+        return buf[: n.value]
+
+    def export_index(self, u_begin=None, u_end=None, stream=None) -> np.ndarray:
+        """Group index dump as uint32 words (layout in include/bingo.h, bingo_export_index_range)."""
+        L = load()
+        n = C.c_uint64(0)
+        ub = 0 if u_begin is None else u_begin
+        ue = self.n if u_end is None else u_end
+        rc = L.bingo_export_index_range(self.h, ub, ue, None, 0, C.byref(n), _stream(stream))
+        _check(rc, "bingo_export_index_range")
+        buf = np.zeros(max(n.value, 1), dtype=np.uint32)
+        rc = L.bingo_export_index_range(self.h, ub, ue, C.c_void_p(buf.ctypes.data), buf.size, C.byref(n),
+                                        _stream(stream))
+        _check(rc, "bingo_export_index_range")
         return buf[: n.value]
 
     def compact(self, pool_bytes=0, stream=None):

@@ -186,6 +186,12 @@ int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_
     return export_graph(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
+int bingo_export_index_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
+                             uint64_t* h_len, void* stream) {
+    if (!g || !h_len) return BINGO_E_INVALID;
+    return export_index(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
+}
+
 int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream) {
     if (!g) return BINGO_E_INVALID;
     if (pool_bytes > (1ull << 37)) return BINGO_E_INVALID;

@@ -80,9 +80,19 @@ __global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __res
         }
     }
     const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
+    // |S(u)|: the edges in at least one sparse group (Sec. 5.1)
+    const uint32_t smask = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+    uint32_t slen = 0;
+    for (uint32_t c0 = 0; smask && c0 < d; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        const bool in = i < d && (member_word(cw[b + i], rule.fbits) & smask);
+        slen += __popcll(__ballot(in));
+    }
+    const uint32_t cap = adj_cap_for(d), scap = s_cap_for(slen);
     // W = sum of the weights (= sum_k c_k 2^k for integer biases)
     uint64_t wsum = wraw;
-    uint64_t lw = type_listed(t) ? (uint64_t)list_cap_for(cnt) : 0ull;
+    // pool words: each listed group's block (list, then index), then the S(u) block
+    uint64_t lw = type_listed(t) ? list_block_words(list_cap_for(cnt), index_cap_for(t, cap, scap)) : 0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         wsum += __shfl_xor(wsum, o);
@@ -95,20 +105,22 @@ __global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __res
         h[H_INFO + lane] = (t == GT_ONE) ? last : 0u;
     }
     if (lane == 0) {
-        const uint32_t cap = adj_cap_for(d);
         h[H_MASK] = (uint32_t)mask;
         h[H_DEG] = d;
         h[H_WLO] = (uint32_t)wsum;
         h[H_WHI] = (uint32_t)(wsum >> 32);
         h[H_ACAP] = cap;
         h[H_NSEQ] = d;
+        h[H_SLEN] = slen;
+        h[H_SCAP] = scap;
+        h[H_SBLK] = 0;
         adjw[u] = adj_block_words(cap);
-        listw[u] = lw;
+        listw[u] = lw + scap;
     }
 }
 
-// Pass 2: adjacency blocks (edge words and sequence numbers) and listed-group
-// lists (ascending neighbor indices).
+// Pass 2: adjacency blocks (edge words and sequence numbers), listed-group
+// lists (ascending neighbor indices) with their indexes, and S(u).
 __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restrict__ start,
                                              const uint32_t* __restrict__ cdst, const uint32_t* __restrict__ cw,
                                              const uint64_t* __restrict__ adj_off, const uint64_t* __restrict__ list_off,
@@ -134,14 +146,20 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
     const bool lst = type_listed(t);
     const uint32_t lcap = lst ? list_cap_for(cnt) : 0u;
-    uint64_t x = lcap;  // inclusive scan over lanes
+    const uint32_t scap = h[H_SCAP];
+    // lanes 0..31: the group blocks (list, then index); lane 32: the S(u) block
+    const uint64_t bw = lst ? list_block_words(lcap, index_cap_for(t, cap, scap)) : (lane == 32 ? scap : 0ull);
+    uint64_t x = bw;  // inclusive scan over lanes
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint64_t y = __shfl_up(x, o, 64);
         if (lane >= (uint32_t)o) x += y;
     }
-    const uint64_t my_block = list_base + list_off[u] + (x - lcap);  // words
+    const uint64_t my_block = list_base + list_off[u] + (x - bw);  // words
     if (lane < 32 && lst) h[H_INFO + lane] = (uint32_t)(my_block / LIST_UNIT_WORDS);
+    if (lane == 32) h[H_SBLK] = (uint32_t)(my_block / LIST_UNIT_WORDS);
+    const uint64_t sblk = __shfl(my_block, 32, 64);
+    const uint32_t smask = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
     // one-element groups: the member's destination in the count slot
     const bool one = lane < 32 && t == GT_ONE;
     if (one) h[H_CNT + lane] = cdst[b + h[H_INFO + lane]];
@@ -155,7 +173,8 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     packed |= __shfl_xor(packed, 2);
     if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
     const uint32_t lmask = (uint32_t)(__ballot(lst) & 0xFFFFFFFFull);
-    uint32_t fill = 0;  // lane k: entries written so far into group k
+    uint32_t fill = 0;   // lane k: entries written so far into group k
+    uint32_t sfill = 0;  // entries written so far into S(u) (uniform)
     for (uint32_t c0 = 0; c0 < d; c0 += 64) {
         const uint32_t i = c0 + lane;
         uint32_t wv = 0;
@@ -165,6 +184,12 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
             seqs[i] = i;
             wv = member_word(w, rule.fbits);
         }
+        // S(u) in ascending index order; spos is this edge's position in it
+        const bool sb = (wv & smask) != 0u;
+        const uint64_t sbal = __ballot(sb);
+        const uint32_t spos = sfill + __popcll(sbal & lanemask_lt());
+        if (sb) pool[sblk + spos] = i;
+        sfill += __popcll(sbal);
         uint32_t mm = lmask;
         while (mm) {
             const int k = __ffs(mm) - 1;
@@ -173,7 +198,13 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
             const uint64_t bal = __ballot(bit);
             const uint64_t blk = __shfl(my_block, k, 64);
             const uint32_t f = __shfl(fill, k, 64);
-            if (bit) pool[blk + f + __popcll(bal & lanemask_lt())] = i;
+            const uint32_t lk = __shfl(lcap, k, 64);
+            const bool reg = ((smask >> k) & 1u) == 0u;  // a listed group that is not sparse is regular
+            if (bit) {
+                const uint32_t pos = f + __popcll(bal & lanemask_lt());
+                pool[blk + pos] = i;
+                pool[blk + lk + (reg ? i : spos)] = pos;  // the group's index entry
+            }
             if (lane == (uint32_t)k) fill += __popcll(bal);
         }
     }
@@ -271,6 +302,118 @@ __global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// S(u) rebuild (Sec. 5.1 sparse groups): after an update, S(u) = the ascending
+// neighbor indices i < d whose membership word meets the sparse mask, written
+// into the vertex's S(u) block; then every sparse group's index over S(u):
+// entry s = the position of S[s] in the group's list.  One block per vertex.
+// Pass 1 ranks the flagged entries of each tile of SR_TB * SR_TPT indices by
+// ballots (rows of SR_TB consecutive indices, waves in order); pass 2 finds
+// each list member's position in S(u) by a search that starts in LDS samples
+// of S(u) (every 2^sh-th entry) and ends with at most sh steps in global memory.
+// ---------------------------------------------------------------------------
+constexpr int SR_TB = 256;
+constexpr uint32_t SR_TPT = 4;
+constexpr uint32_t SR_XL = 4096;
+
+__global__ void __launch_bounds__(SR_TB) k_srebuild(uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                                    uint32_t n, GroupRule rule, const uint32_t* __restrict__ list,
+                                                    const unsigned long long* __restrict__ dcount, uint64_t maxc,
+                                                    const uint32_t* __restrict__ dirty) {
+    __shared__ uint32_t smp[SR_XL];
+    __shared__ uint32_t g_c[32], g_info[32], g_lcap[32];
+    __shared__ uint32_t wcnt[SR_TPT][SR_TB / 64];
+    __shared__ uint32_t s_smask;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint64_t total = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
+    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        if (dirty && !dirty[it]) continue;
+        const uint32_t u = list ? list[it] : (uint32_t)it;
+        if (u >= n) continue;
+        uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        __syncthreads();  // the previous vertex is done with the shared arrays
+        if (wave == 0) {
+            const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
+            const bool ne = lane < 32 && ((mask >> lane) & 1u);
+            const uint32_t c = ne ? slot_count(h[H_CNT + lane], onem, lane) : 0u;
+            const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+            const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+            if (lane < 32) {
+                g_c[lane] = c;
+                g_info[lane] = h[H_INFO + lane];
+                g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+            }
+            if (lane == 0) s_smask = sm;
+        }
+        __syncthreads();
+        const uint32_t smask = s_smask;
+        if (!smask) {
+            if (tid == 0) h[H_SLEN] = 0;
+            continue;
+        }
+        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
+        uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+        uint32_t sfill = 0;
+        for (uint32_t q0 = 0; q0 < d; q0 += SR_TB * SR_TPT) {
+            uint64_t bal[SR_TPT];
+            bool in[SR_TPT];
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                const uint32_t i = q0 + j * SR_TB + tid;
+                in[j] = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask) != 0u;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                bal[j] = __ballot(in[j]);
+                if (lane == 0) wcnt[j][wave] = (uint32_t)__popcll(bal[j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                uint32_t rk = sfill + (uint32_t)__popcll(bal[j] & lanemask_lt());
+                for (uint32_t w = 0; w < wave; ++w) rk += wcnt[j][w];
+                if (in[j]) S[rk] = q0 + j * SR_TB + tid;
+                sfill += wcnt[j][0] + wcnt[j][1] + wcnt[j][2] + wcnt[j][3];
+            }
+            __syncthreads();  // wcnt is rewritten by the next tile
+        }
+        if (tid == 0) h[H_SLEN] = sfill;
+        __threadfence_block();
+        __syncthreads();  // S(u) complete and visible to the block
+        uint32_t sh = 0;
+        while ((sfill >> sh) >= SR_XL) ++sh;
+        const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
+        for (uint32_t j = tid; j < nl; j += SR_TB) smp[j] = S[(uint64_t)j << sh];
+        __syncthreads();
+        for (uint32_t mm = smask; mm; mm &= mm - 1) {
+            const int k = __ffs(mm) - 1;
+            const uint32_t c = g_c[k];
+            uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
+            uint32_t* I = L + g_lcap[k];
+            for (uint32_t p = tid; p < c; p += SR_TB) {
+                const uint32_t v = L[p];
+                uint32_t lo = 0, hi = nl;  // samples below v
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (smp[mid] < v) lo = mid + 1; else hi = mid;
+                }
+                uint32_t pos = 0;
+                if (lo > 0) {
+                    uint32_t a = ((lo - 1) << sh) + 1, b = min(lo << sh, sfill);
+                    while (a < b) {
+                        const uint32_t mid = (a + b) >> 1;
+                        if (S[mid] < v) a = mid + 1; else b = mid;
+                    }
+                    pos = a;
+                }
+                I[pos] = p;
+            }
+        }
+    }
+}
+
 int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
     int b = 0;
     while (b < 64 && (v >> b)) ++b;
@@ -284,6 +427,14 @@ void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* 
     if (!g->alias || max_count == 0) return;
     hipLaunchKernelGGL(k_alias_rows, dim3(grid_for(max_count, ALIAS_TB)), dim3(ALIAS_TB), 0, st,
                        (const uint32_t*)g->hdr, g->n, list, count, max_count, g->alias);
+}
+
+void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
+                    const uint32_t* dirty, hipStream_t st) {
+    if (max_count == 0 || !g->rule.adaptive) return;  // without adaption no group is sparse
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(max_count, 4096);
+    hipLaunchKernelGGL(k_srebuild, dim3(grid), dim3(SR_TB), 0, st, g->hdr, g->pool, g->n, g->rule, list, count,
+                       max_count, dirty);
 }
 
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st) {

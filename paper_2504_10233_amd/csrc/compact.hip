@@ -1,6 +1,7 @@
 // compact.hip -- pool compaction.  Every live block (a vertex's adjacency block
 // at its capacity, one list block per listed group at its capacity; Sec. 5.2
-// dynamic arrays) is copied into a fresh arena in vertex order and the headers
+// dynamic arrays; each with its group index, Sec. 4.2; the reduced list S(u),
+// Sec. 5.1) is copied into a fresh arena in vertex order and the headers
 // take the new offsets; the blocks that earlier batches replaced by larger ones
 // (the pool's garbage) stay behind.  Block sizes and contents do not change, so
 // neither does the canonical dump nor any walk: only where blocks live.
@@ -11,13 +12,17 @@ namespace {
 
 constexpr int WB = 256;
 
-// Lane k < 32: the list capacity (words) of group k if it is listed, else 0.
+// Lane k < 32: the block words (list and index) of group k if it is listed;
+// lane 32: the S(u) block; other lanes 0.
 __device__ __forceinline__ uint64_t lane_list_words(const uint32_t* __restrict__ h, uint32_t d, uint32_t mask,
                                                     uint32_t lane, GroupRule rule) {
+    if (lane == 32) return h[H_SCAP];
     if (lane >= 32 || !((mask >> lane) & 1u)) return 0ull;
     const uint32_t c = slot_count(h[H_CNT + lane], h[H_ONEMASK], lane);
-    if (!type_listed(group_type(c, d, rule))) return 0ull;
-    return 1ull << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+    const uint32_t t = group_type(c, d, rule);
+    if (!type_listed(t)) return 0ull;
+    const uint32_t lcap = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+    return list_block_words(lcap, index_cap_for(t, h[H_ACAP], h[H_SCAP]));
 }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
@@ -46,8 +51,8 @@ __device__ __forceinline__ void wave_copy(const uint32_t* __restrict__ src, uint
 }
 
 // Vertex u's blocks from the old arena to the new one at off[u]: the adjacency
-// block first, then the list blocks in ascending k; the header takes the new
-// offsets.  One wave per vertex.
+// block first, then the list blocks (list and index) in ascending k, then the
+// S(u) block; the header takes the new offsets.  One wave per vertex.
 __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ src,
                                                  uint32_t* __restrict__ dst, uint32_t n, GroupRule rule,
                                                  const uint64_t* __restrict__ off) {
@@ -57,7 +62,7 @@ __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, con
         const uint32_t d = h[H_DEG], mask = h[H_MASK], cap = h[H_ACAP];
         const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
         const uint64_t lw = lane_list_words(h, d, mask, lane, rule);
-        const uint32_t info = lane < 32 ? h[H_INFO + lane] : 0u;
+        const uint32_t info = lane < 32 ? h[H_INFO + lane] : (lane == 32 ? h[H_SBLK] : 0u);
         uint64_t o = off[u];
         if (cap) {
             const uint64_t words = adj_block_words(cap);
@@ -76,13 +81,14 @@ __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, con
             if (lane >= (uint32_t)s) x += y;
         }
         const uint64_t mine = o + (x - lw);
-        for (uint32_t lm = (uint32_t)(__ballot(lw != 0) & 0xFFFFFFFFull); lm; lm &= lm - 1) {
-            const int k = __ffs(lm) - 1;
+        for (uint64_t lm = __ballot(lw != 0); lm; lm &= lm - 1) {
+            const int k = __ffsll((long long)lm) - 1;
             const uint64_t from = (uint64_t)__shfl(info, k, 64) * LIST_UNIT_WORDS;
             const uint64_t to = __shfl(mine, k, 64);
             wave_copy(src + from, dst + to, __shfl(lw, k, 64), lane);
         }
-        if (lw) h[H_INFO + lane] = (uint32_t)(mine / LIST_UNIT_WORDS);
+        if (lw && lane < 32) h[H_INFO + lane] = (uint32_t)(mine / LIST_UNIT_WORDS);
+        if (lw && lane == 32) h[H_SBLK] = (uint32_t)(mine / LIST_UNIT_WORDS);
     }
 }
 

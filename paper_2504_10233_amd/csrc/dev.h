@@ -14,7 +14,8 @@
 //   line 1: slot k for k = 26..31, info_k for k = 0..25
 //   line 2: info_k for k = 26..31, adjacency capacity, next sequence number,
 //           log2 of each listed group's list capacity (bytes), mask of
-//           non-empty groups, spare
+//           non-empty groups, the reduced list S(u) (block offset, length,
+//           capacity), spare
 // Slot k holds c_k, except for a one-element group (c_k = 1), whose slot holds
 // its member's destination vertex: a step that selects such a group ends on
 // line 0 without touching the adjacency.  info_k is the member index of a
@@ -35,6 +36,9 @@
 #define H_ACAP 70
 #define H_NSEQ 71
 #define H_LCAPLOG 72   // 32 bytes = 8 words
+#define H_SBLK 81      // S(u) block offset in 32-byte units (valid when H_SCAP > 0)
+#define H_SLEN 82      // |S(u)|
+#define H_SCAP 83      // S(u) capacity in entries (0: the vertex has no sparse group)
 #define STOP_VERTEX 0xFFFFFFFFu
 
 // c_k from slot k (one-element groups keep their member's destination there)
@@ -44,7 +48,17 @@ __host__ __device__ inline uint32_t slot_count(uint32_t slot, uint32_t onemask, 
 
 // Adjacency block of capacity cap (words): cap edge words of 64 bits
 // (dst | weight << 32) followed by cap sequence numbers (u32).
-// List block: cap u32 neighbor indices, 32-byte aligned.
+// List block of a listed group (Sec. 4.2 intra-group neighbor index list and
+// inverted index; Sec. 5.1 sparse and regular groups), 32-byte aligned:
+//   [0, lcap)              the list L: neighbor indices
+//   [lcap, lcap + icap)    the group's index.  Regular: icap = the adjacency
+//                          capacity, entry i = position of neighbor index i in
+//                          L.  Sparse: icap = the capacity of the vertex's
+//                          reduced list S(u), entry s = position of S[s] in L.
+// Only the entries of members are kept: an entry is valid when it is below c
+// and L at that position holds the index (resp. S[s]), so no index needs
+// clearing.  S(u) block: the neighbor indices, ascending, of the edges that
+// belong to at least one sparse group of u (capacity H_SCAP entries).
 #define LIST_UNIT_WORDS 8u
 
 enum { GT_EMPTY = 0, GT_ONE = 1, GT_DENSE = 2, GT_SPARSE = 3, GT_REGULAR = 4 };
@@ -107,6 +121,17 @@ __host__ __device__ inline uint32_t list_cap_for(uint32_t c) {
     while (x < c) x <<= 1;
     return x;
 }
+// index capacity of a listed group of type t: the adjacency capacity (regular)
+// or the S(u) capacity (sparse)
+__host__ __device__ inline uint32_t index_cap_for(uint32_t t, uint32_t acap, uint32_t scap) {
+    return t == GT_REGULAR ? acap : (t == GT_SPARSE ? scap : 0u);
+}
+// words of a list block: the list, then the index, rounded to the 32-byte unit
+__host__ __device__ inline uint64_t list_block_words(uint32_t lcap, uint32_t icap) {
+    return ((uint64_t)lcap + icap + 7) & ~7ull;
+}
+// S(u) capacity for an upper bound on |S(u)| (0: no sparse group)
+__host__ __device__ inline uint32_t s_cap_for(uint32_t n) { return n ? list_cap_for(n) : 0u; }
 
 // ---------------------------------------------------------------------------
 // Counter-based random stream (Philox-4x32-10, Salmon et al. SC'11).  The
@@ -314,6 +339,11 @@ void sort_pairs_u64_dn(const uint64_t* keys_in, const uint32_t* vals_in, uint64_
 // alias rows of the vertices list[0 .. *count) (list == nullptr: vertices 0 .. *count)
 void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
                 hipStream_t st);
+// S(u) (Sec. 5.1) and every sparse group's index over it, rebuilt for the vertices
+// list[0 .. *count) (list == nullptr: vertices 0 .. *count) whose dirty flag is set
+// (dirty == nullptr: all of them), from the final adjacency, types and lists
+void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
+                    const uint32_t* dirty, hipStream_t st);
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st);
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);
@@ -332,6 +362,8 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
             hipStream_t st);
 // export.hip
 int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
+                 hipStream_t st);
+int export_index(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
                  hipStream_t st);
 int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
 // update.hip

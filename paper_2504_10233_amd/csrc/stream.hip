@@ -11,8 +11,10 @@
 // slot, and fixes every list it touched: the deleted member's position takes
 // the list's last entry, and the moved entry is renamed.  A group whose type
 // changes gets a fresh ascending list or its one member, as in the batch.
-// Without an inverted index the positions inside a list are found by a wave
-// scan of that list.
+// A regular group finds a member's position through its inverted index
+// (Sec. 4.2) and keeps the index in step; a sparse group's list is short (below
+// beta % of d) and is scanned, and S(u) with the sparse indexes is rebuilt for
+// the touched sources after the stream.
 #include "dev.h"
 #include <algorithm>
 #include <string.h>
@@ -105,18 +107,35 @@ __device__ uint32_t st_find(const uint32_t* __restrict__ L, uint32_t len, uint32
     return NF;
 }
 
-// Per-vertex state between records; lane k < 32 holds group k.
+// Per-vertex state between records; lane k < 32 holds group k.  sblk / scap:
+// the S(u) block (Sec. 5.1); sdirty: a record touched a vertex with sparse
+// groups, so S(u) and the sparse indexes are rebuilt after the stream.
 struct SV {
     uint32_t u, d, cap, nseq;
     uint64_t adj, W;
+    uint32_t sblk, scap;
+    bool sdirty;
     uint32_t c, info, lcap;
 };
 
+// The S(u) capacity after a record: an upper bound on |S(u)| (the sum of the
+// sparse groups' counts, at most d), kept when the current capacity holds it.
+__device__ __forceinline__ uint32_t st_scap(uint32_t tnew, uint32_t cn, uint32_t d1, uint32_t scap, uint32_t& smn) {
+    smn = (uint32_t)(__ballot(tnew == GT_SPARSE) & 0xFFFFFFFFull);
+    uint64_t sub = tnew == GT_SPARSE ? cn : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sub += __shfl_xor(sub, o);
+    sub = sub < d1 ? sub : d1;
+    return smn ? (sub > scap ? s_cap_for((uint32_t)sub) : scap) : 0u;
+}
+
 // Group-k lists that need writing after an adjacency change: every group in
 // `todo` gets a fresh ascending list of the indices in [0, d) whose membership
-// word has bit k, in the block `blk` (lane k's value).
+// word has bit k, in the block `blk` (lane k's value); a regular group's
+// inverted index follows at iofs (lane k's value; 0 for a sparse group, whose
+// index is rebuilt with S(u)).
 __device__ void st_fresh_lists(uint32_t todo, const uint64_t* __restrict__ edges, uint32_t d, uint32_t fb,
-                               uint64_t blk, uint32_t* __restrict__ pool) {
+                               uint64_t blk, uint32_t iofs, uint32_t* __restrict__ pool) {
     const uint32_t lane = lane_id();
     uint32_t fill = 0;  // lane k: entries written to group k
     for (uint32_t i0 = 0; i0 < d && todo; i0 += 64) {
@@ -130,7 +149,12 @@ __device__ void st_fresh_lists(uint32_t todo, const uint64_t* __restrict__ edges
             const uint64_t b = __ballot(bit);
             const uint64_t kb = __shfl(blk, k, 64);
             const uint32_t f = __shfl(fill, k, 64);
-            if (bit) pool[kb + f + __popcll(b & lanemask_lt())] = i;
+            const uint32_t io = __shfl(iofs, k, 64);
+            if (bit) {
+                const uint32_t pos = f + __popcll(b & lanemask_lt());
+                pool[kb + pos] = i;
+                if (io) pool[kb + io + i] = pos;
+            }
             if (lane == (uint32_t)k) fill += __popcll(b);
         }
     }
@@ -158,16 +182,21 @@ __device__ uint32_t st_first_members(uint32_t todo, const uint64_t* __restrict__
 }
 
 // Copy the live part of every list in `todo` to its new block (lane k: old and
-// new block offsets, length).
-__device__ void st_move_lists(uint32_t todo, uint64_t oblk, uint64_t nblk, uint32_t len,
+// new block offsets, length); a regular group's inverted index is written anew
+// at iofs (lane k's value, 0 for a sparse group).
+__device__ void st_move_lists(uint32_t todo, uint64_t oblk, uint64_t nblk, uint32_t len, uint32_t iofs,
                               uint32_t* __restrict__ pool) {
     const uint32_t lane = lane_id();
     while (todo) {
         const int k = __ffs(todo) - 1;
         todo &= todo - 1;
         const uint64_t o = __shfl(oblk, k, 64), nb = __shfl(nblk, k, 64);
-        const uint32_t L = __shfl(len, k, 64);
-        for (uint32_t p = lane; p < L; p += 64) pool[nb + p] = pool[o + p];
+        const uint32_t L = __shfl(len, k, 64), io = __shfl(iofs, k, 64);
+        for (uint32_t p = lane; p < L; p += 64) {
+            const uint32_t e = pool[o + p];
+            pool[nb + p] = e;
+            if (io) pool[nb + io + e] = p;
+        }
     }
 }
 
@@ -183,6 +212,9 @@ __device__ void st_count(uint32_t code, unsigned long long* acc) {
 
 // One insert record.  Returns false when the pool cannot hold what it needs
 // (nothing changed then).  `freed` is per lane (summed over the wave later).
+// Blocks move when a list outgrows its capacity or an index outgrows its block
+// (a regular group's inverted index spans the adjacency capacity, a sparse
+// group's index the S(u) capacity).
 __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_t* __restrict__ pool,
                           unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc) {
     const uint32_t lane = lane_id();
@@ -196,12 +228,19 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
     const uint32_t tnew = g ? group_type(cn, d1, rule) : GT_EMPTY;
     const bool kept = type_listed(told) && tnew == told;
     const bool fresh = type_listed(tnew) && !kept;
-    const bool relist = kept && bit && cn > s.lcap;
-    // pool words: a larger adjacency block, moved or fresh lists
     const bool grow = d1 > s.cap;
     const uint32_t ncap = grow ? adj_cap_for(d1) : s.cap;
+    const uint32_t smo = (uint32_t)(__ballot(told == GT_SPARSE) & 0xFFFFFFFFull);
+    uint32_t smn = 0;
+    const uint32_t scapn = st_scap(tnew, cn, d1, s.scap, smn);
+    const uint32_t ico = index_cap_for(told, s.cap, s.scap), icn = index_cap_for(tnew, ncap, scapn);
+    const bool relist = kept && ((bit && cn > s.lcap) || icn != ico);
+    const uint32_t nlc = fresh ? list_cap_for(cn) : (relist && cn > s.lcap ? list_cap_for(cn) : s.lcap);
+    const uint32_t iofs = tnew == GT_REGULAR ? nlc : 0u;
+    // pool words: a larger adjacency block, moved or fresh lists, a larger S(u) block (lane 32)
     const uint64_t aw = grow ? adj_block_words(ncap) : 0ull;
-    const uint64_t lw = (relist || fresh) ? (uint64_t)list_cap_for(cn) : 0ull;
+    uint64_t lw = (relist || fresh) ? list_block_words(nlc, icn) : 0ull;
+    if (lane == 32 && scapn && scapn != s.scap) lw = scapn;
     uint64_t x = lw;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -230,25 +269,36 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
         pool[s.adj + 2ull * s.cap + s.d] = s.nseq;
     }
     __threadfence_block();
-    // kept lists: move the ones that outgrow their block, then append index d
+    // kept lists: move the ones whose list or index outgrows its block, then append index d
+    // (at position c; a regular group's inverted index maps d to c)
     const uint64_t oblk = (uint64_t)s.info * LIST_UNIT_WORDS;
     const uint32_t rmask = (uint32_t)(__ballot(relist) & 0xFFFFFFFFull);
-    st_move_lists(rmask, oblk, myblk, s.c, pool);
+    st_move_lists(rmask, oblk, myblk, s.c, iofs, pool);
     if (relist) {
-        freed += s.lcap;
+        freed += list_block_words(s.lcap, ico);
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = list_cap_for(cn);
+        s.lcap = nlc;
     }
-    if (kept && bit) pool[(uint64_t)s.info * LIST_UNIT_WORDS + s.c] = s.d;
+    if (kept && bit) {
+        uint32_t* L = pool + (uint64_t)s.info * LIST_UNIT_WORDS;
+        L[s.c] = s.d;
+        if (tnew == GT_REGULAR) L[s.lcap + s.d] = s.c;
+    }
     // lists of groups that became listed or switched between sparse and regular
-    if (g && type_listed(told) && !kept) freed += s.lcap;
+    if (g && type_listed(told) && !kept) freed += list_block_words(s.lcap, ico);
     const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
     if (fresh) {
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = list_cap_for(cn);
+        s.lcap = nlc;
     }
     __threadfence_block();
-    st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
+    st_fresh_lists(fmask, edges, d1, fb, myblk, iofs, pool);
+    // S(u): a new block when its capacity grows (rebuilt with the sparse indexes after the stream)
+    const uint64_t nsblk = __shfl(myblk, 32, 64);
+    if (lane == 32 && s.scap && scapn != s.scap) freed += s.scap;
+    if (scapn && scapn != s.scap) s.sblk = (uint32_t)(nsblk / LIST_UNIT_WORDS);
+    s.scap = scapn;
+    s.sdirty |= (smo | smn) != 0u;
     // one-element groups: an old member stays; a new one is the inserted edge
     if (tnew == GT_ONE && told != GT_ONE) s.info = s.d;
     if (g && !type_listed(tnew) && tnew != GT_ONE) s.info = 0;
@@ -262,9 +312,21 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
     return true;
 }
 
+// Position of neighbor index i in a kept listed group (lane k's group, every
+// lane calls for the same k): through the inverted index for a regular group
+// (Sec. 4.2, O(1)), by a wave scan of the list for a sparse one.  NF when the
+// index does not hold i at a valid position (an inconsistent structure).
+__device__ __forceinline__ uint32_t st_pos(const uint32_t* __restrict__ L, uint32_t c, uint32_t lcap, bool regular,
+                                           uint32_t i) {
+    if (!regular) return st_find(L, c, i);
+    const uint32_t p = L[lcap + i];
+    return (p < c && L[p] == i) ? p : NF;
+}
+
 // One delete record.
 __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restrict__ pool,
-                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc) {
+                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc,
+                          uint32_t* __restrict__ errw) {
     const uint32_t lane = lane_id();
     const uint32_t fb = rule.fbits;
     const bool g = lane < 32;
@@ -312,7 +374,16 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     const uint32_t tnew = g ? group_type(cn, d1, rule) : GT_EMPTY;
     const bool kept = type_listed(told) && tnew == told;
     const bool fresh = type_listed(tnew) && !kept;
-    const uint64_t lw = fresh ? (uint64_t)list_cap_for(cn) : 0ull;
+    const uint32_t smo = (uint32_t)(__ballot(told == GT_SPARSE) & 0xFFFFFFFFull);
+    uint32_t smn = 0;
+    const uint32_t scapn = st_scap(tnew, cn, d1, s.scap, smn);
+    // the adjacency capacity stays, so only a sparse group's index can outgrow its block
+    const uint32_t ico = index_cap_for(told, s.cap, s.scap), icn = index_cap_for(tnew, s.cap, scapn);
+    const bool relist = kept && icn != ico;
+    const uint32_t nlc = fresh ? list_cap_for(cn) : s.lcap;
+    const uint32_t iofs = tnew == GT_REGULAR ? nlc : 0u;
+    uint64_t lw = (relist || fresh) ? list_block_words(nlc, icn) : 0ull;
+    if (lane == 32 && scapn && scapn != s.scap) lw = scapn;
     uint64_t x = lw;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -328,16 +399,33 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
         edges[i] = el;
         seqs[i] = seqs[last];
     }
+    // kept lists whose index outgrows the block move first (sparse groups; indexes rebuilt later)
+    const uint32_t rmask = (uint32_t)(__ballot(relist) & 0xFFFFFFFFull);
+    st_move_lists(rmask, (uint64_t)s.info * LIST_UNIT_WORDS, myblk, s.c, 0u, pool);
+    if (relist) {
+        freed += list_block_words(s.lcap, ico);
+        s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
+    }
     __threadfence_block();
-    // kept lists: the deleted member's position takes the last entry, then the moved entry is renamed
+    // kept lists: the deleted member's position takes the last entry, then the moved entry is
+    // renamed; a regular group finds both positions through its inverted index and updates it
     uint32_t km = (uint32_t)(__ballot(kept && bit) & 0xFFFFFFFFull);
     while (km) {
         const int k = __ffs(km) - 1;
         km &= km - 1;
         uint32_t* L = pool + (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
-        const uint32_t ck = __shfl(s.c, k, 64);
-        const uint32_t p = st_find(L, ck, i);
-        if (lane == 0 && p != NF && p != ck - 1) L[p] = L[ck - 1];
+        const uint32_t ck = __shfl(s.c, k, 64), lk = __shfl(s.lcap, k, 64);
+        const bool reg = __shfl(told, k, 64) == GT_REGULAR;
+        const uint32_t p = st_pos(L, ck, lk, reg, i);
+        if (lane == 0) {
+            if (p == NF) {
+                atomicOr(errw, ERR_INTERNAL);
+            } else if (p != ck - 1) {
+                const uint32_t e = L[ck - 1];
+                L[p] = e;
+                if (reg) L[lk + e] = p;
+            }
+        }
         __threadfence_block();
     }
     if (moved) {
@@ -346,20 +434,28 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
             const int k = __ffs(rm) - 1;
             rm &= rm - 1;
             uint32_t* L = pool + (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
-            const uint32_t len = __shfl(cn, k, 64);
-            const uint32_t q = st_find(L, len, last);
-            if (lane == 0 && q != NF) L[q] = i;
+            const uint32_t len = __shfl(cn, k, 64), lk = __shfl(s.lcap, k, 64);
+            const bool reg = __shfl(told, k, 64) == GT_REGULAR;
+            const uint32_t q = st_pos(L, len, lk, reg, last);
+            if (lane == 0) {
+                if (q == NF) {
+                    atomicOr(errw, ERR_INTERNAL);
+                } else {
+                    L[q] = i;
+                    if (reg) L[lk + i] = q;
+                }
+            }
             __threadfence_block();
         }
     }
     // fresh lists and one-element members from the final adjacency
-    if (g && type_listed(told) && !kept) freed += s.lcap;
+    if (g && type_listed(told) && !kept) freed += list_block_words(s.lcap, ico);
     const uint32_t fmask = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
     if (fresh) {
         s.info = (uint32_t)(myblk / LIST_UNIT_WORDS);
-        s.lcap = list_cap_for(cn);
+        s.lcap = nlc;
     }
-    st_fresh_lists(fmask, edges, d1, fb, myblk, pool);
+    st_fresh_lists(fmask, edges, d1, fb, myblk, iofs, pool);
     const bool one = tnew == GT_ONE;
     uint32_t member = NF;
     if (one && told == GT_ONE) member = (moved && s.info == last) ? i : s.info;
@@ -367,6 +463,12 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     const uint32_t first = st_first_members(scan, edges, d1, fb);
     if (one) s.info = member != NF ? member : first;
     if (g && !type_listed(tnew) && tnew != GT_ONE) s.info = 0;
+    // S(u)
+    const uint64_t nsblk = __shfl(myblk, 32, 64);
+    if (lane == 32 && s.scap && scapn != s.scap) freed += s.scap;
+    if (scapn && scapn != s.scap) s.sblk = (uint32_t)(nsblk / LIST_UNIT_WORDS);
+    s.scap = scapn;
+    s.sdirty |= (smo | smn) != 0u;
     if (lane == 0) acc[1] += 1;
     st_count(g ? told * 5 + tnew : 31u, acc);
     s.c = cn;
@@ -383,7 +485,8 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
                                                  const uint32_t* __restrict__ w, uint32_t* __restrict__ hdr,
                                                  uint32_t* __restrict__ pool, unsigned long long* ctl,
                                                  uint64_t pool_words, GroupRule rule, uint32_t* __restrict__ errw,
-                                                 unsigned long long* __restrict__ out, uint32_t* __restrict__ left) {
+                                                 unsigned long long* __restrict__ out, uint32_t* __restrict__ left,
+                                                 uint32_t* __restrict__ sdirty) {
     __shared__ unsigned long long red[TB / 64][ST_CTRS];  // per-wave counters, written by lane 0
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     // only the validation bits gate the kernel: waves of this same kernel set ERR_OOM in the same
@@ -405,12 +508,15 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         s.c = lane < 32 ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
         s.info = lane < 32 ? h[H_INFO + lane] : 0u;
         s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
+        s.sblk = h[H_SBLK];
+        s.scap = h[H_SCAP];
+        s.sdirty = false;
         bool ok = true;
         uint32_t stop = e;  // first record not applied
         for (uint32_t p = b; p < e && ok; ++p) {
             const uint32_t r = sv[p];
             if (op[r] == OP_INSERT) ok = st_insert(s, dst[r], w[r], rule, pool, ctl, pool_words, freed, acc);
-            else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, freed, acc);
+            else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, freed, acc, errw);
             if (!ok) stop = p;
             __threadfence_block();
         }
@@ -444,6 +550,10 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
             h[H_ADJHI] = (uint32_t)(s.adj >> 32);
             h[H_ACAP] = s.cap;
             h[H_NSEQ] = s.nseq;
+            h[H_SBLK] = s.sblk;
+            h[H_SCAP] = s.scap;
+            if (!s.scap) h[H_SLEN] = 0;
+            sdirty[sg] = (s.scap && s.sdirty) ? 1u : 0u;
         }
     }
     // garbage words of the wave, then the block's counters
@@ -495,14 +605,17 @@ void add_stats(bingo_update_stats* a, const bingo_update_stats& b) {
     for (int i = 0; i < 25; ++i) a->transitions[i] += b.transitions[i];
 }
 
+// A stream that runs out of pool is continued after a compaction (or a doubling of a
+// library-sized pool) as long as each pass applies some of the records, at most this often.
+constexpr uint32_t STREAM_RETRIES = 8;
 int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
-                 const uint32_t* w, bingo_update_stats* h_stats, bool retry, hipStream_t st);
+                 const uint32_t* w, bingo_update_stats* h_stats, uint32_t retries, hipStream_t st);
 }  // namespace
 
 int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
                   const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st) {
     bingo_update_stats sum{};
-    const int rc = apply_stream(g, m, op, src, dst, w, &sum, true, st);
+    const int rc = apply_stream(g, m, op, src, dst, w, &sum, STREAM_RETRIES, st);
     if (h_stats) *h_stats = sum;
     // every record of a stream that returns OK was applied exactly once: inserted, deleted or
     // counted as an absent delete
@@ -516,12 +629,12 @@ int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t
 
 namespace {
 int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
-                 const uint32_t* w, bingo_update_stats* h_stats, bool retry, hipStream_t st) {
+                 const uint32_t* w, bingo_update_stats* h_stats, uint32_t retries, hipStream_t st) {
     if (m == 0) return BINGO_OK;
     if (m > (1ull << 31)) return BINGO_E_INVALID;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const size_t tmpb = std::max(sort_temp_bytes(m, false), scan_temp_bytes(m));
-    const size_t bytes = al(m * 4) * 7 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
+    const size_t bytes = al(m * 4) * 8 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
     char* ws = (char*)ws_get(g, bytes);
     if (!ws) return BINGO_E_OOM;
     auto take = [&](uint64_t b) { char* r = ws; ws += al(b); return r; };
@@ -532,6 +645,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     uint32_t* seg = (uint32_t*)take(m * 4);
     uint32_t* seg_src = (uint32_t*)take(m * 4);
     uint32_t* left = (uint32_t*)take(m * 4);
+    uint32_t* sdirty = (uint32_t*)take(m * 4);  // per source segment: S(u) to rebuild
     uint64_t* hx = (uint64_t*)take(m * 8);
     unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
     unsigned long long* nseg = (unsigned long long*)take(256);
@@ -539,6 +653,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
     HIPCHK(hipMemsetAsync(out, 0, ST_CTRS * 8, st));
     HIPCHK(hipMemsetAsync(left, 0, m * 4, st));
+    HIPCHK(hipMemsetAsync(sdirty, 0, m * 4, st));
     phase_mark(g, st, true);
     hipLaunchKernelGGL(k_st_validate, dim3(grid_for(m)), dim3(TB), 0, st, m, g->n, op, src, dst, w, g->d_err);
     hipLaunchKernelGGL(k_st_iota, dim3(grid_for(m)), dim3(TB), 0, st, ids, m);
@@ -549,7 +664,9 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     phase_mark(g, st, false);
     hipLaunchKernelGGL(k_st_apply, dim3(ST_GRID), dim3(TB), 0, st, (const uint32_t*)g->d_err,
                        (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
-                       g->pool_words, g->rule, g->d_err, out, left);
+                       g->pool_words, g->rule, g->d_err, out, left, sdirty);
+    // S(u) and the sparse indexes of the sources whose records touched a vertex with sparse groups
+    sparse_rebuild(g, seg_src, nseg, m, sdirty, st);
     // alias-table mode: the sources' inter-group tables (with bad records nothing changed: rewritten as they were)
     alias_rows(g, seg_src, nseg, m, st);
     phase_mark(g, st, false);
@@ -573,7 +690,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
         add_stats(h_stats, part);
         if (!h_stats->touched_vertices) h_stats->touched_vertices = ns;  // the first pass saw every source
     }
-    if (err != ERR_OOM || !retry) return err ? err_to_code(err) : BINGO_OK;
+    if (err != ERR_OOM || !retries) return err ? err_to_code(err) : BINGO_OK;
     // Out of pool: the records each stopped source did not apply are flagged.  Reclaim the
     // replaced blocks, or grow a pool the library sized, and apply those records, in their
     // order, once more (records of different sources are independent, so this equals the
@@ -596,7 +713,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     const bool grow = g->pool_auto && bigger > g->pool_words;
     int rc = BINGO_E_OOM;
     if (ctl[1] > 0 || grow) rc = compact_pool(g, grow ? bigger : 0, st);
-    if (rc == BINGO_OK) rc = apply_stream(g, k, rest, rest + k, rest + 2 * k, rest + 3 * k, h_stats, false, st);
+    if (rc == BINGO_OK) rc = apply_stream(g, k, rest, rest + k, rest + 2 * k, rest + 3 * k, h_stats, retries - 1, st);
     else rc = BINGO_E_OOM;
     HIPCHK(hipFreeAsync(rest, st));
     HIPCHK(hipStreamSynchronize(st));

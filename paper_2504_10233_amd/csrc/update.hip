@@ -506,6 +506,10 @@ struct VState {
     uint32_t ts, ni, nd, N, xoff;
     uint32_t d1, dn;
     uint64_t W;  // fixed-point biases: sum of the weights after the batch (unused for integer biases)
+    // group indexes: adjacency capacity after the batch; S(u) block, capacity before and after
+    // (the new capacity covers an upper bound on |S(u)| after the batch); sparse masks before
+    // and after
+    uint32_t ncap, sblk, scap, scapn, smo, smn;
     // lane k < 32
     uint32_t c, cn, app, del, told, tnew, lcap, info;
 };
@@ -578,15 +582,45 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     s.app = app; s.del = del;
     s.cn = s.c + app - del;
     s.tnew = lane < 32 ? group_type(s.cn, s.dn, rule) : GT_EMPTY;
+    s.ncap = s.dn > s.cap ? adj_cap_for(s.dn) : s.cap;
+    s.sblk = h[H_SBLK];
+    s.scap = h[H_SCAP];
+    s.smo = (uint32_t)(__ballot(s.told == GT_SPARSE) & 0xFFFFFFFFull);
+    s.smn = (uint32_t)(__ballot(s.tnew == GT_SPARSE) & 0xFFFFFFFFull);
+    // |S(u)| after the batch is at most min(d', sum of the new sparse counts)
+    uint64_t sub = s.tnew == GT_SPARSE ? s.cn : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sub += __shfl_xor(sub, o);
+    sub = sub < s.dn ? sub : s.dn;
+    s.scapn = s.smn ? (sub > s.scap ? s_cap_for((uint32_t)sub) : s.scap) : 0u;
 }
 
 __device__ __forceinline__ bool kept_listed(const VState& s) { return type_listed(s.told) && s.tnew == s.told; }
 
-// pool words this vertex allocates: a larger adjacency block, list blocks
+// list capacity of a listed group after the batch (capacities only grow while the type is kept)
+__device__ __forceinline__ uint32_t new_lcap(const VState& s) {
+    if (kept_listed(s)) return s.cn > s.lcap ? list_cap_for(s.cn) : s.lcap;
+    return list_cap_for(s.cn);
+}
+// pool words of lane k's list block before the batch (lane < 32, listed groups)
+__device__ __forceinline__ uint64_t old_block_words(const VState& s) {
+    return list_block_words(s.lcap, index_cap_for(s.told, s.cap, s.scap));
+}
+
+// Pool words this vertex allocates, per lane: lane k < 32 a list block for group
+// k (list and index) when the group becomes listed, changes between sparse and
+// regular, outgrows its list, or its index outgrows its block (regular: the
+// adjacency capacity grows; sparse: the S(u) capacity grows); lane 32 a new
+// S(u) block.  The adjacency block is added by the callers.
 __device__ __forceinline__ uint64_t lane_list_need(const VState& s) {
+    if (lane_id() == 32) return (s.scapn && s.scapn != s.scap) ? (uint64_t)s.scapn : 0ull;
     if (!type_listed(s.tnew)) return 0;
-    if (kept_listed(s)) return s.cn > s.lcap ? (uint64_t)list_cap_for(s.cn) : 0ull;
-    return (uint64_t)list_cap_for(s.cn);
+    const uint32_t icn = index_cap_for(s.tnew, s.ncap, s.scapn);
+    if (kept_listed(s)) {
+        const bool moves = s.cn > s.lcap || icn != index_cap_for(s.told, s.cap, s.scap);
+        return moves ? list_block_words(new_lcap(s), icn) : 0ull;
+    }
+    return list_block_words(list_cap_for(s.cn), icn);
 }
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
@@ -753,7 +787,8 @@ struct BigItem {
     uint32_t dn, nholes, keep, reloc;
     uint32_t sur, hole, ocap, ncap;  // survivor words sur[..], hole slots sur[hole ..], adjacency capacities
     uint64_t a, b, aold;           // block offsets in pool words (meaning per kind, see k_big_apply)
-    uint32_t nh, pad;              // BK_PASSH: holes of the list
+    uint32_t nh;                   // BK_PASSH: holes of the list
+    uint32_t iofs;                 // regular list: its inverted index starts iofs words into block b (0: none)
     unsigned long long hcnt;       // BK_PASSH: hole positions collected so far
 };
 static_assert(sizeof(BigItem) == 104, "BigItem layout");
@@ -798,6 +833,7 @@ struct MutArgs {
     const uint32_t *sv, *id, *wv, *idest;
     const uint64_t* aoff;
     uint32_t* sur;
+    uint32_t* sdirty;  // per touched vertex: 1 when S(u) must be rebuilt
     GroupRule rule;
 };
 
@@ -914,7 +950,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                 bi.kind = BK_COPY; bi.k = 0; bi.n = keep; bi.csize = cs; bi.cbase = cb; bi.u = s.u;
                 bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep; bi.reloc = 1;
                 bi.sur = 0; bi.hole = 0; bi.ocap = s.cap; bi.ncap = ncap; bi.a = s.adj; bi.b = nadj; bi.aold = s.adj;
-                bi.nh = 0; bi.pad = 0; bi.hcnt = 0;
+                bi.nh = 0; bi.iofs = 0; bi.hcnt = 0;
             }
         } else {
             for (uint32_t i = lane; i < keep; i += 64) { enew[i] = eold[i]; qnew[i] = qold[i]; }
@@ -930,10 +966,16 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         }
     }
     // tail survivors fill the holes in rank order
+    const uint32_t sany = s.smo | s.smn;
+    bool smoved = false;  // a moved entry belongs to a sparse group (S(u) changes)
     for (uint32_t q = s.dn + lane; q < s.d1; q += 64) {
         if (q < s.d) {
             const uint32_t dest = xv_rho(xv, q, s.dn, nholes);
-            if (dest != NF) { enew[dest] = eold[q]; qnew[dest] = qold[q]; }
+            if (dest != NF) {
+                const uint64_t e = eold[q];
+                enew[dest] = e; qnew[dest] = qold[q];
+                smoved |= (member_word((uint32_t)(e >> 32), fb) & sany) != 0u;
+            }
         } else {
             const uint32_t a = q - s.d, dest = D[a];
             if (dest != NF) {
@@ -948,8 +990,10 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     uint32_t newinfo = 0, newlcap = s.lcap;
     const bool kl = lane < 32 && kept_listed(s);
     uint32_t km = (uint32_t)(__ballot(kl) & 0xFFFFFFFFull);
-    // per-lane (k) new block for kept lists that outgrow their capacity, or fresh lists
-    const uint64_t lneed = lane < 32 ? lane_list_need(s) : 0ull;
+    // per-lane (k) new block for kept lists that move (the list or its index outgrows the
+    // block), or fresh lists; lane 32: a new S(u) block
+    const uint64_t lneed = lane <= 32 ? lane_list_need(s) : 0ull;
+    const uint32_t nlc = lane < 32 && type_listed(s.tnew) ? new_lcap(s) : 0u;
     uint64_t lx = lneed;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -965,7 +1009,9 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         const uint32_t ck = __shfl(s.c, k, 64), cnk = __shfl(s.cn, k, 64), appk = __shfl(s.app, k, 64);
         const uint32_t lcapk = __shfl(s.lcap, k, 64);
         const uint64_t oblk = (uint64_t)__shfl(s.info, k, 64) * LIST_UNIT_WORDS;
-        const uint64_t nblk = cnk > lcapk ? __shfl(my_block, k, 64) : oblk;
+        const uint64_t nblk = __shfl(lneed, k, 64) ? __shfl(my_block, k, 64) : oblk;
+        // a regular group's inverted index follows its list in the block: entry i = position of i
+        const uint32_t iofs = ((s.smn >> k) & 1u) ? 0u : __shfl(nlc, k, 64);
         const uint32_t lenv = ck + appk;
         const uint32_t* Lold = pool + oblk;
         uint32_t* Lnew = pool + nblk;
@@ -1033,7 +1079,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                     bi.cbase = cb; bi.u = s.u; bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes;
                     bi.keep = keep; bi.reloc = nblk != oblk ? 1u : 0u; bi.sur = (uint32_t)soff;
                     bi.hole = (uint32_t)(soff + nsur); bi.ocap = 0; bi.ncap = 0; bi.a = oblk; bi.b = nblk;
-                    bi.aold = 0; bi.nh = nha; bi.pad = 0; bi.hcnt = 0;
+                    bi.aold = 0; bi.nh = nha; bi.iofs = iofs; bi.hcnt = 0;
                 }
                 nh = nha;
             }
@@ -1048,7 +1094,10 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                 const uint64_t hb = __ballot(hole);
                 if (v) {
                     const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : r;
-                    if (val != e || nblk != oblk) Lnew[p] = val;
+                    if (val != e || nblk != oblk) {
+                        Lnew[p] = val;
+                        if (iofs) Lnew[iofs + val] = p;
+                    }
                 }
                 nh += __popcll(hb);
             }
@@ -1065,7 +1114,11 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                 const uint32_t r = inpre ? D[a] : 0u;
                 const bool hole = inpre && r == NF;
                 const uint64_t hb = __ballot(hole);
-                if (inpre) Lnew[p] = hole ? S[nh + __popcll(hb & lanemask_lt())] : r;
+                if (inpre) {
+                    const uint32_t val = hole ? S[nh + __popcll(hb & lanemask_lt())] : r;
+                    Lnew[p] = val;
+                    if (iofs) Lnew[iofs + val] = p;
+                }
                 nh += __popcll(hb);
                 r2 += __popcll(b);
             }
@@ -1073,14 +1126,17 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         __threadfence_block();
         if (lane == (uint32_t)k) {
             newinfo = (uint32_t)(nblk / LIST_UNIT_WORDS);
-            if (nblk != oblk) { newlcap = list_cap_for(cnk); freed += lcapk; }
+            if (nblk != oblk) { newlcap = nlc; freed += old_block_words(s); }
         }
     }
 
     // ---- groups that become listed or switch between sparse and regular: fresh lists
     const bool fresh = lane < 32 && type_listed(s.tnew) && !kept_listed(s);
-    if (fresh) { newinfo = (uint32_t)(my_block / LIST_UNIT_WORDS); newlcap = list_cap_for(s.cn); }
-    if (lane < 32 && type_listed(s.told) && !kept_listed(s)) freed += s.lcap;
+    if (fresh) { newinfo = (uint32_t)(my_block / LIST_UNIT_WORDS); newlcap = nlc; }
+    if (lane < 32 && type_listed(s.told) && !kept_listed(s)) freed += old_block_words(s);
+    // S(u): a new block (its old one is freed), or none when no group is sparse any more
+    const uint64_t nsblk = __shfl(lneed, 32, 64) ? __shfl(my_block, 32, 64) : (uint64_t)s.sblk * LIST_UNIT_WORDS;
+    if (lane == 32 && s.scap && s.scapn != s.scap) freed += s.scap;
     const uint32_t fm = (uint32_t)(__ballot(fresh) & 0xFFFFFFFFull);
     // one-element groups: the surviving member
     const bool one = lane < 32 && s.tnew == GT_ONE;
@@ -1113,13 +1169,16 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
             mm &= mm - 1;
             uint32_t it, cb, cs;
             const uint64_t blk = (uint64_t)__shfl(newinfo, k, 64) * LIST_UNIT_WORDS;
+            // a fresh regular list's inverted index follows the list (read in every lane)
+            const uint32_t iofs = ((fm >> k) & 1u) && ((s.smn >> k) & 1u) == 0u ? __shfl(nlc, k, 64) : 0u;
             if (big_reserve(bc, uc, s.dn, it, cb, cs)) {
                 if (lane == 0) {
                     BigItem& bi = bc.items[it];
                     bi.kind = ((fm >> k) & 1u) ? BK_FRESH : BK_ONE; bi.k = (uint32_t)k; bi.n = s.dn; bi.csize = cs;
                     bi.cbase = cb; bi.u = s.u; bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes;
                     bi.keep = keep; bi.reloc = reloc ? 1u : 0u; bi.sur = 0; bi.hole = 0; bi.ocap = 0; bi.ncap = 0;
-                    bi.a = nadj; bi.b = blk; bi.aold = s.adj; bi.nh = 0; bi.pad = 0; bi.hcnt = 0;
+                    bi.a = nadj; bi.b = blk; bi.aold = s.adj; bi.nh = 0; bi.hcnt = 0;
+                    bi.iofs = iofs;
                 }
                 fm_seq &= ~(1u << k);
                 ns_seq &= ~(1u << k);
@@ -1143,7 +1202,12 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                 if ((fm_seq >> k) & 1u) {
                     const uint64_t blk = (uint64_t)__shfl(newinfo, k, 64) * LIST_UNIT_WORDS;
                     const uint32_t f = __shfl(fill, k, 64);
-                    if (bit) pool[blk + f + __popcll(b & lanemask_lt())] = i;
+                    const uint32_t iofs = ((s.smn >> k) & 1u) ? 0u : __shfl(nlc, k, 64);
+                    if (bit) {
+                        const uint32_t pos = f + __popcll(b & lanemask_lt());
+                        pool[blk + pos] = i;
+                        if (iofs) pool[blk + iofs + i] = pos;  // a regular group's inverted index
+                    }
                     if (lane == (uint32_t)k) fill += __popcll(b);
                 } else if (b) {
                     const uint32_t first = i0 + (__ffsll((long long)b) - 1);
@@ -1188,7 +1252,19 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         h[H_ADJHI] = (uint32_t)(nadj >> 32);
         h[H_ACAP] = ncap;
         h[H_NSEQ] = s.nseq + s.ni;
+        h[H_SCAP] = s.scapn;
+        h[H_SBLK] = (uint32_t)(nsblk / LIST_UNIT_WORDS);
+        if (!s.smn) h[H_SLEN] = 0;
     }
+    // S(u) and the sparse groups' indexes over it are rebuilt after the mutation
+    // (k_srebuild) when the vertex has a sparse group and S(u) or a sparse list may
+    // have changed: the sparse mask or the S(u) block changed, a sparse list moved or
+    // is fresh, or an inserted, deleted or moved entry belongs to a sparse group
+    const bool touched_sparse = lane < 32 && ((sany >> lane) & 1u) && (s.app | s.del) != 0u;
+    const bool sparse_block = lane < 32 && s.tnew == GT_SPARSE && lneed != 0;
+    const bool dirty = s.smn != 0u && (s.smn != s.smo || s.scapn != s.scap ||
+                                       __ballot(touched_sparse || sparse_block || smoved) != 0ull);
+    if (lane == 0) A.sdirty[t] = dirty ? 1u : 0u;
     return freed;
 }
 
@@ -1339,11 +1415,17 @@ __global__ void __launch_bounds__(256) k_big_apply(const unsigned long long* __r
                 base += wsum[j][0] + wsum[j][1] + wsum[j][2] + wsum[j][3];
                 const bool pr = (b[j] >> lane) & 1ull;
                 if (bi.kind == BK_FRESH) {
-                    if (pr) L[rk] = p;
+                    if (pr) {
+                        L[rk] = p;
+                        if (bi.iofs) L[bi.iofs + p] = rk;
+                    }
                 } else if (p < p1) {
                     const uint32_t e = (uint32_t)w0[j];
                     const uint32_t val = pr ? S[rk] : r[j];
-                    if (val != e || bi.reloc) L[p] = val;
+                    if (val != e || bi.reloc) {
+                        L[p] = val;
+                        if (bi.iofs) L[bi.iofs + val] = p;
+                    }
                 }
             }
             __syncthreads();  // wsum is rewritten by the next tile
@@ -1449,7 +1531,10 @@ __global__ void __launch_bounds__(256) k_big_pass(const unsigned long long* __re
                         const uint64_t slot = base + __popcll(hb & lanemask_lt());
                         if (hole && slot < nh) H[slot] = p;
                     }
-                    if (p < p1 && !hole && (r != e[j] || moved)) Lnew[p] = r;
+                    if (p < p1 && !hole && (r != e[j] || moved)) {
+                        Lnew[p] = r;
+                        if (bi.iofs) Lnew[bi.iofs + r] = p;
+                    }
                 }
             }
         }
@@ -1488,7 +1573,10 @@ __global__ void __launch_bounds__(256) k_big_holes(const unsigned long long* __r
                 __syncthreads();
             }
         }
-        for (uint32_t i = threadIdx.x; i < nh; i += 256) L[hs[i]] = S[i];
+        for (uint32_t i = threadIdx.x; i < nh; i += 256) {
+            L[hs[i]] = S[i];
+            if (bi.iofs) L[bi.iofs + S[i]] = hs[i];
+        }
     }
 }
 
@@ -1537,6 +1625,7 @@ struct UpdPlan {
     uint64_t *keys, *sk, *hx, *fsz, *foff, *ckey, *cks, *xk, *xks, *needw, *aoff, *xoff;
     uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold, *wv, *idest, *blist;
     uint32_t *vacap, *vnseq;  // header fields of the touched vertices before the batch (k_flat_size)
+    uint32_t* sdirty;         // per touched vertex: S(u) to rebuild after the mutation
     uint64_t* vadj;
     unsigned long long* parts;
     BigItem* big_items;
@@ -1589,7 +1678,7 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     const uint64_t R = rmax, C = cmax;
     const size_t tmpb = std::max(std::max(sort_temp_bytes(R, true), sort_temp_bytes(C, true)),
                                  scan_temp_bytes(R + 1));
-    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 11 + al(C * 8) * 2 + al(R * 4) * 18 +
+    const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 11 + al(C * 8) * 2 + al(R * 4) * 19 +
                          al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + al(BIG_IMAX * sizeof(BigItem)) +
                          2 * al(BIG_CMAX * 4) + al(big_smax(R) * 4) + tmpb + 4096;
     UpdPlan* p = new UpdPlan();
@@ -1619,6 +1708,7 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->blist = (uint32_t*)take(R * 4);
     p->vacap = (uint32_t*)take(R * 4);
     p->vnseq = (uint32_t*)take(R * 4);
+    p->sdirty = (uint32_t*)take(R * 4);
     p->vadj = (uint64_t*)take(R * 8);
     p->sur = (uint32_t*)take(R * 8);
     p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
@@ -1697,7 +1787,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, (uint32_t)big_smax(R), g->rule.fbits};
     const uint32_t split = g->update_split;
     const MutArgs ma{p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->wv,
-                     p->idest, p->aoff, p->sur, g->rule};
+                     p->idest, p->aoff, p->sur, p->sdirty, g->rule};
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R)), dim3(TB), 0, st, p->sdirty, R, 0u);
     hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid_m), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
                        (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
     hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid_m,
@@ -1720,6 +1811,8 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                            (const uint32_t*)g->pool, g->hdr);
     }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
+    // S(u) and the sparse groups' indexes of the vertices whose reduced list may have changed
+    sparse_rebuild(g, p->tv, uc + UC_T, R, p->sdirty, st);
     // alias-table mode: the touched vertices' inter-group tables (a rejected batch rewrites them unchanged)
     alias_rows(g, p->tv, uc + UC_T, R, st);
 }

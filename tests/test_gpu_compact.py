@@ -165,6 +165,7 @@ def test_library_sized_pool_grows():
     mem = gg.memory()
     assert mem["pool_bytes"] > pool0 and mem["pool_used_bytes"] <= mem["pool_bytes"]
     assert np.array_equal(gg.export(), og.dump())
+    assert np.array_equal(gg.export_index(), og.index_dump())
     starts = rng.integers(0, n, 500)
     paths, steps = gg.walk(starts, 30, 45)
     opaths, osteps = og.deepwalk(starts, 30, 45)

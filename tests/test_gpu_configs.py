@@ -44,6 +44,7 @@ def test_deepwalk_workload_batches():
     og = O.Graph(n, src.numpy(), dst.numpy(), w.numpy())
     gg = B().Graph(n, src, dst, w)
     assert np.array_equal(gg.export(), og.dump())
+    assert np.array_equal(gg.export_index(), og.index_dump())
     starts = np.arange(n)
     mirror = synth.EdgeMirror(src, dst)
     for b in range(3):
@@ -62,6 +63,7 @@ def test_deepwalk_workload_batches():
         assert (s1["inserted"], s1["deleted"], s1["not_found"]) == (s2["inserted"], s2["deleted"], s2["not_found"])
         assert np.array_equal(s1["transitions"], s2["transitions"])
         assert np.array_equal(gg.export(), og.dump()), b
+        assert np.array_equal(gg.export_index(), og.index_dump()), b
 
 
 @pytest.mark.parametrize("adaptive", [True, False])
@@ -75,6 +77,7 @@ def test_skewed_update_workload(adaptive):
     og = O.Graph(n, src.numpy(), dst.numpy(), w.numpy(), adaptive=adaptive)
     gg = B().Graph(n, src, dst, w, adaptive=adaptive)
     assert np.array_equal(gg.export(), og.dump())
+    assert np.array_equal(gg.export_index(), og.index_dump())
     mirror = synth.EdgeMirror(src, dst)
     for b, size in enumerate([100, 10_000, 100, 100_000]):
         bseed = 4400 + b
@@ -95,6 +98,7 @@ def test_skewed_update_workload(adaptive):
         for h in hubs.tolist()[:4]:
             assert np.array_equal(gg.export(h, h + 1), og.dump(h, h + 1)), (b, h)
     assert np.array_equal(gg.export(), og.dump())
+    assert np.array_equal(gg.export_index(), og.index_dump())
     thr = int(0.15 * 2**32)
     srcs = hubs.numpy()
     off, vtx, cnt, st = gg.ppr(srcs, 200, thr, 200, seed=11)

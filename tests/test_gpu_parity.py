@@ -36,7 +36,18 @@ def both(n, src, dst, w, adaptive=True):
     return og, gg
 
 
+def assert_same_index(og, gg, where=""):
+    """The group indexes (inverted index of regular groups, S(u) and the sparse groups' indexes over
+    it) equal the oracle's, word for word."""
+    a, b = gg.export_index(), og.index_dump()
+    if not np.array_equal(a, b):
+        n = min(len(a), len(b))
+        first = int(np.argmax(a[:n] != b[:n])) if n and np.any(a[:n] != b[:n]) else n
+        raise AssertionError("index dumps differ (%s) at word %d of %d/%d" % (where, first, len(a), len(b)))
+
+
 def assert_same_structure(og, gg, where=""):
+    assert_same_index(og, gg, where)
     a, b = gg.export(), og.dump()
     if not np.array_equal(a, b):
         va, vb = O.parse_dump(a, og.n), O.parse_dump(b, og.n)

@@ -83,6 +83,8 @@ def test_serving_results_equal_sequential(inflight, budget, batch):
             epoch += 1
     assert np.array_equal(g1.export(), og.dump())
     assert np.array_equal(g2.export(), og.dump())
+    assert np.array_equal(g1.export_index(), og.index_dump())
+    assert np.array_equal(g2.export_index(), og.index_dump())
 
 
 def test_serving_concurrent_queries_overlap_and_finish():

@@ -126,6 +126,7 @@ def test_stream_equals_batches_of_one_on_gpu():
             e = torch.tensor([], dtype=torch.int64)
             gb.update(e, e, e, torch.tensor([a]), torch.tensor([c]))
     assert np.array_equal(ga.export(), gb.export())
+    assert np.array_equal(ga.export_index(), gb.export_index())
 
 
 def test_stream_rejects_bad_records():
@@ -184,6 +185,7 @@ def test_stream_grows_a_library_sized_pool():
         assert s1[key] == s2[key], key
     assert s1["inserted"] + s1["deleted"] + s1["not_found"] == k
     assert np.array_equal(g1.export(), g2.export())
+    assert np.array_equal(g1.export_index(), g2.export_index())
 
 
 def test_stream_grows_with_many_more_sources_than_resident_waves():
@@ -216,5 +218,6 @@ def test_stream_grows_with_many_more_sources_than_resident_waves():
     assert s1["inserted"] + s1["deleted"] + s1["not_found"] == k
     assert s1["deleted"] > 0
     assert np.array_equal(g1.export(), g2.export())
+    assert np.array_equal(g1.export_index(), g2.export_index())
     g1.close()
     g2.close()
