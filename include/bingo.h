@@ -229,6 +229,32 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
                uint64_t walk_id_base, uint32_t length, uint64_t seed,
                uint32_t* d_paths, uint64_t* d_steps_taken, uint32_t mode, void* stream);
 
+/*
+ * bingo_walk_noalloc -- bingo_walk in the persistent form, for callers that
+ * cannot allocate: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid allocation.  It makes no allocation of any kind (no
+ * device or host memory, no events, no library routine that allocates), and
+ * launches only kernels (no memset or copy nodes).
+ *   Arguments and results are those of bingo_walk(g, n_walks, d_starts,
+ *   walk_id_base, length, seed, d_paths, d_steps_taken, BINGO_WALK_PERSISTENT,
+ *   stream): the same paths and transition count, bit for bit.
+ *   Scratch: the kernels' work-queue head and transition counter live in a
+ *   fixed 256-byte device array of the library, one per GPU, held until the
+ *   process ends; its size does not depend on n_walks or length, so no input
+ *   size is refused for it.  Its device address is looked up once per GPU, at
+ *   the first call made with that GPU current.  Each call clears it on the
+ *   stream before use.
+ *   Concurrency: every call on one GPU shares that array, so calls that
+ *   overlap on one GPU (on different streams or threads) race and give wrong
+ *   paths and counts; serialize them (one stream, or events).
+ * BINGO_E_INVALID for a null handle, a null d_starts or d_paths with
+ * n_walks > 0, or a length of 0xFFFFFFFF; BINGO_E_HIP if the device address
+ * lookup or a launch fails.  Start ids >= n as in bingo_walk.
+ */
+int bingo_walk_noalloc(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
+                       uint64_t walk_id_base, uint32_t length, uint64_t seed,
+                       uint32_t* d_paths, uint64_t* d_steps_taken, void* stream);
+
 /* One DeepWalk query of a batch: the arguments of one bingo_walk call. */
 typedef struct {
     uint64_t n_walks;

@@ -57,7 +57,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
-           "bingo_compact", "bingo_walk_batch", "bingo_export_index_range"]
+           "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range"]
 
 
 class _ServerConfig(C.Structure):
@@ -104,6 +104,7 @@ def load():
         L.bingo_update_batch.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(_UpdateStats)]
         L.bingo_update_stream.argtypes = [vp, u64, vp, vp, vp, vp, vp, C.POINTER(_UpdateStats)]
         L.bingo_walk.argtypes = [vp, u64, vp, u64, u32, u64, vp, vp, u32, vp]
+        L.bingo_walk_noalloc.argtypes = [vp, u64, vp, u64, u32, u64, vp, vp, vp]
         L.bingo_node2vec.argtypes = [vp, u64, vp, u64, u32, C.c_double, C.c_double, u64, vp, vp, vp]
         L.bingo_ppr.argtypes = [vp, u32, vp, u32, u32, u32, u64, u64, u32, C.POINTER(u64), C.POINTER(u64), vp]
         L.bingo_ppr_fetch.argtypes = [vp, vp, vp, vp, u64, vp]
@@ -230,6 +231,14 @@ class Graph:
         rc = load().bingo_walk(self.h, nw, _ptr(st), base, length, seed, _ptr(paths), _ptr(steps), mode,
                                _stream(stream))
         _check(rc, "bingo_walk")
+        return paths, steps
+
+    def walk_noalloc(self, starts, length, seed, paths, steps, base=0, stream=None):
+        """bingo_walk_noalloc into caller-owned paths (n_walks, length + 1) int32 and steps (1,) int64."""
+        st = as_u32(starts, self.device)
+        rc = load().bingo_walk_noalloc(self.h, st.numel(), _ptr(st), base, length, seed, _ptr(paths), _ptr(steps),
+                                       _stream(stream))
+        _check(rc, "bingo_walk_noalloc")
         return paths, steps
 
     def walk_batch(self, queries, stream=None):

@@ -12,6 +12,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 
 namespace {
 
@@ -1495,4 +1496,69 @@ int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, 
     if (h_entries) *h_entries = U;
     if (h_steps) *h_steps = steps;
     return BINGO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free DeepWalk entry point.  bingo_walk takes its per-call counters
+// (the persistent kernel's work-queue head and its transition count) from the
+// handle's slot ring, whose events it creates on first use.  This variant keeps
+// them in a fixed device array instead and creates nothing: no device memory,
+// no events.  The array is one per device, holds the counters of one call at a
+// time, and is cleared by a fill kernel at the start of every call (no memset,
+// so the call can be captured into a graph).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t NOALLOC_WORDS = 32;  // 256 bytes per device: [0] queue head, [1] transitions
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_WORDS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+unsigned long long* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+__global__ void k_noalloc_begin(unsigned long long* __restrict__ s) {
+    if (threadIdx.x < NOALLOC_WORDS) s[threadIdx.x] = 0ull;
+}
+__global__ void k_noalloc_end(const unsigned long long* __restrict__ s, unsigned long long* __restrict__ steps) {
+    *steps = s[1];
+}
+
+// Device address of this device's copy of the array, looked up once per device
+// with that device current (the array's host-side name is not a device address).
+int noalloc_scratch(unsigned long long** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return BINGO_E_INVALID;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        noalloc_ptr[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = noalloc_ptr[dev];
+    return BINGO_OK;
+}
+
+}  // namespace
+
+extern "C" int bingo_walk_noalloc(const bingo_graph* gc, uint64_t n_walks, const uint32_t* d_starts,
+                                  uint64_t walk_id_base, uint32_t length, uint64_t seed, uint32_t* d_paths,
+                                  uint64_t* d_steps_taken, void* stream) {
+    if (!gc || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    bingo_graph* g = const_cast<bingo_graph*>(gc);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long* ctl = nullptr;
+    if (int rc = noalloc_scratch(&ctl)) return rc;
+    hipLaunchKernelGGL(k_noalloc_begin, dim3(1), dim3(NOALLOC_WORDS), 0, st, ctl);
+    if (n_walks) {
+        switch (g->dense_spec) {
+#define DWN(S) (walk_mode(g) == 1 ? deepwalk_kernels<S, 1> : walk_mode(g) == 2 ? deepwalk_kernels<S, 2> : deepwalk_kernels<S, 0>)
+            case 1: DWN(1)(g, n_walks, d_starts, walk_id_base, length, seed, d_paths, BINGO_WALK_PERSISTENT, ctl, st); break;
+            case 4: DWN(4)(g, n_walks, d_starts, walk_id_base, length, seed, d_paths, BINGO_WALK_PERSISTENT, ctl, st); break;
+            default: DWN(2)(g, n_walks, d_starts, walk_id_base, length, seed, d_paths, BINGO_WALK_PERSISTENT, ctl, st); break;
+#undef DWN
+        }
+    }
+    if (d_steps_taken)
+        hipLaunchKernelGGL(k_noalloc_end, dim3(1), dim3(1), 0, st, ctl, (unsigned long long*)d_steps_taken);
+    return hipGetLastError() == hipSuccess ? BINGO_OK : BINGO_E_HIP;
 }
