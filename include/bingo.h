@@ -83,6 +83,18 @@ typedef struct {
                                integer Walker/Vose table (512 B per vertex beside the header,
                                rebuilt for every vertex an update touches).  Integer biases only
                                (frac_bits must be 0). */
+    uint32_t radix_base;    /* 0 or 2: the method's power-of-two groups.  4: radix base 4
+                               (Supplement S.2): a weight is read as base-4 digits d_k (k = 0..15) and
+                               group k splits into subgroups s = 3k + v - 1 of the edges whose digit k
+                               is v = 1..3, each member carrying v 4^k; a step takes the first
+                               subgroup in ascending s with r < sum of c_s v 4^k (r = below64(W)),
+                               then a member by the subgroup's type from (c_s, d) under the rule of
+                               Sec. 5.1 (dense: i = below32(d) until digit k of w_i is v).  A static
+                               structure: bingo_walk (persistent form), bingo_export /
+                               bingo_export_range (base-4 dump layout, see bingo_export),
+                               bingo_memory, bingo_status, tuning and bingo_destroy; every other call
+                               returns BINGO_E_INVALID.  Integer biases only, no alias table. */
+    uint32_t reserved;      /* 0 */
 } bingo_config;
 
 typedef struct {
@@ -344,6 +356,10 @@ int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uin
  * by the member index (one-element group) or the list in order (sparse and
  * regular groups).  With h_buf == NULL only *h_len (words) is set.
  * Synchronizes.  Returns BINGO_E_CAPACITY if cap_words is too small.
+ * A radix-base-4 graph dumps, per vertex: d, the mask of non-empty subgroups
+ * (subgroups 0..31, then 32..47: two words), (dst, weight) per neighbor index,
+ * then for each non-empty subgroup s ascending: s, type, count, followed by the
+ * member index or the list.
  */
 int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* h_len, void* stream);
 

@@ -33,7 +33,7 @@ class BingoError(RuntimeError):
 class _Config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("adaptive", C.c_uint32), ("alpha_pct", C.c_uint32),
                 ("beta_pct", C.c_uint32), ("pool_bytes", C.c_uint64), ("frac_bits", C.c_uint32),
-                ("alias_table", C.c_uint32)]
+                ("alias_table", C.c_uint32), ("radix_base", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _UpdateStats(C.Structure):
@@ -197,11 +197,12 @@ class Graph:
     """A dynamic graph with its radix-group sampling space resident in device memory."""
 
     def __init__(self, n, src, dst, w, adaptive=True, alpha=40, beta=10, pool_bytes=0, device="cuda", stream=None,
-                 frac_bits=0, alias_table=False):
+                 frac_bits=0, alias_table=False, radix_base=2):
         L = load()
         self.device = torch.device(device)
         s, d, ww = as_u32(src, self.device), as_u32(dst, self.device), as_u32(w, self.device)
-        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes, frac_bits, int(bool(alias_table)))
+        cfg = _Config(C.sizeof(_Config), int(bool(adaptive)), alpha, beta, pool_bytes, frac_bits, int(bool(alias_table)),
+                      radix_base, 0)
         h = C.c_void_p()
         rc = L.bingo_build(C.byref(cfg), n, s.numel(), _ptr(s), _ptr(d), _ptr(ww), _stream(stream), C.byref(h))
         _check(rc, "bingo_build")
@@ -210,6 +211,7 @@ class Graph:
         self.adaptive = bool(adaptive)
         self.frac_bits = frac_bits
         self.alias_table = bool(alias_table)
+        self.radix_base = radix_base
 
     def close(self):
         if getattr(self, "h", None):

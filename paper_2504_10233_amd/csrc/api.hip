@@ -70,6 +70,9 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     if (m && (!d_src || !d_dst || !d_w)) return BINGO_E_INVALID;
     if (cfg->adaptive > 1 || cfg->alpha_pct > 100 || cfg->beta_pct > 100) return BINGO_E_INVALID;
     if (cfg->frac_bits > 16 || cfg->alias_table > 1 || (cfg->alias_table && cfg->frac_bits)) return BINGO_E_INVALID;
+    const uint32_t radix = cfg->radix_base ? cfg->radix_base : 2u;
+    if ((radix != 2 && radix != 4) || cfg->reserved) return BINGO_E_INVALID;
+    if (radix == 4 && (cfg->frac_bits || cfg->alias_table)) return BINGO_E_INVALID;
     hipStream_t st = (hipStream_t)stream;
     bingo_graph* g = new (std::nothrow) bingo_graph();
     if (!g) return BINGO_E_OOM;
@@ -82,13 +85,15 @@ int bingo_build(const bingo_config* cfg, uint32_t n, uint64_t m, const uint32_t*
     g->alias_mode = cfg->alias_table;
     g->pool_words = cfg->pool_bytes / 4;
     g->pool_auto = cfg->pool_bytes == 0;
+    g->radix_base = radix;
+    const size_t hdr_words = radix == 4 ? (size_t)H4_WORDS : (size_t)HDR_WORDS;
     g->hdr = nullptr; g->pool = nullptr; g->d_ctl = nullptr; g->d_err = nullptr; g->alias = nullptr;
-    if (hipMalloc(&g->hdr, (size_t)n * HDR_WORDS * 4) != hipSuccess ||
+    if (hipMalloc(&g->hdr, (size_t)n * hdr_words * 4) != hipSuccess ||
         hipMalloc(&g->d_ctl, CTL_WORDS * 8) != hipSuccess || hipMalloc(&g->d_err, 4) != hipSuccess) {
         release(g);
         return BINGO_E_OOM;
     }
-    if (hipMemsetAsync(g->hdr, 0, (size_t)n * HDR_WORDS * 4, st) != hipSuccess ||
+    if (hipMemsetAsync(g->hdr, 0, (size_t)n * hdr_words * 4, st) != hipSuccess ||
         hipMemsetAsync(g->d_ctl, 0, CTL_WORDS * 8, st) != hipSuccess) {
         release(g);
         return BINGO_E_HIP;
@@ -113,7 +118,7 @@ int bingo_quantize_biases(uint64_t m, const float* d_bias, double lambda, uint32
 int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src, const uint32_t* d_ins_dst,
                        const uint32_t* d_ins_w, uint64_t n_del, const uint32_t* d_del_src, const uint32_t* d_del_dst,
                        void* stream, bingo_update_stats* h_stats) {
-    if (!g) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2) return BINGO_E_INVALID;
     if (n_ins && (!d_ins_src || !d_ins_dst || !d_ins_w)) return BINGO_E_INVALID;
     if (n_del && (!d_del_src || !d_del_dst)) return BINGO_E_INVALID;
     return update_batch(g, n_ins, d_ins_src, d_ins_dst, d_ins_w, n_del, d_del_src, d_del_dst, h_stats,
@@ -122,7 +127,7 @@ int bingo_update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* d_ins_src
 
 int bingo_update_stream(bingo_graph* g, uint64_t n, const uint32_t* d_op, const uint32_t* d_src,
                         const uint32_t* d_dst, const uint32_t* d_w, void* stream, bingo_update_stats* h_stats) {
-    if (!g || (n && (!d_op || !d_src || !d_dst || !d_w))) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2 || (n && (!d_op || !d_src || !d_dst || !d_w))) return BINGO_E_INVALID;
     return update_stream(g, n, d_op, d_src, d_dst, d_w, h_stats, (hipStream_t)stream);
 }
 
@@ -131,12 +136,17 @@ int bingo_walk(const bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts,
                void* stream) {
     if (!g || (n_walks && (!d_starts || !d_paths))) return BINGO_E_INVALID;
     if (mode > BINGO_WALK_PER_STEP || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    if (g->radix_base == 4) {
+        if (mode != BINGO_WALK_PERSISTENT) return BINGO_E_INVALID;
+        return launch_walk4(const_cast<bingo_graph*>(g), n_walks, d_starts, walk_id_base, length, seed, d_paths,
+                            d_steps_taken, (hipStream_t)stream);
+    }
     return launch_walk(const_cast<bingo_graph*>(g), n_walks, d_starts, walk_id_base, length, seed, d_paths,
                        d_steps_taken, mode, (hipStream_t)stream);
 }
 
 int bingo_walk_batch(const bingo_graph* g, uint32_t n_queries, const bingo_walk_query* h_queries, void* stream) {
-    if (!g || n_queries > BINGO_WALK_BATCH_MAX || (n_queries && !h_queries)) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2 || n_queries > BINGO_WALK_BATCH_MAX || (n_queries && !h_queries)) return BINGO_E_INVALID;
     for (uint32_t i = 0; i < n_queries; ++i) {
         const bingo_walk_query& q = h_queries[i];
         if ((q.n_walks && (!q.d_starts || !q.d_paths)) || q.length == 0xFFFFFFFFu) return BINGO_E_INVALID;
@@ -147,7 +157,8 @@ int bingo_walk_batch(const bingo_graph* g, uint32_t n_queries, const bingo_walk_
 int bingo_node2vec(bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, uint64_t walk_id_base,
                    uint32_t length, double p, double q, uint64_t seed, uint32_t* d_paths, uint64_t* d_counts,
                    void* stream) {
-    if (!g || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2 || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu)
+        return BINGO_E_INVALID;
     return run_node2vec(g, n_walks, d_starts, walk_id_base, length, p, q, seed, d_paths, d_counts,
                         (hipStream_t)stream);
 }
@@ -155,7 +166,8 @@ int bingo_node2vec(bingo_graph* g, uint64_t n_walks, const uint32_t* d_starts, u
 int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources, uint32_t walks_per_source,
               uint32_t term_threshold, uint32_t max_len, uint64_t seed, uint64_t walk_id_base, uint32_t mode,
               uint64_t* h_total_entries, uint64_t* h_total_steps, void* stream) {
-    if (!g || !h_total_entries || n_sources == 0 || walks_per_source == 0 || !d_sources) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2 || !h_total_entries || n_sources == 0 || walks_per_source == 0 || !d_sources)
+        return BINGO_E_INVALID;
     if (mode > BINGO_WALK_PER_STEP) return BINGO_E_INVALID;
     if ((uint64_t)n_sources * walks_per_source >= (1ull << 40)) return BINGO_E_INVALID;
     return run_ppr(g, n_sources, d_sources, walks_per_source, term_threshold, max_len, seed, walk_id_base, mode,
@@ -177,29 +189,32 @@ int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uin
 
 int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* h_len, void* stream) {
     if (!g || !h_len) return BINGO_E_INVALID;
+    if (g->radix_base == 4) return export_graph4(g, 0, g->n, h_buf, cap_words, h_len, (hipStream_t)stream);
     return export_graph(g, 0, g->n, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
 int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                        uint64_t* h_len, void* stream) {
     if (!g || !h_len) return BINGO_E_INVALID;
+    if (g->radix_base == 4) return export_graph4(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
     return export_graph(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
 int bingo_export_index_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                              uint64_t* h_len, void* stream) {
-    if (!g || !h_len) return BINGO_E_INVALID;
+    if (!g || !h_len || g->radix_base != 2) return BINGO_E_INVALID;
     return export_index(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
 int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream) {
-    if (!g) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2) return BINGO_E_INVALID;
     if (pool_bytes > (1ull << 37)) return BINGO_E_INVALID;
     return compact_pool(g, pool_bytes / 4, (hipStream_t)stream);
 }
 
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
     if (!g || !out) return BINGO_E_INVALID;
+    if (g->radix_base == 4) return memory_stats4(g, out, (hipStream_t)stream);
     return memory_stats(g, out, (hipStream_t)stream);
 }
 

@@ -210,6 +210,121 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Radix base 4 (Supplement S.2).  Pass 1: per subgroup s = 3k + v - 1 (lane s)
+// the count c_s of edges whose base-4 digit k is v (one ballot per subgroup per
+// 64 edges), the one-element member (the first such edge), types by the rule of
+// Sec. 5.1, W and the block sizes.  Pass 2: adjacency words, one-element
+// destinations, and each listed subgroup's ascending list.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WB) k_header4(uint32_t n, const uint32_t* __restrict__ start,
+                                                const uint32_t* __restrict__ cw, uint32_t* __restrict__ hdr,
+                                                uint64_t* __restrict__ adjw, uint64_t* __restrict__ listw,
+                                                GroupRule rule) {
+    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t b = start[u], d = start[u + 1] - b;
+    uint32_t cnt = 0, first = 0xFFFFFFFFu;  // lane s < 48 owns subgroup s
+    uint64_t wraw = 0;
+    for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        const uint32_t w = i < d ? cw[b + i] : 0u;
+        wraw += w;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t dg = i < d ? r4_digit(w, (uint32_t)k) : 0u;
+#pragma unroll
+            for (int v = 1; v <= 3; ++v) {
+                const uint64_t bal = __ballot(dg == (uint32_t)v);
+                if (lane == (uint32_t)(3 * k + v - 1) && bal) {
+                    cnt += __popcll(bal);
+                    if (first == 0xFFFFFFFFu) first = c0 + (uint32_t)(__ffsll((long long)bal) - 1);
+                }
+            }
+        }
+    }
+    const uint32_t t = lane < R4_SUB ? group_type(cnt, d, rule) : GT_EMPTY;
+    uint64_t wsum = wraw;
+    uint64_t lw = type_listed(t) ? (uint64_t)list_cap_for(cnt) : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        wsum += __shfl_xor(wsum, o);
+        lw += __shfl_xor(lw, o);
+    }
+    const uint64_t mask = __ballot(cnt > 0), onem = __ballot(t == GT_ONE);
+    uint32_t* h = hdr + (size_t)u * H4_WORDS;
+    if (lane < R4_SUB) {
+        h[H4_SLOT + lane] = cnt;
+        h[H4_INFO + lane] = t == GT_ONE ? first : 0u;
+    }
+    if (lane == 0) {
+        const uint32_t cap = adj_cap_for(d);
+        h[H4_DEG] = d;
+        h[H4_ACAP] = cap;
+        h[H4_WLO] = (uint32_t)wsum;
+        h[H4_WHI] = (uint32_t)(wsum >> 32);
+        h[H4_ONELO] = (uint32_t)onem;
+        h[H4_ONEHI] = (uint32_t)(onem >> 32);
+        h[H4_MASKLO] = (uint32_t)mask;
+        h[H4_MASKHI] = (uint32_t)(mask >> 32);
+        adjw[u] = cap ? r4_adj_words(cap) : 0ull;
+        listw[u] = lw;
+    }
+}
+
+__global__ void __launch_bounds__(WB) k_fill4(uint32_t n, const uint32_t* __restrict__ start,
+                                              const uint32_t* __restrict__ cdst, const uint32_t* __restrict__ cw,
+                                              const uint64_t* __restrict__ adj_off, const uint64_t* __restrict__ list_off,
+                                              uint64_t list_base, uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                              GroupRule rule) {
+    const uint32_t u = blockIdx.x * (WB / 64) + (threadIdx.x >> 6);
+    if (u >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t b = start[u], d = start[u + 1] - b;
+    uint32_t* h = hdr + (size_t)u * H4_WORDS;
+    const uint64_t ao = d ? adj_off[u] : 0ull;
+    if (lane == 0) { h[H4_ADJLO] = (uint32_t)ao; h[H4_ADJHI] = (uint32_t)(ao >> 32); }
+    uint64_t* edges = reinterpret_cast<uint64_t*>(pool + ao);
+    const uint32_t cnt = lane < R4_SUB ? h[H4_SLOT + lane] : 0u;
+    const uint32_t t = lane < R4_SUB ? group_type(cnt, d, rule) : GT_EMPTY;
+    const bool lst = type_listed(t);
+    const uint32_t lcap = lst ? list_cap_for(cnt) : 0u;
+    uint64_t x = lcap;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    const uint64_t my_block = list_base + list_off[u] + (x - lcap);
+    if (lst) h[H4_INFO + lane] = (uint32_t)(my_block / LIST_UNIT_WORDS);
+    if (lane < R4_SUB && t == GT_ONE) h[H4_SLOT + lane] = cdst[b + h[H4_INFO + lane]];
+    const uint32_t lg = lst ? (31 - __clz(lcap)) : 0u;
+    uint32_t packed = lg << (8 * (lane & 3));
+    packed |= __shfl_xor(packed, 1);
+    packed |= __shfl_xor(packed, 2);
+    if (lane < R4_SUB && (lane & 3) == 0) h[H4_LCAPLOG + (lane >> 2)] = packed;
+    const uint64_t lmask = __ballot(lst);
+    uint32_t fill = 0;
+    for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        uint32_t w = 0;
+        if (i < d) {
+            w = cw[b + i];
+            edges[i] = (uint64_t)cdst[b + i] | ((uint64_t)w << 32);
+        }
+        for (uint64_t mm = lmask; mm; mm &= mm - 1) {
+            const int sg = __ffsll((long long)mm) - 1;
+            const bool bit = i < d && r4_digit(w, (uint32_t)sg / 3) == (uint32_t)(sg % 3) + 1;
+            const uint64_t bal = __ballot(bit);
+            const uint64_t blk = __shfl(my_block, sg, 64);
+            const uint32_t f = __shfl(fill, sg, 64);
+            if (bit) pool[blk + f + __popcll(bal & lanemask_lt())] = i;
+            if (lane == (uint32_t)sg) fill += __popcll(bal);
+        }
+    }
+}
+
 inline uint32_t grid_for(uint64_t n, uint32_t block) {
     uint64_t g = (n + block - 1) / block;
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1u << 20);
@@ -482,7 +597,9 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
     }
     hipLaunchKernelGGL(k_row_start, dim3(((uint64_t)n + 1 + 255) / 256), dim3(256), 0, st, skeys, m, n, start);
     const uint32_t vgrid = (uint32_t)(((uint64_t)n + 3) / 4);
-    hipLaunchKernelGGL(k_header, dim3(vgrid), dim3(WB), 0, st, n, start, cw, g->hdr, adjw, listw, g->rule);
+    const bool r4 = g->radix_base == 4;
+    if (r4) hipLaunchKernelGGL(k_header4, dim3(vgrid), dim3(WB), 0, st, n, start, cw, g->hdr, adjw, listw, g->rule);
+    else hipLaunchKernelGGL(k_header, dim3(vgrid), dim3(WB), 0, st, n, start, cw, g->hdr, adjw, listw, g->rule);
     scan_u64(adjw, adj_off, n, tmp, totals, st);
     scan_u64(listw, list_off, n, tmp, totals + 1, st);
     unsigned long long tot[2];
@@ -499,8 +616,12 @@ int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t*
         return BINGO_E_OOM;
     }
     g->pool_words = pool_words;
-    hipLaunchKernelGGL(k_fill, dim3(vgrid), dim3(WB), 0, st, n, start, cdst, cw, adj_off, list_off, (uint64_t)tot[0],
-                       g->hdr, g->pool, g->rule);
+    if (r4)
+        hipLaunchKernelGGL(k_fill4, dim3(vgrid), dim3(WB), 0, st, n, start, cdst, cw, adj_off, list_off,
+                           (uint64_t)tot[0], g->hdr, g->pool, g->rule);
+    else
+        hipLaunchKernelGGL(k_fill, dim3(vgrid), dim3(WB), 0, st, n, start, cdst, cw, adj_off, list_off,
+                           (uint64_t)tot[0], g->hdr, g->pool, g->rule);
     if (g->alias_mode) {
         if (hipMalloc(&g->alias, (size_t)n * ALIAS_ENTRIES * sizeof(uint4)) != hipSuccess) {
             g->alias = nullptr;

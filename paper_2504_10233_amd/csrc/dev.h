@@ -41,6 +41,35 @@
 #define H_SCAP 83      // S(u) capacity in entries (0: the vertex has no sparse group)
 #define STOP_VERTEX 0xFFFFFFFFu
 
+// ---------------------------------------------------------------------------
+// Radix base 4 (Supplement S.2): a weight is read as base-4 digits d_k, k = 0..15;
+// subgroup s = 3k + v - 1 (v = 1..3) holds the edges whose digit k is v, each
+// carrying v 4^k, so its total is c_s v 4^k.  Static structure (build and walks).
+// Per-vertex header of 128 words (512 bytes):
+//   degree, adjacency capacity, W (u64), adjacency offset (u64), mask of
+//   one-element subgroups (u64), mask of non-empty subgroups (u64), slot s for
+//   s = 0..47 (c_s, or a one-element subgroup's destination), info s (member
+//   index, or list block offset in 32-byte units), log2 of the list capacities
+//   (one byte per subgroup).  Adjacency block: cap 64-bit words dst | w << 32.
+// ---------------------------------------------------------------------------
+#define R4_SUB 48
+#define H4_WORDS 128
+#define H4_DEG 0
+#define H4_ACAP 1
+#define H4_WLO 2
+#define H4_WHI 3
+#define H4_ADJLO 4
+#define H4_ADJHI 5
+#define H4_ONELO 6
+#define H4_ONEHI 7
+#define H4_MASKLO 8
+#define H4_MASKHI 9
+#define H4_SLOT 10
+#define H4_INFO 58
+#define H4_LCAPLOG 106  // 12 words
+__host__ __device__ inline uint32_t r4_digit(uint32_t w, uint32_t k) { return (w >> (2 * k)) & 3u; }
+__host__ __device__ inline uint64_t r4_adj_words(uint32_t cap) { return ((uint64_t)cap * 2 + 7) & ~7ull; }
+
 // c_k from slot k (one-element groups keep their member's destination there)
 __host__ __device__ inline uint32_t slot_count(uint32_t slot, uint32_t onemask, uint32_t k) {
     return ((onemask >> k) & 1u) ? 1u : slot;
@@ -287,6 +316,9 @@ struct bingo_graph {
     uint64_t* n2v_off = nullptr;
     uint64_t n2v_cap = 0;
     uint64_t n2v_version = ~0ull;
+    // radix base of the structure: 2 (the method) or 4 (Supplement S.2; hdr then holds
+    // n * H4_WORDS words, and only walks, dumps and memory statistics are supported)
+    uint32_t radix_base = 2;
     // per-phase timing of the last walk / PPR / update call (events on its stream)
     hipEvent_t ev[PHASE_EVENTS] = {};
     uint32_t nev = 0;
@@ -347,6 +379,12 @@ void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long lo
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st);
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);
+// radix4.hip
+int launch_walk4(bingo_graph* g, uint64_t n_walks, const uint32_t* starts, uint64_t base, uint32_t len,
+                 uint64_t seed, uint32_t* paths, uint64_t* steps, hipStream_t st);
+int export_graph4(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
+                  hipStream_t st);
+int memory_stats4(bingo_graph* g, bingo_mem_stats* out, hipStream_t st);
 // walk.hip
 #define WALK_BATCH_MAX BINGO_WALK_BATCH_MAX
 // the next walk counter slot for a call on st: if the call that held it last ran on another

@@ -268,7 +268,8 @@ void worker_main(bingo_server* s) {
 extern "C" {
 
 int bingo_server_create(bingo_graph* g, const bingo_server_config* cfg, bingo_server** out) {
-    if (!g || !cfg || !out || cfg->struct_size != sizeof(bingo_server_config)) return BINGO_E_INVALID;
+    if (!g || g->radix_base != 2 || !cfg || !out || cfg->struct_size != sizeof(bingo_server_config))
+        return BINGO_E_INVALID;
     if (cfg->max_inflight == 0 || cfg->max_inflight > 64) return BINGO_E_INVALID;
     if (cfg->max_batch > BINGO_WALK_BATCH_MAX || cfg->reserved) return BINGO_E_INVALID;
     *out = nullptr;

@@ -1543,7 +1543,8 @@ int noalloc_scratch(unsigned long long** out) {
 extern "C" int bingo_walk_noalloc(const bingo_graph* gc, uint64_t n_walks, const uint32_t* d_starts,
                                   uint64_t walk_id_base, uint32_t length, uint64_t seed, uint32_t* d_paths,
                                   uint64_t* d_steps_taken, void* stream) {
-    if (!gc || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu) return BINGO_E_INVALID;
+    if (!gc || gc->radix_base != 2 || (n_walks && (!d_starts || !d_paths)) || length == 0xFFFFFFFFu)
+        return BINGO_E_INVALID;
     bingo_graph* g = const_cast<bingo_graph*>(gc);
     hipStream_t st = (hipStream_t)stream;
     unsigned long long* ctl = nullptr;

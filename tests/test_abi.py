@@ -90,6 +90,16 @@ def test_build_rejects_bad_frac_bits_without_gpu():
         assert lib.bingo_build(ctypes.byref(cfg), 10, 0, None, None, None, None, ctypes.byref(out)) == -1
 
 
+def test_build_rejects_bad_radix_without_gpu():
+    from paper_2504_10233_amd.binding import _Config
+    lib = ctypes.CDLL(_lib_path())
+    out = ctypes.c_void_p()
+    # base 3; base 4 with fixed-point biases or alias rows; a nonzero reserved word
+    for fb, al, rb, rs in ((0, 0, 3, 0), (8, 0, 4, 0), (0, 1, 4, 0), (0, 0, 4, 1)):
+        cfg = _Config(ctypes.sizeof(_Config), 1, 40, 10, 0, fb, al, rb, rs)
+        assert lib.bingo_build(ctypes.byref(cfg), 10, 0, None, None, None, None, ctypes.byref(out)) == -1
+
+
 def test_missing_library_fails_loudly(tmp_path):
     # the package without its shared library: the first call raises, nothing falls back to the host
     import shutil
