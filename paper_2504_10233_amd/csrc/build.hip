@@ -99,9 +99,10 @@ __global__ void __launch_bounds__(WB) k_header(uint32_t n, const uint32_t* __res
         lw += __shfl_xor(lw, o);
     }
     const uint64_t mask = __ballot(cnt > 0) & 0xFFFFFFFFull;
+    const uint32_t hi = mask_hi((uint32_t)mask);
     uint32_t* h = hdr + (size_t)u * HDR_WORDS;
     if (lane < 32) {
-        h[H_CNT + lane] = cnt;
+        if (lane <= hi) h[H_CNT + (hi - lane)] = cnt;
         h[H_INFO + lane] = (t == GT_ONE) ? last : 0u;
     }
     if (lane == 0) {
@@ -138,11 +139,12 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     }
     const uint32_t cap = h[H_ACAP];
     const uint64_t ao = adj_off[u];
-    if (lane == 0) { h[H_ADJLO] = (uint32_t)ao; h[H_ADJHI] = (uint32_t)(ao >> 32); }
+    const uint32_t hi = mask_hi(h[H_MASK]);
+    if (lane == 0) { h[H_ADJLO] = (uint32_t)ao; h[H_ADJHI] = adjhi_word(ao, hi); }
     uint64_t* edges = (uint64_t*)(pool + ao);
     uint32_t* seqs = pool + ao + 2ull * cap;
     // list blocks of the listed groups, in ascending k
-    const uint32_t cnt = lane < 32 ? h[H_CNT + lane] : 0u;
+    const uint32_t cnt = lane < 32 ? hdr_slot(h, lane, hi) : 0u;
     const uint32_t t = lane < 32 ? group_type(cnt, d, rule) : GT_EMPTY;
     const bool lst = type_listed(t);
     const uint32_t lcap = lst ? list_cap_for(cnt) : 0u;
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(WB) k_fill(uint32_t n, const uint32_t* __restr
     const uint32_t smask = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
     // one-element groups: the member's destination in the count slot
     const bool one = lane < 32 && t == GT_ONE;
-    if (one) h[H_CNT + lane] = cdst[b + h[H_INFO + lane]];
+    if (one) h[H_CNT + (hi - lane)] = cdst[b + h[H_INFO + lane]];
     const uint32_t onemask = (uint32_t)(__ballot(one) & 0xFFFFFFFFull);
     if (lane == 0) h[H_ONEMASK] = onemask;
     // list capacity exponents, one byte per group, packed four per word
@@ -369,10 +371,10 @@ __global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restr
         if (u >= n) continue;  // a rejected stream's bad source id
         const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         uint4* row = alias + (size_t)u * ALIAS_ENTRIES;
-        const uint32_t onem = h[H_ONEMASK];
+        const uint32_t onem = h[H_ONEMASK], hi = hdr_hi(h);
         uint64_t W = 0;
         for (int k = 0; k < ALIAS_ENTRIES; ++k) {
-            const uint32_t c = slot_count(h[H_CNT + k], onem, (uint32_t)k);
+            const uint32_t c = slot_count(hdr_slot(h, (uint32_t)k, hi), onem, (uint32_t)k);
             cnt[k][tx] = c;
             W += (uint64_t)c << k;
         }
@@ -439,91 +441,105 @@ __global__ void __launch_bounds__(SR_TB) k_srebuild(uint32_t* __restrict__ hdr, 
     __shared__ uint32_t g_c[32], g_info[32], g_lcap[32];
     __shared__ uint32_t wcnt[SR_TPT][SR_TB / 64];
     __shared__ uint32_t s_smask;
+    __shared__ uint32_t todo[SR_TB], ntodo;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint64_t total = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
-    for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-        if (dirty && !dirty[it]) continue;
-        const uint32_t u = list ? list[it] : (uint32_t)it;
-        if (u >= n) continue;
-        uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-        const uint32_t d = h[H_DEG];
-        __syncthreads();  // the previous vertex is done with the shared arrays
-        if (wave == 0) {
-            const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
-            const bool ne = lane < 32 && ((mask >> lane) & 1u);
-            const uint32_t c = ne ? slot_count(h[H_CNT + lane], onem, lane) : 0u;
-            const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
-            const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
-            if (lane < 32) {
-                g_c[lane] = c;
-                g_info[lane] = h[H_INFO + lane];
-                g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+    // the flags of SR_TB list entries at a time; the flagged vertices one after another
+    for (uint64_t c0 = (uint64_t)blockIdx.x * SR_TB; c0 < total; c0 += (uint64_t)gridDim.x * SR_TB) {
+        __syncthreads();  // the previous chunk is done with todo
+        if (tid == 0) ntodo = 0;
+        __syncthreads();
+        {
+            const uint64_t it = c0 + tid;
+            if (it < total && (!dirty || dirty[it])) {
+                const uint32_t u = list ? list[it] : (uint32_t)it;
+                if (u < n) todo[atomicAdd(&ntodo, 1u)] = u;
             }
-            if (lane == 0) s_smask = sm;
         }
         __syncthreads();
-        const uint32_t smask = s_smask;
-        if (!smask) {
-            if (tid == 0) h[H_SLEN] = 0;
-            continue;
-        }
-        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
-        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
-        uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
-        uint32_t sfill = 0;
-        for (uint32_t q0 = 0; q0 < d; q0 += SR_TB * SR_TPT) {
-            uint64_t bal[SR_TPT];
-            bool in[SR_TPT];
-#pragma unroll
-            for (uint32_t j = 0; j < SR_TPT; ++j) {
-                const uint32_t i = q0 + j * SR_TB + tid;
-                in[j] = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask) != 0u;
-            }
-#pragma unroll
-            for (uint32_t j = 0; j < SR_TPT; ++j) {
-                bal[j] = __ballot(in[j]);
-                if (lane == 0) wcnt[j][wave] = (uint32_t)__popcll(bal[j]);
+        const uint32_t nt = ntodo;
+        for (uint32_t q = 0; q < nt; ++q) {
+            const uint32_t u = todo[q];
+            uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+            const uint32_t d = h[H_DEG];
+            __syncthreads();  // the previous vertex is done with the shared arrays
+            if (wave == 0) {
+                const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
+                const bool ne = lane < 32 && ((mask >> lane) & 1u);
+                const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), onem, lane) : 0u;
+                const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+                const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+                if (lane < 32) {
+                    g_c[lane] = c;
+                    g_info[lane] = h[H_INFO + lane];
+                    g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+                }
+                if (lane == 0) s_smask = sm;
             }
             __syncthreads();
-#pragma unroll
-            for (uint32_t j = 0; j < SR_TPT; ++j) {
-                uint32_t rk = sfill + (uint32_t)__popcll(bal[j] & lanemask_lt());
-                for (uint32_t w = 0; w < wave; ++w) rk += wcnt[j][w];
-                if (in[j]) S[rk] = q0 + j * SR_TB + tid;
-                sfill += wcnt[j][0] + wcnt[j][1] + wcnt[j][2] + wcnt[j][3];
+            const uint32_t smask = s_smask;
+            if (!smask) {
+                if (tid == 0) h[H_SLEN] = 0;
+                continue;
             }
-            __syncthreads();  // wcnt is rewritten by the next tile
-        }
-        if (tid == 0) h[H_SLEN] = sfill;
-        __threadfence_block();
-        __syncthreads();  // S(u) complete and visible to the block
-        uint32_t sh = 0;
-        while ((sfill >> sh) >= SR_XL) ++sh;
-        const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
-        for (uint32_t j = tid; j < nl; j += SR_TB) smp[j] = S[(uint64_t)j << sh];
-        __syncthreads();
-        for (uint32_t mm = smask; mm; mm &= mm - 1) {
-            const int k = __ffs(mm) - 1;
-            const uint32_t c = g_c[k];
-            uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
-            uint32_t* I = L + g_lcap[k];
-            for (uint32_t p = tid; p < c; p += SR_TB) {
-                const uint32_t v = L[p];
-                uint32_t lo = 0, hi = nl;  // samples below v
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (smp[mid] < v) lo = mid + 1; else hi = mid;
+            const uint64_t adj = hdr_adj(h);
+            const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
+            uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+            uint32_t sfill = 0;
+            for (uint32_t q0 = 0; q0 < d; q0 += SR_TB * SR_TPT) {
+                uint64_t bal[SR_TPT];
+                bool in[SR_TPT];
+    #pragma unroll
+                for (uint32_t j = 0; j < SR_TPT; ++j) {
+                    const uint32_t i = q0 + j * SR_TB + tid;
+                    in[j] = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask) != 0u;
                 }
-                uint32_t pos = 0;
-                if (lo > 0) {
-                    uint32_t a = ((lo - 1) << sh) + 1, b = min(lo << sh, sfill);
-                    while (a < b) {
-                        const uint32_t mid = (a + b) >> 1;
-                        if (S[mid] < v) a = mid + 1; else b = mid;
+    #pragma unroll
+                for (uint32_t j = 0; j < SR_TPT; ++j) {
+                    bal[j] = __ballot(in[j]);
+                    if (lane == 0) wcnt[j][wave] = (uint32_t)__popcll(bal[j]);
+                }
+                __syncthreads();
+    #pragma unroll
+                for (uint32_t j = 0; j < SR_TPT; ++j) {
+                    uint32_t rk = sfill + (uint32_t)__popcll(bal[j] & lanemask_lt());
+                    for (uint32_t w = 0; w < wave; ++w) rk += wcnt[j][w];
+                    if (in[j]) S[rk] = q0 + j * SR_TB + tid;
+                    sfill += wcnt[j][0] + wcnt[j][1] + wcnt[j][2] + wcnt[j][3];
+                }
+                __syncthreads();  // wcnt is rewritten by the next tile
+            }
+            if (tid == 0) h[H_SLEN] = sfill;
+            __threadfence_block();
+            __syncthreads();  // S(u) complete and visible to the block
+            uint32_t sh = 0;
+            while ((sfill >> sh) >= SR_XL) ++sh;
+            const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
+            for (uint32_t j = tid; j < nl; j += SR_TB) smp[j] = S[(uint64_t)j << sh];
+            __syncthreads();
+            for (uint32_t mm = smask; mm; mm &= mm - 1) {
+                const int k = __ffs(mm) - 1;
+                const uint32_t c = g_c[k];
+                uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
+                uint32_t* I = L + g_lcap[k];
+                for (uint32_t p = tid; p < c; p += SR_TB) {
+                    const uint32_t v = L[p];
+                    uint32_t lo = 0, hi = nl;  // samples below v
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (smp[mid] < v) lo = mid + 1; else hi = mid;
                     }
-                    pos = a;
+                    uint32_t pos = 0;
+                    if (lo > 0) {
+                        uint32_t a = ((lo - 1) << sh) + 1, b = min(lo << sh, sfill);
+                        while (a < b) {
+                            const uint32_t mid = (a + b) >> 1;
+                            if (S[mid] < v) a = mid + 1; else b = mid;
+                        }
+                        pos = a;
+                    }
+                    I[pos] = p;
                 }
-                I[pos] = p;
             }
         }
     }
@@ -547,7 +563,7 @@ void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* 
 void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
                     const uint32_t* dirty, hipStream_t st) {
     if (max_count == 0 || !g->rule.adaptive) return;  // without adaption no group is sparse
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(max_count, 4096);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((max_count + SR_TB - 1) / SR_TB, 4096);
     hipLaunchKernelGGL(k_srebuild, dim3(grid), dim3(SR_TB), 0, st, g->hdr, g->pool, g->n, g->rule, list, count,
                        max_count, dirty);
 }

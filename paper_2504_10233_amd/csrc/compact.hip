@@ -18,7 +18,7 @@ __device__ __forceinline__ uint64_t lane_list_words(const uint32_t* __restrict__
                                                     uint32_t lane, GroupRule rule) {
     if (lane == 32) return h[H_SCAP];
     if (lane >= 32 || !((mask >> lane) & 1u)) return 0ull;
-    const uint32_t c = slot_count(h[H_CNT + lane], h[H_ONEMASK], lane);
+    const uint32_t c = slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane);
     const uint32_t t = group_type(c, d, rule);
     if (!type_listed(t)) return 0ull;
     const uint32_t lcap = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, con
     for (uint64_t u = (uint64_t)blockIdx.x * (WB / 64) + wave; u < n; u += (uint64_t)gridDim.x * (WB / 64)) {
         uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         const uint32_t d = h[H_DEG], mask = h[H_MASK], cap = h[H_ACAP];
-        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        const uint64_t adj = hdr_adj(h);
         const uint64_t lw = lane_list_words(h, d, mask, lane, rule);
         const uint32_t info = lane < 32 ? h[H_INFO + lane] : (lane == 32 ? h[H_SBLK] : 0u);
         uint64_t o = off[u];
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(WB) k_cmp_copy(uint32_t* __restrict__ hdr, con
             wave_copy(src + adj, dst + o, words, lane);
             if (lane == 0) {
                 h[H_ADJLO] = (uint32_t)o;
-                h[H_ADJHI] = (uint32_t)(o >> 32);
+                h[H_ADJHI] = adjhi_word(o, hdr_hi(h));
             }
             o += words;
         }

@@ -9,19 +9,24 @@
 // ---------------------------------------------------------------------------
 // Per-vertex header: the inter-group sampling space of Sec. 3 / Sec. 4.1, one
 // fixed 384-byte slot (three 128-byte lines) per vertex, 128-byte aligned.
-//   line 0: mask of one-element groups, degree d, W = sum_k c_k 2^k (u64),
-//           adjacency block offset (u64, in pool words), slot k for k = 0..25
-//   line 1: slot k for k = 26..31, info_k for k = 0..25
-//   line 2: info_k for k = 26..31, adjacency capacity, next sequence number,
-//           log2 of each listed group's list capacity (bytes), mask of
-//           non-empty groups, the reduced list S(u) (block offset, length,
-//           capacity), spare
+//   words 0..5: mask of one-element groups, degree d, W = sum_k c_k 2^k (u64),
+//           adjacency block offset (u64, in pool words; bits 24..28 of its
+//           high word hold hi, the highest non-empty group)
+//   words 6..37: the group slots by rank from the top: word 6 + r holds the
+//           slot of group hi - r (r = 0..hi)
+//   words 38..69: info_k, k = 0..31
+//   line 2: adjacency capacity, next sequence number, log2 of each listed
+//           group's list capacity (bytes), mask of non-empty groups, the
+//           reduced list S(u) (block offset, length, capacity), spare
 // Slot k holds c_k, except for a one-element group (c_k = 1), whose slot holds
-// its member's destination vertex: a step that selects such a group ends on
-// line 0 without touching the adjacency.  info_k is the member index of a
+// its member's destination vertex: a step that selects such a group ends in
+// the header without touching the adjacency.  info_k is the member index of a
 // one-element group, or the offset of a listed group's list block in 32-byte
-// units of the pool.  Dense and empty groups have no info.  A walk step reads
-// line 0 and, for listed groups, one word of line 1.
+// units of the pool.  Dense and empty groups have no info.  The first 64 bytes
+// hold W, d, the offset and the ten highest groups, which carry all but a
+// fraction 2^-10 or less of W's mass when the top group is full; a walk step
+// picks its group from the top (suffix sums) and reads further only when the
+// draw falls below them.
 // ---------------------------------------------------------------------------
 #define HDR_WORDS 96
 #define H_ONEMASK 0
@@ -39,6 +44,8 @@
 #define H_SBLK 81      // S(u) block offset in 32-byte units (valid when H_SCAP > 0)
 #define H_SLEN 82      // |S(u)|
 #define H_SCAP 83      // S(u) capacity in entries (0: the vertex has no sparse group)
+#define H_HI_SHIFT 24  // hi in the high word of the adjacency offset
+#define H_ADJHI_MASK 0x00FFFFFFu
 #define STOP_VERTEX 0xFFFFFFFFu
 
 // ---------------------------------------------------------------------------
@@ -73,6 +80,20 @@ __host__ __device__ inline uint64_t r4_adj_words(uint32_t cap) { return ((uint64
 // c_k from slot k (one-element groups keep their member's destination there)
 __host__ __device__ inline uint32_t slot_count(uint32_t slot, uint32_t onemask, uint32_t k) {
     return ((onemask >> k) & 1u) ? 1u : slot;
+}
+// the highest non-empty group of a mask (0 for an empty one)
+__host__ __device__ inline uint32_t mask_hi(uint32_t mask) { return mask ? 31u - (uint32_t)__builtin_clz(mask) : 0u; }
+// header fields: adjacency offset, hi, and the slot of group k (0 above hi: those groups are empty)
+__host__ __device__ inline uint64_t hdr_adj(const uint32_t* h) {
+    return ((uint64_t)(h[H_ADJHI] & H_ADJHI_MASK) << 32) | h[H_ADJLO];
+}
+__host__ __device__ inline uint32_t hdr_hi(const uint32_t* h) { return h[H_ADJHI] >> H_HI_SHIFT; }
+__host__ __device__ inline uint32_t hdr_slot(const uint32_t* h, uint32_t k, uint32_t hi) {
+    return k <= hi ? h[H_CNT + (hi - k)] : 0u;
+}
+// the high word of the adjacency offset with hi
+__host__ __device__ inline uint32_t adjhi_word(uint64_t adj, uint32_t hi) {
+    return (uint32_t)(adj >> 32) | (hi << H_HI_SHIFT);
 }
 
 // Adjacency block of capacity cap (words): cap edge words of 64 bits

@@ -19,11 +19,11 @@ __global__ void k_dump_size(const uint32_t* __restrict__ hdr, uint32_t u0, uint3
     const uint32_t u = u0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= u1) return;
     const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-    const uint32_t d = h[H_DEG], mask = h[H_MASK], onem = h[H_ONEMASK];
+    const uint32_t d = h[H_DEG], mask = h[H_MASK], onem = h[H_ONEMASK], hi = hdr_hi(h);
     uint64_t s = 3 + 3ull * d;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         const int k = __ffs(mm) - 1;
-        const uint32_t c = slot_count(h[H_CNT + k], onem, k);
+        const uint32_t c = slot_count(hdr_slot(h, k, hi), onem, k);
         s += 3 + stored_words(group_type(c, d, rule), c);
     }
     sz[u - u0] = s;
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(WB) k_dump_write(const uint32_t* __restrict__ 
     const uint32_t d = h[H_DEG], mask = h[H_MASK];
     uint32_t* o = out + off[u - u0];
     if (lane == 0) { o[0] = d; o[1] = h[H_NSEQ]; o[2] = mask; }
-    const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+    const uint64_t adj = hdr_adj(h);
     const uint32_t cap = h[H_ACAP];
     const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
     const uint32_t* seqs = pool + adj + 2ull * cap;
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(WB) k_dump_write(const uint32_t* __restrict__ 
     }
     // group records in ascending k: lane k computes its record's size and start
     const bool ne = lane < 32 && ((mask >> lane) & 1u);
-    const uint32_t c = ne ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
+    const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
     const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
     const uint64_t sz = ne ? 3ull + stored_words(t, c) : 0ull;
     uint64_t x = sz;
@@ -92,12 +92,12 @@ __global__ void k_idx_size(const uint32_t* __restrict__ hdr, uint32_t u0, uint32
     const uint32_t u = u0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= u1) return;
     const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-    const uint32_t d = h[H_DEG], mask = h[H_MASK], onem = h[H_ONEMASK];
+    const uint32_t d = h[H_DEG], mask = h[H_MASK], onem = h[H_ONEMASK], hi = hdr_hi(h);
     const uint32_t slen = h[H_SCAP] ? h[H_SLEN] : 0u;
     uint64_t s = 1 + (uint64_t)slen;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         const int k = __ffs(mm) - 1;
-        const uint32_t c = slot_count(h[H_CNT + k], onem, k);
+        const uint32_t c = slot_count(hdr_slot(h, k, hi), onem, k);
         const uint32_t t = group_type(c, d, rule);
         if (t == GT_REGULAR) s += 1 + (uint64_t)c;
         else if (t == GT_SPARSE) s += 1 + (uint64_t)slen;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(WB) k_idx_write(const uint32_t* __restrict__ h
     if (lane == 0) o[0] = slen;
     for (uint32_t i = lane; i < slen; i += 64) o[1 + i] = S[i];
     const bool ne = lane < 32 && ((mask >> lane) & 1u);
-    const uint32_t c = ne ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
+    const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
     const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
     const uint64_t sz = t == GT_REGULAR ? 1ull + c : (t == GT_SPARSE ? 1ull + slen : 0ull);
     uint64_t x = sz;
@@ -169,14 +169,14 @@ __global__ void __launch_bounds__(WB) k_mem(const uint32_t* __restrict__ hdr, co
         const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
         const uint32_t d = h[H_DEG], mask = h[H_MASK];
         const bool ne = lane < 32 && ((mask >> lane) & 1u);
-        const uint32_t c = ne ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
+        const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
         const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
         const uint32_t capb = lane < 32 ? ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
         const uint32_t smask = (uint32_t)(__ballot(ne && t == GT_SPARSE) & 0xFFFFFFFFull);
         // |S(u)|: edges in at least one sparse group
         uint64_t S = 0;
         if (smask) {
-            const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+            const uint64_t adj = hdr_adj(h);
             const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
             for (uint32_t i0 = 0; i0 < d; i0 += 64) {
                 const uint32_t i = i0 + lane;

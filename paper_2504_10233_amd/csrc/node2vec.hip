@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(TB) k_n2v_keys(const uint32_t* __restrict__ hd
          u += ((uint64_t)gridDim.x * blockDim.x) >> 6) {
         const uint32_t* h = hdr + u * HDR_WORDS;
         const uint32_t d = h[H_DEG];
-        const uint64_t adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        const uint64_t adj = hdr_adj(h);
         const uint64_t o = off[u];
         for (uint32_t i = lane; i < d; i += 64) keys[o + i] = (u << 32) | pool[adj + 2ull * i];
     }

@@ -61,6 +61,129 @@ __device__ __forceinline__ uint32_t decimal_pick(const uint32_t* __restrict__ h,
     return STOP_VERTEX;
 }
 
+// The group choice of a step at u (Sec. 4.1: group k with probability
+// c_k 2^k / W, Eq. eq:group_prob).  Returns false at a vertex without out-edges.
+// MODE 0 (integer biases, inverse transform): the ascending scan picks the k
+// with prefix(k-1) <= r < prefix(k); with t = W - r that is the k with
+// suffix(k+1) < t <= suffix(k), found from the top.  The header's first 64
+// bytes hold the ten highest groups, so a step reads the rest of the slots
+// only when t exceeds their total.  MODE 1 (fixed-point biases): integer
+// groups F..31 ascending, the decimal group (slot 0) last, over all slots.
+// MODE 2: the alias table picks the group; its slot comes from the first 64
+// bytes when it is among the ten highest.
+struct GroupPick {
+    int sel;         // the group; -1: the decimal group (MODE 1), or an inconsistent header
+    uint32_t csel;   // its count
+    uint32_t raw;    // its slot word (a one-element group's destination)
+    uint32_t d, onem, hi;
+    uint32_t slot0;  // MODE 1: slot of group 0, the decimal group's count
+    uint64_t adj;
+};
+
+template <int MODE>
+__device__ __forceinline__ bool pick_group(const uint32_t* __restrict__ hdr, uint32_t u, RandStream& rs,
+                                           GroupRule rule, GroupPick& g) {
+    const uint32_t* __restrict__ h = hdr + (size_t)u * HDR_WORDS;
+    const uint4* h4 = reinterpret_cast<const uint4*>(h);
+    const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3];
+    g.d = q0.y;
+    if (g.d == 0) return false;
+    const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
+    g.onem = q0.x;
+    g.hi = q1.y >> H_HI_SHIFT;
+    g.adj = ((uint64_t)(q1.y & H_ADJHI_MASK) << 32) | q1.x;
+    g.sel = -1;
+    g.csel = g.raw = g.slot0 = 0;
+    uint32_t sl[32];  // sl[r]: slot of group hi - r
+    sl[0] = q1.z; sl[1] = q1.w;
+    sl[2] = q2.x; sl[3] = q2.y; sl[4] = q2.z; sl[5] = q2.w;
+    sl[6] = q3.x; sl[7] = q3.y; sl[8] = q3.z; sl[9] = q3.w;
+    if constexpr (MODE == 2) {
+        // alias table: slot j from the top 5 bits of a word, then x < W against the slot's cut
+        const uint32_t j = rs_next32(rs) >> 27;
+        const uint4 e = rule.alias[(size_t)u * ALIAS_ENTRIES + j];
+        const uint64_t x = rs_below64(rs, W);
+        const uint32_t k = x < (((uint64_t)e.y << 32) | e.x) ? j : e.z;
+        if (k > g.hi) return true;  // an empty group: only on an inconsistent structure
+        const uint32_t r = g.hi - k;
+        uint32_t raw = 0;
+        if (r < 10) {
+#pragma unroll
+            for (int q = 0; q < 10; ++q)
+                if ((uint32_t)q == r) raw = sl[q];
+        } else {
+            raw = h[H_CNT + r];
+        }
+        g.sel = (int)k;
+        g.raw = raw;
+        g.csel = ((g.onem >> k) & 1u) ? 1u : raw;
+    } else if constexpr (MODE == 1) {
+        const uint4 q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7], q8 = h4[8], q9 = h4[9];
+        sl[10] = q4.x; sl[11] = q4.y; sl[12] = q4.z; sl[13] = q4.w;
+        sl[14] = q5.x; sl[15] = q5.y; sl[16] = q5.z; sl[17] = q5.w;
+        sl[18] = q6.x; sl[19] = q6.y; sl[20] = q6.z; sl[21] = q6.w;
+        sl[22] = q7.x; sl[23] = q7.y; sl[24] = q7.z; sl[25] = q7.w;
+        sl[26] = q8.x; sl[27] = q8.y; sl[28] = q8.z; sl[29] = q8.w;
+        sl[30] = q9.x; sl[31] = q9.y;
+        // integer groups F..31 ascending (ranks descending), the decimal group last
+        const uint64_t r = rs_below64(rs, W);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int q = 31; q >= 0; --q) {
+            if ((uint32_t)q <= g.hi) {
+                const uint32_t k = g.hi - (uint32_t)q;
+                const uint32_t ck = ((g.onem >> k) & 1u) ? 1u : sl[q];
+                if (k == 0) g.slot0 = sl[q];
+                if (k >= rule.fbits) acc += (uint64_t)ck << k;
+                if (g.sel < 0 && r < acc) { g.sel = (int)k; g.csel = ck; g.raw = sl[q]; }
+            }
+        }
+    } else {
+        const uint64_t t = W - rs_below64(rs, W);  // in [1, W]
+        uint64_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            if (g.sel < 0 && (uint32_t)q <= g.hi) {
+                const uint32_t k = g.hi - (uint32_t)q;
+                const uint32_t ck = ((g.onem >> k) & 1u) ? 1u : sl[q];
+                acc += (uint64_t)ck << k;
+                if (acc >= t) { g.sel = (int)k; g.csel = ck; g.raw = sl[q]; }
+            }
+        }
+        if (g.sel < 0 && g.hi >= 10) {
+            const uint4 q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
+            sl[10] = q4.x; sl[11] = q4.y; sl[12] = q4.z; sl[13] = q4.w;
+            sl[14] = q5.x; sl[15] = q5.y; sl[16] = q5.z; sl[17] = q5.w;
+            sl[18] = q6.x; sl[19] = q6.y; sl[20] = q6.z; sl[21] = q6.w;
+            sl[22] = q7.x; sl[23] = q7.y; sl[24] = q7.z; sl[25] = q7.w;
+#pragma unroll
+            for (int q = 10; q < 26; ++q) {
+                if (g.sel < 0 && (uint32_t)q <= g.hi) {
+                    const uint32_t k = g.hi - (uint32_t)q;
+                    const uint32_t ck = ((g.onem >> k) & 1u) ? 1u : sl[q];
+                    acc += (uint64_t)ck << k;
+                    if (acc >= t) { g.sel = (int)k; g.csel = ck; g.raw = sl[q]; }
+                }
+            }
+            if (g.sel < 0 && g.hi >= 26) {
+                const uint4 q8 = h4[8], q9 = h4[9];
+                sl[26] = q8.x; sl[27] = q8.y; sl[28] = q8.z; sl[29] = q8.w;
+                sl[30] = q9.x; sl[31] = q9.y;
+#pragma unroll
+                for (int q = 26; q < 32; ++q) {
+                    if (g.sel < 0 && (uint32_t)q <= g.hi) {
+                        const uint32_t k = g.hi - (uint32_t)q;
+                        const uint32_t ck = ((g.onem >> k) & 1u) ? 1u : sl[q];
+                        acc += (uint64_t)ck << k;
+                        if (acc >= t) { g.sel = (int)k; g.csel = ck; g.raw = sl[q]; }
+                    }
+                }
+            }
+        }
+    }
+    return true;
+}
+
 // One transition from u (no termination test).  Returns the next vertex or
 // STOP_VERTEX for a vertex without out-edges.  MODE 0: integer biases, inverse
 // transform over the groups; 1: fixed-point biases (rule.fbits > 0, decimal
@@ -69,75 +192,28 @@ __device__ __forceinline__ uint32_t decimal_pick(const uint32_t* __restrict__ h,
 template <int SPEC, int MODE>
 __device__ __forceinline__ uint32_t walk_step_body(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                    uint32_t u, RandStream& rs, GroupRule rule) {
-    const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
-    // line 0 of the header in one go: mask, d, W, adjacency offset, c_0..c_25
-    const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3], q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
-    const uint32_t d = q0.y;
-    if (d == 0) return STOP_VERTEX;
-    const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
-    const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
-                            q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
-    // groups in ascending k; fixed-point biases skip the slots below F (slot 0
-    // is their decimal group, taken last)
-    // (a one-element group's slot holds its member's destination; its count is 1)
-    const uint32_t fb = (MODE == 1) ? rule.fbits : 0u;
-    const uint32_t onem = q0.x;
-    uint64_t acc = 0;
-    int sel = -1;
-    uint32_t csel = 0, raw = 0;
-    if constexpr (MODE == 2) {
-        // alias table: slot j from the top 5 bits of a word, then x < W against the slot's cut
-        const uint32_t j = rs_next32(rs) >> 27;
-        const uint4 e = rule.alias[(size_t)u * ALIAS_ENTRIES + j];
-        const uint64_t x = rs_below64(rs, W);
-        sel = x < (((uint64_t)e.y << 32) | e.x) ? (int)j : (int)e.z;
-        if (sel < 26) {
-#pragma unroll
-            for (int k = 0; k < 26; ++k)
-                if (k == sel) raw = c[k];
-        } else {
-            raw = hdr[(size_t)u * HDR_WORDS + H_CNT + sel];
-        }
-        csel = ((onem >> sel) & 1u) ? 1u : raw;
-    } else {
-        const uint64_t r = rs_below64(rs, W);
-#pragma unroll
-        for (int k = 0; k < 26; ++k) {
-            const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
-            if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
-            if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
-        }
-        if (sel < 0) {
-            const uint4 a = h4[8], b = h4[9];
-            const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
-                acc += (uint64_t)ck << (26 + k);
-                if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
-            }
-        }
-    }
-    const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (MODE == 1 && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, rs);
-    if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
-    if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
-    const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + adj);
-    const uint32_t t = group_type(csel, d, rule);
+    GroupPick g;
+    if (!pick_group<MODE>(hdr, u, rs, rule, g)) return STOP_VERTEX;
+    if (MODE == 1 && g.sel < 0)
+        return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, g.adj, g.d, g.slot0, g.onem, rule, rs);
+    if (g.sel < 0) return STOP_VERTEX;  // only on an inconsistent header
+    if ((g.onem >> g.sel) & 1u) return g.raw;  // one-element group: the step ends in the header
+    const uint64_t* __restrict__ edges = reinterpret_cast<const uint64_t*>(pool + g.adj);
+    const uint32_t t = group_type(g.csel, g.d, rule);
     if (t == GT_DENSE) {
         // rejection on the whole neighbor list: accept a slot whose weight has
         // bit sel.  Acceptance is above alpha % per attempt, so the bound is
         // never reached on a consistent structure; it only keeps a corrupted
         // one from spinning forever.
         for (uint32_t att = 0; att < (1u << 16); att += SPEC) {
-            const uint32_t v = dense_round<SPEC>(edges, d, (uint32_t)sel, rs);
+            const uint32_t v = dense_round<SPEC>(edges, g.d, (uint32_t)g.sel, rs);
             if (v != PENDING) return v;
         }
         return STOP_VERTEX;
     }
-    const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
-    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(rs, csel)];
-    return pool[adj + 2ull * i];
+    const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + g.sel];
+    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(rs, g.csel)];
+    return pool[g.adj + 2ull * i];
 }
 
 // Walk ids are handed to waves in chunks: one atomic per QCHUNK ids, and the

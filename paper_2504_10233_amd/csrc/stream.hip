@@ -503,9 +503,9 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         s.u = sk[b];
         uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
         s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ];
-        s.adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+        s.adj = hdr_adj(h);
         s.W = ((uint64_t)h[H_WHI] << 32) | h[H_WLO];
-        s.c = lane < 32 ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
+        s.c = lane < 32 ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
         s.info = lane < 32 ? h[H_INFO + lane] : 0u;
         s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
         s.sblk = h[H_SBLK];
@@ -531,8 +531,10 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         // one-element groups: the member's destination in the count slot
         const bool onek = lane < 32 && t == GT_ONE;
         const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
+        const uint32_t nhi = mask_hi(nmask);
         if (lane < 32) {
-            h[H_CNT + lane] = onek ? (uint32_t)reinterpret_cast<const uint64_t*>(pool + s.adj)[s.info] : s.c;
+            if (lane <= nhi)
+                h[H_CNT + (nhi - lane)] = onek ? (uint32_t)reinterpret_cast<const uint64_t*>(pool + s.adj)[s.info] : s.c;
             h[H_INFO + lane] = (type_listed(t) || t == GT_ONE) ? s.info : 0u;
         }
         const uint32_t lg = (lane < 32 && type_listed(t)) ? (31 - __clz(s.lcap)) : 0u;
@@ -547,7 +549,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
             h[H_WLO] = (uint32_t)s.W;
             h[H_WHI] = (uint32_t)(s.W >> 32);
             h[H_ADJLO] = (uint32_t)s.adj;
-            h[H_ADJHI] = (uint32_t)(s.adj >> 32);
+            h[H_ADJHI] = adjhi_word(s.adj, nhi);
             h[H_ACAP] = s.cap;
             h[H_NSEQ] = s.nseq;
             h[H_SBLK] = s.sblk;

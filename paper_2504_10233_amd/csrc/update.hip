@@ -165,7 +165,7 @@ __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, 
             dold[t] = d;
             vacap[t] = h[H_ACAP];
             vnseq[t] = h[H_NSEQ];
-            vadj[t] = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+            vadj[t] = hdr_adj(h);
             v = nd ? (uint64_t)d + ni : 0ull;
             if (split && d + ni > split) blist[atomicAdd(uc + UC_NBIG, 1ull)] = (uint32_t)t;
         }
@@ -534,11 +534,11 @@ __device__ void load_state(VState& s, uint32_t t, const uint32_t* __restrict__ t
     s.u = tv[t];
     const uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
     s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ]; s.mask = h[H_MASK];
-    s.adj = ((uint64_t)h[H_ADJHI] << 32) | h[H_ADJLO];
+    s.adj = hdr_adj(h);
     s.ts = ts[t]; s.ni = tdl[t] - ts[t]; s.nd = te[t] - tdl[t];
     s.N = ncnt[t]; s.xoff = (uint32_t)xoff[t];
     s.d1 = s.d + s.ni; s.dn = s.d1 - s.N;
-    s.c = lane < 32 ? slot_count(h[H_CNT + lane], h[H_ONEMASK], lane) : 0u;
+    s.c = lane < 32 ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
     s.info = lane < 32 ? h[H_INFO + lane] : 0u;
     s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
     s.told = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
@@ -1229,8 +1229,9 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
     if (onek && member != NF)
         slot = (uint32_t)(SPLIT ? final_word_xv(member, enew, eold, reloc, keep, xv) : enew[member]);
     const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
+    const uint32_t nhi = mask_hi(nmask);
     if (lane < 32) {
-        h[H_CNT + lane] = slot;
+        if (lane <= nhi) h[H_CNT + (nhi - lane)] = slot;
         uint32_t inf = 0;
         if (type_listed(s.tnew)) inf = newinfo;
         else if (s.tnew == GT_ONE) inf = member;
@@ -1249,7 +1250,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
         h[H_WLO] = (uint32_t)wsum;
         h[H_WHI] = (uint32_t)(wsum >> 32);
         h[H_ADJLO] = (uint32_t)nadj;
-        h[H_ADJHI] = (uint32_t)(nadj >> 32);
+        h[H_ADJHI] = adjhi_word(nadj, nhi);
         h[H_ACAP] = ncap;
         h[H_NSEQ] = s.nseq + s.ni;
         h[H_SCAP] = s.scapn;
@@ -1591,7 +1592,7 @@ __global__ void __launch_bounds__(256) k_big_one_dst(const unsigned long long* _
         if (bi.kind != BK_ONE) continue;
         uint32_t* h = hdr + (size_t)bi.u * HDR_WORDS;
         const uint32_t member = h[H_INFO + bi.k];
-        if (member < bi.n) h[H_CNT + bi.k] = pool[bi.a + 2ull * member];
+        if (member < bi.n) h[H_CNT + (mask_hi(h[H_MASK]) - bi.k)] = pool[bi.a + 2ull * member];
     }
 }
 

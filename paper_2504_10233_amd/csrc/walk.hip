@@ -40,67 +40,21 @@ struct StepState {
 template <int MODE>
 __device__ __forceinline__ uint32_t step_begin(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
                                                uint32_t u, StepState& ss, GroupRule rule, uint32_t wave_deg = 0) {
-    const uint4* h4 = reinterpret_cast<const uint4*>(hdr + (size_t)u * HDR_WORDS);
-    const uint4 q0 = h4[0], q1 = h4[1], q2 = h4[2], q3 = h4[3], q4 = h4[4], q5 = h4[5], q6 = h4[6], q7 = h4[7];
-    const uint32_t d = q0.y;
-    if (d == 0) return STOP_VERTEX;
-    const uint64_t W = ((uint64_t)q0.w << 32) | q0.z;
-    const uint32_t c[26] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z,
-                            q4.w, q5.x, q5.y, q5.z, q5.w, q6.x, q6.y, q6.z, q6.w, q7.x, q7.y, q7.z, q7.w};
-    // groups in ascending k; fixed-point biases skip the slots below F (slot 0
-    // is their decimal group, taken last)
-    // (a one-element group's slot holds its member's destination; its count is 1)
-    const uint32_t fb = (MODE == 1) ? rule.fbits : 0u;
-    const uint32_t onem = q0.x;
-    uint64_t acc = 0;
-    int sel = -1;
-    uint32_t csel = 0, raw = 0;
-    if constexpr (MODE == 2) {
-        // alias table: slot j from the top 5 bits of a word, then x < W against the slot's cut
-        const uint32_t j = rs_next32(ss.rs) >> 27;
-        const uint4 e = rule.alias[(size_t)u * ALIAS_ENTRIES + j];
-        const uint64_t x = rs_below64(ss.rs, W);
-        sel = x < (((uint64_t)e.y << 32) | e.x) ? (int)j : (int)e.z;
-        if (sel < 26) {
-#pragma unroll
-            for (int k = 0; k < 26; ++k)
-                if (k == sel) raw = c[k];
-        } else {
-            raw = hdr[(size_t)u * HDR_WORDS + H_CNT + sel];
-        }
-        csel = ((onem >> sel) & 1u) ? 1u : raw;
-    } else {
-        const uint64_t r = rs_below64(ss.rs, W);
-#pragma unroll
-        for (int k = 0; k < 26; ++k) {
-            const uint32_t ck = ((onem >> k) & 1u) ? 1u : c[k];
-            if ((uint32_t)k >= fb) acc += (uint64_t)ck << k;
-            if (sel < 0 && r < acc) { sel = k; csel = ck; raw = c[k]; }
-        }
-        if (sel < 0) {
-            const uint4 a = h4[8], b = h4[9];
-            const uint32_t hc[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const uint32_t ck = ((onem >> (26 + k)) & 1u) ? 1u : hc[k];
-                acc += (uint64_t)ck << (26 + k);
-                if (sel < 0 && r < acc) { sel = 26 + k; csel = ck; raw = hc[k]; }
-            }
-        }
-    }
-    const uint64_t adj = ((uint64_t)q1.y << 32) | q1.x;
-    if (MODE == 1 && sel < 0) return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, adj, d, c[0], onem, rule, ss.rs);
-    if (sel < 0) return STOP_VERTEX;  // only on an inconsistent header
-    if ((onem >> sel) & 1u) return raw;  // one-element group: the step ends on line 0
-    const uint32_t t = group_type(csel, d, rule);
+    GroupPick g;
+    if (!pick_group<MODE>(hdr, u, ss.rs, rule, g)) return STOP_VERTEX;
+    if (MODE == 1 && g.sel < 0)
+        return decimal_pick(hdr + (size_t)u * HDR_WORDS, pool, g.adj, g.d, g.slot0, g.onem, rule, ss.rs);
+    if (g.sel < 0) return STOP_VERTEX;  // only on an inconsistent header
+    if ((g.onem >> g.sel) & 1u) return g.raw;  // one-element group: the step ends in the header
+    const uint32_t t = group_type(g.csel, g.d, rule);
     if (t == GT_DENSE) {
-        ss.adj = adj; ss.d = d; ss.sel = (uint32_t)sel; ss.tries = 0; ss.pending = true;
-        ss.wave = wave_deg != 0 && d >= wave_deg;
+        ss.adj = g.adj; ss.d = g.d; ss.sel = (uint32_t)g.sel; ss.tries = 0; ss.pending = true;
+        ss.wave = wave_deg != 0 && g.d >= wave_deg;
         return PENDING;
     }
-    const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + sel];
-    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(ss.rs, csel)];
-    return pool[adj + 2ull * i];
+    const uint32_t info = hdr[(size_t)u * HDR_WORDS + H_INFO + g.sel];
+    const uint32_t i = pool[(uint64_t)info * LIST_UNIT_WORDS + rs_below32(ss.rs, g.csel)];
+    return pool[g.adj + 2ull * i];
 }
 
 template <int SPEC>
