@@ -111,6 +111,7 @@ def serve_phase(g, n, src, dst, args, log):
     rng = np.random.default_rng(5005)
     reqs = make_requests(rng, args.serve_requests, n, src, dst, 4, 4, 1 << 24)
     res = serve_requests(g, reqs, args.serve_rate, max_batch=args.serve_batch)
+    res.pop("kept")
     res["warmup_requests"] = len(warm)
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
@@ -461,8 +462,18 @@ def workload_skewed_updates(args):
     torch.cuda.synchronize()
     build_s = time.time() - tb
     log("skewed: %d edges (%d on planted hubs), built in %.2fs" % (m, m - (16 << scale), build_s))
+    # Parity at full size on a vertex sample: the batch changes every vertex independently (all its
+    # inserts, then its deletes, then its rebuild), so the oracle needs only the edges and records
+    # whose source is sampled to reproduce those vertices.  Sample: 20 hubs and 2000 other vertices.
+    sample = torch.unique(torch.cat([hubs[:20].to(dev), synth.below(synth.SEEDS["graph"] + c, 40, 2000, n,
+                                                                       device=dev)]))
+    in_s = torch.zeros(n, dtype=torch.bool, device=dev)
+    in_s[sample] = True
+    em = in_s[src]
+    o_edges = [x[em].cpu().numpy() for x in (src, dst, w)]
+    o_batches = []
     mirror = synth.EdgeMirror(src, dst)
-    del src, dst, w
+    del src, dst, w, em
     reps_for = {100: 40, 10_000: 20, 1_000_000: 4, 10_000_000: 2}
     plan = [(int(x), reps_for.get(int(x), 4)) for x in args.update_sizes.split(",")]
     out = {}
@@ -486,6 +497,9 @@ def workload_skewed_updates(args):
                 dsrc, ddst = mirror.src[pos], mirror.dst[pos]
                 mirror.apply(isrc, idst, pos)
                 bt = tuple(x.to(torch.int32).contiguous() for x in (isrc, idst, iw, dsrc, ddst))
+                mi, md = in_s[isrc], in_s[dsrc]
+                o_batches.append([isrc[mi].cpu().numpy(), idst[mi].cpu().numpy(), iw[mi].cpu().numpy(),
+                                  dsrc[md].cpu().numpy(), ddst[md].cpu().numpy()])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 st = g.update(*bt)
@@ -506,11 +520,35 @@ def workload_skewed_updates(args):
             (size, res["graph"]["median_ms"], res["eager"]["median_ms"], res["graph_speedup"],
              res["graph"]["records_per_s"]))
     g.set_tuning(update_graphs=1)
+    parity = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle as O
+        t = time.time()
+        og = O.Graph(n, *o_edges)
+        for bb in o_batches:
+            og.update(*bb)
+        o_s = time.time() - t
+        su = sample.cpu().numpy()
+        dumps = index = True
+        for u in su.tolist():
+            dumps &= bool(np.array_equal(g.export(u, u + 1), og.dump(u, u + 1)))
+            index &= bool(np.array_equal(g.export_index(u, u + 1), og.index_dump(u, u + 1)))
+        hub_d = [int(O.parse_dump(og.dump(int(h), int(h) + 1), 1)[0]["d"]) for h in hubs[:20].tolist()]
+        parity = {"sampled_vertices": int(su.size), "sampled_hubs": 20, "hub_degrees_min_max": [min(hub_d), max(hub_d)],
+                  "oracle_edges": int(o_edges[0].size), "oracle_records": int(sum(x[0].size + x[3].size for x in o_batches)),
+                  "batches_replayed": len(o_batches), "dumps_equal": dumps, "index_dumps_equal": index,
+                  "oracle_s": o_s,
+                  "method": "the oracle holds only the edges and records whose source is sampled; the batch changes "
+                            "each vertex independently, so the sampled vertices' dumps must equal the GPU's"}
+        log("skewed: parity on %d sampled vertices (20 hubs of degree %d..%d after the batches): dumps %s, "
+            "indexes %s (oracle %.1fs, %d records)" % (su.size, min(hub_d), max(hub_d), dumps, index, o_s,
+                                                       parity["oracle_records"]))
     big = out[str(plan[-1][0])]["graph"]
     r = common_fields(args, big["records_per_s"], "edge-updates/s", big["median_ms"],
                       {"workload": "rmat24-ef16-plus-1000-planted-hubs-lognormal-update-batches",
                        "vertices": n, "edges": m, "batch_sizes": [p[0] for p in plan], "hub_endpoint_share": 0.8})
-    r.update({"batches": out, "build_s": build_s,
+    r.update({"batches": out, "build_s": build_s, "parity": parity,
               "note": "value: edge-updates/s of 10^7-record batches through the captured graph (host clock "
                       "around bingo_update_batch, which synchronizes); the inputs are device-resident"})
     return r
@@ -536,9 +574,10 @@ def make_requests(rng, count, n, src, dst, q_max_exp, u_max_exp, w_hi, base_shif
     return reqs
 
 
-def serve_requests(g, reqs, rate, max_inflight=8, max_batch=1):
+def serve_requests(g, reqs, rate, max_inflight=8, max_batch=1, keep=()):
     """Submit the requests to the serving loop with Poisson arrivals at `rate` per second (0: all at
-    once), collect every result; latency is submission to result ready."""
+    once), collect every result; latency is submission to result ready.  The paths of the walk
+    requests whose indices are in `keep` are returned under "kept"."""
     import threading
     import numpy as np
     from paper_2504_10233_amd import Server
@@ -547,12 +586,16 @@ def serve_requests(g, reqs, rate, max_inflight=8, max_batch=1):
     srv = Server(g, max_inflight=max_inflight, max_batch=max_batch)
     tickets = [None] * len(reqs)
     infos = [None] * len(reqs)
+    kept = {}
+    keep = set(keep)
     ready = threading.Semaphore(0)
 
     def waiter():
         for i in range(len(reqs)):
             ready.acquire()
-            _, infos[i] = srv.wait(tickets[i])
+            paths, infos[i] = srv.wait(tickets[i])
+            if i in keep:
+                kept[i] = paths
 
     th = threading.Thread(target=waiter)
     th.start()
@@ -580,7 +623,7 @@ def serve_requests(g, reqs, rate, max_inflight=8, max_batch=1):
             "update_p50_ms": float(np.percentile(u, 50)) if u.size else None,
             "update_p99_ms": float(np.percentile(u, 99)) if u.size else None,
             "sustained_walk_steps_per_s": steps / makespan, "sustained_edge_updates_per_s": recs / makespan,
-            "makespan_s": makespan, "errors": int(sum(1 for x in infos if x["status"] != 0))}
+            "makespan_s": makespan, "errors": int(sum(1 for x in infos if x["status"] != 0)), "kept": kept}
 
 
 def workload_serving(args):
@@ -602,24 +645,68 @@ def workload_serving(args):
     g = Graph(n, src, dst, w, device=dev)
     torch.cuda.synchronize()
     build_s = time.time() - tb
+    w_host = None if args.no_cpu_baseline else w.cpu().numpy()  # for the oracle's replay
     del w
     rng = np.random.default_rng(synth.SEEDS["serving"] if "serving" in synth.SEEDS else 5005)
     nreq = args.serve_count
+    # every request in submission order, for the oracle's replay; the server applies the updates in
+    # that order and a query sees exactly the updates submitted before it
+    history = []
     warm = make_requests(rng, 200, n, src, dst, 5, 4, 1 << 20)
     serve_requests(g, warm, 0, max_batch=args.serve_batch)
-    sat = serve_requests(g, make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20), 0,
-                         max_batch=args.serve_batch)
+    history += warm
+    sreqs = make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20)
+    sat = serve_requests(g, sreqs, 0, max_batch=args.serve_batch)
+    history += sreqs
+    sat.pop("kept")
     rate_sat = sat["achieved_rate_per_s"]
     log("serving R-MAT 25: saturation %.0f requests/s, %.3g walk steps/s" % (rate_sat, sat["sustained_walk_steps_per_s"]))
     loads = {}
+    checked = {}  # history index -> served paths
     for frac in (0.5, 0.8, 0.95):
-        r = serve_requests(g, make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20), frac * rate_sat,
-                           max_batch=args.serve_batch)
+        reqs = make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20)
+        # a sample of the served queries at 80 % load is checked against the oracle
+        walks = [i for i, q in enumerate(reqs) if q[0] == "walk"]
+        keep = walks[:: max(1, len(walks) // 24)][:24] if frac == 0.8 else []
+        r = serve_requests(g, reqs, frac * rate_sat, max_batch=args.serve_batch, keep=keep)
+        for i, paths in r.pop("kept").items():
+            checked[len(history) + i] = paths
+        history += reqs
         loads["%d%%" % int(frac * 100)] = r
         log("serving at %d%% load: query p50 %.2f ms p99 %.2f ms, update p50 %.2f ms p99 %.2f ms, %.3g steps/s" %
             (frac * 100, r["query_p50_ms"], r["query_p99_ms"], r["update_p50_ms"] or -1, r["update_p99_ms"] or -1,
              r["sustained_walk_steps_per_s"]))
     mid = loads["80%"]
+    parity = None
+    if not args.no_cpu_baseline and checked:
+        import oracle as O
+        t = time.time()
+        log("serving: oracle: building on the host (%d edges)" % m)
+        og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w_host)
+        build_o = time.time() - t
+        log("serving: oracle: built in %.1fs; replaying %d requests" % (build_o, len(history)))
+        equal, walks_checked, steps_checked, recs = True, 0, 0, 0
+        t = time.time()
+        for i, q in enumerate(history):
+            if i % 2000 == 0:
+                log("serving: oracle: request %d of %d" % (i, len(history)))
+            if q[0] == "update":
+                st = og.update(*q[1:])
+                recs += st["inserted"] + st["deleted"] + st["not_found"]
+            elif i in checked:
+                opaths, osteps = og.deepwalk(q[1], q[2], q[3], base=q[4], threads=args.oracle_threads)
+                gp = checked[i]
+                equal &= bool(np.array_equal(np.asarray(gp).reshape(-1).view(np.uint32), opaths.reshape(-1)))
+                walks_checked += int(q[1].size)
+                steps_checked += osteps
+        parity = {"queries_checked": len(checked), "walks_checked": walks_checked, "steps_checked": steps_checked,
+                  "paths_equal": equal, "updates_replayed": int(sum(1 for q in history if q[0] == "update")),
+                  "records_replayed": recs, "oracle_build_s": build_o, "oracle_replay_s": time.time() - t,
+                  "method": "the whole request stream (warm-up, saturation and every load level) replayed on the "
+                            "oracle in submission order; each checked query (a sample at 80 % load) run at its "
+                            "version and its served paths compared word for word"}
+        log("serving: parity on %d served queries (%d walks) after %d replayed updates: %s" %
+            (len(checked), walks_checked, parity["updates_replayed"], equal))
     res = common_fields(args, mid["sustained_walk_steps_per_s"], "walk-steps/s",
                         mid["makespan_s"] * 1e3 / max(mid["requests"], 1),
                         {"workload": "rmat25-ef16-zipf1.5-serving-4to1-queries-updates", "vertices": n, "edges": m,
@@ -627,6 +714,7 @@ def workload_serving(args):
                          "update_records": "log-uniform [1, 1e4]", "max_inflight": 8,
                          "max_batch": args.serve_batch})
     res.update({"p99_query_latency_ms": mid["query_p99_ms"], "saturation": sat, "loads": loads, "build_s": build_s,
+                "parity": parity,
                 "note": "value: sustained walk-steps/s at 80 % of the measured saturation rate; ms_per_step is "
                         "makespan per request at that load"})
     return res

@@ -423,122 +423,364 @@ __global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restr
 // S(u) rebuild (Sec. 5.1 sparse groups): after an update, S(u) = the ascending
 // neighbor indices i < d whose membership word meets the sparse mask, written
 // into the vertex's S(u) block; then every sparse group's index over S(u):
-// entry s = the position of S[s] in the group's list.  One block per vertex.
-// Pass 1 ranks the flagged entries of each tile of SR_TB * SR_TPT indices by
-// ballots (rows of SR_TB consecutive indices, waves in order); pass 2 finds
-// each list member's position in S(u) by a search that starts in LDS samples
-// of S(u) (every 2^sh-th entry) and ends with at most sh steps in global memory.
+// entry s = the position of S[s] in the group's list.  k_sr_compact gathers the
+// flagged vertices, so every one of them gets a block of its own (a batch on a
+// few hubs would otherwise rebuild them one after another); k_srebuild runs
+// one block per vertex.  Pass 1 ranks the flagged entries of each tile of
+// SR_TB * SR_TPT indices by ballots (rows of SR_TB consecutive indices, waves
+// in order); pass 2 finds each list member's position in S(u) by a search
+// that starts in LDS samples of S(u) (every 2^sh-th entry) and ends with at
+// most sh steps in global memory.
 // ---------------------------------------------------------------------------
-constexpr int SR_TB = 256;
-constexpr uint32_t SR_TPT = 4;
-constexpr uint32_t SR_XL = 4096;
+constexpr int SR_TB = 1024;
+constexpr uint32_t SR_TPT = 16;     // adjacency words in flight per thread in pass 1
+constexpr uint32_t SR_XL = 16384;   // LDS samples of S(u) (64 KB)
+constexpr uint32_t SR_ILV = 4;      // list members searched together per thread in pass 2
+constexpr uint32_t SR_LIST0 = 64;
+// Vertices of more than SR_BIG edges are split into chunks of SR_CHUNK adjacency
+// entries, each handled by a block of its own.  Work buffer (u32): [0] small
+// vertices, [1] large vertices, [2] chunks; the small list at SR_LIST0; the large
+// list (vertex, first chunk, chunks) after it; then the chunk owners and counts.
+constexpr uint32_t SR_BIG = 1u << 15;
+constexpr uint32_t SR_CHUNK = 1u << 14;
+constexpr uint32_t SR_NO_OWNER = 0xFFFFFFFFu;
+__host__ __device__ inline uint64_t sr_chunk_cap(uint64_t mc) { return 4 * mc + 65536; }
+__host__ __device__ inline uint64_t sr_big_off(uint64_t mc) { return SR_LIST0 + mc; }
+__host__ __device__ inline uint64_t sr_owner_off(uint64_t mc) { return sr_big_off(mc) + 3 * mc; }
+__host__ __device__ inline uint64_t sr_cnt_off(uint64_t mc) { return sr_owner_off(mc) + sr_chunk_cap(mc); }
+
+__global__ void k_sr_zero(uint32_t* __restrict__ work) {
+    if (threadIdx.x < 3) work[threadIdx.x] = 0;
+}
+
+__global__ void k_sr_compact(uint32_t n, const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ list,
+                             const unsigned long long* __restrict__ dcount, uint64_t maxc,
+                             const uint32_t* __restrict__ dirty, uint32_t* __restrict__ work) {
+    const uint64_t total = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        if (dirty && !dirty[it]) continue;
+        const uint32_t u = list ? list[it] : (uint32_t)it;
+        if (u >= n) continue;
+        const uint32_t d = hdr[(size_t)u * HDR_WORDS + H_DEG];
+        bool small = d <= SR_BIG;
+        if (!small) {
+            const uint32_t nch = (d + SR_CHUNK - 1) / SR_CHUNK;
+            const uint32_t cb = atomicAdd(work + 2, nch);
+            if ((uint64_t)cb + nch <= sr_chunk_cap(maxc)) {
+                const uint32_t b = atomicAdd(work + 1, 1u);
+                uint32_t* e = work + sr_big_off(maxc) + 3ull * b;
+                e[0] = u; e[1] = cb; e[2] = nch;
+                for (uint32_t j = 0; j < nch; ++j) work[sr_owner_off(maxc) + cb + j] = b;
+            } else {
+                // no room in the chunk table: one block does it; the reserved ids below the
+                // table's end get no owner
+                for (uint64_t q = cb; q < (uint64_t)cb + nch && q < sr_chunk_cap(maxc); ++q)
+                    work[sr_owner_off(maxc) + q] = SR_NO_OWNER;
+                small = true;
+            }
+        }
+        if (small) work[SR_LIST0 + atomicAdd(work, 1u)] = u;
+    }
+}
+
+// The sparse mask of vertex u and, in LDS, each group's count, list block and
+// capacity (wave 0 of the block; the caller synchronizes).
+__device__ __forceinline__ void sr_groups(const uint32_t* __restrict__ h, uint32_t d, GroupRule rule,
+                                          uint32_t* g_c, uint32_t* g_info, uint32_t* g_lcap, uint32_t* s_smask) {
+    const uint32_t lane = lane_id();
+    const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
+    const bool ne = lane < 32 && ((mask >> lane) & 1u);
+    const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), onem, lane) : 0u;
+    const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+    const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+    if (lane < 32) {
+        g_c[lane] = c;
+        g_info[lane] = h[H_INFO + lane];
+        g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
+    }
+    if (lane == 0) *s_smask = sm;
+}
+
+constexpr int SRC_TB = 256;       // blocks of the chunked kernels
+constexpr uint32_t SRC_ROWS = 8;  // rows of SRC_TB adjacency words per step (loads in flight)
+
+// Large vertices, pass 1: the members of S(u) in each chunk.
+__global__ void __launch_bounds__(SRC_TB) k_sr_count(const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                                                     GroupRule rule, uint64_t maxc, uint32_t* __restrict__ work) {
+    __shared__ uint32_t red[SRC_TB / 64];
+    const uint32_t nchunks = min(work[2], (uint32_t)sr_chunk_cap(maxc));
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t b = work[sr_owner_off(maxc) + c];
+        if (b == SR_NO_OWNER) continue;
+        const uint32_t* e = work + sr_big_off(maxc) + 3ull * b;
+        const uint32_t u = e[0], j = c - e[1];
+        const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        // sparse mask from the final header (every lane of a wave computes it)
+        const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK], hi = hdr_hi(h);
+        const bool ne = lane < 32 && ((mask >> lane) & 1u);
+        const uint32_t cc = ne ? slot_count(hdr_slot(h, lane, hi), onem, lane) : 0u;
+        const uint32_t smask = (uint32_t)(__ballot(ne && group_type(cc, d, rule) == GT_SPARSE) & 0xFFFFFFFFull);
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + hdr_adj(h));
+        const uint32_t i0 = j * SR_CHUNK, i1 = min(i0 + SR_CHUNK, d);
+        uint32_t cnt = 0;
+        for (uint32_t r0 = i0; r0 < i1; r0 += SRC_TB * SRC_ROWS) {
+            uint64_t x[SRC_ROWS];
+#pragma unroll
+            for (uint32_t q = 0; q < SRC_ROWS; ++q) {
+                const uint32_t i = r0 + q * SRC_TB + threadIdx.x;
+                x[q] = i < i1 ? edges[i] : 0ull;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < SRC_ROWS; ++q)
+                cnt += (member_word((uint32_t)(x[q] >> 32), rule.fbits) & smask) != 0u;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        __syncthreads();
+        if (lane == 0) red[wave] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) work[sr_cnt_off(maxc) + c] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// Large vertices, pass 2: each chunk writes its members at the chunk's offset in
+// S(u) (the counts of the vertex's earlier chunks), in index order (rows of
+// SRC_TB consecutive indices ranked by ballots); the last chunk sets |S(u)|.
+__global__ void __launch_bounds__(SRC_TB) k_sr_write(uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                                     GroupRule rule, uint64_t maxc, const uint32_t* __restrict__ work) {
+    __shared__ uint32_t wc[SRC_ROWS][SRC_TB / 64], s_base;
+    const uint32_t nchunks = min(work[2], (uint32_t)sr_chunk_cap(maxc));
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t b = work[sr_owner_off(maxc) + c];
+        if (b == SR_NO_OWNER) continue;
+        const uint32_t* e = work + sr_big_off(maxc) + 3ull * b;
+        const uint32_t u = e[0], cb = e[1], nch = e[2], j = c - cb;
+        uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK], hi = hdr_hi(h);
+        const bool ne = lane < 32 && ((mask >> lane) & 1u);
+        const uint32_t cc = ne ? slot_count(hdr_slot(h, lane, hi), onem, lane) : 0u;
+        const uint32_t smask = (uint32_t)(__ballot(ne && group_type(cc, d, rule) == GT_SPARSE) & 0xFFFFFFFFull);
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t x = 0;
+            for (uint32_t q = lane; q < j; q += 64) x += work[sr_cnt_off(maxc) + cb + q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) s_base = x;
+        }
+        __syncthreads();
+        uint32_t base = s_base;
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + hdr_adj(h));
+        uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+        const uint32_t i0 = j * SR_CHUNK, i1 = min(i0 + SR_CHUNK, d);
+        for (uint32_t r0 = i0; r0 < i1; r0 += SRC_TB * SRC_ROWS) {
+            uint64_t x[SRC_ROWS];
+#pragma unroll
+            for (uint32_t q = 0; q < SRC_ROWS; ++q) {
+                const uint32_t i = r0 + q * SRC_TB + threadIdx.x;
+                x[q] = i < i1 ? edges[i] : 0ull;
+            }
+            uint64_t bal[SRC_ROWS];
+#pragma unroll
+            for (uint32_t q = 0; q < SRC_ROWS; ++q) {
+                const uint32_t i = r0 + q * SRC_TB + threadIdx.x;
+                bal[q] = __ballot(i < i1 && (member_word((uint32_t)(x[q] >> 32), rule.fbits) & smask) != 0u);
+                if (lane == 0) wc[q][wave] = (uint32_t)__popcll(bal[q]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t q = 0; q < SRC_ROWS; ++q) {
+                uint32_t rk = base + (uint32_t)__popcll(bal[q] & lanemask_lt());
+                for (uint32_t w = 0; w < wave; ++w) rk += wc[q][w];
+                if ((bal[q] >> lane) & 1ull) S[rk] = r0 + q * SRC_TB + threadIdx.x;
+                base += wc[q][0] + wc[q][1] + wc[q][2] + wc[q][3];
+            }
+            __syncthreads();  // wc is rewritten by the next step
+        }
+        if (j == nch - 1 && threadIdx.x == 0) h[H_SLEN] = base;
+    }
+}
+
+// Large vertices, pass 3: chunk j of a vertex with nch chunks fills the index entries of the
+// members in [c_k j / nch, c_k (j + 1) / nch) of every sparse group k (LDS samples of S(u), then
+// at most sh steps in global memory per member).
+constexpr uint32_t SRI_XL = 4096;  // LDS samples of S(u) per chunk block (16 KB)
+__global__ void __launch_bounds__(SRC_TB) k_sr_index(const uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                                     GroupRule rule, uint64_t maxc, const uint32_t* __restrict__ work) {
+    __shared__ uint32_t smp[SRI_XL];
+    __shared__ uint32_t g_c[32], g_info[32], g_lcap[32], s_smask;
+    const uint32_t nchunks = min(work[2], (uint32_t)sr_chunk_cap(maxc));
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t b = work[sr_owner_off(maxc) + c];
+        if (b == SR_NO_OWNER) continue;
+        const uint32_t* e = work + sr_big_off(maxc) + 3ull * b;
+        const uint32_t u = e[0], nch = e[2], j = c - e[1];
+        const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        __syncthreads();  // the previous chunk is done with the shared arrays
+        if ((tid >> 6) == 0) sr_groups(h, d, rule, g_c, g_info, g_lcap, &s_smask);
+        const uint32_t sfill = h[H_SLEN];
+        const uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+        uint32_t sh = 0;
+        while ((sfill >> sh) >= SRI_XL) ++sh;
+        const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
+        for (uint32_t q = tid; q < nl; q += SRC_TB) smp[q] = S[(uint64_t)q << sh];
+        __syncthreads();
+        for (uint32_t mm = s_smask; mm; mm &= mm - 1) {
+            const int k = __ffs(mm) - 1;
+            const uint32_t ck = g_c[k];
+            uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
+            uint32_t* I = L + g_lcap[k];
+            const uint32_t p0 = (uint32_t)((uint64_t)ck * j / nch), p1 = (uint32_t)((uint64_t)ck * (j + 1) / nch);
+            // SR_ILV members per thread at a time, their global search steps interleaved
+            for (uint32_t pb = p0 + tid; pb < p1; pb += SRC_TB * SR_ILV) {
+                uint32_t v[SR_ILV], a[SR_ILV], bb[SR_ILV];
+#pragma unroll
+                for (uint32_t x = 0; x < SR_ILV; ++x) {
+                    const uint32_t p = pb + x * SRC_TB;
+                    v[x] = p < p1 ? L[p] : 0u;
+                }
+#pragma unroll
+                for (uint32_t x = 0; x < SR_ILV; ++x) {
+                    uint32_t lo = 0, hi = nl;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (smp[mid] < v[x]) lo = mid + 1; else hi = mid;
+                    }
+                    a[x] = lo > 0 ? ((lo - 1) << sh) + 1 : 0u;
+                    bb[x] = lo > 0 ? min(lo << sh, sfill) : 0u;
+                }
+                for (uint32_t step = 0; step <= sh; ++step) {
+#pragma unroll
+                    for (uint32_t x = 0; x < SR_ILV; ++x) {
+                        if (a[x] < bb[x]) {
+                            const uint32_t mid = (a[x] + bb[x]) >> 1;
+                            if (S[mid] < v[x]) a[x] = mid + 1; else bb[x] = mid;
+                        }
+                    }
+                }
+#pragma unroll
+                for (uint32_t x = 0; x < SR_ILV; ++x) {
+                    const uint32_t p = pb + x * SRC_TB;
+                    if (p < p1) I[a[x]] = p;
+                }
+            }
+        }
+    }
+}
 
 __global__ void __launch_bounds__(SR_TB) k_srebuild(uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
-                                                    uint32_t n, GroupRule rule, const uint32_t* __restrict__ list,
-                                                    const unsigned long long* __restrict__ dcount, uint64_t maxc,
-                                                    const uint32_t* __restrict__ dirty) {
+                                                    GroupRule rule, const uint32_t* __restrict__ work) {
     __shared__ uint32_t smp[SR_XL];
     __shared__ uint32_t g_c[32], g_info[32], g_lcap[32];
     __shared__ uint32_t wcnt[SR_TPT][SR_TB / 64];
     __shared__ uint32_t s_smask;
-    __shared__ uint32_t todo[SR_TB], ntodo;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    const uint64_t total = dcount ? std::min<uint64_t>(*dcount, maxc) : maxc;
-    // the flags of SR_TB list entries at a time; the flagged vertices one after another
-    for (uint64_t c0 = (uint64_t)blockIdx.x * SR_TB; c0 < total; c0 += (uint64_t)gridDim.x * SR_TB) {
-        __syncthreads();  // the previous chunk is done with todo
-        if (tid == 0) ntodo = 0;
-        __syncthreads();
-        {
-            const uint64_t it = c0 + tid;
-            if (it < total && (!dirty || dirty[it])) {
-                const uint32_t u = list ? list[it] : (uint32_t)it;
-                if (u < n) todo[atomicAdd(&ntodo, 1u)] = u;
+    const uint32_t nt = work[0];
+    for (uint32_t q = blockIdx.x; q < nt; q += gridDim.x) {
+        const uint32_t u = work[SR_LIST0 + q];
+        uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        __syncthreads();  // the previous vertex is done with the shared arrays
+        if (wave == 0) {
+            const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
+            const bool ne = lane < 32 && ((mask >> lane) & 1u);
+            const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), onem, lane) : 0u;
+            const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+            const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+            if (lane < 32) {
+                g_c[lane] = c;
+                g_info[lane] = h[H_INFO + lane];
+                g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
             }
+            if (lane == 0) s_smask = sm;
         }
         __syncthreads();
-        const uint32_t nt = ntodo;
-        for (uint32_t q = 0; q < nt; ++q) {
-            const uint32_t u = todo[q];
-            uint32_t* h = hdr + (size_t)u * HDR_WORDS;
-            const uint32_t d = h[H_DEG];
-            __syncthreads();  // the previous vertex is done with the shared arrays
-            if (wave == 0) {
-                const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
-                const bool ne = lane < 32 && ((mask >> lane) & 1u);
-                const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), onem, lane) : 0u;
-                const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
-                const uint32_t sm = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
-                if (lane < 32) {
-                    g_c[lane] = c;
-                    g_info[lane] = h[H_INFO + lane];
-                    g_lcap[lane] = 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu);
-                }
-                if (lane == 0) s_smask = sm;
+        const uint32_t smask = s_smask;
+        if (!smask) {
+            if (tid == 0) h[H_SLEN] = 0;
+            continue;
+        }
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + hdr_adj(h));
+        uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+        uint32_t sfill = 0;
+        for (uint32_t q0 = 0; q0 < d; q0 += SR_TB * SR_TPT) {
+            uint64_t bal[SR_TPT];
+            bool in[SR_TPT];
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                const uint32_t i = q0 + j * SR_TB + tid;
+                in[j] = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask) != 0u;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                bal[j] = __ballot(in[j]);
+                if (lane == 0) wcnt[j][wave] = (uint32_t)__popcll(bal[j]);
             }
             __syncthreads();
-            const uint32_t smask = s_smask;
-            if (!smask) {
-                if (tid == 0) h[H_SLEN] = 0;
-                continue;
+#pragma unroll
+            for (uint32_t j = 0; j < SR_TPT; ++j) {
+                uint32_t rk = sfill + (uint32_t)__popcll(bal[j] & lanemask_lt()), row = 0;
+                for (uint32_t w = 0; w < SR_TB / 64; ++w) {
+                    const uint32_t x = wcnt[j][w];
+                    if (w < wave) rk += x;
+                    row += x;
+                }
+                if (in[j]) S[rk] = q0 + j * SR_TB + tid;
+                sfill += row;
             }
-            const uint64_t adj = hdr_adj(h);
-            const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + adj);
-            uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
-            uint32_t sfill = 0;
-            for (uint32_t q0 = 0; q0 < d; q0 += SR_TB * SR_TPT) {
-                uint64_t bal[SR_TPT];
-                bool in[SR_TPT];
-    #pragma unroll
-                for (uint32_t j = 0; j < SR_TPT; ++j) {
-                    const uint32_t i = q0 + j * SR_TB + tid;
-                    in[j] = i < d && (member_word((uint32_t)(edges[i] >> 32), rule.fbits) & smask) != 0u;
+            __syncthreads();  // wcnt is rewritten by the next tile
+        }
+        if (tid == 0) h[H_SLEN] = sfill;
+        __threadfence_block();
+        __syncthreads();  // S(u) complete and visible to the block
+        uint32_t sh = 0;
+        while ((sfill >> sh) >= SR_XL) ++sh;
+        const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
+        for (uint32_t j = tid; j < nl; j += SR_TB) smp[j] = S[(uint64_t)j << sh];
+        __syncthreads();
+        for (uint32_t mm = smask; mm; mm &= mm - 1) {
+            const int k = __ffs(mm) - 1;
+            const uint32_t c = g_c[k];
+            uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
+            uint32_t* I = L + g_lcap[k];
+            // SR_ILV members per thread at a time, their global search steps interleaved
+            for (uint32_t p0 = tid; p0 < c; p0 += SR_TB * SR_ILV) {
+                uint32_t v[SR_ILV], a[SR_ILV], b[SR_ILV];
+#pragma unroll
+                for (uint32_t j = 0; j < SR_ILV; ++j) {
+                    const uint32_t p = p0 + j * SR_TB;
+                    v[j] = p < c ? L[p] : 0u;
                 }
-    #pragma unroll
-                for (uint32_t j = 0; j < SR_TPT; ++j) {
-                    bal[j] = __ballot(in[j]);
-                    if (lane == 0) wcnt[j][wave] = (uint32_t)__popcll(bal[j]);
-                }
-                __syncthreads();
-    #pragma unroll
-                for (uint32_t j = 0; j < SR_TPT; ++j) {
-                    uint32_t rk = sfill + (uint32_t)__popcll(bal[j] & lanemask_lt());
-                    for (uint32_t w = 0; w < wave; ++w) rk += wcnt[j][w];
-                    if (in[j]) S[rk] = q0 + j * SR_TB + tid;
-                    sfill += wcnt[j][0] + wcnt[j][1] + wcnt[j][2] + wcnt[j][3];
-                }
-                __syncthreads();  // wcnt is rewritten by the next tile
-            }
-            if (tid == 0) h[H_SLEN] = sfill;
-            __threadfence_block();
-            __syncthreads();  // S(u) complete and visible to the block
-            uint32_t sh = 0;
-            while ((sfill >> sh) >= SR_XL) ++sh;
-            const uint32_t nl = (sfill + (1u << sh) - 1) >> sh;
-            for (uint32_t j = tid; j < nl; j += SR_TB) smp[j] = S[(uint64_t)j << sh];
-            __syncthreads();
-            for (uint32_t mm = smask; mm; mm &= mm - 1) {
-                const int k = __ffs(mm) - 1;
-                const uint32_t c = g_c[k];
-                uint32_t* L = pool + (uint64_t)g_info[k] * LIST_UNIT_WORDS;
-                uint32_t* I = L + g_lcap[k];
-                for (uint32_t p = tid; p < c; p += SR_TB) {
-                    const uint32_t v = L[p];
+#pragma unroll
+                for (uint32_t j = 0; j < SR_ILV; ++j) {
                     uint32_t lo = 0, hi = nl;  // samples below v
                     while (lo < hi) {
                         const uint32_t mid = (lo + hi) >> 1;
-                        if (smp[mid] < v) lo = mid + 1; else hi = mid;
+                        if (smp[mid] < v[j]) lo = mid + 1; else hi = mid;
                     }
-                    uint32_t pos = 0;
-                    if (lo > 0) {
-                        uint32_t a = ((lo - 1) << sh) + 1, b = min(lo << sh, sfill);
-                        while (a < b) {
-                            const uint32_t mid = (a + b) >> 1;
-                            if (S[mid] < v) a = mid + 1; else b = mid;
+                    a[j] = lo > 0 ? ((lo - 1) << sh) + 1 : 0u;
+                    b[j] = lo > 0 ? min(lo << sh, sfill) : 0u;
+                }
+                for (uint32_t step = 0; step <= sh; ++step) {
+#pragma unroll
+                    for (uint32_t j = 0; j < SR_ILV; ++j) {
+                        if (a[j] < b[j]) {
+                            const uint32_t mid = (a[j] + b[j]) >> 1;
+                            if (S[mid] < v[j]) a[j] = mid + 1; else b[j] = mid;
                         }
-                        pos = a;
                     }
-                    I[pos] = p;
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < SR_ILV; ++j) {
+                    const uint32_t p = p0 + j * SR_TB;
+                    if (p < c) I[a[j]] = p;
                 }
             }
         }
@@ -561,11 +803,19 @@ void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* 
 }
 
 void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
-                    const uint32_t* dirty, hipStream_t st) {
+                    const uint32_t* dirty, uint32_t* work, hipStream_t st) {
     if (max_count == 0 || !g->rule.adaptive) return;  // without adaption no group is sparse
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((max_count + SR_TB - 1) / SR_TB, 4096);
-    hipLaunchKernelGGL(k_srebuild, dim3(grid), dim3(SR_TB), 0, st, g->hdr, g->pool, g->n, g->rule, list, count,
-                       max_count, dirty);
+    hipLaunchKernelGGL(k_sr_zero, dim3(1), dim3(64), 0, st, work);
+    hipLaunchKernelGGL(k_sr_compact, dim3(grid_for(max_count, 256)), dim3(256), 0, st, g->n, (const uint32_t*)g->hdr,
+                       list, count, max_count, dirty, work);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(max_count, 2048);
+    hipLaunchKernelGGL(k_srebuild, dim3(grid), dim3(SR_TB), 0, st, g->hdr, g->pool, g->rule, (const uint32_t*)work);
+    hipLaunchKernelGGL(k_sr_count, dim3(2048), dim3(SRC_TB), 0, st, (const uint32_t*)g->hdr, (const uint32_t*)g->pool,
+                       g->rule, max_count, work);
+    hipLaunchKernelGGL(k_sr_write, dim3(2048), dim3(SRC_TB), 0, st, g->hdr, g->pool, g->rule, max_count,
+                       (const uint32_t*)work);
+    hipLaunchKernelGGL(k_sr_index, dim3(2048), dim3(SRC_TB), 0, st, (const uint32_t*)g->hdr, g->pool, g->rule,
+                       max_count, (const uint32_t*)work);
 }
 
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st) {

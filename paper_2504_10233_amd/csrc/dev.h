@@ -394,9 +394,11 @@ void alias_rows(bingo_graph* g, const uint32_t* list, const unsigned long long* 
                 hipStream_t st);
 // S(u) (Sec. 5.1) and every sparse group's index over it, rebuilt for the vertices
 // list[0 .. *count) (list == nullptr: vertices 0 .. *count) whose dirty flag is set
-// (dirty == nullptr: all of them), from the final adjacency, types and lists
+// (dirty == nullptr: all of them), from the final adjacency, types and lists; work
+// holds SPARSE_WORK_WORDS(max_count) u32 of scratch
+#define SPARSE_WORK_WORDS(mc) (64 + 4 * (uint64_t)(mc) + 2 * (4 * (uint64_t)(mc) + 65536))
 void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long long* count, uint64_t max_count,
-                    const uint32_t* dirty, hipStream_t st);
+                    const uint32_t* dirty, uint32_t* work, hipStream_t st);
 int quantize_biases(uint64_t m, const float* b, double lambda, uint32_t F, uint32_t* w, hipStream_t st);
 int build_graph(bingo_graph* g, uint64_t m, const uint32_t* src, const uint32_t* dst, const uint32_t* w,
                 hipStream_t st);

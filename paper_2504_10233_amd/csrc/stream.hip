@@ -636,7 +636,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     if (m > (1ull << 31)) return BINGO_E_INVALID;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const size_t tmpb = std::max(sort_temp_bytes(m, false), scan_temp_bytes(m));
-    const size_t bytes = al(m * 4) * 8 + al(m * 8) + al(ST_CTRS * 8) + 256 + tmpb;
+    const size_t bytes = al(m * 4) * 8 + al(m * 8) + al(SPARSE_WORK_WORDS(m) * 4) + al(ST_CTRS * 8) + 256 + tmpb;
     char* ws = (char*)ws_get(g, bytes);
     if (!ws) return BINGO_E_OOM;
     auto take = [&](uint64_t b) { char* r = ws; ws += al(b); return r; };
@@ -648,6 +648,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     uint32_t* seg_src = (uint32_t*)take(m * 4);
     uint32_t* left = (uint32_t*)take(m * 4);
     uint32_t* sdirty = (uint32_t*)take(m * 4);  // per source segment: S(u) to rebuild
+    uint32_t* srwork = (uint32_t*)take(SPARSE_WORK_WORDS(m) * 4);
     uint64_t* hx = (uint64_t*)take(m * 8);
     unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
     unsigned long long* nseg = (unsigned long long*)take(256);
@@ -668,7 +669,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
                        (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
                        g->pool_words, g->rule, g->d_err, out, left, sdirty);
     // S(u) and the sparse indexes of the sources whose records touched a vertex with sparse groups
-    sparse_rebuild(g, seg_src, nseg, m, sdirty, st);
+    sparse_rebuild(g, seg_src, nseg, m, sdirty, srwork, st);
     // alias-table mode: the sources' inter-group tables (with bad records nothing changed: rewritten as they were)
     alias_rows(g, seg_src, nseg, m, st);
     phase_mark(g, st, false);

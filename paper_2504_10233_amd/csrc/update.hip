@@ -775,7 +775,7 @@ __device__ __forceinline__ uint32_t xv_rho(const XView& x, uint32_t v, uint32_t 
 //   k_big_holes : per pass-A item of the first kind, its holes sorted by
 //                 position take the tail survivors in order
 // ---------------------------------------------------------------------------
-enum { BK_COPY = 1, BK_PASSA = 2, BK_FRESH = 3, BK_ONE = 4, BK_PASSH = 5 };
+enum { BK_COPY = 1, BK_PASSA = 2, BK_FRESH = 3, BK_ONE = 4, BK_PASSH = 5, BK_HOLES = 6 };
 constexpr uint32_t BIG_HOLES = 4096;
 constexpr uint32_t BIG_NONE = 0xFFFFFFFFu;
 constexpr uint32_t BIG_MIN_CHUNK = 2048;
@@ -1070,6 +1070,55 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
             unsigned long long soff = 0;
             if (lane == 0) soff = atomicAdd(uc + UC_BIG_SUR, (unsigned long long)words);
             soff = __shfl(soff, 0, 64);
+            // A regular group whose block stays finds its holes and renamed entries through its
+            // inverted index (Sec. 4.2): O(deleted + moved entries) instead of a pass over the list.
+            const bool by_index = iofs != 0 && nblk == oblk && listed;
+            if (by_index) {
+                unsigned long long it64 = 0;
+                if (lane == 0) it64 = atomicAdd(uc + UC_BIG_ITEMS, 1ull);
+                it64 = __shfl(it64, 0, 64);
+                defer = soff + words <= bc.smax && it64 < bc.imax;
+                if (!defer && it64 < bc.imax && lane == 0) bc.items[it64].kind = 0;  // a slot k_big_holes skips
+                if (defer) {
+                    for (uint32_t i = lane; i < nsur; i += 64) bc.sur[soff + i] = S[i];
+                    uint32_t* H = bc.sur + soff + nsur;
+                    const uint32_t* Iold = Lold + iofs;
+                    // holes: the positions below cnk of deleted old members (a deleted member in the
+                    // tail window leaves no hole)
+                    uint32_t nhf = 0;
+                    for (uint32_t j0 = 0; j0 < N; j0 += 64) {
+                        const uint32_t j = j0 + lane;
+                        // membership by the index's own check (a member's entry is its position, the list
+                        // holds it there): the adjacency slot of a deleted edge may already hold a survivor
+                        const uint32_t x = j < N ? xv_at(xv, j) : NF;
+                        const uint32_t pos = x < s.d ? Iold[x] : NF;
+                        const bool hole = pos < ck && Lold[pos] == x && pos < cnk;
+                        const uint64_t hb = __ballot(hole);
+                        if (hole) H[nhf + __popcll(hb & lanemask_lt())] = pos;
+                        nhf += __popcll(hb);
+                    }
+                    __threadfence_block();
+                    // renames: the survivors the adjacency moved from its tail [dn, d) into its holes
+                    for (uint32_t q = s.dn + lane; q < s.d; q += 64) {
+                        const uint32_t dest = xv_rho(xv, q, s.dn, nholes);
+                        if (dest != NF) {
+                            const uint32_t pos = Iold[q];
+                            if (pos < cnk && Lold[pos] == q) {
+                                Lnew[pos] = dest;
+                                Lnew[iofs + dest] = pos;
+                            }
+                        }
+                    }
+                    if (lane == 0) {
+                        BigItem& bi = bc.items[it64];
+                        bi.kind = BK_HOLES; bi.k = (uint32_t)k; bi.n = 0; bi.csize = 0; bi.cbase = 0; bi.u = s.u;
+                        bi.xoff = s.xoff; bi.N = N; bi.dn = s.dn; bi.nholes = nholes; bi.keep = keep; bi.reloc = 0;
+                        bi.sur = (uint32_t)soff; bi.hole = (uint32_t)(soff + nsur); bi.ocap = 0; bi.ncap = 0;
+                        bi.a = oblk; bi.b = nblk; bi.aold = 0; bi.nh = nha; bi.iofs = iofs; bi.hcnt = nhf;
+                    }
+                    nh = nha;
+                }
+            } else {
             defer = soff + words <= bc.smax && big_reserve(bc, uc, oldpart, it, cb, cs);
             if (defer) {
                 for (uint32_t i = lane; i < nsur; i += 64) bc.sur[soff + i] = S[i];
@@ -1082,6 +1131,7 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
                     bi.aold = 0; bi.nh = nha; bi.iofs = iofs; bi.hcnt = 0;
                 }
                 nh = nha;
+            }
             }
         }
         if (!defer) {
@@ -1542,7 +1592,8 @@ __global__ void __launch_bounds__(256) k_big_pass(const unsigned long long* __re
     }
 }
 
-// Split work, the holes of BK_PASSH lists: one block per item sorts the hole
+// Split work, the holes of BK_PASSH lists (collected by k_big_pass) and of BK_HOLES
+// lists (found by k_mutate through the inverted index): one block per item sorts the hole
 // positions (at most BIG_HOLES) in LDS; the i-th hole takes tail survivor i.
 __global__ void __launch_bounds__(256) k_big_holes(const unsigned long long* __restrict__ uc, BigCtx bc,
                                                    uint32_t* __restrict__ pool) {
@@ -1550,7 +1601,7 @@ __global__ void __launch_bounds__(256) k_big_holes(const unsigned long long* __r
     const uint64_t nitems = std::min<uint64_t>(uc[UC_BIG_ITEMS], bc.imax);
     for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BigItem& bi = bc.items[it];
-        if (bi.kind != BK_PASSH) continue;
+        if (bi.kind != BK_PASSH && bi.kind != BK_HOLES) continue;
         const uint32_t nh = (uint32_t)std::min<unsigned long long>(bi.nh, bi.hcnt);
         if (nh == 0) continue;
         uint32_t P = 1;
@@ -1627,6 +1678,7 @@ struct UpdPlan {
     uint32_t *vals, *sv, *head, *rec_t, *tv, *tsa, *tdl, *te, *cval, *cvs, *first, *matched, *xs, *sur, *ncnt, *dold, *wv, *idest, *blist;
     uint32_t *vacap, *vnseq;  // header fields of the touched vertices before the batch (k_flat_size)
     uint32_t* sdirty;         // per touched vertex: S(u) to rebuild after the mutation
+    uint32_t* srwork;         // scratch of the S(u) rebuild
     uint64_t* vadj;
     unsigned long long* parts;
     BigItem* big_items;
@@ -1681,7 +1733,7 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
                                  scan_temp_bytes(R + 1));
     const size_t bytes = al(R * 4) * 5 + al(UC_WORDS * 8) + al(R * 8) * 11 + al(C * 8) * 2 + al(R * 4) * 19 +
                          al(R * 8) + al(C * 4) * 2 + al(PART_BLOCKS * 32 * 8) + al(BIG_IMAX * sizeof(BigItem)) +
-                         2 * al(BIG_CMAX * 4) + al(big_smax(R) * 4) + tmpb + 4096;
+                         2 * al(BIG_CMAX * 4) + al(big_smax(R) * 4) + al(SPARSE_WORK_WORDS(R) * 4) + tmpb + 4096;
     UpdPlan* p = new UpdPlan();
     p->rmax = R;
     p->cmax = C;
@@ -1710,6 +1762,7 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->vacap = (uint32_t*)take(R * 4);
     p->vnseq = (uint32_t*)take(R * 4);
     p->sdirty = (uint32_t*)take(R * 4);
+    p->srwork = (uint32_t*)take(SPARSE_WORK_WORDS(R) * 4);
     p->vadj = (uint64_t*)take(R * 8);
     p->sur = (uint32_t*)take(R * 8);
     p->cval = (uint32_t*)take(C * 4); p->cvs = (uint32_t*)take(C * 4);
@@ -1813,7 +1866,7 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     }
     hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, g->d_ctl + 1, (const unsigned long long*)(uc + UC_FREED));
     // S(u) and the sparse groups' indexes of the vertices whose reduced list may have changed
-    sparse_rebuild(g, p->tv, uc + UC_T, R, p->sdirty, st);
+    sparse_rebuild(g, p->tv, uc + UC_T, R, p->sdirty, p->srwork, st);
     // alias-table mode: the touched vertices' inter-group tables (a rejected batch rewrites them unchanged)
     alias_rows(g, p->tv, uc + UC_T, R, st);
 }
