@@ -656,22 +656,20 @@ def workload_serving(args):
     serve_requests(g, warm, 0, max_batch=args.serve_batch)
     history += warm
     sreqs = make_requests(rng, max(500, nreq // 4), n, src, dst, 5, 4, 1 << 20)
-    sat = serve_requests(g, sreqs, 0, max_batch=args.serve_batch)
+    # a sample of the served queries of the saturation run (every request submitted at once, so the
+    # most queries and updates in flight together) is checked against the oracle
+    walks = [i for i, q in enumerate(sreqs) if q[0] == "walk"]
+    keep = walks[:: max(1, len(walks) // 24)][:24]
+    sat = serve_requests(g, sreqs, 0, max_batch=args.serve_batch, keep=keep)
+    checked = {len(history) + i: paths for i, paths in sat.pop("kept").items()}
     history += sreqs
-    sat.pop("kept")
     rate_sat = sat["achieved_rate_per_s"]
     log("serving R-MAT 25: saturation %.0f requests/s, %.3g walk steps/s" % (rate_sat, sat["sustained_walk_steps_per_s"]))
     loads = {}
-    checked = {}  # history index -> served paths
     for frac in (0.5, 0.8, 0.95):
         reqs = make_requests(rng, nreq, n, src, dst, 5, 4, 1 << 20)
-        # a sample of the served queries at 80 % load is checked against the oracle
-        walks = [i for i, q in enumerate(reqs) if q[0] == "walk"]
-        keep = walks[:: max(1, len(walks) // 24)][:24] if frac == 0.8 else []
-        r = serve_requests(g, reqs, frac * rate_sat, max_batch=args.serve_batch, keep=keep)
-        for i, paths in r.pop("kept").items():
-            checked[len(history) + i] = paths
-        history += reqs
+        r = serve_requests(g, reqs, frac * rate_sat, max_batch=args.serve_batch)
+        r.pop("kept")
         loads["%d%%" % int(frac * 100)] = r
         log("serving at %d%% load: query p50 %.2f ms p99 %.2f ms, update p50 %.2f ms p99 %.2f ms, %.3g steps/s" %
             (frac * 100, r["query_p50_ms"], r["query_p99_ms"], r["update_p50_ms"] or -1, r["update_p99_ms"] or -1,
@@ -684,12 +682,13 @@ def workload_serving(args):
         log("serving: oracle: building on the host (%d edges)" % m)
         og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w_host)
         build_o = time.time() - t
-        log("serving: oracle: built in %.1fs; replaying %d requests" % (build_o, len(history)))
+        last = max(checked)
+        log("serving: oracle: built in %.1fs; replaying %d requests" % (build_o, last + 1))
         equal, walks_checked, steps_checked, recs = True, 0, 0, 0
         t = time.time()
-        for i, q in enumerate(history):
-            if i % 2000 == 0:
-                log("serving: oracle: request %d of %d" % (i, len(history)))
+        for i, q in enumerate(history[:last + 1]):
+            if i % 250 == 0:
+                log("serving: oracle: request %d of %d" % (i, last + 1))
             if q[0] == "update":
                 st = og.update(*q[1:])
                 recs += st["inserted"] + st["deleted"] + st["not_found"]
@@ -700,11 +699,12 @@ def workload_serving(args):
                 walks_checked += int(q[1].size)
                 steps_checked += osteps
         parity = {"queries_checked": len(checked), "walks_checked": walks_checked, "steps_checked": steps_checked,
-                  "paths_equal": equal, "updates_replayed": int(sum(1 for q in history if q[0] == "update")),
+                  "paths_equal": equal, "updates_replayed": int(sum(1 for q in history[:last + 1] if q[0] == "update")),
                   "records_replayed": recs, "oracle_build_s": build_o, "oracle_replay_s": time.time() - t,
-                  "method": "the whole request stream (warm-up, saturation and every load level) replayed on the "
-                            "oracle in submission order; each checked query (a sample at 80 % load) run at its "
-                            "version and its served paths compared word for word"}
+                  "method": "the request stream (warm-up, then the saturation run with every request submitted "
+                            "at once) replayed on the oracle in submission order up to the last checked query; "
+                            "each checked query (a sample of the saturation run) run at its version and its "
+                            "served paths compared word for word"}
         log("serving: parity on %d served queries (%d walks) after %d replayed updates: %s" %
             (len(checked), walks_checked, parity["updates_replayed"], equal))
     res = common_fields(args, mid["sustained_walk_steps_per_s"], "walk-steps/s",
