@@ -1,7 +1,8 @@
 // prim.hip -- device-wide exclusive scan and stable LSD radix sort (8-bit
 // digits) for gfx950.  Digit ranks inside a wave come from eight ballots that
 // isolate the lanes sharing a digit (wave64 match), then a popcount of the
-// lower lanes; per-wave digit counts are combined through LDS.
+// lower lanes; per-wave digit counts are combined through LDS.  Sorts of at
+// most 4096 entries run as one bitonic block in LDS instead.
 #include "dev.h"
 #include <stdio.h>
 
@@ -174,6 +175,53 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_scatter(const K* __restric
     }
 }
 
+// Small sorts (capacity up to BSORT_MAX) in one block: a bitonic network in LDS
+// over (the key's digits the LSD passes would look at, input position), which
+// orders exactly as the stable LSD sort does, replacing its 3 to 5 launches per
+// 8-bit pass.
+constexpr uint32_t BSORT_MAX = 4096;
+constexpr int BSORT_BLOCK = 1024;
+
+template <typename K, bool HAS_V>
+__global__ void __launch_bounds__(BSORT_BLOCK) k_block_sort(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                            K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                            uint32_t n, const unsigned long long* __restrict__ dn,
+                                                            K mask) {
+    __shared__ K sk[BSORT_MAX];
+    __shared__ uint32_t si[BSORT_MAX];
+    const uint32_t m = dn ? (uint32_t)std::min<uint64_t>(n, *dn) : n;
+    if (m == 0) return;
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += BSORT_BLOCK) {
+        // padding sorts after every entry: the largest masked key, then the largest position
+        sk[i] = i < m ? (K)(kin[i] & mask) : mask;
+        si[i] = i < m ? i : ~0u;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = threadIdx.x; q < (P >> 1); q += BSORT_BLOCK) {
+                const uint32_t a = 2 * j * (q / j) + (q % j), b = a + j;
+                const bool up = (a & k) == 0;
+                const K ka = sk[a], kb = sk[b];
+                const uint32_t ia = si[a], ib = si[b];
+                const bool gt = ka > kb || (ka == kb && ia > ib);
+                if (gt == up) {
+                    sk[a] = kb; sk[b] = ka;
+                    si[a] = ib; si[b] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < m; i += BSORT_BLOCK) {
+        const uint32_t src = si[i];
+        kout[i] = kin[src];
+        if (HAS_V) vout[i] = vin[src];
+    }
+}
+
 // Stable LSD sort of the first min(n, *dn) entries (all n when dn is null);
 // grids are sized by n, so a device-side count keeps the launch sequence fixed.
 template <typename K, bool HAS_V>
@@ -191,6 +239,13 @@ void sort_impl(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint6
     if (passes == 0) {
         hipMemcpyAsync(kout, kin, n * sizeof(K), hipMemcpyDeviceToDevice, st);
         if (HAS_V) hipMemcpyAsync(vout, vin, n * 4, hipMemcpyDeviceToDevice, st);
+        return;
+    }
+    if (n <= BSORT_MAX) {
+        const int pb = 8 * passes;  // the LSD passes look at whole digits
+        const K mask = pb >= (int)(8 * sizeof(K)) ? (K)~(K)0 : (K)(((K)1 << pb) - 1);
+        hipLaunchKernelGGL((k_block_sort<K, HAS_V>), dim3(1), dim3(BSORT_BLOCK), 0, st, kin, vin, kout, vout,
+                           (uint32_t)n, dn, mask);
         return;
     }
     const K* ck = kin;

@@ -311,34 +311,58 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
             }
             held = tlo == thi ? tlo : ~0u;
             __syncthreads();
-            // each thread looks at PER elements; hits stay in registers until the
-            // block has placed them in the LDS buffer
+            // each thread looks at PER elements, in phases so that the loads of all
+            // of them are in flight together: its vertex's fields, then every dst,
+            // then the target searches, then the seq of every hit; hits stay in
+            // registers until the block has placed them in the LDS buffer
             uint64_t hkey[PER];
             uint32_t hidx[PER];
             uint32_t nh = 0;
+            uint32_t e_i[PER], e_d[PER], e_acap[PER], e_nseq[PER], e_ts[PER], e_tdl[PER], e_te[PER], e_dst[PER];
+            uint64_t e_adj[PER];
+            bool e_in[PER];
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
                 const uint64_t f = f0 + (uint64_t)r * TB + threadIdx.x;
                 hkey[r] = 0;
                 hidx[r] = 0;
-                if (f < F) {
-                    uint32_t d, acap, nseq, tsv, tdlv, tev;
-                    uint64_t adj, fo;
+                e_in[r] = f < F;
+                e_i[r] = e_d[r] = e_acap[r] = e_nseq[r] = e_ts[r] = e_tdl[r] = e_te[r] = 0;
+                e_adj[r] = 0;
+                if (e_in[r]) {
+                    uint64_t fo;
                     if (vstaged) {
                         const uint32_t k = find_t_lds(s_fo, nv, f);
                         fo = s_fo[k];
-                        d = s_v[0][k]; acap = s_v[1][k]; nseq = s_v[2][k];
-                        adj = ((uint64_t)s_v[4][k] << 32) | s_v[3][k];
-                        tsv = s_v[5][k]; tdlv = s_v[6][k]; tev = s_v[7][k];
+                        e_d[r] = s_v[0][k]; e_acap[r] = s_v[1][k]; e_nseq[r] = s_v[2][k];
+                        e_adj[r] = ((uint64_t)s_v[4][k] << 32) | s_v[3][k];
+                        e_ts[r] = s_v[5][k]; e_tdl[r] = s_v[6][k]; e_te[r] = s_v[7][k];
                     } else {
                         const uint32_t t = find_t(foff, tlo, thi, f);
                         fo = foff[t];
-                        d = vdeg[t]; acap = vacap[t]; nseq = vnseq[t];
-                        adj = vadj[t];
-                        tsv = ts[t]; tdlv = tdl[t]; tev = te[t];
+                        e_d[r] = vdeg[t]; e_acap[r] = vacap[t]; e_nseq[r] = vnseq[t];
+                        e_adj[r] = vadj[t];
+                        e_ts[r] = ts[t]; e_tdl[r] = tdl[t]; e_te[r] = te[t];
                     }
-                    const uint32_t i = (uint32_t)(f - fo);
-                    const uint32_t dst = i < d ? pool[adj + 2ull * i] : id[sv[tsv + (i - d)]];
+                    e_i[r] = (uint32_t)(f - fo);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                e_dst[r] = 0;
+                if (e_in[r] && e_i[r] < e_d[r]) e_dst[r] = pool[e_adj[r] + 2ull * e_i[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < PER; ++r)
+                if (e_in[r] && e_i[r] >= e_d[r]) e_dst[r] = id[sv[e_ts[r] + (e_i[r] - e_d[r])]];
+            uint32_t e_l[PER];
+            bool e_hit[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                e_hit[r] = false;
+                e_l[r] = 0;
+                if (e_in[r]) {
+                    const uint32_t dst = e_dst[r], tdlv = e_tdl[r], tev = e_te[r];
                     // lower bound of dst among the vertex's delete targets [tdlv, tev): first over
                     // the LDS samples at positions rbase + (j << tsh) inside [tdlv, tev), then
                     // over the records between two samples in global memory
@@ -355,13 +379,18 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                         const uint32_t mid = (l + rr) >> 1;
                         if (key_dst(sk[mid], vb) < dst) l = mid + 1; else rr = mid;
                     }
-                    const bool found = l < tev && (tsh == 0 ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
-                    if (found) {
-                        const uint32_t seq = i < d ? pool[adj + 2ull * acap + i] : nseq + (i - d);
-                        hkey[nh] = ((uint64_t)l << 32) | seq;
-                        hidx[nh] = i;
-                        ++nh;
-                    }
+                    e_hit[r] = l < tev && (tsh == 0 ? tgt[l - rbase] : key_dst(sk[l], vb)) == dst;
+                    e_l[r] = l;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                if (e_hit[r]) {
+                    const uint32_t i = e_i[r];
+                    const uint32_t seq = i < e_d[r] ? pool[e_adj[r] + 2ull * e_acap[r] + i] : e_nseq[r] + (i - e_d[r]);
+                    hkey[nh] = ((uint64_t)e_l[r] << 32) | seq;
+                    hidx[nh] = i;
+                    ++nh;
                 }
             }
             // place the hits at the end of the LDS buffer
@@ -845,14 +874,14 @@ __device__ uint64_t mutate_one(uint64_t t, const MutArgs& A, uint64_t abase0, co
 // set's samples in dynamic LDS; the other runs WB-thread blocks, one vertex per
 // wave at a time.
 constexpr uint32_t XL_WORDS = 8192;  // LDS samples per large vertex (32 KiB)
+constexpr int MUT_WAVES = 5;  // waves per SIMD the small-vertex instance is compiled for
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(WB) k_mutate(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
-                                               MutArgs A, unsigned long long* __restrict__ partials,
-                                               const uint32_t* __restrict__ dold, const uint32_t* __restrict__ blist,
-                                               BigCtx bc, uint32_t split) {
-    __shared__ unsigned long long red[WB / 64];
-    extern __shared__ uint32_t xl[];
+__device__ __forceinline__ void mutate_blocks(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+                                              const MutArgs& A, unsigned long long* __restrict__ partials,
+                                              const uint32_t* __restrict__ dold, const uint32_t* __restrict__ blist,
+                                              const BigCtx& bc, uint32_t split, unsigned long long* red,
+                                              uint32_t* xl) {
     // a batch with bad input, a candidate overflow or no pool space changes nothing
     const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
     const uint64_t T = skip ? 0 : uc[UC_T];
@@ -894,6 +923,28 @@ __global__ void __launch_bounds__(WB) k_mutate(unsigned long long* __restrict__ 
             for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) v += red[w];
         partials[(uint64_t)blockIdx.x * 32 + threadIdx.x] = v;  // counter 0: garbage words
     }
+}
+
+// The vertices up to `split` entries: a wave's work on one vertex is a chain of dependent loads, so
+// the kernel is held to a register budget that keeps five waves per SIMD resident (4 without it;
+// 6 and 8 spill enough registers to be slower).
+__global__ void __launch_bounds__(WB) __attribute__((amdgpu_waves_per_eu(MUT_WAVES, MUT_WAVES)))
+k_mutate(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err, MutArgs A,
+         unsigned long long* __restrict__ partials, const uint32_t* __restrict__ dold,
+         const uint32_t* __restrict__ blist, BigCtx bc, uint32_t split) {
+    __shared__ unsigned long long red[WB / 64];
+    mutate_blocks<false>(uc, err, A, partials, dold, blist, bc, split, red, nullptr);
+}
+
+// The vertices with more than `split` entries, one wave per block.
+__global__ void __launch_bounds__(WB) k_mutate_split(unsigned long long* __restrict__ uc,
+                                                     const uint32_t* __restrict__ err, MutArgs A,
+                                                     unsigned long long* __restrict__ partials,
+                                                     const uint32_t* __restrict__ dold,
+                                                     const uint32_t* __restrict__ blist, BigCtx bc, uint32_t split) {
+    __shared__ unsigned long long red[WB / 64];
+    extern __shared__ uint32_t xl[];
+    mutate_blocks<true>(uc, err, A, partials, dold, blist, bc, split, red, xl);
 }
 
 // Final adjacency word i (< dn) of a vertex whose kept entries may not have been
@@ -1685,7 +1736,7 @@ struct UpdPlan {
     uint32_t *chunk_item, *ccnt, *bsur;
     void* tmp;
     uint32_t split = 0;  // the split threshold the captured graph was made with
-    uint32_t grid_an = PART_BLOCKS, grid_mu = PART_BLOCKS;  // resident blocks of k_analyze, k_mutate<false>
+    uint32_t grid_an = PART_BLOCKS, grid_mu = PART_BLOCKS;  // resident blocks of k_analyze, k_mutate
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_failed = false;
@@ -1738,7 +1789,7 @@ static UpdPlan* plan_make(uint64_t rmax, uint64_t cmax) {
     p->rmax = R;
     p->cmax = C;
     p->grid_an = resident_grid((const void*)k_analyze, WB);
-    p->grid_mu = resident_grid((const void*)k_mutate<false>, WB);
+    p->grid_mu = resident_grid((const void*)k_mutate, WB);
     if (hipMalloc(&p->ws, bytes) != hipSuccess) { delete p; return nullptr; }
     p->bytes = bytes;
     char* w = p->ws;
@@ -1843,14 +1894,14 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     const MutArgs ma{p->tv, p->tsa, p->tdl, p->te, p->ncnt, p->xoff, p->xs, g->hdr, g->pool, p->sv, p->id, p->wv,
                      p->idest, p->aoff, p->sur, p->sdirty, g->rule};
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R)), dim3(TB), 0, st, p->sdirty, R, 0u);
-    hipLaunchKernelGGL((k_mutate<false>), dim3(vgrid_m), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
+    hipLaunchKernelGGL(k_mutate, dim3(vgrid_m), dim3(WB), 0, st, uc, (const uint32_t*)err, ma, p->parts,
                        (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
     hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, vgrid_m,
                        uc + UC_FREED, 0);
     if (split) {
         // vertices with more than `split` entries, then the passes they handed over
         const uint32_t sgrid = (uint32_t)std::min<uint64_t>(R, PART_BLOCKS);
-        hipLaunchKernelGGL((k_mutate<true>), dim3(sgrid), dim3(64), XL_WORDS * 4, st, uc, (const uint32_t*)err, ma,
+        hipLaunchKernelGGL(k_mutate_split, dim3(sgrid), dim3(64), XL_WORDS * 4, st, uc, (const uint32_t*)err, ma,
                            p->parts, (const uint32_t*)p->dold, (const uint32_t*)p->blist, bc, split);
         hipLaunchKernelGGL(k_stats_reduce, dim3(32), dim3(256), 0, st, (const unsigned long long*)p->parts, sgrid,
                            uc + UC_FREED, 1);
@@ -1884,7 +1935,10 @@ static UpdPlan* get_plan(bingo_graph* g, uint64_t rmax, uint64_t cmax_min) {
             break;
         }
     }
-    const uint64_t cmax = std::max<uint64_t>(cmax_min, std::max<uint64_t>(4 * rmax, 1ull << 16));
+    // small batches get a candidate buffer the one-block sort takes (a batch with more candidates than
+    // that retries once with a larger plan)
+    const uint64_t cmax =
+        std::max<uint64_t>(cmax_min, rmax <= 1024 ? 4096ull : std::max<uint64_t>(4 * rmax, 1ull << 16));
     // keep the cached workspaces bounded: drop the largest others first
     size_t total = 0;
     for (auto* p : ps->plans) total += p->bytes;
