@@ -146,6 +146,44 @@ def random_read_probe(dev, sizes_gib=(0.25, 1, 4, 8, 16)):
     return out
 
 
+def replay_probe(g, dev, off, vtx, cnt, nwalks, lanes):
+    """An achievable rate for the walk kernel's own access pattern (bingo_probe_replay): the visits
+    of the query just run (from its per-source histograms, in a seeded random order within each
+    source, sources in order) replayed over the same graph at the walk kernel's resident lane
+    count, one chain of visits per walk; per visit the header line and 1 or 2 random adjacency
+    lines of the vertex; dependent (the next address waits on what was read, as in a walk) at the
+    walk's lane count, and independent (only the header-to-adjacency dependency) at the best of 1, 2
+    and 4 times that many lanes: the pattern's ceiling."""
+    import torch
+    nsrc = off.numel() - 1
+    seg = torch.repeat_interleave(torch.arange(nsrc, device=dev), off[1:] - off[:-1])
+    c = cnt.to(torch.int64)
+    visits = torch.repeat_interleave(vtx, c)
+    key = torch.repeat_interleave(seg, c) << 32
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(12345)
+    key |= torch.randint(0, 1 << 32, key.shape, device=dev, generator=gen)
+    visits = visits[torch.argsort(key)].contiguous()
+    del seg, c, key
+    chain = max(1, int(round(visits.numel() / max(nwalks, 1))))
+    out = {"visits": int(visits.numel()), "chain": chain, "lanes": lanes,
+           "order": "per-source visits of the query, seeded random order within a source, sources in order"}
+    for dep in (True, False):
+        for extra in (1, 2):
+            # the walk kernel's resident lanes, and (as the ceiling) the best of 1, 2 and 4 times as many
+            best = None
+            for mult in ((1,) if dep else (1, 2, 4)):
+                g.probe_replay(visits, chain, lanes * mult, float(extra), dependent=dep, seed=7)  # warm
+                r = g.probe_replay(visits, chain, lanes * mult, float(extra), dependent=dep, seed=7)
+                if best is None or r["GBps"] > best["GBps"]:
+                    best = r
+            out["%s_extra_%d" % ("dependent" if dep else "independent", extra)] = {
+                "ms": best["ms"], "lines": best["lines"], "GBps": best["GBps"], "lanes": best["lanes"]}
+    del visits
+    torch.cuda.empty_cache()
+    return out
+
+
 def stream_copy_GBps(dev, gib=1):
     """Streaming bandwidth: a 1 GiB device-to-device copy (read + write bytes over the kernel time)."""
     import torch
@@ -798,6 +836,7 @@ def main():
         log("autotune: chose %s" % tune["chosen"])
     rows = []
     last = None
+    replay = None
     for i in range(nb):
         base = i * args.sources * R
         torch.cuda.synchronize()
@@ -824,6 +863,16 @@ def main():
         if i == nb - 1:
             last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32),
                     steps)
+            if not args.no_random_probe:
+                tun = g.get_tuning()
+                lanes = tun["blocks_per_cu"] * torch.cuda.get_device_properties(dev).multi_processor_count * 256
+                replay = replay_probe(g, dev, off, vtx, cnt, args.sources * R, lanes)
+                replay["transitions"] = int(steps)
+                log("replay of the last query's %d visits over the graph (%d lanes, chains of %d), 1 / 2 adjacency "
+                    "lines per visit: dependent %.0f / %.0f GB/s, independent %.0f / %.0f GB/s" %
+                    (replay["visits"], lanes, replay["chain"], replay["dependent_extra_1"]["GBps"],
+                     replay["dependent_extra_2"]["GBps"], replay["independent_extra_1"]["GBps"],
+                     replay["independent_extra_2"]["GBps"]))
     timed = rows[args.warmup:]
     tot_ms = sum(r["step_ms"] for r in timed)
     tot_steps = sum(r["steps"] for r in timed)
@@ -1044,6 +1093,21 @@ def main():
         roof["random_probe_table_GiB"] = big["table_GiB"]
         if roof["achieved"] is not None:
             roof["frac_of_random_probe"] = roof["achieved"] / r_rand
+    if replay is not None:
+        roof["replay_probe"] = replay
+        if roof["achieved"] is not None:
+            # the replay's line rate at the walk's own mix: its lines beyond the header per transition,
+            # spread over every visit (the start visits take none), interpolated linearly between the
+            # runs with 1 and 2 extra lines per visit
+            x = (roof["lines_per_transition"] - 1.0) * replay["transitions"] / replay["visits"]
+            x = min(max(x, 1.0), 2.0)
+            replay["walk_extra_lines_per_visit"] = x
+            for form in ("dependent", "independent"):
+                r1, r2 = replay[form + "_extra_1"]["GBps"], replay[form + "_extra_2"]["GBps"]
+                replay[form + "_GBps_at_walk_mix"] = r1 + (x - 1.0) * (r2 - r1)
+            roof["achievable_GBps"] = replay["independent_GBps_at_walk_mix"]
+            roof["frac_of_achievable"] = roof["achieved"] / roof["achievable_GBps"]
+            roof["frac_of_dependent_replay"] = roof["achieved"] / replay["dependent_GBps_at_walk_mix"]
         result["update_roofline"] = update_roofline(timed, mem, m, r_rand, r_stream)
         ur = result["update_roofline"]
         log("update roofline: %.2f ms model (%.2f ms locating deletes) vs %.2f ms measured: %.2f of the model, "

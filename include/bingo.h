@@ -566,6 +566,31 @@ int bingo_probe_random_reads(const void* d_table, uint64_t table_bytes, uint32_t
                              uint32_t dependent, uint32_t line_bytes, uint64_t seed, uint32_t* d_sink,
                              float* h_ms, void* stream);
 
+/*
+ * bingo_probe_replay -- measurement aid, not part of the method.  Replays a walk
+ * query's visit stream over the graph's own header array and adjacency pool:
+ * the access pattern of the walk kernels without their arithmetic, giving an
+ * achievable rate for that pattern next to the uniform random-read probe.
+ *   d_visits     n_visits device uint32 vertex ids in replay order (ids >= n
+ *                are skipped); a chain of `chain` consecutive visits plays one
+ *                walk, and lane l of `lanes` (a multiple of 256) takes chains
+ *                l, l + lanes, ...
+ *   per visit    the 64-byte header line of the vertex, then extra_x256 / 256
+ *                (at most 64 on average) random adjacency entries of it, whose
+ *                address depends on the header's adjacency offset.
+ *   dependent    1: the next visit's address also depends on what was read
+ *                (one chain of dependent reads per walk, as in the walk kernels);
+ *                0: visits are independent (the pattern's ceiling).
+ *   d_counters   two device uint64: [0] the lines read, [1] a checksum that
+ *                keeps the reads live (both cleared first).
+ *   h_ms         receives the kernel time from HIP events on the stream.
+ * Synchronizes.  BINGO_E_INVALID for a null or radix-4 handle, a zero chain, a
+ * bad lane count or extra_x256 above 64 * 256.
+ */
+int bingo_probe_replay(bingo_graph* g, const uint32_t* d_visits, uint64_t n_visits, uint32_t chain, uint32_t lanes,
+                       uint32_t extra_x256, uint32_t dependent, uint64_t seed, unsigned long long* d_counters,
+                       float* h_ms, void* stream);
+
 /* bingo_num_vertices -- n of the handle. */
 uint32_t bingo_num_vertices(const bingo_graph* g);
 

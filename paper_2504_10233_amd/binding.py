@@ -57,7 +57,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
-           "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range"]
+           "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range", "bingo_probe_replay"]
 
 
 class _ServerConfig(C.Structure):
@@ -124,6 +124,7 @@ def load():
         L.bingo_server_wait.argtypes = [vp, u64, vp, u64, C.POINTER(_RequestInfo)]
         L.bingo_server_destroy.argtypes = [vp]
         L.bingo_probe_random_reads.argtypes = [vp, u64, u32, u32, u32, u32, u64, vp, C.POINTER(C.c_float), vp]
+        L.bingo_probe_replay.argtypes = [vp, vp, u64, u32, u32, u32, u32, u64, vp, C.POINTER(C.c_float), vp]
         L.bingo_quantize_biases.argtypes = [u64, vp, C.c_double, u32, vp, vp]
         L.bingo_num_vertices.argtypes = [vp]
         L.bingo_num_vertices.restype = u32
@@ -341,6 +342,20 @@ class Graph:
     def compact(self, pool_bytes=0, stream=None):
         """Move every live block into a fresh arena (0: of the current size), leaving replaced blocks behind."""
         _check(load().bingo_compact(self.h, int(pool_bytes), _stream(stream)), "bingo_compact")
+
+    def probe_replay(self, visits, chain, lanes, extra_lines, dependent=True, seed=1, stream=None) -> dict:
+        """Replay of a visit stream over this graph's headers and adjacency (measurement aid; see
+        bingo_probe_replay): lines read, time and the 64-byte line rate."""
+        v = as_u32(visits, self.device)
+        ctr = torch.zeros(2, dtype=torch.int64, device=self.device)
+        ms = C.c_float(0.0)
+        rc = load().bingo_probe_replay(self.h, _ptr(v), v.numel(), chain, lanes, int(round(extra_lines * 256)),
+                                       int(bool(dependent)), seed, _ptr(ctr), C.byref(ms), _stream(stream))
+        _check(rc, "bingo_probe_replay")
+        lines = int(ctr[0].item())
+        return {"ms": ms.value, "lines": lines, "visits": v.numel(), "chain": chain, "lanes": lanes,
+                "extra_lines_per_visit": extra_lines, "dependent": bool(dependent),
+                "GBps": lines * 64 / (ms.value / 1e3) / 1e9}
 
     def memory(self, stream=None) -> dict:
         m = _MemStats()

@@ -66,6 +66,19 @@ def test_probe_rejects_bad_arguments_without_gpu():
     assert f(fake, 1 << 20, 256, 3, 0, 64, 1, fake, ctypes.byref(ms), None) == -1   # reads
 
 
+def test_replay_probe_rejects_bad_arguments_without_gpu():
+    lib = ctypes.CDLL(_lib_path())
+    f = lib.bingo_probe_replay
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                  ctypes.c_void_p]
+    ms = ctypes.c_float()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its argument checks
+    assert f(None, fake, 10, 5, 256, 256, 1, 1, fake, ctypes.byref(ms), None) == -1     # no graph
+    assert f(fake, None, 10, 5, 256, 256, 1, 1, fake, ctypes.byref(ms), None) == -1     # no visits
+    assert f(fake, fake, 10, 5, 256, 256, 1, 1, None, ctypes.byref(ms), None) == -1     # no counters
+
+
 def test_quantize_rejects_bad_arguments_without_gpu():
     lib = ctypes.CDLL(_lib_path())
     f = lib.bingo_quantize_biases
