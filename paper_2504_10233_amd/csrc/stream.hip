@@ -89,6 +89,7 @@ __device__ __forceinline__ uint64_t st_wave_min(uint64_t x) {
 // position of val in L[0, len) (it occurs once), by a wave scan with eight
 // loads per lane in flight
 constexpr uint32_t ST_UNROLL = 8;
+constexpr uint32_t ST_SCAN = 32;  // loads per lane in flight in a delete's adjacency scan
 __device__ uint32_t st_find(const uint32_t* __restrict__ L, uint32_t len, uint32_t val) {
     const uint32_t lane = lane_id();
     for (uint32_t p0 = 0; p0 < len; p0 += 64 * ST_UNROLL) {
@@ -332,18 +333,19 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     const bool g = lane < 32;
     uint64_t* edges = reinterpret_cast<uint64_t*>(pool + s.adj);
     uint32_t* seqs = pool + s.adj + 2ull * s.cap;
-    // the live occurrence with the smallest sequence number
+    // the live occurrence with the smallest sequence number: a hub's records are one wave's
+    // sequential chain, so its adjacency scan keeps ST_SCAN loads per lane in flight
     uint64_t best = ~0ull;
     uint32_t hits = 0;
-    for (uint32_t i0 = 0; i0 < s.d; i0 += 64 * ST_UNROLL) {
-        uint32_t e[ST_UNROLL];
+    for (uint32_t i0 = 0; i0 < s.d; i0 += 64 * ST_SCAN) {
+        uint32_t e[ST_SCAN];
 #pragma unroll
-        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+        for (uint32_t j = 0; j < ST_SCAN; ++j) {
             const uint32_t i = i0 + j * 64 + lane;
             e[j] = i < s.d ? (uint32_t)edges[i] : ~v;
         }
 #pragma unroll
-        for (uint32_t j = 0; j < ST_UNROLL; ++j) {
+        for (uint32_t j = 0; j < ST_SCAN; ++j) {
             const uint32_t i = i0 + j * 64 + lane;
             const bool m = e[j] == v;
             hits += __popcll(__ballot(m));
