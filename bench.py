@@ -300,6 +300,11 @@ def workload_deepwalk(args):
     res.update({"walk_steps_per_s": tot_steps / (sum(r["walk_kernel_ms"] for r in timed) / 1e3),
                 "edge_updates_per_s": sum(r["records"] for r in timed) / (sum(r["update_ms"] for r in timed) / 1e3),
                 "build_s": build_s, "steps_detail": rows})
+    # the walks of the first 20000 vertices in the last step (walk ids 0..19999, the ids the oracle gives
+    # the same starts; vertex ids are a seeded permutation, so these are a random sample), kept before
+    # the comparisons below reuse the path buffer
+    sample = np.arange(20000, dtype=np.int64)
+    gp = paths[:20000].cpu().numpy().view(np.uint32).copy()
     res["float_bias"] = float_vs_integer(n, src, dst, w, starts, paths, c)
     res["adaption"] = adaption_vs_baseline(n, src, dst, w, starts, paths, c)
     res["alias"] = alias_vs_its(n, src, dst, w, starts, paths, c, batches[:2])
@@ -310,15 +315,13 @@ def workload_deepwalk(args):
         og = O.Graph(n, src.cpu().numpy(), dst.cpu().numpy(), w.cpu().numpy())
         for bt in batches:
             og.update(*[x.cpu().numpy().view(np.uint32) for x in bt])
-        sample = np.arange(0, n, 97, dtype=np.int64)[:20000]
         t = time.time()
         op, osteps = og.deepwalk(sample, 80, synth.SEEDS["walks"] + c + 10 * (nb - 1), threads=th)
         cpu_s = time.time() - t
-        gp = paths.cpu().numpy().view(np.uint32)[sample]
         res["parity"] = {"sampled_walks_equal": bool(np.array_equal(gp, op)), "walks": int(len(sample))}
         res["cpu_baseline"] = {"value": osteps / cpu_s, "unit": "walk-steps/s", "cores": th, "kind": "oracle",
-                               "sample": "%d DeepWalk walks (every 97th vertex) on the graph after the same batches"
-                                         % len(sample)}
+                               "sample": "%d DeepWalk walks (the first vertices, a random sample under the id "
+                                         "permutation) on the graph after the same batches" % len(sample)}
     return res
 
 
@@ -1105,8 +1108,14 @@ def main():
             for form in ("dependent", "independent"):
                 r1, r2 = replay[form + "_extra_1"]["GBps"], replay[form + "_extra_2"]["GBps"]
                 replay[form + "_GBps_at_walk_mix"] = r1 + (x - 1.0) * (r2 - r1)
-            roof["achievable_GBps"] = replay["independent_GBps_at_walk_mix"]
+            roof["achievable_GBps"] = max(replay["independent_GBps_at_walk_mix"],
+                                          replay["dependent_GBps_at_walk_mix"])
             roof["frac_of_achievable"] = roof["achieved"] / roof["achievable_GBps"]
+            roof["achievable_note"] = ("the query's own visits replayed over the graph (bingo_probe_replay) at the "
+                                       "walk's lines per visit, the better of the dependent and independent forms; "
+                                       "near 1: the walk runs at the rate its access pattern sustains (the walk can "
+                                       "exceed it slightly: a wave's lanes walk from one source in step, which the "
+                                       "shuffled replay does not reproduce)")
             roof["frac_of_dependent_replay"] = roof["achieved"] / replay["dependent_GBps_at_walk_mix"]
         result["update_roofline"] = update_roofline(timed, mem, m, r_rand, r_stream)
         ur = result["update_roofline"]

@@ -426,7 +426,8 @@ __global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restr
 // entry s = the position of S[s] in the group's list.  k_sr_compact gathers the
 // flagged vertices, so every one of them gets a block of its own (a batch on a
 // few hubs would otherwise rebuild them one after another); k_srebuild runs
-// one block per vertex.  Pass 1 ranks the flagged entries of each tile of
+// one block per vertex of more than SR_WAVE edges, k_srebuild_wave one wave per
+// smaller one.  Pass 1 ranks the flagged entries of each tile of
 // SR_TB * SR_TPT indices by ballots (rows of SR_TB consecutive indices, waves
 // in order); pass 2 finds each list member's position in S(u) by a search
 // that starts in LDS samples of S(u) (every 2^sh-th entry) and ends with at
@@ -438,19 +439,24 @@ constexpr uint32_t SR_XL = 16384;   // LDS samples of S(u) (64 KB)
 constexpr uint32_t SR_ILV = 4;      // list members searched together per thread in pass 2
 constexpr uint32_t SR_LIST0 = 64;
 // Vertices of more than SR_BIG edges are split into chunks of SR_CHUNK adjacency
-// entries, each handled by a block of its own.  Work buffer (u32): [0] small
-// vertices, [1] large vertices, [2] chunks; the small list at SR_LIST0; the large
-// list (vertex, first chunk, chunks) after it; then the chunk owners and counts.
+// entries, each handled by a block of its own; vertices of at most SR_WAVE edges
+// (most of them) take one wave each, with S(u) staged in the wave's LDS.  Work
+// buffer (u32): [0] block vertices, [1] large vertices, [2] chunks, [3] wave
+// vertices; the block list grows up from SR_LIST0 and the wave list down from
+// SR_LIST0 + mc - 1 (a vertex is in one of them); the large list (vertex, first
+// chunk, chunks) after them; then the chunk owners and counts.
 constexpr uint32_t SR_BIG = 1u << 15;
 constexpr uint32_t SR_CHUNK = 1u << 14;
 constexpr uint32_t SR_NO_OWNER = 0xFFFFFFFFu;
+constexpr uint32_t SR_WAVE = 1024;  // largest degree rebuilt by one wave
+constexpr int SRW_TB = 256;         // blocks of the wave kernel
 __host__ __device__ inline uint64_t sr_chunk_cap(uint64_t mc) { return 4 * mc + 65536; }
 __host__ __device__ inline uint64_t sr_big_off(uint64_t mc) { return SR_LIST0 + mc; }
 __host__ __device__ inline uint64_t sr_owner_off(uint64_t mc) { return sr_big_off(mc) + 3 * mc; }
 __host__ __device__ inline uint64_t sr_cnt_off(uint64_t mc) { return sr_owner_off(mc) + sr_chunk_cap(mc); }
 
 __global__ void k_sr_zero(uint32_t* __restrict__ work) {
-    if (threadIdx.x < 3) work[threadIdx.x] = 0;
+    if (threadIdx.x < 4) work[threadIdx.x] = 0;
 }
 
 __global__ void k_sr_compact(uint32_t n, const uint32_t* __restrict__ hdr, const uint32_t* __restrict__ list,
@@ -480,7 +486,8 @@ __global__ void k_sr_compact(uint32_t n, const uint32_t* __restrict__ hdr, const
                 small = true;
             }
         }
-        if (small) work[SR_LIST0 + atomicAdd(work, 1u)] = u;
+        if (small && d <= SR_WAVE) work[SR_LIST0 + maxc - 1 - atomicAdd(work + 3, 1u)] = u;
+        else if (small) work[SR_LIST0 + atomicAdd(work, 1u)] = u;
     }
 }
 
@@ -787,6 +794,76 @@ __global__ void __launch_bounds__(SR_TB) k_srebuild(uint32_t* __restrict__ hdr, 
     }
 }
 
+// Vertices of at most SR_WAVE edges, one wave each: S(u) by ballots over rows of
+// 64 indices (written to its block and to the wave's LDS), then every sparse
+// group's index by a binary search of each list member in the LDS copy.
+__global__ void __launch_bounds__(SRW_TB) k_srebuild_wave(uint32_t* __restrict__ hdr, uint32_t* __restrict__ pool,
+                                                          GroupRule rule, uint64_t maxc,
+                                                          const uint32_t* __restrict__ work) {
+    __shared__ uint32_t sl[SRW_TB / 64][SR_WAVE];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t* S_l = sl[wave];
+    const uint32_t nt = work[3];
+    for (uint64_t q = (uint64_t)blockIdx.x * (SRW_TB / 64) + wave; q < nt; q += (uint64_t)gridDim.x * (SRW_TB / 64)) {
+        const uint32_t u = work[SR_LIST0 + maxc - 1 - q];
+        uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+        const uint32_t d = h[H_DEG];
+        const uint32_t mask = h[H_MASK], onem = h[H_ONEMASK];
+        const bool ne = lane < 32 && ((mask >> lane) & 1u);
+        const uint32_t c = ne ? slot_count(hdr_slot(h, lane, hdr_hi(h)), onem, lane) : 0u;
+        const uint32_t t = ne ? group_type(c, d, rule) : GT_EMPTY;
+        const uint32_t smask = (uint32_t)(__ballot(t == GT_SPARSE) & 0xFFFFFFFFull);
+        const uint32_t info = lane < 32 ? h[H_INFO + lane] : 0u;
+        const uint32_t lcap = lane < 32 ? 1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu) : 0u;
+        if (!smask) {
+            if (lane == 0) h[H_SLEN] = 0;
+            continue;
+        }
+        const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + hdr_adj(h));
+        uint32_t* S = pool + (uint64_t)h[H_SBLK] * LIST_UNIT_WORDS;
+        uint32_t sfill = 0;
+        constexpr uint32_t ROWS = 8;  // rows of 64 indices whose weights are loaded together
+        for (uint32_t i0 = 0; i0 < d; i0 += 64 * ROWS) {
+            uint32_t wr[ROWS];
+#pragma unroll
+            for (uint32_t j = 0; j < ROWS; ++j) {
+                const uint32_t i = i0 + j * 64 + lane;
+                wr[j] = i < d ? (uint32_t)(edges[i] >> 32) : 0u;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < ROWS; ++j) {
+                const uint32_t i = i0 + j * 64 + lane;
+                const bool in = i < d && (member_word(wr[j], rule.fbits) & smask) != 0u;
+                const uint64_t b = __ballot(in);
+                const uint32_t rk = sfill + (uint32_t)__popcll(b & lanemask_lt());
+                if (in) {
+                    S[rk] = i;
+                    S_l[rk] = i;
+                }
+                sfill += (uint32_t)__popcll(b);
+            }
+        }
+        if (lane == 0) h[H_SLEN] = sfill;
+        __builtin_amdgcn_wave_barrier();  // S_l written by the wave before any lane searches it
+        for (uint32_t mm = smask; mm; mm &= mm - 1) {
+            const int k = __ffs(mm) - 1;
+            const uint32_t ck = __shfl(c, k, 64);
+            uint32_t* L = pool + (uint64_t)__shfl(info, k, 64) * LIST_UNIT_WORDS;
+            uint32_t* I = L + __shfl(lcap, k, 64);
+            for (uint32_t p = lane; p < ck; p += 64) {
+                const uint32_t v = L[p];
+                uint32_t lo = 0, hi = sfill;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (S_l[mid] < v) lo = mid + 1; else hi = mid;
+                }
+                I[lo] = p;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the next vertex overwrites S_l
+    }
+}
+
 int bits_for(uint64_t v) {  // bits needed to hold values in [0, v]
     int b = 0;
     while (b < 64 && (v >> b)) ++b;
@@ -810,6 +887,9 @@ void sparse_rebuild(bingo_graph* g, const uint32_t* list, const unsigned long lo
                        list, count, max_count, dirty, work);
     const uint32_t grid = (uint32_t)std::min<uint64_t>(max_count, 2048);
     hipLaunchKernelGGL(k_srebuild, dim3(grid), dim3(SR_TB), 0, st, g->hdr, g->pool, g->rule, (const uint32_t*)work);
+    const uint32_t wgrid = (uint32_t)std::min<uint64_t>((max_count + SRW_TB / 64 - 1) / (SRW_TB / 64), 4096);
+    hipLaunchKernelGGL(k_srebuild_wave, dim3(wgrid), dim3(SRW_TB), 0, st, g->hdr, g->pool, g->rule, max_count,
+                       (const uint32_t*)work);
     hipLaunchKernelGGL(k_sr_count, dim3(2048), dim3(SRC_TB), 0, st, (const uint32_t*)g->hdr, (const uint32_t*)g->pool,
                        g->rule, max_count, work);
     hipLaunchKernelGGL(k_sr_write, dim3(2048), dim3(SRC_TB), 0, st, g->hdr, g->pool, g->rule, max_count,
