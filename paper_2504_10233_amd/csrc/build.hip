@@ -433,9 +433,9 @@ __global__ void __launch_bounds__(ALIAS_TB) k_alias_rows(const uint32_t* __restr
 // that starts in LDS samples of S(u) (every 2^sh-th entry) and ends with at
 // most sh steps in global memory.
 // ---------------------------------------------------------------------------
-constexpr int SR_TB = 1024;
+constexpr int SR_TB = 256;
 constexpr uint32_t SR_TPT = 16;     // adjacency words in flight per thread in pass 1
-constexpr uint32_t SR_XL = 16384;   // LDS samples of S(u) (64 KB)
+constexpr uint32_t SR_XL = 8192;    // LDS samples of S(u) (32 KB)
 constexpr uint32_t SR_ILV = 4;      // list members searched together per thread in pass 2
 constexpr uint32_t SR_LIST0 = 64;
 // Vertices of more than SR_BIG edges are split into chunks of SR_CHUNK adjacency

@@ -136,3 +136,47 @@ def test_memory_identity_rmat(kind):
     assert mem["index_bytes"] + mem["list_bytes"] + 4 * ones + mem["adjacency_bytes"] == mem["model_ga_bytes"]
     assert mem["index_reserved_bytes"] >= mem["index_bytes"]
     gg.close()
+
+
+@pytest.mark.parametrize("split", [0, 4096])
+def test_sparse_rebuild_at_every_vertex_size(split):
+    """S(u) and the sparse indexes rebuilt for vertices of every size class the rebuild has: 70,000
+    edges (several adjacency chunks, one block each), 3,000 and 1,030 edges (one block per vertex),
+    1,000 edges and fewer (one wave per vertex); weights mostly 1, so every group above bit 0 is
+    sparse and each batch changes S(u) of the vertices it touches; then a stream of records."""
+    rng = np.random.default_rng(21)
+    n = 200
+    sizes = {0: 70000, 1: 3000, 2: 1030, 3: 1000}
+    src = np.concatenate([np.full(d, v) for v, d in sizes.items()] + [rng.integers(4, n, 3000)])
+    m = src.size
+    dst = rng.integers(0, n, m)
+    w = np.where(rng.random(m) < 0.9, 1, rng.integers(1, 1 << 20, m))
+    og, gg = both(n, src, dst, w)
+    gg.set_tuning(update_split=split)
+    assert_same_structure(og, gg, "build")
+    for b in range(3):
+        cur = O.parse_dump(og.dump(), n)
+        live = [(u, int(x)) for u, v in enumerate(cur) for x in v["dst"]]
+        k = 600
+        isrc = rng.choice([0, 1, 2, 3, int(rng.integers(4, n))], size=k)
+        idst = rng.integers(0, n, k)
+        iw = np.where(rng.random(k) < 0.5, 1, rng.integers(1, 1 << 20, k))
+        pick = rng.choice(len(live), size=700, replace=False)
+        dsrc = np.array([live[i][0] for i in pick])
+        ddst = np.array([live[i][1] for i in pick])
+        og.update(isrc, idst, iw, dsrc, ddst)
+        gg.update(t(isrc), t(idst), t(iw), t(dsrc), t(ddst))
+        assert_same_structure(og, gg, "batch %d" % b)
+    cur = O.parse_dump(og.dump(), n)
+    live = [(u, int(x)) for u, v in enumerate(cur) for x in v["dst"]]
+    recs = []
+    for _ in range(300):
+        if rng.random() < 0.5:
+            recs.append((0, int(rng.integers(0, 4)), int(rng.integers(0, n)), int(rng.integers(1, 1 << 20))))
+        else:
+            u, x = live[int(rng.integers(0, len(live)))]
+            recs.append((1, u, x, 0))
+    ops, s, d, ww = (np.array(c, dtype=np.int64) for c in zip(*recs))
+    og.update_stream(ops, s, d, ww)
+    gg.update_stream(*[t(x) for x in (ops, s, d, ww)])
+    assert_same_structure(og, gg, "stream")
