@@ -1132,6 +1132,12 @@ def main():
     result["walk_src_hash"] = walk_src_hash()
     if args.stream_records:
         result["streaming"] = stream_phase(g, n, scale, src, dst, c, args.stream_records)
+    # release the graph (pool, update plans, streams) and the inputs before the result line, so no
+    # device work or allocation of the run outlives it
+    g.close()
+    del g, batches, src, dst, w
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
 
 

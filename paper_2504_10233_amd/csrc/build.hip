@@ -486,8 +486,20 @@ __global__ void k_sr_compact(uint32_t n, const uint32_t* __restrict__ hdr, const
                 small = true;
             }
         }
-        if (small && d <= SR_WAVE) work[SR_LIST0 + maxc - 1 - atomicAdd(work + 3, 1u)] = u;
-        else if (small) work[SR_LIST0 + atomicAdd(work, 1u)] = u;
+        // one atomic per wave and list: the lanes of a list take consecutive slots
+        const bool to_wave = small && d <= SR_WAVE, to_block = small && !to_wave;
+        const uint64_t bw = __ballot(to_wave), bb = __ballot(to_block);
+        const uint32_t lane = lane_id(), leader = __ffsll((long long)(bw | bb)) - 1;
+        uint32_t basew = 0, baseb = 0;
+        if (lane == leader) {
+            if (bw) basew = atomicAdd(work + 3, (uint32_t)__popcll(bw));
+            if (bb) baseb = atomicAdd(work, (uint32_t)__popcll(bb));
+        }
+        basew = __shfl(basew, leader, 64);
+        baseb = __shfl(baseb, leader, 64);
+        const uint64_t lt = lanemask_lt();
+        if (to_wave) work[SR_LIST0 + maxc - 1 - (basew + (uint32_t)__popcll(bw & lt))] = u;
+        if (to_block) work[SR_LIST0 + baseb + (uint32_t)__popcll(bb & lt)] = u;
     }
 }
 
