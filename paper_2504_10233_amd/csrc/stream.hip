@@ -59,13 +59,21 @@ __global__ void k_st_starts(const uint32_t* __restrict__ head, const uint64_t* _
         if (head[p]) { seg_start[hx[p]] = (uint32_t)p; seg_src[hx[p]] = sk[p]; }
 }
 
-// Pool words for the current record, taken with one compare-and-swap on the
-// bump counter (ctl[0]) so that a failed reservation leaves it unchanged.
-// Every lane calls; the result (NF64 on failure) is uniform.
+// Pool words for the current record.  Each wave takes the pool in chunks of ST_CHUNK words (or
+// the request, if larger) from the bump counter (ctl[0]) by compare-and-swap, so that a failed
+// reservation leaves the counter unchanged, and serves its records from the chunk; one global
+// operation per chunk instead of per record keeps thousands of waves from contending on the
+// counter.  The unused tail of a chunk is garbage (counted in `waste`, reclaimed by compaction).
+// Near the end of the pool a chunk that does not fit falls back to the exact request.  Every
+// lane calls with the same values; the result (NF64 on failure) is uniform.
 constexpr uint64_t NF64 = ~0ull;
-__device__ uint64_t st_alloc(unsigned long long* ctl, uint64_t pool_words, uint64_t words) {
+constexpr uint64_t ST_CHUNK = 1u << 14;
+struct StChunk {
+    uint64_t cur = 0, end = 0;
+};
+__device__ uint64_t st_reserve(unsigned long long* ctl, uint64_t pool_words, uint64_t words) {
     unsigned long long got = 0;
-    if (lane_id() == 0 && words) {
+    if (lane_id() == 0) {
         unsigned long long cur = *reinterpret_cast<volatile unsigned long long*>(ctl);
         for (;;) {
             if (cur + words > pool_words) { got = NF64; break; }
@@ -75,6 +83,27 @@ __device__ uint64_t st_alloc(unsigned long long* ctl, uint64_t pool_words, uint6
         }
     }
     return __shfl(got, 0, 64);
+}
+__device__ uint64_t st_alloc(StChunk& ch, unsigned long long* ctl, uint64_t pool_words, uint64_t words,
+                             uint64_t& waste) {
+    if (!words) return 0;
+    if (ch.cur + words <= ch.end) {
+        const uint64_t r = ch.cur;
+        ch.cur += words;
+        return r;
+    }
+    const uint64_t take = words > ST_CHUNK ? words : ST_CHUNK;
+    uint64_t got = st_reserve(ctl, pool_words, take);
+    uint64_t end = got + take;
+    if (got == NF64 && take > words) {
+        got = st_reserve(ctl, pool_words, words);
+        end = got + words;
+    }
+    if (got == NF64) return NF64;  // the current chunk stays for smaller requests
+    if (lane_id() == 0) waste += ch.end - ch.cur;  // the old chunk's unused tail
+    ch.cur = got + words;
+    ch.end = end;
+    return got;
 }
 
 __device__ __forceinline__ uint64_t st_wave_min(uint64_t x) {
@@ -217,7 +246,8 @@ __device__ void st_count(uint32_t code, unsigned long long* acc) {
 // (a regular group's inverted index spans the adjacency capacity, a sparse
 // group's index the S(u) capacity).
 __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_t* __restrict__ pool,
-                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc) {
+                          unsigned long long* ctl, uint64_t pool_words, StChunk& ch, uint64_t& freed,
+                          unsigned long long* acc) {
     const uint32_t lane = lane_id();
     const uint32_t fb = rule.fbits;
     const uint32_t mw = member_word(w, fb);
@@ -249,7 +279,7 @@ __device__ bool st_insert(SV& s, uint32_t v, uint32_t w, GroupRule rule, uint32_
         if (lane >= (uint32_t)o) x += y;
     }
     const uint64_t total = aw + __shfl(x, 63, 64);
-    const uint64_t base = st_alloc(ctl, pool_words, total);
+    const uint64_t base = st_alloc(ch, ctl, pool_words, total, freed);
     if (base == NF64) return false;
     const uint64_t myblk = base + aw + (x - lw);
     // adjacency
@@ -326,7 +356,8 @@ __device__ __forceinline__ uint32_t st_pos(const uint32_t* __restrict__ L, uint3
 
 // One delete record.
 __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restrict__ pool,
-                          unsigned long long* ctl, uint64_t pool_words, uint64_t& freed, unsigned long long* acc,
+                          unsigned long long* ctl, uint64_t pool_words, StChunk& ch, uint64_t& freed,
+                          unsigned long long* acc,
                           uint32_t* __restrict__ errw) {
     const uint32_t lane = lane_id();
     const uint32_t fb = rule.fbits;
@@ -393,7 +424,7 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
         if (lane >= (uint32_t)o) x += y;
     }
     const uint64_t total = __shfl(x, 63, 64);
-    const uint64_t base = st_alloc(ctl, pool_words, total);
+    const uint64_t base = st_alloc(ch, ctl, pool_words, total, freed);
     if (base == NF64) return false;
     const uint64_t myblk = base + (x - lw);
     // adjacency: the tail entry takes the deleted slot
@@ -498,6 +529,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
     if (lane < ST_CTRS) acc[lane] = 0;
     __threadfence_block();
     uint64_t freed = 0;  // per lane
+    StChunk ch;          // the wave's pool chunk
     for (uint64_t sg = (uint64_t)blockIdx.x * (TB / 64) + wave; sg < nseg; sg += (uint64_t)gridDim.x * (TB / 64)) {
         const uint32_t b = seg_start[sg];
         const uint32_t e = sg + 1 < nseg ? seg_start[sg + 1] : (uint32_t)m;
@@ -517,8 +549,8 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         uint32_t stop = e;  // first record not applied
         for (uint32_t p = b; p < e && ok; ++p) {
             const uint32_t r = sv[p];
-            if (op[r] == OP_INSERT) ok = st_insert(s, dst[r], w[r], rule, pool, ctl, pool_words, freed, acc);
-            else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, freed, acc, errw);
+            if (op[r] == OP_INSERT) ok = st_insert(s, dst[r], w[r], rule, pool, ctl, pool_words, ch, freed, acc);
+            else ok = st_delete(s, dst[r], rule, pool, ctl, pool_words, ch, freed, acc, errw);
             if (!ok) stop = p;
             __threadfence_block();
         }
@@ -560,7 +592,8 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
             sdirty[sg] = (s.scap && s.sdirty) ? 1u : 0u;
         }
     }
-    // garbage words of the wave, then the block's counters
+    // garbage words of the wave (with its last chunk's unused tail), then the block's counters
+    if (lane == 0) freed += ch.end - ch.cur;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) freed += __shfl_xor(freed, o);
     if (lane == 0 && freed) atomicAdd(ctl + 1, (unsigned long long)freed);
