@@ -24,6 +24,7 @@ namespace {
 constexpr int TB = 256;
 constexpr uint32_t NF = 0xFFFFFFFFu;
 constexpr uint32_t ST_GRID = 2048;
+constexpr uint32_t ST_BIG_GRID = 1024;
 constexpr int ST_CTRS = 32;  // 0 inserted, 1 deleted, 2 not found, 3..27 transitions, 28 scanned, 29 matches
 
 enum { OP_INSERT = 0, OP_DELETE = 1 };
@@ -119,6 +120,8 @@ __device__ __forceinline__ uint64_t st_wave_min(uint64_t x) {
 // loads per lane in flight
 constexpr uint32_t ST_UNROLL = 8;
 constexpr uint32_t ST_SCAN = 32;  // loads per lane in flight in a delete's adjacency scan
+constexpr uint32_t ST_BIG_D = 1u << 14;  // sources of at least this degree take a block each
+constexpr int STB = 512;                 // threads of k_st_apply_big
 __device__ uint32_t st_find(const uint32_t* __restrict__ L, uint32_t len, uint32_t val) {
     const uint32_t lane = lane_id();
     for (uint32_t p0 = 0; p0 < len; p0 += 64 * ST_UNROLL) {
@@ -355,25 +358,21 @@ __device__ __forceinline__ uint32_t st_pos(const uint32_t* __restrict__ L, uint3
 }
 
 // One delete record.
-__device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restrict__ pool,
-                          unsigned long long* ctl, uint64_t pool_words, StChunk& ch, uint64_t& freed,
-                          unsigned long long* acc,
-                          uint32_t* __restrict__ errw) {
+// The live occurrence of v with the smallest sequence number among adjacency
+// entries [lo, hi): (seq << 32 | index), ~0 if none, and the number of
+// occurrences; the wave's result in every lane.  A hub's records are a
+// sequential chain, so the scan keeps ST_SCAN loads per lane in flight.
+__device__ uint64_t st_scan_oldest(const uint64_t* __restrict__ edges, const uint32_t* __restrict__ seqs, uint32_t lo,
+                                   uint32_t hi, uint32_t v, uint32_t& hits) {
     const uint32_t lane = lane_id();
-    const uint32_t fb = rule.fbits;
-    const bool g = lane < 32;
-    uint64_t* edges = reinterpret_cast<uint64_t*>(pool + s.adj);
-    uint32_t* seqs = pool + s.adj + 2ull * s.cap;
-    // the live occurrence with the smallest sequence number: a hub's records are one wave's
-    // sequential chain, so its adjacency scan keeps ST_SCAN loads per lane in flight
     uint64_t best = ~0ull;
-    uint32_t hits = 0;
-    for (uint32_t i0 = 0; i0 < s.d; i0 += 64 * ST_SCAN) {
+    hits = 0;
+    for (uint32_t i0 = lo; i0 < hi; i0 += 64 * ST_SCAN) {
         uint32_t e[ST_SCAN];
 #pragma unroll
         for (uint32_t j = 0; j < ST_SCAN; ++j) {
             const uint32_t i = i0 + j * 64 + lane;
-            e[j] = i < s.d ? (uint32_t)edges[i] : ~v;
+            e[j] = i < hi ? (uint32_t)edges[i] : ~v;
         }
 #pragma unroll
         for (uint32_t j = 0; j < ST_SCAN; ++j) {
@@ -386,7 +385,19 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
             }
         }
     }
-    best = st_wave_min(best);
+    return st_wave_min(best);
+}
+
+// One delete record whose oldest occurrence (best, from st_scan_oldest over the whole adjacency)
+// and occurrence count are known.
+__device__ bool st_delete_at(SV& s, uint32_t v, uint64_t best, uint32_t hits, GroupRule rule,
+                             uint32_t* __restrict__ pool, unsigned long long* ctl, uint64_t pool_words, StChunk& ch,
+                             uint64_t& freed, unsigned long long* acc, uint32_t* __restrict__ errw) {
+    const uint32_t lane = lane_id();
+    const uint32_t fb = rule.fbits;
+    const bool g = lane < 32;
+    uint64_t* edges = reinterpret_cast<uint64_t*>(pool + s.adj);
+    uint32_t* seqs = pool + s.adj + 2ull * s.cap;
     if (lane == 0) { acc[28] += s.d; acc[29] += hits; }
     const uint32_t told = g ? group_type(s.c, s.d, rule) : GT_EMPTY;
     if (best == ~0ull) {
@@ -510,7 +521,80 @@ __device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restric
     return true;
 }
 
-// One wave per touched source vertex: its records in order.
+// One delete record, the whole adjacency scanned by the wave.
+__device__ bool st_delete(SV& s, uint32_t v, GroupRule rule, uint32_t* __restrict__ pool, unsigned long long* ctl,
+                          uint64_t pool_words, StChunk& ch, uint64_t& freed, unsigned long long* acc,
+                          uint32_t* __restrict__ errw) {
+    const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + s.adj);
+    const uint32_t* seqs = pool + s.adj + 2ull * s.cap;
+    uint32_t hits;
+    const uint64_t best = st_scan_oldest(edges, seqs, 0, s.d, v, hits);
+    return st_delete_at(s, v, best, hits, rule, pool, ctl, pool_words, ch, freed, acc, errw);
+}
+
+// The state of source u's vertex from its header (lane k < 32: group k).
+__device__ __forceinline__ void st_load(SV& s, uint32_t u, const uint32_t* __restrict__ hdr) {
+    const uint32_t lane = lane_id();
+    s.u = u;
+    const uint32_t* h = hdr + (size_t)u * HDR_WORDS;
+    s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ];
+    s.adj = hdr_adj(h);
+    s.W = ((uint64_t)h[H_WHI] << 32) | h[H_WLO];
+    s.c = lane < 32 ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
+    s.info = lane < 32 ? h[H_INFO + lane] : 0u;
+    s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
+    s.sblk = h[H_SBLK];
+    s.scap = h[H_SCAP];
+    s.sdirty = false;
+}
+
+// After a source's records: the records not applied (an out-of-pool stop at record `stop`) are
+// flagged in `left`, and the vertex's header is rewritten from the state (the wave's lanes).
+__device__ void st_store(const SV& s, bool ok, uint32_t stop, uint32_t e, const uint32_t* __restrict__ sv,
+                         uint64_t sg, GroupRule rule, uint32_t* __restrict__ hdr, const uint32_t* __restrict__ pool,
+                         uint32_t* __restrict__ errw, uint32_t* __restrict__ left, uint32_t* __restrict__ sdirty) {
+    const uint32_t lane = lane_id();
+    if (!ok) {
+        if (lane == 0) atomicOr(errw, ERR_OOM);
+        for (uint32_t q = stop + lane; q < e; q += 64) left[sv[q]] = 1u;  // this source's records not applied
+    }
+    uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
+    const bool ne = lane < 32 && s.c > 0;
+    const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
+    const uint32_t t = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
+    // one-element groups: the member's destination in the count slot
+    const bool onek = lane < 32 && t == GT_ONE;
+    const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
+    const uint32_t nhi = mask_hi(nmask);
+    if (lane < 32) {
+        if (lane <= nhi)
+            h[H_CNT + (nhi - lane)] = onek ? (uint32_t)reinterpret_cast<const uint64_t*>(pool + s.adj)[s.info] : s.c;
+        h[H_INFO + lane] = (type_listed(t) || t == GT_ONE) ? s.info : 0u;
+    }
+    const uint32_t lg = (lane < 32 && type_listed(t)) ? (31 - __clz(s.lcap)) : 0u;
+    uint32_t packed = lg << (8 * (lane & 3));
+    packed |= __shfl_xor(packed, 1);
+    packed |= __shfl_xor(packed, 2);
+    if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
+    if (lane == 0) {
+        h[H_MASK] = nmask;
+        h[H_ONEMASK] = onemask;
+        h[H_DEG] = s.d;
+        h[H_WLO] = (uint32_t)s.W;
+        h[H_WHI] = (uint32_t)(s.W >> 32);
+        h[H_ADJLO] = (uint32_t)s.adj;
+        h[H_ADJHI] = adjhi_word(s.adj, nhi);
+        h[H_ACAP] = s.cap;
+        h[H_NSEQ] = s.nseq;
+        h[H_SBLK] = s.sblk;
+        h[H_SCAP] = s.scap;
+        if (!s.scap) h[H_SLEN] = 0;
+        sdirty[sg] = (s.scap && s.sdirty) ? 1u : 0u;
+    }
+}
+
+// One wave per touched source vertex: its records in order.  Sources of at least ST_BIG_D
+// edges are listed in `big` instead, for k_st_apply_big.
 __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ err, const unsigned long long* nseg_p,
                                                  uint64_t m, const uint32_t* __restrict__ sk,
                                                  const uint32_t* __restrict__ sv, const uint32_t* __restrict__ seg_start,
@@ -519,7 +603,8 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
                                                  uint32_t* __restrict__ pool, unsigned long long* ctl,
                                                  uint64_t pool_words, GroupRule rule, uint32_t* __restrict__ errw,
                                                  unsigned long long* __restrict__ out, uint32_t* __restrict__ left,
-                                                 uint32_t* __restrict__ sdirty) {
+                                                 uint32_t* __restrict__ sdirty, uint32_t* __restrict__ big,
+                                                 unsigned long long* __restrict__ nbig) {
     __shared__ unsigned long long red[TB / 64][ST_CTRS];  // per-wave counters, written by lane 0
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     // only the validation bits gate the kernel: waves of this same kernel set ERR_OOM in the same
@@ -533,18 +618,13 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
     for (uint64_t sg = (uint64_t)blockIdx.x * (TB / 64) + wave; sg < nseg; sg += (uint64_t)gridDim.x * (TB / 64)) {
         const uint32_t b = seg_start[sg];
         const uint32_t e = sg + 1 < nseg ? seg_start[sg + 1] : (uint32_t)m;
+        const uint32_t u = sk[b];
+        if (hdr[(size_t)u * HDR_WORDS + H_DEG] >= ST_BIG_D) {
+            if (lane == 0) big[atomicAdd(nbig, 1ull)] = (uint32_t)sg;
+            continue;
+        }
         SV s;
-        s.u = sk[b];
-        uint32_t* h = hdr + (size_t)s.u * HDR_WORDS;
-        s.d = h[H_DEG]; s.cap = h[H_ACAP]; s.nseq = h[H_NSEQ];
-        s.adj = hdr_adj(h);
-        s.W = ((uint64_t)h[H_WHI] << 32) | h[H_WLO];
-        s.c = lane < 32 ? slot_count(hdr_slot(h, lane, hdr_hi(h)), h[H_ONEMASK], lane) : 0u;
-        s.info = lane < 32 ? h[H_INFO + lane] : 0u;
-        s.lcap = lane < 32 ? (1u << ((h[H_LCAPLOG + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu)) : 0u;
-        s.sblk = h[H_SBLK];
-        s.scap = h[H_SCAP];
-        s.sdirty = false;
+        st_load(s, u, hdr);
         bool ok = true;
         uint32_t stop = e;  // first record not applied
         for (uint32_t p = b; p < e && ok; ++p) {
@@ -554,43 +634,7 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
             if (!ok) stop = p;
             __threadfence_block();
         }
-        if (!ok) {
-            if (lane == 0) atomicOr(errw, ERR_OOM);
-            for (uint32_t q = stop + lane; q < e; q += 64) left[sv[q]] = 1u;  // this source's records not applied
-        }
-        // header of the vertex (the records applied so far)
-        const bool ne = lane < 32 && s.c > 0;
-        const uint32_t nmask = (uint32_t)(__ballot(ne) & 0xFFFFFFFFull);
-        const uint32_t t = lane < 32 ? group_type(s.c, s.d, rule) : GT_EMPTY;
-        // one-element groups: the member's destination in the count slot
-        const bool onek = lane < 32 && t == GT_ONE;
-        const uint32_t onemask = (uint32_t)(__ballot(onek) & 0xFFFFFFFFull);
-        const uint32_t nhi = mask_hi(nmask);
-        if (lane < 32) {
-            if (lane <= nhi)
-                h[H_CNT + (nhi - lane)] = onek ? (uint32_t)reinterpret_cast<const uint64_t*>(pool + s.adj)[s.info] : s.c;
-            h[H_INFO + lane] = (type_listed(t) || t == GT_ONE) ? s.info : 0u;
-        }
-        const uint32_t lg = (lane < 32 && type_listed(t)) ? (31 - __clz(s.lcap)) : 0u;
-        uint32_t packed = lg << (8 * (lane & 3));
-        packed |= __shfl_xor(packed, 1);
-        packed |= __shfl_xor(packed, 2);
-        if (lane < 32 && (lane & 3) == 0) h[H_LCAPLOG + (lane >> 2)] = packed;
-        if (lane == 0) {
-            h[H_MASK] = nmask;
-            h[H_ONEMASK] = onemask;
-            h[H_DEG] = s.d;
-            h[H_WLO] = (uint32_t)s.W;
-            h[H_WHI] = (uint32_t)(s.W >> 32);
-            h[H_ADJLO] = (uint32_t)s.adj;
-            h[H_ADJHI] = adjhi_word(s.adj, nhi);
-            h[H_ACAP] = s.cap;
-            h[H_NSEQ] = s.nseq;
-            h[H_SBLK] = s.sblk;
-            h[H_SCAP] = s.scap;
-            if (!s.scap) h[H_SLEN] = 0;
-            sdirty[sg] = (s.scap && s.sdirty) ? 1u : 0u;
-        }
+        st_store(s, ok, stop, e, sv, sg, rule, hdr, pool, errw, left, sdirty);
     }
     // garbage words of the wave (with its last chunk's unused tail), then the block's counters
     if (lane == 0) freed += ch.end - ch.cur;
@@ -603,6 +647,95 @@ __global__ void __launch_bounds__(TB) k_st_apply(const uint32_t* __restrict__ er
         for (int wv = 0; wv < TB / 64; ++wv) v += red[wv][threadIdx.x];
         if (v) atomicAdd(out + threadIdx.x, v);
     }
+}
+
+// The listed sources of at least ST_BIG_D edges, one block of STB threads per source: wave 0
+// holds the state and applies the records in order; for a delete every wave scans its share of
+// the adjacency for the oldest occurrence first, so a hub's chain of deletes runs STB / 64 times
+// as many loads in flight as one wave would.
+__global__ void __launch_bounds__(STB) k_st_apply_big(const uint32_t* __restrict__ err,
+                                                      const unsigned long long* nseg_p, uint64_t m,
+                                                      const uint32_t* __restrict__ sk, const uint32_t* __restrict__ sv,
+                                                      const uint32_t* __restrict__ seg_start,
+                                                      const uint32_t* __restrict__ op, const uint32_t* __restrict__ dst,
+                                                      const uint32_t* __restrict__ w, uint32_t* __restrict__ hdr,
+                                                      uint32_t* __restrict__ pool, unsigned long long* ctl,
+                                                      uint64_t pool_words, GroupRule rule, uint32_t* __restrict__ errw,
+                                                      unsigned long long* __restrict__ out,
+                                                      uint32_t* __restrict__ left, uint32_t* __restrict__ sdirty,
+                                                      const uint32_t* __restrict__ big,
+                                                      const unsigned long long* __restrict__ nbig) {
+    constexpr int NW = STB / 64;
+    __shared__ unsigned long long acc[ST_CTRS];  // wave 0's counters
+    __shared__ uint64_t w_best[NW];
+    __shared__ uint32_t w_hits[NW];
+    __shared__ uint64_t s_adj;
+    __shared__ uint32_t s_d, s_cap, s_ok;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t nseg = (*err & (ERR_RANGE | ERR_WEIGHT)) ? 0 : *nseg_p;
+    const uint64_t nb = nseg ? *nbig : 0;
+    if (threadIdx.x < ST_CTRS) acc[threadIdx.x] = 0;
+    uint64_t freed = 0;  // per lane of wave 0
+    StChunk ch;          // wave 0's pool chunk
+    SV s;                // wave 0
+    for (uint64_t q = blockIdx.x; q < nb; q += gridDim.x) {
+        const uint64_t sg = big[q];
+        const uint32_t b = seg_start[sg];
+        const uint32_t e = sg + 1 < nseg ? seg_start[sg + 1] : (uint32_t)m;
+        __syncthreads();  // the previous source is done with the shared state
+        if (wave == 0) {
+            st_load(s, sk[b], hdr);
+            if (lane == 0) { s_d = s.d; s_cap = s.cap; s_adj = s.adj; s_ok = 1u; }
+        }
+        __syncthreads();
+        uint32_t stop = e;
+        for (uint32_t p = b; p < e; ++p) {
+            const uint32_t r = sv[p];
+            const bool del = op[r] != OP_INSERT;
+            const uint32_t v = dst[r];
+            if (del) {
+                const uint32_t d = s_d;
+                const uint64_t* edges = reinterpret_cast<const uint64_t*>(pool + s_adj);
+                const uint32_t* seqs = pool + s_adj + 2ull * s_cap;
+                const uint32_t share = (d + NW - 1) / NW;
+                const uint32_t lo = min(d, wave * share), hi = min(d, lo + share);
+                uint32_t hits;
+                const uint64_t bw = st_scan_oldest(edges, seqs, lo, hi, v, hits);
+                if (lane == 0) { w_best[wave] = bw; w_hits[wave] = hits; }
+                __syncthreads();  // every share scanned
+            }
+            if (wave == 0) {
+                bool ok;
+                if (del) {
+                    uint64_t best = ~0ull;
+                    uint32_t hits = 0;
+                    for (int x = 0; x < NW; ++x) {
+                        best = w_best[x] < best ? w_best[x] : best;
+                        hits += w_hits[x];
+                    }
+                    ok = st_delete_at(s, v, best, hits, rule, pool, ctl, pool_words, ch, freed, acc, errw);
+                } else {
+                    ok = st_insert(s, v, w[r], rule, pool, ctl, pool_words, ch, freed, acc);
+                }
+                __threadfence_block();
+                if (lane == 0) { s_d = s.d; s_cap = s.cap; s_adj = s.adj; s_ok = ok ? 1u : 0u; }
+            }
+            __syncthreads();  // the record is applied; the shared state is current
+            if (!s_ok) {
+                stop = p;
+                break;
+            }
+        }
+        if (wave == 0) st_store(s, stop == e, stop, e, sv, sg, rule, hdr, pool, errw, left, sdirty);
+    }
+    if (wave == 0) {
+        if (lane == 0) freed += ch.end - ch.cur;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) freed += __shfl_xor(freed, o);
+        if (lane == 0 && freed) atomicAdd(ctl + 1, (unsigned long long)freed);
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_CTRS && acc[threadIdx.x]) atomicAdd(out + threadIdx.x, acc[threadIdx.x]);
 }
 
 inline uint32_t grid_for(uint64_t n) {
@@ -671,7 +804,7 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     if (m > (1ull << 31)) return BINGO_E_INVALID;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const size_t tmpb = std::max(sort_temp_bytes(m, false), scan_temp_bytes(m));
-    const size_t bytes = al(m * 4) * 8 + al(m * 8) + al(SPARSE_WORK_WORDS(m) * 4) + al(ST_CTRS * 8) + 256 + tmpb;
+    const size_t bytes = al(m * 4) * 9 + al(m * 8) + al(SPARSE_WORK_WORDS(m) * 4) + al(ST_CTRS * 8) + 512 + tmpb;
     char* ws = (char*)ws_get(g, bytes);
     if (!ws) return BINGO_E_OOM;
     auto take = [&](uint64_t b) { char* r = ws; ws += al(b); return r; };
@@ -687,11 +820,14 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     uint64_t* hx = (uint64_t*)take(m * 8);
     unsigned long long* out = (unsigned long long*)take(ST_CTRS * 8);
     unsigned long long* nseg = (unsigned long long*)take(256);
+    uint32_t* big = (uint32_t*)take(m * 4);  // segments of the sources of at least ST_BIG_D edges
+    unsigned long long* nbig = (unsigned long long*)take(256);
     void* tmp = ws;
     HIPCHK(hipMemsetAsync(g->d_err, 0, 4, st));
     HIPCHK(hipMemsetAsync(out, 0, ST_CTRS * 8, st));
     HIPCHK(hipMemsetAsync(left, 0, m * 4, st));
     HIPCHK(hipMemsetAsync(sdirty, 0, m * 4, st));
+    HIPCHK(hipMemsetAsync(nbig, 0, 8, st));
     phase_mark(g, st, true);
     hipLaunchKernelGGL(k_st_validate, dim3(grid_for(m)), dim3(TB), 0, st, m, g->n, op, src, dst, w, g->d_err);
     hipLaunchKernelGGL(k_st_iota, dim3(grid_for(m)), dim3(TB), 0, st, ids, m);
@@ -702,7 +838,11 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
     phase_mark(g, st, false);
     hipLaunchKernelGGL(k_st_apply, dim3(ST_GRID), dim3(TB), 0, st, (const uint32_t*)g->d_err,
                        (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
-                       g->pool_words, g->rule, g->d_err, out, left, sdirty);
+                       g->pool_words, g->rule, g->d_err, out, left, sdirty, big, nbig);
+    hipLaunchKernelGGL(k_st_apply_big, dim3(ST_BIG_GRID), dim3(STB), 0, st, (const uint32_t*)g->d_err,
+                       (const unsigned long long*)nseg, m, sk, sv, seg, op, dst, w, g->hdr, g->pool, g->d_ctl,
+                       g->pool_words, g->rule, g->d_err, out, left, sdirty, (const uint32_t*)big,
+                       (const unsigned long long*)nbig);
     // S(u) and the sparse indexes of the sources whose records touched a vertex with sparse groups
     sparse_rebuild(g, seg_src, nseg, m, sdirty, srwork, st);
     // alias-table mode: the sources' inter-group tables (with bad records nothing changed: rewritten as they were)

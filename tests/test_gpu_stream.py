@@ -221,3 +221,39 @@ def test_stream_grows_with_many_more_sources_than_resident_waves():
     assert np.array_equal(g1.export_index(), g2.export_index())
     g1.close()
     g2.close()
+
+
+def test_stream_hub_above_block_threshold():
+    """Sources of at least 16,384 edges take a block each (every wave scans a share of the adjacency
+    for a delete, wave 0 applies the records): a 40,000-edge hub's interleaved streams equal the
+    oracle's, and a fixed pool that runs out in the middle of the hub's inserts keeps exactly the
+    records before the failing one."""
+    b = B()
+    rng = random.Random(77)
+    n = 300
+    m = 46000
+    src = [0] * 40000 + [rng.randrange(1, n) for _ in range(m - 40000)]
+    dst = [rng.randrange(n) for _ in range(m)]
+    w = [rng.choice([1, 3, 255, 1 << rng.randrange(32), rng.randrange(1, 1 << 32)]) for _ in range(m)]
+    og, gg = both(n, src, dst, w)
+    for r in range(2):
+        cur = O.parse_dump(og.dump(), n)
+        ops, s, d, ww = random_stream(rng, cur, n, 3000, hub=0, hub_share=0.6)
+        run_both(og, gg, ops, s, d, ww, "hub stream %d" % r)
+    gg.close()
+    probe = b.Graph(n, torch.tensor(src), torch.tensor(dst), torch.tensor(w))
+    used = probe.memory()["pool_used_bytes"]
+    probe.close()
+    gg = b.Graph(n, torch.tensor(src), torch.tensor(dst), torch.tensor(w), pool_bytes=used + (256 << 10))
+    og = O.Graph(n, src, dst, w)
+    d0 = O.parse_dump(gg.export(), n)[0]["d"]
+    k = 60000
+    ops, s, d, ww = [0] * k, [0] * k, [rng.randrange(n) for _ in range(k)], [rng.randrange(1, 1 << 32) for _ in range(k)]
+    with pytest.raises(b.BingoError) as e:
+        gg.update_stream(*[torch.tensor(x) for x in (ops, s, d, ww)])
+    assert e.value.code == -4
+    applied = O.parse_dump(gg.export(), n)[0]["d"] - d0
+    assert 0 < applied < k
+    og.update_stream(ops[:applied], s[:applied], d[:applied], ww[:applied])
+    assert_same_structure(og, gg, "prefix of %d hub inserts" % applied)
+    gg.close()
