@@ -1135,7 +1135,7 @@ def main():
     # release the graph (pool, update plans, streams) and the inputs before the result line, so no
     # device work or allocation of the run outlives it
     g.close()
-    del g, batches, src, dst, w
+    del g, batches
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
