@@ -16,7 +16,7 @@ import os
 # The binned PPR kernel has attempt-interleaved lanes whatever walk_variant says; variant 1 is also
 # the faster one for the segmented fallback, so the sweep keeps it fixed.
 DEFAULT_SPACE = [dict(walk_variant=1, blocks_per_cu=b, queue_chunk=c, dense_spec=s, wave_degree=0)
-                 for b in (0, 4, 2) for c in (64, 256, 1024) for s in (1, 2, 4)]
+                 for b in (0, 2, 4, 5, 6, 8) for c in (128, 256, 512) for s in (1, 2, 4)]
 # degree thresholds of the wave-per-vertex form (0: every step thread per walk; 1: every dense step
 # wave per vertex)
 WAVE_DEGREES = (0, 1, 64, 1024, 16384, 262144)
