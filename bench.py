@@ -98,6 +98,9 @@ def walk_src_hash():
     return h.hexdigest()[:16]
 
 
+SERVE_TUNING = dict(walk_variant=1, blocks_per_cu=4, queue_chunk=256, dense_spec=2, wave_degree=0)
+
+
 def serve_phase(g, n, src, dst, args, log):
     """Requests through the serving loop on the resident graph: Poisson arrivals at args.serve_rate,
     4 walk queries per update batch; query start sets log-uniform in [1, 10^4] walks with length
@@ -106,13 +109,20 @@ def serve_phase(g, n, src, dst, args, log):
     stream of 400 requests of the same law comes first: the first batch of each update-size bucket
     builds that bucket's plan and captured graph, which a resident server does once."""
     import numpy as np
+    # the server runs with a latency setting (two dense attempts in flight per round, four resident
+    # blocks per CU): the PPR throughput setting (one attempt, eight blocks) lengthens each walk's
+    # chain of rounds, which a small query waits for; no setting changes a result
+    kept = g.get_tuning()
+    g.set_tuning(**SERVE_TUNING)
     warm = make_requests(np.random.default_rng(5004), 400, n, src, dst, 4, 4, 1 << 24)
     serve_requests(g, warm, args.serve_rate, max_batch=args.serve_batch)
     rng = np.random.default_rng(5005)
     reqs = make_requests(rng, args.serve_requests, n, src, dst, 4, 4, 1 << 24)
     res = serve_requests(g, reqs, args.serve_rate, max_batch=args.serve_batch)
+    g.set_tuning(**kept)
     res.pop("kept")
     res["warmup_requests"] = len(warm)
+    res["tuning"] = SERVE_TUNING
     log("serving: query p50 %.3f ms p99 %.3f ms, update p50 %.3f ms p99 %.3f ms" %
         (res["query_p50_ms"], res["query_p99_ms"], res["update_p50_ms"] or -1, res["update_p99_ms"] or -1))
     return res
