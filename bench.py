@@ -893,7 +893,9 @@ def main():
                     steps)
             if not args.no_random_probe:
                 tun = g.get_tuning()
-                lanes = tun["blocks_per_cu"] * torch.cuda.get_device_properties(dev).multi_processor_count * 256
+                # resident blocks per CU of the walk kernel (0: as many as fit, 8 blocks of 256 threads)
+                bpc = tun["blocks_per_cu"] or 8
+                lanes = bpc * torch.cuda.get_device_properties(dev).multi_processor_count * 256
                 replay = replay_probe(g, dev, off, vtx, cnt, args.sources * R, lanes)
                 replay["transitions"] = int(steps)
                 log("replay of the last query's %d visits over the graph (%d lanes, chains of %d), 1 / 2 adjacency "
