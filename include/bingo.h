@@ -103,8 +103,10 @@ typedef struct {
     uint64_t not_found;         /* delete records with no live matching edge */
     uint64_t touched_vertices;  /* vertices with at least one record */
     uint64_t transitions[25];   /* [old*5 + new] group-type changes over all groups of touched vertices */
-    uint64_t match_scanned;     /* live edges and inserts of vertices with deletes, scanned to locate them */
-    uint64_t match_candidates;  /* scanned entries whose dst is among their vertex's delete targets */
+    uint64_t match_scanned;     /* entries read to locate the deletes: locator slots probed and the
+                                   inserts of vertices with deletes (with update_locate = 0: their live
+                                   edges and inserts, scanned) */
+    uint64_t match_candidates;  /* entries whose dst is among their vertex's delete targets */
 } bingo_update_stats;
 
 typedef struct {
@@ -122,6 +124,7 @@ typedef struct {
     uint64_t index_bytes;           /* live group indexes (Sec. 4.2, 5.1): 4 d per regular group, 4 |S(u)|
                                        per sparse group and for S(u) itself */
     uint64_t index_reserved_bytes;  /* their capacities in the pool (list_reserved_bytes counts the lists) */
+    uint64_t locator_bytes;         /* edge locator of bingo_update_batch (16 B per slot; 0 when none) */
 } bingo_mem_stats;
 
 /*
@@ -406,6 +409,18 @@ int bingo_export_index_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, u
  */
 int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream);
 
+/*
+ * bingo_check_locator -- consistency of the edge locator of bingo_update_batch
+ * (the update_locate tuning): *h_bad receives the number of live edges whose
+ * (src, dst, neighbour index) has no slot, plus the difference between the
+ * live slots and the live edges, plus one when the library's own count of live
+ * slots is off; 0 means every live edge has exactly its slot.  *h_live
+ * (optional) receives the live slots.  Synchronizes.  BINGO_E_INVALID for a
+ * null handle or h_bad, a radix-base-4 graph, or no locator in step (none
+ * built yet, or made stale by bingo_update_stream or a batch run without it).
+ */
+int bingo_check_locator(bingo_graph* g, uint64_t* h_bad, uint64_t* h_live, void* stream);
+
 /* bingo_memory -- device memory by structure (synchronizes). */
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream);
 
@@ -463,6 +478,15 @@ int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n
  *                    the first accepting one in stream order taken by ballot)
  *                    instead of by its own lane (thread per walk).  0 (default)
  *                    = never.  Same results either way.
+ *   update_locate    bingo_update_batch: 1 (default) finds the live edges a
+ *                    delete names through the edge locator, a hash multiset of
+ *                    the live edges keyed by (src, dst) that gives an edge's
+ *                    neighbour index in a few probes (16 bytes per slot, at
+ *                    least 1.6 slots per edge; built by the first batch that
+ *                    needs it, kept in step by every batch, rebuilt after
+ *                    bingo_update_stream or a batch run with 0); 0 scans the
+ *                    adjacency of every source with deletes instead.  Same
+ *                    results either way.
  */
 typedef struct {
     uint32_t struct_size;
@@ -474,6 +498,7 @@ typedef struct {
     uint32_t ppr_bins;
     uint32_t update_split;
     uint32_t wave_degree;
+    uint32_t update_locate;
 } bingo_tuning;
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t);

@@ -49,7 +49,8 @@ class _MemStats(C.Structure):
                 ("adjacency_reserved_bytes", C.c_uint64), ("list_bytes", C.c_uint64),
                 ("list_reserved_bytes", C.c_uint64), ("groups_by_type", C.c_uint64 * 5),
                 ("model_ga_bytes", C.c_uint64), ("model_bs_bytes", C.c_uint64), ("alias_bytes", C.c_uint64),
-                ("index_bytes", C.c_uint64), ("index_reserved_bytes", C.c_uint64)]
+                ("index_bytes", C.c_uint64), ("index_reserved_bytes", C.c_uint64),
+                ("locator_bytes", C.c_uint64)]
 
 
 EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bingo_ppr_fetch", "bingo_export",
@@ -57,7 +58,8 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_get_tuning", "bingo_num_vertices", "bingo_destroy", "bingo_strerror", "bingo_server_create",
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
-           "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range", "bingo_probe_replay"]
+           "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range", "bingo_probe_replay",
+           "bingo_check_locator"]
 
 
 class _ServerConfig(C.Structure):
@@ -83,7 +85,8 @@ class _RequestInfo(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("walk_variant", C.c_uint32), ("blocks_per_cu", C.c_uint32),
                 ("queue_chunk", C.c_uint32), ("update_graphs", C.c_uint32), ("dense_spec", C.c_uint32),
-                ("ppr_bins", C.c_uint32), ("update_split", C.c_uint32), ("wave_degree", C.c_uint32)]
+                ("ppr_bins", C.c_uint32), ("update_split", C.c_uint32), ("wave_degree", C.c_uint32),
+                ("update_locate", C.c_uint32)]
 
 
 def lib_path() -> str:
@@ -112,6 +115,7 @@ def load():
         L.bingo_export_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_export_index_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
+        L.bingo_check_locator.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), vp]
         L.bingo_compact.argtypes = [vp, C.c_uint64, vp]
         L.bingo_walk_batch.argtypes = [vp, C.c_uint32, C.POINTER(_WalkQuery), vp]
         L.bingo_status.argtypes = [vp, vp]
@@ -357,6 +361,15 @@ class Graph:
                 "extra_lines_per_visit": extra_lines, "dependent": bool(dependent),
                 "GBps": lines * 64 / (ms.value / 1e3) / 1e9}
 
+    def check_locator(self, stream=None):
+        """(inconsistencies, live slots) of the edge locator; None when no locator is in step."""
+        bad, live = C.c_uint64(0), C.c_uint64(0)
+        rc = load().bingo_check_locator(self.h, C.byref(bad), C.byref(live), _stream(stream))
+        if rc == -1:  # BINGO_E_INVALID
+            return None
+        _check(rc, "bingo_check_locator")
+        return int(bad.value), int(live.value)
+
     def memory(self, stream=None) -> dict:
         m = _MemStats()
         _check(load().bingo_memory(self.h, C.byref(m), _stream(stream)), "bingo_memory")
@@ -373,7 +386,7 @@ class Graph:
         return [float(buf[i]) for i in range(n.value)]
 
     def set_tuning(self, walk_variant=None, blocks_per_cu=None, queue_chunk=None, update_graphs=None, dense_spec=None,
-                   ppr_bins=None, update_split=None, wave_degree=None):
+                   ppr_bins=None, update_split=None, wave_degree=None, update_locate=None):
         cur = self.get_tuning()
         t = _Tuning(C.sizeof(_Tuning), cur["walk_variant"] if walk_variant is None else walk_variant,
                     cur["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu,
@@ -382,7 +395,8 @@ class Graph:
                     cur["dense_spec"] if dense_spec is None else dense_spec,
                     cur["ppr_bins"] if ppr_bins is None else ppr_bins,
                     cur["update_split"] if update_split is None else update_split,
-                    cur["wave_degree"] if wave_degree is None else wave_degree)
+                    cur["wave_degree"] if wave_degree is None else wave_degree,
+                    cur["update_locate"] if update_locate is None else update_locate)
         _check(load().bingo_set_tuning(self.h, C.byref(t)), "bingo_set_tuning")
 
     def get_tuning(self) -> dict:
@@ -390,7 +404,7 @@ class Graph:
         _check(load().bingo_get_tuning(self.h, C.byref(t)), "bingo_get_tuning")
         return {"walk_variant": t.walk_variant, "blocks_per_cu": t.blocks_per_cu, "queue_chunk": t.queue_chunk,
                 "update_graphs": t.update_graphs, "dense_spec": t.dense_spec, "ppr_bins": t.ppr_bins,
-                "update_split": t.update_split, "wave_degree": t.wave_degree}
+                "update_split": t.update_split, "wave_degree": t.wave_degree, "update_locate": t.update_locate}
 
     def status(self, stream=None) -> int:
         return load().bingo_status(self.h, _stream(stream))

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["api.hip", "prim.hip", "build.hip", "walk.hip", "export.hip", "update.hip", "serve.hip", "probe.hip", "stream.hip",
-           "node2vec.hip", "compact.hip", "radix4.hip"]
+           "node2vec.hip", "compact.hip", "radix4.hip", "locate.hip"]
 OUT = os.path.join(HERE, "libbingo.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 FLAGS = [

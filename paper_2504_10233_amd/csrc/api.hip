@@ -1,5 +1,6 @@
 // api.hip -- the extern "C" entry points of libbingo (declared in bingo.h).
 #include "dev.h"
+#include "locate.h"
 #include <stdio.h>
 #include <string.h>
 #include <new>
@@ -40,6 +41,7 @@ int err_to_code(uint32_t bits) {
 static void release(bingo_graph* g) {
     if (!g) return;
     update_release(g);
+    locator_release(g);
     for (int i = 0; i < PHASE_EVENTS; ++i)
         if (g->ev[i]) hipEventDestroy(g->ev[i]);
     for (int i = 0; i < WALK_SLOTS; ++i)
@@ -214,6 +216,7 @@ int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream) {
 
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
     if (!g || !out) return BINGO_E_INVALID;
+    memset(out, 0, sizeof(*out));
     if (g->radix_base == 4) return memory_stats4(g, out, (hipStream_t)stream);
     return memory_stats(g, out, (hipStream_t)stream);
 }
@@ -232,7 +235,8 @@ uint32_t bingo_num_vertices(const bingo_graph* g) { return g ? g->n : 0u; }
 
 int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     if (!g || !t || t->struct_size != sizeof(bingo_tuning)) return BINGO_E_INVALID;
-    if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1 || t->ppr_bins > 1)
+    if (t->walk_variant > 1 || t->blocks_per_cu > 64 || t->update_graphs > 1 || t->ppr_bins > 1 ||
+        t->update_locate > 1)
         return BINGO_E_INVALID;
     if (t->update_split != 0 && t->update_split < 64) return BINGO_E_INVALID;
     const uint32_t qc = t->queue_chunk ? t->queue_chunk : 256u;
@@ -247,6 +251,7 @@ int bingo_set_tuning(bingo_graph* g, const bingo_tuning* t) {
     g->queue_chunk = qc;
     g->update_graphs = t->update_graphs;
     g->wave_degree = t->wave_degree;
+    g->update_locate = t->update_locate;
     return BINGO_OK;
 }
 
@@ -261,6 +266,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
     t->ppr_bins = g->ppr_bins;
     t->update_split = g->update_split;
     t->wave_degree = g->wave_degree;
+    t->update_locate = g->update_locate;
     return BINGO_OK;
 }
 

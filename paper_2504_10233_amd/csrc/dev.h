@@ -329,6 +329,14 @@ struct bingo_graph {
     // attempt-interleaved walks: dense steps at vertices of at least this degree are served by
     // the whole wave (0 = never)
     uint32_t wave_degree = 0;
+    // update pipeline: 1 = deletes located through the edge locator (locate.h), 0 = by scanning
+    // their source's adjacency
+    uint32_t update_locate = 1;
+    // edge locator: 16-byte slots (key, neighbour index; capacity loc_cap, a power of two); live
+    // slots and slots ever taken (live + TOMB); valid = in step with the adjacency
+    uint64_t* loc_tab = nullptr;
+    uint64_t loc_cap = 0, loc_live = 0, loc_used = 0;
+    bool loc_valid = false;
     struct UpdPlans* upd = nullptr;  // per-bucket workspaces and graphs (update.hip)
     // structure version: bumped by every applied update batch
     uint64_t version = 0;
@@ -346,9 +354,11 @@ struct bingo_graph {
 };
 void phase_mark(bingo_graph* g, hipStream_t st, bool first);
 // d_ctl layout (u64): [0] pool words used, [1] garbage words, [2..6] PPR
-// counters, [8..11] node2vec counters (CTL_N2V), [16 + 2*i .. 17 + 2*i] walk
+// counters, [8..11] node2vec counters (CTL_N2V), [12..13] edge locator
+// counters (CTL_LOC), [16 + 2*i .. 17 + 2*i] walk
 // call slot i (WALK_SLOTS slots).
 #define CTL_N2V 8
+#define CTL_LOC 12  // [12..13] edge locator counters (locate.hip)
 #define CTL_WALK0 16
 #define CTL_WORDS (CTL_WALK0 + 2 * WALK_SLOTS)
 

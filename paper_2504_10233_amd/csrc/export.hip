@@ -315,5 +315,6 @@ int memory_stats(bingo_graph* g, bingo_mem_stats* out, hipStream_t st) {
     out->alias_bytes = g->alias ? (uint64_t)g->n * ALIAS_ENTRIES * sizeof(uint4) : 0;
     out->index_bytes = a[14];
     out->index_reserved_bytes = a[15];
+    out->locator_bytes = g->loc_tab ? g->loc_cap * 16 : 0;
     return BINGO_OK;
 }

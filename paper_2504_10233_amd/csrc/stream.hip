@@ -16,6 +16,7 @@
 // beta % of d) and is scanned, and S(u) with the sparse indexes is rebuilt for
 // the touched sources after the stream.
 #include "dev.h"
+#include "locate.h"
 #include <algorithm>
 #include <string.h>
 
@@ -785,6 +786,8 @@ int apply_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t*
 int update_stream(bingo_graph* g, uint64_t m, const uint32_t* op, const uint32_t* src, const uint32_t* dst,
                   const uint32_t* w, bingo_update_stats* h_stats, hipStream_t st) {
     bingo_update_stats sum{};
+    // records applied here move edges without the edge locator: the next batch rebuilds it
+    locator_invalidate(g);
     const int rc = apply_stream(g, m, op, src, dst, w, &sum, STREAM_RETRIES, st);
     if (h_stats) *h_stats = sum;
     // every record of a stream that returns OK was applied exactly once: inserted, deleted or

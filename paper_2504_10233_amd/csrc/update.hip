@@ -17,6 +17,7 @@
 //      renames of moved indices, fresh lists for groups that change type, and
 //      the new header (the inter-group space, updated once per vertex).
 #include "dev.h"
+#include "locate.h"
 #include <stdio.h>
 #include <algorithm>
 #include <string.h>
@@ -50,12 +51,15 @@ int bits_for(uint64_t v) {
 //   [13] large vertices (more than the split threshold of entries)
 //   [16..47] statistics (inserted, deleted, not found, 25 type transitions)
 //   [48..79] freed pool words (entry 48)
+//   [80..84] edge locator: slots probed to match deletes, slots turned TOMB, claims,
+//            claims of EMPTY slots, lookups that found no slot (a locator out of step)
 // Every kernel reads its element counts from here, so the whole pipeline runs
 // without host round trips and can be captured in a hipGraph; grids and
 // buffers are sized by the batch-size bucket Rmax.
 enum { UC_NI = 0, UC_ND = 1, UC_T = 2, UC_F = 3, UC_C = 4, UC_X = 5, UC_ALLOC = 6, UC_BASE = 7, UC_FLAGS = 8,
        UC_R = 9, UC_BIG_ITEMS = 10, UC_BIG_CHUNKS = 11, UC_BIG_SUR = 12, UC_NBIG = 13,
-       UC_STATS = 16, UC_FREED = 48, UC_WORDS = 96 };
+       UC_STATS = 16, UC_FREED = 48, UC_LPROBE = 80, UC_LKILL = 81, UC_LCLAIM = 82, UC_LFRESH = 83, UC_LBAD = 84,
+       UC_WORDS = 96 };
 
 __global__ void k_upd_begin(unsigned long long* __restrict__ uc, uint64_t ni, uint64_t nd, uint32_t* __restrict__ err) {
     const uint32_t i = threadIdx.x;
@@ -145,7 +149,8 @@ __global__ void k_seg_end(const unsigned long long* __restrict__ uc, const uint3
     }
 }
 
-// flat size of the delete-matching space of t: its live edges and its inserts (0 past T);
+// flat size of the delete-matching space of t: its live edges and its inserts (0 past T;
+// only the inserts when the edge locator finds the live edges);
 // also the degree before the batch, dold[t], and the list of the vertices with more than
 // `split` entries after the inserts (in no particular order)
 __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, const uint32_t* __restrict__ tv,
@@ -153,7 +158,7 @@ __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, 
                             const uint32_t* __restrict__ te, const uint32_t* __restrict__ hdr,
                             uint64_t* __restrict__ fsz, uint32_t* __restrict__ dold, uint32_t* __restrict__ vacap,
                             uint32_t* __restrict__ vnseq, uint64_t* __restrict__ vadj, uint32_t split,
-                            uint32_t* __restrict__ blist) {
+                            uint32_t* __restrict__ blist, uint32_t ins_only) {
     const uint64_t T = uc[UC_T];
     GRID_LOOP(t, rmax) {
         uint64_t v = 0;
@@ -166,7 +171,7 @@ __global__ void k_flat_size(unsigned long long* __restrict__ uc, uint64_t rmax, 
             vacap[t] = h[H_ACAP];
             vnseq[t] = h[H_NSEQ];
             vadj[t] = hdr_adj(h);
-            v = nd ? (uint64_t)d + ni : 0ull;
+            v = nd ? (uint64_t)(ins_only ? 0u : d) + ni : 0ull;
             if (split && d + ni > split) blist[atomicAdd(uc + UC_NBIG, 1ull)] = (uint32_t)t;
         }
         fsz[t] = v;
@@ -240,7 +245,7 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                                               const uint64_t* __restrict__ vadj, const uint64_t* __restrict__ sk,
                                               const uint32_t* __restrict__ sv, int vb, const uint32_t* __restrict__ id,
                                               const uint32_t* __restrict__ pool, uint64_t* __restrict__ ckey,
-                                              uint32_t* __restrict__ cval, uint64_t cap) {
+                                              uint32_t* __restrict__ cval, uint64_t cap, uint32_t ins_only) {
     __shared__ uint64_t s_fo[MV];
     __shared__ uint32_t s_v[8][MV];  // d, acap, nseq, adj lo, adj hi, ts, tdl, te
     __shared__ uint32_t tgt[LDS_TARGETS];
@@ -344,7 +349,8 @@ __global__ void __launch_bounds__(TB) k_match(unsigned long long* __restrict__ u
                         e_adj[r] = vadj[t];
                         e_ts[r] = ts[t]; e_tdl[r] = tdl[t]; e_te[r] = te[t];
                     }
-                    e_i[r] = (uint32_t)(f - fo);
+                    // a vertex's flat range covers virtual indices from d when it holds only the inserts
+                    e_i[r] = (uint32_t)(f - fo) + (ins_only ? e_d[r] : 0u);
                 }
             }
 #pragma unroll
@@ -524,6 +530,310 @@ __global__ void k_ins_prep(const unsigned long long* __restrict__ uc, uint64_t r
         wv[j] = iw[sv[j]];
         idest[j] = dest;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Edge locator (locate.h) in the batch pipeline.  Matching probes it for the
+// live edges (k_match then scans only the batch's inserts); after the mutation
+// three kernels bring it in step: slots of deleted live edges turn TOMB, live
+// edges that moved into holes take their new index, surviving inserts claim
+// slots.  The kill pass comes first so that no two live slots of one key ever
+// share an index; moves and claims touch disjoint index ranges (a moved edge is
+// looked up by an index >= dn, every new index is below dn or an insert's own).
+// ---------------------------------------------------------------------------
+// Sum v over the block into *dst (one atomic per block).  Every thread calls it.
+__device__ __forceinline__ void block_add(unsigned long long* dst, uint32_t v, uint32_t* sh) {
+    v = loc_wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) s += sh[w];
+        if (s) atomicAdd(dst, (unsigned long long)s);
+    }
+}
+
+// Wave-uniform grid loop: every lane of a wave runs the same iterations (i may
+// be past n), so the wave-cooperative probes of locate.h can run inside.
+#define WAVE_LOOP(i, n)                                                                                    \
+    for (uint64_t i##_b = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u), i = i##_b + lane_id(); \
+         i##_b < (n); i##_b += (uint64_t)gridDim.x * blockDim.x, i = i##_b + lane_id())
+
+// Candidates among the live edges: the first record of each run of equal delete
+// records (its sorted position r is the run id k_match uses as well) probes the
+// locator for its (src, dst) and emits every occurrence as (r << 32 | seq,
+// neighbour index).  A block counts its hits, reserves their space with one
+// atomic, then writes them: the first HOLD of a record from registers, the rest
+// (a key with many copies) by its wave walking the sequence again.
+__global__ void __launch_bounds__(TB) k_loc_match(unsigned long long* __restrict__ uc, const uint64_t* __restrict__ sk,
+                                                  int vb, const uint32_t* __restrict__ rec_t,
+                                                  const uint32_t* __restrict__ tv, const uint32_t* __restrict__ tdl,
+                                                  const uint32_t* __restrict__ dold, const uint32_t* __restrict__ vacap,
+                                                  const uint64_t* __restrict__ vadj, const uint32_t* __restrict__ pool,
+                                                  LocView L, uint64_t* __restrict__ ckey, uint32_t* __restrict__ cval,
+                                                  uint64_t cap) {
+    constexpr uint32_t HOLD = 4;
+    __shared__ uint32_t wt[TB / 64];
+    __shared__ unsigned long long bb;
+    const uint64_t R = uc[UC_NI] + uc[UC_ND];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t probes = 0, bad = 0;
+    for (uint64_t base = (uint64_t)blockIdx.x * TB; base < R; base += (uint64_t)gridDim.x * TB) {
+        const uint64_t r = base + threadIdx.x;
+        bool head = false;
+        uint64_t k = 0;
+        uint32_t t = 0, d = 0;
+        if (r < R) {
+            t = rec_t[r];
+            d = dold[t];
+            const uint32_t dl = tdl[t];
+            if (r >= dl) {
+                const uint32_t dst = key_dst(sk[r], vb);
+                head = r == dl || key_dst(sk[r - 1], vb) != dst;
+                k = loc_key(tv[t], dst);
+            }
+        }
+        // count the hits; keep the first HOLD indexes
+        uint32_t nh = 0, hp[HOLD], hs[HOLD];
+        uint64_t next = 0;
+        bool lng = false;
+        if (head)
+            lng = loc_first_line(L, k, &next, &probes, [&](uint64_t, uint64_t key, uint32_t p) {
+                // an index past the degree would mean a locator out of step: never used
+                if (key == k) {
+                    if (p < d) {
+                        if (nh < HOLD) hp[nh] = p;
+                        ++nh;
+                    } else {
+                        ++bad;
+                    }
+                }
+                return false;
+            });
+        for (uint64_t todo = __ballot(lng); todo; todo &= todo - 1) {
+            const int o = __ffsll((long long)todo) - 1;
+            const uint64_t kk = __shfl(k, o, 64);
+            const uint32_t dd = __shfl(d, o, 64);
+            uint64_t start = __shfl(next, o, 64);
+            uint32_t cnt = __shfl(nh, o, 64);
+            for (uint64_t s = 0; s <= L.mask; s += 64) {
+                const LocSlot c = loc_slot(L, (start + lane) & L.mask);
+                const uint64_t em = __ballot(c.key == LOC_EMPTY), live = loc_before_empty(em);
+                uint64_t m = __ballot(c.key == kk && (uint32_t)c.pos < dd) & live;
+                const uint64_t bm = __ballot(c.key == kk && (uint32_t)c.pos >= dd) & live;
+                const uint32_t nm = (uint32_t)__popcll(m);
+#pragma unroll
+                for (uint32_t q = 0; q < HOLD; ++q) {
+                    if (q >= cnt && m) {
+                        const uint32_t p = __shfl((uint32_t)c.pos, __ffsll((long long)m) - 1, 64);
+                        if (lane == (uint32_t)o) hp[q] = p;
+                        m &= m - 1;
+                    }
+                }
+                if (lane == (uint32_t)o) {
+                    nh += nm;
+                    bad += (uint32_t)__popcll(bm);
+                    probes += em ? (uint32_t)__ffsll((long long)em) : 64u;
+                }
+                cnt += nm;
+                if (em) break;
+                start = (start + 64) & L.mask;
+            }
+        }
+        const uint64_t seqb = head ? vadj[t] + 2ull * vacap[t] : 0ull;
+#pragma unroll
+        for (uint32_t j = 0; j < HOLD; ++j)
+            if (j < nh) hs[j] = pool[seqb + hp[j]];
+        uint32_t x = nh;  // inclusive prefix over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        __syncthreads();  // the previous round's readers of wt and bb are done
+        if (lane == 63) wt[wave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < TB / 64; ++w) tot += wt[w];
+            bb = tot ? atomicAdd(uc + UC_C, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        uint64_t ob = bb + x - nh;
+        for (int w = 0; w < (int)wave; ++w) ob += wt[w];
+#pragma unroll
+        for (uint32_t j = 0; j < HOLD; ++j) {
+            if (j < nh && ob + j < cap) {
+                ckey[ob + j] = ((uint64_t)r << 32) | hs[j];
+                cval[ob + j] = hp[j];
+            }
+        }
+        // hits past the first HOLD: the wave walks the record's sequence from its start
+        for (uint64_t todo = __ballot(nh > HOLD); todo; todo &= todo - 1) {
+            const int o = __ffsll((long long)todo) - 1;
+            const uint64_t kk = __shfl(k, o, 64), oo = __shfl(ob, o, 64), sb = __shfl(seqb, o, 64);
+            const uint64_t rr = __shfl(r, o, 64);
+            const uint32_t dd = __shfl(d, o, 64), nn = __shfl(nh, o, 64);
+            uint64_t start = loc_hash(kk) & L.mask;
+            uint32_t run = 0;
+            for (uint64_t s = 0; s <= L.mask && run < nn; s += 64) {
+                const LocSlot c = loc_slot(L, (start + lane) & L.mask);
+                const uint64_t em = __ballot(c.key == LOC_EMPTY);
+                const bool mine = c.key == kk && (uint32_t)c.pos < dd && ((loc_before_empty(em) >> lane) & 1ull);
+                const uint64_t m = __ballot(mine);
+                const uint32_t rank = run + (uint32_t)__popcll(m & lanemask_lt());
+                if (mine && rank >= HOLD && rank < nn && oo + rank < cap) {
+                    ckey[oo + rank] = (rr << 32) | pool[sb + (uint32_t)c.pos];
+                    cval[oo + rank] = (uint32_t)c.pos;
+                }
+                run += (uint32_t)__popcll(m);
+                if (em) break;
+                start = (start + 64) & L.mask;
+            }
+        }
+    }
+    block_add(uc + UC_LPROBE, probes, wt);
+    block_add(uc + UC_LBAD, bad, wt);
+}
+
+// The slots of the deleted live edges turn TOMB (a rejected batch changes nothing).
+__global__ void __launch_bounds__(TB) k_loc_kill(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+                                                 const uint64_t* __restrict__ sk, int vb,
+                                                 const uint32_t* __restrict__ rec_t, const uint32_t* __restrict__ tv,
+                                                 const uint32_t* __restrict__ dold,
+                                                 const uint32_t* __restrict__ matched, LocView L) {
+    __shared__ uint32_t sh[TB / 64];
+    const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
+    const uint64_t R = skip ? 0 : uc[UC_NI] + uc[UC_ND];
+    uint32_t kills = 0, bad = 0, seen = 0;
+    WAVE_LOOP(r, R) {
+        bool act = false;
+        uint32_t x = NF;
+        uint64_t k = 0, found = LOC_EMPTY, next = 0;
+        if (r < R) {
+            // the record's own fields load beside its vertex's
+            const uint32_t t = rec_t[r];
+            x = matched[r];
+            const uint64_t key = sk[r];
+            act = x != NF && x < dold[t];  // not an insert record, not absent, not an insert of this batch
+            if (act) k = loc_key(tv[t], key_dst(key, vb));
+        }
+        bool lng = false;
+        if (act)
+            lng = loc_first_line(L, k, &next, &seen, [&](uint64_t h, uint64_t key, uint32_t p) {
+                if (key == k && p == x) {
+                    found = h;
+                    return true;
+                }
+                return false;
+            });
+        loc_wave_find(L, lng, k, x, next, &found);
+        if (act) {
+            if (found == LOC_EMPTY) {
+                ++bad;
+            } else {
+                L.tab[2 * found] = LOC_TOMB;
+                ++kills;
+            }
+        }
+    }
+    block_add(uc + UC_LKILL, kills, sh);
+    block_add(uc + UC_LBAD, bad, sh);
+}
+
+// Live edges that move into a hole take their new index.  Entry e of the
+// deleted sets belongs to touched vertex t = xks[e] >> 32 (xoff[t] <= e < xoff[t] + N); the
+// virtual index v = dn + (e - xoff[t]) runs over [dn, d + ni), and a surviving
+// old edge among them (v < d) goes to hole X[j] by the rank rule of the
+// mutation (the rule k_ins_prep applies to inserts).  Runs before the mutation,
+// so the edge's dst is read at v in the old adjacency.
+__global__ void __launch_bounds__(TB) k_loc_move(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+                                                 const uint64_t* __restrict__ xks, const uint64_t* __restrict__ xoff,
+                                                 const uint32_t* __restrict__ ncnt,
+                                                 const uint32_t* __restrict__ xs, const uint32_t* __restrict__ tv,
+                                                 const uint32_t* __restrict__ ts, const uint32_t* __restrict__ tdl,
+                                                 const uint32_t* __restrict__ dold, const uint64_t* __restrict__ vadj,
+                                                 const uint32_t* __restrict__ pool, LocView L) {
+    __shared__ uint32_t sh[TB / 64];
+    const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
+    const uint64_t NX = skip ? 0 : uc[UC_X];
+    uint32_t bad = 0, seen = 0;
+    WAVE_LOOP(e, NX) {
+        bool act = false;
+        uint32_t v = 0, hole = 0;
+        uint64_t k = 0, found = LOC_EMPTY, next = 0;
+        if (e < NX) {
+            const uint32_t t = (uint32_t)(xks[e] >> 32), N = ncnt[t], d = dold[t], u = tv[t];
+            const uint64_t xo = xoff[t], adj = vadj[t];
+            const uint32_t* X = xs + xo;
+            const uint32_t dn = d + (tdl[t] - ts[t]) - N;
+            v = dn + (uint32_t)(e - xo);
+            if (v < d) {  // an old edge (an insert is placed by k_loc_claim)
+                const uint32_t dst = pool[adj + 2ull * v];  // issued before the searches of the deleted set
+                const uint32_t pv = lower_bound_u32(X, N, v);
+                if (!(pv < N && X[pv] == v)) {  // it survives
+                    hole = X[(v - dn) - (pv - lower_bound_u32(X, N, dn))];
+                    k = loc_key(u, dst);
+                    act = true;
+                }
+            }
+        }
+        bool lng = false;
+        if (act)
+            lng = loc_first_line(L, k, &next, &seen, [&](uint64_t h, uint64_t key, uint32_t p) {
+                if (key == k && p == v) {
+                    found = h;
+                    return true;
+                }
+                return false;
+            });
+        loc_wave_find(L, lng, k, v, next, &found);
+        if (act) {
+            if (found == LOC_EMPTY) ++bad; else L.tab[2 * found + 1] = hole;
+        }
+    }
+    block_add(uc + UC_LBAD, bad, sh);
+}
+
+// Every insert that survives the batch claims a slot at its final index.
+__global__ void __launch_bounds__(TB) k_loc_claim(unsigned long long* __restrict__ uc, const uint32_t* __restrict__ err,
+                                                  const uint32_t* __restrict__ rec_t, const uint32_t* __restrict__ tv,
+                                                  const uint32_t* __restrict__ tdl, const uint32_t* __restrict__ sv,
+                                                  const uint32_t* __restrict__ id, const uint32_t* __restrict__ idest,
+                                                  LocView L) {
+    __shared__ uint32_t sh[TB / 64];
+    const bool skip = *err != 0 || uc[UC_FLAGS] != 0;
+    const uint64_t R = skip ? 0 : uc[UC_NI] + uc[UC_ND];
+    uint32_t claims = 0, fresh = 0, bad = 0;
+    WAVE_LOOP(r, R) {
+        bool act = false;
+        uint32_t dest = 0, res = 0;
+        uint64_t k = 0, next = 0;
+        if (r < R) {
+            const uint32_t t = rec_t[r], o = sv[r];
+            dest = idest[r];
+            // an insert record (r < tdl[t]) that the batch does not delete again
+            act = r < tdl[t] && dest != NF;
+            if (act) k = loc_key(tv[t], id[o]);
+        }
+        bool lng = false;
+        if (act) {
+            res = loc_claim_line(L, k, dest, &next);
+            lng = res == 0;
+        }
+        loc_wave_claim(L, lng, k, dest, next, &res);
+        if (act) {
+            if (res == 0) ++bad;
+            else {
+                ++claims;
+                fresh += res == 2;
+            }
+        }
+    }
+    block_add(uc + UC_LCLAIM, claims, sh);
+    block_add(uc + UC_LFRESH, fresh, sh);
+    block_add(uc + UC_LBAD, bad, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1736,6 +2046,7 @@ struct UpdPlan {
     uint32_t *chunk_item, *ccnt, *bsur;
     void* tmp;
     uint32_t split = 0;  // the split threshold the captured graph was made with
+    LocView lv{nullptr, 0};  // the edge locator the captured graph was made with
     uint32_t grid_an = PART_BLOCKS, grid_mu = PART_BLOCKS;  // resident blocks of k_analyze, k_mutate
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1833,8 +2144,12 @@ static uint64_t pow2_at_least(uint64_t x, uint64_t lo) {
 }
 
 // The whole pipeline for one batch, sizes from the control block; no host round trips.
+// With p->lv.tab set, deletes are located through the edge locator, which the
+// pipeline then keeps in step.
 static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
     const uint64_t R = p->rmax, C = p->cmax;
+    const LocView lv = p->lv;
+    const uint32_t ins_only = lv.tab ? 1u : 0u;
     const int vb = std::max(1, bits_for((uint64_t)g->n - 1));
     const int cbits = bits_for(R) + 32;  // candidate key: run (< R) << 32 | seq
     const uint64_t xpad = cbits >= 64 ? ~0ull : (1ull << cbits) - 1;
@@ -1859,11 +2174,16 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                        p->tdl);
     hipLaunchKernelGGL(k_flat_size, dim3(grid_for(R)), dim3(TB), 0, st, uc, R, p->tv,
                        p->tsa, p->tdl, p->te, g->hdr, p->fsz, p->dold, p->vacap, p->vnseq, p->vadj, g->update_split,
-                       p->blist);
+                       p->blist, ins_only);
     scan_u64(p->fsz, p->foff, R, p->tmp, uc + UC_F, st);
     // 2. delete matching: candidates, sorted by (run, seq); the k oldest per run
     hipLaunchKernelGGL(k_match, dim3(MATCH_GRID), dim3(TB), 0, st, uc, p->foff, p->tsa, p->tdl, p->te, p->dold,
-                       p->vacap, p->vnseq, p->vadj, p->sk, p->sv, vb, p->id, g->pool, p->ckey, p->cval, C);
+                       p->vacap, p->vnseq, p->vadj, p->sk, p->sv, vb, p->id, g->pool, p->ckey, p->cval, C, ins_only);
+    if (lv.tab)
+        hipLaunchKernelGGL(k_loc_match, dim3(grid_for(R)), dim3(TB), 0, st, uc, (const uint64_t*)p->sk, vb,
+                           (const uint32_t*)p->rec_t, (const uint32_t*)p->tv, (const uint32_t*)p->tdl,
+                           (const uint32_t*)p->dold, (const uint32_t*)p->vacap, (const uint64_t*)p->vadj,
+                           (const uint32_t*)g->pool, lv, p->ckey, p->cval, C);
     hipLaunchKernelGGL(k_check_overflow, dim3(1), dim3(1), 0, st, uc, C);
     sort_pairs_u64_dn(p->ckey, p->cval, p->cks, p->cvs, C, uc + UC_C, cbits, p->tmp, st);
     hipLaunchKernelGGL(k_cand_first, dim3(grid_for(C)), dim3(TB), 0, st, p->cks, (const unsigned long long*)uc, C,
@@ -1888,6 +2208,22 @@ static void enqueue_update(bingo_graph* g, UpdPlan* p, hipStream_t st) {
                        uc + UC_STATS, 0);
     scan_u64(p->needw, p->aoff, R, p->tmp, uc + UC_ALLOC, st);
     hipLaunchKernelGGL(k_alloc_check, dim3(1), dim3(1), 0, st, g->d_ctl, g->pool_words, uc, err);
+    // the edge locator in step with what the mutation will do (before it: the moved edges' dst
+    // are read in the old adjacency; a rejected batch skips these as it skips the mutation)
+    if (lv.tab) {
+        hipLaunchKernelGGL(k_loc_kill, dim3(grid_for(R)), dim3(TB), 0, st, uc, (const uint32_t*)err,
+                           (const uint64_t*)p->sk, vb, (const uint32_t*)p->rec_t, (const uint32_t*)p->tv,
+                           (const uint32_t*)p->dold, (const uint32_t*)p->matched, lv);
+        hipLaunchKernelGGL(k_loc_move, dim3(grid_for(R)), dim3(TB), 0, st, uc, (const uint32_t*)err,
+                           (const uint64_t*)p->xks, (const uint64_t*)p->xoff, (const uint32_t*)p->ncnt,
+                           (const uint32_t*)p->xs,
+                           (const uint32_t*)p->tv, (const uint32_t*)p->tsa, (const uint32_t*)p->tdl,
+                           (const uint32_t*)p->dold, (const uint64_t*)p->vadj, (const uint32_t*)g->pool, lv);
+        hipLaunchKernelGGL(k_loc_claim, dim3(grid_for(R)), dim3(TB), 0, st, uc, (const uint32_t*)err,
+                           (const uint32_t*)p->rec_t, (const uint32_t*)p->tv, (const uint32_t*)p->tdl,
+                           (const uint32_t*)p->sv, (const uint32_t*)p->id, (const uint32_t*)p->idest, lv);
+    }
+
     // 5. mutation (a no-op for a rejected batch)
     BigCtx bc{p->big_items, p->chunk_item, p->bsur, BIG_IMAX, BIG_CMAX, (uint32_t)big_smax(R), g->rule.fbits};
     const uint32_t split = g->update_split;
@@ -1983,9 +2319,13 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
     const uint64_t rmax = pow2_at_least(R, 1024);
     uint64_t cmin = 0;
     bool compacted = false, grown = false;
+    // the edge locator, made ready for this batch's claims (when it cannot be, deletes are
+    // located by scanning)
+    locator_prepare(g, n_ins, st);
     for (int attempt = 0; attempt < 6; ++attempt) {
         UpdPlan* p = get_plan(g, rmax, cmin);
         if (!p) return BINGO_E_OOM;
+        const LocView lv = locator_view(g);
         if (n_ins) {
             HIPCHK(hipMemcpyAsync(p->is, is, n_ins * 4, hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(p->id, id, n_ins * 4, hipMemcpyDeviceToDevice, st));
@@ -1998,7 +2338,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
         hipLaunchKernelGGL(k_upd_begin, dim3(1), dim3(128), 0, st, p->uc, n_ins, n_del, g->d_err);
         phase_mark(g, st, true);
         bool launched = false;
-        if (p->exec && p->split != g->update_split) {
+        if (p->exec && (p->split != g->update_split || p->lv.tab != lv.tab || p->lv.mask != lv.mask)) {
             hipGraphExecDestroy(p->exec);
             hipGraphDestroy(p->graph);
             p->exec = nullptr;
@@ -2007,6 +2347,7 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
         if (g->update_graphs && !p->graph_failed) {
             if (!p->exec) {
                 p->split = g->update_split;
+                p->lv = lv;
                 if (!g->upd->cap_stream &&
                     hipStreamCreateWithFlags(&g->upd->cap_stream, hipStreamNonBlocking) != hipSuccess)
                     g->upd->cap_stream = nullptr;
@@ -2024,7 +2365,10 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
             }
             if (p->exec && hipGraphLaunch(p->exec, st) == hipSuccess) launched = true;
         }
-        if (!launched) enqueue_update(g, p, st);
+        if (!launched) {
+            p->lv = lv;
+            enqueue_update(g, p, st);
+        }
         phase_mark(g, st, false);
         unsigned long long uc[UC_WORDS];
         uint32_t err = 0;
@@ -2055,10 +2399,12 @@ int update_batch(bingo_graph* g, uint64_t n_ins, const uint32_t* is, const uint3
             h_stats->deleted = uc[UC_STATS + 1];
             h_stats->not_found = uc[UC_STATS + 2];
             h_stats->touched_vertices = uc[UC_T];
-            h_stats->match_scanned = uc[UC_F];
+            h_stats->match_scanned = uc[UC_F] + uc[UC_LPROBE];
             h_stats->match_candidates = uc[UC_C];
             for (int i = 0; i < 25; ++i) h_stats->transitions[i] = uc[UC_STATS + 3 + i];
         }
+        if (lv.tab) locator_after_batch(g, uc[UC_LKILL], uc[UC_LCLAIM], uc[UC_LFRESH], uc[UC_LBAD]);
+        else locator_invalidate(g);  // the batch did not keep it in step
         ++g->version;
         return BINGO_OK;
     }
