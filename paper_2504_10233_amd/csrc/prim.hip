@@ -11,10 +11,13 @@ namespace {
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr uint64_t SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+constexpr uint64_t RAW_PART_MAX = 2048;  // tiles whose sums each tile adds up itself
 
-constexpr int SORT_BLOCK = 256;
+// a tile of 4096 keys per block of 1024 threads (16 waves, so a compute unit keeps
+// enough loads in flight when the grid has about one block per CU)
+constexpr int SORT_BLOCK = 1024;
 constexpr int SORT_WAVES = SORT_BLOCK / 64;
-constexpr int SORT_SUBTILES = 16;
+constexpr int SORT_SUBTILES = 4;
 constexpr uint64_t SORT_TILE = (uint64_t)SORT_BLOCK * SORT_SUBTILES;
 constexpr int RADIX = 256;
 
@@ -57,10 +60,20 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const T* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// part: the tiles' bases (scanned), or with raw_part their sums, of which each block
+// adds up those before it itself (one launch fewer than scanning them first).
 template <typename T>
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tile(const T* __restrict__ in, uint64_t* __restrict__ out,
                                                           uint64_t n, const uint64_t* __restrict__ part,
-                                                          unsigned long long* __restrict__ total) {
+                                                          unsigned long long* __restrict__ total, int raw_part) {
+    uint64_t tbase = 0;
+    if (part && raw_part) {
+        uint64_t acc = 0;
+        for (uint64_t j = threadIdx.x; j < blockIdx.x; j += SCAN_BLOCK) acc += part[j];
+        block_exclusive_scan(acc, &tbase);
+    } else if (part) {
+        tbase = part[blockIdx.x];
+    }
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
     T v[SCAN_ITEMS];
     uint64_t s = 0;
@@ -70,14 +83,13 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tile(const T* __restrict__ 
         s += (uint64_t)v[i];
     }
     uint64_t tot;
-    uint64_t run = block_exclusive_scan(s, &tot) + (part ? part[blockIdx.x] : 0ull);
+    uint64_t run = block_exclusive_scan(s, &tot) + tbase;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         if (base + i < n) out[base + i] = run;
         run += (uint64_t)v[i];
     }
-    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-        *total = (part ? part[blockIdx.x] : 0ull) + tot;
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = tbase + tot;
 }
 
 template <typename T>
@@ -89,15 +101,20 @@ void scan_impl(const T* in, uint64_t* out, uint64_t n, void* temp, unsigned long
     const uint64_t nb = cdiv(n, SCAN_TILE);
     if (nb == 1) {
         hipLaunchKernelGGL(k_scan_tile<T>, dim3(1), dim3(SCAN_BLOCK), 0, st, in, out, n, (const uint64_t*)nullptr,
-                           d_total);
+                           d_total, 0);
         return;
     }
     uint64_t* part = (uint64_t*)temp;
     void* rest = (char*)temp + align256(nb * 8);
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((uint32_t)nb), dim3(SCAN_BLOCK), 0, st, in, n, part);
+    if (nb <= RAW_PART_MAX) {  // each tile adds up the sums before it
+        hipLaunchKernelGGL(k_scan_tile<T>, dim3((uint32_t)nb), dim3(SCAN_BLOCK), 0, st, in, out, n,
+                           (const uint64_t*)part, d_total, 1);
+        return;
+    }
     scan_impl<uint64_t>(part, part, nb, rest, nullptr, st);  // in place: each tile reads then writes its own range
     hipLaunchKernelGGL(k_scan_tile<T>, dim3((uint32_t)nb), dim3(SCAN_BLOCK), 0, st, in, out, n,
-                       (const uint64_t*)part, d_total);
+                       (const uint64_t*)part, d_total, 0);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -112,16 +129,20 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_hist(const K* __restrict__
                                                            uint32_t* __restrict__ hist, uint32_t nblocks) {
     __shared__ uint32_t h[RADIX];
     if (dn) n = std::min<uint64_t>(n, *dn);
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < RADIX) h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
-#pragma unroll 4
+    K k[SORT_SUBTILES];
+#pragma unroll
     for (int i = 0; i < SORT_SUBTILES; ++i) {
         const uint64_t idx = base + (uint64_t)i * SORT_BLOCK + threadIdx.x;
-        if (idx < n) atomicAdd(&h[digit_of(keys[idx], sh)], 1u);
+        k[i] = idx < n ? keys[idx] : (K)0;
     }
+#pragma unroll
+    for (int i = 0; i < SORT_SUBTILES; ++i)
+        if (base + (uint64_t)i * SORT_BLOCK + threadIdx.x < n) atomicAdd(&h[digit_of(k[i], sh)], 1u);
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < RADIX) hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 template <typename K, bool HAS_V>
@@ -131,21 +152,33 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_scatter(const K* __restric
                                                               int sh, const uint64_t* __restrict__ offs,
                                                               uint32_t nblocks) {
     __shared__ uint64_t run[RADIX];
+    __shared__ uint32_t tot[RADIX];
     if (dn) n = std::min<uint64_t>(n, *dn);
     __shared__ uint32_t wc[SORT_WAVES][RADIX];
     const int tid = threadIdx.x, wave = tid >> 6;
-    run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
+    if (tid < RADIX) {
+        run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
 #pragma unroll
-    for (int w = 0; w < SORT_WAVES; ++w) wc[w][tid] = 0;
-    __syncthreads();
+        for (int w = 0; w < SORT_WAVES; ++w) wc[w][tid] = 0;
+    }
     const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
     const uint64_t below = lanemask_lt();
+    // the tile's keys and values, all loads issued before the first subtile is ranked
+    K keys[SORT_SUBTILES];
+    uint32_t vals[SORT_SUBTILES];
+#pragma unroll
+    for (int i = 0; i < SORT_SUBTILES; ++i) {
+        const uint64_t idx = base + (uint64_t)i * SORT_BLOCK + tid;
+        keys[i] = idx < n ? kin[idx] : (K)0;
+        vals[i] = (HAS_V && idx < n) ? vin[idx] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
     for (int i = 0; i < SORT_SUBTILES; ++i) {
         const uint64_t idx = base + (uint64_t)i * SORT_BLOCK + tid;
         const bool valid = idx < n;
-        K key = valid ? kin[idx] : (K)0;
-        uint32_t val = 0;
-        if (HAS_V && valid) val = vin[idx];
+        const K key = keys[i];
+        const uint32_t val = vals[i];
         const uint32_t dg = digit_of(key, sh);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -157,20 +190,29 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_digit_scatter(const K* __restric
         const uint32_t lrank = __popcll(peers & below);
         if (valid && lrank == 0) wc[wave][dg] = __popcll(peers);
         __syncthreads();
+        // per digit, the keys of the lower waves (an exclusive scan down each column)
+        if (tid < RADIX) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int w = 0; w < SORT_WAVES; ++w) {
+                const uint32_t c = wc[w][tid];
+                wc[w][tid] = acc;
+                acc += c;
+            }
+            tot[tid] = acc;
+        }
+        __syncthreads();
         if (valid) {
-            uint64_t pos = run[dg] + lrank;
-            for (int w = 0; w < wave; ++w) pos += wc[w][dg];
+            const uint64_t pos = run[dg] + wc[wave][dg] + lrank;
             kout[pos] = key;
             if (HAS_V) vout[pos] = val;
         }
         __syncthreads();
-        uint32_t add = 0;
+        if (tid < RADIX) {
+            run[tid] += tot[tid];
 #pragma unroll
-        for (int w = 0; w < SORT_WAVES; ++w) {
-            add += wc[w][tid];
-            wc[w][tid] = 0;
+            for (int w = 0; w < SORT_WAVES; ++w) wc[w][tid] = 0;
         }
-        run[tid] += add;
         __syncthreads();
     }
 }
