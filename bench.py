@@ -234,9 +234,11 @@ def update_roofline(rows, mem, edges, r_rand_GBps, r_stream_GBps):
     8-byte keys) over the streaming bandwidth, plus random 64-byte lines (an insert touches its adjacency
     slot and, per listed group of the edge, a list slot and its block; a delete the same for the
     deleted edge and for the moved tail edge) over the random-line rate.  Listed groups per edge are
-    taken from the structure (live list entries / edges).  Locating deletes (the scan of the touched
-    adjacencies, 8 B per scanned entry) is reported beside it, since the paper does not say how an
-    edge (src, dst) is found."""
+    taken from the structure (live list entries / edges).  Locating deletes is reported beside it, since
+    the paper does not say how an edge (src, dst) is found: through the edge locator, one random line per
+    delete to find it and, to keep the locator in step, one per delete to retire its slot, two per moved
+    edge (its dst and its slot; about one moved edge per delete) and one per insert to claim a slot; with
+    the locator off, a scan of the touched adjacencies (8 B per scanned entry)."""
     le = mem["list_bytes"] / 4.0 / max(edges, 1)
     n = len(rows)
     ins = sum(r["inserted"] for r in rows) / n
@@ -246,11 +248,13 @@ def update_roofline(rows, mem, edges, r_rand_GBps, r_stream_GBps):
     b_seq = ins * 12 + dels * 8 + (ins + dels) * 4 * 2 * 8
     lines = ins * (1 + 2 * le) + dels * (1 + 4 * le)
     t_min = b_seq / (r_stream_GBps * 1e9) + lines * 64 / (r_rand_GBps * 1e9)
-    t_loc = scanned * 8 / (r_stream_GBps * 1e9)
+    located = all(r.get("located", True) for r in rows)
+    t_loc = ((4 * dels + ins) * 64 / (r_rand_GBps * 1e9)) if located else scanned * 8 / (r_stream_GBps * 1e9)
     rec = ins + dels
     return {"records_per_batch": rec, "list_entries_per_edge": le, "streamed_bytes": b_seq, "random_lines": lines,
             "R_stream_GBps": r_stream_GBps, "R_rand_GBps": r_rand_GBps, "t_min_ms": t_min * 1e3,
-            "locate_scanned_entries": scanned, "t_locate_ms": t_loc * 1e3, "measured_ms": ms,
+            "locate_scanned_entries": scanned, "locate_by": "locator" if located else "scan",
+            "t_locate_ms": t_loc * 1e3, "measured_ms": ms,
             "ceiling_updates_per_s": rec / t_min, "ceiling_with_locate_updates_per_s": rec / (t_min + t_loc),
             "frac": (t_min * 1e3) / ms, "frac_with_locate": ((t_min + t_loc) * 1e3) / ms}
 
@@ -865,6 +869,7 @@ def main():
     rows = []
     last = None
     replay = None
+    loc_on = g.get_tuning().get("update_locate", 1) == 1
     for i in range(nb):
         base = i * args.sources * R
         torch.cuda.synchronize()
@@ -883,8 +888,8 @@ def main():
                      "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel()),
                      "inserted": st["inserted"], "deleted": st["deleted"], "not_found": st["not_found"],
                      "touched_vertices": st["touched_vertices"], "match_scanned": st["match_scanned"],
-                     "match_candidates": st["match_candidates"]})
-        log("step %d: update %.2f ms %s (%d touched, %d scanned to locate deletes), ppr %.2f ms (bound %.2f, walk "
+                     "match_candidates": st["match_candidates"], "located": loc_on})
+        log("step %d: update %.2f ms %s (%d touched, %d entries read to locate deletes), ppr %.2f ms (bound %.2f, walk "
             "kernel %.2f, histogram %.2f), %d transitions" %
             (i, rows[-1]["update_ms"], ["%.2f" % x for x in upd_phases], st["touched_vertices"], st["match_scanned"],
              rows[-1]["ppr_ms"], ppr_phases[0], ppr_phases[1], ppr_phases[2], steps))
