@@ -67,6 +67,8 @@ def parse():
                     help="node2vec walks (length 80, p = 0.5, q = 2) on the final graph; 0 skips")
     ap.add_argument("--stream-records", type=int, default=1_000_000,
                     help="records of the streaming-update measurement on the final graph (0 skips)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the timed steps one at a time (no PPR histogram beside the next update batch)")
     ap.add_argument("--no-random-probe", action="store_true",
                     help="skip the random-line read probe (context for the roofline)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -870,47 +872,82 @@ def main():
     last = None
     replay = None
     loc_on = g.get_tuning().get("update_locate", 1) == 1
+    # the timed steps run back to back on a stream of their own: each query's visit histogram is
+    # left running on a second stream (bingo_ppr_async) beside the next step's update batch, and
+    # the K steps are timed as a whole between two device synchronizations; warm-up steps, and
+    # every step with --no-overlap or the per-step form, run one at a time
+    overlap = mode == MODE_PERSISTENT and not args.no_overlap
+    main_st = torch.cuda.Stream() if overlap else stream
+    hist_st = torch.cuda.Stream() if overlap else None
+    t_timed = None
+    pend = []
     for i in range(nb):
         base = i * args.sources * R
-        torch.cuda.synchronize()
+        timed_async = overlap and i >= args.warmup
+        if not timed_async or i == args.warmup:
+            torch.cuda.synchronize()
+        if timed_async and i == args.warmup:
+            t_timed = time.perf_counter()
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        st = g.update(*batches[i])
-        upd_phases = g.last_phase_ms()
-        e1.record(stream)
-        off, vtx, cnt, steps = g.ppr(sources, R, thr, cap, seed, base=base, mode=mode)
-        ppr_phases = g.last_phase_ms()
-        e2.record(stream)
-        torch.cuda.synchronize()
-        rows.append({"update_ms": e0.elapsed_time(e1), "ppr_ms": e1.elapsed_time(e2),
-                     "step_ms": e0.elapsed_time(e2), "bound_ms": ppr_phases[0], "walk_kernel_ms": ppr_phases[1],
+        with torch.cuda.stream(main_st):
+            e0.record(main_st)
+            st = g.update(*batches[i])
+            upd_phases = g.last_phase_ms()
+            e1.record(main_st)
+            if overlap:
+                steps = g.ppr_async(sources, R, thr, cap, seed, base=base, hist_stream=hist_st)
+                ppr_phases = list(g.last_phase_ms()[:2]) + [None]
+                vtx = None
+                if not timed_async:  # a warm-up step (first use of both streams) waits for its histogram
+                    ne, hms = g.ppr_wait()
+                    ppr_phases[2] = hms
+            else:
+                off, vtx, cnt, steps = g.ppr(sources, R, thr, cap, seed, base=base, mode=mode)
+                ppr_phases = g.last_phase_ms()
+            e2.record(main_st)
+        if not timed_async:
+            torch.cuda.synchronize()
+        pend.append((e0, e1, e2))
+        rows.append({"bound_ms": ppr_phases[0], "walk_kernel_ms": ppr_phases[1],
                      "hist_ms": ppr_phases[2], "update_phases_ms": upd_phases, "steps": steps,
-                     "records": st["inserted"] + st["deleted"] + st["not_found"], "entries": int(vtx.numel()),
+                     "records": st["inserted"] + st["deleted"] + st["not_found"],
+                     "entries": int(vtx.numel()) if vtx is not None else (ne if overlap and not timed_async else None),
                      "inserted": st["inserted"], "deleted": st["deleted"], "not_found": st["not_found"],
                      "touched_vertices": st["touched_vertices"], "match_scanned": st["match_scanned"],
-                     "match_candidates": st["match_candidates"], "located": loc_on})
+                     "match_candidates": st["match_candidates"], "located": loc_on,
+                     "histogram_overlapped": timed_async})
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_timed) * 1e3 if t_timed is not None else None
+    if overlap:
+        ne, hms = g.ppr_wait()
+        rows[-1]["hist_ms"], rows[-1]["entries"] = hms, ne
+        off, vtx, cnt = g.ppr_result()
+    for i, ((e0, e1, e2), r) in enumerate(zip(pend, rows)):
+        r["update_ms"], r["ppr_ms"], r["step_ms"] = e0.elapsed_time(e1), e1.elapsed_time(e2), e0.elapsed_time(e2)
         log("step %d: update %.2f ms %s (%d touched, %d entries read to locate deletes), ppr %.2f ms (bound %.2f, walk "
-            "kernel %.2f, histogram %.2f), %d transitions" %
-            (i, rows[-1]["update_ms"], ["%.2f" % x for x in upd_phases], st["touched_vertices"], st["match_scanned"],
-             rows[-1]["ppr_ms"], ppr_phases[0], ppr_phases[1], ppr_phases[2], steps))
-        if i == nb - 1:
-            last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32),
-                    steps)
-            if not args.no_random_probe:
-                tun = g.get_tuning()
-                # resident blocks per CU of the walk kernel (0: as many as fit, 8 blocks of 256 threads)
-                bpc = tun["blocks_per_cu"] or 8
-                lanes = bpc * torch.cuda.get_device_properties(dev).multi_processor_count * 256
-                replay = replay_probe(g, dev, off, vtx, cnt, args.sources * R, lanes)
-                replay["transitions"] = int(steps)
-                log("replay of the last query's %d visits over the graph (%d lanes, chains of %d), 1 / 2 adjacency "
-                    "lines per visit: dependent %.0f / %.0f GB/s, independent %.0f / %.0f GB/s, ordered %.0f / %.0f "
-                    "GB/s" % (replay["visits"], lanes, replay["chain"], replay["dependent_extra_1"]["GBps"],
-                              replay["dependent_extra_2"]["GBps"], replay["independent_extra_1"]["GBps"],
-                              replay["independent_extra_2"]["GBps"], replay["ordered_extra_1"]["GBps"],
-                              replay["ordered_extra_2"]["GBps"]))
+            "kernel %.2f, histogram %s), %d transitions" %
+            (i, r["update_ms"], ["%.2f" % x for x in r["update_phases_ms"]], r["touched_vertices"],
+             r["match_scanned"], r["ppr_ms"], r["bound_ms"], r["walk_kernel_ms"],
+             "%.2f" % r["hist_ms"] if r["hist_ms"] is not None else "beside the next update", r["steps"]))
+    steps = rows[-1]["steps"]
+    base = (nb - 1) * args.sources * R
+    last = (base, off.cpu().numpy(), vtx.cpu().numpy().view(np.uint32), cnt.cpu().numpy().view(np.uint32), steps)
+    if not args.no_random_probe:
+        tun = g.get_tuning()
+        # resident blocks per CU of the walk kernel (0: as many as fit, 8 blocks of 256 threads)
+        bpc = tun["blocks_per_cu"] or 8
+        lanes = bpc * torch.cuda.get_device_properties(dev).multi_processor_count * 256
+        replay = replay_probe(g, dev, off, vtx, cnt, args.sources * R, lanes)
+        replay["transitions"] = int(steps)
+        log("replay of the last query's %d visits over the graph (%d lanes, chains of %d), 1 / 2 adjacency "
+            "lines per visit: dependent %.0f / %.0f GB/s, independent %.0f / %.0f GB/s, ordered %.0f / %.0f "
+            "GB/s" % (replay["visits"], lanes, replay["chain"], replay["dependent_extra_1"]["GBps"],
+                      replay["dependent_extra_2"]["GBps"], replay["independent_extra_1"]["GBps"],
+                      replay["independent_extra_2"]["GBps"], replay["ordered_extra_1"]["GBps"],
+                      replay["ordered_extra_2"]["GBps"]))
     timed = rows[args.warmup:]
-    tot_ms = sum(r["step_ms"] for r in timed)
+    # overlapped steps: the wall time of the K steps together; else the sum of the steps' own times
+    tot_ms = wall_ms if wall_ms is not None else sum(r["step_ms"] for r in timed)
     tot_steps = sum(r["steps"] for r in timed)
     upd_ms = sum(r["update_ms"] for r in timed)
     walk_ms = sum(r["walk_kernel_ms"] for r in timed)
@@ -1022,7 +1059,10 @@ def main():
                    "termination_prob": 0.15, "max_len": cap, "update_batch_records": args.batch,
                    "walk_form": args.mode, "group_adaption": True},
         "walk_steps_per_s": tot_steps / (walk_ms / 1e3),
+        # the query's walk phase; its histogram runs beside the next update batch (overlapped steps)
         "ppr_query_ms": ppr_ms / len(timed),
+        "histogram_overlap": overlap,
+        "step_sum_ms": sum(r["step_ms"] for r in timed) / len(timed),
         "edge_updates_per_s": recs / (upd_ms / 1e3),
         "update_batch_ms": upd_ms / len(timed),
         "update_h2d": update_h2d,

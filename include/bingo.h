@@ -344,6 +344,36 @@ int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources,
               uint64_t* h_total_entries, uint64_t* h_total_steps, void* stream);
 
 /*
+ * bingo_ppr_async -- bingo_ppr in the persistent form whose visit histogram is
+ * left running, so that it can overlap the next update batch (the histogram
+ * reads only the visit bins, never the graph).  The walk phase runs on stream
+ * and the call waits for it as bingo_ppr does; the histogram is then enqueued
+ * on hist_stream (after the walk) and the call returns.  *h_total_steps
+ * (optional) receives the transitions.  The result is complete once
+ * bingo_ppr_wait returns; bingo_ppr_fetch waits for it by itself.  Until then
+ * the handle accepts bingo_update_batch, which runs beside the histogram, and
+ * bingo_ppr / bingo_ppr_async, whose walk waits for it on the device (its
+ * result then gives way to the new query's); every other call on the handle
+ * first waits for it on the host, except bingo_last_phase_ms, which reports
+ * [walk-length bound pass, walk kernel] for it without waiting (the
+ * histogram's time comes from bingo_ppr_wait).  When a bin overflows, the query reruns with exact
+ * per-walk segments and finishes before returning.  Same results as bingo_ppr.
+ * BINGO_E_INVALID as bingo_ppr.
+ */
+int bingo_ppr_async(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources,
+                    uint32_t walks_per_source, uint32_t term_threshold, uint32_t max_len,
+                    uint64_t seed, uint64_t walk_id_base, uint64_t* h_total_steps,
+                    void* stream, void* hist_stream);
+
+/*
+ * bingo_ppr_wait -- wait for the histogram of the last bingo_ppr_async (no-op
+ * after a synchronous bingo_ppr): *h_total_entries (optional) receives the
+ * (vertex, count) pairs of the last result and *h_hist_ms (optional) the
+ * histogram's device time (0 when there was none pending).
+ */
+int bingo_ppr_wait(bingo_graph* g, uint64_t* h_total_entries, float* h_hist_ms);
+
+/*
  * bingo_ppr_fetch -- copy the last PPR result: d_offsets (n_sources + 1
  * uint64, CSR offsets per source), d_vertex and d_count (capacity uint32
  * each).  Returns BINGO_E_CAPACITY if capacity is below the entry count.

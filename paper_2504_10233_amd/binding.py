@@ -59,7 +59,7 @@ EXPORTS = ["bingo_build", "bingo_update_batch", "bingo_walk", "bingo_ppr", "bing
            "bingo_server_submit_walk", "bingo_server_submit_update", "bingo_server_wait", "bingo_server_destroy",
            "bingo_probe_random_reads", "bingo_node2vec", "bingo_quantize_biases", "bingo_update_stream",
            "bingo_compact", "bingo_walk_batch", "bingo_walk_noalloc", "bingo_export_index_range", "bingo_probe_replay",
-           "bingo_check_locator"]
+           "bingo_check_locator", "bingo_ppr_async", "bingo_ppr_wait"]
 
 
 class _ServerConfig(C.Structure):
@@ -116,6 +116,8 @@ def load():
         L.bingo_export_index_range.argtypes = [vp, u32, u32, vp, u64, C.POINTER(u64), vp]
         L.bingo_memory.argtypes = [vp, C.POINTER(_MemStats), vp]
         L.bingo_check_locator.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), vp]
+        L.bingo_ppr_async.argtypes = [vp, u32, vp, u32, u32, u32, u64, u64, C.POINTER(u64), vp, vp]
+        L.bingo_ppr_wait.argtypes = [vp, C.POINTER(u64), C.POINTER(C.c_float)]
         L.bingo_compact.argtypes = [vp, C.c_uint64, vp]
         L.bingo_walk_batch.argtypes = [vp, C.c_uint32, C.POINTER(_WalkQuery), vp]
         L.bingo_status.argtypes = [vp, vp]
@@ -290,6 +292,36 @@ class Graph:
         rc = L.bingo_ppr_fetch(self.h, _ptr(off), _ptr(vtx), _ptr(cnt), vtx.numel(), _stream(stream))
         _check(rc, "bingo_ppr_fetch")
         return off, vtx[: ne.value], cnt[: ne.value], int(ns.value)
+
+    def ppr_async(self, sources, walks_per_source, thr, max_len, seed, base=0, stream=None, hist_stream=None):
+        """Walk phase of a persistent PPR query; its histogram is left running on hist_stream
+        (see bingo_ppr_async).  Returns the transitions; ppr_result() collects the histograms.
+        `sources` must stay alive until then."""
+        src = as_u32(sources, self.device)
+        self._async_src = src
+        ns = C.c_uint64(0)
+        rc = load().bingo_ppr_async(self.h, src.numel(), _ptr(src), walks_per_source, thr, max_len, seed, base,
+                                    C.byref(ns), _stream(stream), _stream(hist_stream))
+        _check(rc, "bingo_ppr_async")
+        self._async_nsrc = src.numel()
+        return int(ns.value)
+
+    def ppr_wait(self):
+        """(entries, histogram ms) of the last query, after waiting for its histogram."""
+        ne, ms = C.c_uint64(0), C.c_float(0)
+        _check(load().bingo_ppr_wait(self.h, C.byref(ne), C.byref(ms)), "bingo_ppr_wait")
+        return int(ne.value), float(ms.value)
+
+    def ppr_result(self, stream=None):
+        """(offsets, vertex, count) of the last PPR query (waits for a pending histogram)."""
+        ne, _ = self.ppr_wait()
+        L = load()
+        off = torch.empty(self._async_nsrc + 1, dtype=torch.int64, device=self.device)
+        vtx = torch.empty(max(ne, 1), dtype=torch.int32, device=self.device)
+        cnt = torch.empty(max(ne, 1), dtype=torch.int32, device=self.device)
+        rc = L.bingo_ppr_fetch(self.h, _ptr(off), _ptr(vtx), _ptr(cnt), vtx.numel(), _stream(stream))
+        _check(rc, "bingo_ppr_fetch")
+        return off, vtx[:ne], cnt[:ne]
 
     def update(self, ins_src, ins_dst, ins_w, del_src, del_dst, stream=None):
         a, b, c = (as_u32(x, self.device) for x in (ins_src, ins_dst, ins_w))

@@ -8,6 +8,8 @@
 #include <cmath>
 
 void* ws_get(bingo_graph* g, size_t bytes) {
+    // a pending asynchronous PPR histogram still reads its visit bins here
+    if (ppr_drain(g) != BINGO_OK) return nullptr;
     if (bytes <= g->ws_bytes && g->ws) return g->ws;
     hipDeviceSynchronize();
     if (g->ws) hipFree(g->ws);
@@ -46,6 +48,8 @@ static void release(bingo_graph* g) {
         if (g->ev[i]) hipEventDestroy(g->ev[i]);
     for (int i = 0; i < WALK_SLOTS; ++i)
         if (g->slot_ev[i]) hipEventDestroy(g->slot_ev[i]);
+    for (hipEvent_t e : {g->ppr_done, g->ppr_h0, g->ppr_h1})
+        if (e) hipEventDestroy(e);
     hipFree(g->hdr);
     hipFree(g->alias);
     hipFree(g->pool);
@@ -176,9 +180,25 @@ int bingo_ppr(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources, uin
                    h_total_entries, h_total_steps, (hipStream_t)stream);
 }
 
+int bingo_ppr_async(bingo_graph* g, uint32_t n_sources, const uint32_t* d_sources, uint32_t walks_per_source,
+                    uint32_t term_threshold, uint32_t max_len, uint64_t seed, uint64_t walk_id_base,
+                    uint64_t* h_total_steps, void* stream, void* hist_stream) {
+    if (!g || g->radix_base != 2 || n_sources == 0 || walks_per_source == 0 || !d_sources) return BINGO_E_INVALID;
+    if ((uint64_t)n_sources * walks_per_source >= (1ull << 40)) return BINGO_E_INVALID;
+    uint64_t entries = 0;
+    return run_ppr(g, n_sources, d_sources, walks_per_source, term_threshold, max_len, seed, walk_id_base,
+                   BINGO_WALK_PERSISTENT, &entries, h_total_steps, (hipStream_t)stream, (hipStream_t)hist_stream);
+}
+
+int bingo_ppr_wait(bingo_graph* g, uint64_t* h_total_entries, float* h_hist_ms) {
+    if (!g) return BINGO_E_INVALID;
+    return ppr_wait(g, h_total_entries, h_hist_ms);
+}
+
 int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uint32_t* d_count, uint64_t capacity,
                     void* stream) {
     if (!g || !d_offsets || !d_vertex || !d_count || !g->ppr_off) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     if (capacity < g->ppr_entries) return BINGO_E_CAPACITY;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipMemcpyAsync(d_offsets, g->ppr_off, ((uint64_t)g->ppr_nsrc + 1) * 8, hipMemcpyDeviceToDevice, st));
@@ -191,6 +211,7 @@ int bingo_ppr_fetch(bingo_graph* g, uint64_t* d_offsets, uint32_t* d_vertex, uin
 
 int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* h_len, void* stream) {
     if (!g || !h_len) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     if (g->radix_base == 4) return export_graph4(g, 0, g->n, h_buf, cap_words, h_len, (hipStream_t)stream);
     return export_graph(g, 0, g->n, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
@@ -198,6 +219,7 @@ int bingo_export(bingo_graph* g, uint32_t* h_buf, uint64_t cap_words, uint64_t* 
 int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                        uint64_t* h_len, void* stream) {
     if (!g || !h_len) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     if (g->radix_base == 4) return export_graph4(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
     return export_graph(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
@@ -205,17 +227,20 @@ int bingo_export_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_
 int bingo_export_index_range(bingo_graph* g, uint32_t u_begin, uint32_t u_end, uint32_t* h_buf, uint64_t cap_words,
                              uint64_t* h_len, void* stream) {
     if (!g || !h_len || g->radix_base != 2) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     return export_index(g, u_begin, u_end, h_buf, cap_words, h_len, (hipStream_t)stream);
 }
 
 int bingo_compact(bingo_graph* g, uint64_t pool_bytes, void* stream) {
     if (!g || g->radix_base != 2) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     if (pool_bytes > (1ull << 37)) return BINGO_E_INVALID;
     return compact_pool(g, pool_bytes / 4, (hipStream_t)stream);
 }
 
 int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
     if (!g || !out) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     memset(out, 0, sizeof(*out));
     if (g->radix_base == 4) return memory_stats4(g, out, (hipStream_t)stream);
     return memory_stats(g, out, (hipStream_t)stream);
@@ -223,6 +248,7 @@ int bingo_memory(bingo_graph* g, bingo_mem_stats* out, void* stream) {
 
 int bingo_status(bingo_graph* g, void* stream) {
     if (!g) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     hipStream_t st = (hipStream_t)stream;
     uint32_t bits = 0;
     HIPCHK(hipMemcpyAsync(&bits, g->d_err, 4, hipMemcpyDeviceToHost, st));
@@ -271,7 +297,7 @@ int bingo_get_tuning(const bingo_graph* g, bingo_tuning* t) {
 }
 
 int bingo_last_phase_ms(bingo_graph* g, float* h_ms, uint32_t cap, uint32_t* h_n) {
-    if (!g || !h_n) return BINGO_E_INVALID;
+    if (!g || !h_n) return BINGO_E_INVALID;  // a pending histogram records no phase: no wait
     const uint32_t n = g->nev > 1 ? g->nev - 1 : 0;
     *h_n = n;
     if (!h_ms) return BINGO_OK;

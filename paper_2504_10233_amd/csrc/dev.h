@@ -303,6 +303,10 @@ struct bingo_graph {
     uint32_t* ppr_cnt = nullptr;
     uint64_t ppr_entries = 0, ppr_cap = 0;
     uint32_t ppr_nsrc = 0, ppr_off_cap = 0;
+    // bingo_ppr_async: the histogram of the last query still running on another stream until
+    // ppr_done; ppr_h0..ppr_h1 time it; its entry count lands in d_ctl[CTL_PPR_U]
+    bool ppr_pending = false;
+    hipEvent_t ppr_done = nullptr, ppr_h0 = nullptr, ppr_h1 = nullptr;
     // grow-only scratch for sorts, scans and temporaries
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -354,9 +358,10 @@ struct bingo_graph {
 };
 void phase_mark(bingo_graph* g, hipStream_t st, bool first);
 // d_ctl layout (u64): [0] pool words used, [1] garbage words, [2..6] PPR
-// counters, [8..11] node2vec counters (CTL_N2V), [12..13] edge locator
+// counters, [7] asynchronous PPR entry count (CTL_PPR_U), [8..11] node2vec counters (CTL_N2V), [12..13] edge locator
 // counters (CTL_LOC), [16 + 2*i .. 17 + 2*i] walk
 // call slot i (WALK_SLOTS slots).
+#define CTL_PPR_U 7  // entry count of the last asynchronous PPR histogram
 #define CTL_N2V 8
 #define CTL_LOC 12  // [12..13] edge locator counters (locate.hip)
 #define CTL_WALK0 16
@@ -428,9 +433,13 @@ int walk_slot_release(bingo_graph* g, uint32_t slot, hipStream_t st);
 int launch_walk_batch(bingo_graph* g, uint32_t nq, const bingo_walk_query* hq, hipStream_t st);
 int launch_walk(bingo_graph* g, uint64_t n_walks, const uint32_t* starts, uint64_t base, uint32_t len,
                 uint64_t seed, uint32_t* paths, uint64_t* steps, uint32_t mode, hipStream_t st);
+// hist_st: run the visit histogram there and return without waiting for it (nullptr: wait)
 int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr, uint32_t cap,
             uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps,
-            hipStream_t st);
+            hipStream_t st, hipStream_t hist_st = nullptr);
+// Finish a pending asynchronous histogram: wait for it, take its entry count (and its time).
+int ppr_wait(bingo_graph* g, uint64_t* h_entries, float* h_hist_ms);
+inline int ppr_drain(bingo_graph* g) { return g && g->ppr_pending ? ppr_wait(g, nullptr, nullptr) : BINGO_OK; }
 // export.hip
 int export_graph(bingo_graph* g, uint32_t u0, uint32_t u1, uint32_t* h_buf, uint64_t cap, uint64_t* h_len,
                  hipStream_t st);

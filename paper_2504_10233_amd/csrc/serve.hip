@@ -272,6 +272,7 @@ int bingo_server_create(bingo_graph* g, const bingo_server_config* cfg, bingo_se
         return BINGO_E_INVALID;
     if (cfg->max_inflight == 0 || cfg->max_inflight > 64) return BINGO_E_INVALID;
     if (cfg->max_batch > BINGO_WALK_BATCH_MAX || cfg->reserved) return BINGO_E_INVALID;
+    if (int rc = ppr_drain(g)) return rc;
     *out = nullptr;
     bingo_server* s = new bingo_server();
     s->g = g;

@@ -1251,7 +1251,9 @@ static int finish_lds_hist(bingo_graph* g, uint32_t* vis, uint32_t* hcnt, uint32
     const uint64_t U = hv[1];
     if (g->ppr_cap < U || !g->ppr_vtx) {
         hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
-        g->ppr_cap = std::max<uint64_t>(U, 1024) * 5 / 4;
+        // sized for every visit a distinct vertex (as the asynchronous form needs), so that a
+        // later query of the same shape, synchronous or not, allocates nothing
+        g->ppr_cap = std::max<uint64_t>(std::max(U, total), 1024);
         if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess || hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
             g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
             return BINGO_E_OOM;
@@ -1269,6 +1271,69 @@ static int finish_lds_hist(bingo_graph* g, uint32_t* vis, uint32_t* hcnt, uint32
     return BINGO_OK;
 }
 
+// The same histogram enqueued on hs after the walk phase on st, without waiting:
+// the outputs are sized for every visit being a distinct vertex, so no count is
+// needed before the compaction; the count lands in d_ctl[CTL_PPR_U] for ppr_wait.
+static int finish_lds_hist_async(bingo_graph* g, uint32_t* vis, uint32_t* hcnt, uint32_t* ucount, uint32_t R,
+                                 uint64_t C, const uint32_t* bin_cnt, uint32_t nsrc, uint64_t total, uint64_t maxlen,
+                                 void* tmp, unsigned long long* ctl, uint64_t steps, uint64_t* h_steps, hipStream_t st,
+                                 hipStream_t hs) {
+    int rc = ensure_ppr_off(g, nsrc);
+    if (rc != BINGO_OK) return rc;
+    if (g->ppr_cap < total || !g->ppr_vtx) {
+        hipFree(g->ppr_vtx); hipFree(g->ppr_cnt);
+        g->ppr_cap = std::max<uint64_t>(total, 1024);
+        if (hipMalloc(&g->ppr_vtx, g->ppr_cap * 4) != hipSuccess || hipMalloc(&g->ppr_cnt, g->ppr_cap * 4) != hipSuccess) {
+            g->ppr_vtx = g->ppr_cnt = nullptr; g->ppr_cap = 0;
+            return BINGO_E_OOM;
+        }
+    }
+    for (hipEvent_t* e : {&g->ppr_done, &g->ppr_h0, &g->ppr_h1})
+        if (!*e) HIPCHK(hipEventCreate(e));
+    HIPCHK(hipEventRecord(g->ppr_done, st));  // the walk phase
+    HIPCHK(hipStreamWaitEvent(hs, g->ppr_done, 0));
+    HIPCHK(hipEventRecord(g->ppr_h0, hs));
+    HIPCHK(hipMemsetAsync(ctl, 0, 8, hs));
+#define BINGO_HIST(E_)                                                                                            \
+    hipLaunchKernelGGL((k_hist_seg<E_>), dim3(nsrc), dim3(HSB), 0, hs, vis, hcnt, (const uint64_t*)nullptr, R, nsrc, \
+                       total, C, bin_cnt, ucount, ctl)
+    if (maxlen <= HSB * 1) BINGO_HIST(1);
+    else if (maxlen <= HSB * 2) BINGO_HIST(2);
+    else if (maxlen <= HSB * 4) BINGO_HIST(4);
+    else if (maxlen <= HSB * 8) BINGO_HIST(8);
+    else if (maxlen <= HSB * 16) BINGO_HIST(16);
+    else BINGO_HIST(32);
+#undef BINGO_HIST
+    scan_u32_to_u64(ucount, g->ppr_off, nsrc, tmp, ctl + 1, hs);
+    hipLaunchKernelGGL(k_set_last_off, dim3(1), dim3(1), 0, hs, g->ppr_off, nsrc, (const unsigned long long*)(ctl + 1));
+    hipLaunchKernelGGL(k_hist_compact, dim3(nsrc), dim3(256), 0, hs, vis, hcnt, (const uint64_t*)nullptr, R, C, ucount,
+                       g->ppr_off, g->ppr_vtx, g->ppr_cnt);
+    HIPCHK(hipMemcpyAsync(g->d_ctl + CTL_PPR_U, ctl + 1, 8, hipMemcpyDeviceToDevice, hs));
+    HIPCHK(hipEventRecord(g->ppr_h1, hs));
+    HIPCHK(hipEventRecord(g->ppr_done, hs));
+    g->ppr_pending = true;
+    g->ppr_entries = 0;
+    g->ppr_nsrc = nsrc;
+    if (h_steps) *h_steps = steps;
+    return BINGO_OK;
+}
+
+int ppr_wait(bingo_graph* g, uint64_t* h_entries, float* h_hist_ms) {
+    if (!g->ppr_pending) {
+        if (h_entries) *h_entries = g->ppr_entries;
+        if (h_hist_ms) *h_hist_ms = 0.f;
+        return BINGO_OK;
+    }
+    g->ppr_pending = false;
+    HIPCHK(hipEventSynchronize(g->ppr_done));
+    unsigned long long u = 0;
+    HIPCHK(hipMemcpy(&u, g->d_ctl + CTL_PPR_U, 8, hipMemcpyDeviceToHost));
+    g->ppr_entries = u;
+    if (h_entries) *h_entries = u;
+    if (h_hist_ms) HIPCHK(hipEventElapsedTime(h_hist_ms, g->ppr_h0, g->ppr_h1));
+    return BINGO_OK;
+}
+
 constexpr int PPR_RETRY = 1;
 
 // Persistent PPR into per-source bins (k_ppr_binned).  Returns PPR_RETRY when a
@@ -1276,7 +1341,7 @@ constexpr int PPR_RETRY = 1;
 // holds; the caller then reruns the query with exact per-walk segments.
 static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr,
                           uint32_t cap, uint64_t seed, uint64_t base, uint64_t* h_entries, uint64_t* h_steps,
-                          hipStream_t st) {
+                          hipStream_t st, hipStream_t hs) {
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     // bin capacity: 1.25 x the expected visits of R walks plus slack, at most the worst case R (cap + 1)
     const double keep = 1.0 - (double)thr / 4294967296.0;
@@ -1323,16 +1388,27 @@ static int run_ppr_binned(bingo_graph* g, uint32_t nsrc, const uint32_t* sources
     HIPCHK(hipStreamSynchronize(st));
     if (err) return err_to_code(err);
     if (c4[2] || c4[3] > C || c4[3] > HCAP) return PPR_RETRY;
+    if (hs)
+        return finish_lds_hist_async(g, vis, hcnt, ucount, R, C, bin_cnt, nsrc, cells, c4[3], tmp, ctl + 2, c4[1],
+                                     h_steps, st, hs);
     return finish_lds_hist(g, vis, hcnt, ucount, nullptr, R, C, bin_cnt, nsrc, cells, c4[3], tmp, ctl + 2, c4[1],
                            h_entries, h_steps, st);
 }
 
 int run_ppr(bingo_graph* g, uint32_t nsrc, const uint32_t* sources, uint32_t R, uint32_t thr, uint32_t cap,
-            uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps, hipStream_t st) {
+            uint64_t seed, uint64_t base, uint32_t mode, uint64_t* h_entries, uint64_t* h_steps, hipStream_t st,
+            hipStream_t hist_st) {
+    if (g->ppr_pending) {
+        // the previous query's histogram still reads the visit bins this query is about to
+        // overwrite: st waits for it on the device; its result gives way to this query's
+        HIPCHK(hipStreamWaitEvent(st, g->ppr_done, 0));
+        g->ppr_pending = false;
+    }
     if (mode == BINGO_WALK_PERSISTENT && g->ppr_bins) {
-        const int rc = run_ppr_binned(g, nsrc, sources, R, thr, cap, seed, base, h_entries, h_steps, st);
+        const int rc = run_ppr_binned(g, nsrc, sources, R, thr, cap, seed, base, h_entries, h_steps, st, hist_st);
         if (rc != PPR_RETRY) return rc;
     }
+    // the exact-segment form below finishes its histogram before returning, asynchronous call or not
     const uint64_t nw = (uint64_t)nsrc * R;
     const int vbits = std::max(1, bits_for((uint64_t)g->n - 1));
     const int qbits = std::max(1, bits_for(nsrc));  // q < nsrc < 2^qbits
