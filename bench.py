@@ -258,7 +258,13 @@ def update_roofline(rows, mem, edges, r_rand_GBps, r_stream_GBps):
             "locate_scanned_entries": scanned, "locate_by": "locator" if located else "scan",
             "t_locate_ms": t_loc * 1e3, "measured_ms": ms,
             "ceiling_updates_per_s": rec / t_min, "ceiling_with_locate_updates_per_s": rec / (t_min + t_loc),
-            "frac": (t_min * 1e3) / ms, "frac_with_locate": ((t_min + t_loc) * 1e3) / ms}
+            "frac": (t_min * 1e3) / ms, "frac_with_locate": ((t_min + t_loc) * 1e3) / ms,
+            # the batch's random 64-byte lines (the model's, plus the locator's when it is used) per
+            # second of the measured batch, as a fraction of the measured random-line rate and of the
+            # 8 TB/s peak: the same denominators the walk's roofline uses
+            "random_lines_frac_of_probe": (lines + (4 * dels + ins if located else 0)) * 64 / (ms / 1e3)
+            / (r_rand_GBps * 1e9),
+            "random_lines_frac_of_peak": (lines + (4 * dels + ins if located else 0)) * 64 / (ms / 1e3) / 8e12}
 
 
 def torch_index(pos):
