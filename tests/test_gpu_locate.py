@@ -132,3 +132,27 @@ def test_locator_grows_and_toggles():
     gg.set_tuning(update_locate=1)
     apply_both(og, gg, [(1, 2, 5)], [(1, 2)], "batch with the locator again")
     assert_in_step(gg, "after toggling back")
+
+
+def test_locator_in_step_after_compaction():
+    """Compaction moves blocks but keeps every neighbour index, so the locator stays in step through
+    it and the batches after it still equal the oracle's."""
+    rng = random.Random(12)
+    n = 300
+    src = [rng.randrange(n) for _ in range(4000)] + [1] * 2000
+    dst = [rng.randrange(n) for _ in range(6000)]
+    w = [rng.randrange(1, 1 << 24) for _ in range(6000)]
+    og, gg = both(n, src, dst, w)
+    for b in range(3):
+        cur = O.parse_dump(og.dump(), n)
+        live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
+        ins = [(rng.choice([1, rng.randrange(n)]), rng.randrange(n), rng.randrange(1, 1 << 24)) for _ in range(3000)]
+        dels = [rng.choice(live) for _ in range(1500)]
+        apply_both(og, gg, ins, dels, "before compaction %d" % b)
+    assert_in_step(gg, "before compaction")
+    gg.compact()
+    assert_in_step(gg, "after compaction")
+    cur = O.parse_dump(og.dump(), n)
+    live = [(u, int(t)) for u, v in enumerate(cur) for t in v["dst"]]
+    apply_both(og, gg, [(1, 2, 3)] * 10, [rng.choice(live) for _ in range(800)], "after compaction")
+    assert_in_step(gg, "batch after compaction")
